@@ -1,0 +1,258 @@
+/*
+ * tdvp.h -- C-ABI of the GSE-TDVP1 hot path on MI355X (gfx950).
+ *
+ * Method: Yang & White, "Time dependent variational principle with ancillary
+ * Krylov subspace".  One GSE-TDVP1 time step (section I.C) is
+ *   1. tdvp_expand_basis: apply the MPO of 1 - i tau H k-1 times to |psi>
+ *      (global Krylov vectors, eq. (10), cutoff eps_K) and extend the bond
+ *      bases of |psi> by them (state-averaged basis extension, section I.A,
+ *      eqs. (5)-(7), cutoff eps_M), ending with the center on the first site;
+ *   2. tdvp_sweep: one-site TDVP sweep left to right then right to left
+ *      (cutoff eps, used only when unitarity is not required).
+ * tdvp_measure returns energy, norm, <S^z_i>, bond dimensions and overlaps.
+ *
+ * Conventions fixed at this boundary
+ *   - spin 1/2, local dimension d = 2, basis order {up, down};
+ *   - operator codes: 0 = identity, 1 = S^+, 2 = S^-, 3 = S^z;
+ *   - complex numbers are interleaved (re, im) pairs: complex128 = 2 doubles,
+ *     complex64 = 2 floats; every array is row-major (last index fastest);
+ *   - site tensors M[a, s, b]: left bond a, physical s, right bond b;
+ *   - MPO tensors W[alpha, beta, s', s] (s' is the output index);
+ *   - left environment L[a', alpha, a] (a' on the bra side);
+ *   - right environment, stored transposed, Rt[beta, b, b'] (b' on the bra side);
+ *   - time steps are complex: a step evolves exp(-i H dt); imaginary time
+ *     uses dt = -i dtau.
+ *
+ * Ownership: input arrays are copied, the caller keeps them.  Handles own
+ * their device memory and are freed by *_destroy.  Outputs go to
+ * caller-provided buffers; nothing returns pointers into internal memory.
+ * A context is bound to one device and one HIP stream and is not thread-safe.
+ *
+ * Errors: every call returns a tdvp_status and never throws.  The message of
+ * the last failure is kept per context (tdvp_last_error).  Arguments are
+ * checked before any state is changed, so TDVP_ERR_ARG leaves every handle as
+ * it was.  A device or numeric failure in the middle of a call marks the
+ * handles it was changing invalid; later use returns TDVP_ERR_STATE.
+ * Device pointers passed to the kernel-level calls must hold at least the
+ * stated number of elements; they are not checked.
+ */
+#ifndef TDVP_H_
+#define TDVP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdvp_ctx_s* tdvp_ctx;
+typedef struct tdvp_mpo_s* tdvp_mpo;
+typedef struct tdvp_mps_s* tdvp_mps;
+
+typedef enum {
+  TDVP_OK = 0,
+  TDVP_ERR_ARG = 1,      /* invalid argument; nothing was changed          */
+  TDVP_ERR_ALLOC = 2,    /* device allocation failed or above a stated cap */
+  TDVP_ERR_DEVICE = 3,   /* HIP / rocSOLVER runtime error                  */
+  TDVP_ERR_NOCONV = 4,   /* Lanczos hit krylov_max in strict mode          */
+  TDVP_ERR_NUMERIC = 5,  /* NaN/Inf or a failed factorisation              */
+  TDVP_ERR_STATE = 6     /* handle invalidated by an earlier failure       */
+} tdvp_status;
+
+/* Precision of the contractions (environments, effective Hamiltonians, MPO
+ * application).  Lanczos recurrences, reorthogonalisation, the tridiagonal
+ * exponential, QR/SVD/eigh and the stored site tensors are always FP64. */
+typedef enum { TDVP_FP64 = 0, TDVP_FP32 = 1 } tdvp_prec;
+
+/* GEMM operand modes: N = as stored, T = transposed, C = conjugate transpose,
+ * R = conjugated (not transposed). */
+typedef enum { TDVP_OP_N = 0, TDVP_OP_T = 1, TDVP_OP_C = 2, TDVP_OP_R = 3 } tdvp_op;
+
+/* Device memory callbacks (e.g. PyTorch's caching allocator).  alloc returns
+ * NULL on failure; memory freed by free_ may be reused by later work on the
+ * context's stream only.  Both may be NULL: the library then uses hipMalloc
+ * and hipFree. */
+typedef void* (*tdvp_alloc_fn)(size_t bytes, void* user);
+typedef void (*tdvp_free_fn)(void* ptr, void* user);
+
+/* ---------------------------------------------------------------- context */
+
+/* Bind a context to `device` and the HIP stream `hip_stream` (NULL = the
+ * default stream).  All work of the context is issued on that stream. */
+tdvp_status tdvp_ctx_create(int device, void* hip_stream, tdvp_alloc_fn alloc, tdvp_free_fn free_,
+                            void* user, tdvp_ctx* out);
+void tdvp_ctx_destroy(tdvp_ctx ctx);
+/* Message of the last failure on this context ("" if none).  Valid until the
+ * next call on the context. */
+const char* tdvp_last_error(tdvp_ctx ctx);
+/* Library version string. */
+const char* tdvp_version(void);
+
+/* -------------------------------------------------------------------- MPO */
+
+/* One Hamiltonian term: coef * op_i(site_i) op_j(site_j); site_j = -1 gives
+ * the one-site term coef * op_i(site_i).  Sites are 0-based path positions. */
+typedef struct {
+  int32_t site_i, site_j;
+  int32_t op_i, op_j;
+  double re, im;
+} tdvp_term;
+
+/* Build the MPO of c0 * 1 + c1 * H for H = sum of `terms` on n_sites sites
+ * (section I.C step 1: 1 - i tau H is c0 = 1, c1 = -i tau).  The MPO is a
+ * finite-state automaton (start / open channels / done) in which open
+ * channels with identical pending futures are merged, which is exact.
+ * w_out (may be NULL) receives the n_sites + 1 MPO bond dimensions.
+ * Errors: TDVP_ERR_ARG for n_sites < 1, a site out of range, site_i ==
+ * site_j, or an operator code outside 0..3. */
+tdvp_status tdvp_create_mpo(tdvp_ctx ctx, int n_sites, const tdvp_term* terms, int n_terms,
+                            double c0_re, double c0_im, double c1_re, double c1_im,
+                            tdvp_mpo* out, int* w_out);
+/* Copy the MPO tensors to host: concatenated W_i (w_i x w_{i+1} x 2 x 2
+ * complex128), `capacity` in doubles.  Returns TDVP_ERR_ARG if too small.
+ * Host-only: needs no GPU. */
+tdvp_status tdvp_mpo_to_host(tdvp_mpo mpo, double* out, size_t capacity);
+/* Host-only MPO construction for checking the builder without a device:
+ * same arguments as tdvp_create_mpo minus the context; fills dims[n_sites+1]
+ * and, if `out` is not NULL, the tensors as in tdvp_mpo_to_host. */
+tdvp_status tdvp_build_mpo_host(int n_sites, const tdvp_term* terms, int n_terms, double c0_re,
+                                double c0_im, double c1_re, double c1_im, int* dims, double* out,
+                                size_t capacity);
+void tdvp_mpo_destroy(tdvp_mpo mpo);
+
+/* -------------------------------------------------------------------- MPS */
+
+/* Upload an MPS: bond_dims has n_sites + 1 entries (first and last 1);
+ * tensors are the concatenated site tensors M_i[a,s,b] in complex128.
+ * Errors: TDVP_ERR_ARG for inconsistent sizes or non-finite entries. */
+tdvp_status tdvp_mps_from_host(tdvp_ctx ctx, int n_sites, const int* bond_dims,
+                               const double* tensors, tdvp_mps* out);
+/* Number of sites and current bond dims (n_sites + 1 entries). */
+tdvp_status tdvp_mps_bond_dims(tdvp_mps mps, int* n_sites, int* bond_dims, int capacity);
+/* Download the tensors (layout as in tdvp_mps_from_host); capacity in doubles. */
+tdvp_status tdvp_mps_to_host(tdvp_mps mps, double* tensors, size_t capacity);
+void tdvp_mps_destroy(tdvp_mps mps);
+
+/* ------------------------------------------------------- GSE-TDVP1 step */
+
+typedef struct {
+  int k;             /* Krylov order: k-1 global Krylov vectors (k >= 1)           */
+  double eps_K;      /* Krylov-vector cutoff (relative discarded weight)            */
+  double eps_M;      /* cutoff on states added by the extension (relative to
+                        sum_l |C~_l|^2)                                             */
+  int chi_max;       /* cap on every bond (Krylov vectors and extended psi)         */
+  int prec;          /* tdvp_prec of the contractions                               */
+  int skip_if_full;  /* 1: skip steps 1-2 when every bond is already at its largest
+                        useful size min(chi_max, 2^(i+1), 2^(N-i-1))                */
+} tdvp_expand_params;
+
+typedef struct {
+  double ms_krylov, ms_extend;   /* wall time of the two stages               */
+  int n_added;                   /* states added over all bonds               */
+  int max_bond;                  /* largest bond after the extension          */
+  int krylov_max_bond;           /* largest bond of any Krylov vector         */
+  int skipped;                   /* 1 if the expansion was skipped            */
+  double discarded_K;            /* total discarded weight of the MPO applications */
+} tdvp_expand_stats;
+
+/* Steps 1-2 of GSE-TDVP1 for n independent states psi[0..n-1], each with its
+ * own MPO op[j] = 1 - i tau H.  On return every psi[j] is right-canonical
+ * with its center on site 0 and represents the same state as before (up to
+ * rounding).  stats may be NULL, else n entries.
+ * Errors: TDVP_ERR_ARG (n < 1, site counts differ from the MPO, k < 1,
+ * chi_max < 1, eps < 0, unknown prec). */
+tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* op,
+                              const tdvp_expand_params* params, tdvp_expand_stats* stats);
+
+typedef struct {
+  double dt_re, dt_im;   /* the sweep evolves exp(-i H dt); imaginary dtau: dt = -i dtau */
+  double eps;            /* gauge-move cutoff (0 = QR, unitary)                           */
+  int chi_max;           /* cap on bonds when eps > 0                                     */
+  double krylov_tol;     /* Lanczos stop: beta_j |c_j| <= tol |c|                          */
+  int krylov_max;        /* at most this many Lanczos vectors (<= 64)                      */
+  int prec;              /* tdvp_prec of the contractions                                  */
+  int normalize;         /* renormalise after every local step (imaginary time)            */
+  int strict;            /* 1: reaching krylov_max is TDVP_ERR_NOCONV                      */
+} tdvp_sweep_params;
+
+typedef struct {
+  double ms;                 /* wall time of the sweep                                    */
+  double ms_matvec;          /* device time of the one-site H_eff applications            */
+  double flops_matvec;       /* algorithmic flops of those applications (8 per complex MAC,
+                                nonzero MPO entries only)                                */
+  long long n_matvec;        /* one-site H_eff applications                               */
+  long long n_keff;          /* zero-site K_eff applications                              */
+  int max_lanczos;           /* largest Lanczos dimension used                            */
+  int n_unconverged;         /* local steps that reached krylov_max                       */
+  double discarded;          /* weight dropped at gauge moves (eps > 0)                   */
+  double energy;             /* <C|H_eff|C>/<C|C> at site 0 after the sweep                */
+} tdvp_sweep_stats;
+
+/* Step 3 of GSE-TDVP1: one symmetric one-site TDVP sweep (left to right by
+ * dt/2 per site, right to left by dt/2; the last site takes dt at once).
+ * Precondition: center at site 0, sites 1..N-1 right-canonical (the state
+ * tdvp_expand_basis leaves).  Postcondition: the same gauge.
+ * Errors: TDVP_ERR_ARG (bad parameters, MPO/MPS mismatch), TDVP_ERR_NOCONV
+ * (strict mode), TDVP_ERR_NUMERIC (non-finite values). */
+tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H,
+                       const tdvp_sweep_params* params, tdvp_sweep_stats* stats);
+
+/* Caller-owned result arrays; pointer fields may be NULL to skip. */
+typedef struct {
+  double energy;        /* <psi|H|psi>/<psi|psi> (when H is given)       */
+  double norm;          /* sqrt(<psi|psi>)                                */
+  double overlap_re, overlap_im;  /* <other|psi> (when other is given)    */
+  double* sz;           /* n_sites entries: <S^z_i>                       */
+  int* bond_dims;       /* n_sites + 1 entries                            */
+} tdvp_observables;
+
+/* Measure psi[j] (any gauge) for j < n; H and other may be NULL (then n
+ * entries each when given). */
+tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mpo* H,
+                         const tdvp_mps* other, tdvp_observables* out);
+
+/* ---------------------------------------------------- kernel-level calls
+ * Device pointers, complex in the precision `prec` (complex128 or complex64),
+ * issued on the context's stream, asynchronous. */
+
+/* Batched complex GEMM C = alpha op(A) op(B) + beta C (row-major), batch
+ * strides in elements; op(A) is M x K, op(B) is K x N. */
+tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, int K,
+                      double alpha_re, double alpha_im, const void* A, long long lda,
+                      long long stride_a, const void* B, long long ldb, long long stride_b,
+                      double beta_re, double beta_im, void* C, long long ldc, long long stride_c,
+                      int batch);
+
+/* One-site effective Hamiltonian (the one-site TDVP local generator):
+ * Y[a',s',b'] = sum L[a',al,a] W[al,be,s',s] C[a,s,b] Rt[be,b,b'].
+ * Sizes: L ml*wl*ml, Rt wr*mr*mr, C and Y ml*2*mr; W_host is a host array of
+ * wl*wr*4 complex128.  workspace may be NULL (allocated internally) or hold
+ * 2*ml*mr*2*max(wl,wr) elements of the precision. */
+tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr,
+                            const double* W_host, const void* L, const void* Rt, const void* C,
+                            void* Y, void* workspace);
+
+/* Zero-site effective Hamiltonian on the bond: Y[a',b'] = sum L[a',al,a] X[a,b] Rt[al,b,b'].
+ * Sizes: L ml*w*ml, Rt w*mr*mr, X and Y ml*mr. */
+tdvp_status tdvp_keff_apply(tdvp_ctx ctx, int prec, int ml, int w, int mr, const void* L,
+                            const void* Rt, const void* X, void* Y, void* workspace);
+
+/* Environment updates.  Left: Lout[b',be,b] = sum conj(A[a',s',b']) L[a',al,a]
+ * W[al,be,s',s] A[a,s,b] (A is ml x 2 x mr, L ml*wl*ml, Lout mr*wr*mr).
+ * Right: Rout[al,a,a'] = sum B[a,s,b] W[al,be,s',s] Rt[be,b,b'] conj(B[a',s',b'])
+ * (B is ml x 2 x mr, Rt wr*mr*mr, Rout wl*ml*ml). */
+tdvp_status tdvp_env_left(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr,
+                          const double* W_host, const void* L, const void* A, void* Lout,
+                          void* workspace);
+tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr,
+                           const double* W_host, const void* Rt, const void* B, void* Rout,
+                           void* workspace);
+
+/* Wait for all work issued on the context's stream. */
+tdvp_status tdvp_synchronize(tdvp_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDVP_H_ */

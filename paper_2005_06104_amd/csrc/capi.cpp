@@ -1,0 +1,399 @@
+// extern "C" entry points: argument checks, status codes, context plumbing.
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+
+#define TDVP_VERSION "tdvp-mi355x 0.1 (gfx950)"
+
+void* tdvp_ctx_s::dalloc(size_t bytes) {
+  void* p = nullptr;
+  if (alloc) {
+    p = alloc(bytes, user);
+    if (!p) TDVP_THROW(TDVP_ERR_ALLOC, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess || !p)
+      TDVP_THROW(TDVP_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+void tdvp_ctx_s::dfree(void* p) {
+  if (!p) return;
+  if (free_) free_(p, user);
+  else (void)hipFree(p);
+}
+
+void tdvp_ctx_s::sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
+
+namespace {
+
+template <class F>
+tdvp_status guarded(tdvp_ctx_s* ctx, F&& f) {
+  try {
+    f();
+    if (ctx) ctx->last_error.clear();
+    return TDVP_OK;
+  } catch (const TdvpError& e) {
+    if (ctx) ctx->last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return TDVP_ERR_ALLOC;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->last_error = e.what();
+    return TDVP_ERR_DEVICE;
+  } catch (...) {
+    if (ctx) ctx->last_error = "unknown failure";
+    return TDVP_ERR_DEVICE;
+  }
+}
+
+void bind(tdvp_ctx_s* ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
+
+bool all_finite(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+std::vector<zc> host_W(const double* W, int wl, int wr) {
+  std::vector<zc> out((size_t)wl * wr * 4);
+  for (size_t i = 0; i < out.size(); ++i) out[i] = zc(W[2 * i], W[2 * i + 1]);
+  return out;
+}
+
+}  // namespace
+
+namespace {
+
+template <class F>
+tdvp_status kernel_call(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host, void* workspace,
+                        F&& f) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(prec == TDVP_FP64 || prec == TDVP_FP32, "unknown precision");
+    ARG_CHECK(ml >= 1 && mr >= 1 && wl >= 1 && wr >= 1 && wl <= 32 && wr <= 32, "bad sizes");
+    bind(ctx);
+    const int cb = prec == TDVP_FP64 ? 16 : 8;
+    const size_t half = (size_t)2 * ml * mr * std::max(wl, wr) * cb;
+    DBuf ws(ctx), tab(ctx);
+    char* w1;
+    if (workspace) w1 = static_cast<char*>(workspace);
+    else w1 = static_cast<char*>(ws.ensure(2 * half));
+    SiteTables tb{};
+    if (W_host) tb = upload_tables(ctx, host_W(W_host, wl, wr), wl, wr, tab);
+    f(tb, w1, w1 + half);
+    if (!workspace || W_host) ctx->sync();  // keep temporaries alive until the kernels finish
+  });
+}
+}  // namespace
+
+extern "C" {
+
+const char* tdvp_version(void) { return TDVP_VERSION; }
+
+tdvp_status tdvp_ctx_create(int device, void* hip_stream, tdvp_alloc_fn alloc, tdvp_free_fn free_, void* user,
+                            tdvp_ctx* out) {
+  if (!out) return TDVP_ERR_ARG;
+  *out = nullptr;
+  auto* ctx = new (std::nothrow) tdvp_ctx_s();
+  if (!ctx) return TDVP_ERR_ALLOC;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->alloc = alloc;
+  ctx->free_ = free_;
+  ctx->user = user;
+  if ((alloc == nullptr) != (free_ == nullptr)) {
+    delete ctx;
+    return TDVP_ERR_ARG;
+  }
+  tdvp_status st = guarded(ctx, [&] {
+    int n = 0;
+    HIP_CHECK(hipGetDeviceCount(&n));
+    ARG_CHECK(device >= 0 && device < n, "device index out of range");
+    bind(ctx);
+    if (rocblas_create_handle(&ctx->blas) != rocblas_status_success)
+      TDVP_THROW(TDVP_ERR_DEVICE, "rocblas_create_handle failed");
+    if (rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success)
+      TDVP_THROW(TDVP_ERR_DEVICE, "rocblas_set_stream failed");
+    HIP_CHECK(hipEventCreate(&ctx->ev_a));
+    HIP_CHECK(hipEventCreate(&ctx->ev_b));
+  });
+  if (st != TDVP_OK) {
+    if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return TDVP_OK;
+}
+
+void tdvp_ctx_destroy(tdvp_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
+  if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+  if (ctx->blas) rocblas_destroy_handle(ctx->blas);
+  delete ctx;
+}
+
+const char* tdvp_last_error(tdvp_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+tdvp_status tdvp_synchronize(tdvp_ctx ctx) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] { ctx->sync(); });
+}
+
+// ------------------------------------------------------------------ MPO
+tdvp_status tdvp_build_mpo_host(int n_sites, const tdvp_term* terms, int n_terms, double c0_re, double c0_im,
+                                double c1_re, double c1_im, int* dims, double* out, size_t capacity) {
+  return guarded(nullptr, [&] {
+    ARG_CHECK(dims != nullptr, "dims must not be NULL");
+    HostMPO h = build_host_mpo(n_sites, terms, n_terms, zc(c0_re, c0_im), zc(c1_re, c1_im));
+    for (int b = 0; b <= n_sites; ++b) dims[b] = h.w[b];
+    if (out) {
+      size_t need = 0;
+      for (auto& W : h.W) need += 2 * W.size();
+      ARG_CHECK(capacity >= need, "output capacity too small");
+      size_t off = 0;
+      for (auto& W : h.W)
+        for (const zc& x : W) {
+          out[off++] = x.real();
+          out[off++] = x.imag();
+        }
+    }
+  });
+}
+
+tdvp_status tdvp_create_mpo(tdvp_ctx ctx, int n_sites, const tdvp_term* terms, int n_terms, double c0_re,
+                            double c0_im, double c1_re, double c1_im, tdvp_mpo* out, int* w_out) {
+  if (!ctx || !out) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    bind(ctx);
+    HostMPO h = build_host_mpo(n_sites, terms, n_terms, zc(c0_re, c0_im), zc(c1_re, c1_im));
+    for (auto& W : h.W)
+      for (const zc& x : W) ARG_CHECK(std::isfinite(x.real()) && std::isfinite(x.imag()), "non-finite coefficient");
+    if (w_out)
+      for (int b = 0; b <= n_sites; ++b) w_out[b] = h.w[b];
+    for (int b = 0; b <= n_sites; ++b) ARG_CHECK(h.w[b] <= 32, "MPO bond dimension above 32 is not supported");
+    *out = make_mpo(ctx, std::move(h)).release();
+  });
+}
+
+tdvp_status tdvp_mpo_to_host(tdvp_mpo mpo, double* out, size_t capacity) {
+  if (!mpo || !out) return TDVP_ERR_ARG;
+  return guarded(mpo->ctx, [&] {
+    size_t need = 0;
+    for (auto& W : mpo->host.W) need += 2 * W.size();
+    ARG_CHECK(capacity >= need, "output capacity too small");
+    size_t off = 0;
+    for (auto& W : mpo->host.W)
+      for (const zc& x : W) {
+        out[off++] = x.real();
+        out[off++] = x.imag();
+      }
+  });
+}
+
+void tdvp_mpo_destroy(tdvp_mpo mpo) {
+  if (!mpo) return;
+  (void)hipSetDevice(mpo->ctx->device);
+  (void)hipStreamSynchronize(mpo->ctx->stream);
+  delete mpo;
+}
+
+// ------------------------------------------------------------------ MPS
+tdvp_status tdvp_mps_from_host(tdvp_ctx ctx, int n_sites, const int* bond_dims, const double* tensors,
+                               tdvp_mps* out) {
+  if (!ctx || !out) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n_sites >= 1, "n_sites must be >= 1");
+    ARG_CHECK(bond_dims && tensors, "NULL array");
+    ARG_CHECK(bond_dims[0] == 1 && bond_dims[n_sites] == 1, "first and last bond dimensions must be 1");
+    size_t total = 0;
+    for (int i = 0; i <= n_sites; ++i) ARG_CHECK(bond_dims[i] >= 1 && bond_dims[i] <= (1 << 16), "bad bond dimension");
+    for (int i = 0; i < n_sites; ++i) total += (size_t)bond_dims[i] * 2 * bond_dims[i + 1];
+    ARG_CHECK(all_finite(tensors, 2 * total), "non-finite tensor entry");
+    bind(ctx);
+    *out = make_mps(ctx, n_sites, bond_dims, tensors).release();
+  });
+}
+
+tdvp_status tdvp_mps_bond_dims(tdvp_mps mps, int* n_sites, int* bond_dims, int capacity) {
+  if (!mps) return TDVP_ERR_ARG;
+  return guarded(mps->ctx, [&] {
+    if (n_sites) *n_sites = mps->N;
+    if (bond_dims) {
+      ARG_CHECK(capacity >= mps->N + 1, "capacity too small");
+      for (int b = 0; b <= mps->N; ++b) bond_dims[b] = mps->m[b];
+    }
+  });
+}
+
+tdvp_status tdvp_mps_to_host(tdvp_mps mps, double* tensors, size_t capacity) {
+  if (!mps || !tensors) return TDVP_ERR_ARG;
+  return guarded(mps->ctx, [&] {
+    if (!mps->valid) TDVP_THROW(TDVP_ERR_STATE, "MPS handle was invalidated by an earlier failure");
+    size_t need = 0;
+    for (int i = 0; i < mps->N; ++i) need += 2 * (size_t)mps->elems(i);
+    ARG_CHECK(capacity >= need, "output capacity too small");
+    bind(mps->ctx);
+    size_t off = 0;
+    for (int i = 0; i < mps->N; ++i) {
+      const size_t bytes = (size_t)mps->elems(i) * 16;
+      HIP_CHECK(hipMemcpyAsync(tensors + off, mps->t[i].p, bytes, hipMemcpyDeviceToHost, mps->ctx->stream));
+      off += 2 * (size_t)mps->elems(i);
+    }
+    mps->ctx->sync();
+  });
+}
+
+void tdvp_mps_destroy(tdvp_mps mps) {
+  if (!mps) return;
+  if (mps->ctx) {
+    (void)hipSetDevice(mps->ctx->device);
+    (void)hipStreamSynchronize(mps->ctx->stream);
+  }
+  delete mps;
+}
+
+// ------------------------------------------------------------ GSE-TDVP1
+tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* op,
+                              const tdvp_expand_params* params, tdvp_expand_stats* stats) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && psi && op && params, "bad arguments");
+    const tdvp_expand_params& p = *params;
+    ARG_CHECK(p.k >= 1 && p.k <= 16, "k must be in 1..16");
+    ARG_CHECK(p.chi_max >= 1, "chi_max must be >= 1");
+    ARG_CHECK(p.eps_K >= 0 && p.eps_M >= 0, "cutoffs must be >= 0");
+    ARG_CHECK(p.prec == TDVP_FP64 || p.prec == TDVP_FP32, "unknown precision");
+    for (int j = 0; j < n; ++j) {
+      ARG_CHECK(psi[j] && op[j], "NULL handle");
+      ARG_CHECK(psi[j]->N == op[j]->N(), "MPS and MPO site counts differ");
+      if (!psi[j]->valid || !op[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
+    }
+    bind(ctx);
+    for (int j = 0; j < n; ++j) {
+      tdvp_expand_stats st{};
+      try {
+        run_expand(ctx, *psi[j], *op[j], p, st);
+      } catch (...) {
+        psi[j]->valid = false;
+        throw;
+      }
+      if (stats) stats[j] = st;
+    }
+  });
+}
+
+tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, const tdvp_sweep_params* params,
+                       tdvp_sweep_stats* stats) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && psi && H && params, "bad arguments");
+    const tdvp_sweep_params& p = *params;
+    ARG_CHECK(std::isfinite(p.dt_re) && std::isfinite(p.dt_im), "non-finite time step");
+    ARG_CHECK(p.eps >= 0, "eps must be >= 0");
+    ARG_CHECK(p.chi_max >= 1, "chi_max must be >= 1");
+    ARG_CHECK(p.krylov_max >= 1 && p.krylov_max <= 64, "krylov_max must be in 1..64");
+    ARG_CHECK(p.krylov_tol >= 0, "krylov_tol must be >= 0");
+    ARG_CHECK(p.prec == TDVP_FP64 || p.prec == TDVP_FP32, "unknown precision");
+    for (int j = 0; j < n; ++j) {
+      ARG_CHECK(psi[j] && H[j], "NULL handle");
+      ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
+      if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
+    }
+    bind(ctx);
+    for (int j = 0; j < n; ++j) {
+      tdvp_sweep_stats st{};
+      try {
+        run_sweep(ctx, *psi[j], *H[j], p, st);
+      } catch (const TdvpError& e) {
+        if (e.code != TDVP_ERR_NOCONV) psi[j]->valid = false;
+        throw;
+      } catch (...) {
+        psi[j]->valid = false;
+        throw;
+      }
+      if (stats) stats[j] = st;
+    }
+  });
+}
+
+tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mpo* H, const tdvp_mps* other,
+                         tdvp_observables* out) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && psi && out, "bad arguments");
+    for (int j = 0; j < n; ++j) {
+      ARG_CHECK(psi[j], "NULL handle");
+      if (!psi[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
+      if (H) ARG_CHECK(H[j] && H[j]->N() == psi[j]->N, "MPO does not match the MPS");
+      if (other) ARG_CHECK(other[j] && other[j]->N == psi[j]->N, "other MPS does not match");
+    }
+    bind(ctx);
+    for (int j = 0; j < n; ++j) run_measure(ctx, *psi[j], H ? H[j] : nullptr, other ? other[j] : nullptr, out[j]);
+  });
+}
+
+// ---------------------------------------------------------- kernel level
+tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, int K, double alpha_re,
+                      double alpha_im, const void* A, long long lda, long long stride_a, const void* B, long long ldb,
+                      long long stride_b, double beta_re, double beta_im, void* C, long long ldc, long long stride_c,
+                      int batch) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(M >= 0 && N >= 0 && K >= 0 && batch >= 0, "negative size");
+    ARG_CHECK(op_a >= 0 && op_a <= 3 && op_b >= 0 && op_b <= 3, "bad op");
+    ARG_CHECK(prec == TDVP_FP64 || prec == TDVP_FP32, "unknown precision");
+    bind(ctx);
+    if (prec == TDVP_FP64)
+      kern::gemm<double>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
+                         zc(beta_re, beta_im), C, ldc, stride_c, batch);
+    else
+      kern::gemm<float>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
+                        zc(beta_re, beta_im), C, ldc, stride_c, batch);
+  });
+}
+
+
+tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
+                            const void* L, const void* Rt, const void* C, void* Y, void* workspace) {
+  if (!W_host) return TDVP_ERR_ARG;
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace, [&](const SiteTables& tb, void* w1, void* w2) {
+    if (prec == TDVP_FP64) heff_apply<double>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2);
+    else heff_apply<float>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2);
+  });
+}
+
+tdvp_status tdvp_keff_apply(tdvp_ctx ctx, int prec, int ml, int w, int mr, const void* L, const void* Rt,
+                            const void* X, void* Y, void* workspace) {
+  return kernel_call(ctx, prec, ml, w, w, mr, nullptr, workspace, [&](const SiteTables&, void* w1, void*) {
+    if (prec == TDVP_FP64) keff_apply<double>(ctx, ml, w, mr, L, Rt, X, Y, w1);
+    else keff_apply<float>(ctx, ml, w, mr, L, Rt, X, Y, w1);
+  });
+}
+
+tdvp_status tdvp_env_left(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
+                          const void* L, const void* A, void* Lout, void* workspace) {
+  if (!W_host) return TDVP_ERR_ARG;
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace, [&](const SiteTables& tb, void* w1, void* w2) {
+    if (prec == TDVP_FP64) env_left<double>(ctx, tb, ml, wl, wr, mr, L, A, Lout, w1, w2);
+    else env_left<float>(ctx, tb, ml, wl, wr, mr, L, A, Lout, w1, w2);
+  });
+}
+
+tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
+                           const void* Rt, const void* B, void* Rout, void* workspace) {
+  if (!W_host) return TDVP_ERR_ARG;
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace, [&](const SiteTables& tb, void* w1, void* w2) {
+    if (prec == TDVP_FP64) env_right<double>(ctx, tb, ml, wl, wr, mr, Rt, B, Rout, w1, w2);
+    else env_right<float>(ctx, tb, ml, wl, wr, mr, Rt, B, Rout, w1, w2);
+  });
+}
+
+}  // extern "C"

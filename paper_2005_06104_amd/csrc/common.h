@@ -1,0 +1,164 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "tdvp.h"
+
+using zc = std::complex<double>;
+
+struct TdvpError : std::runtime_error {
+  tdvp_status code;
+  TdvpError(tdvp_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TDVP_THROW(code, msg) throw TdvpError((code), (msg))
+#define HIP_CHECK(x)                                                                        \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      throw TdvpError(TDVP_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+#define ARG_CHECK(cond, msg)                  \
+  do {                                        \
+    if (!(cond)) TDVP_THROW(TDVP_ERR_ARG, msg); \
+  } while (0)
+
+struct tdvp_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  tdvp_alloc_fn alloc = nullptr;
+  tdvp_free_fn free_ = nullptr;
+  void* user = nullptr;
+  std::string last_error;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
+  void* dalloc(size_t bytes);
+  void dfree(void* p);
+  void sync();
+};
+
+// Growable device buffer owned through the context's allocator.
+struct DBuf {
+  tdvp_ctx_s* ctx = nullptr;
+  void* p = nullptr;
+  size_t cap = 0;
+  DBuf() = default;
+  explicit DBuf(tdvp_ctx_s* c) : ctx(c) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : ctx(o.ctx), p(o.p), cap(o.cap) { o.p = nullptr; o.cap = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); ctx = o.ctx; p = o.p; cap = o.cap; o.p = nullptr; o.cap = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p && ctx) ctx->dfree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  // Ensure capacity for `bytes`; contents are not preserved on growth.
+  void* ensure(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (bytes > cap) {
+      release();
+      p = ctx->dalloc(bytes);
+      cap = bytes;
+    }
+    return p;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------ kernels API
+// All launches are asynchronous on `s`.  Complex arrays are interleaved.
+namespace kern {
+
+// C = alpha op(A) op(B) + beta C, row-major, batched with element strides.
+template <typename T>
+void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
+          long long lda, long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
+          long long ldc, long long sc, int batch);
+
+// Sparse MPO contraction over two channel indices (MPO index, physical index):
+// out[p, q, o1, o2] = sum_e val[e] * in[p, q, i1(e), i2(e)] for the CSR rows
+// o = o1*2 + o2; all eight strides in elements of the precision.
+struct WTable {
+  const int* rowptr;      // device, n_out_ch + 1
+  const int* col;         // device, in-channel index i1*2 + i2
+  const double* val;      // device, complex128 coefficients
+  int n_in_ch, n_out_ch;
+};
+template <typename T>
+void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long nP, long long nQ,
+            long long isP, long long isQ, long long is1, long long is2, long long osP,
+            long long osQ, long long os1, long long os2);
+
+// complex128 vector helpers (n complex elements)
+// out[j] = sum_x conj(V[j*ldv + x]) w[x], j < nv (deterministic two-stage
+// reduction); without conjugation when conjugate = false
+void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n,
+           void* partial, int n_partial_blocks, void* out, bool conjugate = true);
+int zdots_blocks(long long n);
+// w[x] += sign * sum_j c[j] V[j*ldv + x]   (c complex128 on device)
+void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c,
+              double sign, long long n);
+// dst = a * src (complex scalar a)
+void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n);
+// precision conversions (complex)
+void z2c(hipStream_t s, void* dst, const void* src, long long n);
+void c2z(hipStream_t s, void* dst, const void* src, long long n);
+// copy a rows x cols block between matrices with leading dims (complex of `esize` bytes)
+void copy2d(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+            long long cols, int esize);
+// dst[i*ldd + j] = (mask(i,j) ? src[...] : 0), complex128; mode 0: keep j >= i, mode 1: keep j <= i
+void ztri(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+          long long cols, int mode);
+// dst[i*ldd + j] = conj(src[j*lds + i]) (conjugate transpose), complex128
+void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long long lds,
+                long long rows, long long cols);
+// Hermitian part in place: A = (A + A^H)/2, n x n complex128
+void zhermitize(hipStream_t s, void* A, long long n);
+// fill complex with value
+void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
+// per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
+void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
+// dst[i*ldd+j] = f[i] * src[i*lds+j] (rows) or f[j] * src[...] (cols); f device doubles
+void zscale_rows(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+                 long long cols, const double* f);
+void zscale_cols(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+                 long long cols, const double* f);
+
+}  // namespace kern
+
+// ------------------------------------------------------------ linear algebra (FP64)
+namespace la {
+// C[rows x cols] row-major = A R with A (rows x k) orthonormal columns, R (k x cols) upper,
+// k = min(rows, cols).  work must hold rows*cols complex128.
+void qr_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
+                 DBuf& tau);
+// C[rows x cols] = L Q with Q (k x cols) orthonormal rows, L (rows x k).
+void lq_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* Q, DBuf& work,
+                 DBuf& tau);
+// thin SVD of row-major C (rows x cols): U (rows x k), S (k, host), Vh (k x cols); k = min.
+void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
+                  void* Vh, DBuf& work, DBuf& work2);
+// eigh of row-major Hermitian H (n x n): eigenvalues descending (host) and the
+// matrix of eigenvectors-as-rows-conjugated: rows[j] = v_j^dagger (row-major n x n)
+void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows,
+                    DBuf& work);
+// host: eigen-decomposition of a small real symmetric matrix (Jacobi), ascending
+void jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V);
+}  // namespace la
+
+// truncation rule (same definition as the oracle's keep_count)
+int keep_count(const std::vector<double>& w_desc, double eps, double trace_ref, int cap, int min_keep);

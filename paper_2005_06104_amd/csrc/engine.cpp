@@ -1,0 +1,946 @@
+// GSE-TDVP1 drivers on the device: one-site TDVP sweep, global Krylov
+// vectors by the density-matrix MPO application, state-averaged basis
+// extension, measurements.  Tensor layouts (row-major, complex interleaved):
+//   site M[a,s,b]; MPO W[alpha,beta,s',s]; left env L[a',alpha,a];
+//   right env Rt[beta,b,b'] (bra index last so that the second stage of the
+//   effective Hamiltonian is a plain GEMM); double-layer env E[al,a,al',a'].
+// Environments L[i] and Rt[i] live on bond i (left of site i): L[i] covers
+// sites 0..i-1, Rt[i] covers sites i..N-1.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <cstring>
+
+namespace {
+
+constexpr int ZB = 16;  // bytes per complex128
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T> constexpr int cbytes() { return 2 * (int)sizeof(T); }
+
+void upload(tdvp_ctx_s* ctx, void* dst, const void* src, size_t bytes) {
+  HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+}
+
+void download(tdvp_ctx_s* ctx, void* dst, const void* src, size_t bytes) {
+  HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+}
+
+void set_one(tdvp_ctx_s* ctx, DBuf& b, int esize) {
+  b.ensure(esize);
+  kern::zfill(ctx->stream, b.p, zc(1.0, 0.0), 1, esize);
+}
+
+// ------------------------------------------------------------ FP64 scalars
+struct Scalars {
+  tdvp_ctx_s* ctx;
+  DBuf partial, out;
+  explicit Scalars(tdvp_ctx_s* c) : ctx(c), partial(c), out(c) {}
+  // <a|b> (conjugated) or sum a*b for n complex128 entries, returned to host
+  zc dot(const void* a, const void* b, long long n, bool conj = true) {
+    const int nb = kern::zdots_blocks(n);
+    partial.ensure((size_t)nb * ZB);
+    out.ensure(ZB);
+    kern::zdots(ctx->stream, a, n, 1, b, n, partial.p, nb, out.p, conj);
+    zc r;
+    download(ctx, &r, out.p, ZB);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    return r;
+  }
+  double norm(const void* a, long long n) { return std::sqrt(std::max(0.0, dot(a, a, n).real())); }
+};
+
+// ------------------------------------------------------------ Lanczos
+struct MatvecTimer {
+  tdvp_ctx_s* ctx = nullptr;
+  bool on = false, pending = false;
+  double ms = 0.0;
+  void start() {
+    if (on) HIP_CHECK(hipEventRecord(ctx->ev_a, ctx->stream));
+  }
+  void stop() {
+    if (on) {
+      HIP_CHECK(hipEventRecord(ctx->ev_b, ctx->stream));
+      pending = true;
+    }
+  }
+  void collect() {
+    if (!pending) return;
+    float t = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&t, ctx->ev_a, ctx->ev_b));
+    ms += t;
+    pending = false;
+  }
+};
+
+struct Lanczos {
+  tdvp_ctx_s* ctx;
+  DBuf V, partial, scal;
+  explicit Lanczos(tdvp_ctx_s* c) : ctx(c), V(c), partial(c), scal(c) {}
+
+  // x <- exp(-i dt H) x by Lanczos with full reorthogonalisation (classical
+  // Gram-Schmidt applied twice).  Returns the number of H applications.
+  template <class MV>
+  int run(MV&& mv, void* x, long long n, zc dt, double tol, int maxit, bool normalize, bool* unconv,
+          MatvecTimer* timer) {
+    *unconv = false;
+    if (n <= 0) return 0;
+    const int nb = kern::zdots_blocks(n);
+    partial.ensure((size_t)nb * (maxit + 1) * ZB);
+    scal.ensure(256 * ZB);
+    double2* S = scal.as<double2>();
+    char* Vb = static_cast<char*>(V.ensure((size_t)(maxit + 1) * n * ZB));
+    auto vec = [&](int j) { return static_cast<void*>(Vb + (size_t)j * n * ZB); };
+
+    kern::zdots(ctx->stream, x, n, 1, x, n, partial.p, nb, S + 128);
+    zc nrm2;
+    download(ctx, &nrm2, S + 128, ZB);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    const double nrm = std::sqrt(std::max(0.0, nrm2.real()));
+    if (!(nrm > 0.0)) {
+      if (!std::isfinite(nrm)) TDVP_THROW(TDVP_ERR_NUMERIC, "non-finite vector entering Lanczos");
+      return 0;
+    }
+    kern::zscale(ctx->stream, vec(0), x, zc(1.0 / nrm, 0.0), n);
+    std::vector<double> alpha, beta, Tm, lam, Q;
+    std::vector<zc> c;
+    int napp = 0, dim = 0;
+    for (int j = 0; j < maxit; ++j) {
+      void* w = vec(j + 1);
+      if (timer) timer->start();
+      mv(vec(j), w);
+      if (timer) timer->stop();
+      ++napp;
+      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S);
+      kern::zcombine(ctx->stream, w, Vb, n, j + 1, S, -1.0, n);
+      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S + 64);
+      kern::zcombine(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n);
+      kern::zdots(ctx->stream, w, n, 1, w, n, partial.p, nb, S + 128);
+      zc hv[2];
+      download(ctx, &hv[0], S + j, ZB);
+      download(ctx, &hv[1], S + 128, ZB);
+      HIP_CHECK(hipStreamSynchronize(ctx->stream));
+      if (timer) timer->collect();
+      const double a = hv[0].real(), b = std::sqrt(std::max(0.0, hv[1].real()));
+      if (!std::isfinite(a) || !std::isfinite(b)) TDVP_THROW(TDVP_ERR_NUMERIC, "non-finite Lanczos coefficient");
+      alpha.push_back(a);
+      dim = j + 1;
+      Tm.assign((size_t)dim * dim, 0.0);
+      for (int i = 0; i < dim; ++i) Tm[(size_t)i * dim + i] = alpha[i];
+      for (int i = 0; i + 1 < dim; ++i) {
+        Tm[(size_t)i * dim + i + 1] = beta[i];
+        Tm[(size_t)(i + 1) * dim + i] = beta[i];
+      }
+      la::jacobi_eigh(Tm, dim, lam, Q);
+      c.assign(dim, zc(0.0, 0.0));
+      for (int r = 0; r < dim; ++r) {
+        zc acc(0.0, 0.0);
+        for (int e = 0; e < dim; ++e)
+          acc += Q[(size_t)r * dim + e] * std::exp(zc(0.0, -1.0) * dt * lam[e]) * Q[(size_t)0 * dim + e];
+        c[r] = acc;
+      }
+      double cn = 0.0;
+      for (const zc& v : c) cn += std::norm(v);
+      cn = std::sqrt(cn);
+      double scale = 0.0;
+      for (double v : alpha) scale = std::max(scale, std::fabs(v));
+      for (double v : beta) scale = std::max(scale, v);
+      const bool conv = b * std::abs(c[dim - 1]) <= tol * cn || b <= 1e-14 * scale;
+      if (conv || j == maxit - 1) {
+        if (!conv) *unconv = true;
+        break;
+      }
+      beta.push_back(b);
+      kern::zscale(ctx->stream, w, w, zc(1.0 / b, 0.0), n);
+    }
+    double f = nrm;
+    if (normalize) {
+      double cn = 0.0;
+      for (const zc& v : c) cn += std::norm(v);
+      f = 1.0 / std::sqrt(cn);
+    }
+    std::vector<zc> cs(dim);
+    for (int r = 0; r < dim; ++r) cs[r] = f * c[r];
+    upload(ctx, S + 192, cs.data(), (size_t)dim * ZB);
+    kern::zfill(ctx->stream, x, zc(0.0, 0.0), n, ZB);
+    kern::zcombine(ctx->stream, x, Vb, n, dim, S + 192, 1.0, n);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));  // `cs` is pageable host memory
+    return napp;
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------ contractions
+template <typename T>
+void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2) {
+  hipStream_t s = ctx->stream;
+  // T1[(a',al),(s,b)] = L[(a',al),a] C[a,(s,b)]
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml * wl, 2 * mr, ml, 1.0, L, ml, 0, C, 2 * mr, 0, 0.0, ws1, 2 * mr, 0, 1);
+  // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
+  kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
+                  mr, (long long)wr * mr);
+  // Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b']
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, wr * mr, 1.0, ws2, (long long)wr * mr, 0, Rt, mr, 0, 0.0, Y,
+                mr, 0, 1);
+}
+
+template <typename T>
+void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
+                void* ws1) {
+  hipStream_t s = ctx->stream;
+  // Y1[(a',al),b] = L[(a',al),a] X[a,b];  Y[a',b'] = Y1[a',(al,b)] Rt[(al,b),b']
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml * w, mr, ml, 1.0, L, ml, 0, X, mr, 0, 0.0, ws1, mr, 0, 1);
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml, mr, w * mr, 1.0, ws1, (long long)w * mr, 0, Rt, mr, 0, 0.0, Y, mr, 0,
+                1);
+}
+
+template <typename T>
+void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L, const void* A,
+              void* Lout, void* ws1, void* ws2) {
+  hipStream_t s = ctx->stream;
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml * wl, 2 * mr, ml, 1.0, L, ml, 0, A, 2 * mr, 0, 0.0, ws1, 2 * mr, 0, 1);
+  kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
+                  mr, (long long)wr * mr);
+  // Lout[b',(be,b)] = sum_{(a',s')} conj(A[(a',s'),b']) T2[(a',s'),(be,b)]
+  kern::gemm<T>(s, TDVP_OP_C, TDVP_OP_N, mr, wr * mr, 2 * ml, 1.0, A, mr, 0, ws2, (long long)wr * mr, 0, 0.0, Lout,
+                (long long)wr * mr, 0, 1);
+}
+
+template <typename T>
+void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* Rt,
+               const void* B, void* Rout, void* ws1, void* ws2) {
+  hipStream_t s = ctx->stream;
+  // U1[be][(a,s),b'] = B[(a,s),b] Rt[be][b,b']   (batched over be)
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, mr, 1.0, B, mr, 0, Rt, mr, (long long)mr * mr, 0.0, ws1, mr,
+                2LL * ml * mr, wr);
+  // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
+  kern::wapply<T>(s, tb.B, ws1, ws2, ml, mr, 2LL * mr, 1, 2LL * ml * mr, mr, 2LL * mr, 1, 2LL * ml * mr, mr);
+  // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(B[a',(s',b')])
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, wl * ml, ml, 2 * mr, 1.0, ws2, 2LL * mr, 0, B, 2LL * mr, 0, 0.0, Rout, ml,
+                0, 1);
+}
+
+template void heff_apply<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
+                                 const void*, void*, void*, void*);
+template void heff_apply<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
+                                const void*, void*, void*, void*);
+template void keff_apply<double>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*);
+template void keff_apply<float>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*);
+template void env_left<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
+                               void*, void*);
+template void env_left<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
+                              void*, void*);
+template void env_right<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
+                                void*, void*);
+template void env_right<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
+                               void*, void*);
+
+// ------------------------------------------------------------ handles
+namespace {
+
+struct TableBlob {
+  std::vector<char> bytes;
+  size_t add(const void* p, size_t n) {
+    const size_t off = (bytes.size() + 15) & ~size_t(15);
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, p, n);
+    return off;
+  }
+};
+
+struct TableOffsets {
+  size_t rp, col, val;
+  int n_in, n_out;
+};
+
+TableOffsets add_table(TableBlob& blob, const std::vector<zc>& W, int wl, int wr, int mode) {
+  std::vector<int> rp, col;
+  std::vector<zc> val;
+  build_site_csr(W, wl, wr, mode, rp, col, val);
+  TableOffsets o;
+  o.rp = blob.add(rp.data(), rp.size() * sizeof(int));
+  o.col = blob.add(col.data(), std::max<size_t>(1, col.size()) * sizeof(int));
+  o.val = blob.add(val.data(), std::max<size_t>(1, val.size()) * sizeof(zc));
+  o.n_in = (mode == 0 ? wl : wr) * 2;
+  o.n_out = (mode == 0 ? wr : wl) * 2;
+  return o;
+}
+
+kern::WTable resolve(const char* base, const TableOffsets& o) {
+  return kern::WTable{reinterpret_cast<const int*>(base + o.rp), reinterpret_cast<const int*>(base + o.col),
+                      reinterpret_cast<const double*>(base + o.val), o.n_in, o.n_out};
+}
+
+}  // namespace
+
+SiteTables upload_tables(tdvp_ctx_s* ctx, const std::vector<zc>& W, int wl, int wr, DBuf& buf) {
+  TableBlob blob;
+  TableOffsets f = add_table(blob, W, wl, wr, 0), b = add_table(blob, W, wl, wr, 1), h = add_table(blob, W, wl, wr, 2);
+  buf.ensure(blob.bytes.size());
+  upload(ctx, buf.p, blob.bytes.data(), blob.bytes.size());
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  const char* base = static_cast<const char*>(buf.p);
+  SiteTables t;
+  t.F = resolve(base, f);
+  t.B = resolve(base, b);
+  t.BH = resolve(base, h);
+  t.nnz = site_nnz(W);
+  return t;
+}
+
+std::unique_ptr<tdvp_mpo_s> make_mpo(tdvp_ctx_s* ctx, HostMPO&& host) {
+  auto m = std::make_unique<tdvp_mpo_s>();
+  m->ctx = ctx;
+  m->host = std::move(host);
+  m->dev = DBuf(ctx);
+  const int N = m->host.N;
+  TableBlob blob;
+  std::vector<TableOffsets> offs;
+  for (int i = 0; i < N; ++i)
+    for (int mode = 0; mode < 3; ++mode)
+      offs.push_back(add_table(blob, m->host.W[i], m->host.w[i], m->host.w[i + 1], mode));
+  m->dev.ensure(blob.bytes.size());
+  upload(ctx, m->dev.p, blob.bytes.data(), blob.bytes.size());
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  const char* base = static_cast<const char*>(m->dev.p);
+  m->tab.resize(N);
+  for (int i = 0; i < N; ++i) {
+    m->tab[i].F = resolve(base, offs[3 * i]);
+    m->tab[i].B = resolve(base, offs[3 * i + 1]);
+    m->tab[i].BH = resolve(base, offs[3 * i + 2]);
+    m->tab[i].nnz = site_nnz(m->host.W[i]);
+  }
+  return m;
+}
+
+std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host) {
+  auto p = std::make_unique<tdvp_mps_s>();
+  p->ctx = ctx;
+  p->N = N;
+  p->m.assign(dims, dims + N + 1);
+  size_t off = 0;
+  for (int i = 0; i < N; ++i) {
+    p->t.emplace_back(ctx);
+    const size_t bytes = (size_t)p->elems(i) * ZB;
+    p->t[i].ensure(bytes);
+    upload(ctx, p->t[i].p, host + 2 * off, bytes);
+    off += p->elems(i);
+  }
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  return p;
+}
+
+// ------------------------------------------------------------ drivers
+namespace {
+
+struct Work {
+  tdvp_ctx_s* ctx;
+  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec;
+  Scalars sc;
+  Lanczos lz;
+  explicit Work(tdvp_ctx_s* c)
+      : ctx(c), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
+        dvec(c), sc(c), lz(c) {}
+};
+
+// site tensor in the working precision (a converted copy for FP32)
+template <typename T>
+const void* site_in(tdvp_ctx_s* ctx, const void* z, long long n, DBuf& conv) {
+  if (sizeof(T) == 8) return z;
+  conv.ensure((size_t)n * 8);
+  kern::z2c(ctx->stream, conv.p, z, n);
+  return conv.p;
+}
+
+// C = A B for complex128 row-major (A: M x K, B: K x N) into a fresh buffer
+void zmatmul(tdvp_ctx_s* ctx, int opa, int opb, int M, int N, int K, const void* A, long long lda, const void* B,
+             long long ldb, DBuf& out) {
+  out.ensure((size_t)M * N * ZB);
+  kern::gemm<double>(ctx->stream, opa, opb, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, out.p, N, 0, 1);
+}
+
+// Gauge move to the right: C (ml x 2 x mr) -> A (ml x 2 x k) and R (k x mr).
+int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& A, DBuf& R, double* disc) {
+  tdvp_ctx_s* ctx = W.ctx;
+  const int rows = 2 * ml, cols = mr, kk = std::min(rows, cols);
+  if (eps == 0.0) {
+    A.ensure((size_t)rows * kk * ZB);
+    R.ensure((size_t)kk * cols * ZB);
+    la::qr_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tau);
+    return kk;
+  }
+  std::vector<double> S;
+  W.tmpA.ensure((size_t)rows * kk * ZB);
+  W.tmpB.ensure((size_t)kk * cols * ZB);
+  la::svd_rowmajor(ctx, C, rows, cols, W.tmpA.p, S, W.tmpB.p, W.work, W.work2);
+  std::vector<double> w(kk);
+  double tot = 0.0;
+  for (int j = 0; j < kk; ++j) tot += (w[j] = S[j] * S[j]);
+  const int n = keep_count(w, eps, tot, chi_max, 1);
+  for (int j = n; j < kk; ++j) *disc += w[j];
+  A.ensure((size_t)rows * n * ZB);
+  R.ensure((size_t)n * cols * ZB);
+  kern::copy2d(ctx->stream, A.p, n, W.tmpA.p, kk, rows, n, ZB);
+  W.dvec.ensure(sizeof(double) * n);
+  upload(ctx, W.dvec.p, S.data(), sizeof(double) * n);
+  kern::zscale_rows(ctx->stream, R.p, cols, W.tmpB.p, cols, n, cols, W.dvec.as<double>());
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  return n;
+}
+
+// Gauge move to the left: C (ml x 2 x mr) -> L (ml x k) and B (k x 2 x mr).
+int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& L, DBuf& B, double* disc) {
+  tdvp_ctx_s* ctx = W.ctx;
+  const int rows = ml, cols = 2 * mr, kk = std::min(rows, cols);
+  if (eps == 0.0) {
+    L.ensure((size_t)rows * kk * ZB);
+    B.ensure((size_t)kk * cols * ZB);
+    la::lq_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tau);
+    return kk;
+  }
+  std::vector<double> S;
+  W.tmpA.ensure((size_t)rows * kk * ZB);
+  W.tmpB.ensure((size_t)kk * cols * ZB);
+  la::svd_rowmajor(ctx, C, rows, cols, W.tmpA.p, S, W.tmpB.p, W.work, W.work2);
+  std::vector<double> w(kk);
+  double tot = 0.0;
+  for (int j = 0; j < kk; ++j) tot += (w[j] = S[j] * S[j]);
+  const int n = keep_count(w, eps, tot, chi_max, 1);
+  for (int j = n; j < kk; ++j) *disc += w[j];
+  L.ensure((size_t)rows * n * ZB);
+  B.ensure((size_t)n * cols * ZB);
+  W.dvec.ensure(sizeof(double) * n);
+  upload(ctx, W.dvec.p, S.data(), sizeof(double) * n);
+  kern::zscale_cols(ctx->stream, L.p, n, W.tmpA.p, kk, rows, n, W.dvec.as<double>());
+  kern::copy2d(ctx->stream, B.p, cols, W.tmpB.p, cols, n, cols, ZB);
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  return n;
+}
+
+void left_canonicalize(Work& W, tdvp_mps_s& psi) {
+  tdvp_ctx_s* ctx = W.ctx;
+  DBuf A(ctx), R(ctx), nxt(ctx);
+  double disc = 0.0;
+  for (int i = 0; i + 1 < psi.N; ++i) {
+    const int ml = psi.m[i], mr = psi.m[i + 1];
+    const int k = split_left(W, psi.site(i), ml, mr, 0.0, 1 << 30, A, R, &disc);
+    std::swap(psi.t[i], A);
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, k, 2 * psi.m[i + 2], mr, R.p, mr, psi.site(i + 1), 2LL * psi.m[i + 2], nxt);
+    std::swap(psi.t[i + 1], nxt);
+    psi.m[i + 1] = k;
+  }
+}
+
+void right_canonicalize(Work& W, tdvp_mps_s& psi) {
+  tdvp_ctx_s* ctx = W.ctx;
+  DBuf Lm(ctx), B(ctx), prv(ctx);
+  double disc = 0.0;
+  for (int i = psi.N - 1; i > 0; --i) {
+    const int ml = psi.m[i], mr = psi.m[i + 1];
+    const int k = split_right(W, psi.site(i), ml, mr, 0.0, 1 << 30, Lm, B, &disc);
+    std::swap(psi.t[i], B);
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], k, ml, psi.site(i - 1), ml, Lm.p, k, prv);
+    std::swap(psi.t[i - 1], prv);
+    psi.m[i] = k;
+  }
+}
+
+template <typename T>
+void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
+                tdvp_sweep_stats& st) {
+  const int N = psi.N;
+  const int cb = cbytes<T>();
+  const zc dt(p.dt_re, p.dt_im), half = 0.5 * dt;
+  Work W(ctx);
+  std::vector<DBuf> L, R;
+  for (int i = 0; i <= N; ++i) {
+    L.emplace_back(ctx);
+    R.emplace_back(ctx);
+  }
+  set_one(ctx, L[0], cb);
+  set_one(ctx, R[N], cb);
+  MatvecTimer timer;
+  timer.ctx = ctx;
+  timer.on = true;
+  auto ensure_ws = [&](int ml, int wl, int wr, int mr) {
+    const size_t need = (size_t)2 * ml * mr * std::max(wl, wr) * cb;
+    W.ws1.ensure(need);
+    W.ws2.ensure(need);
+  };
+  auto build_R = [&](int i) {  // Rt[i] from Rt[i+1] and site i
+    const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
+    ensure_ws(ml, wl, wr, mr);
+    R[i].ensure((size_t)wl * ml * ml * cb);
+    const void* Bt = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
+    env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p);
+  };
+  auto build_L = [&](int i) {  // L[i+1] from L[i] and site i
+    const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
+    ensure_ws(ml, wl, wr, mr);
+    L[i + 1].ensure((size_t)mr * wr * mr * cb);
+    const void* At = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
+    env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p);
+  };
+  auto stepinfo = [&](int napp, bool unconv) {
+    st.max_lanczos = std::max(st.max_lanczos, napp);
+    if (unconv) {
+      ++st.n_unconverged;
+      if (p.strict) TDVP_THROW(TDVP_ERR_NOCONV, "Lanczos reached krylov_max without converging");
+    }
+  };
+  auto evolve_site = [&](int i, zc step) {
+    const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
+    const long long n = psi.elems(i);
+    ensure_ws(ml, wl, wr, mr);
+    const double flops = 8.0 * ((double)ml * wl * ml * 2 * mr + (double)H.tab[i].nnz * ml * mr +
+                                (double)2 * ml * wr * mr * mr);
+    auto mv = [&](const void* in, void* out) {
+      if (sizeof(T) == 8) {
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p);
+      } else {
+        W.xf.ensure((size_t)n * 8);
+        W.yf.ensure((size_t)n * 8);
+        kern::z2c(ctx->stream, W.xf.p, in, n);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p);
+        kern::c2z(ctx->stream, out, W.yf.p, n);
+      }
+      st.flops_matvec += flops;
+    };
+    bool unconv = false;
+    const int napp = W.lz.run(mv, psi.site(i), n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv, &timer);
+    st.n_matvec += napp;
+    stepinfo(napp, unconv);
+  };
+  auto evolve_bond = [&](int b, void* X, int ml, int mr, zc step) {
+    // K_eff on bond b with L[b] (ml x w x ml) and Rt[b] (w x mr x mr)
+    const int w = H.w(b);
+    const long long n = (long long)ml * mr;
+    W.ws1.ensure((size_t)ml * w * mr * cb);
+    auto mv = [&](const void* in, void* out) {
+      if (sizeof(T) == 8) {
+        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, in, out, W.ws1.p);
+      } else {
+        W.xf.ensure((size_t)n * 8);
+        W.yf.ensure((size_t)n * 8);
+        kern::z2c(ctx->stream, W.xf.p, in, n);
+        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, W.xf.p, W.yf.p, W.ws1.p);
+        kern::c2z(ctx->stream, out, W.yf.p, n);
+      }
+    };
+    bool unconv = false;
+    const int napp = W.lz.run(mv, X, n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv, nullptr);
+    st.n_keff += napp;
+    stepinfo(napp, unconv);
+  };
+
+  for (int i = N - 1; i >= 1; --i) build_R(i);
+  DBuf A(ctx), Rm(ctx), nxt(ctx);
+  // left -> right
+  for (int i = 0; i + 1 < N; ++i) {
+    evolve_site(i, half);
+    const int ml = psi.m[i], mr = psi.m[i + 1];
+    const int k = split_left(W, psi.site(i), ml, mr, p.eps, p.chi_max, A, Rm, &st.discarded);
+    std::swap(psi.t[i], A);
+    psi.m[i + 1] = k;  // site i is now ml x 2 x k; Rm is k x mr
+    build_L(i);
+    evolve_bond(i + 1, Rm.p, k, mr, -half);
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, k, 2 * psi.m[i + 2], mr, Rm.p, mr, psi.site(i + 1), 2LL * psi.m[i + 2], nxt);
+    std::swap(psi.t[i + 1], nxt);
+  }
+  evolve_site(N - 1, dt);
+  // right -> left
+  for (int i = N - 1; i >= 1; --i) {
+    if (i < N - 1) evolve_site(i, half);
+    const int ml = psi.m[i], mr = psi.m[i + 1];
+    const int k = split_right(W, psi.site(i), ml, mr, p.eps, p.chi_max, Rm, A, &st.discarded);
+    std::swap(psi.t[i], A);
+    psi.m[i] = k;  // site i is now k x 2 x mr; Rm (the L factor) is ml x k
+    build_R(i);
+    evolve_bond(i, Rm.p, ml, k, -half);
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], k, ml, psi.site(i - 1), ml, Rm.p, k, nxt);
+    std::swap(psi.t[i - 1], nxt);
+  }
+  if (N > 1) evolve_site(0, half);
+  // energy at site 0
+  {
+    const int ml = psi.m[0], mr = psi.m[1];
+    const long long n = psi.elems(0);
+    ensure_ws(ml, H.w(0), H.w(1), mr);
+    W.tmpC.ensure((size_t)n * ZB);
+    if (sizeof(T) == 8) {
+      heff_apply<T>(ctx, H.tab[0], ml, H.w(0), H.w(1), mr, L[0].p, R[1].p, psi.site(0), W.tmpC.p, W.ws1.p, W.ws2.p);
+    } else {
+      W.xf.ensure((size_t)n * 8);
+      W.yf.ensure((size_t)n * 8);
+      kern::z2c(ctx->stream, W.xf.p, psi.site(0), n);
+      heff_apply<T>(ctx, H.tab[0], ml, H.w(0), H.w(1), mr, L[0].p, R[1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p);
+      kern::c2z(ctx->stream, W.tmpC.p, W.yf.p, n);
+    }
+    const zc e = W.sc.dot(psi.site(0), W.tmpC.p, n);
+    const double nn = W.sc.dot(psi.site(0), psi.site(0), n).real();
+    st.energy = e.real() / nn;
+  }
+  st.ms_matvec = timer.ms;
+}
+
+// ---------------------------------------------------- density-matrix apply
+// Right double-layer environment step: E_i from E_{i+1} and site i.
+template <typename T>
+void dl_env_step(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* M,
+                 const void* E, void* Eout, DBuf& f1, DBuf& f2) {
+  hipStream_t s = ctx->stream;
+  const int cb = cbytes<T>();
+  const long long q = (long long)wr * mr;
+  f1.ensure((size_t)wr * 2 * ml * q * cb);
+  f2.ensure((size_t)std::max<long long>((long long)wl * ml * 2 * q, (long long)wl * ml * wl * 2 * mr) * cb);
+  // F1[y][(a,s),(Y,B)] = M[(a,s),b] E[y][b,(Y,B)]
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, (int)q, mr, 1.0, M, mr, 0, E, q, (long long)mr * q, 0.0, f1.p, q,
+                2LL * ml * q, wr);
+  // F2[x,a,t,(Y,B)] = sum_{y,s} W[x,y,t,s] F1[y,a,s,(Y,B)]
+  kern::wapply<T>(s, tb.B, f1.p, f2.p, ml, q, 2 * q, 1, 2LL * ml * q, q, 2 * q, 1, 2LL * ml * q, q);
+  // F3[(x,a),X,S,B] = sum_{Y,t} conj(W[X,Y,t,S]) F2[(x,a),t,Y,B]  (into f1)
+  f1.ensure((size_t)wl * ml * wl * 2 * mr * cb);
+  kern::wapply<T>(s, tb.BH, f2.p, f1.p, (long long)wl * ml, mr, 2 * q, 1, mr, q, (long long)wl * 2 * mr, 1, 2LL * mr,
+                  mr);
+  // E[(x,a,X),A] = sum_{(S,B)} F3[(x,a,X),(S,B)] conj(M[A,(S,B)])
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, wl * ml * wl, ml, 2 * mr, 1.0, f1.p, 2LL * mr, 0, M, 2LL * mr, 0, 0.0, Eout,
+                ml, 0, 1);
+}
+
+// out = normalise(trunc_{eps, chi_max}(op |in>)), left-canonical
+template <typename T>
+double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps, int chi_max, tdvp_mps_s& out) {
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  const int N = in.N;
+  const int cb = cbytes<T>();
+  // working-precision copies of the input tensors
+  std::vector<DBuf> Mt;
+  std::vector<const void*> Mp(N);
+  for (int i = 0; i < N; ++i) {
+    if (sizeof(T) == 8) {
+      Mp[i] = in.site(i);
+    } else {
+      Mt.emplace_back(ctx);
+      Mt.back().ensure((size_t)in.elems(i) * cb);
+      kern::z2c(s, Mt.back().p, in.site(i), in.elems(i));
+      Mp[i] = Mt.back().p;
+    }
+  }
+  std::vector<DBuf> E;
+  for (int i = 0; i <= N; ++i) E.emplace_back(ctx);
+  set_one(ctx, E[N], cb);
+  DBuf f1(ctx), f2(ctx);
+  for (int i = N - 1; i >= 1; --i) {
+    const int ml = in.m[i], mr = in.m[i + 1], wl = op.w(i), wr = op.w(i + 1);
+    E[i].ensure((size_t)wl * ml * wl * ml * cb);
+    dl_env_step<T>(ctx, op.tab[i], ml, wl, wr, mr, Mp[i], E[i + 1].p, E[i].p, f1, f2);
+  }
+  out.ctx = ctx;
+  out.N = N;
+  out.m.assign(N + 1, 1);
+  out.t.clear();
+  for (int i = 0; i < N; ++i) out.t.emplace_back(ctx);
+  DBuf X(ctx), Y(ctx), G(ctx), rho(ctx), rho64(ctx), rows(ctx), rowsT(ctx);
+  set_one(ctx, X, cb);
+  int kd = 1;
+  double disc = 0.0;
+  std::vector<double> lam;
+  for (int i = 0; i < N; ++i) {
+    const int ml = in.m[i], mr = in.m[i + 1], wl = op.w(i), wr = op.w(i + 1);
+    const long long q = (long long)wr * mr;
+    // Y[k,t,be,b] = sum X[k,al,a] M[a,s,b] W[al,be,t,s]
+    f1.ensure((size_t)kd * wl * 2 * mr * cb);
+    Y.ensure((size_t)kd * 2 * q * cb);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, kd * wl, 2 * mr, ml, 1.0, X.p, ml, 0, Mp[i], 2 * mr, 0, 0.0, f1.p, 2 * mr,
+                  0, 1);
+    kern::wapply<T>(s, op.tab[i].F, f1.p, Y.p, kd, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, 2 * q, 1, mr, q);
+    if (i == N - 1) {
+      // last site: C[k,t] = Y[k,t,0,0]
+      const long long n = 2LL * kd;
+      out.t[i].ensure((size_t)n * ZB);
+      if (sizeof(T) == 8)
+        HIP_CHECK(hipMemcpyAsync(out.t[i].p, Y.p, n * ZB, hipMemcpyDeviceToDevice, s));
+      else
+        kern::c2z(s, out.t[i].p, Y.p, n);
+      const double nr = W.sc.norm(out.t[i].p, n);
+      if (!(nr > 0.0) || !std::isfinite(nr)) TDVP_THROW(TDVP_ERR_NUMERIC, "Krylov vector vanished or is not finite");
+      kern::zscale(s, out.t[i].p, out.t[i].p, zc(1.0 / nr, 0.0), n);
+      out.m[i] = kd;
+      break;
+    }
+    // rho = Y E Y^dagger   (2kd x 2kd)
+    const int d2 = 2 * kd;
+    G.ensure((size_t)d2 * q * cb);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, d2, (int)q, (int)q, 1.0, Y.p, q, 0, E[i + 1].p, q, 0, 0.0, G.p, q, 0, 1);
+    rho.ensure((size_t)d2 * d2 * cb);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, d2, d2, (int)q, 1.0, G.p, q, 0, Y.p, q, 0, 0.0, rho.p, d2, 0, 1);
+    const void* r64 = rho.p;
+    if (sizeof(T) != 8) {
+      rho64.ensure((size_t)d2 * d2 * ZB);
+      kern::c2z(s, rho64.p, rho.p, (long long)d2 * d2);
+      r64 = rho64.p;
+    }
+    rows.ensure((size_t)d2 * d2 * ZB);
+    la::eigh_rows_desc(ctx, r64, d2, lam, rows.p, W.work);
+    double tr = 0.0;
+    for (double v : lam) tr += v;
+    const int n = keep_count(lam, eps, tr, chi_max, 1);
+    for (int j = n; j < d2; ++j) disc += std::max(0.0, lam[j]);
+    // A_i[(k,t),n] = v_n  (conjugate transpose of the first n rows)
+    out.t[i].ensure((size_t)d2 * n * ZB);
+    kern::zconjtrans(s, out.t[i].p, n, rows.p, d2, d2, n);
+    out.m[i + 1] = n;
+    out.m[i] = kd;
+    // X[n,(be,b)] = rows[0:n] Y
+    const void* rw = rows.p;
+    if (sizeof(T) != 8) {
+      rowsT.ensure((size_t)n * d2 * cb);
+      kern::z2c(s, rowsT.p, rows.p, (long long)n * d2);
+      rw = rowsT.p;
+    }
+    X.ensure((size_t)n * q * cb);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, n, (int)q, d2, 1.0, rw, d2, 0, Y.p, q, 0, 0.0, X.p, q, 0, 1);
+    kd = n;
+  }
+  out.m[0] = 1;
+  out.m[N] = 1;
+  HIP_CHECK(hipStreamSynchronize(s));
+  return disc;
+}
+
+// ------------------------------------------------------ basis extension
+void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps_M, int chi_max, int* n_added) {
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  const int N = psi.N;
+  DBuf Vh(ctx), Bp(ctx), Xs(ctx), P(ctx), rhob(ctx), rows(ctx), Pb(ctx), Mc(ctx), nxt(ctx), Mt(ctx);
+  std::vector<double> S, lam;
+  for (int i = N - 1; i >= 1; --i) {
+    const int ml = psi.m[i], mr = psi.m[i + 1], D = 2 * mr;
+    const void* C = psi.site(i);
+    const int kk = std::min(ml, D);
+    Vh.ensure((size_t)kk * D * ZB);
+    la::svd_rowmajor(ctx, C, ml, D, nullptr, S, Vh.p, W.work, W.work2);
+    int r = 0;
+    if (!S.empty() && S[0] > 0.0)
+      for (double v : S) r += (v > 1e-13 * S[0]) ? 1 : 0;
+    const int cap = std::min(chi_max - r, D - r);
+    // B' rows: B (r x D) then B_bar
+    Bp.ensure((size_t)D * D * ZB);  // r + n <= D rows
+    kern::copy2d(s, Bp.p, D, Vh.p, D, r, D, ZB);
+    int n = 0;
+    if (cap > 0 && !kv.empty()) {
+      // projected Krylov centers, stacked: X_l = Ct_l - (Ct_l B^dagger) B
+      int rows_tot = 0;
+      for (auto& k : kv) rows_tot += k.m[i];
+      Xs.ensure((size_t)rows_tot * D * ZB);
+      double tr_ref = 0.0;
+      int off = 0;
+      for (auto& k : kv) {
+        const int mt = k.m[i];
+        void* Xl = static_cast<char*>(Xs.p) + (size_t)off * D * ZB;
+        HIP_CHECK(hipMemcpyAsync(Xl, k.site(i), (size_t)mt * D * ZB, hipMemcpyDeviceToDevice, s));
+        if (r > 0) {
+          P.ensure((size_t)mt * r * ZB);
+          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, mt, r, D, 1.0, k.site(i), D, 0, Bp.p, D, 0, 0.0, P.p, r, 0, 1);
+          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mt, D, r, -1.0, P.p, r, 0, Bp.p, D, 0, 1.0, Xl, D, 0, 1);
+        }
+        tr_ref += W.sc.dot(k.site(i), k.site(i), (long long)mt * D).real();
+        off += mt;
+      }
+      // rho_bar = sum_l X_l^dagger X_l   (D x D)
+      rhob.ensure((size_t)D * D * ZB);
+      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, D, D, rows_tot, 1.0, Xs.p, D, 0, Xs.p, D, 0, 0.0, rhob.p, D, 0, 1);
+      rows.ensure((size_t)D * D * ZB);
+      la::eigh_rows_desc(ctx, rhob.p, D, lam, rows.p, W.work);
+      n = keep_count(lam, eps_M, tr_ref, cap, 0);
+      int nz = 0;
+      for (double v : lam) nz += (v > 1e-14 * std::max(tr_ref, 1e-300)) ? 1 : 0;
+      n = std::min(n, nz);
+      if (n > 0) {
+        void* Bbar = static_cast<char*>(Bp.p) + (size_t)r * D * ZB;
+        kern::copy2d(s, Bbar, D, rows.p, D, n, D, ZB);
+        if (r > 0) {
+          Pb.ensure((size_t)n * r * ZB);
+          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, r, D, 1.0, Bbar, D, 0, Bp.p, D, 0, 0.0, Pb.p, r, 0, 1);
+          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, D, r, -1.0, Pb.p, r, 0, Bp.p, D, 0, 1.0, Bbar, D, 0, 1);
+        }
+        // orthonormalise the rows of B_bar: QR of the column-major D x n view
+        W.work.ensure((size_t)n * D * ZB);
+        HIP_CHECK(hipMemcpyAsync(W.work.p, Bbar, (size_t)n * D * ZB, hipMemcpyDeviceToDevice, s));
+        // lq_rowmajor of the n x D row-major matrix gives orthonormal rows Q with the same span
+        Mt.ensure((size_t)n * n * ZB);
+        la::lq_rowmajor(ctx, W.work.p, n, D, Mt.p, Bbar, W.work2, W.tau);
+      }
+    }
+    const int mnew = r + n;
+    // center moves: C_{i-1} = A_{i-1} (C_i B'^dagger), same for every Krylov vector
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_C, ml, mnew, D, C, D, Bp.p, D, Mc);
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], mnew, ml, psi.site(i - 1), ml, Mc.p, mnew, nxt);
+    std::swap(psi.t[i - 1], nxt);
+    for (auto& k : kv) {
+      const int mt = k.m[i];
+      zmatmul(ctx, TDVP_OP_N, TDVP_OP_C, mt, mnew, D, k.site(i), D, Bp.p, D, Mc);
+      zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * k.m[i - 1], mnew, mt, k.site(i - 1), mt, Mc.p, mnew, nxt);
+      std::swap(k.t[i - 1], nxt);
+      k.m[i] = mnew;
+    }
+    // the new right-orthonormal tensor of psi at site i
+    DBuf Bnew(ctx);
+    Bnew.ensure((size_t)mnew * D * ZB);
+    HIP_CHECK(hipMemcpyAsync(Bnew.p, Bp.p, (size_t)mnew * D * ZB, hipMemcpyDeviceToDevice, s));
+    std::swap(psi.t[i], Bnew);
+    psi.m[i] = mnew;
+    *n_added += n;
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+}
+
+template <typename T>
+void expand_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const tdvp_expand_params& p,
+                 tdvp_expand_stats& st) {
+  Work W(ctx);
+  const int N = psi.N;
+  bool full = true;
+  for (int b = 1; b < N; ++b) {
+    const double cap = std::min<double>(p.chi_max, std::min(std::ldexp(1.0, std::min(b, 60)),
+                                                            std::ldexp(1.0, std::min(N - b, 60))));
+    if (psi.m[b] < cap) full = false;
+  }
+  if (p.k < 2 || (p.skip_if_full && full)) {
+    right_canonicalize(W, psi);
+    st.skipped = 1;
+  } else {
+    const double t0 = now_ms();
+    left_canonicalize(W, psi);
+    std::vector<tdvp_mps_s> kv(p.k - 1);
+    const tdvp_mps_s* prev = &psi;
+    for (int l = 0; l + 1 < p.k; ++l) {
+      st.discarded_K += denmat_apply<T>(W, *prev, op, p.eps_K, p.chi_max, kv[l]);
+      prev = &kv[l];
+      for (int b = 0; b <= N; ++b) st.krylov_max_bond = std::max(st.krylov_max_bond, kv[l].m[b]);
+    }
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    const double t1 = now_ms();
+    extension(W, psi, kv, p.eps_M, p.chi_max, &st.n_added);
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    st.ms_krylov = t1 - t0;
+    st.ms_extend = now_ms() - t1;
+  }
+  for (int b = 0; b <= N; ++b) st.max_bond = std::max(st.max_bond, psi.m[b]);
+}
+
+}  // namespace
+
+void run_sweep(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
+               tdvp_sweep_stats& st) {
+  const double t0 = now_ms();
+  if (p.prec == TDVP_FP64) sweep_impl<double>(ctx, psi, H, p, st);
+  else sweep_impl<float>(ctx, psi, H, p, st);
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  st.ms = now_ms() - t0;
+}
+
+void run_expand(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const tdvp_expand_params& p,
+                tdvp_expand_stats& st) {
+  if (p.prec == TDVP_FP64) expand_impl<double>(ctx, psi, op, p, st);
+  else expand_impl<float>(ctx, psi, op, p, st);
+}
+
+// ------------------------------------------------------------ measurement
+void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, const tdvp_mps_s* other,
+                 tdvp_observables& out) {
+  hipStream_t s = ctx->stream;
+  const int N = psi.N;
+  Work W(ctx);
+  // right transfers of <psi|psi>: Rtr[i][x,y] for sites i..N-1
+  std::vector<DBuf> Rtr;
+  for (int i = 0; i <= N; ++i) Rtr.emplace_back(ctx);
+  set_one(ctx, Rtr[N], ZB);
+  DBuf G(ctx), Tn(ctx), Tz(ctx), Tl(ctx);
+  for (int i = N - 1; i >= 0; --i) {
+    const int ml = psi.m[i], mr = psi.m[i + 1];
+    G.ensure((size_t)2 * ml * mr * ZB);
+    // G[(y,s),p] = sum_q M[(y,s),q] Rtr[p,q]
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_T, 2 * ml, mr, mr, 1.0, psi.site(i), mr, 0, Rtr[i + 1].p, mr, 0, 0.0, G.p,
+                       mr, 0, 1);
+    // Rtr[x,y] = sum_{(s,p)} conj(M[x,(s,p)]) G[y,(s,p)]
+    Rtr[i].ensure((size_t)ml * ml * ZB);
+    kern::gemm<double>(s, TDVP_OP_R, TDVP_OP_T, ml, ml, 2 * mr, 1.0, psi.site(i), 2LL * mr, 0, G.p, 2LL * mr, 0, 0.0,
+                       Rtr[i].p, ml, 0, 1);
+  }
+  zc nn;
+  download(ctx, &nn, Rtr[0].p, ZB);
+  HIP_CHECK(hipStreamSynchronize(s));
+  const double norm2 = nn.real();
+  out.norm = std::sqrt(std::max(0.0, norm2));
+  if (out.bond_dims)
+    for (int b = 0; b <= N; ++b) out.bond_dims[b] = psi.m[b];
+  if (out.sz) {
+    set_one(ctx, Tl, ZB);
+    for (int i = 0; i < N; ++i) {
+      const int ml = psi.m[i], mr = psi.m[i + 1];
+      G.ensure((size_t)ml * 2 * mr * ZB);
+      // G[x,(s,q)] = sum_y T[x,y] M[y,(s,q)]
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, ml, 2 * mr, ml, 1.0, Tl.p, ml, 0, psi.site(i), 2LL * mr, 0, 0.0, G.p,
+                         2LL * mr, 0, 1);
+      Tn.ensure((size_t)mr * mr * ZB);
+      Tz.ensure((size_t)mr * mr * ZB);
+      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mr, mr, 2 * ml, 1.0, psi.site(i), mr, 0, G.p, mr, 0, 0.0, Tn.p, mr, 0,
+                         1);
+      kern::zscale_phys(s, G.p, ml, mr, 0.5, -0.5);
+      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mr, mr, 2 * ml, 1.0, psi.site(i), mr, 0, G.p, mr, 0, 0.0, Tz.p, mr, 0,
+                         1);
+      const zc v = W.sc.dot(Tz.p, Rtr[i + 1].p, (long long)mr * mr, false);
+      out.sz[i] = v.real() / norm2;
+      std::swap(Tl, Tn);
+    }
+  }
+  if (H) {
+    std::vector<DBuf> envs;
+    envs.emplace_back(ctx);
+    envs.emplace_back(ctx);
+    set_one(ctx, envs[0], ZB);
+    for (int i = 0; i < N; ++i) {
+      const int ml = psi.m[i], mr = psi.m[i + 1], wl = H->w(i), wr = H->w(i + 1);
+      const size_t need = (size_t)2 * ml * mr * std::max(wl, wr) * ZB;
+      W.ws1.ensure(need);
+      W.ws2.ensure(need);
+      envs[1].ensure((size_t)mr * wr * mr * ZB);
+      env_left<double>(ctx, H->tab[i], ml, wl, wr, mr, envs[0].p, psi.site(i), envs[1].p, W.ws1.p, W.ws2.p);
+      std::swap(envs[0], envs[1]);
+    }
+    zc e;
+    download(ctx, &e, envs[0].p, ZB);
+    HIP_CHECK(hipStreamSynchronize(s));
+    out.energy = e.real() / norm2;
+  }
+  if (other) {
+    set_one(ctx, Tl, ZB);
+    for (int i = 0; i < N; ++i) {
+      const int ml = psi.m[i], mr = psi.m[i + 1], ol = other->m[i], orr = other->m[i + 1];
+      G.ensure((size_t)ol * 2 * mr * ZB);
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, ol, 2 * mr, ml, 1.0, Tl.p, ml, 0, psi.site(i), 2LL * mr, 0, 0.0, G.p,
+                         2LL * mr, 0, 1);
+      Tn.ensure((size_t)orr * mr * ZB);
+      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, orr, mr, 2 * ol, 1.0, other->site(i), orr, 0, G.p, mr, 0, 0.0, Tn.p,
+                         mr, 0, 1);
+      std::swap(Tl, Tn);
+    }
+    zc ov;
+    download(ctx, &ov, Tl.p, ZB);
+    HIP_CHECK(hipStreamSynchronize(s));
+    out.overlap_re = ov.real();
+    out.overlap_im = ov.imag();
+  }
+}

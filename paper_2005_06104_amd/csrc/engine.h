@@ -1,0 +1,58 @@
+// MPS / MPO handles and the GSE-TDVP1 drivers.
+#pragma once
+
+#include <memory>
+
+#include "common.h"
+#include "mpo_host.h"
+
+struct SiteTables {
+  kern::WTable F, B, BH;
+  long long nnz = 0;
+};
+
+struct tdvp_mpo_s {
+  tdvp_ctx_s* ctx = nullptr;
+  HostMPO host;
+  DBuf dev;                      // CSR tables of every site and mode
+  std::vector<SiteTables> tab;
+  bool valid = true;
+  int N() const { return host.N; }
+  int w(int b) const { return host.w[b]; }
+};
+
+struct tdvp_mps_s {
+  tdvp_ctx_s* ctx = nullptr;
+  int N = 0;
+  std::vector<int> m;            // N + 1 bond dims; site i is m[i] x 2 x m[i+1]
+  std::vector<DBuf> t;           // complex128 site tensors
+  bool valid = true;
+  long long elems(int i) const { return (long long)m[i] * 2 * m[i + 1]; }
+  double* site(int i) const { return t[i].as<double>(); }
+};
+
+std::unique_ptr<tdvp_mpo_s> make_mpo(tdvp_ctx_s* ctx, HostMPO&& host);
+std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host);
+
+void run_sweep(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
+               tdvp_sweep_stats& st);
+void run_expand(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const tdvp_expand_params& p,
+                tdvp_expand_stats& st);
+void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, const tdvp_mps_s* other,
+                 tdvp_observables& out);
+
+// kernel-level helpers used by the C-ABI
+template <typename T>
+void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2);
+template <typename T>
+void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
+                void* ws1);
+template <typename T>
+void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
+              const void* A, void* Lout, void* ws1, void* ws2);
+template <typename T>
+void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* Rt,
+               const void* B, void* Rout, void* ws1, void* ws2);
+// CSR tables for a single host W (kernel-level calls); keeps the device copy in `buf`
+SiteTables upload_tables(tdvp_ctx_s* ctx, const std::vector<zc>& W, int wl, int wr, DBuf& buf);

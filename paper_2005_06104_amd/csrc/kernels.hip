@@ -1,0 +1,581 @@
+// Device kernels of the GSE-TDVP1 hot path (gfx950 / CDNA4).
+//
+// * zgemm/cgemm: complex GEMM split into real MFMA products.  A complex
+//   product (Ar + i Ai)(Br + i Bi) is four real MFMA accumulations into the
+//   real and imaginary output tiles (Ar Br - Ai Bi, Ar Bi + Ai Br); operand
+//   tiles are de-interleaved into real and imaginary planes in LDS.
+//   FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32 (same lane
+//   layout).  These carry every contraction of the method: effective
+//   Hamiltonians, environments, MPO application, basis extension.
+// * wapply: contraction with the sparse MPO tensor over (MPO index, physical
+//   index), staged through LDS; memory bound.
+// * complex128 vector helpers for the Lanczos recurrence (FP64 always).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct VT;
+template <> struct VT<double> { using c2 = double2; using acc = d4; };
+template <> struct VT<float> { using c2 = float2; using acc = f4; };
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- GEMM
+// Block tile BM x BN complex outputs, BK complex per stage, 256 threads =
+// 4 waves in a 2 x 2 grid, each wave 32 x 32 outputs = 2 x 2 MFMA 16x16
+// tiles for the real and for the imaginary part.
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int PAD = 1;
+
+template <typename T, bool TA, bool CA, bool TB, bool CB>
+__global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T ai, const T* __restrict__ A,
+                                                   long long lda, long long sa, const T* __restrict__ B,
+                                                   long long ldb, long long sb, T br, T bi,
+                                                   T* __restrict__ C, long long ldc, long long sc) {
+  using c2 = typename VT<T>::c2;
+  using acc_t = typename VT<T>::acc;
+  __shared__ T As_r[BK][BM + PAD], As_i[BK][BM + PAD];
+  __shared__ T Bs_r[BK][BN + PAD], Bs_i[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const long long bz = blockIdx.z;
+  const c2* Ab = reinterpret_cast<const c2*>(A) + bz * sa;
+  const c2* Bb = reinterpret_cast<const c2*>(B) + bz * sb;
+  c2* Cb = reinterpret_cast<c2*>(C) + bz * sc;
+
+  constexpr int PER = (BM * BK) / NT;  // complex elements per thread per operand (4)
+  c2 ra[PER], rb[PER];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = tid + it * NT;
+      int m, k;
+      if (!TA) { m = idx / BK; k = idx % BK; } else { k = idx / BM; m = idx % BM; }
+      const int gm = m0 + m, gk = k0 + k;
+      c2 v;
+      v.x = T(0); v.y = T(0);
+      if (gm < M && gk < K) v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
+      if (CA) v.y = -v.y;
+      ra[it] = v;
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = tid + it * NT;
+      int n, k;
+      if (!TB) { k = idx / BN; n = idx % BN; } else { n = idx / BK; k = idx % BK; }
+      const int gn = n0 + n, gk = k0 + k;
+      c2 v;
+      v.x = T(0); v.y = T(0);
+      if (gn < N && gk < K) v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
+      if (CB) v.y = -v.y;
+      rb[it] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = tid + it * NT;
+      int m, k;
+      if (!TA) { m = idx / BK; k = idx % BK; } else { k = idx / BM; m = idx % BM; }
+      As_r[k][m] = ra[it].x;
+      As_i[k][m] = ra[it].y;
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = tid + it * NT;
+      int n, k;
+      if (!TB) { k = idx / BN; n = idx % BN; } else { n = idx / BK; k = idx % BK; }
+      Bs_r[k][n] = rb[it].x;
+      Bs_i[k][n] = rb[it].y;
+    }
+  };
+
+  acc_t cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = acc_t{0, 0, 0, 0};
+      ci[i][j] = acc_t{0, 0, 0, 0};
+    }
+
+  const int lr = lane & 15, lk = lane >> 4;
+  load(0);
+  store();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = (k0 + BK) < K;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + lk;
+      T a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        a_r[i] = As_r[kr][wm * 32 + i * 16 + lr];
+        a_i[i] = As_i[kr][wm * 32 + i * 16 + lr];
+        a_n[i] = -a_i[i];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        b_r[j] = Bs_r[kr][wn * 32 + j * 16 + lr];
+        b_i[j] = Bs_i[kr][wn * 32 + j * 16 + lr];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = mfma(a_r[i], b_r[j], cr[i][j]);
+          cr[i][j] = mfma(a_n[i], b_i[j], cr[i][j]);
+          ci[i][j] = mfma(a_r[i], b_i[j], ci[i][j]);
+          ci[i][j] = mfma(a_i[i], b_r[j], ci[i][j]);
+        }
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+
+  const bool has_beta = (br != T(0)) || (bi != T(0));
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // output row inside the 16x16 tile: the f32 MFMA puts rows 4*(lane/16)+r
+        // in a lane, the f64 MFMA rows (lane/16)+4*r (columns are lane%16 for both)
+        const int tr = sizeof(T) == 8 ? (lk + 4 * r) : (lk * 4 + r);
+        const int gm = m0 + wm * 32 + i * 16 + tr;
+        const int gn = n0 + wn * 32 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          const T xr = cr[i][j][r], xi = ci[i][j][r];
+          c2 o;
+          o.x = ar * xr - ai * xi;
+          o.y = ar * xi + ai * xr;
+          if (has_beta) {
+            const c2 old = Cb[(long long)gm * ldc + gn];
+            o.x += br * old.x - bi * old.y;
+            o.y += br * old.y + bi * old.x;
+          }
+          Cb[(long long)gm * ldc + gn] = o;
+        }
+      }
+}
+
+template <typename T, int OA, int OB>
+void launch_gemm(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda,
+                 long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
+                 long long ldc, long long sc, int batch) {
+  constexpr bool TA = (OA == TDVP_OP_T || OA == TDVP_OP_C), CA = (OA == TDVP_OP_C || OA == TDVP_OP_R);
+  constexpr bool TB = (OB == TDVP_OP_T || OB == TDVP_OP_C), CB = (OB == TDVP_OP_C || OB == TDVP_OP_R);
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+  hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB>), grid, dim3(NT), 0, s, M, N, K, T(alpha.real()),
+                     T(alpha.imag()), static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb,
+                     sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
+}
+
+template <typename T, int OA>
+void dispatch_b(hipStream_t s, int opb, int M, int N, int K, zc alpha, const void* A, long long lda,
+                long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
+                long long ldc, long long sc, int batch) {
+  switch (opb) {
+    case TDVP_OP_N: launch_gemm<T, OA, TDVP_OP_N>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_T: launch_gemm<T, OA, TDVP_OP_T>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_C: launch_gemm<T, OA, TDVP_OP_C>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_R: launch_gemm<T, OA, TDVP_OP_R>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    default: TDVP_THROW(TDVP_ERR_ARG, "bad GEMM op_b");
+  }
+}
+
+// ---------------------------------------------------------------- W apply
+constexpr int WQ = 64;      // q extent per block
+constexpr int WNT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T* __restrict__ out, long long nQ,
+                                                      long long isP, long long isQ, long long is1,
+                                                      long long is2, long long osP, long long osQ,
+                                                      long long os1, long long os2,
+                                                      const int* __restrict__ rowptr,
+                                                      const int* __restrict__ col,
+                                                      const double2* __restrict__ val, int n_in,
+                                                      int n_out) {
+  using c2 = typename VT<T>::c2;
+  extern __shared__ unsigned char smem_raw[];
+  c2* lds = reinterpret_cast<c2*>(smem_raw);  // [n_in][WQ]
+  const long long p = blockIdx.y;
+  const long long q0 = (long long)blockIdx.x * WQ;
+  const c2* inb = reinterpret_cast<const c2*>(in);
+  c2* outb = reinterpret_cast<c2*>(out);
+  for (int idx = threadIdx.x; idx < n_in * WQ; idx += WNT) {
+    const int c = idx / WQ, q = idx % WQ;
+    c2 v;
+    v.x = T(0); v.y = T(0);
+    if (q0 + q < nQ) v = inb[p * isP + (q0 + q) * isQ + (c >> 1) * is1 + (c & 1) * is2];
+    lds[idx] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n_out * WQ; idx += WNT) {
+    const int o = idx / WQ, q = idx % WQ;
+    if (q0 + q >= nQ) continue;
+    T sr = T(0), si = T(0);
+    for (int e = rowptr[o]; e < rowptr[o + 1]; ++e) {
+      const double2 w = val[e];
+      const c2 x = lds[col[e] * WQ + q];
+      sr += T(w.x) * x.x - T(w.y) * x.y;
+      si += T(w.x) * x.y + T(w.y) * x.x;
+    }
+    c2 r;
+    r.x = sr;
+    r.y = si;
+    outb[p * osP + (q0 + q) * osQ + (o >> 1) * os1 + (o & 1) * os2] = r;
+  }
+}
+
+// ---------------------------------------------------------------- vectors
+constexpr int VNT = 256;
+constexpr int DOT_CHUNK = 8192;
+
+__device__ inline double warp_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  v = warp_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < VNT / 64; ++i) t += sh[i];
+  return t;  // valid on thread 0
+}
+
+template <bool CONJ>
+__global__ __launch_bounds__(VNT) void zdots_partial_kernel(const double2* __restrict__ V, long long ldv, int nv,
+                                                             const double2* __restrict__ w, long long n,
+                                                             double2* __restrict__ partial) {
+  __shared__ double sh[VNT / 64];
+  const long long beg = (long long)blockIdx.x * DOT_CHUNK;
+  const long long end = min(n, beg + DOT_CHUNK);
+  for (int j = 0; j < nv; ++j) {
+    double sr = 0.0, si = 0.0;
+    const double2* v = V + (long long)j * ldv;
+    for (long long x = beg + threadIdx.x; x < end; x += VNT) {
+      const double2 a = v[x], b = w[x];
+      if (CONJ) {                    // conj(a) * b
+        sr += a.x * b.x + a.y * b.y;
+        si += a.x * b.y - a.y * b.x;
+      } else {                       // a * b
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+    }
+    const double tr = block_sum(sr, sh);
+    const double ti = block_sum(si, sh);
+    if (threadIdx.x == 0) partial[(long long)blockIdx.x * nv + j] = make_double2(tr, ti);
+  }
+}
+
+__global__ void zdots_final_kernel(const double2* __restrict__ partial, int nb, int nv,
+                                   double2* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nv) return;
+  double sr = 0.0, si = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double2 p = partial[(long long)b * nv + j];
+    sr += p.x;
+    si += p.y;
+  }
+  out[j] = make_double2(sr, si);
+}
+
+__global__ __launch_bounds__(VNT) void zcombine_kernel(double2* __restrict__ w, const double2* __restrict__ V,
+                                                        long long ldv, int nv, const double2* __restrict__ c,
+                                                        double sign, long long n) {
+  const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
+  if (x >= n) return;
+  double sr = 0.0, si = 0.0;
+  for (int j = 0; j < nv; ++j) {
+    const double2 cj = c[j];
+    const double2 v = V[(long long)j * ldv + x];
+    sr += cj.x * v.x - cj.y * v.y;
+    si += cj.x * v.y + cj.y * v.x;
+  }
+  double2 o = w[x];
+  o.x += sign * sr;
+  o.y += sign * si;
+  w[x] = o;
+}
+
+__global__ void zscale_kernel(double2* __restrict__ dst, const double2* __restrict__ src, double ar,
+                              double ai, long long n) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const double2 v = src[x];
+  dst[x] = make_double2(ar * v.x - ai * v.y, ar * v.y + ai * v.x);
+}
+
+__global__ void z2c_kernel(float2* __restrict__ dst, const double2* __restrict__ src, long long n) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const double2 v = src[x];
+  dst[x] = make_float2(float(v.x), float(v.y));
+}
+
+__global__ void c2z_kernel(double2* __restrict__ dst, const float2* __restrict__ src, long long n) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const float2 v = src[x];
+  dst[x] = make_double2(double(v.x), double(v.y));
+}
+
+template <typename E>
+__global__ void copy2d_kernel(E* __restrict__ dst, long long ldd, const E* __restrict__ src, long long lds,
+                              long long rows, long long cols) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const long long i = idx / cols, j = idx % cols;
+  dst[i * ldd + j] = src[i * lds + j];
+}
+
+__global__ void ztri_kernel(double2* __restrict__ dst, long long ldd, const double2* __restrict__ src,
+                            long long lds, long long rows, long long cols, int mode) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const long long i = idx / cols, j = idx % cols;
+  const bool keep = mode == 0 ? (j >= i) : (j <= i);
+  dst[i * ldd + j] = keep ? src[i * lds + j] : make_double2(0.0, 0.0);
+}
+
+__global__ void zconjtrans_kernel(double2* __restrict__ dst, long long ldd, const double2* __restrict__ src,
+                                  long long lds, long long rows, long long cols) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const long long i = idx / cols, j = idx % cols;
+  const double2 v = src[j * lds + i];
+  dst[i * ldd + j] = make_double2(v.x, -v.y);
+}
+
+__global__ void zhermitize_kernel(double2* __restrict__ A, long long n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const long long i = idx / n, j = idx % n;
+  if (j < i) return;
+  const double2 a = A[i * n + j], b = A[j * n + i];
+  if (i == j) {
+    A[i * n + j] = make_double2(a.x, 0.0);
+  } else {
+    const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    A[i * n + j] = h;
+    A[j * n + i] = make_double2(h.x, -h.y);
+  }
+}
+
+template <typename E>
+__global__ void fill_kernel(E* __restrict__ dst, E v, long long n) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) dst[x] = v;
+}
+
+__global__ void zscale_phys_kernel(double2* __restrict__ G, long long nx, long long nq, double f0,
+                                   double f1) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nx * 2 * nq) return;
+  const long long s = (idx / nq) & 1;
+  const double f = s ? f1 : f0;
+  double2 v = G[idx];
+  v.x *= f;
+  v.y *= f;
+  G[idx] = v;
+}
+
+__global__ void zscale_rc_kernel(double2* __restrict__ dst, long long ldd, const double2* __restrict__ src,
+                                 long long lds, long long rows, long long cols, const double* __restrict__ f,
+                                 int by_col) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const long long i = idx / cols, j = idx % cols;
+  const double g = by_col ? f[j] : f[i];
+  const double2 v = src[i * lds + j];
+  dst[i * ldd + j] = make_double2(g * v.x, g * v.y);
+}
+
+inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+namespace kern {
+
+template <typename T>
+void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda,
+          long long sa, const void* B, long long ldb, long long sb, zc beta, void* C, long long ldc,
+          long long sc, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  switch (opa) {
+    case TDVP_OP_N: dispatch_b<T, TDVP_OP_N>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_T: dispatch_b<T, TDVP_OP_T>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_C: dispatch_b<T, TDVP_OP_C>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_R: dispatch_b<T, TDVP_OP_R>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    default: TDVP_THROW(TDVP_ERR_ARG, "bad GEMM op_a");
+  }
+  HIP_CHECK(hipGetLastError());
+}
+template void gemm<double>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
+                           const void*, long long, long long, zc, void*, long long, long long, int);
+template void gemm<float>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
+                          const void*, long long, long long, zc, void*, long long, long long, int);
+
+template <typename T>
+void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long nP, long long nQ,
+            long long isP, long long isQ, long long is1, long long is2, long long osP, long long osQ,
+            long long os1, long long os2) {
+  if (nP <= 0 || nQ <= 0) return;
+  if (nP > 65535) TDVP_THROW(TDVP_ERR_ARG, "wapply: P extent too large");
+  dim3 grid((unsigned)((nQ + WQ - 1) / WQ), (unsigned)nP);
+  const size_t sh = (size_t)t.n_in_ch * WQ * sizeof(typename VT<T>::c2);
+  if (sh > 64 * 1024) TDVP_THROW(TDVP_ERR_ARG, "wapply: MPO bond dimension too large");
+  hipLaunchKernelGGL(wapply_kernel<T>, grid, dim3(WNT), sh, s, static_cast<const T*>(in), static_cast<T*>(out),
+                     nQ, isP, isQ, is1, is2, osP, osQ, os1, os2, t.rowptr, t.col,
+                     reinterpret_cast<const double2*>(t.val), t.n_in_ch, t.n_out_ch);
+  HIP_CHECK(hipGetLastError());
+}
+template void wapply<double>(hipStream_t, const WTable&, const void*, void*, long long, long long, long long,
+                             long long, long long, long long, long long, long long, long long, long long);
+template void wapply<float>(hipStream_t, const WTable&, const void*, void*, long long, long long, long long,
+                            long long, long long, long long, long long, long long, long long, long long);
+
+int zdots_blocks(long long n) { return (int)std::max<long long>(1, (n + DOT_CHUNK - 1) / DOT_CHUNK); }
+
+void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
+           int nb, void* out, bool conjugate) {
+  if (nv <= 0) return;
+  if (conjugate)
+    hipLaunchKernelGGL(zdots_partial_kernel<true>, dim3(nb), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
+                       nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
+  else
+    hipLaunchKernelGGL(zdots_partial_kernel<false>, dim3(nb), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
+                       nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
+  hipLaunchKernelGGL(zdots_final_kernel, dim3(nblk(nv, 64)), dim3(64), 0, s,
+                     static_cast<const double2*>(partial), nb, nv, static_cast<double2*>(out));
+  HIP_CHECK(hipGetLastError());
+}
+
+void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
+              long long n) {
+  if (n <= 0 || nv <= 0) return;
+  hipLaunchKernelGGL(zcombine_kernel, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
+                     static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(c), sign, n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zscale_kernel, dim3(nblk(n)), dim3(256), 0, s, static_cast<double2*>(dst),
+                     static_cast<const double2*>(src), a.real(), a.imag(), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void z2c(hipStream_t s, void* dst, const void* src, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(z2c_kernel, dim3(nblk(n)), dim3(256), 0, s, static_cast<float2*>(dst),
+                     static_cast<const double2*>(src), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void c2z(hipStream_t s, void* dst, const void* src, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(c2z_kernel, dim3(nblk(n)), dim3(256), 0, s, static_cast<double2*>(dst),
+                     static_cast<const float2*>(src), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void copy2d(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+            long long cols, int esize) {
+  if (rows <= 0 || cols <= 0) return;
+  if (esize == 16)
+    hipLaunchKernelGGL(copy2d_kernel<double2>, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<double2*>(dst),
+                       ldd, static_cast<const double2*>(src), lds, rows, cols);
+  else
+    hipLaunchKernelGGL(copy2d_kernel<float2>, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<float2*>(dst),
+                       ldd, static_cast<const float2*>(src), lds, rows, cols);
+  HIP_CHECK(hipGetLastError());
+}
+
+void ztri(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+          long long cols, int mode) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(ztri_kernel, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<double2*>(dst), ldd,
+                     static_cast<const double2*>(src), lds, rows, cols, mode);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+                long long cols) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(zconjtrans_kernel, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<double2*>(dst),
+                     ldd, static_cast<const double2*>(src), lds, rows, cols);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zhermitize(hipStream_t s, void* A, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zhermitize_kernel, dim3(nblk(n * n)), dim3(256), 0, s, static_cast<double2*>(A), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zfill(hipStream_t s, void* dst, zc v, long long n, int esize) {
+  if (n <= 0) return;
+  if (esize == 16)
+    hipLaunchKernelGGL(fill_kernel<double2>, dim3(nblk(n)), dim3(256), 0, s, static_cast<double2*>(dst),
+                       make_double2(v.real(), v.imag()), n);
+  else
+    hipLaunchKernelGGL(fill_kernel<float2>, dim3(nblk(n)), dim3(256), 0, s, static_cast<float2*>(dst),
+                       make_float2(float(v.real()), float(v.imag())), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1) {
+  if (nx <= 0 || nq <= 0) return;
+  hipLaunchKernelGGL(zscale_phys_kernel, dim3(nblk(nx * 2 * nq)), dim3(256), 0, s, static_cast<double2*>(G),
+                     nx, nq, f0, f1);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscale_rows(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+                 long long cols, const double* f) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(zscale_rc_kernel, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<double2*>(dst), ldd,
+                     static_cast<const double2*>(src), lds, rows, cols, f, 0);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscale_cols(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
+                 long long cols, const double* f) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL(zscale_rc_kernel, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<double2*>(dst), ldd,
+                     static_cast<const double2*>(src), lds, rows, cols, f, 1);
+  HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace kern

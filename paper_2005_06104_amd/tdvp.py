@@ -1,0 +1,422 @@
+"""Thin ctypes binding of the C-ABI in include/tdvp.h (argument marshalling only).
+
+Every numerical step runs in the HIP library ``lib/libtdvp_gfx950.so``; this
+module only converts Python/NumPy/PyTorch arguments to plain pointers and
+sizes.  Loading fails loudly when the library has not been built.  PyTorch
+provides device memory (its caching allocator is handed to the library) and
+the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libtdvp_gfx950.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "tdvp.h")
+
+TDVP_OK, TDVP_ERR_ARG, TDVP_ERR_ALLOC, TDVP_ERR_DEVICE, TDVP_ERR_NOCONV, TDVP_ERR_NUMERIC, TDVP_ERR_STATE = range(7)
+STATUS_NAMES = ["OK", "ERR_ARG", "ERR_ALLOC", "ERR_DEVICE", "ERR_NOCONV", "ERR_NUMERIC", "ERR_STATE"]
+TDVP_FP64, TDVP_FP32 = 0, 1
+OP_N, OP_T, OP_C, OP_R = 0, 1, 2, 3
+PREC = {"fp64": TDVP_FP64, "fp32": TDVP_FP32}
+
+
+class TdvpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+class tdvp_term(C.Structure):
+    _fields_ = [("site_i", C.c_int32), ("site_j", C.c_int32), ("op_i", C.c_int32), ("op_j", C.c_int32),
+                ("re", C.c_double), ("im", C.c_double)]
+
+
+class tdvp_expand_params(C.Structure):
+    _fields_ = [("k", C.c_int), ("eps_K", C.c_double), ("eps_M", C.c_double), ("chi_max", C.c_int),
+                ("prec", C.c_int), ("skip_if_full", C.c_int)]
+
+
+class tdvp_expand_stats(C.Structure):
+    _fields_ = [("ms_krylov", C.c_double), ("ms_extend", C.c_double), ("n_added", C.c_int),
+                ("max_bond", C.c_int), ("krylov_max_bond", C.c_int), ("skipped", C.c_int),
+                ("discarded_K", C.c_double)]
+
+
+class tdvp_sweep_params(C.Structure):
+    _fields_ = [("dt_re", C.c_double), ("dt_im", C.c_double), ("eps", C.c_double), ("chi_max", C.c_int),
+                ("krylov_tol", C.c_double), ("krylov_max", C.c_int), ("prec", C.c_int),
+                ("normalize", C.c_int), ("strict", C.c_int)]
+
+
+class tdvp_sweep_stats(C.Structure):
+    _fields_ = [("ms", C.c_double), ("ms_matvec", C.c_double), ("flops_matvec", C.c_double),
+                ("n_matvec", C.c_longlong), ("n_keff", C.c_longlong), ("max_lanczos", C.c_int),
+                ("n_unconverged", C.c_int), ("discarded", C.c_double), ("energy", C.c_double)]
+
+
+class tdvp_observables(C.Structure):
+    _fields_ = [("energy", C.c_double), ("norm", C.c_double), ("overlap_re", C.c_double),
+                ("overlap_im", C.c_double), ("sz", C.POINTER(C.c_double)), ("bond_dims", C.POINTER(C.c_int))]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def header_functions() -> List[str]:
+    """Names of the functions declared in include/tdvp.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(tdvp_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if not n.endswith("_fn")))
+
+
+def load():
+    """Load the HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d, ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+    sig = {
+        "tdvp_version": (C.c_char_p, []),
+        "tdvp_ctx_create": (i, [i, vp, ALLOC_FN, FREE_FN, vp, C.POINTER(vp)]),
+        "tdvp_ctx_destroy": (None, [vp]),
+        "tdvp_last_error": (C.c_char_p, [vp]),
+        "tdvp_synchronize": (i, [vp]),
+        "tdvp_create_mpo": (i, [vp, i, C.POINTER(tdvp_term), i, d, d, d, d, C.POINTER(vp), C.POINTER(i)]),
+        "tdvp_mpo_to_host": (i, [vp, C.POINTER(d), C.c_size_t]),
+        "tdvp_build_mpo_host": (i, [i, C.POINTER(tdvp_term), i, d, d, d, d, C.POINTER(i), C.POINTER(d), C.c_size_t]),
+        "tdvp_mpo_destroy": (None, [vp]),
+        "tdvp_mps_from_host": (i, [vp, i, C.POINTER(i), C.POINTER(d), C.POINTER(vp)]),
+        "tdvp_mps_bond_dims": (i, [vp, C.POINTER(i), C.POINTER(i), i]),
+        "tdvp_mps_to_host": (i, [vp, C.POINTER(d), C.c_size_t]),
+        "tdvp_mps_destroy": (None, [vp]),
+        "tdvp_expand_basis": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_expand_params),
+                                  C.POINTER(tdvp_expand_stats)]),
+        "tdvp_sweep": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_sweep_params),
+                           C.POINTER(tdvp_sweep_stats)]),
+        "tdvp_measure": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_observables)]),
+        "tdvp_gemm": (i, [vp, i, i, i, i, i, i, d, d, vp, ll, ll, vp, ll, ll, d, d, vp, ll, ll, i]),
+        "tdvp_heff_apply": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp, vp]),
+        "tdvp_keff_apply": (i, [vp, i, i, i, i, vp, vp, vp, vp, vp]),
+        "tdvp_env_left": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
+        "tdvp_env_right": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def terms_array(terms) -> "C.Array":
+    arr = (tdvp_term * max(1, len(terms)))()
+    for k, (i, j, oi, oj, cf) in enumerate(terms):
+        cf = complex(cf)
+        arr[k] = tdvp_term(int(i), int(j), int(oi), int(oj), cf.real, cf.imag)
+    return arr
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """tdvp_ctx bound to the current torch device and stream, allocating
+    through torch's caching allocator."""
+
+    def __init__(self, device: Optional[int] = None, use_torch_allocator: bool = True):
+        import torch
+        self.lib = load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._torch = torch
+        if use_torch_allocator:
+            dev, st = self.device, self.stream
+
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = ALLOC_FN(_alloc)
+            self._free = FREE_FN(_free)
+        else:
+            self._alloc = ALLOC_FN()
+            self._free = FREE_FN()
+        h = C.c_void_p()
+        st = self.lib.tdvp_ctx_create(self.device, C.c_void_p(self.stream.cuda_stream), self._alloc, self._free,
+                                      None, C.byref(h))
+        if st != TDVP_OK:
+            raise TdvpError(st, "tdvp_ctx_create failed")
+        self.h = h
+
+    def check(self, st: int, what: str):
+        if st != TDVP_OK:
+            raise TdvpError(st, f"{what}: {self.lib.tdvp_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdvp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tdvp_ctx_create(device: Optional[int] = None) -> Context:
+    return Context(device)
+
+
+def tdvp_version() -> str:
+    return load().tdvp_version().decode()
+
+
+def tdvp_synchronize(ctx: Context):
+    ctx.check(ctx.lib.tdvp_synchronize(ctx.h), "tdvp_synchronize")
+
+
+# ---------------------------------------------------------------------- MPO
+class MPO:
+    def __init__(self, ctx: Context, h, dims):
+        self.ctx, self.h, self.dims = ctx, h, list(dims)
+
+    @property
+    def n_sites(self):
+        return len(self.dims) - 1
+
+    def to_host(self) -> List[np.ndarray]:
+        n = sum(self.dims[i] * self.dims[i + 1] * 4 for i in range(self.n_sites))
+        buf = np.zeros(2 * n, dtype=np.float64)
+        self.ctx.check(self.ctx.lib.tdvp_mpo_to_host(self.h, _dptr(buf), buf.size), "tdvp_mpo_to_host")
+        z = buf.view(np.complex128)
+        out, off = [], 0
+        for i in range(self.n_sites):
+            sz = self.dims[i] * self.dims[i + 1] * 4
+            out.append(z[off:off + sz].reshape(self.dims[i], self.dims[i + 1], 2, 2).copy())
+            off += sz
+        return out
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.tdvp_mpo_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def tdvp_create_mpo(ctx: Context, n_sites: int, terms, c0: complex = 0.0, c1: complex = 1.0) -> MPO:
+    arr = terms_array(terms)
+    dims = np.zeros(n_sites + 1, dtype=np.int32)
+    h = C.c_void_p()
+    c0, c1 = complex(c0), complex(c1)
+    ctx.check(ctx.lib.tdvp_create_mpo(ctx.h, n_sites, arr, len(terms), c0.real, c0.imag, c1.real, c1.imag,
+                                      C.byref(h), _iptr(dims)), "tdvp_create_mpo")
+    return MPO(ctx, h, dims)
+
+
+def tdvp_build_mpo_host(n_sites: int, terms, c0: complex = 0.0, c1: complex = 1.0) -> List[np.ndarray]:
+    """Host-only MPO construction (no device needed)."""
+    lib = load()
+    arr = terms_array(terms)
+    dims = np.zeros(n_sites + 1, dtype=np.int32)
+    c0, c1 = complex(c0), complex(c1)
+    st = lib.tdvp_build_mpo_host(n_sites, arr, len(terms), c0.real, c0.imag, c1.real, c1.imag, _iptr(dims),
+                                 None, 0)
+    if st != TDVP_OK:
+        raise TdvpError(st, "tdvp_build_mpo_host")
+    n = sum(int(dims[i]) * int(dims[i + 1]) * 4 for i in range(n_sites))
+    buf = np.zeros(2 * n, dtype=np.float64)
+    st = lib.tdvp_build_mpo_host(n_sites, arr, len(terms), c0.real, c0.imag, c1.real, c1.imag, _iptr(dims),
+                                 _dptr(buf), buf.size)
+    if st != TDVP_OK:
+        raise TdvpError(st, "tdvp_build_mpo_host")
+    z = buf.view(np.complex128)
+    out, off = [], 0
+    for i in range(n_sites):
+        sz = int(dims[i] * dims[i + 1] * 4)
+        out.append(z[off:off + sz].reshape(int(dims[i]), int(dims[i + 1]), 2, 2).copy())
+        off += sz
+    return out
+
+
+# ---------------------------------------------------------------------- MPS
+class MPS:
+    def __init__(self, ctx: Context, h, n_sites: int):
+        self.ctx, self.h, self.n_sites = ctx, h, n_sites
+
+    def bond_dims(self) -> List[int]:
+        dims = np.zeros(self.n_sites + 1, dtype=np.int32)
+        n = C.c_int()
+        self.ctx.check(self.ctx.lib.tdvp_mps_bond_dims(self.h, C.byref(n), _iptr(dims), dims.size),
+                       "tdvp_mps_bond_dims")
+        return [int(x) for x in dims]
+
+    def to_host(self) -> List[np.ndarray]:
+        return tdvp_mps_to_host(self)
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.tdvp_mps_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def tdvp_mps_from_host(ctx: Context, tensors: Sequence[np.ndarray]) -> MPS:
+    N = len(tensors)
+    dims = np.array([tensors[0].shape[0]] + [t.shape[2] for t in tensors], dtype=np.int32)
+    flat = np.concatenate([np.ascontiguousarray(t, dtype=np.complex128).ravel() for t in tensors])
+    buf = flat.view(np.float64)
+    h = C.c_void_p()
+    ctx.check(ctx.lib.tdvp_mps_from_host(ctx.h, N, _iptr(dims), _dptr(buf), C.byref(h)), "tdvp_mps_from_host")
+    return MPS(ctx, h, N)
+
+
+def tdvp_mps_to_host(mps: MPS) -> List[np.ndarray]:
+    dims = mps.bond_dims()
+    n = sum(dims[i] * 2 * dims[i + 1] for i in range(mps.n_sites))
+    buf = np.zeros(2 * n, dtype=np.float64)
+    mps.ctx.check(mps.ctx.lib.tdvp_mps_to_host(mps.h, _dptr(buf), buf.size), "tdvp_mps_to_host")
+    z = buf.view(np.complex128)
+    out, off = [], 0
+    for i in range(mps.n_sites):
+        sz = dims[i] * 2 * dims[i + 1]
+        out.append(z[off:off + sz].reshape(dims[i], 2, dims[i + 1]).copy())
+        off += sz
+    return out
+
+
+# ------------------------------------------------------------ GSE-TDVP1 step
+def _handles(objs):
+    arr = (C.c_void_p * len(objs))()
+    for k, o in enumerate(objs):
+        arr[k] = o.h
+    return arr
+
+
+def tdvp_expand_basis(ctx: Context, psi: Sequence[MPS], op: Sequence[MPO], k: int, eps_K: float, eps_M: float,
+                      chi_max: int, prec: str = "fp64", skip_if_full: bool = True) -> List[dict]:
+    p = tdvp_expand_params(int(k), float(eps_K), float(eps_M), int(chi_max), PREC[prec], int(bool(skip_if_full)))
+    stats = (tdvp_expand_stats * len(psi))()
+    ctx.check(ctx.lib.tdvp_expand_basis(ctx.h, len(psi), _handles(psi), _handles(op), C.byref(p), stats),
+              "tdvp_expand_basis")
+    return [{f: getattr(s, f) for f, _ in tdvp_expand_stats._fields_} for s in stats]
+
+
+def tdvp_sweep(ctx: Context, psi: Sequence[MPS], H: Sequence[MPO], dt: complex, eps: float = 0.0,
+               chi_max: int = 1 << 30, krylov_tol: float = 1e-12, krylov_max: int = 30, prec: str = "fp64",
+               normalize: bool = False, strict: bool = False) -> List[dict]:
+    dt = complex(dt)
+    p = tdvp_sweep_params(dt.real, dt.imag, float(eps), int(min(chi_max, 2 ** 31 - 1)), float(krylov_tol),
+                          int(krylov_max), PREC[prec], int(bool(normalize)), int(bool(strict)))
+    stats = (tdvp_sweep_stats * len(psi))()
+    ctx.check(ctx.lib.tdvp_sweep(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats), "tdvp_sweep")
+    return [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
+
+
+def tdvp_measure(ctx: Context, psi: Sequence[MPS], H: Optional[Sequence[MPO]] = None,
+                 other: Optional[Sequence[MPS]] = None) -> List[dict]:
+    n = len(psi)
+    obs = (tdvp_observables * n)()
+    keep = []
+    for j, m in enumerate(psi):
+        sz = np.zeros(m.n_sites, dtype=np.float64)
+        bd = np.zeros(m.n_sites + 1, dtype=np.int32)
+        keep.append((sz, bd))
+        obs[j].sz = _dptr(sz)
+        obs[j].bond_dims = _iptr(bd)
+    ctx.check(ctx.lib.tdvp_measure(ctx.h, n, _handles(psi), _handles(H) if H else None,
+                                   _handles(other) if other else None, obs), "tdvp_measure")
+    out = []
+    for j in range(n):
+        out.append({"energy": obs[j].energy, "norm": obs[j].norm,
+                    "overlap": complex(obs[j].overlap_re, obs[j].overlap_im),
+                    "sz": keep[j][0].copy(), "bond_dims": [int(x) for x in keep[j][1]]})
+    return out
+
+
+# -------------------------------------------------------- kernel-level calls
+def _tp(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _prec_of(t) -> int:
+    import torch
+    if t.dtype == torch.complex128:
+        return TDVP_FP64
+    if t.dtype == torch.complex64:
+        return TDVP_FP32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def tdvp_gemm(ctx: Context, op_a: int, op_b: int, M: int, N: int, K: int, alpha, A, lda, stride_a, B, ldb, stride_b,
+              beta, Cout, ldc, stride_c, batch: int = 1):
+    alpha, beta = complex(alpha), complex(beta)
+    ctx.check(ctx.lib.tdvp_gemm(ctx.h, _prec_of(A), op_a, op_b, M, N, K, alpha.real, alpha.imag, _tp(A), lda,
+                                stride_a, _tp(B), ldb, stride_b, beta.real, beta.imag, _tp(Cout), ldc, stride_c,
+                                batch), "tdvp_gemm")
+
+
+def _w_host(W: np.ndarray):
+    Wc = np.ascontiguousarray(W, dtype=np.complex128)
+    return Wc, Wc.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def tdvp_heff_apply(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, workspace=None):
+    ml, wl, _ = L.shape
+    wr, mr, _ = Rt.shape
+    Wc, wp = _w_host(W)
+    ctx.check(ctx.lib.tdvp_heff_apply(ctx.h, _prec_of(L), ml, wl, wr, mr, wp, _tp(L), _tp(Rt), _tp(Cin), _tp(Y),
+                                      _tp(workspace)), "tdvp_heff_apply")
+
+
+def tdvp_keff_apply(ctx: Context, L, Rt, X, Y, workspace=None):
+    ml, w, _ = L.shape
+    _, mr, _ = Rt.shape
+    ctx.check(ctx.lib.tdvp_keff_apply(ctx.h, _prec_of(L), ml, w, mr, _tp(L), _tp(Rt), _tp(X), _tp(Y),
+                                      _tp(workspace)), "tdvp_keff_apply")
+
+
+def tdvp_env_left(ctx: Context, W: np.ndarray, L, A, Lout, workspace=None):
+    ml, wl, _ = L.shape
+    mr = A.shape[2]
+    wr = W.shape[1]
+    Wc, wp = _w_host(W)
+    ctx.check(ctx.lib.tdvp_env_left(ctx.h, _prec_of(L), ml, wl, wr, mr, wp, _tp(L), _tp(A), _tp(Lout),
+                                    _tp(workspace)), "tdvp_env_left")
+
+
+def tdvp_env_right(ctx: Context, W: np.ndarray, Rt, B, Rout, workspace=None):
+    wr, mr, _ = Rt.shape
+    ml = B.shape[0]
+    wl = W.shape[0]
+    Wc, wp = _w_host(W)
+    ctx.check(ctx.lib.tdvp_env_right(ctx.h, _prec_of(Rt), ml, wl, wr, mr, wp, _tp(Rt), _tp(B), _tp(Rout),
+                                     _tp(workspace)), "tdvp_env_right")

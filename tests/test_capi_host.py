@@ -1,0 +1,77 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/tdvp.h declares, its host MPO builder agrees with the oracle's, and
+bad arguments are rejected with TDVP_ERR_ARG."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from paper_2005_06104_amd import inputs as I
+from paper_2005_06104_amd import tdvp as T
+
+pytestmark = pytest.mark.skipif(not os.path.exists(T.LIB_PATH), reason="HIP library not built")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(T.LIB_PATH)
+    declared = T.header_functions()
+    assert "tdvp_sweep" in declared and "tdvp_expand_basis" in declared and len(declared) >= 20
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    assert T.tdvp_version().startswith("tdvp-mi355x")
+
+
+@pytest.mark.parametrize("case", ["snake", "zigzag", "cyl", "oat", "complex"])
+def test_host_mpo_matches_oracle(case):
+    from oracle import ed, mpo
+    if case == "snake":
+        lat = I.ladder(3, 1.0, 1.0, "snake"); N = lat.n_sites; terms = I.heisenberg_terms(lat.couplings)
+    elif case == "zigzag":
+        lat = I.ladder(3, 1.0, 0.0, "zigzag"); N = lat.n_sites; terms = I.heisenberg_terms(lat.couplings)
+    elif case == "cyl":
+        lat = I.cylinder(4, 2, 1.0, 0.5); N = lat.n_sites; terms = I.heisenberg_terms(lat.couplings)
+    elif case == "oat":
+        N = 7; terms = I.oat_terms(N)
+    else:
+        rng = np.random.default_rng(5); N = 6; terms = []
+        for _ in range(20):
+            i, j = rng.choice(N, size=2, replace=False)
+            terms.append((int(i), int(j), int(rng.integers(0, 4)), int(rng.integers(0, 4)),
+                          complex(rng.standard_normal(), rng.standard_normal())))
+        terms += [(i, -1, 3, 0, 0.3 + 0.1j * i) for i in range(N)]
+    c0, c1 = 1.0, -0.2j
+    Ws = T.tdvp_build_mpo_host(N, terms, c0, c1)
+    ref = mpo.build_mpo(N, terms, c0, c1)
+    assert [W.shape[0] for W in Ws] == [W.shape[0] for W in ref]
+    assert np.abs(mpo.mpo_to_dense(Ws) - ed.hamiltonian(N, terms, c0, c1).toarray()).max() < 1e-12
+    if case == "oat":
+        assert max(W.shape[0] for W in Ws) == 3
+
+
+def test_host_mpo_rejects_bad_terms():
+    lib = T.load()
+    dims = np.zeros(5, dtype=np.int32)
+    for bad in ([(0, 9, 3, 3, 1.0)], [(0, 0, 3, 3, 1.0)], [(0, 1, 7, 3, 1.0)], [(-1, 1, 3, 3, 1.0)]):
+        arr = T.terms_array(bad)
+        st = lib.tdvp_build_mpo_host(4, arr, 1, 0.0, 0.0, 1.0, 0.0, T._iptr(dims), None, 0)
+        assert st == T.TDVP_ERR_ARG
+    arr = T.terms_array([(0, 1, 3, 3, 1.0)])
+    assert lib.tdvp_build_mpo_host(0, arr, 1, 0.0, 0.0, 1.0, 0.0, T._iptr(dims), None, 0) == T.TDVP_ERR_ARG
+    assert lib.tdvp_build_mpo_host(4, arr, 1, 0.0, 0.0, 1.0, 0.0, None, None, 0) == T.TDVP_ERR_ARG
+    # output capacity too small
+    buf = np.zeros(4)
+    assert lib.tdvp_build_mpo_host(4, arr, 1, 0.0, 0.0, 1.0, 0.0, T._iptr(dims), T._dptr(buf), 4) == T.TDVP_ERR_ARG
+
+
+def test_null_handles_are_rejected():
+    lib = T.load()
+    assert lib.tdvp_sweep(None, 1, None, None, None, None) == T.TDVP_ERR_ARG
+    assert lib.tdvp_expand_basis(None, 1, None, None, None, None) == T.TDVP_ERR_ARG
+    assert lib.tdvp_measure(None, 1, None, None, None, None) == T.TDVP_ERR_ARG
+    assert lib.tdvp_synchronize(None) == T.TDVP_ERR_ARG
+    h = C.c_void_p()
+    assert lib.tdvp_ctx_create(0, None, T.ALLOC_FN(), T.FREE_FN(), None, None) == T.TDVP_ERR_ARG
+    lib.tdvp_ctx_destroy(None)
+    lib.tdvp_mps_destroy(None)
+    lib.tdvp_mpo_destroy(None)
