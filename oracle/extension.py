@@ -6,8 +6,9 @@ with their centers on the last site (eq. (1)).  Sweeping from the right end
 to site 1, at site i:
 
 1. SVD the center of psi without truncation, C = U S B (reading: only
-   directions with singular value <= 1e-13 s_1 are dropped -- they carry no
-   weight and would otherwise put arbitrary rows into B);
+   directions whose weight s^2 is at round-off level, s^2 <= 1e-14 s_1^2 --
+   the numerical-zero floor shared by every cut -- are left out; they carry
+   no weight and would otherwise put arbitrary rows into B);
 2. project every Krylov center on the null space of B, X_l = C~_l P with
    P = 1 - B^dagger B, and mix rho_bar = sum_l X_l^dagger X_l = P rho~ P
    (eqs. (5)-(6));
@@ -30,13 +31,13 @@ import numpy as np
 from . import mps as M
 from .tdvp import keep_count
 
-RANK_REL = 1e-13
+RANK_WEIGHT_REL = 1e-14
 
 
 def _rank(S):
     if len(S) == 0 or S[0] <= 0.0:
         return 0
-    return int(np.count_nonzero(S > RANK_REL * S[0]))
+    return int(np.count_nonzero(S ** 2 > RANK_WEIGHT_REL * S[0] ** 2))
 
 
 def extension_step(C, Ct_list, eps_M, chi_max, use_gram_of_stack=False):
