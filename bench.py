@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""GSE-TDVP1 time-step benchmark on one MI355X.
+
+One "step" is a full GSE-TDVP1 time step through the C-ABI: global Krylov
+vectors by MPO application + basis extension (tdvp_expand_basis), the
+one-site TDVP sweep (tdvp_sweep) and the measurement of energy, norm and
+<S^z_i> (tdvp_measure).  Inputs are seeded synthetic workloads resident on
+the device before the timed region starts.
+
+Default workload: rung-decoupled Heisenberg ladder, leg length 32 (64 sites,
+zigzag path), imaginary time from a seeded random MPS of bond dimension 16,
+dtau = 0.5, Krylov order k = 3, chi_max = 256, FP64.  W warmup steps are
+evolved first (the bond dimension grows), then K steps are timed.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TDVP sweep time/step & H_eff matvec TFLOP/s, mixed vs FP64, at fixed fidelity"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+DTYPE = {"fp64": "f64", "fp32": "f32"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, seconds: float, chi_probe: int):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload:
+    GSE-TDVP1 steps from the same seeded initial state until `seconds` have
+    elapsed, plus one one-site H_eff application at bond dimension chi_probe."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import gse, mpo, tdvp as OT
+    from paper_2005_06104_amd import inputs as I
+
+    N = w.lattice.n_sites
+    Ws = mpo.build_mpo(N, w.terms)
+    Wop = mpo.build_mpo(N, w.terms, 1.0, -1j * w.tau)
+    psi = w.initial_mps()
+    t0 = time.perf_counter()
+    n = 0
+    bonds = 1
+    while time.perf_counter() - t0 < seconds and n < w.n_steps:
+        psi, _ = gse.gse_step(psi, Ws, Wop, w.dt, w.k, w.eps_K, w.eps_M, w.eps, w.chi_max, 1e-12, 30, w.normalize)
+        n += 1
+        bonds = max(t.shape[2] for t in psi)
+    el = time.perf_counter() - t0
+    # one H_eff application at the full bond dimension (synthetic tensors)
+    wmax = max(W.shape[1] for W in Ws)
+    L = I.random_hermitian_env(chi_probe, wmax, 1)
+    R = I.random_hermitian_env(chi_probe, wmax, 2)
+    C = I.random_complex((chi_probe, 2, chi_probe), 3)
+    Wm = I.random_mpo_site(wmax, wmax, 4)
+    t1 = time.perf_counter()
+    OT.heff_apply(L, Wm, R, C)
+    mv_ms = (time.perf_counter() - t1) * 1e3
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": n / el if el > 0 else None, "unit": "GSE-TDVP1 steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"first {n} steps of the same workload from the same seed (bond dims up to {bonds}), "
+                      f"{el:.1f} s; one-site H_eff application at chi={chi_probe}, w={wmax}: {mv_ms:.0f} ms",
+            "matvec_ms": mv_ms, "steps_timed": n, "max_bond_reached": int(bonds)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=14)
+    ap.add_argument("--workload", type=int, default=1, help="0..3: the benchmark workloads")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the GSE-TDVP1 sweep of one MPS is sequential over sites and "
+              f"this build has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2005_06104_amd import inputs as I
+    from paper_2005_06104_amd import tdvp as T
+
+    torch.cuda.set_device(0)
+    w = I.workload(args.workload)
+    prec = args.prec or ("fp64" if w.prec == "fp64" else "fp32")
+    N = w.lattice.n_sites
+    ctx = T.Context(0)
+    H = T.tdvp_create_mpo(ctx, N, w.terms)
+    op = T.tdvp_create_mpo(ctx, N, w.terms, 1.0, -1j * w.tau)
+    psi = T.tdvp_mps_from_host(ctx, w.initial_mps())
+    torch.cuda.synchronize()
+
+    def step():
+        e = T.tdvp_expand_basis(ctx, [psi], [op], w.k, w.eps_K, w.eps_M, w.chi_max, prec)[0]
+        s = T.tdvp_sweep(ctx, [psi], [H], w.dt, w.eps, w.chi_max, 1e-12, 30, prec, w.normalize)[0]
+        m = T.tdvp_measure(ctx, [psi], [H])[0]
+        return e, s, m
+
+    log(f"workload {w.name}: N={N}, chi_max={w.chi_max}, k={w.k}, dt={w.dt}, prec={prec}")
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        e, s, m = step()
+        log(f"warmup {i}: {1e3 * (time.perf_counter() - t):.1f} ms, max bond {max(m['bond_dims'])}, "
+            f"E={m['energy']:.10f}, matvecs {s['n_matvec']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = {"ms_heff_gemm": 0.0, "flops_heff_gemm": 0.0, "n_heff_gemm": 0, "ms_matvec": 0.0, "flops_matvec": 0.0,
+           "n_matvec": 0, "ms_sweep": 0.0, "ms_krylov": 0.0, "ms_extend": 0.0}
+    per_step = []
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        e, s, m = step()
+        per_step.append(1e3 * (time.perf_counter() - ts))
+        for k in ("ms_heff_gemm", "flops_heff_gemm", "n_heff_gemm", "ms_matvec", "flops_matvec", "n_matvec"):
+            acc[k] += s[k]
+        acc["ms_sweep"] += s["ms"]
+        acc["ms_krylov"] += e["ms_krylov"]
+        acc["ms_extend"] += e["ms_extend"]
+        log(f"step {i}: {per_step[-1]:.1f} ms (krylov {e['ms_krylov']:.1f}, extend {e['ms_extend']:.1f}, "
+            f"sweep {s['ms']:.1f}), max bond {max(m['bond_dims'])}, E={m['energy']:.10f}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / max(args.steps, 1)
+    gemm_tf = acc["flops_heff_gemm"] / (acc["ms_heff_gemm"] * 1e-3) / 1e12 if acc["ms_heff_gemm"] > 0 else None
+    mv_tf = acc["flops_matvec"] / (acc["ms_matvec"] * 1e-3) / 1e12 if acc["ms_matvec"] > 0 else None
+    peak = PEAK_TFLOPS[prec]
+    final = T.tdvp_measure(ctx, [psi], [H])[0]
+    out = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "GSE-TDVP1 steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_sites": N, "chi_max": w.chi_max, "k": w.k,
+                   "dt": [w.dt.real, w.dt.imag], "eps_K": w.eps_K, "eps_M": w.eps_M, "eps": w.eps,
+                   "mpo_w_max": max(H.dims), "parallelism": "single GPU"},
+        "matvec_tflops": mv_tf,
+        "heff_gemm_tflops": gemm_tf,
+        "split_ms_per_step": {"krylov": acc["ms_krylov"] / args.steps, "extend": acc["ms_extend"] / args.steps,
+                              "sweep": acc["ms_sweep"] / args.steps,
+                              "heff_matvec": acc["ms_matvec"] / args.steps},
+        "heff_gemm_launches": acc["n_heff_gemm"],
+        "heff_gemm_avg_us": 1e3 * acc["ms_heff_gemm"] / acc["n_heff_gemm"] if acc["n_heff_gemm"] else None,
+        "max_bond": max(final["bond_dims"]),
+        "energy": final["energy"],
+        "roofline": {"bound": "mfma", "kernel": "one-site H_eff GEMM (gemm_kernel TAG=1)",
+                     "achieved": gemm_tf, "peak": peak, "unit": "TFLOP/s",
+                     "frac": (gemm_tf / peak) if gemm_tf else None, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, min(w.chi_max, max(final["bond_dims"])))
+    del psi, H, op
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

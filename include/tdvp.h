@@ -187,6 +187,9 @@ typedef struct {
   int n_unconverged;         /* local steps that reached krylov_max                       */
   double discarded;          /* weight dropped at gauge moves (eps > 0)                   */
   double energy;             /* <C|H_eff|C>/<C|C> at site 0 after the sweep                */
+  double ms_heff_gemm;       /* device time of the two GEMM launches of each H_eff application */
+  double flops_heff_gemm;    /* algorithmic flops of those GEMM launches                        */
+  long long n_heff_gemm;     /* number of those GEMM launches                                   */
 } tdvp_sweep_stats;
 
 /* Step 3 of GSE-TDVP1: one symmetric one-site TDVP sweep (left to right by

@@ -120,6 +120,8 @@ tdvp_status tdvp_ctx_create(int device, void* hip_stream, tdvp_alloc_fn alloc, t
       TDVP_THROW(TDVP_ERR_DEVICE, "rocblas_set_stream failed");
     HIP_CHECK(hipEventCreate(&ctx->ev_a));
     HIP_CHECK(hipEventCreate(&ctx->ev_b));
+    HIP_CHECK(hipEventCreate(&ctx->ev_c));
+    HIP_CHECK(hipEventCreate(&ctx->ev_d));
   });
   if (st != TDVP_OK) {
     if (ctx->blas) rocblas_destroy_handle(ctx->blas);
@@ -136,6 +138,8 @@ void tdvp_ctx_destroy(tdvp_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+  if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
+  if (ctx->ev_d) (void)hipEventDestroy(ctx->ev_d);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   delete ctx;
 }

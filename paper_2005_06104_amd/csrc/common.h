@@ -39,7 +39,7 @@ struct tdvp_ctx_s {
   tdvp_free_fn free_ = nullptr;
   void* user = nullptr;
   std::string last_error;
-  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
 
   void* dalloc(size_t bytes);
   void dfree(void* p);
@@ -88,6 +88,12 @@ template <typename T>
 void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
           long long lda, long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
           long long ldc, long long sc, int batch);
+
+// The same product (NN, alpha = 1, beta = 0, no batch) as a separate kernel
+// instantiation reserved for the one-site effective Hamiltonian.
+template <typename T>
+void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
+               void* C, long long ldc);
 
 // Sparse MPO contraction over two channel indices (MPO index, physical index):
 // out[p, q, o1, o2] = sum_e val[e] * in[p, q, i1(e), i2(e)] for the CSR rows

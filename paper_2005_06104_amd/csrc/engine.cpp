@@ -58,28 +58,6 @@ struct Scalars {
 };
 
 // ------------------------------------------------------------ Lanczos
-struct MatvecTimer {
-  tdvp_ctx_s* ctx = nullptr;
-  bool on = false, pending = false;
-  double ms = 0.0;
-  void start() {
-    if (on) HIP_CHECK(hipEventRecord(ctx->ev_a, ctx->stream));
-  }
-  void stop() {
-    if (on) {
-      HIP_CHECK(hipEventRecord(ctx->ev_b, ctx->stream));
-      pending = true;
-    }
-  }
-  void collect() {
-    if (!pending) return;
-    float t = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&t, ctx->ev_a, ctx->ev_b));
-    ms += t;
-    pending = false;
-  }
-};
-
 struct Lanczos {
   tdvp_ctx_s* ctx;
   DBuf V, partial, scal;
@@ -114,9 +92,7 @@ struct Lanczos {
     int napp = 0, dim = 0;
     for (int j = 0; j < maxit; ++j) {
       void* w = vec(j + 1);
-      if (timer) timer->start();
       mv(vec(j), w);
-      if (timer) timer->stop();
       ++napp;
       kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S);
       kern::zcombine(ctx->stream, w, Vb, n, j + 1, S, -1.0, n);
@@ -181,16 +157,20 @@ struct Lanczos {
 // ------------------------------------------------------------ contractions
 template <typename T>
 void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-                const void* Rt, const void* C, void* Y, void* ws1, void* ws2) {
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm) {
   hipStream_t s = ctx->stream;
+  if (tm) tm->mark(0);
   // T1[(a',al),(s,b)] = L[(a',al),a] C[a,(s,b)]
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml * wl, 2 * mr, ml, 1.0, L, ml, 0, C, 2 * mr, 0, 0.0, ws1, 2 * mr, 0, 1);
+  kern::gemm_heff<T>(s, ml * wl, 2 * mr, ml, L, ml, C, 2 * mr, ws1, 2 * mr);
+  if (tm) tm->mark(1);
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
                   mr, (long long)wr * mr);
+  if (tm) tm->mark(2);
   // Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b']
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, wr * mr, 1.0, ws2, (long long)wr * mr, 0, Rt, mr, 0, 0.0, Y,
-                mr, 0, 1);
+  kern::gemm_heff<T>(s, 2 * ml, mr, wr * mr, ws2, (long long)wr * mr, Rt, mr, Y, mr);
+  if (tm) tm->mark(3);
+  if (tm) tm->gemm_flops += 8.0 * ((double)ml * wl * ml * 2 * mr + (double)2 * ml * wr * mr * mr);
 }
 
 template <typename T>
@@ -230,9 +210,9 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
 }
 
 template void heff_apply<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
-                                 const void*, void*, void*, void*);
+                                 const void*, void*, void*, void*, MatvecTimer*);
 template void heff_apply<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
-                                const void*, void*, void*, void*);
+                                const void*, void*, void*, void*, MatvecTimer*);
 template void keff_apply<double>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*);
 template void keff_apply<float>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*);
 template void env_left<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
@@ -368,9 +348,24 @@ void zmatmul(tdvp_ctx_s* ctx, int opa, int opb, int M, int N, int K, const void*
   kern::gemm<double>(ctx->stream, opa, opb, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, out.p, N, 0, 1);
 }
 
+// Truncated gauge moves.  The weights are the eigenvalues of the Gram matrix
+// of C (= squared singular values) and the kept subspace is spanned by the
+// leading eigenvectors, i.e. the leading singular subspace, so the cut and
+// the truncated state are those of a truncated SVD; an orthonormal basis of
+// the kept subspace then comes from one QR/LQ and the remainder factor is the
+// exact projection of C on it.
+int trunc_count(const std::vector<double>& lam, double eps, int chi_max, double* disc) {
+  double tot = 0.0;
+  for (double v : lam) tot += std::max(0.0, v);
+  const int n = keep_count(lam, eps, tot, chi_max, 1);
+  for (size_t j = n; j < lam.size(); ++j) *disc += std::max(0.0, lam[j]);
+  return n;
+}
+
 // Gauge move to the right: C (ml x 2 x mr) -> A (ml x 2 x k) and R (k x mr).
 int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& A, DBuf& R, double* disc) {
   tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
   const int rows = 2 * ml, cols = mr, kk = std::min(rows, cols);
   if (eps == 0.0) {
     A.ensure((size_t)rows * kk * ZB);
@@ -378,28 +373,28 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     la::qr_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tau);
     return kk;
   }
-  std::vector<double> S;
-  W.tmpA.ensure((size_t)rows * kk * ZB);
-  W.tmpB.ensure((size_t)kk * cols * ZB);
-  la::svd_rowmajor(ctx, C, rows, cols, W.tmpA.p, S, W.tmpB.p, W.work, W.work2);
-  std::vector<double> w(kk);
-  double tot = 0.0;
-  for (int j = 0; j < kk; ++j) tot += (w[j] = S[j] * S[j]);
-  const int n = keep_count(w, eps, tot, chi_max, 1);
-  for (int j = n; j < kk; ++j) *disc += w[j];
+  // G = C^dagger C (cols x cols); rows of V^dagger from its eigendecomposition
+  W.tmpA.ensure((size_t)cols * cols * ZB);
+  W.tmpB.ensure((size_t)cols * cols * ZB);
+  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, cols, cols, rows, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, cols, 0, 1);
+  std::vector<double> lam;
+  la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
+  const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
+  // Y = C V_n (rows x n), A = orth(Y), R = A^dagger C
+  W.tmpC.ensure((size_t)rows * n * ZB);
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, W.tmpB.p, cols, 0, 0.0, W.tmpC.p, n, 0, 1);
   A.ensure((size_t)rows * n * ZB);
   R.ensure((size_t)n * cols * ZB);
-  kern::copy2d(ctx->stream, A.p, n, W.tmpA.p, kk, rows, n, ZB);
-  W.dvec.ensure(sizeof(double) * n);
-  upload(ctx, W.dvec.p, S.data(), sizeof(double) * n);
-  kern::zscale_rows(ctx->stream, R.p, cols, W.tmpB.p, cols, n, cols, W.dvec.as<double>());
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  W.tmpA.ensure((size_t)n * n * ZB);
+  la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, 0, C, cols, 0, 0.0, R.p, cols, 0, 1);
   return n;
 }
 
 // Gauge move to the left: C (ml x 2 x mr) -> L (ml x k) and B (k x 2 x mr).
 int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& L, DBuf& B, double* disc) {
   tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
   const int rows = ml, cols = 2 * mr, kk = std::min(rows, cols);
   if (eps == 0.0) {
     L.ensure((size_t)rows * kk * ZB);
@@ -407,22 +402,21 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     la::lq_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tau);
     return kk;
   }
-  std::vector<double> S;
-  W.tmpA.ensure((size_t)rows * kk * ZB);
-  W.tmpB.ensure((size_t)kk * cols * ZB);
-  la::svd_rowmajor(ctx, C, rows, cols, W.tmpA.p, S, W.tmpB.p, W.work, W.work2);
-  std::vector<double> w(kk);
-  double tot = 0.0;
-  for (int j = 0; j < kk; ++j) tot += (w[j] = S[j] * S[j]);
-  const int n = keep_count(w, eps, tot, chi_max, 1);
-  for (int j = n; j < kk; ++j) *disc += w[j];
+  // G = C C^dagger (rows x rows); rows of U^dagger from its eigendecomposition
+  W.tmpA.ensure((size_t)rows * rows * ZB);
+  W.tmpB.ensure((size_t)rows * rows * ZB);
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, rows, 0, 1);
+  std::vector<double> lam;
+  la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
+  const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
+  // Y = U_n^dagger C (n x cols), B = orth rows of Y, L = C B^dagger
+  W.tmpC.ensure((size_t)n * cols * ZB);
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, 0, C, cols, 0, 0.0, W.tmpC.p, cols, 0, 1);
   L.ensure((size_t)rows * n * ZB);
   B.ensure((size_t)n * cols * ZB);
-  W.dvec.ensure(sizeof(double) * n);
-  upload(ctx, W.dvec.p, S.data(), sizeof(double) * n);
-  kern::zscale_cols(ctx->stream, L.p, n, W.tmpA.p, kk, rows, n, W.dvec.as<double>());
-  kern::copy2d(ctx->stream, B.p, cols, W.tmpB.p, cols, n, cols, ZB);
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  W.tmpA.ensure((size_t)n * n * ZB);
+  la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, B.p, cols, 0, 0.0, L.p, n, 0, 1);
   return n;
 }
 
@@ -505,12 +499,12 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
                                 (double)2 * ml * wr * mr * mr);
     auto mv = [&](const void* in, void* out) {
       if (sizeof(T) == 8) {
-        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, &timer);
       } else {
         W.xf.ensure((size_t)n * 8);
         W.yf.ensure((size_t)n * 8);
         kern::z2c(ctx->stream, W.xf.p, in, n);
-        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p, &timer);
         kern::c2z(ctx->stream, out, W.yf.p, n);
       }
       st.flops_matvec += flops;
@@ -590,6 +584,9 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     st.energy = e.real() / nn;
   }
   st.ms_matvec = timer.ms;
+  st.ms_heff_gemm = timer.gemm_ms;
+  st.flops_heff_gemm = timer.gemm_flops;
+  st.n_heff_gemm = timer.n_gemm;
 }
 
 // ---------------------------------------------------- density-matrix apply
@@ -728,12 +725,25 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
   for (int i = N - 1; i >= 1; --i) {
     const int ml = psi.m[i], mr = psi.m[i + 1], D = 2 * mr;
     const void* C = psi.site(i);
-    const int kk = std::min(ml, D);
-    Vh.ensure((size_t)kk * D * ZB);
-    la::svd_rowmajor(ctx, C, ml, D, nullptr, S, Vh.p, W.work, W.work2);
+    // B: orthonormal rows spanning the row space of C ("SVD without
+    // truncation").  The weights s_j^2 are the eigenvalues of C C^dagger;
+    // directions at round-off level (s^2 <= 1e-14 s_1^2) are not part of the
+    // row space.  B = orth(U_r^dagger C), whose rows are s_j v_j^dagger.
+    W.tmpA.ensure((size_t)ml * ml * ZB);
+    W.tmpB.ensure((size_t)ml * ml * ZB);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, ml, ml, D, 1.0, C, D, 0, C, D, 0, 0.0, W.tmpA.p, ml, 0, 1);
+    la::eigh_rows_desc(ctx, W.tmpA.p, ml, S, W.tmpB.p, W.work2);
     int r = 0;
     if (!S.empty() && S[0] > 0.0)
-      for (double v : S) r += (v > 1e-13 * S[0]) ? 1 : 0;
+      for (double v : S) r += (v > 1e-14 * S[0]) ? 1 : 0;
+    r = std::min(r, D);
+    Vh.ensure((size_t)std::max(r, 1) * D * ZB);
+    if (r > 0) {
+      W.tmpC.ensure((size_t)r * D * ZB);
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, r, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
+      W.tmpA.ensure((size_t)r * r * ZB);
+      la::lq_rowmajor(ctx, W.tmpC.p, r, D, W.tmpA.p, Vh.p, W.work, W.tau);
+    }
     const int cap = std::min(chi_max - r, D - r);
     // B' rows: B (r x D) then B_bar
     Bp.ensure((size_t)D * D * ZB);  // r + n <= D rows

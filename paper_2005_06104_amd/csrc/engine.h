@@ -41,10 +41,36 @@ void run_expand(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const td
 void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, const tdvp_mps_s* other,
                  tdvp_observables& out);
 
+// HIP-event timing of the one-site effective Hamiltonian: marks 0..3 bracket
+// the first GEMM (0-1), the MPO contraction (1-2) and the second GEMM (2-3).
+struct MatvecTimer {
+  tdvp_ctx_s* ctx = nullptr;
+  bool on = false, pending = false;
+  double ms = 0.0, gemm_ms = 0.0, gemm_flops = 0.0;
+  long long n_gemm = 0;
+  void mark(int k) {
+    if (!on) return;
+    hipEvent_t e = k == 0 ? ctx->ev_a : k == 1 ? ctx->ev_b : k == 2 ? ctx->ev_c : ctx->ev_d;
+    HIP_CHECK(hipEventRecord(e, ctx->stream));
+    if (k == 3) pending = true;
+  }
+  void collect() {
+    if (!pending) return;
+    float t = 0.f, g1 = 0.f, g2 = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&t, ctx->ev_a, ctx->ev_d));
+    HIP_CHECK(hipEventElapsedTime(&g1, ctx->ev_a, ctx->ev_b));
+    HIP_CHECK(hipEventElapsedTime(&g2, ctx->ev_c, ctx->ev_d));
+    ms += t;
+    gemm_ms += g1 + g2;
+    n_gemm += 2;
+    pending = false;
+  }
+};
+
 // kernel-level helpers used by the C-ABI
 template <typename T>
 void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-                const void* Rt, const void* C, void* Y, void* ws1, void* ws2);
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm = nullptr);
 template <typename T>
 void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
                 void* ws1);

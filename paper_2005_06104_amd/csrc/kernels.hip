@@ -37,7 +37,9 @@ __device__ inline f4 mfma(float a, float b, f4 c) {
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 constexpr int PAD = 1;
 
-template <typename T, bool TA, bool CA, bool TB, bool CB>
+// TAG only separates instantiations (the one-site effective Hamiltonian uses
+// its own so that profilers and timers see it apart from the other GEMMs).
+template <typename T, bool TA, bool CA, bool TB, bool CB, int TAG>
 __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T ai, const T* __restrict__ A,
                                                    long long lda, long long sa, const T* __restrict__ B,
                                                    long long ldb, long long sb, T br, T bi,
@@ -180,14 +182,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       }
 }
 
-template <typename T, int OA, int OB>
+template <typename T, int OA, int OB, int TAG = 0>
 void launch_gemm(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda,
                  long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
                  long long ldc, long long sc, int batch) {
   constexpr bool TA = (OA == TDVP_OP_T || OA == TDVP_OP_C), CA = (OA == TDVP_OP_C || OA == TDVP_OP_R);
   constexpr bool TB = (OB == TDVP_OP_T || OB == TDVP_OP_C), CB = (OB == TDVP_OP_C || OB == TDVP_OP_R);
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
-  hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB>), grid, dim3(NT), 0, s, M, N, K, T(alpha.real()),
+  hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, T(alpha.real()),
                      T(alpha.imag()), static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb,
                      sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
 }
@@ -443,6 +445,18 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
 }
 template void gemm<double>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
                            const void*, long long, long long, zc, void*, long long, long long, int);
+
+template <typename T>
+void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
+               void* C, long long ldc) {
+  if (M <= 0 || N <= 0) return;
+  launch_gemm<T, TDVP_OP_N, TDVP_OP_N, 1>(s, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1);
+  HIP_CHECK(hipGetLastError());
+}
+template void gemm_heff<double>(hipStream_t, int, int, int, const void*, long long, const void*, long long, void*,
+                                long long);
+template void gemm_heff<float>(hipStream_t, int, int, int, const void*, long long, const void*, long long, void*,
+                               long long);
 template void gemm<float>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
                           const void*, long long, long long, zc, void*, long long, long long, int);
 

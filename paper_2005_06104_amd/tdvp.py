@@ -57,7 +57,8 @@ class tdvp_sweep_params(C.Structure):
 class tdvp_sweep_stats(C.Structure):
     _fields_ = [("ms", C.c_double), ("ms_matvec", C.c_double), ("flops_matvec", C.c_double),
                 ("n_matvec", C.c_longlong), ("n_keff", C.c_longlong), ("max_lanczos", C.c_int),
-                ("n_unconverged", C.c_int), ("discarded", C.c_double), ("energy", C.c_double)]
+                ("n_unconverged", C.c_int), ("discarded", C.c_double), ("energy", C.c_double),
+                ("ms_heff_gemm", C.c_double), ("flops_heff_gemm", C.c_double), ("n_heff_gemm", C.c_longlong)]
 
 
 class tdvp_observables(C.Structure):
