@@ -77,8 +77,8 @@ def cpu_baseline(w, seconds: float, chi_probe: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=14)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", type=int, default=1, help="0..3: the benchmark workloads")
     ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -155,7 +155,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_sites": N, "chi_max": w.chi_max, "k": w.k,
                    "dt": [w.dt.real, w.dt.imag], "eps_K": w.eps_K, "eps_M": w.eps_M, "eps": w.eps,
-                   "mpo_w_max": max(H.dims), "parallelism": "single GPU"},
+                   "mpo_w_max": int(max(H.dims)), "parallelism": "single GPU"},
         "matvec_tflops": mv_tf,
         "heff_gemm_tflops": gemm_tf,
         "split_ms_per_step": {"krylov": acc["ms_krylov"] / args.steps, "extend": acc["ms_extend"] / args.steps,

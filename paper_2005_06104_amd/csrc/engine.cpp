@@ -726,23 +726,25 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     const int ml = psi.m[i], mr = psi.m[i + 1], D = 2 * mr;
     const void* C = psi.site(i);
     // B: orthonormal rows spanning the row space of C ("SVD without
-    // truncation").  The weights s_j^2 are the eigenvalues of C C^dagger;
-    // directions at round-off level (s^2 <= 1e-14 s_1^2) are not part of the
-    // row space.  B = orth(U_r^dagger C), whose rows are s_j v_j^dagger.
+    // truncation"); directions whose weight is at round-off level
+    // (s^2 <= 1e-14 s_1^2) are not part of it.  The eigenvalues of C C^dagger
+    // are the weights to ~1e-15 of the largest: when all of them are clearly
+    // above the floor, C has full row rank and an LQ factorisation gives B;
+    // otherwise a Jacobi SVD resolves the small singular values.
     W.tmpA.ensure((size_t)ml * ml * ZB);
     W.tmpB.ensure((size_t)ml * ml * ZB);
     kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, ml, ml, D, 1.0, C, D, 0, C, D, 0, 0.0, W.tmpA.p, ml, 0, 1);
     la::eigh_rows_desc(ctx, W.tmpA.p, ml, S, W.tmpB.p, W.work2);
     int r = 0;
-    if (!S.empty() && S[0] > 0.0)
-      for (double v : S) r += (v > 1e-14 * S[0]) ? 1 : 0;
-    r = std::min(r, D);
-    Vh.ensure((size_t)std::max(r, 1) * D * ZB);
-    if (r > 0) {
-      W.tmpC.ensure((size_t)r * D * ZB);
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, r, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
-      W.tmpA.ensure((size_t)r * r * ZB);
-      la::lq_rowmajor(ctx, W.tmpC.p, r, D, W.tmpA.p, Vh.p, W.work, W.tau);
+    Vh.ensure((size_t)std::min(ml, D) * D * ZB);
+    if (ml <= D && !S.empty() && S[0] > 0.0 && S[ml - 1] > 1e-10 * S[0]) {
+      r = ml;
+      W.tmpA.ensure((size_t)ml * ml * ZB);
+      la::lq_rowmajor(ctx, C, ml, D, W.tmpA.p, Vh.p, W.work, W.tau);
+    } else {
+      la::svd_rowmajor(ctx, C, ml, D, nullptr, S, Vh.p, W.work, W.work2);
+      if (!S.empty() && S[0] > 0.0)
+        for (double v : S) r += (v * v > 1e-14 * S[0] * S[0]) ? 1 : 0;
     }
     const int cap = std::min(chi_max - r, D - r);
     // B' rows: B (r x D) then B_bar
