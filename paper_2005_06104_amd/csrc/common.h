@@ -91,9 +91,14 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
 
 // The same product (NN, alpha = 1, beta = 0, no batch) as a separate kernel
 // instantiation reserved for the one-site effective Hamiltonian.
+// ws (may be NULL) is scratch for split-K partial products.
 template <typename T>
 void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
-               void* C, long long ldc);
+               void* C, long long ldc, void* ws = nullptr, size_t ws_bytes = 0);
+// Plain NN product with split-K scratch (environments, zero-site H_eff).
+template <typename T>
+void gemm_nn_ws(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,
+                long long ldb, zc beta, void* C, long long ldc, void* ws, size_t ws_bytes);
 
 // Sparse MPO contraction over two channel indices (MPO index, physical index):
 // out[p, q, o1, o2] = sum_e val[e] * in[p, q, i1(e), i2(e)] for the CSR rows
@@ -138,6 +143,8 @@ void zhermitize(hipStream_t s, void* A, long long n);
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
+// G = a G + b I (n x n complex128)
+void zshift_diag(hipStream_t s, void* G, long long n, double a, double b);
 // dst[i*ldd+j] = f[i] * src[i*lds+j] (rows) or f[j] * src[...] (cols); f device doubles
 void zscale_rows(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long rows,
                  long long cols, const double* f);

@@ -157,37 +157,36 @@ struct Lanczos {
 // ------------------------------------------------------------ contractions
 template <typename T>
 void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm) {
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm, SplitWS sk) {
   hipStream_t s = ctx->stream;
   if (tm) tm->mark(0);
   // T1[(a',al),(s,b)] = L[(a',al),a] C[a,(s,b)]
-  kern::gemm_heff<T>(s, ml * wl, 2 * mr, ml, L, ml, C, 2 * mr, ws1, 2 * mr);
+  kern::gemm_heff<T>(s, ml * wl, 2 * mr, ml, L, ml, C, 2 * mr, ws1, 2 * mr, sk.p, sk.bytes);
   if (tm) tm->mark(1);
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
                   mr, (long long)wr * mr);
   if (tm) tm->mark(2);
   // Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b']
-  kern::gemm_heff<T>(s, 2 * ml, mr, wr * mr, ws2, (long long)wr * mr, Rt, mr, Y, mr);
+  kern::gemm_heff<T>(s, 2 * ml, mr, wr * mr, ws2, (long long)wr * mr, Rt, mr, Y, mr, sk.p, sk.bytes);
   if (tm) tm->mark(3);
   if (tm) tm->gemm_flops += 8.0 * ((double)ml * wl * ml * 2 * mr + (double)2 * ml * wr * mr * mr);
 }
 
 template <typename T>
 void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
-                void* ws1) {
+                void* ws1, SplitWS sk) {
   hipStream_t s = ctx->stream;
   // Y1[(a',al),b] = L[(a',al),a] X[a,b];  Y[a',b'] = Y1[a',(al,b)] Rt[(al,b),b']
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml * w, mr, ml, 1.0, L, ml, 0, X, mr, 0, 0.0, ws1, mr, 0, 1);
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml, mr, w * mr, 1.0, ws1, (long long)w * mr, 0, Rt, mr, 0, 0.0, Y, mr, 0,
-                1);
+  kern::gemm_nn_ws<T>(s, ml * w, mr, ml, 1.0, L, ml, X, mr, 0.0, ws1, mr, sk.p, sk.bytes);
+  kern::gemm_nn_ws<T>(s, ml, mr, w * mr, 1.0, ws1, (long long)w * mr, Rt, mr, 0.0, Y, mr, sk.p, sk.bytes);
 }
 
 template <typename T>
 void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L, const void* A,
-              void* Lout, void* ws1, void* ws2) {
+              void* Lout, void* ws1, void* ws2, SplitWS sk) {
   hipStream_t s = ctx->stream;
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml * wl, 2 * mr, ml, 1.0, L, ml, 0, A, 2 * mr, 0, 0.0, ws1, 2 * mr, 0, 1);
+  kern::gemm_nn_ws<T>(s, ml * wl, 2 * mr, ml, 1.0, L, ml, A, 2 * mr, 0.0, ws1, 2 * mr, sk.p, sk.bytes);
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
                   mr, (long long)wr * mr);
   // Lout[b',(be,b)] = sum_{(a',s')} conj(A[(a',s'),b']) T2[(a',s'),(be,b)]
@@ -197,7 +196,8 @@ void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int
 
 template <typename T>
 void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* Rt,
-               const void* B, void* Rout, void* ws1, void* ws2) {
+               const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk) {
+  (void)sk;
   hipStream_t s = ctx->stream;
   // U1[be][(a,s),b'] = B[(a,s),b] Rt[be][b,b']   (batched over be)
   kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, mr, 1.0, B, mr, 0, Rt, mr, (long long)mr * mr, 0.0, ws1, mr,
@@ -210,19 +210,21 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
 }
 
 template void heff_apply<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
-                                 const void*, void*, void*, void*, MatvecTimer*);
+                                 const void*, void*, void*, void*, MatvecTimer*, SplitWS);
 template void heff_apply<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
-                                const void*, void*, void*, void*, MatvecTimer*);
-template void keff_apply<double>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*);
-template void keff_apply<float>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*);
+                                const void*, void*, void*, void*, MatvecTimer*, SplitWS);
+template void keff_apply<double>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*,
+                                 SplitWS);
+template void keff_apply<float>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*,
+                                SplitWS);
 template void env_left<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                               void*, void*);
+                               void*, void*, SplitWS);
 template void env_left<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                              void*, void*);
+                              void*, void*, SplitWS);
 template void env_right<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                                void*, void*);
+                                void*, void*, SplitWS);
 template void env_right<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                               void*, void*);
+                               void*, void*, SplitWS);
 
 // ------------------------------------------------------------ handles
 namespace {
@@ -324,12 +326,18 @@ namespace {
 
 struct Work {
   tdvp_ctx_s* ctx;
-  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec;
+  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst;
   Scalars sc;
   Lanczos lz;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
-        dvec(c), sc(c), lz(c) {}
+        dvec(c), wsk(c), nsg(c), nst(c), sc(c), lz(c) {}
+  // split-K scratch for products whose output is ml x mr (or smaller)
+  SplitWS split(long long ml, long long mr, int cb) {
+    const size_t b = (size_t)16 * 2 * ml * mr * cb;
+    wsk.ensure(b);
+    return SplitWS{wsk.p, b};
+  }
 };
 
 // site tensor in the working precision (a converted copy for FP32)
@@ -346,6 +354,46 @@ void zmatmul(tdvp_ctx_s* ctx, int opa, int opb, int M, int N, int K, const void*
              long long ldb, DBuf& out) {
   out.ensure((size_t)M * N * ZB);
   kern::gemm<double>(ctx->stream, opa, opb, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, out.p, N, 0, 1);
+}
+
+// Newton-Schulz orthonormalisation: for A with nearly orthonormal columns,
+// A <- A (3 I - A^dagger A) / 2 keeps the column span and squares the
+// deviation from orthonormality at every step (GEMMs only).
+void ns_cols(Work& W, void* A, int rows, int n, int iters) {
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  W.nsg.ensure((size_t)n * n * ZB);
+  W.nst.ensure((size_t)rows * n * ZB);
+  for (int it = 0; it < iters; ++it) {
+    kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, W.nsg.p, n, 0, 1);
+    kern::zshift_diag(s, W.nsg.p, n, -0.5, 1.5);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, A, n, 0, W.nsg.p, n, 0, 0.0, W.nst.p, n, 0, 1);
+    HIP_CHECK(hipMemcpyAsync(A, W.nst.p, (size_t)rows * n * ZB, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+// Same for nearly orthonormal rows: B <- (3 I - B B^dagger) B / 2.
+void ns_rows(Work& W, void* B, int n, int cols, int iters) {
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  W.nsg.ensure((size_t)n * n * ZB);
+  W.nst.ensure((size_t)n * cols * ZB);
+  for (int it = 0; it < iters; ++it) {
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, W.nsg.p, n, 0, 1);
+    kern::zshift_diag(s, W.nsg.p, n, -0.5, 1.5);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, W.nsg.p, n, 0, B, cols, 0, 0.0, W.nst.p, cols, 0, 1);
+    HIP_CHECK(hipMemcpyAsync(B, W.nst.p, (size_t)n * cols * ZB, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+// 1/sqrt of the first n weights on the device
+const double* inv_sqrt_weights(Work& W, const std::vector<double>& lam, int n) {
+  std::vector<double> f(n);
+  for (int j = 0; j < n; ++j) f[j] = 1.0 / std::sqrt(std::max(lam[j], 1e-300));
+  W.dvec.ensure(sizeof(double) * std::max(n, 1));
+  upload(W.ctx, W.dvec.p, f.data(), sizeof(double) * n);
+  HIP_CHECK(hipStreamSynchronize(W.ctx->stream));  // `f` is pageable host memory
+  return W.dvec.as<double>();
 }
 
 // Truncated gauge moves.  The weights are the eigenvalues of the Gram matrix
@@ -380,13 +428,13 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   std::vector<double> lam;
   la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
-  // Y = C V_n (rows x n), A = orth(Y), R = A^dagger C
+  // A = C V_n S_n^-1 (orthonormal up to rounding), polished by Newton-Schulz; R = A^dagger C
   W.tmpC.ensure((size_t)rows * n * ZB);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, W.tmpB.p, cols, 0, 0.0, W.tmpC.p, n, 0, 1);
   A.ensure((size_t)rows * n * ZB);
   R.ensure((size_t)n * cols * ZB);
-  W.tmpA.ensure((size_t)n * n * ZB);
-  la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+  kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
+  ns_cols(W, A.p, rows, n, 3);
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, 0, C, cols, 0, 0.0, R.p, cols, 0, 1);
   return n;
 }
@@ -409,13 +457,13 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   std::vector<double> lam;
   la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
-  // Y = U_n^dagger C (n x cols), B = orth rows of Y, L = C B^dagger
+  // B = S_n^-1 U_n^dagger C (orthonormal rows up to rounding), polished by Newton-Schulz; L = C B^dagger
   W.tmpC.ensure((size_t)n * cols * ZB);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, 0, C, cols, 0, 0.0, W.tmpC.p, cols, 0, 1);
   L.ensure((size_t)rows * n * ZB);
   B.ensure((size_t)n * cols * ZB);
-  W.tmpA.ensure((size_t)n * n * ZB);
-  la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+  kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
+  ns_rows(W, B.p, n, cols, 3);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, B.p, cols, 0, 0.0, L.p, n, 0, 1);
   return n;
 }
@@ -482,7 +530,7 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     ensure_ws(ml, wl, wr, mr);
     L[i + 1].ensure((size_t)mr * wr * mr * cb);
     const void* At = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
-    env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p);
+    env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p, W.split(ml, mr, cb));
   };
   auto stepinfo = [&](int napp, bool unconv) {
     st.max_lanczos = std::max(st.max_lanczos, napp);
@@ -497,14 +545,15 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     ensure_ws(ml, wl, wr, mr);
     const double flops = 8.0 * ((double)ml * wl * ml * 2 * mr + (double)H.tab[i].nnz * ml * mr +
                                 (double)2 * ml * wr * mr * mr);
+    const SplitWS sk = W.split(ml, mr, cb);
     auto mv = [&](const void* in, void* out) {
       if (sizeof(T) == 8) {
-        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, &timer);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, &timer, sk);
       } else {
         W.xf.ensure((size_t)n * 8);
         W.yf.ensure((size_t)n * 8);
         kern::z2c(ctx->stream, W.xf.p, in, n);
-        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p, &timer);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p, &timer, sk);
         kern::c2z(ctx->stream, out, W.yf.p, n);
       }
       st.flops_matvec += flops;
@@ -519,14 +568,15 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const int w = H.w(b);
     const long long n = (long long)ml * mr;
     W.ws1.ensure((size_t)ml * w * mr * cb);
+    const SplitWS sk = W.split(ml, mr, cb);
     auto mv = [&](const void* in, void* out) {
       if (sizeof(T) == 8) {
-        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, in, out, W.ws1.p);
+        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, in, out, W.ws1.p, sk);
       } else {
         W.xf.ensure((size_t)n * 8);
         W.yf.ensure((size_t)n * 8);
         kern::z2c(ctx->stream, W.xf.p, in, n);
-        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, W.xf.p, W.yf.p, W.ws1.p);
+        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, W.xf.p, W.yf.p, W.ws1.p, sk);
         kern::c2z(ctx->stream, out, W.yf.p, n);
       }
     };
@@ -739,8 +789,11 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     Vh.ensure((size_t)std::min(ml, D) * D * ZB);
     if (ml <= D && !S.empty() && S[0] > 0.0 && S[ml - 1] > 1e-10 * S[0]) {
       r = ml;
-      W.tmpA.ensure((size_t)ml * ml * ZB);
-      la::lq_rowmajor(ctx, C, ml, D, W.tmpA.p, Vh.p, W.work, W.tau);
+      // B = S^-1 U^dagger C, polished by Newton-Schulz
+      W.tmpC.ensure((size_t)ml * D * ZB);
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, ml, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
+      kern::zscale_rows(s, Vh.p, D, W.tmpC.p, D, ml, D, inv_sqrt_weights(W, S, ml));
+      ns_rows(W, Vh.p, ml, D, 3);
     } else {
       la::svd_rowmajor(ctx, C, ml, D, nullptr, S, Vh.p, W.work, W.work2);
       if (!S.empty() && S[0] > 0.0)
@@ -787,12 +840,9 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
           kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, r, D, 1.0, Bbar, D, 0, Bp.p, D, 0, 0.0, Pb.p, r, 0, 1);
           kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, D, r, -1.0, Pb.p, r, 0, Bp.p, D, 0, 1.0, Bbar, D, 0, 1);
         }
-        // orthonormalise the rows of B_bar: QR of the column-major D x n view
-        W.work.ensure((size_t)n * D * ZB);
-        HIP_CHECK(hipMemcpyAsync(W.work.p, Bbar, (size_t)n * D * ZB, hipMemcpyDeviceToDevice, s));
-        // lq_rowmajor of the n x D row-major matrix gives orthonormal rows Q with the same span
-        Mt.ensure((size_t)n * n * ZB);
-        la::lq_rowmajor(ctx, W.work.p, n, D, Mt.p, Bbar, W.work2, W.tau);
+        // the eigenvector rows stay orthonormal up to the projection above;
+        // Newton-Schulz restores orthonormality within their span
+        ns_rows(W, Bbar, n, D, 2);
       }
     }
     const int mnew = r + n;

@@ -68,17 +68,24 @@ struct MatvecTimer {
 };
 
 // kernel-level helpers used by the C-ABI
+// Split-K scratch for the contractions (may be empty: no K splitting).
+struct SplitWS {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
 template <typename T>
 void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm = nullptr);
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm = nullptr,
+                SplitWS sk = {});
 template <typename T>
 void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
-                void* ws1);
+                void* ws1, SplitWS sk = {});
 template <typename T>
 void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-              const void* A, void* Lout, void* ws1, void* ws2);
+              const void* A, void* Lout, void* ws1, void* ws2, SplitWS sk = {});
 template <typename T>
 void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* Rt,
-               const void* B, void* Rout, void* ws1, void* ws2);
+               const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk = {});
 // CSR tables for a single host W (kernel-level calls); keeps the device copy in `buf`
 SiteTables upload_tables(tdvp_ctx_s* ctx, const std::vector<zc>& W, int wl, int wr, DBuf& buf);

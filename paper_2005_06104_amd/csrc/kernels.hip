@@ -39,11 +39,14 @@ constexpr int PAD = 1;
 
 // TAG only separates instantiations (the one-site effective Hamiltonian uses
 // its own so that profilers and timers see it apart from the other GEMMs).
+// Split-K: blockIdx.z = batch * S + split; split s covers k in
+// [s*Kc, min(K, (s+1)*Kc)) and writes its partial product at C + s*sps.
 template <typename T, bool TA, bool CA, bool TB, bool CB, int TAG>
 __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T ai, const T* __restrict__ A,
                                                    long long lda, long long sa, const T* __restrict__ B,
                                                    long long ldb, long long sb, T br, T bi,
-                                                   T* __restrict__ C, long long ldc, long long sc) {
+                                                   T* __restrict__ C, long long ldc, long long sc, int S, int Kc,
+                                                   long long sps) {
   using c2 = typename VT<T>::c2;
   using acc_t = typename VT<T>::acc;
   __shared__ T As_r[BK][BM + PAD], As_i[BK][BM + PAD];
@@ -54,10 +57,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const long long bz = blockIdx.z;
+  const long long bz = blockIdx.z / S;
+  const int split = blockIdx.z % S;
+  const int kb = split * Kc;
+  const int ke = min(K, kb + Kc);
   const c2* Ab = reinterpret_cast<const c2*>(A) + bz * sa;
   const c2* Bb = reinterpret_cast<const c2*>(B) + bz * sb;
-  c2* Cb = reinterpret_cast<c2*>(C) + bz * sc;
+  c2* Cb = reinterpret_cast<c2*>(C) + bz * sc + split * sps;
 
   constexpr int PER = (BM * BK) / NT;  // complex elements per thread per operand (4)
   c2 ra[PER], rb[PER];
@@ -71,7 +77,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       const int gm = m0 + m, gk = k0 + k;
       c2 v;
       v.x = T(0); v.y = T(0);
-      if (gm < M && gk < K) v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
+      if (gm < M && gk < ke) v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
       if (CA) v.y = -v.y;
       ra[it] = v;
     }
@@ -83,7 +89,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       const int gn = n0 + n, gk = k0 + k;
       c2 v;
       v.x = T(0); v.y = T(0);
-      if (gn < N && gk < K) v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
+      if (gn < N && gk < ke) v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
       if (CB) v.y = -v.y;
       rb[it] = v;
     }
@@ -117,11 +123,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
     }
 
   const int lr = lane & 15, lk = lane >> 4;
-  load(0);
+  load(kb);
   store();
   __syncthreads();
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const bool more = (k0 + BK) < K;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = (k0 + BK) < ke;
     if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
@@ -182,16 +188,68 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       }
 }
 
+// Deterministic split-K reduction: C = alpha * sum_s P[s] + beta * C.
+template <typename T>
+__global__ void splitk_reduce_kernel(const T* __restrict__ P, int S, long long M, long long N, T ar, T ai,
+                                     T br, T bi, T* __restrict__ C, long long ldc) {
+  using c2 = typename VT<T>::c2;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const c2* Pc = reinterpret_cast<const c2*>(P);
+  T xr = T(0), xi = T(0);
+  for (int s = 0; s < S; ++s) {
+    const c2 v = Pc[(long long)s * M * N + idx];
+    xr += v.x;
+    xi += v.y;
+  }
+  const long long m = idx / N, n = idx % N;
+  c2* Cc = reinterpret_cast<c2*>(C);
+  c2 o;
+  o.x = ar * xr - ai * xi;
+  o.y = ar * xi + ai * xr;
+  if (br != T(0) || bi != T(0)) {
+    const c2 old = Cc[m * ldc + n];
+    o.x += br * old.x - bi * old.y;
+    o.y += br * old.y + bi * old.x;
+  }
+  Cc[m * ldc + n] = o;
+}
+
+// Number of K splits: enough workgroups to cover the CUs when the output
+// has few tiles and K is long; each split keeps >= 128 of K.
+inline int choose_splits(int M, int N, int K, int batch, size_t ws_bytes, size_t cbytes) {
+  const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+  if (batch != 1 || ws_bytes == 0 || tiles >= 512 || K < 256) return 1;
+  int S = (int)std::min<long long>((512 + tiles - 1) / tiles, K / 128);
+  S = std::min(S, 16);
+  while (S > 1 && (size_t)S * M * N * cbytes > ws_bytes) --S;
+  return std::max(S, 1);
+}
+
 template <typename T, int OA, int OB, int TAG = 0>
 void launch_gemm(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda,
                  long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
-                 long long ldc, long long sc, int batch) {
+                 long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0) {
   constexpr bool TA = (OA == TDVP_OP_T || OA == TDVP_OP_C), CA = (OA == TDVP_OP_C || OA == TDVP_OP_R);
   constexpr bool TB = (OB == TDVP_OP_T || OB == TDVP_OP_C), CB = (OB == TDVP_OP_C || OB == TDVP_OP_R);
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
-  hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, T(alpha.real()),
-                     T(alpha.imag()), static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb,
-                     sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
+  const int S = choose_splits(M, N, K, batch, ws_bytes, sizeof(typename VT<T>::c2));
+  if (S == 1) {
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, T(alpha.real()),
+                       T(alpha.imag()), static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb,
+                       sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc, 1, std::max(K, 1), 0LL);
+    return;
+  }
+  const int Kc = ((K + S - 1) / S + BK - 1) / BK * BK;
+  const int Sx = (K + Kc - 1) / Kc;
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, Sx);
+  hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, T(1), T(0),
+                     static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb, sb, T(0), T(0),
+                     static_cast<T*>(ws), (long long)N, 0LL, Sx, Kc, (long long)M * N);
+  const long long MN = (long long)M * N;
+  hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const T*>(ws), Sx, (long long)M, (long long)N, T(alpha.real()), T(alpha.imag()),
+                     T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc);
 }
 
 template <typename T, int OA>
@@ -254,7 +312,7 @@ __global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T
 
 // ---------------------------------------------------------------- vectors
 constexpr int VNT = 256;
-constexpr int DOT_CHUNK = 8192;
+constexpr int DOT_CHUNK = 4096;
 
 __device__ inline double warp_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -273,30 +331,30 @@ __device__ inline double block_sum(double v, double* sh) {
   return t;  // valid on thread 0
 }
 
+// One block per (vector j, chunk): partial[b * nv + j] = sum over the chunk.
 template <bool CONJ>
 __global__ __launch_bounds__(VNT) void zdots_partial_kernel(const double2* __restrict__ V, long long ldv, int nv,
                                                              const double2* __restrict__ w, long long n,
                                                              double2* __restrict__ partial) {
   __shared__ double sh[VNT / 64];
+  const int j = blockIdx.y;
   const long long beg = (long long)blockIdx.x * DOT_CHUNK;
   const long long end = min(n, beg + DOT_CHUNK);
-  for (int j = 0; j < nv; ++j) {
-    double sr = 0.0, si = 0.0;
-    const double2* v = V + (long long)j * ldv;
-    for (long long x = beg + threadIdx.x; x < end; x += VNT) {
-      const double2 a = v[x], b = w[x];
-      if (CONJ) {                    // conj(a) * b
-        sr += a.x * b.x + a.y * b.y;
-        si += a.x * b.y - a.y * b.x;
-      } else {                       // a * b
-        sr += a.x * b.x - a.y * b.y;
-        si += a.x * b.y + a.y * b.x;
-      }
+  double sr = 0.0, si = 0.0;
+  const double2* v = V + (long long)j * ldv;
+  for (long long x = beg + threadIdx.x; x < end; x += VNT) {
+    const double2 a = v[x], b = w[x];
+    if (CONJ) {                    // conj(a) * b
+      sr += a.x * b.x + a.y * b.y;
+      si += a.x * b.y - a.y * b.x;
+    } else {                       // a * b
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
     }
-    const double tr = block_sum(sr, sh);
-    const double ti = block_sum(si, sh);
-    if (threadIdx.x == 0) partial[(long long)blockIdx.x * nv + j] = make_double2(tr, ti);
   }
+  const double tr = block_sum(sr, sh);
+  const double ti = block_sum(si, sh);
+  if (threadIdx.x == 0) partial[(long long)blockIdx.x * nv + j] = make_double2(tr, ti);
 }
 
 __global__ void zdots_final_kernel(const double2* __restrict__ partial, int nb, int nv,
@@ -423,6 +481,16 @@ __global__ void zscale_rc_kernel(double2* __restrict__ dst, long long ldd, const
   dst[i * ldd + j] = make_double2(g * v.x, g * v.y);
 }
 
+__global__ void zshift_diag_kernel(double2* __restrict__ G, long long n, double a, double b) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  double2 v = G[idx];
+  v.x *= a;
+  v.y *= a;
+  if (idx / n == idx % n) v.x += b;
+  G[idx] = v;
+}
+
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -448,15 +516,28 @@ template void gemm<double>(hipStream_t, int, int, int, int, int, zc, const void*
 
 template <typename T>
 void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
-               void* C, long long ldc) {
+               void* C, long long ldc, void* ws, size_t ws_bytes) {
   if (M <= 0 || N <= 0) return;
-  launch_gemm<T, TDVP_OP_N, TDVP_OP_N, 1>(s, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1);
+  launch_gemm<T, TDVP_OP_N, TDVP_OP_N, 1>(s, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, C, ldc, 0, 1, ws, ws_bytes);
   HIP_CHECK(hipGetLastError());
 }
 template void gemm_heff<double>(hipStream_t, int, int, int, const void*, long long, const void*, long long, void*,
-                                long long);
+                                long long, void*, size_t);
 template void gemm_heff<float>(hipStream_t, int, int, int, const void*, long long, const void*, long long, void*,
-                               long long);
+                               long long, void*, size_t);
+
+template <typename T>
+void gemm_nn_ws(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,
+                long long ldb, zc beta, void* C, long long ldc, void* ws, size_t ws_bytes) {
+  if (M <= 0 || N <= 0) return;
+  launch_gemm<T, TDVP_OP_N, TDVP_OP_N, 0>(s, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, ws,
+                                          ws_bytes);
+  HIP_CHECK(hipGetLastError());
+}
+template void gemm_nn_ws<double>(hipStream_t, int, int, int, zc, const void*, long long, const void*, long long, zc,
+                                 void*, long long, void*, size_t);
+template void gemm_nn_ws<float>(hipStream_t, int, int, int, zc, const void*, long long, const void*, long long, zc,
+                                void*, long long, void*, size_t);
 template void gemm<float>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
                           const void*, long long, long long, zc, void*, long long, long long, int);
 
@@ -485,10 +566,10 @@ void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, l
            int nb, void* out, bool conjugate) {
   if (nv <= 0) return;
   if (conjugate)
-    hipLaunchKernelGGL(zdots_partial_kernel<true>, dim3(nb), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
+    hipLaunchKernelGGL(zdots_partial_kernel<true>, dim3(nb, nv), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
                        nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
   else
-    hipLaunchKernelGGL(zdots_partial_kernel<false>, dim3(nb), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
+    hipLaunchKernelGGL(zdots_partial_kernel<false>, dim3(nb, nv), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
                        nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
   hipLaunchKernelGGL(zdots_final_kernel, dim3(nblk(nv, 64)), dim3(64), 0, s,
                      static_cast<const double2*>(partial), nb, nv, static_cast<double2*>(out));
@@ -573,6 +654,12 @@ void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, 
   if (nx <= 0 || nq <= 0) return;
   hipLaunchKernelGGL(zscale_phys_kernel, dim3(nblk(nx * 2 * nq)), dim3(256), 0, s, static_cast<double2*>(G),
                      nx, nq, f0, f1);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zshift_diag(hipStream_t s, void* G, long long n, double a, double b) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zshift_diag_kernel, dim3(nblk(n * n)), dim3(256), 0, s, static_cast<double2*>(G), n, a, b);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -180,3 +180,35 @@ def test_gse_imaginary_time_random_start(env):
     rows = _run_both(T, ctx, w, w.n_steps)
     for (loss, de, dsz, bg, bo) in rows:
         assert loss < 1e-9 and abs(de) < 1e-9
+
+
+def test_gse_oat_closed_form_on_device(env):
+    # eq. (13): <S^x(t)> = (N/2) cos^(N-1) t for the one-axis-twisting model
+    # (w = 3 long-range MPO), section II.B settings dt = 0.025, tau = dt, k = 3,
+    # eps = 0; real-time energy error below 1e-10 (Fig. 4(c)).  At N = 16 the
+    # method itself is 1.1e-8 off the closed form at t = 0.25 (the oracle shows
+    # the same), so the device must agree with the oracle far more tightly.
+    T, ctx = env
+    from oracle import gse, mpo, observables as O
+    N = 16
+    terms = I.oat_terms(N)
+    dt = 0.025
+    H = T.tdvp_create_mpo(ctx, N, terms)
+    op = T.tdvp_create_mpo(ctx, N, terms, 1.0, -1j * dt)
+    assert max(H.dims) == 3
+    g = T.tdvp_mps_from_host(ctx, I.x_polarized_mps(N))
+    Ws, Wop = mpo.build_mpo(N, terms), mpo.build_mpo(N, terms, 1.0, -1j * dt)
+    psi = I.x_polarized_mps(N)
+    e0 = T.tdvp_measure(ctx, [g], [H])[0]["energy"]
+    t = 0.0
+    for _ in range(10):
+        T.tdvp_expand_basis(ctx, [g], [op], 3, 1e-10, 1e-10, 64, "fp64")
+        T.tdvp_sweep(ctx, [g], [H], dt, 0.0, 64, 1e-12, 30, "fp64", False)
+        psi, _ = gse.gse_step(psi, Ws, Wop, dt, 3, 1e-10, 1e-10, 0.0, 64)
+        t += dt
+        m = T.tdvp_measure(ctx, [g], [H])[0]
+        assert abs(m["energy"] - e0) < 1e-10 * abs(e0)
+        assert np.abs(m["sz"]).max() < 1e-10            # <S^z> = 0
+        sx = O.sx_total(T.tdvp_mps_to_host(g))
+        assert abs(sx - O.sx_total(psi)) < 1e-10
+        assert abs(sx - O.oat_sx_exact(N, t)) < 5e-8
