@@ -74,32 +74,28 @@ def cpu_baseline(w, seconds: float, chi_probe: int):
             "matvec_ms": mv_ms, "steps_timed": n, "max_bond_reached": int(bonds)}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
-    ap.add_argument("--warmup", type=int, default=4)
-    ap.add_argument("--workload", type=int, default=1, help="0..3: the benchmark workloads")
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the GSE-TDVP1 sweep of one MPS is sequential over sites and "
-              f"this build has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
-        sys.exit(2)
+def traffic_from_profile(kernel_src: str):
+    """HBM bytes per H_eff GEMM launch from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "heff_gemm_traffic_ladder64_chi256.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    want = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    rec = dict(line.split(":", 1) for line in txt.splitlines() if line.startswith(("kernels_sha256:", "bytes_per_launch:")))
+    if rec.get("kernels_sha256", "").strip() != want:
+        return None
+    try:
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
-    import numpy as np
+
+def run_workload(T, ctx, w, prec, warmup, steps, label):
+    """Evolve the workload from its seeded initial state; time `steps` steps after `warmup`."""
     import torch
-
-    from paper_2005_06104_amd import inputs as I
-    from paper_2005_06104_amd import tdvp as T
-
-    torch.cuda.set_device(0)
-    w = I.workload(args.workload)
-    prec = args.prec or ("fp64" if w.prec == "fp64" else "fp32")
     N = w.lattice.n_sites
-    ctx = T.Context(0)
     H = T.tdvp_create_mpo(ctx, N, w.terms)
     op = T.tdvp_create_mpo(ctx, N, w.terms, 1.0, -1j * w.tau)
     psi = T.tdvp_mps_from_host(ctx, w.initial_mps())
@@ -111,43 +107,136 @@ def main():
         m = T.tdvp_measure(ctx, [psi], [H])[0]
         return e, s, m
 
-    log(f"workload {w.name}: N={N}, chi_max={w.chi_max}, k={w.k}, dt={w.dt}, prec={prec}")
-    for i in range(args.warmup):
+    for i in range(warmup):
         t = time.perf_counter()
         e, s, m = step()
-        log(f"warmup {i}: {1e3 * (time.perf_counter() - t):.1f} ms, max bond {max(m['bond_dims'])}, "
+        log(f"[{label}] warmup {i}: {1e3 * (time.perf_counter() - t):.1f} ms, max bond {max(m['bond_dims'])}, "
             f"E={m['energy']:.10f}, matvecs {s['n_matvec']}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     acc = {"ms_heff_gemm": 0.0, "flops_heff_gemm": 0.0, "n_heff_gemm": 0, "ms_matvec": 0.0, "flops_matvec": 0.0,
            "n_matvec": 0, "ms_sweep": 0.0, "ms_krylov": 0.0, "ms_extend": 0.0}
-    per_step = []
-    for i in range(args.steps):
+    for i in range(steps):
         ts = time.perf_counter()
         e, s, m = step()
-        per_step.append(1e3 * (time.perf_counter() - ts))
         for k in ("ms_heff_gemm", "flops_heff_gemm", "n_heff_gemm", "ms_matvec", "flops_matvec", "n_matvec"):
             acc[k] += s[k]
         acc["ms_sweep"] += s["ms"]
         acc["ms_krylov"] += e["ms_krylov"]
         acc["ms_extend"] += e["ms_extend"]
-        log(f"step {i}: {per_step[-1]:.1f} ms (krylov {e['ms_krylov']:.1f}, extend {e['ms_extend']:.1f}, "
-            f"sweep {s['ms']:.1f}), max bond {max(m['bond_dims'])}, E={m['energy']:.10f}")
+        log(f"[{label}] step {i}: {1e3 * (time.perf_counter() - ts):.1f} ms (krylov {e['ms_krylov']:.1f}, "
+            f"extend {e['ms_extend']:.1f}, sweep {s['ms']:.1f}), max bond {max(m['bond_dims'])}, E={m['energy']:.10f}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ms_per_step = 1e3 * el / max(args.steps, 1)
+    acc["elapsed"] = el
+    acc["final"] = T.tdvp_measure(ctx, [psi], [H])[0]
+    acc["H"], acc["op"], acc["psi"] = H, op, psi
+    return acc
+
+
+def summarize(acc, steps, prec):
     gemm_tf = acc["flops_heff_gemm"] / (acc["ms_heff_gemm"] * 1e-3) / 1e12 if acc["ms_heff_gemm"] > 0 else None
     mv_tf = acc["flops_matvec"] / (acc["ms_matvec"] * 1e-3) / 1e12 if acc["ms_matvec"] > 0 else None
+    return {
+        "value": steps / acc["elapsed"],
+        "ms_per_step": 1e3 * acc["elapsed"] / max(steps, 1),
+        "matvec_tflops": mv_tf,
+        "heff_gemm_tflops": gemm_tf,
+        "heff_gemm_frac_of_peak": (gemm_tf / PEAK_TFLOPS[prec]) if gemm_tf else None,
+        "split_ms_per_step": {"krylov": acc["ms_krylov"] / steps, "extend": acc["ms_extend"] / steps,
+                              "sweep": acc["ms_sweep"] / steps, "heff_matvec": acc["ms_matvec"] / steps},
+        "heff_gemm_launches": acc["n_heff_gemm"],
+        "heff_gemm_avg_us": 1e3 * acc["ms_heff_gemm"] / acc["n_heff_gemm"] if acc["n_heff_gemm"] else None,
+        "max_bond": max(acc["final"]["bond_dims"]),
+        "energy": acc["final"]["energy"],
+    }
+
+
+def kernel_only(args):
+    """Short run for hardware-counter passes: H_eff applications at the bench
+    workload's full size (chi = 256, w = 8, FP64) and a plain copy of known size."""
+    import numpy as np
+    import torch
+
+    from paper_2005_06104_amd import inputs as I
+    from paper_2005_06104_amd import tdvp as T
+    chi, w = 256, 8
+    ctx = T.Context(0)
+    dt = torch.complex128 if args.prec != "fp32" else torch.complex64
+    L = torch.from_numpy(I.random_hermitian_env(chi, w, 1)).to(dt).cuda()
+    Rt = torch.from_numpy(np.ascontiguousarray(I.random_hermitian_env(chi, w, 2).transpose(1, 2, 0))).to(dt).cuda()
+    Cin = torch.from_numpy(I.random_complex((chi, 2, chi), 3)).to(dt).cuda()
+    Y = torch.empty_like(Cin)
+    W = I.random_mpo_site(w, w, 4)
+    nnz = int(np.count_nonzero(W))
+    ws = torch.empty((4 * w + 32) * chi * chi, dtype=dt, device="cuda")
+    for _ in range(3):
+        T.tdvp_heff_apply(ctx, W, L, Rt, Cin, Y, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        T.tdvp_heff_apply(ctx, W, L, Rt, Cin, Y, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(args.steps, 1)
+    fl = 8.0 * (2 * chi ** 3 * w * 2 + nnz * chi * chi)
+    log(f"kernel-only: H_eff application {ms * 1e3:.1f} us incl. host W upload, {fl / ms / 1e9:.1f} TFLOP/s")
+    src = torch.empty(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"kernel-only: {args.steps} H_eff applications at chi={chi}, w={w}; copied {src.numel() * 8} bytes")
+    ctx.close()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", type=int, default=1, help="0..3: the benchmark workloads")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
+                    help="skip the run in the other precision (mixed vs FP64)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only H_eff applications at full size plus a plain copy (for counter passes)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the GSE-TDVP1 sweep of one MPS is sequential over sites and "
+              f"this build has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    if args.kernel_only:
+        kernel_only(args)
+        return
+    import torch
+
+    from paper_2005_06104_amd import inputs as I
+    from paper_2005_06104_amd import tdvp as T
+
+    torch.cuda.set_device(0)
+    w = I.workload(args.workload)
+    prec = args.prec or ("fp64" if w.prec == "fp64" else "fp32")
+    N = w.lattice.n_sites
+    ctx = T.Context(0)
+    log(f"workload {w.name}: N={N}, chi_max={w.chi_max}, k={w.k}, dt={w.dt}, prec={prec}")
+    main_run = run_workload(T, ctx, w, prec, args.warmup, args.steps, prec)
+    res = summarize(main_run, args.steps, prec)
+    gemm_tf = res["heff_gemm_tflops"]
     peak = PEAK_TFLOPS[prec]
-    final = T.tdvp_measure(ctx, [psi], [H])[0]
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2005_06104_amd", "csrc", "kernels.hip")) \
+        if prec == "fp64" and args.workload == 1 else None
     out = {
         "metric": METRIC,
-        "value": args.steps / el,
+        "value": res["value"],
         "unit": "GSE-TDVP1 steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -155,24 +244,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n_sites": N, "chi_max": w.chi_max, "k": w.k,
                    "dt": [w.dt.real, w.dt.imag], "eps_K": w.eps_K, "eps_M": w.eps_M, "eps": w.eps,
-                   "mpo_w_max": int(max(H.dims)), "parallelism": "single GPU"},
-        "matvec_tflops": mv_tf,
-        "heff_gemm_tflops": gemm_tf,
-        "split_ms_per_step": {"krylov": acc["ms_krylov"] / args.steps, "extend": acc["ms_extend"] / args.steps,
-                              "sweep": acc["ms_sweep"] / args.steps,
-                              "heff_matvec": acc["ms_matvec"] / args.steps},
-        "heff_gemm_launches": acc["n_heff_gemm"],
-        "heff_gemm_avg_us": 1e3 * acc["ms_heff_gemm"] / acc["n_heff_gemm"] if acc["n_heff_gemm"] else None,
-        "max_bond": max(final["bond_dims"]),
-        "energy": final["energy"],
-        "roofline": {"bound": "mfma", "kernel": "one-site H_eff GEMM (gemm_kernel TAG=1)",
-                     "achieved": gemm_tf, "peak": peak, "unit": "TFLOP/s",
-                     "frac": (gemm_tf / peak) if gemm_tf else None, "traffic": None},
+                   "mpo_w_max": int(max(main_run["H"].dims)), "parallelism": "single GPU"},
     }
+    out.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step")})
+    out["roofline"] = {"bound": "mfma", "kernel": "one-site H_eff GEMM (gemm_kernel TAG=1)",
+                       "achieved": gemm_tf, "peak": peak, "unit": "TFLOP/s",
+                       "frac": (gemm_tf / peak) if gemm_tf else None, "traffic": traffic}
+    if args.compare_prec:
+        other = "fp32" if prec == "fp64" else "fp64"
+        alt = run_workload(T, ctx, w, other, args.warmup, args.steps, other)
+        ra = summarize(alt, args.steps, other)
+        ov = T.tdvp_measure(ctx, [alt["psi"]], None, [main_run["psi"]])[0]
+        fid = abs(ov["overlap"]) ** 2 / (main_run["final"]["norm"] ** 2 * alt["final"]["norm"] ** 2)
+        ra["fidelity_vs_" + prec] = fid
+        ra["energy_diff_vs_" + prec] = ra["energy"] - res["energy"]
+        ra["speedup_vs_" + prec] = ra["value"] / res["value"]
+        t_total = abs(w.dt) * (args.warmup + args.steps)
+        ra["fidelity_loss_per_unit_time"] = (1 - fid) / t_total
+        out[other] = ra
+        del alt
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, min(w.chi_max, max(final["bond_dims"])))
-    del psi, H, op
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, min(w.chi_max, res["max_bond"]))
+    del main_run
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -231,20 +231,21 @@ tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, 
  * Y[a',s',b'] = sum L[a',al,a] W[al,be,s',s] C[a,s,b] Rt[be,b,b'].
  * Sizes: L ml*wl*ml, Rt wr*mr*mr, C and Y ml*2*mr; W_host is a host array of
  * wl*wr*4 complex128.  workspace may be NULL (allocated internally) or hold
- * 2*ml*mr*2*max(wl,wr) elements of the precision. */
+ * (4*max(wl,wr) + 32)*ml*mr elements of the precision (intermediates and
+ * split-K partial products). */
 tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr,
                             const double* W_host, const void* L, const void* Rt, const void* C,
                             void* Y, void* workspace);
 
 /* Zero-site effective Hamiltonian on the bond: Y[a',b'] = sum L[a',al,a] X[a,b] Rt[al,b,b'].
- * Sizes: L ml*w*ml, Rt w*mr*mr, X and Y ml*mr. */
+ * Sizes: L ml*w*ml, Rt w*mr*mr, X and Y ml*mr; workspace as for tdvp_heff_apply. */
 tdvp_status tdvp_keff_apply(tdvp_ctx ctx, int prec, int ml, int w, int mr, const void* L,
                             const void* Rt, const void* X, void* Y, void* workspace);
 
 /* Environment updates.  Left: Lout[b',be,b] = sum conj(A[a',s',b']) L[a',al,a]
  * W[al,be,s',s] A[a,s,b] (A is ml x 2 x mr, L ml*wl*ml, Lout mr*wr*mr).
  * Right: Rout[al,a,a'] = sum B[a,s,b] W[al,be,s',s] Rt[be,b,b'] conj(B[a',s',b'])
- * (B is ml x 2 x mr, Rt wr*mr*mr, Rout wl*ml*ml). */
+ * (B is ml x 2 x mr, Rt wr*mr*mr, Rout wl*ml*ml).  workspace as for tdvp_heff_apply. */
 tdvp_status tdvp_env_left(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr,
                           const double* W_host, const void* L, const void* A, void* Lout,
                           void* workspace);

@@ -1,6 +1,8 @@
 // extern "C" entry points: argument checks, status codes, context plumbing.
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <thread>
 
 #include "engine.h"
 
@@ -8,7 +10,11 @@
 
 void* tdvp_ctx_s::dalloc(size_t bytes) {
   void* p = nullptr;
-  if (alloc) {
+  if (async_alloc) {
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess || !p)
+      TDVP_THROW(TDVP_ERR_ALLOC, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+  } else if (alloc) {
     p = alloc(bytes, user);
     if (!p) TDVP_THROW(TDVP_ERR_ALLOC, "device allocation of " + std::to_string(bytes) + " bytes failed");
   } else {
@@ -21,8 +27,50 @@ void* tdvp_ctx_s::dalloc(size_t bytes) {
 
 void tdvp_ctx_s::dfree(void* p) {
   if (!p) return;
-  if (free_) free_(p, user);
+  if (async_alloc) (void)hipFreeAsync(p, stream);
+  else if (free_) free_(p, user);
   else (void)hipFree(p);
+}
+
+void tdvp_ctx_s::ensure_workers(int n) {
+  if (workers.empty() && n > 0) {
+    // keep freed stream-ordered memory in the pool between calls
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  }
+  while ((int)workers.size() < n) {
+    auto* w = new tdvp_ctx_s();
+    w->device = device;
+    w->async_alloc = true;
+    w->owns_stream = true;
+    workers.push_back(w);
+    HIP_CHECK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
+    if (rocblas_create_handle(&w->blas) != rocblas_status_success)
+      TDVP_THROW(TDVP_ERR_DEVICE, "rocblas_create_handle failed");
+    if (rocblas_set_stream(w->blas, w->stream) != rocblas_status_success)
+      TDVP_THROW(TDVP_ERR_DEVICE, "rocblas_set_stream failed");
+    HIP_CHECK(hipEventCreate(&w->ev_a));
+    HIP_CHECK(hipEventCreate(&w->ev_b));
+    HIP_CHECK(hipEventCreate(&w->ev_c));
+    HIP_CHECK(hipEventCreate(&w->ev_d));
+  }
+}
+
+void tdvp_ctx_s::destroy_workers() {
+  for (tdvp_ctx_s* w : workers) {
+    if (w->stream) (void)hipStreamSynchronize(w->stream);
+    if (w->ev_a) (void)hipEventDestroy(w->ev_a);
+    if (w->ev_b) (void)hipEventDestroy(w->ev_b);
+    if (w->ev_c) (void)hipEventDestroy(w->ev_c);
+    if (w->ev_d) (void)hipEventDestroy(w->ev_d);
+    if (w->blas) rocblas_destroy_handle(w->blas);
+    if (w->stream) (void)hipStreamDestroy(w->stream);
+    delete w;
+  }
+  workers.clear();
 }
 
 void tdvp_ctx_s::sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
@@ -52,6 +100,44 @@ tdvp_status guarded(tdvp_ctx_s* ctx, F&& f) {
 
 void bind(tdvp_ctx_s* ctx) { HIP_CHECK(hipSetDevice(ctx->device)); }
 
+// Run f(worker_ctx, j) for j < n.  One instance runs on the context itself;
+// several run concurrently, one host thread and one worker context each (a
+// GSE-TDVP1 step is a chain of latency-bound factorisations, so independent
+// chains on separate streams fill the device).  Every stream is synchronised
+// before returning; the first failure is rethrown after all threads joined.
+template <class F>
+void for_instances(tdvp_ctx_s* ctx, int n, F&& f) {
+  if (n == 1) {
+    f(ctx, 0);
+    return;
+  }
+  ctx->sync();
+  const int nw = std::min(n, 16);
+  ctx->ensure_workers(nw);
+  std::vector<std::exception_ptr> errs(n);
+  std::vector<std::thread> threads;
+  for (int w = 0; w < nw; ++w) {
+    threads.emplace_back([&, w] {
+      tdvp_ctx_s* wc = ctx->workers[w];
+      if (hipSetDevice(ctx->device) != hipSuccess) {
+        for (int j = w; j < n; j += nw) errs[j] = std::make_exception_ptr(TdvpError(TDVP_ERR_DEVICE, "hipSetDevice"));
+        return;
+      }
+      for (int j = w; j < n; j += nw) {
+        try {
+          f(wc, j);
+        } catch (...) {
+          errs[j] = std::current_exception();
+        }
+      }
+      (void)hipStreamSynchronize(wc->stream);
+    });
+  }
+  for (auto& t : threads) t.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+}
+
 bool all_finite(const double* x, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(x[i])) return false;
@@ -78,13 +164,14 @@ tdvp_status kernel_call(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, 
     bind(ctx);
     const int cb = prec == TDVP_FP64 ? 16 : 8;
     const size_t half = (size_t)2 * ml * mr * std::max(wl, wr) * cb;
+    const size_t split = (size_t)32 * ml * mr * cb;  // split-K partial products
     DBuf ws(ctx), tab(ctx);
     char* w1;
     if (workspace) w1 = static_cast<char*>(workspace);
-    else w1 = static_cast<char*>(ws.ensure(2 * half));
+    else w1 = static_cast<char*>(ws.ensure(2 * half + split));
     SiteTables tb{};
     if (W_host) tb = upload_tables(ctx, host_W(W_host, wl, wr), wl, wr, tab);
-    f(tb, w1, w1 + half);
+    f(tb, w1, w1 + half, SplitWS{w1 + 2 * half, split});
     if (!workspace || W_host) ctx->sync();  // keep temporaries alive until the kernels finish
   });
 }
@@ -136,6 +223,7 @@ void tdvp_ctx_destroy(tdvp_ctx ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->destroy_workers();
   if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
   if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
@@ -281,16 +369,16 @@ tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo
       if (!psi[j]->valid || !op[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
     bind(ctx);
-    for (int j = 0; j < n; ++j) {
+    for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
       tdvp_expand_stats st{};
       try {
-        run_expand(ctx, *psi[j], *op[j], p, st);
+        run_expand(c, *psi[j], *op[j], p, st);
       } catch (...) {
         psi[j]->valid = false;
         throw;
       }
       if (stats) stats[j] = st;
-    }
+    });
   });
 }
 
@@ -312,10 +400,10 @@ tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, co
       if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
     bind(ctx);
-    for (int j = 0; j < n; ++j) {
+    for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
       tdvp_sweep_stats st{};
       try {
-        run_sweep(ctx, *psi[j], *H[j], p, st);
+        run_sweep(c, *psi[j], *H[j], p, st);
       } catch (const TdvpError& e) {
         if (e.code != TDVP_ERR_NOCONV) psi[j]->valid = false;
         throw;
@@ -324,7 +412,7 @@ tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, co
         throw;
       }
       if (stats) stats[j] = st;
-    }
+    });
   });
 }
 
@@ -340,7 +428,9 @@ tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mp
       if (other) ARG_CHECK(other[j] && other[j]->N == psi[j]->N, "other MPS does not match");
     }
     bind(ctx);
-    for (int j = 0; j < n; ++j) run_measure(ctx, *psi[j], H ? H[j] : nullptr, other ? other[j] : nullptr, out[j]);
+    for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
+      run_measure(c, *psi[j], H ? H[j] : nullptr, other ? other[j] : nullptr, out[j]);
+    });
   });
 }
 
@@ -368,35 +458,38 @@ tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, 
 tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
                             const void* L, const void* Rt, const void* C, void* Y, void* workspace) {
   if (!W_host) return TDVP_ERR_ARG;
-  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace, [&](const SiteTables& tb, void* w1, void* w2) {
-    if (prec == TDVP_FP64) heff_apply<double>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2);
-    else heff_apply<float>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2);
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace,
+                     [&](const SiteTables& tb, void* w1, void* w2, SplitWS sk) {
+    if (prec == TDVP_FP64) heff_apply<double>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2, nullptr, sk);
+    else heff_apply<float>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2, nullptr, sk);
   });
 }
 
 tdvp_status tdvp_keff_apply(tdvp_ctx ctx, int prec, int ml, int w, int mr, const void* L, const void* Rt,
                             const void* X, void* Y, void* workspace) {
-  return kernel_call(ctx, prec, ml, w, w, mr, nullptr, workspace, [&](const SiteTables&, void* w1, void*) {
-    if (prec == TDVP_FP64) keff_apply<double>(ctx, ml, w, mr, L, Rt, X, Y, w1);
-    else keff_apply<float>(ctx, ml, w, mr, L, Rt, X, Y, w1);
+  return kernel_call(ctx, prec, ml, w, w, mr, nullptr, workspace, [&](const SiteTables&, void* w1, void*, SplitWS sk) {
+    if (prec == TDVP_FP64) keff_apply<double>(ctx, ml, w, mr, L, Rt, X, Y, w1, sk);
+    else keff_apply<float>(ctx, ml, w, mr, L, Rt, X, Y, w1, sk);
   });
 }
 
 tdvp_status tdvp_env_left(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
                           const void* L, const void* A, void* Lout, void* workspace) {
   if (!W_host) return TDVP_ERR_ARG;
-  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace, [&](const SiteTables& tb, void* w1, void* w2) {
-    if (prec == TDVP_FP64) env_left<double>(ctx, tb, ml, wl, wr, mr, L, A, Lout, w1, w2);
-    else env_left<float>(ctx, tb, ml, wl, wr, mr, L, A, Lout, w1, w2);
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace,
+                     [&](const SiteTables& tb, void* w1, void* w2, SplitWS sk) {
+    if (prec == TDVP_FP64) env_left<double>(ctx, tb, ml, wl, wr, mr, L, A, Lout, w1, w2, sk);
+    else env_left<float>(ctx, tb, ml, wl, wr, mr, L, A, Lout, w1, w2, sk);
   });
 }
 
 tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
                            const void* Rt, const void* B, void* Rout, void* workspace) {
   if (!W_host) return TDVP_ERR_ARG;
-  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace, [&](const SiteTables& tb, void* w1, void* w2) {
-    if (prec == TDVP_FP64) env_right<double>(ctx, tb, ml, wl, wr, mr, Rt, B, Rout, w1, w2);
-    else env_right<float>(ctx, tb, ml, wl, wr, mr, Rt, B, Rout, w1, w2);
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, workspace,
+                     [&](const SiteTables& tb, void* w1, void* w2, SplitWS sk) {
+    if (prec == TDVP_FP64) env_right<double>(ctx, tb, ml, wl, wr, mr, Rt, B, Rout, w1, w2, sk);
+    else env_right<float>(ctx, tb, ml, wl, wr, mr, Rt, B, Rout, w1, w2, sk);
   });
 }
 

@@ -40,10 +40,19 @@ struct tdvp_ctx_s {
   void* user = nullptr;
   std::string last_error;
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
+  // Worker contexts for calls on several independent instances: each owns a
+  // stream, a rocBLAS handle and events, and allocates stream-ordered memory
+  // (hipMallocAsync on its own stream).  Created on first use, kept until the
+  // parent is destroyed.
+  bool owns_stream = false;
+  bool async_alloc = false;
+  std::vector<tdvp_ctx_s*> workers;
 
   void* dalloc(size_t bytes);
   void dfree(void* p);
   void sync();
+  void ensure_workers(int n);
+  void destroy_workers();
 };
 
 // Growable device buffer owned through the context's allocator.

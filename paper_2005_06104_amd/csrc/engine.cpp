@@ -670,16 +670,27 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
   hipStream_t s = ctx->stream;
   const int N = in.N;
   const int cb = cbytes<T>();
-  // working-precision copies of the input tensors
+  // working-precision copies of the input tensors.  The input is
+  // left-canonical, so its norm sits in the last site; the output is
+  // normalised and every cut is relative, so that site enters scaled to unit
+  // norm (an unnormalised state would overflow FP32).
   std::vector<DBuf> Mt;
   std::vector<const void*> Mp(N);
+  const double in_norm = W.sc.norm(in.site(N - 1), in.elems(N - 1));
+  if (!(in_norm > 0.0) || !std::isfinite(in_norm)) TDVP_THROW(TDVP_ERR_NUMERIC, "MPS with zero or non-finite norm");
   for (int i = 0; i < N; ++i) {
     if (sizeof(T) == 8) {
       Mp[i] = in.site(i);
     } else {
       Mt.emplace_back(ctx);
       Mt.back().ensure((size_t)in.elems(i) * cb);
-      kern::z2c(s, Mt.back().p, in.site(i), in.elems(i));
+      if (i == N - 1) {
+        W.tmpC.ensure((size_t)in.elems(i) * ZB);
+        kern::zscale(s, W.tmpC.p, in.site(i), zc(1.0 / in_norm, 0.0), in.elems(i));
+        kern::z2c(s, Mt.back().p, W.tmpC.p, in.elems(i));
+      } else {
+        kern::z2c(s, Mt.back().p, in.site(i), in.elems(i));
+      }
       Mp[i] = Mt.back().p;
     }
   }

@@ -49,16 +49,25 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
                                                    long long sps) {
   using c2 = typename VT<T>::c2;
   using acc_t = typename VT<T>::acc;
-  __shared__ T As_r[BK][BM + PAD], As_i[BK][BM + PAD];
-  __shared__ T Bs_r[BK][BN + PAD], Bs_i[BK][BN + PAD];
+  __shared__ T As_r[2][BK][BM + PAD], As_i[2][BK][BM + PAD];
+  __shared__ T Bs_r[2][BK][BN + PAD], Bs_i[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const long long bz = blockIdx.z / S;
-  const int split = blockIdx.z % S;
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // linear id g runs on XCD g % 8.  Give each XCD a contiguous band of tiles
+  // (z-slice, then tile row, then tile column) so that the operand panels a
+  // band needs stay in that XCD's L2.
+  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const unsigned tot = gx * gy * gz;
+  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned t = (tot % 8u == 0u) ? (lin % 8u) * (tot / 8u) + lin / 8u : lin;
+  const unsigned tz = t / (gx * gy), trem = t % (gx * gy);
+  const int m0 = (int)(trem / gx) * BM, n0 = (int)(trem % gx) * BN;
+  const long long bz = tz / S;
+  const int split = tz % S;
   const int kb = split * Kc;
   const int ke = min(K, kb + Kc);
   const c2* Ab = reinterpret_cast<const c2*>(A) + bz * sa;
@@ -94,22 +103,22 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       rb[it] = v;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
       const int idx = tid + it * NT;
       int m, k;
       if (!TA) { m = idx / BK; k = idx % BK; } else { k = idx / BM; m = idx % BM; }
-      As_r[k][m] = ra[it].x;
-      As_i[k][m] = ra[it].y;
+      As_r[buf][k][m] = ra[it].x;
+      As_i[buf][k][m] = ra[it].y;
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
       const int idx = tid + it * NT;
       int n, k;
       if (!TB) { k = idx / BN; n = idx % BN; } else { n = idx / BK; k = idx % BK; }
-      Bs_r[k][n] = rb[it].x;
-      Bs_i[k][n] = rb[it].y;
+      Bs_r[buf][k][n] = rb[it].x;
+      Bs_i[buf][k][n] = rb[it].y;
     }
   };
 
@@ -123,9 +132,12 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
     }
 
   const int lr = lane & 15, lk = lane >> 4;
+  // double-buffered LDS: compute on `cur` while the next tile's global loads
+  // are in flight, then store them into the other buffer; one barrier per tile
   load(kb);
-  store();
+  store(0);
   __syncthreads();
+  int cur = 0;
   for (int k0 = kb; k0 < ke; k0 += BK) {
     const bool more = (k0 + BK) < ke;
     if (more) load(k0 + BK);
@@ -135,14 +147,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       T a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a_r[i] = As_r[kr][wm * 32 + i * 16 + lr];
-        a_i[i] = As_i[kr][wm * 32 + i * 16 + lr];
+        a_r[i] = As_r[cur][kr][wm * 32 + i * 16 + lr];
+        a_i[i] = As_i[cur][kr][wm * 32 + i * 16 + lr];
         a_n[i] = -a_i[i];
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        b_r[j] = Bs_r[kr][wn * 32 + j * 16 + lr];
-        b_i[j] = Bs_i[kr][wn * 32 + j * 16 + lr];
+        b_r[j] = Bs_r[cur][kr][wn * 32 + j * 16 + lr];
+        b_i[j] = Bs_i[cur][kr][wn * 32 + j * 16 + lr];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -154,11 +166,9 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
           ci[i][j] = mfma(a_i[i], b_r[j], ci[i][j]);
         }
     }
+    if (more) store(cur ^ 1);
     __syncthreads();
-    if (more) {
-      store();
-      __syncthreads();
-    }
+    cur ^= 1;
   }
 
   const bool has_beta = (br != T(0)) || (bi != T(0));
@@ -216,11 +226,12 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ P, int S, long long M
 }
 
 // Number of K splits: enough workgroups to cover the CUs when the output
-// has few tiles and K is long; each split keeps >= 128 of K.
+// has few tiles and K is long; each split keeps >= 256 of K, so the extra
+// partial-product traffic stays below the operand traffic.
 inline int choose_splits(int M, int N, int K, int batch, size_t ws_bytes, size_t cbytes) {
   const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
-  if (batch != 1 || ws_bytes == 0 || tiles >= 512 || K < 256) return 1;
-  int S = (int)std::min<long long>((512 + tiles - 1) / tiles, K / 128);
+  if (batch != 1 || ws_bytes == 0 || tiles >= 256 || K < 512) return 1;
+  int S = (int)std::min<long long>((512 + tiles - 1) / tiles, K / 256);
   S = std::min(S, 16);
   while (S > 1 && (size_t)S * M * N * cbytes > ws_bytes) --S;
   return std::max(S, 1);

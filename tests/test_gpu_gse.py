@@ -212,3 +212,34 @@ def test_gse_oat_closed_form_on_device(env):
         sx = O.sx_total(T.tdvp_mps_to_host(g))
         assert abs(sx - O.sx_total(psi)) < 1e-10
         assert abs(sx - O.oat_sx_exact(N, t)) < 5e-8
+
+
+def test_batched_instances_match_single_runs(env):
+    # several independent ladders of different sizes in one call (worker
+    # streams) give the same states as the same ladders run one by one
+    T, ctx = env
+    from oracle import mps as M
+    lats = [I.ladder(L, jl, jr, "snake") for (L, jl, jr) in ((4, 1.0, 0.6), (6, 0.8, 1.2), (5, 1.1, 0.9),
+                                                             (3, 1.0, 1.0), (7, 0.7, 1.3))]
+    Hs, ops, batch, single = [], [], [], []
+    for j, lat in enumerate(lats):
+        terms = I.heisenberg_terms(lat.couplings)
+        lam = I.energy_scale(lat.couplings)
+        Hs.append(T.tdvp_create_mpo(ctx, lat.n_sites, terms))
+        ops.append(T.tdvp_create_mpo(ctx, lat.n_sites, terms, 1.0, -1j * (-1j / lam)))
+        psi0 = I.product_mps(lat.neel())
+        batch.append(T.tdvp_mps_from_host(ctx, psi0))
+        single.append(T.tdvp_mps_from_host(ctx, psi0))
+    for _ in range(3):
+        T.tdvp_expand_basis(ctx, batch, ops, 3, 1e-12, 1e-8, 32, "fp64")
+        T.tdvp_sweep(ctx, batch, Hs, -0.2j, 1e-10, 32, 1e-12, 30, "fp64", True)
+        for j in range(len(lats)):
+            T.tdvp_expand_basis(ctx, [single[j]], [ops[j]], 3, 1e-12, 1e-8, 32, "fp64")
+            T.tdvp_sweep(ctx, [single[j]], [Hs[j]], -0.2j, 1e-10, 32, 1e-12, 30, "fp64", True)
+    mb = T.tdvp_measure(ctx, batch, Hs)
+    ms = T.tdvp_measure(ctx, single, Hs)
+    for j in range(len(lats)):
+        a, b = T.tdvp_mps_to_host(batch[j]), T.tdvp_mps_to_host(single[j])
+        assert M.bond_dims(a) == M.bond_dims(b)
+        assert 1 - M.fidelity(a, b) < 1e-12
+        assert abs(mb[j]["energy"] - ms[j]["energy"]) < 1e-11
