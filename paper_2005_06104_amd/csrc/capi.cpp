@@ -126,6 +126,9 @@ void for_instances(tdvp_ctx_s* ctx, int n, F&& f) {
       for (int j = w; j < n; j += nw) {
         try {
           f(wc, j);
+        } catch (const TdvpError& e) {
+          errs[j] = std::make_exception_ptr(TdvpError(e.code, std::string(e.what()) + " (instance " +
+                                                                    std::to_string(j) + ")"));
         } catch (...) {
           errs[j] = std::current_exception();
         }

@@ -428,13 +428,21 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   std::vector<double> lam;
   la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
-  // A = C V_n S_n^-1 (orthonormal up to rounding), polished by Newton-Schulz; R = A^dagger C
+  // A spans C V_n; R = A^dagger C.  When every kept weight is well above the
+  // eigenvector accuracy (u lambda_1 / lambda_n << 1), C V_n S_n^-1 is
+  // orthonormal up to rounding and Newton-Schulz polishes it; otherwise a QR
+  // of C V_n gives the orthonormal basis.
   W.tmpC.ensure((size_t)rows * n * ZB);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, W.tmpB.p, cols, 0, 0.0, W.tmpC.p, n, 0, 1);
   A.ensure((size_t)rows * n * ZB);
   R.ensure((size_t)n * cols * ZB);
-  kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
-  ns_cols(W, A.p, rows, n, 3);
+  if (lam[n - 1] > 1e-8 * lam[0]) {
+    kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
+    ns_cols(W, A.p, rows, n, 3);
+  } else {
+    W.tmpA.ensure((size_t)n * n * ZB);
+    la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+  }
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, 0, C, cols, 0, 0.0, R.p, cols, 0, 1);
   return n;
 }
@@ -457,13 +465,19 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   std::vector<double> lam;
   la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
-  // B = S_n^-1 U_n^dagger C (orthonormal rows up to rounding), polished by Newton-Schulz; L = C B^dagger
+  // B spans the rows of U_n^dagger C; L = C B^dagger (Newton-Schulz on
+  // S_n^-1 U_n^dagger C when the kept weights allow it, an LQ otherwise)
   W.tmpC.ensure((size_t)n * cols * ZB);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, 0, C, cols, 0, 0.0, W.tmpC.p, cols, 0, 1);
   L.ensure((size_t)rows * n * ZB);
   B.ensure((size_t)n * cols * ZB);
-  kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
-  ns_rows(W, B.p, n, cols, 3);
+  if (lam[n - 1] > 1e-8 * lam[0]) {
+    kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
+    ns_rows(W, B.p, n, cols, 3);
+  } else {
+    W.tmpA.ensure((size_t)n * n * ZB);
+    la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+  }
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, B.p, cols, 0, 0.0, L.p, n, 0, 1);
   return n;
 }

@@ -89,20 +89,54 @@ void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, s
 
 void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows, DBuf& work) {
   const size_t nn = (size_t)n * n;
-  char* base = static_cast<char*>(work.ensure(sizeof(rz) * nn + sizeof(double) * (2 * (size_t)n + 2) + 64));
+  const int nb = kern::zdots_blocks((long long)nn);
+  char* base = static_cast<char*>(work.ensure(sizeof(rz) * nn + sizeof(double) * (2 * (size_t)n + 8) +
+                                              sizeof(rz) * ((size_t)nb + 2) + 128));
+  // layout (16-byte aligned complex first): X | partial sums | sum | D | E | info, sweeps
   rz* X = reinterpret_cast<rz*>(base);
-  double* dD = reinterpret_cast<double*>(base + sizeof(rz) * nn);
+  rz* dpart = X + nn;
+  rz* dsum = dpart + nb;
+  double* dD = reinterpret_cast<double*>(dsum + 1);
   double* dE = dD + n + 1;
-  int* dinfo = reinterpret_cast<int*>(dE + n + 1);
+  double* dres = dE + n + 1;
+  int* dinfo = reinterpret_cast<int*>(dres + 2);
+  int* dsweeps = dinfo + 1;
   HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
   kern::zhermitize(ctx->stream, X, n);
   blas_check(rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, X, n, dD, dE, dinfo),
              "zheevd");
-  // ascending -> descending: output row j is input row n-1-j
-  kern::copy2d(ctx->stream, rows, n, X + (size_t)(n - 1) * n, -(long long)n, n, n, 16);
+  // validate: orthonormal eigenvectors have sum |v|^2 = n, eigenvalues finite
+  kern::zdots(ctx->stream, X, (long long)nn, 1, X, (long long)nn, dpart, nb, dsum);
+  int info = 0;
+  zc vsum;
+  HIP_CHECK(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipMemcpyAsync(&vsum, dsum, sizeof(rz), hipMemcpyDeviceToHost, ctx->stream));
   std::vector<double> asc(n);
   HIP_CHECK(hipMemcpyAsync(asc.data(), dD, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
-  read_info(ctx, dinfo, "zheevd");
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  bool ok = info == 0 && std::isfinite(vsum.real()) && std::fabs(vsum.real() - n) <= 1e-6 * n;
+  for (double v : asc) ok = ok && std::isfinite(v);
+  if (!ok) {
+    // divide and conquer failed (no convergence, or a non-finite result):
+    // check the input, then use the Jacobi eigensolver on a fresh copy
+    std::vector<double> h(2 * nn);
+    HIP_CHECK(hipMemcpyAsync(h.data(), H, sizeof(rz) * nn, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    for (double v : h)
+      if (!std::isfinite(v)) TDVP_THROW(TDVP_ERR_NUMERIC, "eigh: non-finite input matrix (n = " + std::to_string(n) + ")");
+    HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
+    kern::zhermitize(ctx->stream, X, n);
+    blas_check(rocsolver_zheevj(ctx->blas, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, n, X,
+                                n, 0.0, dres, 100, dsweeps, dD, dinfo),
+               "zheevj");
+    read_info(ctx, dinfo, "zheevj");
+  }
+  // ascending -> descending: output row j is input row n-1-j
+  kern::copy2d(ctx->stream, rows, n, X + (size_t)(n - 1) * n, -(long long)n, n, n, 16);
+  if (!ok) {
+    HIP_CHECK(hipMemcpyAsync(asc.data(), dD, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  }
   lam.resize(n);
   for (int j = 0; j < n; ++j) lam[j] = asc[n - 1 - j];
 }
