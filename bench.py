@@ -27,8 +27,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "TDVP sweep time/step & H_eff matvec TFLOP/s, mixed vs FP64, at fixed fidelity"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-DTYPE = {"fp64": "f64", "fp32": "f32"}
+# dense matrix-core peaks of the arithmetic each precision runs on
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
+# matrix-core products issued per algorithmic product (the split uses three)
+MFMA_PER_FLOP = {"fp64": 1, "fp32": 1, "bf16": 1, "bf16x3": 3}
 
 
 def log(*a):
@@ -143,6 +146,7 @@ def summarize(acc, steps, prec):
         "matvec_tflops": mv_tf,
         "heff_gemm_tflops": gemm_tf,
         "heff_gemm_frac_of_peak": (gemm_tf / PEAK_TFLOPS[prec]) if gemm_tf else None,
+        "heff_gemm_mfma_frac_of_peak": (gemm_tf * MFMA_PER_FLOP[prec] / PEAK_TFLOPS[prec]) if gemm_tf else None,
         "split_ms_per_step": {"krylov": acc["ms_krylov"] / steps, "extend": acc["ms_extend"] / steps,
                               "sweep": acc["ms_sweep"] / steps, "heff_matvec": acc["ms_matvec"] / steps},
         "heff_gemm_launches": acc["n_heff_gemm"],
@@ -230,7 +234,8 @@ def kernel_only(args):
     from paper_2005_06104_amd import tdvp as T
     chi, w = 256, 8
     ctx = T.Context(0)
-    dt = torch.complex128 if args.prec != "fp32" else torch.complex64
+    dt = torch.complex128 if args.prec in (None, "fp64") else torch.complex64
+    kp = None if args.prec in (None, "fp64") else args.prec
     L = torch.from_numpy(I.random_hermitian_env(chi, w, 1)).to(dt).cuda()
     Rt = torch.from_numpy(np.ascontiguousarray(I.random_hermitian_env(chi, w, 2).transpose(1, 2, 0))).to(dt).cuda()
     Cin = torch.from_numpy(I.random_complex((chi, 2, chi), 3)).to(dt).cuda()
@@ -239,12 +244,12 @@ def kernel_only(args):
     nnz = int(np.count_nonzero(W))
     ws = torch.empty((4 * w + 32) * chi * chi, dtype=dt, device="cuda")
     for _ in range(3):
-        T.tdvp_heff_apply(ctx, W, L, Rt, Cin, Y, ws)
+        T.tdvp_heff_apply(ctx, W, L, Rt, Cin, Y, ws, prec=kp)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(args.steps):
-        T.tdvp_heff_apply(ctx, W, L, Rt, Cin, Y, ws)
+        T.tdvp_heff_apply(ctx, W, L, Rt, Cin, Y, ws, prec=kp)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / max(args.steps, 1)
@@ -264,11 +269,14 @@ def main():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--workload", type=int, default=1, help="0..3: the benchmark workloads")
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16", "bf16x3"], default=None)
+    ap.add_argument("--compare", default=None,
+                    help="comma-separated precisions run after the main one on the same workload "
+                         "(default: fp32,bf16x3,bf16 after fp64; fp64 after a mixed precision)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
-                    help="skip the run in the other precision (mixed vs FP64)")
+                    help="skip the runs in the other precisions (mixed vs FP64)")
     ap.add_argument("--batch", action="store_true",
                     help="many independent ladders stepped concurrently (instance-steps/s)")
     ap.add_argument("--batch-size", type=int, default=64)
@@ -326,18 +334,23 @@ def main():
                        "achieved": gemm_tf, "peak": peak, "unit": "TFLOP/s",
                        "frac": (gemm_tf / peak) if gemm_tf else None, "traffic": traffic}
     if args.compare_prec:
-        other = "fp32" if prec == "fp64" else "fp64"
-        alt = run_workload(T, ctx, w, other, args.warmup, args.steps, other)
-        ra = summarize(alt, args.steps, other)
-        ov = T.tdvp_measure(ctx, [alt["psi"]], None, [main_run["psi"]])[0]
-        fid = abs(ov["overlap"]) ** 2 / (main_run["final"]["norm"] ** 2 * alt["final"]["norm"] ** 2)
-        ra["fidelity_vs_" + prec] = fid
-        ra["energy_diff_vs_" + prec] = ra["energy"] - res["energy"]
-        ra["speedup_vs_" + prec] = ra["value"] / res["value"]
-        t_total = abs(w.dt) * (args.warmup + args.steps)
-        ra["fidelity_loss_per_unit_time"] = (1 - fid) / t_total
-        out[other] = ra
-        del alt
+        others = args.compare.split(",") if args.compare else (
+            ["fp32", "bf16x3", "bf16"] if prec == "fp64" else ["fp64"])
+        for other in others:
+            if other == prec or other not in PEAK_TFLOPS:
+                continue
+            alt = run_workload(T, ctx, w, other, args.warmup, args.steps, other)
+            ra = summarize(alt, args.steps, other)
+            ov = T.tdvp_measure(ctx, [alt["psi"]], None, [main_run["psi"]])[0]
+            fid = abs(ov["overlap"]) ** 2 / (main_run["final"]["norm"] ** 2 * alt["final"]["norm"] ** 2)
+            ra["fidelity_vs_" + prec] = fid
+            ra["energy_diff_vs_" + prec] = ra["energy"] - res["energy"]
+            ra["max_abs_sz_diff_vs_" + prec] = float(abs(alt["final"]["sz"] - main_run["final"]["sz"]).max())
+            ra["speedup_vs_" + prec] = ra["value"] / res["value"]
+            t_total = abs(w.dt) * (args.warmup + args.steps)
+            ra["fidelity_loss_per_unit_time"] = (1 - fid) / t_total
+            out[other] = ra
+            del alt
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, min(w.chi_max, res["max_bond"]))

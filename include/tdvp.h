@@ -62,8 +62,20 @@ typedef enum {
 
 /* Precision of the contractions (environments, effective Hamiltonians, MPO
  * application).  Lanczos recurrences, reorthogonalisation, the tridiagonal
- * exponential, QR/SVD/eigh and the stored site tensors are always FP64. */
-typedef enum { TDVP_FP64 = 0, TDVP_FP32 = 1 } tdvp_prec;
+ * exponential, QR/SVD/eigh and the stored site tensors are always FP64.
+ *   TDVP_FP32            complex64 operands, FP32 MFMA;
+ *   TDVP_BF16_FP32ACC    complex64 operands rounded to BF16 (nearest even) as
+ *                        they enter the matrix cores, FP32 accumulation;
+ *   TDVP_BF16X3_FP32ACC  each FP32 operand split into two BF16 terms
+ *                        x = hi + lo, products ah*bh + ah*bl + al*bh with FP32
+ *                        accumulation (about 16 significant bits).
+ * All three keep the environments and intermediates in complex64. */
+typedef enum {
+  TDVP_FP64 = 0,
+  TDVP_FP32 = 1,
+  TDVP_BF16_FP32ACC = 2,
+  TDVP_BF16X3_FP32ACC = 3
+} tdvp_prec;
 
 /* GEMM operand modes: N = as stored, T = transposed, C = conjugate transpose,
  * R = conjugated (not transposed). */

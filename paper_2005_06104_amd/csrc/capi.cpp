@@ -162,7 +162,7 @@ tdvp_status kernel_call(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, 
                         F&& f) {
   if (!ctx) return TDVP_ERR_ARG;
   return guarded(ctx, [&] {
-    ARG_CHECK(prec == TDVP_FP64 || prec == TDVP_FP32, "unknown precision");
+    ARG_CHECK(prec >= TDVP_FP64 && prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
     ARG_CHECK(ml >= 1 && mr >= 1 && wl >= 1 && wr >= 1 && wl <= 32 && wr <= 32, "bad sizes");
     bind(ctx);
     const int cb = prec == TDVP_FP64 ? 16 : 8;
@@ -174,6 +174,7 @@ tdvp_status kernel_call(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, 
     else w1 = static_cast<char*>(ws.ensure(2 * half + split));
     SiteTables tb{};
     if (W_host) tb = upload_tables(ctx, host_W(W_host, wl, wr), wl, wr, tab);
+    kern::FloatModeScope mode(kern::float_mode_of(prec));
     f(tb, w1, w1 + half, SplitWS{w1 + 2 * half, split});
     if (!workspace || W_host) ctx->sync();  // keep temporaries alive until the kernels finish
   });
@@ -365,7 +366,7 @@ tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo
     ARG_CHECK(p.k >= 1 && p.k <= 16, "k must be in 1..16");
     ARG_CHECK(p.chi_max >= 1, "chi_max must be >= 1");
     ARG_CHECK(p.eps_K >= 0 && p.eps_M >= 0, "cutoffs must be >= 0");
-    ARG_CHECK(p.prec == TDVP_FP64 || p.prec == TDVP_FP32, "unknown precision");
+    ARG_CHECK(p.prec >= TDVP_FP64 && p.prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
     for (int j = 0; j < n; ++j) {
       ARG_CHECK(psi[j] && op[j], "NULL handle");
       ARG_CHECK(psi[j]->N == op[j]->N(), "MPS and MPO site counts differ");
@@ -396,7 +397,7 @@ tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, co
     ARG_CHECK(p.chi_max >= 1, "chi_max must be >= 1");
     ARG_CHECK(p.krylov_max >= 1 && p.krylov_max <= 64, "krylov_max must be in 1..64");
     ARG_CHECK(p.krylov_tol >= 0, "krylov_tol must be >= 0");
-    ARG_CHECK(p.prec == TDVP_FP64 || p.prec == TDVP_FP32, "unknown precision");
+    ARG_CHECK(p.prec >= TDVP_FP64 && p.prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
     for (int j = 0; j < n; ++j) {
       ARG_CHECK(psi[j] && H[j], "NULL handle");
       ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
@@ -446,14 +447,16 @@ tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, 
   return guarded(ctx, [&] {
     ARG_CHECK(M >= 0 && N >= 0 && K >= 0 && batch >= 0, "negative size");
     ARG_CHECK(op_a >= 0 && op_a <= 3 && op_b >= 0 && op_b <= 3, "bad op");
-    ARG_CHECK(prec == TDVP_FP64 || prec == TDVP_FP32, "unknown precision");
+    ARG_CHECK(prec >= TDVP_FP64 && prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
     bind(ctx);
     if (prec == TDVP_FP64)
       kern::gemm<double>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
                          zc(beta_re, beta_im), C, ldc, stride_c, batch);
-    else
+    else {
+      kern::FloatModeScope mode(kern::float_mode_of(prec));
       kern::gemm<float>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
                         zc(beta_re, beta_im), C, ldc, stride_c, batch);
+    }
   });
 }
 

@@ -104,6 +104,22 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
 template <typename T>
 void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
                void* C, long long ldc, void* ws = nullptr, size_t ws_bytes = 0);
+// Arithmetic of the complex64 GEMMs issued from the calling host thread:
+// 0 FP32 MFMA; 1 BF16 inputs (rounded to nearest even), FP32 accumulation;
+// 2 BF16 three-term split x = hi + lo with FP32 accumulation.
+void set_float_mode(int mode);
+int float_mode();
+struct FloatModeScope {
+  int saved;
+  explicit FloatModeScope(int mode) : saved(float_mode()) { set_float_mode(mode); }
+  ~FloatModeScope() { set_float_mode(saved); }
+  FloatModeScope(const FloatModeScope&) = delete;
+  FloatModeScope& operator=(const FloatModeScope&) = delete;
+};
+// complex64 GEMM mode of a tdvp_prec other than TDVP_FP64
+inline int float_mode_of(int prec) {
+  return prec == TDVP_BF16_FP32ACC ? 1 : prec == TDVP_BF16X3_FP32ACC ? 2 : 0;
+}
 // Plain NN product with split-K scratch (environments, zero-site H_eff).
 template <typename T>
 void gemm_nn_ws(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,

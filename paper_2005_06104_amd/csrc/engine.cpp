@@ -932,16 +932,24 @@ void expand_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const t
 void run_sweep(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
                tdvp_sweep_stats& st) {
   const double t0 = now_ms();
-  if (p.prec == TDVP_FP64) sweep_impl<double>(ctx, psi, H, p, st);
-  else sweep_impl<float>(ctx, psi, H, p, st);
+  if (p.prec == TDVP_FP64) {
+    sweep_impl<double>(ctx, psi, H, p, st);
+  } else {
+    kern::FloatModeScope mode(kern::float_mode_of(p.prec));
+    sweep_impl<float>(ctx, psi, H, p, st);
+  }
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
   st.ms = now_ms() - t0;
 }
 
 void run_expand(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const tdvp_expand_params& p,
                 tdvp_expand_stats& st) {
-  if (p.prec == TDVP_FP64) expand_impl<double>(ctx, psi, op, p, st);
-  else expand_impl<float>(ctx, psi, op, p, st);
+  if (p.prec == TDVP_FP64) {
+    expand_impl<double>(ctx, psi, op, p, st);
+  } else {
+    kern::FloatModeScope mode(kern::float_mode_of(p.prec));
+    expand_impl<float>(ctx, psi, op, p, st);
+  }
 }
 
 // ------------------------------------------------------------ measurement

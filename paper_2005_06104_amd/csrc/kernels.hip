@@ -198,6 +198,215 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
       }
 }
 
+// ---------------------------------------------------------------- BF16 GEMM
+// Complex GEMM on complex64 operands with BF16 MFMA inputs and FP32
+// accumulation (v_mfma_f32_16x16x32_bf16: lane l holds row l%16 and the
+// eight k values 8*(l/16)..+7 of its operand; outputs as the f32 MFMA).
+// Operand tiles are rounded to BF16 (nearest even) as they are staged into
+// LDS, one plane per real/imaginary part, k contiguous.  SPLIT = 1 keeps the
+// rounding residual as a second BF16 term, x = hi + lo, and forms each real
+// product as ah bh + ah bl + al bh (three MFMA products, ~16-bit operands).
+constexpr int BK2 = 32, BKP2 = BK2 + 8, PL2 = 64 * BKP2;
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0,
+                                                  0);
+}
+__device__ inline uint4 bf16_neg(uint4 v) {
+  const unsigned s = 0x80008000u;
+  return uint4{v.x ^ s, v.y ^ s, v.z ^ s, v.w ^ s};
+}
+
+// A 64 x 32 complex operand tile (rows r = m of A or n of B) as two quads of
+// four consecutive k per thread.  KC: k is the contiguous index in memory.
+template <bool KC, bool CONJ>
+__device__ inline void bf_load(const float2* __restrict__ X, long long ld, int r0, int R, int k0, int ke, int tid,
+                               float2 (&v)[2][4]) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int q = tid + it * NT;
+    const int row = KC ? (q >> 3) : (q & 63);
+    const int kq = KC ? (q & 7) : (q >> 6);
+    const int gr = r0 + row;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gk = k0 + 4 * kq + j;
+      float2 e;
+      e.x = 0.f;
+      e.y = 0.f;
+      if (gr < R && gk < ke) e = KC ? X[(long long)gr * ld + gk] : X[(long long)gk * ld + gr];
+      if (CONJ) e.y = -e.y;
+      v[it][j] = e;
+    }
+  }
+}
+
+template <bool KC, int SPLIT>
+__device__ inline void bf_store(unsigned short* P, int tid, const float2 (&v)[2][4]) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int q = tid + it * NT;
+    const int row = KC ? (q >> 3) : (q & 63);
+    const int kq = KC ? (q & 7) : (q >> 6);
+    us4 hr, hi, lr, li;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hr[j] = bf16_rne(v[it][j].x);
+      hi[j] = bf16_rne(v[it][j].y);
+      if (SPLIT) {
+        lr[j] = bf16_rne(v[it][j].x - bf16_val(hr[j]));
+        li[j] = bf16_rne(v[it][j].y - bf16_val(hi[j]));
+      }
+    }
+    const int off = row * BKP2 + 4 * kq;
+    *reinterpret_cast<us4*>(P + off) = hr;
+    *reinterpret_cast<us4*>(P + PL2 + off) = hi;
+    if (SPLIT) {
+      *reinterpret_cast<us4*>(P + 2 * PL2 + off) = lr;
+      *reinterpret_cast<us4*>(P + 3 * PL2 + off) = li;
+    }
+  }
+}
+
+template <int SPLIT, bool TA, bool CA, bool TB, bool CB, int TAG>
+__global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, float ar, float ai,
+                                                        const float* __restrict__ A, long long lda, long long sa,
+                                                        const float* __restrict__ B, long long ldb, long long sb,
+                                                        float br, float bi, float* __restrict__ C, long long ldc,
+                                                        long long sc, int S, int Kc, long long sps) {
+  constexpr int NPL = SPLIT ? 4 : 2;
+  __shared__ __attribute__((aligned(16))) unsigned short As[2][NPL * PL2];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPL * PL2];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const unsigned tot = gx * gy * gz;
+  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned t = (tot % 8u == 0u) ? (lin % 8u) * (tot / 8u) + lin / 8u : lin;
+  const unsigned tz = t / (gx * gy), trem = t % (gx * gy);
+  const int m0 = (int)(trem / gx) * BM, n0 = (int)(trem % gx) * BN;
+  const long long bz = tz / S;
+  const int split = tz % S;
+  const int kb = split * Kc;
+  const int ke = min(K, kb + Kc);
+  const float2* Ab = reinterpret_cast<const float2*>(A) + bz * sa;
+  const float2* Bb = reinterpret_cast<const float2*>(B) + bz * sb;
+  float2* Cb = reinterpret_cast<float2*>(C) + bz * sc + split * sps;
+
+  // A tile rows are m (k contiguous when A is not transposed); B tile rows
+  // are n (k contiguous when B is transposed)
+  float2 va[2][4], vb[2][4];
+  auto load = [&](int k0) {
+    bf_load<!TA, CA>(Ab, lda, m0, M, k0, ke, tid, va);
+    bf_load<TB, CB>(Bb, ldb, n0, N, k0, ke, tid, vb);
+  };
+  auto store = [&](int buf) {
+    bf_store<!TA, SPLIT>(As[buf], tid, va);
+    bf_store<TB, SPLIT>(Bs[buf], tid, vb);
+  };
+
+  f4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f4{0, 0, 0, 0};
+      ci[i][j] = f4{0, 0, 0, 0};
+    }
+
+  const int lr = lane & 15, lk = lane >> 4;
+  load(kb);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kb; k0 < ke; k0 += BK2) {
+    const bool more = (k0 + BK2) < ke;
+    if (more) load(k0 + BK2);
+    const unsigned short* Ap = As[cur];
+    const unsigned short* Bp = Bs[cur];
+    uint4 a_hr[2], a_hi[2], a_lr[2], a_li[2], b_hr[2], b_hi[2], b_hn[2], b_lr[2], b_li[2], b_ln[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int off = (wm * 32 + i * 16 + lr) * BKP2 + 8 * lk;
+      a_hr[i] = *reinterpret_cast<const uint4*>(Ap + off);
+      a_hi[i] = *reinterpret_cast<const uint4*>(Ap + PL2 + off);
+      if (SPLIT) {
+        a_lr[i] = *reinterpret_cast<const uint4*>(Ap + 2 * PL2 + off);
+        a_li[i] = *reinterpret_cast<const uint4*>(Ap + 3 * PL2 + off);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int off = (wn * 32 + j * 16 + lr) * BKP2 + 8 * lk;
+      b_hr[j] = *reinterpret_cast<const uint4*>(Bp + off);
+      b_hi[j] = *reinterpret_cast<const uint4*>(Bp + PL2 + off);
+      b_hn[j] = bf16_neg(b_hi[j]);
+      if (SPLIT) {
+        b_lr[j] = *reinterpret_cast<const uint4*>(Bp + 2 * PL2 + off);
+        b_li[j] = *reinterpret_cast<const uint4*>(Bp + 3 * PL2 + off);
+        b_ln[j] = bf16_neg(b_li[j]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (SPLIT) {
+          cr[i][j] = mfma_bf16(a_hr[i], b_lr[j], cr[i][j]);
+          cr[i][j] = mfma_bf16(a_lr[i], b_hr[j], cr[i][j]);
+          cr[i][j] = mfma_bf16(a_hi[i], b_ln[j], cr[i][j]);
+          cr[i][j] = mfma_bf16(a_li[i], b_hn[j], cr[i][j]);
+          ci[i][j] = mfma_bf16(a_hr[i], b_li[j], ci[i][j]);
+          ci[i][j] = mfma_bf16(a_lr[i], b_hi[j], ci[i][j]);
+          ci[i][j] = mfma_bf16(a_hi[i], b_lr[j], ci[i][j]);
+          ci[i][j] = mfma_bf16(a_li[i], b_hr[j], ci[i][j]);
+        }
+        cr[i][j] = mfma_bf16(a_hr[i], b_hr[j], cr[i][j]);
+        cr[i][j] = mfma_bf16(a_hi[i], b_hn[j], cr[i][j]);
+        ci[i][j] = mfma_bf16(a_hr[i], b_hi[j], ci[i][j]);
+        ci[i][j] = mfma_bf16(a_hi[i], b_hr[j], ci[i][j]);
+      }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  const bool has_beta = (br != 0.f) || (bi != 0.f);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + i * 16 + lk * 4 + r;
+        const int gn = n0 + wn * 32 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          const float xr = cr[i][j][r], xi = ci[i][j][r];
+          float2 o;
+          o.x = ar * xr - ai * xi;
+          o.y = ar * xi + ai * xr;
+          if (has_beta) {
+            const float2 old = Cb[(long long)gm * ldc + gn];
+            o.x += br * old.x - bi * old.y;
+            o.y += br * old.y + bi * old.x;
+          }
+          Cb[(long long)gm * ldc + gn] = o;
+        }
+      }
+}
+
 // Deterministic split-K reduction: C = alpha * sum_s P[s] + beta * C.
 template <typename T>
 __global__ void splitk_reduce_kernel(const T* __restrict__ P, int S, long long M, long long N, T ar, T ai,
@@ -237,30 +446,69 @@ inline int choose_splits(int M, int N, int K, int batch, size_t ws_bytes, size_t
   return std::max(S, 1);
 }
 
-template <typename T, int OA, int OB, int TAG = 0>
-void launch_gemm(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda,
-                 long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
-                 long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0) {
+// Compute mode of the complex64 GEMMs on the calling host thread:
+// 0 FP32 MFMA, 1 BF16 MFMA, 2 three-term BF16 split (see gemm_bf16_kernel).
+thread_local int tl_float_mode = 0;
+
+template <typename T, int MODE, bool TA, bool CA, bool TB, bool CB, int TAG>
+void launch_tiles(dim3 grid, hipStream_t s, int M, int N, int K, T ar, T ai, const T* A, long long lda,
+                  long long sa, const T* B, long long ldb, long long sb, T br, T bi, T* C, long long ldc,
+                  long long sc, int S, int Kc, long long sps) {
+  if constexpr (MODE == 0) {
+    hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, ar, ai, A, lda, sa, B,
+                       ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
+  } else {
+    hipLaunchKernelGGL((gemm_bf16_kernel<MODE - 1, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, ar, ai,
+                       A, lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
+  }
+}
+
+template <typename T, int MODE, int OA, int OB, int TAG>
+void launch_gemm_mode(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda, long long sa,
+                      const void* B, long long ldb, long long sb, zc beta, void* C, long long ldc, long long sc,
+                      int batch, void* ws, size_t ws_bytes) {
   constexpr bool TA = (OA == TDVP_OP_T || OA == TDVP_OP_C), CA = (OA == TDVP_OP_C || OA == TDVP_OP_R);
   constexpr bool TB = (OB == TDVP_OP_T || OB == TDVP_OP_C), CB = (OB == TDVP_OP_C || OB == TDVP_OP_R);
+  constexpr int KSTEP = MODE == 0 ? BK : BK2;
+  const T* a = static_cast<const T*>(A);
+  const T* b = static_cast<const T*>(B);
   const int S = choose_splits(M, N, K, batch, ws_bytes, sizeof(typename VT<T>::c2));
   if (S == 1) {
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
-    hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, T(alpha.real()),
-                       T(alpha.imag()), static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb,
-                       sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc, 1, std::max(K, 1), 0LL);
+    launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(alpha.real()), T(alpha.imag()), a, lda, sa, b,
+                                               ldb, sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc,
+                                               sc, 1, std::max(K, 1), 0LL);
     return;
   }
-  const int Kc = ((K + S - 1) / S + BK - 1) / BK * BK;
+  const int Kc = ((K + S - 1) / S + KSTEP - 1) / KSTEP * KSTEP;
   const int Sx = (K + Kc - 1) / Kc;
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, Sx);
-  hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, T(1), T(0),
-                     static_cast<const T*>(A), lda, sa, static_cast<const T*>(B), ldb, sb, T(0), T(0),
-                     static_cast<T*>(ws), (long long)N, 0LL, Sx, Kc, (long long)M * N);
+  launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(1), T(0), a, lda, sa, b, ldb, sb, T(0), T(0),
+                                             static_cast<T*>(ws), (long long)N, 0LL, Sx, Kc, (long long)M * N);
   const long long MN = (long long)M * N;
   hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s,
                      static_cast<const T*>(ws), Sx, (long long)M, (long long)N, T(alpha.real()), T(alpha.imag()),
                      T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc);
+}
+
+template <typename T, int OA, int OB, int TAG = 0>
+void launch_gemm(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda,
+                 long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
+                 long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0) {
+  if constexpr (sizeof(T) == 4) {
+    if (tl_float_mode == 1) {
+      launch_gemm_mode<T, 1, OA, OB, TAG>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws,
+                                          ws_bytes);
+      return;
+    }
+    if (tl_float_mode == 2) {
+      launch_gemm_mode<T, 2, OA, OB, TAG>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws,
+                                          ws_bytes);
+      return;
+    }
+  }
+  launch_gemm_mode<T, 0, OA, OB, TAG>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws,
+                                      ws_bytes);
 }
 
 template <typename T, int OA>
@@ -507,6 +755,12 @@ inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) /
 }  // namespace
 
 namespace kern {
+
+void set_float_mode(int mode) {
+  if (mode < 0 || mode > 2) TDVP_THROW(TDVP_ERR_ARG, "bad complex64 GEMM mode");
+  tl_float_mode = mode;
+}
+int float_mode() { return tl_float_mode; }
 
 template <typename T>
 void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda,

@@ -21,9 +21,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "tdvp.h")
 
 TDVP_OK, TDVP_ERR_ARG, TDVP_ERR_ALLOC, TDVP_ERR_DEVICE, TDVP_ERR_NOCONV, TDVP_ERR_NUMERIC, TDVP_ERR_STATE = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_ALLOC", "ERR_DEVICE", "ERR_NOCONV", "ERR_NUMERIC", "ERR_STATE"]
-TDVP_FP64, TDVP_FP32 = 0, 1
+TDVP_FP64, TDVP_FP32, TDVP_BF16_FP32ACC, TDVP_BF16X3_FP32ACC = 0, 1, 2, 3
 OP_N, OP_T, OP_C, OP_R = 0, 1, 2, 3
-PREC = {"fp64": TDVP_FP64, "fp32": TDVP_FP32}
+PREC = {"fp64": TDVP_FP64, "fp32": TDVP_FP32, "bf16": TDVP_BF16_FP32ACC, "bf16x3": TDVP_BF16X3_FP32ACC}
 
 
 class TdvpError(RuntimeError):
@@ -368,19 +368,25 @@ def _tp(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _prec_of(t) -> int:
+def _prec_of(t, prec: Optional[str] = None) -> int:
+    """complex128 tensors run in FP64; complex64 tensors in FP32 or, when
+    prec is "bf16" or "bf16x3", with BF16 matrix-core inputs."""
     import torch
     if t.dtype == torch.complex128:
+        if prec not in (None, "fp64"):
+            raise TypeError(f"precision {prec} needs complex64 operands")
         return TDVP_FP64
     if t.dtype == torch.complex64:
-        return TDVP_FP32
+        if prec == "fp64":
+            raise TypeError("precision fp64 needs complex128 operands")
+        return PREC[prec or "fp32"]
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
 def tdvp_gemm(ctx: Context, op_a: int, op_b: int, M: int, N: int, K: int, alpha, A, lda, stride_a, B, ldb, stride_b,
-              beta, Cout, ldc, stride_c, batch: int = 1):
+              beta, Cout, ldc, stride_c, batch: int = 1, prec: Optional[str] = None):
     alpha, beta = complex(alpha), complex(beta)
-    ctx.check(ctx.lib.tdvp_gemm(ctx.h, _prec_of(A), op_a, op_b, M, N, K, alpha.real, alpha.imag, _tp(A), lda,
+    ctx.check(ctx.lib.tdvp_gemm(ctx.h, _prec_of(A, prec), op_a, op_b, M, N, K, alpha.real, alpha.imag, _tp(A), lda,
                                 stride_a, _tp(B), ldb, stride_b, beta.real, beta.imag, _tp(Cout), ldc, stride_c,
                                 batch), "tdvp_gemm")
 
@@ -390,34 +396,34 @@ def _w_host(W: np.ndarray):
     return Wc, Wc.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
 
 
-def tdvp_heff_apply(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, workspace=None):
+def tdvp_heff_apply(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, workspace=None, prec: Optional[str] = None):
     ml, wl, _ = L.shape
     wr, mr, _ = Rt.shape
     Wc, wp = _w_host(W)
-    ctx.check(ctx.lib.tdvp_heff_apply(ctx.h, _prec_of(L), ml, wl, wr, mr, wp, _tp(L), _tp(Rt), _tp(Cin), _tp(Y),
+    ctx.check(ctx.lib.tdvp_heff_apply(ctx.h, _prec_of(L, prec), ml, wl, wr, mr, wp, _tp(L), _tp(Rt), _tp(Cin), _tp(Y),
                                       _tp(workspace)), "tdvp_heff_apply")
 
 
-def tdvp_keff_apply(ctx: Context, L, Rt, X, Y, workspace=None):
+def tdvp_keff_apply(ctx: Context, L, Rt, X, Y, workspace=None, prec: Optional[str] = None):
     ml, w, _ = L.shape
     _, mr, _ = Rt.shape
-    ctx.check(ctx.lib.tdvp_keff_apply(ctx.h, _prec_of(L), ml, w, mr, _tp(L), _tp(Rt), _tp(X), _tp(Y),
+    ctx.check(ctx.lib.tdvp_keff_apply(ctx.h, _prec_of(L, prec), ml, w, mr, _tp(L), _tp(Rt), _tp(X), _tp(Y),
                                       _tp(workspace)), "tdvp_keff_apply")
 
 
-def tdvp_env_left(ctx: Context, W: np.ndarray, L, A, Lout, workspace=None):
+def tdvp_env_left(ctx: Context, W: np.ndarray, L, A, Lout, workspace=None, prec: Optional[str] = None):
     ml, wl, _ = L.shape
     mr = A.shape[2]
     wr = W.shape[1]
     Wc, wp = _w_host(W)
-    ctx.check(ctx.lib.tdvp_env_left(ctx.h, _prec_of(L), ml, wl, wr, mr, wp, _tp(L), _tp(A), _tp(Lout),
+    ctx.check(ctx.lib.tdvp_env_left(ctx.h, _prec_of(L, prec), ml, wl, wr, mr, wp, _tp(L), _tp(A), _tp(Lout),
                                     _tp(workspace)), "tdvp_env_left")
 
 
-def tdvp_env_right(ctx: Context, W: np.ndarray, Rt, B, Rout, workspace=None):
+def tdvp_env_right(ctx: Context, W: np.ndarray, Rt, B, Rout, workspace=None, prec: Optional[str] = None):
     wr, mr, _ = Rt.shape
     ml = B.shape[0]
     wl = W.shape[0]
     Wc, wp = _w_host(W)
-    ctx.check(ctx.lib.tdvp_env_right(ctx.h, _prec_of(Rt), ml, wl, wr, mr, wp, _tp(Rt), _tp(B), _tp(Rout),
+    ctx.check(ctx.lib.tdvp_env_right(ctx.h, _prec_of(Rt, prec), ml, wl, wr, mr, wp, _tp(Rt), _tp(B), _tp(Rout),
                                      _tp(workspace)), "tdvp_env_right")

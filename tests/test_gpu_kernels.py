@@ -131,3 +131,142 @@ def test_env_updates_match_oracle(env, prec, ml, wl, wr, mr):
     refR = O.right_env_update(R, A, W).transpose(1, 2, 0)
     assert np.abs(_host(dLo) - refL).max() / np.abs(refL).max() < TOL[prec]
     assert np.abs(_host(dRo) - refR).max() / np.abs(refR).max() < TOL[prec]
+
+
+# ------------------------------------------------------------ BF16 inputs
+# Bounds from the arithmetic.  An FP32 operand x enters the matrix cores as
+# bf16(x) = x(1 + d), |d| <= u = 2^-8 (8 significant bits, nearest even), so
+# one real product carries (2u + u^2)|a||b|.  The three-term split x = hi + lo
+# represents x to 2^-16|x| and drops lo_a lo_b <= 2^-16|a||b|, so a product
+# carries <= 3.1 * 2^-16 |a||b|.  FP32 accumulation adds at most one rounding
+# (2^-24) of the running sum per accumulated product.  With S = |A| |B| in the
+# magnitude norm |z| = |Re z| + |Im z| this gives |C - AB| <= (c + n_acc 2^-24) S.
+BF_C = {"bf16": 2.0 ** -7 + 2.0 ** -16, "bf16x3": 3.1 * 2.0 ** -16}
+BF_PRODUCTS = {"bf16": 2, "bf16x3": 6}     # real products per output part per k
+
+
+def _mag(a):
+    return np.abs(a.real) + np.abs(a.imag)
+
+
+def _c64(a):
+    return np.asarray(a).astype(np.complex64).astype(np.complex128)
+
+
+def _bf_bound(prec, K, S):
+    return (BF_C[prec] + (BF_PRODUCTS[prec] * K + 64) * 2.0 ** -24) * S
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("opa", [0, 1, 2, 3])
+@pytest.mark.parametrize("opb", [0, 1, 2, 3])
+def test_gemm_bf16_all_ops_ragged_batched(env, prec, opa, opb):
+    T, torch, ctx = env
+    M, N, K, batch = 77, 45, 131, 3
+    rng = np.random.default_rng(300 + 4 * opa + opb)
+    ashape = (M, K) if opa in (0, 3) else (K, M)
+    bshape = (K, N) if opb in (0, 3) else (N, K)
+    A = _c64(rng.standard_normal((batch,) + ashape) + 1j * rng.standard_normal((batch,) + ashape))
+    B = _c64(rng.standard_normal((batch,) + bshape) + 1j * rng.standard_normal((batch,) + bshape))
+    C0 = _c64(rng.standard_normal((batch, M, N)) + 1j * rng.standard_normal((batch, M, N)))
+    alpha, beta = 0.7 - 0.3j, -0.4 + 0.2j
+    dA, dB, dC = _dev(torch, A, "fp32"), _dev(torch, B, "fp32"), _dev(torch, C0, "fp32")
+    T.tdvp_gemm(ctx, opa, opb, M, N, K, alpha, dA, ashape[1], ashape[0] * ashape[1], dB, bshape[1],
+                bshape[0] * bshape[1], beta, dC, N, M * N, batch, prec=prec)
+    torch.cuda.synchronize()
+    ref = np.stack([alpha * _op(A[b], opa) @ _op(B[b], opb) + beta * C0[b] for b in range(batch)])
+    S = np.stack([abs(alpha) * (_mag(_op(A[b], opa)) @ _mag(_op(B[b], opb))) for b in range(batch)])
+    err = np.abs(_host(dC) - ref)
+    bound = _bf_bound(prec, K, S) + 2.0 ** -22 * (np.abs(ref) + abs(beta) * np.abs(C0))
+    assert (err <= bound).all(), (err / bound).max()
+    # the split keeps about 16 bits: its typical error is far below plain BF16's
+    rel = np.sqrt((err ** 2).mean() / (np.abs(ref) ** 2).mean())
+    assert rel < (2.0 ** -7 if prec == "bf16" else 2.0 ** -13), rel
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (1, 300, 7), (256, 256, 256), (513, 130, 65), (64, 64, 4096)])
+def test_gemm_bf16_shapes(env, prec, M, N, K):
+    T, torch, ctx = env
+    rng = np.random.default_rng(M + N + K + 1)
+    A = _c64(rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K)))
+    B = _c64(rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N)))
+    dA, dB = _dev(torch, A, "fp32"), _dev(torch, B, "fp32")
+    dC = _dev(torch, np.zeros((M, N)), "fp32")
+    T.tdvp_gemm(ctx, 0, 0, M, N, K, 1.0, dA, K, 0, dB, N, 0, 0.0, dC, N, 0, 1, prec=prec)
+    torch.cuda.synchronize()
+    ref = A @ B
+    err = np.abs(_host(dC) - ref)
+    bound = _bf_bound(prec, K, _mag(A) @ _mag(B)) + 2.0 ** -22 * np.abs(ref)
+    assert (err <= bound).all(), (err / bound).max()
+
+
+def _abs_c(a):
+    return _mag(a).astype(np.complex128)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("ml,wl,wr,mr", SIZES)
+def test_heff_bf16_within_bound(env, prec, ml, wl, wr, mr):
+    # two BF16 GEMM stages around the FP32 sparse-W stage: the first stage's
+    # error passes through W and the second GEMM, so |Y - HC| <= 2 (c + acc) S_H
+    # with S_H the magnitude-propagated product |L| |W| |C| |R|
+    from oracle import tdvp as O
+    T, torch, ctx = env
+    L, W, R, C = _heff_inputs(ml, wl, wr, mr, 7 * ml + mr)
+    L, R, C = _c64(L), _c64(R), _c64(C)
+    Rt = np.ascontiguousarray(R.transpose(1, 2, 0))
+    dL, dRt, dC = _dev(torch, L, "fp32"), _dev(torch, Rt, "fp32"), _dev(torch, C, "fp32")
+    dY = _dev(torch, np.zeros_like(C), "fp32")
+    T.tdvp_heff_apply(ctx, W, dL, dRt, dC, dY, prec=prec)
+    torch.cuda.synchronize()
+    ref = O.heff_apply(L, W, R, C)
+    S = O.heff_apply(_abs_c(L), _abs_c(W), _abs_c(R), _abs_c(C)).real
+    err = np.abs(_host(dY) - ref)
+    Kmax = max(ml, wr * mr)
+    bound = 2 * _bf_bound(prec, Kmax, S) + 2.0 ** -20 * S
+    assert (err <= bound).all(), (err / bound).max()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("ml,w,mr", [(1, 5, 3), (33, 8, 47), (128, 8, 128)])
+def test_keff_bf16_within_bound(env, prec, ml, w, mr):
+    from oracle import tdvp as O
+    T, torch, ctx = env
+    L = _c64(I.random_hermitian_env(ml, w, 3 * ml))
+    R = _c64(I.random_hermitian_env(mr, w, 5 * mr))
+    X = _c64(I.random_complex((ml, mr), ml + mr))
+    dL, dRt = _dev(torch, L, "fp32"), _dev(torch, np.ascontiguousarray(R.transpose(1, 2, 0)), "fp32")
+    dX, dY = _dev(torch, X, "fp32"), _dev(torch, np.zeros_like(X), "fp32")
+    T.tdvp_keff_apply(ctx, dL, dRt, dX, dY, prec=prec)
+    torch.cuda.synchronize()
+    ref = O.keff_apply(L, R, X)
+    S = O.keff_apply(_abs_c(L), _abs_c(R), _abs_c(X)).real
+    err = np.abs(_host(dY) - ref)
+    bound = 2 * _bf_bound(prec, max(ml, w * mr), S) + 2.0 ** -20 * S
+    assert (err <= bound).all(), (err / bound).max()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("ml,wl,wr,mr", SIZES)
+def test_env_updates_bf16_within_bound(env, prec, ml, wl, wr, mr):
+    from oracle import tdvp as O
+    T, torch, ctx = env
+    L, W, R, A = _heff_inputs(ml, wl, wr, mr, 11 * ml + mr)
+    L, R, A = _c64(L), _c64(R), _c64(A)
+    dL, dA = _dev(torch, L, "fp32"), _dev(torch, A, "fp32")
+    dLo = _dev(torch, np.zeros((mr, wr, mr)), "fp32")
+    T.tdvp_env_left(ctx, W, dL, dA, dLo, prec=prec)
+    dRt = _dev(torch, np.ascontiguousarray(R.transpose(1, 2, 0)), "fp32")
+    dRo = _dev(torch, np.zeros((wl, ml, ml)), "fp32")
+    T.tdvp_env_right(ctx, W, dRt, dA, dRo, prec=prec)
+    torch.cuda.synchronize()
+    refL = O.left_env_update(L, A, W)
+    refR = O.right_env_update(R, A, W).transpose(1, 2, 0)
+    SL = O.left_env_update(_abs_c(L), _abs_c(A), _abs_c(W)).real
+    SR = O.right_env_update(_abs_c(R), _abs_c(A), _abs_c(W)).transpose(1, 2, 0).real
+    Kmax = max(2 * ml, 2 * mr, wl * ml, wr * mr)
+    for got, ref, S in ((_host(dLo), refL, SL), (_host(dRo), refR, SR)):
+        err = np.abs(got - ref)
+        bound = 2 * _bf_bound(prec, Kmax, S) + 2.0 ** -20 * S
+        assert (err <= bound).all(), (err / bound).max()
