@@ -461,6 +461,20 @@ tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, 
 }
 
 
+tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows, double* lam) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && H && rows && lam, "bad arguments");
+    ARG_CHECK(method >= la::EIGH_AUTO && method <= la::EIGH_HEEVD, "unknown method");
+    bind(ctx);
+    DBuf work(ctx);
+    std::vector<double> w;
+    la::eigh_rows_desc(ctx, H, n, w, rows, work, method);
+    std::copy(w.begin(), w.end(), lam);
+    ctx->sync();
+  });
+}
+
 tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
                             const void* L, const void* Rt, const void* C, void* Y, void* workspace) {
   if (!W_host) return TDVP_ERR_ARG;

@@ -104,6 +104,16 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
 template <typename T>
 void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
                void* C, long long ldc, void* ws = nullptr, size_t ws_bytes = 0);
+// Householder tridiagonalisation of a Hermitian n x n complex128 matrix
+// (row-major, full storage; n <= 512) in one cooperative launch:
+// H = Q T Q^H with T real tridiagonal (diagonal D[n], off-diagonal E[n-1]) and
+// Q (row-major) unitary.  scratch holds tridiag_scratch_bytes(n); *err is set
+// nonzero when a grid barrier wait ran out.  Returns the launch status.
+int tridiag_groups(int n);
+size_t tridiag_scratch_bytes(int n);
+hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err);
+// out[j][m] = Z[m][n-1-j] (complex), Z column-major real n x n
+void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n);
 // Arithmetic of the complex64 GEMMs issued from the calling host thread:
 // 0 FP32 MFMA; 1 BF16 inputs (rounded to nearest even), FP32 accumulation;
 // 2 BF16 three-term split x = hi + lo with FP32 accumulation.
@@ -187,13 +197,26 @@ void qr_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, vo
 // C[rows x cols] = L Q with Q (k x cols) orthonormal rows, L (rows x k).
 void lq_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* Q, DBuf& work,
                  DBuf& tau);
+// ||X^H X - I||_F^2 for orthonormal columns (orth_rows = false) or
+// ||X X^H - I||_F^2 for orthonormal rows; synchronises; +inf for non-finite.
+double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth_rows, DBuf& work);
+// C (rows >= cols) = A R by two Cholesky-QR passes, A orthonormal columns,
+// R = A^dagger C (cols x cols, not triangular); false (A, R undefined) when
+// the Gram matrix is numerically singular or A fails the orthonormality check.
+bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work);
+// C (rows <= cols) = L B with B orthonormal rows, L = C B^dagger (rows x rows).
+bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work);
 // thin SVD of row-major C (rows x cols): U (rows x k), S (k, host), Vh (k x cols); k = min.
 void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
                   void* Vh, DBuf& work, DBuf& work2);
 // eigh of row-major Hermitian H (n x n): eigenvalues descending (host) and the
-// matrix of eigenvectors-as-rows-conjugated: rows[j] = v_j^dagger (row-major n x n)
+// matrix of eigenvectors-as-rows-conjugated: rows[j] = v_j^dagger (row-major n x n).
+// method: EIGH_AUTO (cooperative tridiagonalisation for 128 <= n <= 512,
+// rocSOLVER divide and conquer otherwise or when the first fails validation),
+// EIGH_TRIDIAG (the first only), EIGH_HEEVD (rocSOLVER only).
+enum { EIGH_AUTO = 0, EIGH_TRIDIAG = 1, EIGH_HEEVD = 2 };
 void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows,
-                    DBuf& work);
+                    DBuf& work, int method = EIGH_AUTO);
 // host: eigen-decomposition of a small real symmetric matrix (Jacobi), ascending
 void jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V);
 }  // namespace la

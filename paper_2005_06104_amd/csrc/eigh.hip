@@ -1,0 +1,359 @@
+// Hermitian eigendecomposition for the mid-size Gram and density matrices of
+// the method (n <= 512): Householder reduction to real tridiagonal form by one
+// cooperative launch, tridiagonal divide and conquer (rocSOLVER), and one
+// MFMA GEMM for the back transformation.
+//
+// The reduction is the unblocked Householder algorithm (Golub & Van Loan,
+// Matrix Computations, Sec. 8.3.1; the LAPACK xHETD2 scheme with lower
+// storage): for k = 0..n-2 the reflector H_k = I - tau v v^H with v_{k+1} = 1
+// maps A[k+1:, k] to (beta, 0, ..., 0) with beta real, and the trailing block
+// becomes H_k^H A H_k = A - v w^H - w v^H with x = tau A v,
+// w = x - (tau/2)(x^H v) v.  Q = H_0 H_1 ... H_{n-2} is accumulated row by row.
+//
+// A library call per column costs a few microseconds of dispatch on this GPU,
+// so the whole reduction is one launch: G workgroups keep the matrix rows
+// (row r on workgroup r % G) and the matching rows of Q in LDS and meet at
+// one grid barrier per column (one flag per workgroup, no shared counter).
+// Every barrier wait is bounded; a wait that runs out raises an error flag
+// that makes every workgroup leave, and the caller then uses another solver.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace {
+
+constexpr int TNT = 256;            // threads per workgroup
+constexpr int TD_LDS = 8192;        // complex128 slots for the A and Q rows (128 KiB)
+constexpr int TD_NMAX = 512;
+constexpr int TD_ROWS = 128;        // rows per workgroup at most
+constexpr int FLAG_STRIDE = 16;     // one 64-byte line per workgroup flag
+constexpr unsigned SPIN_LIMIT = 1u << 22;
+
+struct TdArgs {
+  const double2* H;   // n x n Hermitian, row-major
+  double2* Q;         // n x n out, row-major
+  double* D;          // n out
+  double* E;          // n-1 out
+  double2* xv;        // 2n scratch: published x = tau A v (two buffers)
+  double2* prow;      // 2n scratch: published pivot row (two buffers)
+  double2* p2;        // 2G scratch: partial x^H v (two buffers)
+  unsigned* flags;    // G * FLAG_STRIDE, zero at launch
+  int* err;           // 0 at launch; 1 when a barrier wait ran out
+  int n, G, R;
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+  return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+__device__ inline double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+
+// grid barrier, split into arrive and wait
+__device__ inline void bar_arrive(const TdArgs& a, unsigned epoch) {
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&a.flags[blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool bar_wait(const TdArgs& a, unsigned epoch, int* s_fail) {
+  if (threadIdx.x < 64) {
+    unsigned polls = 0;
+    bool fail = false;
+    while (true) {
+      bool mine = true;
+      for (int j = threadIdx.x; j < a.G; j += 64)
+        mine = mine && (__hip_atomic_load(&a.flags[j * FLAG_STRIDE], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= epoch);
+      if (__all(mine)) break;
+      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++polls > SPIN_LIMIT) {
+        fail = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (threadIdx.x == 0) {
+      if (fail) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      *s_fail = fail ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  return *s_fail == 0;
+}
+
+// One grid barrier per column.  Every workgroup holds the current pivot row k
+// (row k of the partly reduced matrix; column k below the diagonal is its
+// conjugate) and derives the reflector H_k from it with the same arithmetic,
+// so all workgroups agree bit for bit.  The barrier gathers x = tau A v from
+// the row owners; the owner of row k+1 also publishes that row, from which
+// every workgroup forms the next pivot row by the rank-2 update.  Published
+// buffers alternate between two copies: a workgroup can be one barrier ahead
+// of the slowest one.
+__global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
+  __shared__ double2 sM[TD_LDS];        // A rows [R][n], then Q rows [R][n]
+  __shared__ double2 sv[TD_NMAX], sw[TD_NMAX], srow[TD_NMAX];
+  __shared__ double2 sred[TNT / 64];
+  __shared__ double2 s_part[TD_ROWS];
+  __shared__ double s_tau_r, s_tau_i, s_sc_r, s_sc_i, s_a2_r, s_a2_i;
+  __shared__ int s_fail;
+
+  const int n = a.n, G = a.G, R = a.R, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double2* sA = sM;
+  double2* sQ = sM + (size_t)R * n;
+  const int nrow = (n - g + G - 1) / G;   // rows r = g + j G < n
+  // T threads per own row (a power of two, within one wave): thread tid works
+  // on local row rj = tid / T, columns rt, rt + T, ...
+  int T = 64;
+  while (T > 1 && T * R > TNT) T >>= 1;
+  const int rj = tid / T, rt = tid % T;
+
+  // own rows, Q = I, pivot row 0
+  for (int j = 0; j < nrow; ++j) {
+    const int r = g + j * G;
+    for (int c = tid; c < n; c += TNT) {
+      sA[j * n + c] = a.H[(size_t)r * n + c];
+      sQ[j * n + c] = double2{r == c ? 1.0 : 0.0, 0.0};
+    }
+  }
+  for (int c = tid; c < n; c += TNT) srow[c] = a.H[c];
+  __syncthreads();
+
+  unsigned epoch = 0;
+  bool alive = true;
+  for (int k = 0; k + 1 < n; ++k) {
+    const int par = k & 1;
+    // ---- reflector from the pivot row: alpha = conj(row[k+1]), x = conj(row[k+2:])
+    double ssq = 0.0;
+    for (int c = k + 2 + tid; c < n; c += TNT) ssq += srow[c].x * srow[c].x + srow[c].y * srow[c].y;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o);
+    if (lane == 0) sred[wave].x = ssq;
+    __syncthreads();
+    if (tid == 0) {
+      double xn2 = 0.0;
+      for (int w = 0; w < TNT / 64; ++w) xn2 += sred[w].x;
+      const double2 al{srow[k + 1].x, -srow[k + 1].y};
+      double beta;
+      if (xn2 == 0.0 && al.y == 0.0) {
+        // already reduced: H_k = I (tau = 0 makes every update below vanish)
+        beta = al.x;
+        s_tau_r = s_tau_i = s_sc_r = s_sc_i = 0.0;
+      } else {
+        const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+        beta = al.x >= 0.0 ? -nrm : nrm;
+        s_tau_r = (beta - al.x) / beta;
+        s_tau_i = -al.y / beta;
+        const double dr = al.x - beta, di = al.y;   // scale = 1 / (alpha - beta)
+        const double den = dr * dr + di * di;
+        s_sc_r = dr / den;
+        s_sc_i = -di / den;
+      }
+      if (g == 0) {
+        a.D[k] = srow[k].x;
+        a.E[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double2 tau{s_tau_r, s_tau_i}, sc{s_sc_r, s_sc_i};
+    for (int c = k + 1 + tid; c < n; c += TNT)
+      sv[c] = (c == k + 1) ? double2{1.0, 0.0} : cmul(double2{srow[c].x, -srow[c].y}, sc);
+    __syncthreads();
+
+    // ---- one pass over the own rows (T threads per row): x = tau A v for
+    // rows >= k+1 and tau (Q v) for the accumulation of Q; partial x^H v.
+    // The owner of row k+1 publishes it (before this column's update).
+    double2* xvp = a.xv + (size_t)par * n;
+    double2* rowp = a.prow + (size_t)par * n;
+    double2* p2p = a.p2 + (size_t)par * G;
+    double2 tqs{0.0, 0.0};
+    if (rj < nrow) {
+      double2 sa{0.0, 0.0}, sq{0.0, 0.0};
+      const double2* arow = sA + rj * n;
+      const double2* qrow = sQ + rj * n;
+      for (int c = k + 1 + rt; c < n; c += T) {
+        const double2 v = sv[c], m = arow[c], q = qrow[c];
+        sa.x += m.x * v.x - m.y * v.y;
+        sa.y += m.x * v.y + m.y * v.x;
+        sq.x += q.x * v.x - q.y * v.y;
+        sq.y += q.x * v.y + q.y * v.x;
+      }
+      for (int o = T >> 1; o > 0; o >>= 1) {
+        sa.x += __shfl_xor(sa.x, o);
+        sa.y += __shfl_xor(sa.y, o);
+        sq.x += __shfl_xor(sq.x, o);
+        sq.y += __shfl_xor(sq.y, o);
+      }
+      tqs = cmul(tau, sq);
+      const int r = g + rj * G;
+      if (rt == 0) {
+        double2 contrib{0.0, 0.0};
+        if (r >= k + 1) {
+          const double2 x = cmul(tau, sa), vr = sv[r];
+          xvp[r] = x;
+          contrib = double2{x.x * vr.x + x.y * vr.y, x.x * vr.y - x.y * vr.x};   // conj(x) v
+        }
+        s_part[rj] = contrib;
+      }
+    }
+    if ((k + 1) % G == g) {
+      const int j = (k + 1) / G;
+      for (int c = k + 1 + tid; c < n; c += TNT) rowp[c] = sA[j * n + c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double2 t{0.0, 0.0};
+      for (int j = 0; j < nrow; ++j) {
+        t.x += s_part[j].x;
+        t.y += s_part[j].y;
+      }
+      p2p[g] = t;
+    }
+    bar_arrive(a, ++epoch);
+
+    // ---- while the others arrive: Q <- Q H_k = Q - tau (Q v) v^H on the own rows
+    if (rj < nrow) {
+      double2* qrow = sQ + rj * n;
+      for (int c = k + 1 + rt; c < n; c += T) {
+        const double2 d = cmulc(tqs, sv[c]);
+        qrow[c].x -= d.x;
+        qrow[c].y -= d.y;
+      }
+    }
+    if (!bar_wait(a, epoch, &s_fail)) {
+      alive = false;
+      break;
+    }
+
+    // ---- w = x - (tau/2)(x^H v) v; next pivot row; A <- A - v w^H - w v^H
+    {
+      double2 xq[(TD_NMAX + TNT - 1) / TNT], rq[(TD_NMAX + TNT - 1) / TNT];
+#pragma unroll
+      for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
+        const int c = k + 1 + tid + q * TNT;
+        xq[q] = c < n ? xvp[c] : double2{0.0, 0.0};
+        rq[q] = c < n ? rowp[c] : double2{0.0, 0.0};
+      }
+      if (wave == 0) {
+        double2 t = lane < G ? p2p[lane] : double2{0.0, 0.0};
+        t = wave_sum(t);
+        if (lane == 0) {
+          const double2 a2 = cmul(tau, t);
+          s_a2_r = -0.5 * a2.x;
+          s_a2_i = -0.5 * a2.y;
+        }
+      }
+      __syncthreads();
+      const double2 a2{s_a2_r, s_a2_i};
+#pragma unroll
+      for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
+        const int c = k + 1 + tid + q * TNT;
+        if (c < n) {
+          const double2 t = cmul(a2, sv[c]);
+          sw[c] = double2{xq[q].x + t.x, xq[q].y + t.y};
+        }
+      }
+      __syncthreads();
+      const double2 v1 = sv[k + 1], w1 = sw[k + 1];
+#pragma unroll
+      for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
+        const int c = k + 1 + tid + q * TNT;
+        if (c < n) {
+          const double2 d1 = cmulc(v1, sw[c]), d2 = cmulc(w1, sv[c]);
+          srow[c] = double2{rq[q].x - (d1.x + d2.x), rq[q].y - (d1.y + d2.y)};
+        }
+      }
+    }
+    if (rj < nrow && g + rj * G >= k + 2) {   // rows <= k+1 are finished
+      const int r = g + rj * G;
+      const double2 vr = sv[r], wr = sw[r];
+      double2* arow = sA + rj * n;
+      for (int c = k + 1 + rt; c < n; c += T) {
+        const double2 d1 = cmulc(vr, sw[c]), d2 = cmulc(wr, sv[c]);
+        arow[c].x -= d1.x + d2.x;
+        arow[c].y -= d1.y + d2.y;
+      }
+    }
+    __syncthreads();
+  }
+
+  if (alive) {
+    if (g == 0 && tid == 0) a.D[n - 1] = srow[n - 1].x;
+    for (int j = 0; j < nrow; ++j) {
+      const int r = g + j * G;
+      for (int c = tid; c < n; c += TNT) a.Q[(size_t)r * n + c] = sQ[j * n + c];
+    }
+  }
+}
+
+// rows[j][m] = Z[m][n-1-j] as complex, Z column-major real (eigenvector j'
+// contiguous): the eigenvectors of the tridiagonal matrix in descending order
+__global__ void zrows_from_real_kernel(double2* __restrict__ out, const double* __restrict__ Z, int n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  const int j = (int)(idx / n), m = (int)(idx % n);
+  out[idx] = double2{Z[(size_t)(n - 1 - j) * n + m], 0.0};
+}
+
+__global__ void u32_fill_kernel(unsigned* p, unsigned v, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+namespace kern {
+
+int tridiag_groups(int n) {
+  if (n < 1 || n > TD_NMAX) return 0;
+  // smallest G with 2 ceil(n/G) n <= TD_LDS complex slots (A and Q rows) and
+  // ceil(n/G) within the row-sum slots
+  // (the partial sums are combined by one wave: G <= 64)
+  for (int G = 1; G <= 64; ++G) {
+    const int R = (n + G - 1) / G;
+    if (2 * R * n <= TD_LDS && R <= TD_ROWS) return G;
+  }
+  return 0;
+}
+
+size_t tridiag_scratch_bytes(int n) {
+  const int G = tridiag_groups(n);
+  return sizeof(double2) * (4 * (size_t)n + 2 * (size_t)G) + sizeof(unsigned) * (size_t)G * FLAG_STRIDE + 256;
+}
+
+hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err) {
+  const int G = tridiag_groups(n);
+  if (G == 0) return hipErrorInvalidValue;
+  char* p = static_cast<char*>(scratch);
+  TdArgs a{};
+  a.H = static_cast<const double2*>(H);
+  a.Q = static_cast<double2*>(Q);
+  a.D = D;
+  a.E = E;
+  a.xv = reinterpret_cast<double2*>(p);     // two buffers of n each
+  a.prow = a.xv + 2 * (size_t)n;
+  a.p2 = a.prow + 2 * (size_t)n;            // two buffers of G
+  a.flags = reinterpret_cast<unsigned*>(a.p2 + 2 * (size_t)G);
+  a.err = err;
+  a.n = n;
+  a.G = G;
+  a.R = (n + G - 1) / G;
+  const int nf = G * FLAG_STRIDE;
+  hipLaunchKernelGGL(u32_fill_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.flags, 0u, nf);
+  hipLaunchKernelGGL(u32_fill_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(err), 0u, 1);
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_kernel), dim3(G), dim3(TNT), args, 0, s);
+}
+
+void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n) {
+  const long long nn = (long long)n * n;
+  hipLaunchKernelGGL(zrows_from_real_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                     static_cast<double2*>(out), Z, n);
+}
+
+}  // namespace kern

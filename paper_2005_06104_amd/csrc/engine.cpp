@@ -418,7 +418,8 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   if (eps == 0.0) {
     A.ensure((size_t)rows * kk * ZB);
     R.ensure((size_t)kk * cols * ZB);
-    la::qr_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tau);
+    if (!la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work))
+      la::qr_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tau);
     return kk;
   }
   // G = C^dagger C (cols x cols); rows of V^dagger from its eigendecomposition
@@ -436,12 +437,17 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, W.tmpB.p, cols, 0, 0.0, W.tmpC.p, n, 0, 1);
   A.ensure((size_t)rows * n * ZB);
   R.ensure((size_t)n * cols * ZB);
+  // (Newton-Schulz converges while the starting deviation is below ~1/2; for
+  // small kept weights five steps and a check, with a QR when the check fails)
+  kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
   if (lam[n - 1] > 1e-8 * lam[0]) {
-    kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
     ns_cols(W, A.p, rows, n, 3);
   } else {
-    W.tmpA.ensure((size_t)n * n * ZB);
-    la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+    ns_cols(W, A.p, rows, n, 5);
+    if (!(la::orth_defect(ctx, A.p, rows, n, false, W.work) <= 1e-20)) {
+      W.tmpA.ensure((size_t)n * n * ZB);
+      la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+    }
   }
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, 0, C, cols, 0, 0.0, R.p, cols, 0, 1);
   return n;
@@ -455,7 +461,8 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   if (eps == 0.0) {
     L.ensure((size_t)rows * kk * ZB);
     B.ensure((size_t)kk * cols * ZB);
-    la::lq_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tau);
+    if (!la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work))
+      la::lq_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tau);
     return kk;
   }
   // G = C C^dagger (rows x rows); rows of U^dagger from its eigendecomposition
@@ -471,12 +478,15 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, 0, C, cols, 0, 0.0, W.tmpC.p, cols, 0, 1);
   L.ensure((size_t)rows * n * ZB);
   B.ensure((size_t)n * cols * ZB);
+  kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
   if (lam[n - 1] > 1e-8 * lam[0]) {
-    kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
     ns_rows(W, B.p, n, cols, 3);
   } else {
-    W.tmpA.ensure((size_t)n * n * ZB);
-    la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+    ns_rows(W, B.p, n, cols, 5);
+    if (!(la::orth_defect(ctx, B.p, n, cols, true, W.work) <= 1e-20)) {
+      W.tmpA.ensure((size_t)n * n * ZB);
+      la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+    }
   }
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, B.p, cols, 0, 0.0, L.p, n, 0, 1);
   return n;

@@ -9,6 +9,7 @@
 //            reading of the V'^H buffer is conj(V'), of the U' buffer U'^T.
 //   eigh of Hermitian M: X = conj(M); its eigenvectors are conj(v_j), stored
 //            as columns, so row j of the row-major reading is v_j^dagger.
+#include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -61,6 +62,103 @@ void lq_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, vo
   kern::copy2d(ctx->stream, Q, cols, X, cols, k, cols, 16);
 }
 
+double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth_rows, DBuf& work) {
+  // ||X^H X - I||_F^2 (orthonormal columns) or ||X X^H - I||_F^2 (rows)
+  const int n = orth_rows ? rows : cols;
+  const size_t nn = (size_t)n * n;
+  const int nb = kern::zdots_blocks((long long)nn);
+  rz* G = static_cast<rz*>(work.ensure(sizeof(rz) * (nn + (size_t)nb + 2)));
+  rz* dpart = G + nn;
+  rz* dsum = dpart + nb;
+  hipStream_t s = ctx->stream;
+  if (orth_rows)
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, X, cols, 0, X, cols, 0, 0.0, G, n, 0, 1);
+  else
+    kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, cols, 0, X, cols, 0, 0.0, G, n, 0, 1);
+  kern::zshift_diag(s, G, n, 1.0, -1.0);
+  kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
+  zc dev;
+  HIP_CHECK(hipMemcpyAsync(&dev, dsum, sizeof(rz), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return std::isfinite(dev.real()) ? dev.real() : HUGE_VAL;
+}
+
+// Two passes of Cholesky QR (CholeskyQR2: Yamamoto, Nakatsukasa, Yanagisawa
+// and Fukaya, 2015): X <- X R^-1 with X^H X = R^H R, twice; the second pass
+// restores orthonormality to rounding when cond(C) < ~1e7.  A row-major
+// n x n Gram matrix read column-major is its conjugate M; potrf gives
+// M = U^H U, so R = conj(U) and the row-major solve X R = Y is, column-major,
+// U^H X^T = Y^T.  The result is accepted when both factorisations succeed and
+// ||A^H A - I||_F <= 1e-10; the caller then factors by Householder QR.
+bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work) {
+  if (cols < 1 || rows < cols) return false;
+  const int n = cols;
+  const size_t nn = (size_t)n * n;
+  const int nb = kern::zdots_blocks((long long)nn);
+  char* base = static_cast<char*>(work.ensure(sizeof(rz) * (nn + (size_t)nb + 2) + 64));
+  rz* G = reinterpret_cast<rz*>(base);
+  rz* dpart = G + nn;
+  rz* dsum = dpart + nb;
+  int* dinfo = reinterpret_cast<int*>(dsum + 1);
+  hipStream_t s = ctx->stream;
+  HIP_CHECK(hipMemcpyAsync(A, C, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+  const rz one{1.0, 0.0};
+  for (int pass = 0; pass < 2; ++pass) {
+    kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, G, n, 0, 1);
+    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_upper, n, G, n, dinfo + pass), "zpotrf");
+    blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                             rocblas_diagonal_non_unit, n, rows, &one, G, n, static_cast<rz*>(A), n),
+               "ztrsm");
+  }
+  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, G, n, 0, 1);
+  kern::zshift_diag(s, G, n, 1.0, -1.0);
+  kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
+  int info[2];
+  zc dev;
+  HIP_CHECK(hipMemcpyAsync(info, dinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&dev, dsum, sizeof(rz), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (info[0] != 0 || info[1] != 0 || !(dev.real() <= 1e-20)) return false;
+  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, C, n, 0, 0.0, R, n, 0, 1);
+  return true;
+}
+
+// The same for orthonormal rows (rows <= cols): C = L B, C C^H = L L^H; the
+// row-major Gram read column-major is M = Lc Lc^H with L = conj(Lc), and
+// B = L^-1 C is, column-major, B^T Lc^H = C^T.
+bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work) {
+  if (rows < 1 || cols < rows) return false;
+  const int n = rows;
+  const size_t nn = (size_t)n * n;
+  const int nb = kern::zdots_blocks((long long)nn);
+  char* base = static_cast<char*>(work.ensure(sizeof(rz) * (nn + (size_t)nb + 2) + 64));
+  rz* G = reinterpret_cast<rz*>(base);
+  rz* dpart = G + nn;
+  rz* dsum = dpart + nb;
+  int* dinfo = reinterpret_cast<int*>(dsum + 1);
+  hipStream_t s = ctx->stream;
+  HIP_CHECK(hipMemcpyAsync(B, C, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+  const rz one{1.0, 0.0};
+  for (int pass = 0; pass < 2; ++pass) {
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, G, n, 0, 1);
+    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, G, n, dinfo + pass), "zpotrf");
+    blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
+                             rocblas_diagonal_non_unit, cols, n, &one, G, n, static_cast<rz*>(B), cols),
+               "ztrsm");
+  }
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, G, n, 0, 1);
+  kern::zshift_diag(s, G, n, 1.0, -1.0);
+  kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
+  int info[2];
+  zc dev;
+  HIP_CHECK(hipMemcpyAsync(info, dinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&dev, dsum, sizeof(rz), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (info[0] != 0 || info[1] != 0 || !(dev.real() <= 1e-20)) return false;
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, 0, B, cols, 0, 0.0, L, n, 0, 1);
+  return true;
+}
+
 void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
                   void* Vh, DBuf& work, DBuf& work2) {
   // one-sided Jacobi SVD (accurate small singular values; far faster than the
@@ -87,7 +185,60 @@ void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, s
   read_info(ctx, dinfo, "zgesvdj");
 }
 
-void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows, DBuf& work) {
+// Householder tridiagonalisation in one cooperative launch (Q accumulated),
+// tridiagonal divide and conquer, rows = Z^T Q^H by one GEMM.  Returns false
+// (and leaves `rows` undefined) when the launch is not possible or the result
+// fails validation, so that the caller can use the rocSOLVER route.
+bool eigh_rows_desc_tridiag(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows,
+                            DBuf& work) {
+  const int G = kern::tridiag_groups(n);
+  if (n < 2 || G == 0) return false;
+  const size_t nn = (size_t)n * n;
+  const int nb = kern::zdots_blocks((long long)nn);
+  const size_t scr = kern::tridiag_scratch_bytes(n);
+  char* base = static_cast<char*>(work.ensure(2 * sizeof(rz) * nn + sizeof(double) * nn + scr +
+                                              sizeof(rz) * ((size_t)nb + 2) + sizeof(double) * (2 * (size_t)n + 4) +
+                                              512));
+  // layout (16-byte aligned first): X | Q | partial sums | sum | scratch | Z | D | E | info, err
+  rz* X = reinterpret_cast<rz*>(base);
+  rz* Q = X + nn;
+  rz* dpart = Q + nn;
+  rz* dsum = dpart + nb;
+  char* scratch = reinterpret_cast<char*>(dsum + 1);
+  double* Z = reinterpret_cast<double*>(scratch + (scr + 255) / 256 * 256);
+  double* dD = Z + nn;
+  double* dE = dD + n + 1;
+  int* dinfo = reinterpret_cast<int*>(dE + n + 1);
+  int* derr = dinfo + 2;
+  HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
+  kern::zhermitize(ctx->stream, X, n);
+  const hipError_t le = kern::tridiag(ctx->stream, X, n, Q, dD, dE, scratch, derr);
+  if (le != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  blas_check(rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, dD, dE, Z, n, dinfo), "dstedc");
+  kern::zrows_from_real_desc(ctx->stream, X, Z, n);
+  kern::gemm<double>(ctx->stream, TDVP_OP_N, TDVP_OP_C, n, n, n, 1.0, X, n, 0, Q, n, 0, 0.0, rows, n, 0, 1);
+  kern::zdots(ctx->stream, static_cast<const rz*>(rows), (long long)nn, 1, static_cast<const rz*>(rows), (long long)nn,
+              dpart, nb, dsum);
+  int flags[2] = {0, 0};
+  zc vsum;
+  std::vector<double> asc(n);
+  HIP_CHECK(hipMemcpyAsync(flags, dinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipMemcpyAsync(&flags[1], derr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipMemcpyAsync(&vsum, dsum, sizeof(rz), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipMemcpyAsync(asc.data(), dD, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  bool ok = flags[0] == 0 && flags[1] == 0 && std::isfinite(vsum.real()) && std::fabs(vsum.real() - n) <= 1e-6 * n;
+  for (double v : asc) ok = ok && std::isfinite(v);
+  if (!ok) return false;
+  lam.resize(n);
+  for (int j = 0; j < n; ++j) lam[j] = asc[n - 1 - j];
+  return true;
+}
+
+void eigh_rows_desc_heevd(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows, DBuf& work) {
   const size_t nn = (size_t)n * n;
   const int nb = kern::zdots_blocks((long long)nn);
   char* base = static_cast<char*>(work.ensure(sizeof(rz) * nn + sizeof(double) * (2 * (size_t)n + 8) +
@@ -139,6 +290,16 @@ void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& 
   }
   lam.resize(n);
   for (int j = 0; j < n; ++j) lam[j] = asc[n - 1 - j];
+}
+
+void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows, DBuf& work,
+                    int method) {
+  // the cooperative reduction pays from n ~ 128 on; below, a few workgroups
+  // leave most of the chip idle and the library route is as fast
+  const bool try_tridiag = method == EIGH_TRIDIAG || (method == EIGH_AUTO && n >= 128);
+  if (try_tridiag && eigh_rows_desc_tridiag(ctx, H, n, lam, rows, work)) return;
+  if (method == EIGH_TRIDIAG) TDVP_THROW(TDVP_ERR_NUMERIC, "cooperative tridiagonal eigensolver not applicable");
+  eigh_rows_desc_heevd(ctx, H, n, lam, rows, work);
 }
 
 void jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V) {

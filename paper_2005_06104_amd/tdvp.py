@@ -113,6 +113,7 @@ def load():
         "tdvp_keff_apply": (i, [vp, i, i, i, i, vp, vp, vp, vp, vp]),
         "tdvp_env_left": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
         "tdvp_env_right": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
+        "tdvp_eigh": (i, [vp, i, i, vp, vp, C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -389,6 +390,15 @@ def tdvp_gemm(ctx: Context, op_a: int, op_b: int, M: int, N: int, K: int, alpha,
     ctx.check(ctx.lib.tdvp_gemm(ctx.h, _prec_of(A, prec), op_a, op_b, M, N, K, alpha.real, alpha.imag, _tp(A), lda,
                                 stride_a, _tp(B), ldb, stride_b, beta.real, beta.imag, _tp(Cout), ldc, stride_c,
                                 batch), "tdvp_gemm")
+
+
+def tdvp_eigh(ctx: Context, H, rows, method: int = 0) -> np.ndarray:
+    """Eigendecomposition of the Hermitian complex128 device matrix H:
+    fills rows (row j = v_j^dagger) and returns the eigenvalues, descending."""
+    n = H.shape[0]
+    lam = np.zeros(n)
+    ctx.check(ctx.lib.tdvp_eigh(ctx.h, int(method), n, _tp(H), _tp(rows), _dptr(lam)), "tdvp_eigh")
+    return lam
 
 
 def _w_host(W: np.ndarray):

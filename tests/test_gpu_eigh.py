@@ -1,0 +1,104 @@
+"""Hermitian eigendecomposition on the device (tdvp_eigh): the cooperative
+Householder tridiagonalisation route and the rocSOLVER route against the
+eigenvalues of numpy's LAPACK eigensolver, orthonormality and reconstruction,
+on Gram matrices with decaying spectra, exact multiplets, rank deficiency and
+already-reduced (diagonal / tridiagonal) inputs."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2005_06104_amd import tdvp as T
+    ctx = T.Context(0)
+    yield T, torch, ctx
+    ctx.close()
+
+
+def _gram(n, seed, decay=12.0):
+    rng = np.random.default_rng(seed)
+    X = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) * np.exp(-decay * np.arange(n) / n)
+    return X @ X.conj().T
+
+
+def _multiplets(n, seed):
+    # eigenvalues repeated in multiplets of 1..4 (as the SU(2) multiplets of
+    # the Heisenberg models), some exactly zero
+    rng = np.random.default_rng(seed)
+    lam = []
+    v = 1.0
+    while len(lam) < n:
+        lam += [v] * int(rng.integers(1, 5))
+        v *= 0.7
+    lam = np.array(lam[:n])
+    lam[-max(1, n // 8):] = 0.0
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return (U * lam) @ U.conj().T
+
+
+def _tridiagonal(n, seed):
+    rng = np.random.default_rng(seed)
+    H = np.diag(rng.standard_normal(n)).astype(complex)
+    off = rng.standard_normal(n - 1) + 1j * rng.standard_normal(n - 1)
+    return H + np.diag(off, 1) + np.diag(off.conj(), -1)
+
+
+CASES = {"gram": _gram, "multiplets": _multiplets, "tridiagonal": _tridiagonal,
+         "diagonal": lambda n, s: np.diag(np.random.default_rng(s).standard_normal(n)).astype(complex)}
+
+
+def _check(T, torch, ctx, H, method):
+    n = H.shape[0]
+    dH = torch.from_numpy(H).cuda()
+    rows = torch.zeros_like(dH)
+    lam = T.tdvp_eigh(ctx, dH, rows, method)
+    V = rows.cpu().numpy()
+    ref = np.linalg.eigvalsh(H)[::-1]
+    scale = max(np.abs(ref).max(), 1e-300)
+    tol = (1e-14 * n + 1e-13) * scale
+    assert np.all(np.diff(lam) <= 0)
+    assert np.abs(lam - ref).max() <= tol
+    assert np.abs(V @ V.conj().T - np.eye(n)).max() <= 1e-14 * n + 1e-13
+    assert np.abs((V.conj().T * lam) @ V - H).max() <= tol
+
+
+@pytest.mark.parametrize("kind", sorted(CASES))
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 100, 255, 256, 301, 512])
+@pytest.mark.parametrize("method", [1, 2])
+def test_eigh_routes(env, kind, n, method):
+    T, torch, ctx = env
+    _check(T, torch, ctx, CASES[kind](n, 7 * n + len(kind)), method)
+
+
+@pytest.mark.parametrize("n", [1, 513, 700])
+def test_eigh_auto_outside_cooperative_range(env, n):
+    T, torch, ctx = env
+    _check(T, torch, ctx, _gram(n, n), 0)
+
+
+def test_eigh_cooperative_route_refuses_large(env):
+    T, torch, ctx = env
+    H = _gram(513, 1)
+    dH = torch.from_numpy(H).cuda()
+    with pytest.raises(T.TdvpError):
+        T.tdvp_eigh(ctx, dH, torch.zeros_like(dH), 1)
+
+
+def test_eigh_routes_agree_on_subspaces(env):
+    # the two routes give the same eigenvalues and the same spectral
+    # projectors onto well-separated groups
+    T, torch, ctx = env
+    H = _gram(300, 5)
+    dH = torch.from_numpy(H).cuda()
+    out = []
+    for m in (1, 2):
+        rows = torch.zeros_like(dH)
+        lam = T.tdvp_eigh(ctx, dH, rows, m)
+        out.append((lam, rows.cpu().numpy()))
+    assert np.abs(out[0][0] - out[1][0]).max() <= 1e-12 * out[0][0][0]
+    for k in (10, 50):
+        P = [r[:k].conj().T @ r[:k] for _, r in out]
+        assert np.abs(P[0] - P[1]).max() < 1e-9
