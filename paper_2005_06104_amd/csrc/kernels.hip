@@ -31,18 +31,23 @@ __device__ inline f4 mfma(float a, float b, f4 c) {
 }
 
 // ---------------------------------------------------------------- GEMM
-// Block tile BM x BN complex outputs, BK complex per stage, 256 threads =
-// 4 waves in a 2 x 2 grid, each wave 32 x 32 outputs = 2 x 2 MFMA 16x16
-// tiles for the real and for the imaginary part.
+// Block tile BM x BN complex outputs, BK complex per stage.  FP64: 1024
+// threads = 16 waves in a 4 x 4 grid, one 16x16 MFMA tile each (four waves
+// per SIMD keep the long FP64 MFMA pipeline fed while others wait on LDS or
+// the stage barrier); FP32: 256 threads = 4 waves in a 2 x 2 grid, each
+// 32 x 32 outputs = 2 x 2 MFMA tiles, for the real and for the imaginary part.
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 constexpr int PAD = 1;
+template <typename T> struct WaveGrid { static constexpr int WM = 2, WN = 2; };
+template <> struct WaveGrid<double> { static constexpr int WM = 4, WN = 4; };
+template <typename T> constexpr int gemm_threads() { return WaveGrid<T>::WM * WaveGrid<T>::WN * 64; }
 
 // TAG only separates instantiations (the one-site effective Hamiltonian uses
 // its own so that profilers and timers see it apart from the other GEMMs).
 // Split-K: blockIdx.z = batch * S + split; split s covers k in
 // [s*Kc, min(K, (s+1)*Kc)) and writes its partial product at C + s*sps.
 template <typename T, bool TA, bool CA, bool TB, bool CB, int TAG>
-__global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T ai, const T* __restrict__ A,
+__global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, int K, T ar, T ai, const T* __restrict__ A,
                                                    long long lda, long long sa, const T* __restrict__ B,
                                                    long long ldb, long long sb, T br, T bi,
                                                    T* __restrict__ C, long long ldc, long long sc, int S, int Kc,
@@ -52,10 +57,12 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
   __shared__ T As_r[2][BK][BM + PAD], As_i[2][BK][BM + PAD];
   __shared__ T Bs_r[2][BK][BN + PAD], Bs_i[2][BK][BN + PAD];
 
+  constexpr int WM = WaveGrid<T>::WM, WN = WaveGrid<T>::WN, NTH = WM * WN * 64;
+  constexpr int SI = BM / WM / 16, SJ = BN / WN / 16;   // MFMA tiles per wave
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
   // linear id g runs on XCD g % 8.  Give each XCD a contiguous band of tiles
   // (z-slice, then tile row, then tile column) so that the operand panels a
@@ -74,13 +81,13 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
   const c2* Bb = reinterpret_cast<const c2*>(B) + bz * sb;
   c2* Cb = reinterpret_cast<c2*>(C) + bz * sc + split * sps;
 
-  constexpr int PER = (BM * BK) / NT;  // complex elements per thread per operand (4)
+  constexpr int PER = (BM * BK) / NTH;  // complex elements per thread per operand
   c2 ra[PER], rb[PER];
 
   auto load = [&](int k0) {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
-      const int idx = tid + it * NT;
+      const int idx = tid + it * NTH;
       int m, k;
       if (!TA) { m = idx / BK; k = idx % BK; } else { k = idx / BM; m = idx % BM; }
       const int gm = m0 + m, gk = k0 + k;
@@ -92,7 +99,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
-      const int idx = tid + it * NT;
+      const int idx = tid + it * NTH;
       int n, k;
       if (!TB) { k = idx / BN; n = idx % BN; } else { n = idx / BK; k = idx % BK; }
       const int gn = n0 + n, gk = k0 + k;
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
   auto store = [&](int buf) {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
-      const int idx = tid + it * NT;
+      const int idx = tid + it * NTH;
       int m, k;
       if (!TA) { m = idx / BK; k = idx % BK; } else { k = idx / BM; m = idx % BM; }
       As_r[buf][k][m] = ra[it].x;
@@ -114,7 +121,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
-      const int idx = tid + it * NT;
+      const int idx = tid + it * NTH;
       int n, k;
       if (!TB) { k = idx / BN; n = idx % BN; } else { n = idx / BK; k = idx % BK; }
       Bs_r[buf][k][n] = rb[it].x;
@@ -122,11 +129,11 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
     }
   };
 
-  acc_t cr[2][2], ci[2][2];
+  acc_t cr[SI][SJ], ci[SI][SJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < SJ; ++j) {
       cr[i][j] = acc_t{0, 0, 0, 0};
       ci[i][j] = acc_t{0, 0, 0, 0};
     }
@@ -144,22 +151,22 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
-      T a_r[2], a_i[2], a_n[2], b_r[2], b_i[2];
+      T a_r[SI], a_i[SI], a_n[SI], b_r[SJ], b_i[SJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        a_r[i] = As_r[cur][kr][wm * 32 + i * 16 + lr];
-        a_i[i] = As_i[cur][kr][wm * 32 + i * 16 + lr];
+      for (int i = 0; i < SI; ++i) {
+        a_r[i] = As_r[cur][kr][wm * (BM / WM) + i * 16 + lr];
+        a_i[i] = As_i[cur][kr][wm * (BM / WM) + i * 16 + lr];
         a_n[i] = -a_i[i];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        b_r[j] = Bs_r[cur][kr][wn * 32 + j * 16 + lr];
-        b_i[j] = Bs_i[cur][kr][wn * 32 + j * 16 + lr];
+      for (int j = 0; j < SJ; ++j) {
+        b_r[j] = Bs_r[cur][kr][wn * (BN / WN) + j * 16 + lr];
+        b_i[j] = Bs_i[cur][kr][wn * (BN / WN) + j * 16 + lr];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < SI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < SJ; ++j) {
           cr[i][j] = mfma(a_r[i], b_r[j], cr[i][j]);
           cr[i][j] = mfma(a_n[i], b_i[j], cr[i][j]);
           ci[i][j] = mfma(a_r[i], b_i[j], ci[i][j]);
@@ -173,16 +180,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int M, int N, int K, T ar, T a
 
   const bool has_beta = (br != T(0)) || (bi != T(0));
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < SI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < SJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // output row inside the 16x16 tile: the f32 MFMA puts rows 4*(lane/16)+r
         // in a lane, the f64 MFMA rows (lane/16)+4*r (columns are lane%16 for both)
         const int tr = sizeof(T) == 8 ? (lk + 4 * r) : (lk * 4 + r);
-        const int gm = m0 + wm * 32 + i * 16 + tr;
-        const int gn = n0 + wn * 32 + j * 16 + lr;
+        const int gm = m0 + wm * (BM / WM) + i * 16 + tr;
+        const int gn = n0 + wn * (BN / WN) + j * 16 + lr;
         if (gm < M && gn < N) {
           const T xr = cr[i][j][r], xi = ci[i][j][r];
           c2 o;
@@ -455,8 +462,8 @@ void launch_tiles(dim3 grid, hipStream_t s, int M, int N, int K, T ar, T ai, con
                   long long sa, const T* B, long long ldb, long long sb, T br, T bi, T* C, long long ldc,
                   long long sc, int S, int Kc, long long sps) {
   if constexpr (MODE == 0) {
-    hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, ar, ai, A, lda, sa, B,
-                       ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
+    hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(gemm_threads<T>()), 0, s, M, N, K, ar, ai, A,
+                       lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
   } else {
     hipLaunchKernelGGL((gemm_bf16_kernel<MODE - 1, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, ar, ai,
                        A, lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
