@@ -44,6 +44,39 @@ def xi2_from_moments(N, sx, syy, szz, syz, szy):
     return N * (syy + szz - np.sqrt((syy - szz) ** 2 + (syz + szy) ** 2)) / (2.0 * sx ** 2)
 
 
+def dicke_spin_matrices(N: int):
+    """Total-spin operators J_x, J_y, J_z on the symmetric subspace, j = N/2,
+    basis m = j, j-1, ..., -j, with J_+|j,m> = sqrt(j(j+1) - m(m+1))|j,m+1>."""
+    j = 0.5 * N
+    m = j - np.arange(N + 1)
+    Jp = np.zeros((N + 1, N + 1))
+    for k in range(1, N + 1):
+        Jp[k - 1, k] = np.sqrt(j * (j + 1) - m[k] * (m[k] + 1))
+    Jm = Jp.T
+    return 0.5 * (Jp + Jm), -0.5j * (Jp - Jm), np.diag(m)
+
+
+def oat_moments_dicke(N: int, t: float) -> dict:
+    """Exact one-axis-twisting dynamics (eq. (12) with chi = 1) from the +x
+    product state, which lies in the symmetric subspace (the top eigenvector
+    of J_x): psi(t) = exp(-i t J_z^2) psi(0).  Returns <S^a> and the second
+    moments s_ab = <S^a S^b> that eq. (15) takes, plus the anticommutator
+    s_yz + s_zy."""
+    Jx, Jy, Jz = dicke_spin_matrices(N)
+    _, V = np.linalg.eigh(Jx)
+    psi = np.exp(-1j * t * np.diag(Jz) ** 2) * V[:, -1]
+    ev = lambda A: complex(np.vdot(psi, A @ psi))
+    out = {"sx": ev(Jx).real, "sy": ev(Jy).real, "sz": ev(Jz).real, "syy": ev(Jy @ Jy).real,
+           "szz": ev(Jz @ Jz).real, "syz": ev(Jy @ Jz), "szy": ev(Jz @ Jy)}
+    out["syz_szy"] = (out["syz"] + out["szy"]).real
+    return out
+
+
+def oat_xi2_dicke(N: int, t: float) -> float:
+    m = oat_moments_dicke(N, t)
+    return float(xi2_from_moments(N, m["sx"], m["syy"], m["szz"], m["syz_szy"], 0.0))
+
+
 def xi2_dense(psi_vec: np.ndarray, N: int) -> float:
     """Eq. (14) evaluated directly: N min over n_perp of the variance along
     n_perp divided by <S>^2, by scanning the angle in the y-z plane."""

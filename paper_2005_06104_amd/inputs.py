@@ -154,6 +154,35 @@ def oat_terms(N: int, chi: float = 1.0) -> List[Term]:
     return terms
 
 
+def spin_moment_terms(N: int, which: str) -> List[Term]:
+    """Term lists of the total-spin moments that eqs. (13)-(15) use, for
+    measuring them as MPO expectation values: "x", "y", "z" (S^a_tot),
+    "yy", "zz" ((S^a_tot)^2) and "yz" (S^y_tot S^z_tot + S^z_tot S^y_tot).
+    S^y = (S^+ - S^-) / 2i; (S^a_i)^2 = 1/4 and {S^y_i, S^z_i} = 0 for spin 1/2."""
+    one = {"x": [(OP_SP, 0.5), (OP_SM, 0.5)], "y": [(OP_SP, -0.5j), (OP_SM, 0.5j)], "z": [(OP_SZ, 1.0)]}
+    if which in one:
+        return [(i, -1, op, OP_I, complex(c)) for i in range(N) for op, c in one[which]]
+    if which == "zz":
+        return oat_terms(N)
+    if which == "yy":
+        terms: List[Term] = [(i, -1, OP_I, OP_I, complex(0.25)) for i in range(N)]
+        pairs = [(OP_SP, OP_SP, -0.25), (OP_SP, OP_SM, 0.25), (OP_SM, OP_SP, 0.25), (OP_SM, OP_SM, -0.25)]
+        for i in range(N):
+            for j in range(i + 1, N):
+                terms += [(i, j, a, b, complex(2.0 * c)) for a, b, c in pairs]
+        return terms
+    if which == "yz":
+        sy = [(OP_SP, -0.5j), (OP_SM, 0.5j)]
+        terms = []
+        for i in range(N):
+            for j in range(i + 1, N):
+                for op, c in sy:
+                    terms.append((i, j, op, OP_SZ, complex(2.0 * c)))
+                    terms.append((i, j, OP_SZ, op, complex(2.0 * c)))
+        return terms
+    raise ValueError(f"unknown moment {which}")
+
+
 def terms_as_arrays(terms: Sequence[Term]):
     """Split a term list into the plain arrays the C-ABI takes."""
     ii = np.array([t[0] for t in terms], dtype=np.int32)

@@ -9,6 +9,7 @@ the stream.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 import os
 import re
 from typing import List, Optional, Sequence
@@ -173,6 +174,9 @@ class Context:
         if st != TDVP_OK:
             raise TdvpError(st, "tdvp_ctx_create failed")
         self.h = h
+        # MPO / MPS handles free their device memory through this context:
+        # they are destroyed before it
+        self._children = weakref.WeakSet()
 
     def check(self, st: int, what: str):
         if st != TDVP_OK:
@@ -180,6 +184,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for child in list(getattr(self, "_children", ())):
+                child._destroy()
             self.lib.tdvp_ctx_destroy(self.h)
             self.h = None
 
@@ -206,6 +212,7 @@ def tdvp_synchronize(ctx: Context):
 class MPO:
     def __init__(self, ctx: Context, h, dims):
         self.ctx, self.h, self.dims = ctx, h, list(dims)
+        ctx._children.add(self)
 
     @property
     def n_sites(self):
@@ -223,11 +230,14 @@ class MPO:
             off += sz
         return out
 
+    def _destroy(self):
+        if self.h and self.ctx.h:
+            self.ctx.lib.tdvp_mpo_destroy(self.h)
+        self.h = None
+
     def __del__(self):
         try:
-            if self.h:
-                self.ctx.lib.tdvp_mpo_destroy(self.h)
-                self.h = None
+            self._destroy()
         except Exception:
             pass
 
@@ -271,6 +281,7 @@ def tdvp_build_mpo_host(n_sites: int, terms, c0: complex = 0.0, c1: complex = 1.
 class MPS:
     def __init__(self, ctx: Context, h, n_sites: int):
         self.ctx, self.h, self.n_sites = ctx, h, n_sites
+        ctx._children.add(self)
 
     def bond_dims(self) -> List[int]:
         dims = np.zeros(self.n_sites + 1, dtype=np.int32)
@@ -282,11 +293,14 @@ class MPS:
     def to_host(self) -> List[np.ndarray]:
         return tdvp_mps_to_host(self)
 
+    def _destroy(self):
+        if self.h and self.ctx.h:
+            self.ctx.lib.tdvp_mps_destroy(self.h)
+        self.h = None
+
     def __del__(self):
         try:
-            if self.h:
-                self.ctx.lib.tdvp_mps_destroy(self.h)
-                self.h = None
+            self._destroy()
         except Exception:
             pass
 

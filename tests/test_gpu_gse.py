@@ -241,6 +241,36 @@ def test_gse_oat_closed_form_on_device(env):
         assert abs(sx - O.oat_sx_exact(N, t)) < 5e-8
 
 
+def test_oat_squeezing_moments_on_device(env):
+    # eqs. (14)-(15): the total-spin moments measured on the device as MPO
+    # expectation values agree with the oracle's state to rounding and with
+    # the exact symmetric-subspace dynamics to the method's error (1e-5 on xi^2)
+    T, ctx = env
+    from oracle import gse, mpo, observables as O
+    N, dt = 16, 0.025
+    terms = I.oat_terms(N)
+    H = T.tdvp_create_mpo(ctx, N, terms)
+    op = T.tdvp_create_mpo(ctx, N, terms, 1.0, -1j * dt)
+    names = ("x", "yy", "zz", "yz")
+    dev_ops = {k: T.tdvp_create_mpo(ctx, N, I.spin_moment_terms(N, k)) for k in names}
+    cpu_ops = {k: mpo.build_mpo(N, I.spin_moment_terms(N, k)) for k in names}
+    Ws, Wop = mpo.build_mpo(N, terms), mpo.build_mpo(N, terms, 1.0, -1j * dt)
+    g = T.tdvp_mps_from_host(ctx, I.x_polarized_mps(N))
+    psi = I.x_polarized_mps(N)
+    t = 0.0
+    for _ in range(10):
+        T.tdvp_expand_basis(ctx, [g], [op], 3, 1e-10, 1e-10, 64, "fp64")
+        T.tdvp_sweep(ctx, [g], [H], dt, 0.0, 64, 1e-12, 30, "fp64", False)
+        psi, _ = gse.gse_step(psi, Ws, Wop, dt, 3, 1e-10, 1e-10, 0.0, 64)
+        t += dt
+        dev = {k: T.tdvp_measure(ctx, [g], [dev_ops[k]])[0]["energy"] for k in names}
+        ref = {k: O.energy(psi, cpu_ops[k]) for k in names}
+        for k in names:
+            assert abs(dev[k] - ref[k]) < 1e-9 * max(1.0, abs(ref[k])), (k, dev[k], ref[k])
+        xi2 = O.xi2_from_moments(N, dev["x"], dev["yy"], dev["zz"], dev["yz"], 0.0)
+        assert abs(xi2 - O.oat_xi2_dicke(N, t)) < 1e-5 * O.oat_xi2_dicke(N, t)
+
+
 def test_batched_instances_match_single_runs(env):
     # several independent ladders of different sizes in one call (worker
     # streams) give the same states as the same ladders run one by one

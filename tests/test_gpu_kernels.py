@@ -270,3 +270,21 @@ def test_env_updates_bf16_within_bound(env, prec, ml, wl, wr, mr):
         err = np.abs(got - ref)
         bound = 2 * _bf_bound(prec, Kmax, S) + 2.0 ** -20 * S
         assert (err <= bound).all(), (err / bound).max()
+
+
+def test_context_close_before_handles():
+    # handles free their device memory through the context: closing the
+    # context first must destroy them, and their later collection must not
+    # touch the closed context
+    import gc
+
+    from paper_2005_06104_amd import tdvp as T
+    ctx = T.Context(0)
+    N = 6
+    H = T.tdvp_create_mpo(ctx, N, I.oat_terms(N))
+    g = T.tdvp_mps_from_host(ctx, I.x_polarized_mps(N))
+    assert T.tdvp_measure(ctx, [g], [H])[0]["norm"] > 0
+    ctx.close()
+    assert H.h is None and g.h is None
+    del H, g
+    gc.collect()
