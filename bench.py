@@ -234,6 +234,92 @@ def oat_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def tdvp2_compare_mode(args):
+    """GSE-TDVP1 against two-site TDVP at the same bond dimension m' (the cost
+    statement closing section I.C, made for real time with k = 5 and m' ~ 3m):
+    the 64-site ladder of the main bench is prepared at bond dimension
+    m = chi/3 (four imaginary-time GSE steps), quenched to the rung-coupled
+    ladder and evolved in real time with dt = 0.05, k = 5, eps_K = 1e-4,
+    eps_M = 1e-8, eps = 0 (the section II.B settings for dt = 0.05).  Timed:
+    one GSE-TDVP1 step from the bond-m state (its extension grows the bonds to
+    m' <= chi), and one two-site TDVP sweep of a state already at m' with the
+    cap m'; each K times from the same states."""
+    import torch
+
+    from paper_2005_06104_amd import inputs as I
+    from paper_2005_06104_amd import tdvp as T
+    torch.cuda.set_device(0)
+    ctx = T.Context(0)
+    w0 = I.workload(1)
+    N = w0.lattice.n_sites
+    chi = w0.chi_max
+    m = chi // 3
+    H0 = T.tdvp_create_mpo(ctx, N, w0.terms)
+    op0 = T.tdvp_create_mpo(ctx, N, w0.terms, 1.0, -1j * w0.tau)
+    psi = T.tdvp_mps_from_host(ctx, w0.initial_mps())
+    for i in range(4):
+        T.tdvp_expand_basis(ctx, [psi], [op0], w0.k, w0.eps_K, w0.eps_M, m, "fp64")
+        T.tdvp_sweep(ctx, [psi], [H0], w0.dt, w0.eps, m, 1e-12, 30, "fp64", True)
+    lat1 = I.ladder(32, 1.0, 1.0, "zigzag")
+    terms1 = I.heisenberg_terms(lat1.couplings)
+    dt, k, eK, eM = 0.05, 5, 1e-4, 1e-8
+    H1 = T.tdvp_create_mpo(ctx, N, terms1)
+    op1 = T.tdvp_create_mpo(ctx, N, terms1, 1.0, -1j * dt)
+    start = T.tdvp_mps_to_host(psi)
+    m0 = T.tdvp_measure(ctx, [psi], [H1])[0]
+    log(f"[compare] prepared: max bond {max(m0['bond_dims'])}, E(H1) = {m0['energy']:.10f}")
+    del psi
+    split = {"krylov": 0.0, "extend": 0.0, "sweep": 0.0}
+    ms_gse = 0.0
+    mprime = 0
+    after = None
+    for i in range(args.steps + 1):
+        g = T.tdvp_mps_from_host(ctx, start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = T.tdvp_expand_basis(ctx, [g], [op1], k, eK, eM, chi, "fp64")[0]
+        sw = T.tdvp_sweep(ctx, [g], [H1], dt, 0.0, chi, 1e-12, 30, "fp64", False)[0]
+        torch.cuda.synchronize()
+        el = 1e3 * (time.perf_counter() - t0)
+        mprime = max(mprime, e["max_bond"])
+        log(f"[compare] GSE-TDVP1 step from m = {max(m0['bond_dims'])}: {el:.0f} ms (krylov {e['ms_krylov']:.0f}, "
+            f"extend {e['ms_extend']:.0f}, sweep {sw['ms']:.0f}), m' = {e['max_bond']}")
+        if i > 0:
+            ms_gse += el / args.steps
+            split["krylov"] += e["ms_krylov"] / args.steps
+            split["extend"] += e["ms_extend"] / args.steps
+            split["sweep"] += sw["ms"] / args.steps
+        after = T.tdvp_mps_to_host(g)
+        del g
+    ms_t2 = 0.0
+    for i in range(args.steps + 1):
+        g2 = T.tdvp_mps_from_host(ctx, after)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = T.tdvp_sweep2(ctx, [g2], [H1], dt, 0.0, mprime, 1e-12, 30, "fp64", False)[0]
+        torch.cuda.synchronize()
+        el = 1e3 * (time.perf_counter() - t0)
+        log(f"[compare] TDVP2 sweep at m' = {mprime}: {el:.0f} ms, pair matvecs {st['n_matvec']}")
+        if i > 0:
+            ms_t2 += el / args.steps
+        del g2
+    out = {
+        "metric": "GSE-TDVP1 step time over two-site TDVP step time at equal bond dimension",
+        "value": ms_gse / ms_t2, "unit": "ratio", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": ms_gse, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2x32 ladder prepared at m = chi/3, quenched to J_rung = 1, real time",
+                   "n_sites": N, "m": max(m0["bond_dims"]), "m_prime": mprime, "chi_max": chi, "dt": dt, "k": k,
+                   "eps_K": eK, "eps_M": eM, "eps": 0.0, "parallelism": "single GPU"},
+        "ms_per_gse_step": ms_gse, "ms_per_tdvp2_step": ms_t2, "gse_split_ms": split,
+        "gse_steps12_over_step3": (split["krylov"] + split["extend"]) / split["sweep"] if split["sweep"] else None,
+        "paper_ratio_context": "section I.C reports about 0.36 for this ratio and about 1/3 for steps 1+2 over "
+                               "step 3 (CPU, ITensor)",
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def batch_mode(args):
     """Many independent ladders (seeded leg lengths U{8..32}, couplings
     U[0.5,1.5]) stepped together: each C-ABI call takes all instances and runs
@@ -359,6 +445,8 @@ def main():
                     help="many independent ladders stepped concurrently (instance-steps/s)")
     ap.add_argument("--batch-size", type=int, default=64)
     ap.add_argument("--batch-serial", action="store_true", help="step the batch one instance per call")
+    ap.add_argument("--tdvp2-compare", action="store_true",
+                    help="GSE-TDVP1 step against a two-site TDVP step at the same bond dimension")
     ap.add_argument("--oat", action="store_true",
                     help="one-axis twisting workload with squeezing moments (section II.B)")
     ap.add_argument("--oat-n", type=int, default=100)
@@ -379,6 +467,9 @@ def main():
         return
     if args.oat:
         oat_mode(args)
+        return
+    if args.tdvp2_compare:
+        tdvp2_compare_mode(args)
         return
     import torch
 

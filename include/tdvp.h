@@ -222,6 +222,19 @@ typedef struct {
   int* bond_dims;       /* n_sites + 1 entries                            */
 } tdvp_observables;
 
+/* One symmetric two-site TDVP sweep on psi[j], j < n: the conventional
+ * method with which the cost statement closing section I.C and the
+ * benchmarks of section II compare GSE-TDVP1.  Left to right over the site
+ * pairs with dt/2 each (the last pair once by dt), right to left with dt/2;
+ * each pair is split by the truncated gauge move (discarded weight <= eps
+ * times its norm squared, at most chi_max kept; with eps = 0 only zero
+ * weights and the chi_max cap cut) and the new one-site center is evolved
+ * backwards by dt/2.  Parameters and statistics as for tdvp_sweep (n_keff
+ * counts the backward one-site matvecs); same pre- and postcondition; needs
+ * n_sites >= 2.  No tdvp_expand_basis is needed before it. */
+tdvp_status tdvp_sweep2(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H,
+                        const tdvp_sweep_params* params, tdvp_sweep_stats* stats);
+
 /* Measure psi[j] (any gauge) for j < n; H and other may be NULL (then n
  * entries each when given). */
 tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mpo* H,

@@ -420,6 +420,41 @@ tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, co
   });
 }
 
+tdvp_status tdvp_sweep2(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, const tdvp_sweep_params* params,
+                       tdvp_sweep_stats* stats) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && psi && H && params, "bad arguments");
+    for (int j = 0; j < n; ++j) ARG_CHECK(psi[j] && psi[j]->N >= 2, "two-site TDVP needs at least two sites");
+    const tdvp_sweep_params& p = *params;
+    ARG_CHECK(std::isfinite(p.dt_re) && std::isfinite(p.dt_im), "non-finite time step");
+    ARG_CHECK(p.eps >= 0, "eps must be >= 0");
+    ARG_CHECK(p.chi_max >= 1, "chi_max must be >= 1");
+    ARG_CHECK(p.krylov_max >= 1 && p.krylov_max <= 64, "krylov_max must be in 1..64");
+    ARG_CHECK(p.krylov_tol >= 0, "krylov_tol must be >= 0");
+    ARG_CHECK(p.prec >= TDVP_FP64 && p.prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
+    for (int j = 0; j < n; ++j) {
+      ARG_CHECK(psi[j] && H[j], "NULL handle");
+      ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
+      if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
+    }
+    bind(ctx);
+    for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
+      tdvp_sweep_stats st{};
+      try {
+        run_sweep2(c, *psi[j], *H[j], p, st);
+      } catch (const TdvpError& e) {
+        if (e.code != TDVP_ERR_NOCONV) psi[j]->valid = false;
+        throw;
+      } catch (...) {
+        psi[j]->valid = false;
+        throw;
+      }
+      if (stats) stats[j] = st;
+    });
+  });
+}
+
 tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mpo* H, const tdvp_mps* other,
                          tdvp_observables* out) {
   if (!ctx) return TDVP_ERR_ARG;

@@ -209,6 +209,31 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
                 0, 1);
 }
 
+// Two-site effective Hamiltonian on Th[a,(s,v),b] for the sites i, i+1:
+// Y[a',t,u,b'] = sum L[a',al,a] W1[al,be,t,s] W2[be,ga,u,v] Th[a,s,v,b] Rt[ga,b,b'].
+// Work buffers hold 4*ml*mr*max(wl,wm,wr) elements each.
+template <typename T>
+void heff2_apply(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int ml, int wl, int wm, int wr, int mr,
+                 const void* L, const void* Rt, const void* Th, void* Y, void* ws1, void* ws2, MatvecTimer* tm,
+                 SplitWS sk) {
+  hipStream_t s = ctx->stream;
+  if (tm) tm->mark(0);
+  // T1[(a',al),(s,v,b)] = L[(a',al),a] Th[a,(s,v,b)]
+  kern::gemm_heff<T>(s, ml * wl, 4 * mr, ml, L, ml, Th, 4 * mr, ws1, 4 * mr, sk.p, sk.bytes);
+  if (tm) tm->mark(1);
+  // T2[a',t,be,(v,b)] = sum W1[al,be,t,s] T1[a',al,s,(v,b)]
+  kern::wapply<T>(s, t1.F, ws1, ws2, ml, 2LL * mr, (long long)wl * 4 * mr, 1, 4LL * mr, 2LL * mr,
+                  (long long)2 * wm * 2 * mr, 1, 2LL * mr, (long long)wm * 2 * mr);
+  // T3[(a',t),u,ga,b] = sum W2[be,ga,u,v] T2[(a',t),be,v,b]
+  kern::wapply<T>(s, t2.F, ws2, ws1, 2LL * ml, mr, (long long)wm * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr,
+                  1, mr, (long long)wr * mr);
+  if (tm) tm->mark(2);
+  // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b']
+  kern::gemm_heff<T>(s, 4 * ml, mr, wr * mr, ws1, (long long)wr * mr, Rt, mr, Y, mr, sk.p, sk.bytes);
+  if (tm) tm->mark(3);
+  if (tm) tm->gemm_flops += 8.0 * ((double)ml * wl * ml * 4 * mr + (double)4 * ml * wr * mr * mr);
+}
+
 template void heff_apply<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
                                  const void*, void*, void*, void*, MatvecTimer*, SplitWS);
 template void heff_apply<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
@@ -415,7 +440,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int rows = 2 * ml, cols = mr, kk = std::min(rows, cols);
-  if (eps == 0.0) {
+  if (eps == 0.0 && kk <= chi_max) {
     A.ensure((size_t)rows * kk * ZB);
     R.ensure((size_t)kk * cols * ZB);
     if (!la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work))
@@ -458,7 +483,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int rows = ml, cols = 2 * mr, kk = std::min(rows, cols);
-  if (eps == 0.0) {
+  if (eps == 0.0 && kk <= chi_max) {
     L.ensure((size_t)rows * kk * ZB);
     B.ensure((size_t)kk * cols * ZB);
     if (!la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work))
@@ -643,6 +668,171 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const int ml = psi.m[0], mr = psi.m[1];
     const long long n = psi.elems(0);
     ensure_ws(ml, H.w(0), H.w(1), mr);
+    W.tmpC.ensure((size_t)n * ZB);
+    if (sizeof(T) == 8) {
+      heff_apply<T>(ctx, H.tab[0], ml, H.w(0), H.w(1), mr, L[0].p, R[1].p, psi.site(0), W.tmpC.p, W.ws1.p, W.ws2.p);
+    } else {
+      W.xf.ensure((size_t)n * 8);
+      W.yf.ensure((size_t)n * 8);
+      kern::z2c(ctx->stream, W.xf.p, psi.site(0), n);
+      heff_apply<T>(ctx, H.tab[0], ml, H.w(0), H.w(1), mr, L[0].p, R[1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p);
+      kern::c2z(ctx->stream, W.tmpC.p, W.yf.p, n);
+    }
+    const zc e = W.sc.dot(psi.site(0), W.tmpC.p, n);
+    const double nn = W.sc.dot(psi.site(0), psi.site(0), n).real();
+    st.energy = e.real() / nn;
+  }
+  st.ms_matvec = timer.ms;
+  st.ms_heff_gemm = timer.gemm_ms;
+  st.flops_heff_gemm = timer.gemm_flops;
+  st.n_heff_gemm = timer.n_gemm;
+}
+
+// Two-site TDVP sweep (the comparison method of the cost statement in
+// section I.C and of the benchmarks of section II): left to right over the
+// pairs (i, i+1) with dt/2, right to left with dt/2, the last pair evolved
+// once by dt; each pair is split by the truncated gauge move (eps, chi_max;
+// zero weights and the cap only when eps = 0) and the new one-site center is
+// evolved backwards by dt/2 except after the last pair of a half sweep.
+// Pre- and postcondition: center at site 0, sites 1..N-1 right-canonical.
+template <typename T>
+void sweep2_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
+                 tdvp_sweep_stats& st) {
+  const int N = psi.N;
+  if (N < 2) TDVP_THROW(TDVP_ERR_ARG, "two-site TDVP needs at least two sites");
+  const int cb = cbytes<T>();
+  const zc dt(p.dt_re, p.dt_im), half = 0.5 * dt;
+  Work W(ctx);
+  std::vector<DBuf> L, R;
+  for (int i = 0; i <= N; ++i) {
+    L.emplace_back(ctx);
+    R.emplace_back(ctx);
+  }
+  set_one(ctx, L[0], cb);
+  set_one(ctx, R[N], cb);
+  MatvecTimer timer;
+  timer.ctx = ctx;
+  timer.on = true;
+  auto ensure_ws = [&](size_t elems) {
+    W.ws1.ensure(elems * cb);
+    W.ws2.ensure(elems * cb);
+  };
+  auto build_R = [&](int i) {
+    const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
+    ensure_ws((size_t)2 * ml * mr * std::max(wl, wr));
+    R[i].ensure((size_t)wl * ml * ml * cb);
+    const void* Bt = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
+    env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p);
+  };
+  auto build_L = [&](int i) {
+    const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
+    ensure_ws((size_t)2 * ml * mr * std::max(wl, wr));
+    L[i + 1].ensure((size_t)mr * wr * mr * cb);
+    const void* At = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
+    env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p, W.split(ml, mr, cb));
+  };
+  auto stepinfo = [&](int napp, bool unconv) {
+    st.max_lanczos = std::max(st.max_lanczos, napp);
+    if (unconv) {
+      ++st.n_unconverged;
+      if (p.strict) TDVP_THROW(TDVP_ERR_NOCONV, "Lanczos reached krylov_max without converging");
+    }
+  };
+  // FP64 master in x; working-precision copies for the mixed paths
+  auto run_lanczos = [&](void* x, long long n, zc step, auto&& apply_T, double flops, bool timed, auto* count) {
+    auto mv = [&](const void* in, void* out) {
+      if (sizeof(T) == 8) {
+        apply_T(in, out);
+      } else {
+        W.xf.ensure((size_t)n * 8);
+        W.yf.ensure((size_t)n * 8);
+        kern::z2c(ctx->stream, W.xf.p, in, n);
+        apply_T(W.xf.p, W.yf.p);
+        kern::c2z(ctx->stream, out, W.yf.p, n);
+      }
+      st.flops_matvec += flops;
+    };
+    bool unconv = false;
+    const int napp = W.lz.run(mv, x, n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv,
+                              timed ? &timer : nullptr);
+    *count += napp;
+    stepinfo(napp, unconv);
+  };
+  DBuf Th(ctx), A(ctx), Cn(ctx);
+  auto form_pair = [&](int i) {  // Th = site(i) site(i+1), ml x 2 x 2 x mr
+    const int ml = psi.m[i], mb = psi.m[i + 1], mr = psi.m[i + 2];
+    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * ml, 2 * mr, mb, psi.site(i), mb, psi.site(i + 1), 2LL * mr, Th);
+  };
+  auto evolve_pair = [&](int i, zc step) {
+    const int ml = psi.m[i], mr = psi.m[i + 2], wl = H.w(i), wm = H.w(i + 1), wr = H.w(i + 2);
+    const long long n = 4LL * ml * mr;
+    ensure_ws((size_t)4 * ml * mr * std::max(wl, std::max(wm, wr)));
+    const SplitWS sk = W.split(2 * ml, 2 * mr, cb);
+    const double flops = 8.0 * ((double)ml * wl * ml * 4 * mr + (double)H.tab[i].nnz * ml * 2 * mr +
+                                (double)H.tab[i + 1].nnz * 2 * ml * mr + (double)4 * ml * wr * mr * mr);
+    auto ap = [&](const void* in, void* out) {
+      heff2_apply<T>(ctx, H.tab[i], H.tab[i + 1], ml, wl, wm, wr, mr, L[i].p, R[i + 2].p, in, out, W.ws1.p, W.ws2.p,
+                     &timer, sk);
+    };
+    run_lanczos(Th.p, n, step, ap, flops, true, &st.n_matvec);
+  };
+  auto evolve_site = [&](int i, void* C, zc step) {
+    const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
+    const long long n = 2LL * ml * mr;
+    ensure_ws((size_t)2 * ml * mr * std::max(wl, wr));
+    const SplitWS sk = W.split(ml, mr, cb);
+    const double flops = 8.0 * ((double)ml * wl * ml * 2 * mr + (double)H.tab[i].nnz * ml * mr +
+                                (double)2 * ml * wr * mr * mr);
+    auto ap = [&](const void* in, void* out) {
+      heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, nullptr, sk);
+    };
+    run_lanczos(C, n, step, ap, flops, false, &st.n_keff);
+  };
+  // split Th (pair i) with the center moving right: site i = A, site i+1 = S V^dagger
+  auto split_to_right = [&](int i) {
+    const int ml = psi.m[i], mr = psi.m[i + 2];
+    const int k = split_left(W, Th.as<double>(), ml, 2 * mr, p.eps, p.chi_max, A, Cn, &st.discarded);
+    std::swap(psi.t[i], A);
+    std::swap(psi.t[i + 1], Cn);
+    psi.m[i + 1] = k;
+  };
+  // ... with the center moving left: site i = U S, site i+1 = V^dagger
+  auto split_to_left = [&](int i) {
+    const int ml = psi.m[i], mr = psi.m[i + 2];
+    const int k = split_right(W, Th.as<double>(), 2 * ml, mr, p.eps, p.chi_max, A, Cn, &st.discarded);
+    std::swap(psi.t[i], A);
+    std::swap(psi.t[i + 1], Cn);
+    psi.m[i + 1] = k;
+  };
+
+  for (int i = N - 1; i >= 2; --i) build_R(i);
+  // left -> right
+  for (int i = 0; i + 1 < N; ++i) {
+    form_pair(i);
+    if (i + 2 < N) {
+      evolve_pair(i, half);
+      split_to_right(i);
+      build_L(i);
+      evolve_site(i + 1, psi.site(i + 1), -half);
+    } else {
+      evolve_pair(i, dt);  // merged with the first pair of the right-to-left half
+      split_to_left(i);
+      build_R(i + 1);
+    }
+  }
+  // right -> left
+  for (int i = N - 3; i >= 0; --i) {
+    evolve_site(i + 1, psi.site(i + 1), -half);
+    form_pair(i);
+    evolve_pair(i, half);
+    split_to_left(i);
+    build_R(i + 1);
+  }
+  // energy at site 0 (fresh right environment of site 1 exists)
+  {
+    const int ml = psi.m[0], mr = psi.m[1];
+    const long long n = psi.elems(0);
+    ensure_ws((size_t)2 * ml * mr * std::max(H.w(0), H.w(1)));
     W.tmpC.ensure((size_t)n * ZB);
     if (sizeof(T) == 8) {
       heff_apply<T>(ctx, H.tab[0], ml, H.w(0), H.w(1), mr, L[0].p, R[1].p, psi.site(0), W.tmpC.p, W.ws1.p, W.ws2.p);
@@ -947,6 +1137,19 @@ void run_sweep(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp
   } else {
     kern::FloatModeScope mode(kern::float_mode_of(p.prec));
     sweep_impl<float>(ctx, psi, H, p, st);
+  }
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  st.ms = now_ms() - t0;
+}
+
+void run_sweep2(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
+                tdvp_sweep_stats& st) {
+  const double t0 = now_ms();
+  if (p.prec == TDVP_FP64) {
+    sweep2_impl<double>(ctx, psi, H, p, st);
+  } else {
+    kern::FloatModeScope mode(kern::float_mode_of(p.prec));
+    sweep2_impl<float>(ctx, psi, H, p, st);
   }
   HIP_CHECK(hipStreamSynchronize(ctx->stream));
   st.ms = now_ms() - t0;

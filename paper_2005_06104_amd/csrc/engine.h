@@ -36,6 +36,8 @@ std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, co
 
 void run_sweep(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
                tdvp_sweep_stats& st);
+void run_sweep2(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
+                tdvp_sweep_stats& st);
 void run_expand(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const tdvp_expand_params& p,
                 tdvp_expand_stats& st);
 void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, const tdvp_mps_s* other,

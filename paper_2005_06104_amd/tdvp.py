@@ -109,6 +109,8 @@ def load():
         "tdvp_sweep": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_sweep_params),
                            C.POINTER(tdvp_sweep_stats)]),
         "tdvp_measure": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_observables)]),
+        "tdvp_sweep2": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_sweep_params),
+                            C.POINTER(tdvp_sweep_stats)]),
         "tdvp_gemm": (i, [vp, i, i, i, i, i, i, d, d, vp, ll, ll, vp, ll, ll, d, d, vp, ll, ll, i]),
         "tdvp_heff_apply": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp, vp]),
         "tdvp_keff_apply": (i, [vp, i, i, i, i, vp, vp, vp, vp, vp]),
@@ -354,6 +356,18 @@ def tdvp_sweep(ctx: Context, psi: Sequence[MPS], H: Sequence[MPO], dt: complex, 
                           int(krylov_max), PREC[prec], int(bool(normalize)), int(bool(strict)))
     stats = (tdvp_sweep_stats * len(psi))()
     ctx.check(ctx.lib.tdvp_sweep(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats), "tdvp_sweep")
+    return [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
+
+
+def tdvp_sweep2(ctx: Context, psi: Sequence[MPS], H: Sequence[MPO], dt: complex, eps: float = 0.0,
+                chi_max: int = 1 << 30, krylov_tol: float = 1e-12, krylov_max: int = 30, prec: str = "fp64",
+                normalize: bool = False, strict: bool = False) -> List[dict]:
+    """One two-site TDVP sweep (the comparison method); arguments as tdvp_sweep."""
+    dt = complex(dt)
+    p = tdvp_sweep_params(dt.real, dt.imag, float(eps), int(min(chi_max, 2 ** 31 - 1)), float(krylov_tol),
+                          int(krylov_max), PREC[prec], int(bool(normalize)), int(bool(strict)))
+    stats = (tdvp_sweep_stats * len(psi))()
+    ctx.check(ctx.lib.tdvp_sweep2(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats), "tdvp_sweep2")
     return [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
 
 
