@@ -390,13 +390,16 @@ def batch_mode(args):
 
 def kernel_only(args):
     """Short run for hardware-counter passes: H_eff applications at the bench
-    workload's full size (chi = 256, w = 8, FP64) and a plain copy of known size."""
+    workload's full size (chi = 256, w = 8, FP64 by default) and a plain copy
+    of known size.  With --kernel-chi / --kernel-w other sizes (the chi = 1024,
+    w = 20 cylinder shapes) are timed, with the two H_eff GEMM shapes timed
+    apart as well."""
     import numpy as np
     import torch
 
     from paper_2005_06104_amd import inputs as I
     from paper_2005_06104_amd import tdvp as T
-    chi, w = 256, 8
+    chi, w = args.kernel_chi, args.kernel_w
     ctx = T.Context(0)
     dt = torch.complex128 if args.prec in (None, "fp64") else torch.complex64
     kp = None if args.prec in (None, "fp64") else args.prec
@@ -419,6 +422,23 @@ def kernel_only(args):
     ms = e0.elapsed_time(e1) / max(args.steps, 1)
     fl = 8.0 * (2 * chi ** 3 * w * 2 + nnz * chi * chi)
     log(f"kernel-only: H_eff application {ms * 1e3:.1f} us incl. host W upload, {fl / ms / 1e9:.1f} TFLOP/s")
+    # the two GEMM stages alone (the same kernels, launched through tdvp_gemm)
+    peak = PEAK_TFLOPS[args.prec or "fp64"]
+    T1 = torch.empty((chi * w, 2 * chi), dtype=dt, device="cuda")
+    for name, (M_, N_, K_, A_, B_, C_) in {"GEMM1 L.C": (chi * w, 2 * chi, chi, L, Cin, T1),
+                                           "GEMM2 T2.Rt": (2 * chi, chi, w * chi, T1, Rt, Y)}.items():
+        for _ in range(2):
+            T.tdvp_gemm(ctx, 0, 0, M_, N_, K_, 1.0, A_, K_, 0, B_, N_, 0, 0.0, C_, N_, 0, 1, prec=kp)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            T.tdvp_gemm(ctx, 0, 0, M_, N_, K_, 1.0, A_, K_, 0, B_, N_, 0, 0.0, C_, N_, 0, 1, prec=kp)
+        e1.record()
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / max(args.steps, 1)
+        gfl = 8.0 * M_ * N_ * K_
+        log(f"kernel-only: {name} M={M_} N={N_} K={K_}: {gms * 1e3:.1f} us, {gfl / gms / 1e9:.1f} TFLOP/s "
+            f"({100 * gfl / gms / 1e9 / peak:.1f}% of the {args.prec or 'fp64'} peak)")
     src = torch.empty(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -447,6 +467,8 @@ def main():
     ap.add_argument("--batch-serial", action="store_true", help="step the batch one instance per call")
     ap.add_argument("--tdvp2-compare", action="store_true",
                     help="GSE-TDVP1 step against a two-site TDVP step at the same bond dimension")
+    ap.add_argument("--kernel-chi", type=int, default=256)
+    ap.add_argument("--kernel-w", type=int, default=8)
     ap.add_argument("--oat", action="store_true",
                     help="one-axis twisting workload with squeezing moments (section II.B)")
     ap.add_argument("--oat-n", type=int, default=100)

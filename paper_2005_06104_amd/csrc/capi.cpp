@@ -484,13 +484,21 @@ tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, 
     ARG_CHECK(op_a >= 0 && op_a <= 3 && op_b >= 0 && op_b <= 3, "bad op");
     ARG_CHECK(prec >= TDVP_FP64 && prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
     bind(ctx);
+    // split-K scratch for long-K products with few output tiles (freed in
+    // stream order: later work on the stream only)
+    DBuf ws(ctx);
+    size_t wsb = 0;
+    if (batch == 1 && K >= 512 && M > 0 && N > 0) {
+      wsb = (size_t)8 * M * N * (prec == TDVP_FP64 ? 16 : 8);
+      ws.ensure(wsb);
+    }
     if (prec == TDVP_FP64)
       kern::gemm<double>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
-                         zc(beta_re, beta_im), C, ldc, stride_c, batch);
+                         zc(beta_re, beta_im), C, ldc, stride_c, batch, ws.p, wsb);
     else {
       kern::FloatModeScope mode(kern::float_mode_of(prec));
       kern::gemm<float>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
-                        zc(beta_re, beta_im), C, ldc, stride_c, batch);
+                        zc(beta_re, beta_im), C, ldc, stride_c, batch, ws.p, wsb);
     }
   });
 }

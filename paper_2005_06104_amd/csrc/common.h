@@ -92,11 +92,12 @@ struct DBuf {
 // All launches are asynchronous on `s`.  Complex arrays are interleaved.
 namespace kern {
 
-// C = alpha op(A) op(B) + beta C, row-major, batched with element strides.
+// C = alpha op(A) op(B) + beta C, row-major, batched with element strides;
+// ws (may be NULL) is scratch for split-K partial products.
 template <typename T>
 void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
           long long lda, long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
-          long long ldc, long long sc, int batch);
+          long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0);
 
 // The same product (NN, alpha = 1, beta = 0, no batch) as a separate kernel
 // instantiation reserved for the one-site effective Hamiltonian.

@@ -216,6 +216,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
 constexpr int BK2 = 32, BKP2 = BK2 + 8, PL2 = 64 * BKP2;
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
 typedef unsigned short us4 __attribute__((ext_vector_type(4)));
 
 __device__ inline unsigned short bf16_rne(float x) {
@@ -233,16 +234,18 @@ __device__ inline uint4 bf16_neg(uint4 v) {
   return uint4{v.x ^ s, v.y ^ s, v.z ^ s, v.w ^ s};
 }
 
-// A 64 x 32 complex operand tile (rows r = m of A or n of B) as two quads of
-// four consecutive k per thread.  KC: k is the contiguous index in memory.
-template <bool KC, bool CONJ>
+// A ROWS x 32 complex operand tile (rows r = m of A or n of B) as ROWS/32
+// quads of four consecutive k per thread.  KC: k is the contiguous index in
+// memory.  Planes (real, imaginary; and the residual terms with SPLIT) of
+// ROWS x BKP2 bf16 each, k contiguous.
+template <bool KC, bool CONJ, int ROWS = 64>
 __device__ inline void bf_load(const float2* __restrict__ X, long long ld, int r0, int R, int k0, int ke, int tid,
-                               float2 (&v)[2][4]) {
+                               float2 (&v)[ROWS / 32][4]) {
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < ROWS / 32; ++it) {
     const int q = tid + it * NT;
-    const int row = KC ? (q >> 3) : (q & 63);
-    const int kq = KC ? (q & 7) : (q >> 6);
+    const int row = KC ? (q >> 3) : (q % ROWS);
+    const int kq = KC ? (q & 7) : (q / ROWS);
     const int gr = r0 + row;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -257,13 +260,14 @@ __device__ inline void bf_load(const float2* __restrict__ X, long long ld, int r
   }
 }
 
-template <bool KC, int SPLIT>
-__device__ inline void bf_store(unsigned short* P, int tid, const float2 (&v)[2][4]) {
+template <bool KC, int SPLIT, int ROWS = 64>
+__device__ inline void bf_store(unsigned short* P, int tid, const float2 (&v)[ROWS / 32][4]) {
+  constexpr int PL = ROWS * BKP2;
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < ROWS / 32; ++it) {
     const int q = tid + it * NT;
-    const int row = KC ? (q >> 3) : (q & 63);
-    const int kq = KC ? (q & 7) : (q >> 6);
+    const int row = KC ? (q >> 3) : (q % ROWS);
+    const int kq = KC ? (q & 7) : (q / ROWS);
     us4 hr, hi, lr, li;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -276,10 +280,10 @@ __device__ inline void bf_store(unsigned short* P, int tid, const float2 (&v)[2]
     }
     const int off = row * BKP2 + 4 * kq;
     *reinterpret_cast<us4*>(P + off) = hr;
-    *reinterpret_cast<us4*>(P + PL2 + off) = hi;
+    *reinterpret_cast<us4*>(P + PL + off) = hi;
     if (SPLIT) {
-      *reinterpret_cast<us4*>(P + 2 * PL2 + off) = lr;
-      *reinterpret_cast<us4*>(P + 3 * PL2 + off) = li;
+      *reinterpret_cast<us4*>(P + 2 * PL + off) = lr;
+      *reinterpret_cast<us4*>(P + 3 * PL + off) = li;
     }
   }
 }
@@ -521,12 +525,12 @@ void launch_gemm(hipStream_t s, int M, int N, int K, zc alpha, const void* A, lo
 template <typename T, int OA>
 void dispatch_b(hipStream_t s, int opb, int M, int N, int K, zc alpha, const void* A, long long lda,
                 long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
-                long long ldc, long long sc, int batch) {
+                long long ldc, long long sc, int batch, void* ws, size_t wsb) {
   switch (opb) {
-    case TDVP_OP_N: launch_gemm<T, OA, TDVP_OP_N>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
-    case TDVP_OP_T: launch_gemm<T, OA, TDVP_OP_T>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
-    case TDVP_OP_C: launch_gemm<T, OA, TDVP_OP_C>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
-    case TDVP_OP_R: launch_gemm<T, OA, TDVP_OP_R>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_N: launch_gemm<T, OA, TDVP_OP_N>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, wsb); break;
+    case TDVP_OP_T: launch_gemm<T, OA, TDVP_OP_T>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, wsb); break;
+    case TDVP_OP_C: launch_gemm<T, OA, TDVP_OP_C>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, wsb); break;
+    case TDVP_OP_R: launch_gemm<T, OA, TDVP_OP_R>(s, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, wsb); break;
     default: TDVP_THROW(TDVP_ERR_ARG, "bad GEMM op_b");
   }
 }
@@ -772,19 +776,19 @@ int float_mode() { return tl_float_mode; }
 template <typename T>
 void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda,
           long long sa, const void* B, long long ldb, long long sb, zc beta, void* C, long long ldc,
-          long long sc, int batch) {
+          long long sc, int batch, void* ws, size_t ws_bytes) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   switch (opa) {
-    case TDVP_OP_N: dispatch_b<T, TDVP_OP_N>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
-    case TDVP_OP_T: dispatch_b<T, TDVP_OP_T>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
-    case TDVP_OP_C: dispatch_b<T, TDVP_OP_C>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
-    case TDVP_OP_R: dispatch_b<T, TDVP_OP_R>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch); break;
+    case TDVP_OP_N: dispatch_b<T, TDVP_OP_N>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, ws_bytes); break;
+    case TDVP_OP_T: dispatch_b<T, TDVP_OP_T>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, ws_bytes); break;
+    case TDVP_OP_C: dispatch_b<T, TDVP_OP_C>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, ws_bytes); break;
+    case TDVP_OP_R: dispatch_b<T, TDVP_OP_R>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, ws_bytes); break;
     default: TDVP_THROW(TDVP_ERR_ARG, "bad GEMM op_a");
   }
   HIP_CHECK(hipGetLastError());
 }
 template void gemm<double>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
-                           const void*, long long, long long, zc, void*, long long, long long, int);
+                           const void*, long long, long long, zc, void*, long long, long long, int, void*, size_t);
 
 template <typename T>
 void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
@@ -811,7 +815,7 @@ template void gemm_nn_ws<double>(hipStream_t, int, int, int, zc, const void*, lo
 template void gemm_nn_ws<float>(hipStream_t, int, int, int, zc, const void*, long long, const void*, long long, zc,
                                 void*, long long, void*, size_t);
 template void gemm<float>(hipStream_t, int, int, int, int, int, zc, const void*, long long, long long,
-                          const void*, long long, long long, zc, void*, long long, long long, int);
+                          const void*, long long, long long, zc, void*, long long, long long, int, void*, size_t);
 
 template <typename T>
 void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long nP, long long nQ,

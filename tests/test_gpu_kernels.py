@@ -288,3 +288,53 @@ def test_context_close_before_handles():
     assert H.h is None and g.h is None
     del H, g
     gc.collect()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (2, 0), (0, 2), (1, 3)])
+def test_gemm_bf16_large_tiles(env, prec, opa, opb):
+    # products with >= 256 tiles of 128 x 128 take the large-tile kernel;
+    # ragged in every dimension
+    T, torch, ctx = env
+    M, N, K = 2048 + 17, 2048 + 3, 200
+    rng = np.random.default_rng(900 + 4 * opa + opb)
+    ashape = (M, K) if opa in (0, 3) else (K, M)
+    bshape = (K, N) if opb in (0, 3) else (N, K)
+    A = _c64(rng.standard_normal(ashape) + 1j * rng.standard_normal(ashape))
+    B = _c64(rng.standard_normal(bshape) + 1j * rng.standard_normal(bshape))
+    dA, dB = _dev(torch, A, "fp32"), _dev(torch, B, "fp32")
+    dC = _dev(torch, np.zeros((M, N)), "fp32")
+    T.tdvp_gemm(ctx, opa, opb, M, N, K, 1.0, dA, ashape[1], 0, dB, bshape[1], 0, 0.0, dC, N, 0, 1, prec=prec)
+    torch.cuda.synchronize()
+    oA, oB = _op(A, opa), _op(B, opb)
+    ref = oA @ oB
+    err = np.abs(_host(dC) - ref)
+    bound = _bf_bound(prec, K, _mag(oA) @ _mag(oB)) + 2.0 ** -22 * np.abs(ref)
+    assert (err <= bound).all(), (err / bound).max()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3", "fp32", "fp64"])
+def test_gemm_long_k_split(env, prec):
+    # long K with few output tiles: split-K partial products and their reduction
+    T, torch, ctx = env
+    M, N, K = 1024 + 5, 1024 - 7, 4096 + 33
+    rng = np.random.default_rng(77)
+    A = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    p = "fp64" if prec == "fp64" else "fp32"
+    if p == "fp32":
+        A, B = _c64(A), _c64(B)
+    dA, dB = _dev(torch, A, p), _dev(torch, B, p)
+    C0 = _c64(rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N)))
+    dC = _dev(torch, C0, p)
+    alpha, beta = 0.5 + 0.25j, -1.0
+    T.tdvp_gemm(ctx, 0, 0, M, N, K, alpha, dA, K, 0, dB, N, 0, beta, dC, N, 0, 1,
+                prec=None if prec in ("fp64", "fp32") else prec)
+    torch.cuda.synchronize()
+    ref = alpha * (A @ B) + beta * C0
+    err = np.abs(_host(dC) - ref)
+    if prec in ("bf16", "bf16x3"):
+        bound = _bf_bound(prec, K, abs(alpha) * (_mag(A) @ _mag(B))) + 2.0 ** -22 * (np.abs(ref) + np.abs(C0))
+        assert (err <= bound).all(), (err / bound).max()
+    else:
+        assert err.max() / np.abs(ref).max() < TOL[prec] * np.sqrt(K / 256)
