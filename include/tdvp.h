@@ -285,7 +285,7 @@ tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int m
  * (only its Hermitian part is used); rows: device complex128 n x n out, row j
  * is the conjugated eigenvector v_j^dagger for the j-th largest eigenvalue;
  * lam: host double[n] out, descending.  method: 0 automatic (cooperative
- * tridiagonalisation for 128 <= n <= 512, rocSOLVER divide and conquer
+ * tridiagonalisation for 2 <= n <= 512, rocSOLVER divide and conquer
  * otherwise or when the first fails its check), 1 cooperative tridiagonalisation only
  * (TDVP_ERR_NUMERIC when not applicable), 2 rocSOLVER only.  Synchronous. */
 tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows, double* lam);

@@ -294,9 +294,9 @@ void eigh_rows_desc_heevd(tdvp_ctx_s* ctx, const void* H, int n, std::vector<dou
 
 void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows, DBuf& work,
                     int method) {
-  // the cooperative reduction pays from n ~ 128 on; below, a few workgroups
-  // leave most of the chip idle and the library route is as fast
-  const bool try_tridiag = method == EIGH_TRIDIAG || (method == EIGH_AUTO && n >= 128);
+  // the cooperative reduction is at least as fast as the library route for
+  // every size it supports (n <= 512)
+  const bool try_tridiag = method == EIGH_TRIDIAG || method == EIGH_AUTO;
   if (try_tridiag && eigh_rows_desc_tridiag(ctx, H, n, lam, rows, work)) return;
   if (method == EIGH_TRIDIAG) TDVP_THROW(TDVP_ERR_NUMERIC, "cooperative tridiagonal eigensolver not applicable");
   eigh_rows_desc_heevd(ctx, H, n, lam, rows, work);
