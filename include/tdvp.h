@@ -285,9 +285,11 @@ tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int m
  * (only its Hermitian part is used); rows: device complex128 n x n out, row j
  * is the conjugated eigenvector v_j^dagger for the j-th largest eigenvalue;
  * lam: host double[n] out, descending.  method: 0 automatic (cooperative
- * tridiagonalisation for 2 <= n <= 512, rocSOLVER divide and conquer
- * otherwise or when the first fails its check), 1 cooperative tridiagonalisation only
- * (TDVP_ERR_NUMERIC when not applicable), 2 rocSOLVER only.  Synchronous. */
+ * tridiagonalisation and tridiagonal divide and conquer for 2 <= n <= 512,
+ * rocSOLVER zheevd otherwise or when the first fails its check), 1 the
+ * first only (TDVP_ERR_NUMERIC when not applicable), 2 rocSOLVER zheevd
+ * only, 3 cooperative tridiagonalisation with rocSOLVER's tridiagonal divide
+ * and conquer (TDVP_ERR_NUMERIC when not applicable).  Synchronous. */
 tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows, double* lam);
 
 /* Wait for all work issued on the context's stream. */

@@ -62,6 +62,11 @@ void tdvp_ctx_s::ensure_workers(int n) {
 void tdvp_ctx_s::destroy_workers() {
   for (tdvp_ctx_s* w : workers) {
     if (w->stream) (void)hipStreamSynchronize(w->stream);
+    w->dfree(w->split_ws);
+    if (w->stream) (void)hipStreamSynchronize(w->stream);
+    if (w->hstage) (void)hipHostFree(w->hstage);
+    for (hipEvent_t e : w->ev_stage)
+      if (e) (void)hipEventDestroy(e);
     if (w->ev_a) (void)hipEventDestroy(w->ev_a);
     if (w->ev_b) (void)hipEventDestroy(w->ev_b);
     if (w->ev_c) (void)hipEventDestroy(w->ev_c);
@@ -74,6 +79,26 @@ void tdvp_ctx_s::destroy_workers() {
 }
 
 void tdvp_ctx_s::sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
+
+const void* tdvp_ctx_s::fetch(const void* dev, size_t bytes) {
+  if (bytes > HSTAGE_BYTES / 2) TDVP_THROW(TDVP_ERR_ARG, "staged download too large");
+  if (!hstage) HIP_CHECK(hipHostMalloc(&hstage, HSTAGE_BYTES, hipHostMallocDefault));
+  HIP_CHECK(hipMemcpyAsync(hstage, dev, bytes, hipMemcpyDeviceToHost, stream));
+  HIP_CHECK(hipStreamSynchronize(stream));
+  return hstage;
+}
+
+const void* tdvp_ctx_s::stage_async(int k, const void* dev, size_t bytes) {
+  if (bytes > HSTAGE_BYTES / 4 || k < 0 || k > 1) TDVP_THROW(TDVP_ERR_ARG, "staged download too large");
+  if (!hstage) HIP_CHECK(hipHostMalloc(&hstage, HSTAGE_BYTES, hipHostMallocDefault));
+  if (!ev_stage[k]) HIP_CHECK(hipEventCreateWithFlags(&ev_stage[k], hipEventDisableTiming));
+  char* slot = static_cast<char*>(hstage) + HSTAGE_BYTES / 2 + (size_t)k * (HSTAGE_BYTES / 4);
+  HIP_CHECK(hipMemcpyAsync(slot, dev, bytes, hipMemcpyDeviceToHost, stream));
+  HIP_CHECK(hipEventRecord(ev_stage[k], stream));
+  return slot;
+}
+
+void tdvp_ctx_s::wait_stage(int k) { HIP_CHECK(hipEventSynchronize(ev_stage[k])); }
 
 namespace {
 
@@ -228,6 +253,11 @@ void tdvp_ctx_destroy(tdvp_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->destroy_workers();
+  ctx->dfree(ctx->split_ws);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->hstage) (void)hipHostFree(ctx->hstage);
+  for (hipEvent_t e : ctx->ev_stage)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
   if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
   if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
@@ -484,21 +514,15 @@ tdvp_status tdvp_gemm(tdvp_ctx ctx, int prec, int op_a, int op_b, int M, int N, 
     ARG_CHECK(op_a >= 0 && op_a <= 3 && op_b >= 0 && op_b <= 3, "bad op");
     ARG_CHECK(prec >= TDVP_FP64 && prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
     bind(ctx);
-    // split-K scratch for long-K products with few output tiles (freed in
-    // stream order: later work on the stream only)
-    DBuf ws(ctx);
-    size_t wsb = 0;
-    if (batch == 1 && K >= 512 && M > 0 && N > 0) {
-      wsb = (size_t)8 * M * N * (prec == TDVP_FP64 ? 16 : 8);
-      ws.ensure(wsb);
-    }
+    // split-K scratch for long-K products with few output tiles
+    kern::SplitWorkspaceScope gws(ctx->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES);
     if (prec == TDVP_FP64)
       kern::gemm<double>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
-                         zc(beta_re, beta_im), C, ldc, stride_c, batch, ws.p, wsb);
+                         zc(beta_re, beta_im), C, ldc, stride_c, batch);
     else {
       kern::FloatModeScope mode(kern::float_mode_of(prec));
       kern::gemm<float>(ctx->stream, op_a, op_b, M, N, K, zc(alpha_re, alpha_im), A, lda, stride_a, B, ldb, stride_b,
-                        zc(beta_re, beta_im), C, ldc, stride_c, batch, ws.p, wsb);
+                        zc(beta_re, beta_im), C, ldc, stride_c, batch);
     }
   });
 }
@@ -508,8 +532,9 @@ tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows
   if (!ctx) return TDVP_ERR_ARG;
   return guarded(ctx, [&] {
     ARG_CHECK(n >= 1 && H && rows && lam, "bad arguments");
-    ARG_CHECK(method >= la::EIGH_AUTO && method <= la::EIGH_HEEVD, "unknown method");
+    ARG_CHECK(method >= la::EIGH_AUTO && method <= la::EIGH_TRIDIAG_LIB, "unknown method");
     bind(ctx);
+    kern::SplitWorkspaceScope gws(ctx->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES);
     DBuf work(ctx);
     std::vector<double> w;
     la::eigh_rows_desc(ctx, H, n, w, rows, work, method);

@@ -47,6 +47,28 @@ struct tdvp_ctx_s {
   bool owns_stream = false;
   bool async_alloc = false;
   std::vector<tdvp_ctx_s*> workers;
+  // Split-K partial products of the GEMMs issued for this context: one
+  // buffer of SPLIT_WS_BYTES, allocated on first use, freed with the context.
+  // Work on the context's stream is ordered, so every product may reuse it.
+  static constexpr size_t SPLIT_WS_BYTES = size_t(32) << 20;
+  void* split_ws = nullptr;
+  void* split_workspace() {
+    if (!split_ws) split_ws = dalloc(SPLIT_WS_BYTES);
+    return split_ws;
+  }
+  // Pinned host staging for the small results the host branches on (Lanczos
+  // coefficients, eigenvalues, check flags): one DMA copy instead of a staged
+  // pageable one.  Allocated on first use, freed with the context.
+  static constexpr size_t HSTAGE_BYTES = size_t(64) << 10;
+  void* hstage = nullptr;
+  // copy `bytes` (<= HSTAGE_BYTES / 2) from device memory, wait, return the host copy
+  const void* fetch(const void* dev, size_t bytes);
+  // Asynchronous variant into slot k (0 or 1, each HSTAGE_BYTES / 4, apart
+  // from fetch's region): stage_async enqueues the copy and returns where it
+  // lands; wait_stage(k) blocks until it has.
+  hipEvent_t ev_stage[2] = {nullptr, nullptr};
+  const void* stage_async(int k, const void* dev, size_t bytes);
+  void wait_stage(int k);
 
   void* dalloc(size_t bytes);
   void dfree(void* p);
@@ -99,6 +121,18 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
           long long lda, long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
           long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0);
 
+// Split-K scratch used by gemm() calls from the calling host thread that
+// pass no ws of their own (NULL: none, products run unsplit).
+void set_split_workspace(void* p, size_t bytes);
+struct SplitWorkspaceScope {
+  void* saved_p;
+  size_t saved_b;
+  SplitWorkspaceScope(void* p, size_t bytes);
+  ~SplitWorkspaceScope();
+  SplitWorkspaceScope(const SplitWorkspaceScope&) = delete;
+  SplitWorkspaceScope& operator=(const SplitWorkspaceScope&) = delete;
+};
+
 // The same product (NN, alpha = 1, beta = 0, no batch) as a separate kernel
 // instantiation reserved for the one-site effective Hamiltonian.
 // ws (may be NULL) is scratch for split-K partial products.
@@ -113,6 +147,12 @@ void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda,
 int tridiag_groups(int n);
 size_t tridiag_scratch_bytes(int n);
 hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err);
+// Eigen-decomposition of the real symmetric tridiagonal matrix (diagonal D[n],
+// off-diagonal E[n-1]; 1 <= n <= 512) by divide and conquer: on return D holds
+// the eigenvalues ascending and Z (column-major n x n) the eigenvectors.
+// scratch holds tridiag_eig_scratch_bytes(n).  Returns the launch status.
+size_t tridiag_eig_scratch_bytes(int n);
+hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double* Z, void* scratch);
 // out[j][m] = Z[m][n-1-j] (complex), Z column-major real n x n
 void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n);
 // Arithmetic of the complex64 GEMMs issued from the calling host thread:
@@ -156,9 +196,19 @@ void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long
 void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n,
            void* partial, int n_partial_blocks, void* out, bool conjugate = true);
 int zdots_blocks(long long n);
+// The conjugated dot products of zdots in one launch: the block that finishes
+// last adds the partial sums in block order.  counter: a device unsigned that
+// is zero before the call and is left at zero.
+void zdots_fused(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
+                 int n_partial_blocks, unsigned* counter, void* out);
 // w[x] += sign * sum_j c[j] V[j*ldv + x]   (c complex128 on device)
 void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c,
               double sign, long long n);
+// zcombine, then out[0] = |w|^2 (real part) in the same launch; partial holds
+// zcombine_norm_blocks(n) complex entries, counter as for zdots_fused
+int zcombine_norm_blocks(long long n);
+void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
+                   long long n, void* partial, unsigned* counter, void* out);
 // dst = a * src (complex scalar a)
 void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n);
 // precision conversions (complex)
@@ -177,6 +227,8 @@ void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long l
 void zhermitize(hipStream_t s, void* A, long long n);
 // fill complex with value
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
+// w /= sqrt(Re nrm2[0]) with nrm2 on the device (complex128)
+void zscale_invnorm(hipStream_t s, void* w, const void* nrm2, long long n);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
 // G = a G + b I (n x n complex128)
@@ -212,14 +264,19 @@ void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, s
                   void* Vh, DBuf& work, DBuf& work2);
 // eigh of row-major Hermitian H (n x n): eigenvalues descending (host) and the
 // matrix of eigenvectors-as-rows-conjugated: rows[j] = v_j^dagger (row-major n x n).
-// method: EIGH_AUTO (cooperative tridiagonalisation for 128 <= n <= 512,
-// rocSOLVER divide and conquer otherwise or when the first fails validation),
-// EIGH_TRIDIAG (the first only), EIGH_HEEVD (rocSOLVER only).
-enum { EIGH_AUTO = 0, EIGH_TRIDIAG = 1, EIGH_HEEVD = 2 };
+// method: EIGH_AUTO (cooperative tridiagonalisation and tridiagonal divide
+// and conquer for 2 <= n <= 512, rocSOLVER zheevd otherwise or when the first
+// fails validation), EIGH_TRIDIAG (the first only), EIGH_HEEVD (rocSOLVER
+// only), EIGH_TRIDIAG_LIB (cooperative tridiagonalisation, rocSOLVER dstedc).
+enum { EIGH_AUTO = 0, EIGH_TRIDIAG = 1, EIGH_HEEVD = 2, EIGH_TRIDIAG_LIB = 3 };
 void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows,
                     DBuf& work, int method = EIGH_AUTO);
-// host: eigen-decomposition of a small real symmetric matrix (Jacobi), ascending
-void jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V);
+// host: eigenvalues of the small symmetric tridiagonal matrix (diagonal d[n],
+// off-diagonal e[0..n-2]; e[n-1] is scratch) by implicit QL, returned in d
+// (unordered); each of the nr rows of Zr (nr x n, row-major) is multiplied by
+// the eigenvector matrix, so rows of the identity give rows of it.  False when
+// an eigenvalue needs more than 60 sweeps.
+bool tridiag_ql(double* d, double* e, int n, double* Zr, int nr);
 }  // namespace la
 
 // truncation rule (same definition as the oracle's keep_count)

@@ -62,6 +62,8 @@ __device__ inline void bar_arrive(const TdArgs& a, unsigned epoch) {
   if (threadIdx.x == 0)
     __hip_atomic_store(&a.flags[blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// wave 0 polls the flags with relaxed loads and orders the later reads of
+// the published data by one acquire fence once every flag has arrived
 __device__ inline bool bar_wait(const TdArgs& a, unsigned epoch, int* s_fail) {
   if (threadIdx.x < 64) {
     unsigned polls = 0;
@@ -69,7 +71,7 @@ __device__ inline bool bar_wait(const TdArgs& a, unsigned epoch, int* s_fail) {
     while (true) {
       bool mine = true;
       for (int j = threadIdx.x; j < a.G; j += 64)
-        mine = mine && (__hip_atomic_load(&a.flags[j * FLAG_STRIDE], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= epoch);
+        mine = mine && (__hip_atomic_load(&a.flags[j * FLAG_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch);
       if (__all(mine)) break;
       if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++polls > SPIN_LIMIT) {
         fail = true;
@@ -77,6 +79,7 @@ __device__ inline bool bar_wait(const TdArgs& a, unsigned epoch, int* s_fail) {
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (threadIdx.x == 0) {
       if (fail) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       *s_fail = fail ? 1 : 0;
@@ -86,20 +89,49 @@ __device__ inline bool bar_wait(const TdArgs& a, unsigned epoch, int* s_fail) {
   return *s_fail == 0;
 }
 
+// Reflector of column k from the pivot row: alpha = conj(row[k+1]),
+// x = conj(row[k+2:]) with |x|^2 = xn2.  Every thread of every workgroup
+// evaluates it with the same operands in the same order, so all agree bit
+// for bit.  tau = sc = 0 (H_k = I) when the column is already reduced.
+struct Reflector {
+  double2 tau, sc;
+  double beta;
+};
+__device__ inline Reflector reflector(double2 row_k1, double xn2) {
+  const double2 al{row_k1.x, -row_k1.y};
+  Reflector r;
+  if (xn2 == 0.0 && al.y == 0.0) {
+    r.beta = al.x;
+    r.tau = r.sc = double2{0.0, 0.0};
+  } else {
+    const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+    r.beta = al.x >= 0.0 ? -nrm : nrm;
+    r.tau = double2{(r.beta - al.x) / r.beta, -al.y / r.beta};
+    const double dr = al.x - r.beta, di = al.y;   // sc = 1 / (alpha - beta)
+    const double den = dr * dr + di * di;
+    r.sc = double2{dr / den, -di / den};
+  }
+  return r;
+}
+
+// component c >= k+1 of the Householder vector (v_{k+1} = 1)
+__device__ inline double2 hh_v(int c, int k, double2 row_c, double2 sc) {
+  return c == k + 1 ? double2{1.0, 0.0} : cmul(double2{row_c.x, -row_c.y}, sc);
+}
+
 // One grid barrier per column.  Every workgroup holds the current pivot row k
 // (row k of the partly reduced matrix; column k below the diagonal is its
-// conjugate) and derives the reflector H_k from it with the same arithmetic,
-// so all workgroups agree bit for bit.  The barrier gathers x = tau A v from
-// the row owners; the owner of row k+1 also publishes that row, from which
-// every workgroup forms the next pivot row by the rank-2 update.  Published
-// buffers alternate between two copies: a workgroup can be one barrier ahead
-// of the slowest one.
+// conjugate) and derives the reflector H_k from it.  The barrier gathers
+// x = tau A v from the row owners; the owner of row k+1 also publishes that
+// row, from which every workgroup forms the next pivot row by the rank-2
+// update (and, in the same pass, the norm that the next reflector needs).
+// Published buffers alternate between two copies: a workgroup can be one
+// barrier ahead of the slowest one.
 __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
   __shared__ double2 sM[TD_LDS];        // A rows [R][n], then Q rows [R][n]
   __shared__ double2 sv[TD_NMAX], sw[TD_NMAX], srow[TD_NMAX];
-  __shared__ double2 sred[TNT / 64];
+  __shared__ double sred[TNT / 64];     // per-wave |row[k+2:]|^2 of the pivot row
   __shared__ double2 s_part[TD_ROWS];
-  __shared__ double s_tau_r, s_tau_i, s_sc_r, s_sc_i, s_a2_r, s_a2_i;
   __shared__ int s_fail;
 
   const int n = a.n, G = a.G, R = a.R, g = blockIdx.x, tid = threadIdx.x;
@@ -113,7 +145,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
   while (T > 1 && T * R > TNT) T >>= 1;
   const int rj = tid / T, rt = tid % T;
 
-  // own rows, Q = I, pivot row 0
+  // own rows, Q = I, pivot row 0 and its norm beyond column 1
   for (int j = 0; j < nrow; ++j) {
     const int r = g + j * G;
     for (int c = tid; c < n; c += TNT) {
@@ -121,52 +153,36 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       sQ[j * n + c] = double2{r == c ? 1.0 : 0.0, 0.0};
     }
   }
-  for (int c = tid; c < n; c += TNT) srow[c] = a.H[c];
+  {
+    double ssq = 0.0;
+    for (int c = tid; c < n; c += TNT) {
+      const double2 h = a.H[c];
+      srow[c] = h;
+      if (c >= 2) ssq += h.x * h.x + h.y * h.y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o);
+    if (lane == 0) sred[wave] = ssq;
+  }
   __syncthreads();
 
   unsigned epoch = 0;
   bool alive = true;
   for (int k = 0; k + 1 < n; ++k) {
     const int par = k & 1;
-    // ---- reflector from the pivot row: alpha = conj(row[k+1]), x = conj(row[k+2:])
-    double ssq = 0.0;
-    for (int c = k + 2 + tid; c < n; c += TNT) ssq += srow[c].x * srow[c].x + srow[c].y * srow[c].y;
+    double xn2 = 0.0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o);
-    if (lane == 0) sred[wave].x = ssq;
-    __syncthreads();
-    if (tid == 0) {
-      double xn2 = 0.0;
-      for (int w = 0; w < TNT / 64; ++w) xn2 += sred[w].x;
-      const double2 al{srow[k + 1].x, -srow[k + 1].y};
-      double beta;
-      if (xn2 == 0.0 && al.y == 0.0) {
-        // already reduced: H_k = I (tau = 0 makes every update below vanish)
-        beta = al.x;
-        s_tau_r = s_tau_i = s_sc_r = s_sc_i = 0.0;
-      } else {
-        const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
-        beta = al.x >= 0.0 ? -nrm : nrm;
-        s_tau_r = (beta - al.x) / beta;
-        s_tau_i = -al.y / beta;
-        const double dr = al.x - beta, di = al.y;   // scale = 1 / (alpha - beta)
-        const double den = dr * dr + di * di;
-        s_sc_r = dr / den;
-        s_sc_i = -di / den;
-      }
-      if (g == 0) {
-        a.D[k] = srow[k].x;
-        a.E[k] = beta;
-      }
+    for (int w = 0; w < TNT / 64; ++w) xn2 += sred[w];
+    const Reflector hr = reflector(srow[k + 1], xn2);
+    const double2 tau = hr.tau, sc = hr.sc;
+    if (g == 0 && tid == 0) {
+      a.D[k] = srow[k].x;
+      a.E[k] = hr.beta;
     }
-    __syncthreads();
-    const double2 tau{s_tau_r, s_tau_i}, sc{s_sc_r, s_sc_i};
-    for (int c = k + 1 + tid; c < n; c += TNT)
-      sv[c] = (c == k + 1) ? double2{1.0, 0.0} : cmul(double2{srow[c].x, -srow[c].y}, sc);
-    __syncthreads();
 
     // ---- one pass over the own rows (T threads per row): x = tau A v for
     // rows >= k+1 and tau (Q v) for the accumulation of Q; partial x^H v.
+    // v is formed on the fly (the threads of local row 0 also store it).
     // The owner of row k+1 publishes it (before this column's update).
     double2* xvp = a.xv + (size_t)par * n;
     double2* rowp = a.prow + (size_t)par * n;
@@ -177,7 +193,8 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       const double2* arow = sA + rj * n;
       const double2* qrow = sQ + rj * n;
       for (int c = k + 1 + rt; c < n; c += T) {
-        const double2 v = sv[c], m = arow[c], q = qrow[c];
+        const double2 v = hh_v(c, k, srow[c], sc), m = arow[c], q = qrow[c];
+        if (rj == 0) sv[c] = v;
         sa.x += m.x * v.x - m.y * v.y;
         sa.y += m.x * v.y + m.y * v.x;
         sq.x += q.x * v.x - q.y * v.y;
@@ -194,7 +211,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       if (rt == 0) {
         double2 contrib{0.0, 0.0};
         if (r >= k + 1) {
-          const double2 x = cmul(tau, sa), vr = sv[r];
+          const double2 x = cmul(tau, sa), vr = hh_v(r, k, srow[r], sc);
           xvp[r] = x;
           contrib = double2{x.x * vr.x + x.y * vr.y, x.x * vr.y - x.y * vr.x};   // conj(x) v
         }
@@ -230,7 +247,8 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       break;
     }
 
-    // ---- w = x - (tau/2)(x^H v) v; next pivot row; A <- A - v w^H - w v^H
+    // ---- w = x - (tau/2)(x^H v) v; next pivot row and its norm beyond
+    // column k+2; A <- A - v w^H - w v^H on the own rows
     {
       double2 xq[(TD_NMAX + TNT - 1) / TNT], rq[(TD_NMAX + TNT - 1) / TNT];
 #pragma unroll
@@ -239,35 +257,35 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         xq[q] = c < n ? xvp[c] : double2{0.0, 0.0};
         rq[q] = c < n ? rowp[c] : double2{0.0, 0.0};
       }
-      if (wave == 0) {
-        double2 t = lane < G ? p2p[lane] : double2{0.0, 0.0};
-        t = wave_sum(t);
-        if (lane == 0) {
-          const double2 a2 = cmul(tau, t);
-          s_a2_r = -0.5 * a2.x;
-          s_a2_i = -0.5 * a2.y;
-        }
-      }
-      __syncthreads();
-      const double2 a2{s_a2_r, s_a2_i};
+      // x^H v: every wave sums the published partials in the same order
+      double2 t = lane < G ? p2p[lane] : double2{0.0, 0.0};
+      t = wave_sum(t);
+      const double2 a2x = cmul(tau, t);
+      const double2 a2{-0.5 * a2x.x, -0.5 * a2x.y};
 #pragma unroll
       for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
         const int c = k + 1 + tid + q * TNT;
         if (c < n) {
-          const double2 t = cmul(a2, sv[c]);
-          sw[c] = double2{xq[q].x + t.x, xq[q].y + t.y};
+          const double2 tv = cmul(a2, sv[c]);
+          sw[c] = double2{xq[q].x + tv.x, xq[q].y + tv.y};
         }
       }
       __syncthreads();
       const double2 v1 = sv[k + 1], w1 = sw[k + 1];
+      double ssq = 0.0;
 #pragma unroll
       for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
         const int c = k + 1 + tid + q * TNT;
         if (c < n) {
           const double2 d1 = cmulc(v1, sw[c]), d2 = cmulc(w1, sv[c]);
-          srow[c] = double2{rq[q].x - (d1.x + d2.x), rq[q].y - (d1.y + d2.y)};
+          const double2 nr{rq[q].x - (d1.x + d2.x), rq[q].y - (d1.y + d2.y)};
+          srow[c] = nr;
+          if (c >= k + 3) ssq += nr.x * nr.x + nr.y * nr.y;
         }
       }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o);
+      if (lane == 0) sred[wave] = ssq;
     }
     if (rj < nrow && g + rj * G >= k + 2) {   // rows <= k+1 are finished
       const int r = g + rj * G;

@@ -49,10 +49,7 @@ struct Scalars {
     partial.ensure((size_t)nb * ZB);
     out.ensure(ZB);
     kern::zdots(ctx->stream, a, n, 1, b, n, partial.p, nb, out.p, conj);
-    zc r;
-    download(ctx, &r, out.p, ZB);
-    HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    return r;
+    return *static_cast<const zc*>(ctx->fetch(out.p, ZB));
   }
   double norm(const void* a, long long n) { return std::sqrt(std::max(0.0, dot(a, a, n).real())); }
 };
@@ -71,70 +68,99 @@ struct Lanczos {
     *unconv = false;
     if (n <= 0) return 0;
     const int nb = kern::zdots_blocks(n);
-    partial.ensure((size_t)nb * (maxit + 1) * ZB);
+    partial.ensure((size_t)std::max<long long>((long long)nb * (maxit + 1), kern::zcombine_norm_blocks(n)) * ZB);
     scal.ensure(256 * ZB);
     double2* S = scal.as<double2>();
+    // S: [0, 64) and [64, 128) the two projection passes, 128 |w|^2, 192.. the
+    // result coefficients, 255 the completion counter of the fused reductions
+    unsigned* counter = reinterpret_cast<unsigned*>(S + 255);
+    kern::zfill(ctx->stream, S + 255, zc(0.0, 0.0), 1, ZB);
     char* Vb = static_cast<char*>(V.ensure((size_t)(maxit + 1) * n * ZB));
     auto vec = [&](int j) { return static_cast<void*>(Vb + (size_t)j * n * ZB); };
 
     kern::zdots(ctx->stream, x, n, 1, x, n, partial.p, nb, S + 128);
-    zc nrm2;
-    download(ctx, &nrm2, S + 128, ZB);
-    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    const zc nrm2 = *static_cast<const zc*>(ctx->fetch(S + 128, ZB));
     const double nrm = std::sqrt(std::max(0.0, nrm2.real()));
     if (!(nrm > 0.0)) {
       if (!std::isfinite(nrm)) TDVP_THROW(TDVP_ERR_NUMERIC, "non-finite vector entering Lanczos");
       return 0;
     }
     kern::zscale(ctx->stream, vec(0), x, zc(1.0 / nrm, 0.0), n);
-    std::vector<double> alpha, beta, Tm, lam, Q;
+    std::vector<double> alpha, beta, dd, ee, Z;
     std::vector<zc> c;
     int napp = 0, dim = 0;
-    for (int j = 0; j < maxit; ++j) {
+    // exp(-i dt T) e_1 from the eigen-decomposition T = Z diag(l) Z^T of the
+    // Lanczos matrix: component r is sum_e Z[r][e] exp(-i dt l_e) Z[0][e]
+    auto tridiag_eig = [&](int nr) {
+      dd = alpha;
+      ee.assign(dim, 0.0);
+      for (int i = 0; i + 1 < dim; ++i) ee[i] = beta[i];
+      Z.assign((size_t)nr * dim, 0.0);
+      if (nr == dim) {
+        for (int r = 0; r < dim; ++r) Z[(size_t)r * dim + r] = 1.0;
+      } else {   // rows 0 and dim-1 only
+        Z[0] = 1.0;
+        Z[(size_t)(nr - 1) * dim + dim - 1] = 1.0;
+      }
+      if (!la::tridiag_ql(dd.data(), ee.data(), dim, Z.data(), nr))
+        TDVP_THROW(TDVP_ERR_NUMERIC, "Lanczos tridiagonal eigensolver did not converge");
+    };
+    auto phase = [&](int e) { return std::exp(zc(0.0, -1.0) * dt * dd[e]); };
+    // Iteration j on the device: w = H v_j, classical Gram-Schmidt twice
+    // against v_0..v_j, |w|^2, an asynchronous copy of the scalars to the
+    // host, and v_{j+1} = w / |w| with the norm read on the device.  The next
+    // iteration is enqueued before the host reads this one's scalars, so the
+    // device never waits for the convergence test; when the test stops the
+    // recurrence, the one extra iteration is discarded.
+    const zc* staged[2] = {nullptr, nullptr};
+    auto enqueue = [&](int j) {
       void* w = vec(j + 1);
+      if (timer) timer->cur = j & 1;
       mv(vec(j), w);
-      ++napp;
-      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S);
+      kern::zdots_fused(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, counter, S);
       kern::zcombine(ctx->stream, w, Vb, n, j + 1, S, -1.0, n);
-      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S + 64);
-      kern::zcombine(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n);
-      kern::zdots(ctx->stream, w, n, 1, w, n, partial.p, nb, S + 128);
-      zc hv[2];
-      download(ctx, &hv[0], S + j, ZB);
-      download(ctx, &hv[1], S + 128, ZB);
-      HIP_CHECK(hipStreamSynchronize(ctx->stream));
-      if (timer) timer->collect();
-      const double a = hv[0].real(), b = std::sqrt(std::max(0.0, hv[1].real()));
+      kern::zdots_fused(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, counter, S + 64);
+      kern::zcombine_norm(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n, partial.p, counter, S + 128);
+      // the first-pass projections (alpha_j = <v_j|H v_j>) and |w|^2
+      staged[j & 1] = static_cast<const zc*>(ctx->stage_async(j & 1, S, 129 * ZB));
+      kern::zscale_invnorm(ctx->stream, w, S + 128, n);
+    };
+    enqueue(0);
+    for (int j = 0; j < maxit; ++j) {
+      if (j + 1 < maxit) enqueue(j + 1);
+      ctx->wait_stage(j & 1);
+      const zc* hv = staged[j & 1];
+      if (timer) timer->collect(j & 1);
+      ++napp;
+      const double a = hv[j].real(), b = std::sqrt(std::max(0.0, hv[128].real()));
       if (!std::isfinite(a) || !std::isfinite(b)) TDVP_THROW(TDVP_ERR_NUMERIC, "non-finite Lanczos coefficient");
       alpha.push_back(a);
       dim = j + 1;
-      Tm.assign((size_t)dim * dim, 0.0);
-      for (int i = 0; i < dim; ++i) Tm[(size_t)i * dim + i] = alpha[i];
-      for (int i = 0; i + 1 < dim; ++i) {
-        Tm[(size_t)i * dim + i + 1] = beta[i];
-        Tm[(size_t)(i + 1) * dim + i] = beta[i];
+      // convergence needs |exp(-i dt T) e_1| and its last component only
+      const int nr = dim == 1 ? 1 : 2;
+      tridiag_eig(nr);
+      double cn2 = 0.0;
+      zc clast(0.0, 0.0);
+      for (int e = 0; e < dim; ++e) {
+        const zc ph = phase(e) * Z[e];
+        cn2 += std::norm(ph);
+        clast += Z[(size_t)(nr - 1) * dim + e] * ph;
       }
-      la::jacobi_eigh(Tm, dim, lam, Q);
-      c.assign(dim, zc(0.0, 0.0));
-      for (int r = 0; r < dim; ++r) {
-        zc acc(0.0, 0.0);
-        for (int e = 0; e < dim; ++e)
-          acc += Q[(size_t)r * dim + e] * std::exp(zc(0.0, -1.0) * dt * lam[e]) * Q[(size_t)0 * dim + e];
-        c[r] = acc;
-      }
-      double cn = 0.0;
-      for (const zc& v : c) cn += std::norm(v);
-      cn = std::sqrt(cn);
       double scale = 0.0;
       for (double v : alpha) scale = std::max(scale, std::fabs(v));
       for (double v : beta) scale = std::max(scale, v);
-      const bool conv = b * std::abs(c[dim - 1]) <= tol * cn || b <= 1e-14 * scale;
+      const bool conv = b * std::abs(clast) <= tol * std::sqrt(cn2) || b <= 1e-14 * scale;
       if (conv || j == maxit - 1) {
         if (!conv) *unconv = true;
         break;
       }
       beta.push_back(b);
-      kern::zscale(ctx->stream, w, w, zc(1.0 / b, 0.0), n);
+    }
+    tridiag_eig(dim);
+    c.assign(dim, zc(0.0, 0.0));
+    for (int e = 0; e < dim; ++e) {
+      const zc ph = phase(e) * Z[e];
+      for (int r = 0; r < dim; ++r) c[r] += Z[(size_t)r * dim + e] * ph;
     }
     double f = nrm;
     if (normalize) {
@@ -148,6 +174,7 @@ struct Lanczos {
     kern::zfill(ctx->stream, x, zc(0.0, 0.0), n, ZB);
     kern::zcombine(ctx->stream, x, Vb, n, dim, S + 192, 1.0, n);
     HIP_CHECK(hipStreamSynchronize(ctx->stream));  // `cs` is pageable host memory
+    if (timer) timer->collect_all();                // the discarded iteration ran too
     return napp;
   }
 };
@@ -351,11 +378,12 @@ namespace {
 
 struct Work {
   tdvp_ctx_s* ctx;
+  kern::SplitWorkspaceScope gws;   // split-K scratch of the products issued below
   DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst;
   Scalars sc;
   Lanczos lz;
   explicit Work(tdvp_ctx_s* c)
-      : ctx(c), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
+      : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
         dvec(c), wsk(c), nsg(c), nst(c), sc(c), lz(c) {}
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {

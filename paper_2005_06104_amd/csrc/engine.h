@@ -46,26 +46,46 @@ void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, co
 // HIP-event timing of the one-site effective Hamiltonian: marks 0..3 bracket
 // the first GEMM (0-1), the MPO contraction (1-2) and the second GEMM (2-3).
 struct MatvecTimer {
+  // HIP events around the two GEMM stages of each H_eff application, in two
+  // sets: the Lanczos recurrence enqueues the next application before it
+  // reads back the current one, so consecutive applications alternate sets.
   tdvp_ctx_s* ctx = nullptr;
-  bool on = false, pending = false;
+  bool on = false;
+  int cur = 0;                      // set the next application records into
+  bool pending[2] = {false, false};
+  hipEvent_t ev[2][4] = {};
   double ms = 0.0, gemm_ms = 0.0, gemm_flops = 0.0;
   long long n_gemm = 0;
+  MatvecTimer() = default;
+  MatvecTimer(const MatvecTimer&) = delete;
+  MatvecTimer& operator=(const MatvecTimer&) = delete;
+  ~MatvecTimer() {
+    for (auto& set : ev)
+      for (hipEvent_t& e : set)
+        if (e) (void)hipEventDestroy(e);
+  }
   void mark(int k) {
     if (!on) return;
-    hipEvent_t e = k == 0 ? ctx->ev_a : k == 1 ? ctx->ev_b : k == 2 ? ctx->ev_c : ctx->ev_d;
-    HIP_CHECK(hipEventRecord(e, ctx->stream));
-    if (k == 3) pending = true;
+    if (!ev[cur][k]) HIP_CHECK(hipEventCreate(&ev[cur][k]));
+    HIP_CHECK(hipEventRecord(ev[cur][k], ctx->stream));
+    if (k == 3) pending[cur] = true;
   }
-  void collect() {
-    if (!pending) return;
+  // accumulate set `k` (its events must have completed)
+  void collect(int k) {
+    if (!pending[k]) return;
     float t = 0.f, g1 = 0.f, g2 = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&t, ctx->ev_a, ctx->ev_d));
-    HIP_CHECK(hipEventElapsedTime(&g1, ctx->ev_a, ctx->ev_b));
-    HIP_CHECK(hipEventElapsedTime(&g2, ctx->ev_c, ctx->ev_d));
+    HIP_CHECK(hipEventElapsedTime(&t, ev[k][0], ev[k][3]));
+    HIP_CHECK(hipEventElapsedTime(&g1, ev[k][0], ev[k][1]));
+    HIP_CHECK(hipEventElapsedTime(&g2, ev[k][2], ev[k][3]));
     ms += t;
     gemm_ms += g1 + g2;
     n_gemm += 2;
-    pending = false;
+    pending[k] = false;
+  }
+  void collect() { collect(cur); }
+  void collect_all() {
+    collect(0);
+    collect(1);
   }
 };
 

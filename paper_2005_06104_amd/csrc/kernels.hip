@@ -445,14 +445,15 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ P, int S, long long M
   Cc[m * ldc + n] = o;
 }
 
-// Number of K splits: enough workgroups to cover the CUs when the output
-// has few tiles and K is long; each split keeps >= 256 of K, so the extra
-// partial-product traffic stays below the operand traffic.
+// Number of K splits: about one workgroup per CU when the output has few
+// tiles (Gram matrices, back transformations: 16-64 tiles would leave most
+// of the 256 CUs idle), each split keeping >= 64 of K.  The partial products
+// (S M N complex) mostly stay in the last-level cache.
 inline int choose_splits(int M, int N, int K, int batch, size_t ws_bytes, size_t cbytes) {
   const long long tiles = (long long)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
-  if (batch != 1 || ws_bytes == 0 || tiles >= 256 || K < 512) return 1;
-  int S = (int)std::min<long long>((512 + tiles - 1) / tiles, K / 256);
-  S = std::min(S, 16);
+  if (batch != 1 || ws_bytes == 0 || tiles >= 256 || K < 128) return 1;
+  int S = (int)std::min<long long>((256 + tiles - 1) / tiles, K / 64);
+  S = std::min(S, 32);
   while (S > 1 && (size_t)S * M * N * cbytes > ws_bytes) --S;
   return std::max(S, 1);
 }
@@ -640,6 +641,98 @@ __global__ void zdots_final_kernel(const double2* __restrict__ partial, int nb, 
   out[j] = make_double2(sr, si);
 }
 
+// The same dot products with the reduction in the same launch: every block
+// stores its partial sum, and the block that finishes last (a counter that
+// starts at zero and is left at zero) adds them in block order, so the result
+// is the same as that of the two-launch form.
+template <bool CONJ>
+__global__ __launch_bounds__(VNT) void zdots_fused_kernel(const double2* __restrict__ V, long long ldv, int nv,
+                                                           const double2* __restrict__ w, long long n,
+                                                           double2* __restrict__ partial, unsigned* counter,
+                                                           double2* __restrict__ out) {
+  __shared__ double sh[VNT / 64];
+  __shared__ int s_last;
+  const int j = blockIdx.y;
+  const long long beg = (long long)blockIdx.x * DOT_CHUNK;
+  const long long end = min(n, beg + DOT_CHUNK);
+  double sr = 0.0, si = 0.0;
+  const double2* v = V + (long long)j * ldv;
+  for (long long x = beg + threadIdx.x; x < end; x += VNT) {
+    const double2 a = v[x], b = w[x];
+    if (CONJ) {
+      sr += a.x * b.x + a.y * b.y;
+      si += a.x * b.y - a.y * b.x;
+    } else {
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+  }
+  const double tr = block_sum(sr, sh);
+  const double ti = block_sum(si, sh);
+  if (threadIdx.x == 0) {
+    partial[(long long)blockIdx.x * nv + j] = make_double2(tr, ti);
+    __threadfence();
+    const unsigned total = gridDim.x * gridDim.y;
+    s_last = atomicAdd(counter, 1u) == total - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  for (int jj = threadIdx.x; jj < nv; jj += VNT) {
+    double ar = 0.0, ai = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double2 p = partial[(long long)b * nv + jj];
+      ar += p.x;
+      ai += p.y;
+    }
+    out[jj] = make_double2(ar, ai);
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// w += sign * V c, then |w|^2 into out (real part), reduced in the same launch
+// as zdots_fused_kernel (one partial per block of VNT entries).
+__global__ __launch_bounds__(VNT) void zcombine_norm_kernel(double2* __restrict__ w, const double2* __restrict__ V,
+                                                             long long ldv, int nv, const double2* __restrict__ c,
+                                                             double sign, long long n, double2* __restrict__ partial,
+                                                             unsigned* counter, double2* __restrict__ out) {
+  __shared__ double sh[VNT / 64];
+  __shared__ int s_last;
+  const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
+  double sq = 0.0;
+  if (x < n) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      const double2 cj = c[j];
+      const double2 v = V[(long long)j * ldv + x];
+      sr += cj.x * v.x - cj.y * v.y;
+      si += cj.x * v.y + cj.y * v.x;
+    }
+    double2 o = w[x];
+    o.x += sign * sr;
+    o.y += sign * si;
+    w[x] = o;
+    sq = o.x * o.x + o.y * o.y;
+  }
+  const double t = block_sum(sq, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = make_double2(t, 0.0);
+    __threadfence();
+    s_last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += VNT) acc += partial[b].x;
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    out[0] = make_double2(tot, 0.0);
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 __global__ __launch_bounds__(VNT) void zcombine_kernel(double2* __restrict__ w, const double2* __restrict__ V,
                                                         long long ldv, int nv, const double2* __restrict__ c,
                                                         double sign, long long n) {
@@ -664,6 +757,15 @@ __global__ void zscale_kernel(double2* __restrict__ dst, const double2* __restri
   if (x >= n) return;
   const double2 v = src[x];
   dst[x] = make_double2(ar * v.x - ai * v.y, ar * v.y + ai * v.x);
+}
+
+// dst = src / sqrt(Re *nrm2): normalisation by a norm that is still on the device
+__global__ void zscale_invnorm_kernel(double2* __restrict__ w, const double2* __restrict__ nrm2, long long n) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const double inv = 1.0 / sqrt(fmax(nrm2->x, 0.0));
+  const double2 v = w[x];
+  w[x] = make_double2(v.x * inv, v.y * inv);
 }
 
 __global__ void z2c_kernel(float2* __restrict__ dst, const double2* __restrict__ src, long long n) {
@@ -773,11 +875,26 @@ void set_float_mode(int mode) {
 }
 int float_mode() { return tl_float_mode; }
 
+thread_local void* tl_split_ws = nullptr;
+thread_local size_t tl_split_wsb = 0;
+void set_split_workspace(void* p, size_t bytes) {
+  tl_split_ws = p;
+  tl_split_wsb = p ? bytes : 0;
+}
+SplitWorkspaceScope::SplitWorkspaceScope(void* p, size_t bytes) : saved_p(tl_split_ws), saved_b(tl_split_wsb) {
+  set_split_workspace(p, bytes);
+}
+SplitWorkspaceScope::~SplitWorkspaceScope() { set_split_workspace(saved_p, saved_b); }
+
 template <typename T>
 void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda,
           long long sa, const void* B, long long ldb, long long sb, zc beta, void* C, long long ldc,
           long long sc, int batch, void* ws, size_t ws_bytes) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (!ws) {
+    ws = tl_split_ws;
+    ws_bytes = tl_split_wsb;
+  }
   switch (opa) {
     case TDVP_OP_N: dispatch_b<T, TDVP_OP_N>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, ws_bytes); break;
     case TDVP_OP_T: dispatch_b<T, TDVP_OP_T>(s, opb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, ws, ws_bytes); break;
@@ -852,6 +969,26 @@ void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, l
   HIP_CHECK(hipGetLastError());
 }
 
+void zdots_fused(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
+                 int nb, unsigned* counter, void* out) {
+  if (nv <= 0) return;
+  hipLaunchKernelGGL(zdots_fused_kernel<true>, dim3(nb, nv), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
+                     nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial), counter,
+                     static_cast<double2*>(out));
+  HIP_CHECK(hipGetLastError());
+}
+
+int zcombine_norm_blocks(long long n) { return (int)std::max<long long>(1, nblk(n, VNT)); }
+
+void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
+                   long long n, void* partial, unsigned* counter, void* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zcombine_norm_kernel, dim3(zcombine_norm_blocks(n)), dim3(VNT), 0, s, static_cast<double2*>(w),
+                     static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(c), sign, n,
+                     static_cast<double2*>(partial), counter, static_cast<double2*>(out));
+  HIP_CHECK(hipGetLastError());
+}
+
 void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
               long long n) {
   if (n <= 0 || nv <= 0) return;
@@ -864,6 +1001,13 @@ void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zscale_kernel, dim3(nblk(n)), dim3(256), 0, s, static_cast<double2*>(dst),
                      static_cast<const double2*>(src), a.real(), a.imag(), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscale_invnorm(hipStream_t s, void* w, const void* nrm2, long long n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zscale_invnorm_kernel, dim3(nblk(n)), dim3(256), 0, s, static_cast<double2*>(w),
+                     static_cast<const double2*>(nrm2), n);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 
@@ -77,9 +78,7 @@ double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth
     kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, cols, 0, X, cols, 0, 0.0, G, n, 0, 1);
   kern::zshift_diag(s, G, n, 1.0, -1.0);
   kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
-  zc dev;
-  HIP_CHECK(hipMemcpyAsync(&dev, dsum, sizeof(rz), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  const zc dev = *static_cast<const zc*>(ctx->fetch(dsum, sizeof(rz)));
   return std::isfinite(dev.real()) ? dev.real() : HUGE_VAL;
 }
 
@@ -113,11 +112,12 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, G, n, 0, 1);
   kern::zshift_diag(s, G, n, 1.0, -1.0);
   kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
+  // one download: the defect (complex) and the two factorisation flags after it
+  const char* hs = static_cast<const char*>(ctx->fetch(dsum, sizeof(rz) + 2 * sizeof(int)));
   int info[2];
   zc dev;
-  HIP_CHECK(hipMemcpyAsync(info, dinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(&dev, dsum, sizeof(rz), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  std::memcpy(&dev, hs, sizeof(rz));
+  std::memcpy(info, hs + sizeof(rz), 2 * sizeof(int));
   if (info[0] != 0 || info[1] != 0 || !(dev.real() <= 1e-20)) return false;
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, C, n, 0, 0.0, R, n, 0, 1);
   return true;
@@ -149,11 +149,12 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, G, n, 0, 1);
   kern::zshift_diag(s, G, n, 1.0, -1.0);
   kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
+  // one download: the defect (complex) and the two factorisation flags after it
+  const char* hs = static_cast<const char*>(ctx->fetch(dsum, sizeof(rz) + 2 * sizeof(int)));
   int info[2];
   zc dev;
-  HIP_CHECK(hipMemcpyAsync(info, dinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(&dev, dsum, sizeof(rz), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  std::memcpy(&dev, hs, sizeof(rz));
+  std::memcpy(info, hs + sizeof(rz), 2 * sizeof(int));
   if (info[0] != 0 || info[1] != 0 || !(dev.real() <= 1e-20)) return false;
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, 0, B, cols, 0, 0.0, L, n, 0, 1);
   return true;
@@ -190,48 +191,63 @@ void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, s
 // (and leaves `rows` undefined) when the launch is not possible or the result
 // fails validation, so that the caller can use the rocSOLVER route.
 bool eigh_rows_desc_tridiag(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows,
-                            DBuf& work) {
+                            DBuf& work, bool lib_tridiagonal) {
   const int G = kern::tridiag_groups(n);
   if (n < 2 || G == 0) return false;
   const size_t nn = (size_t)n * n;
   const int nb = kern::zdots_blocks((long long)nn);
-  const size_t scr = kern::tridiag_scratch_bytes(n);
-  char* base = static_cast<char*>(work.ensure(2 * sizeof(rz) * nn + sizeof(double) * nn + scr +
-                                              sizeof(rz) * ((size_t)nb + 2) + sizeof(double) * (2 * (size_t)n + 4) +
-                                              512));
-  // layout (16-byte aligned first): X | Q | partial sums | sum | scratch | Z | D | E | info, err
-  rz* X = reinterpret_cast<rz*>(base);
-  rz* Q = X + nn;
-  rz* dpart = Q + nn;
-  rz* dsum = dpart + nb;
-  char* scratch = reinterpret_cast<char*>(dsum + 1);
-  double* Z = reinterpret_cast<double*>(scratch + (scr + 255) / 256 * 256);
-  double* dD = Z + nn;
-  double* dE = dD + n + 1;
-  int* dinfo = reinterpret_cast<int*>(dE + n + 1);
+  const size_t scr = std::max(kern::tridiag_scratch_bytes(n), kern::tridiag_eig_scratch_bytes(n));
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  // layout (256-byte aligned parts): X | Q | partial sums | staged block | E | scratch | Z
+  // staged block (one download): sum |v|^2 (complex), info, barrier error, D[n]
+  const size_t stage_bytes = sizeof(rz) + 4 * sizeof(int) + sizeof(double) * (size_t)n;
+  char* base = static_cast<char*>(work.ensure(up(sizeof(rz) * nn) * 2 + up(sizeof(rz) * (size_t)nb) +
+                                              up(stage_bytes) + up(sizeof(double) * (size_t)n) + up(scr) +
+                                              up(sizeof(double) * nn)));
+  char* p = base;
+  auto take = [&](size_t b) {
+    char* q = p;
+    p += up(b);
+    return q;
+  };
+  rz* X = reinterpret_cast<rz*>(take(sizeof(rz) * nn));
+  rz* Q = reinterpret_cast<rz*>(take(sizeof(rz) * nn));
+  rz* dpart = reinterpret_cast<rz*>(take(sizeof(rz) * (size_t)nb));
+  char* stage = take(stage_bytes);
+  rz* dsum = reinterpret_cast<rz*>(stage);
+  int* dinfo = reinterpret_cast<int*>(stage + sizeof(rz));
   int* derr = dinfo + 2;
+  double* dD = reinterpret_cast<double*>(stage + sizeof(rz) + 4 * sizeof(int));
+  double* dE = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
+  char* scratch = take(scr);
+  double* Z = reinterpret_cast<double*>(take(sizeof(double) * nn));
   HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
   kern::zhermitize(ctx->stream, X, n);
+  kern::zfill(ctx->stream, dinfo, zc(0.0, 0.0), 1, 16);   // info and barrier error
   const hipError_t le = kern::tridiag(ctx->stream, X, n, Q, dD, dE, scratch, derr);
   if (le != hipSuccess) {
     (void)hipGetLastError();
     return false;
   }
-  blas_check(rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, dD, dE, Z, n, dinfo), "dstedc");
+  if (lib_tridiagonal) {
+    blas_check(rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, dD, dE, Z, n, dinfo), "dstedc");
+  } else if (kern::tridiag_eig(ctx->stream, dD, dE, n, Z, scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
   kern::zrows_from_real_desc(ctx->stream, X, Z, n);
   kern::gemm<double>(ctx->stream, TDVP_OP_N, TDVP_OP_C, n, n, n, 1.0, X, n, 0, Q, n, 0, 0.0, rows, n, 0, 1);
   kern::zdots(ctx->stream, static_cast<const rz*>(rows), (long long)nn, 1, static_cast<const rz*>(rows), (long long)nn,
               dpart, nb, dsum);
-  int flags[2] = {0, 0};
+  const char* hs = static_cast<const char*>(ctx->fetch(stage, stage_bytes));
   zc vsum;
-  std::vector<double> asc(n);
-  HIP_CHECK(hipMemcpyAsync(flags, dinfo, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_CHECK(hipMemcpyAsync(&flags[1], derr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_CHECK(hipMemcpyAsync(&vsum, dsum, sizeof(rz), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_CHECK(hipMemcpyAsync(asc.data(), dD, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  int flags[2];
+  std::memcpy(&vsum, hs, sizeof(rz));
+  std::memcpy(&flags[0], hs + sizeof(rz), sizeof(int));
+  std::memcpy(&flags[1], hs + sizeof(rz) + 2 * sizeof(int), sizeof(int));
+  const double* asc = reinterpret_cast<const double*>(hs + sizeof(rz) + 4 * sizeof(int));
   bool ok = flags[0] == 0 && flags[1] == 0 && std::isfinite(vsum.real()) && std::fabs(vsum.real() - n) <= 1e-6 * n;
-  for (double v : asc) ok = ok && std::isfinite(v);
+  for (int j = 0; j < n; ++j) ok = ok && std::isfinite(asc[j]);
   if (!ok) return false;
   lam.resize(n);
   for (int j = 0; j < n; ++j) lam[j] = asc[n - 1 - j];
@@ -273,8 +289,17 @@ void eigh_rows_desc_heevd(tdvp_ctx_s* ctx, const void* H, int n, std::vector<dou
     std::vector<double> h(2 * nn);
     HIP_CHECK(hipMemcpyAsync(h.data(), H, sizeof(rz) * nn, hipMemcpyDeviceToHost, ctx->stream));
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    for (double v : h)
+    bool zero = true;
+    for (double v : h) {
       if (!std::isfinite(v)) TDVP_THROW(TDVP_ERR_NUMERIC, "eigh: non-finite input matrix (n = " + std::to_string(n) + ")");
+      zero = zero && v == 0.0;
+    }
+    if (zero) {   // the library routes do not converge on the zero matrix: V = I, all eigenvalues 0
+      kern::zfill(ctx->stream, rows, zc(0.0, 0.0), (long long)nn, 16);
+      kern::zshift_diag(ctx->stream, rows, n, 1.0, 1.0);
+      lam.assign(n, 0.0);
+      return;
+    }
     HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
     kern::zhermitize(ctx->stream, X, n);
     blas_check(rocsolver_zheevj(ctx->blas, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, n, X,
@@ -296,61 +321,63 @@ void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& 
                     int method) {
   // the cooperative reduction is at least as fast as the library route for
   // every size it supports (n <= 512)
-  const bool try_tridiag = method == EIGH_TRIDIAG || method == EIGH_AUTO;
-  if (try_tridiag && eigh_rows_desc_tridiag(ctx, H, n, lam, rows, work)) return;
-  if (method == EIGH_TRIDIAG) TDVP_THROW(TDVP_ERR_NUMERIC, "cooperative tridiagonal eigensolver not applicable");
+  const bool try_tridiag = method == EIGH_TRIDIAG || method == EIGH_AUTO || method == EIGH_TRIDIAG_LIB;
+  if (try_tridiag && eigh_rows_desc_tridiag(ctx, H, n, lam, rows, work, method == EIGH_TRIDIAG_LIB)) return;
+  if (method == EIGH_TRIDIAG || method == EIGH_TRIDIAG_LIB)
+    TDVP_THROW(TDVP_ERR_NUMERIC, "cooperative tridiagonal eigensolver not applicable");
   eigh_rows_desc_heevd(ctx, H, n, lam, rows, work);
 }
 
-void jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V) {
-  // cyclic Jacobi rotations on the symmetric n x n matrix A (row-major);
-  // on return w holds the eigenvalues ascending and column j of V the
-  // eigenvector of w[j]
-  V.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += a(i, j) * a(i, j);
-        if (i != j) off += a(i, j) * a(i, j);
+bool tridiag_ql(double* d, double* e, int n, double* Zr, int nr) {
+  // Implicit QL sweeps with a Wilkinson shift from the leading 2 x 2 block of
+  // the unreduced part (Golub & Van Loan, Sec. 8.3); every rotation is
+  // applied to the columns of Zr.
+  if (n <= 0) return true;
+  e[n - 1] = 0.0;
+  const double eps = 2.220446049250313e-16;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m)
+        if (std::fabs(e[m]) <= eps * (std::fabs(d[m]) + std::fabs(d[m + 1]))) break;
+      if (m == l) break;
+      if (iter == 60) return false;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+      double s = 1.0, c = 1.0, p = 0.0;
+      bool split = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {   // the chase decoupled the block: restart on the shorter one
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          split = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        for (int k = 0; k < nr; ++k) {
+          double* z = Zr + (size_t)k * n;
+          const double zf = z[i + 1];
+          z[i + 1] = s * z[i] + c * zf;
+          z[i] = c * z[i] - s * zf;
+        }
       }
-    if (off <= 1e-32 * tot || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = a(p, q);
-        if (apq == 0.0) continue;
-        const double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int r = 0; r < n; ++r) {  // columns p, q
-          const double arp = a(r, p), arq = a(r, q);
-          a(r, p) = c * arp - s * arq;
-          a(r, q) = s * arp + c * arq;
-        }
-        for (int r = 0; r < n; ++r) {  // rows p, q
-          const double apr = a(p, r), aqr = a(q, r);
-          a(p, r) = c * apr - s * aqr;
-          a(q, r) = s * apr + c * aqr;
-        }
-        for (int r = 0; r < n; ++r) {
-          const double vrp = V[(size_t)r * n + p], vrq = V[(size_t)r * n + q];
-          V[(size_t)r * n + p] = c * vrp - s * vrq;
-          V[(size_t)r * n + q] = s * vrp + c * vrq;
-        }
-      }
+      if (split) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
   }
-  std::vector<int> idx(n);
-  for (int i = 0; i < n; ++i) idx[i] = i;
-  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
-  std::vector<double> V2((size_t)n * n);
-  w.resize(n);
-  for (int j = 0; j < n; ++j) {
-    w[j] = a(idx[j], idx[j]);
-    for (int r = 0; r < n; ++r) V2[(size_t)r * n + j] = V[(size_t)r * n + idx[j]];
-  }
-  V.swap(V2);
+  return true;
 }
 
 }  // namespace la

@@ -1,8 +1,10 @@
 """Hermitian eigendecomposition on the device (tdvp_eigh): the cooperative
-Householder tridiagonalisation route and the rocSOLVER route against the
+Householder tridiagonalisation with the own tridiagonal divide and conquer
+(method 1) or rocSOLVER's (method 3), and the rocSOLVER route (2), against the
 eigenvalues of numpy's LAPACK eigensolver, orthonormality and reconstruction,
-on Gram matrices with decaying spectra, exact multiplets, rank deficiency and
-already-reduced (diagonal / tridiagonal) inputs."""
+on Gram matrices with decaying spectra, exact multiplets, rank deficiency,
+graded spectra, tight clusters, the zero matrix and already-reduced (diagonal /
+tridiagonal) inputs."""
 import numpy as np
 import pytest
 
@@ -46,8 +48,29 @@ def _tridiagonal(n, seed):
     return H + np.diag(off, 1) + np.diag(off.conj(), -1)
 
 
+def _spectrum(lam, seed):
+    n = len(lam)
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    return (U * lam) @ U.conj().T
+
+
+def _graded(n, seed):
+    # eigenvalues spread over fifteen decades (the tail of a density matrix)
+    return _spectrum(np.logspace(0, -15, n), seed)
+
+
+def _clusters(n, seed):
+    # two tight clusters (relative splittings 1e-10) and their mirror images:
+    # deflation by rotation in the tridiagonal divide and conquer
+    rng = np.random.default_rng(seed)
+    lam = np.concatenate([1.0 + 1e-10 * rng.standard_normal(n // 2), -0.5 + 1e-10 * rng.standard_normal(n - n // 2)])
+    return _spectrum(lam, seed + 1)
+
+
 CASES = {"gram": _gram, "multiplets": _multiplets, "tridiagonal": _tridiagonal,
-         "diagonal": lambda n, s: np.diag(np.random.default_rng(s).standard_normal(n)).astype(complex)}
+         "diagonal": lambda n, s: np.diag(np.random.default_rng(s).standard_normal(n)).astype(complex),
+         "zero": lambda n, s: np.zeros((n, n), complex), "graded": _graded, "clusters": _clusters}
 
 
 def _check(T, torch, ctx, H, method):
@@ -67,7 +90,7 @@ def _check(T, torch, ctx, H, method):
 
 @pytest.mark.parametrize("kind", sorted(CASES))
 @pytest.mark.parametrize("n", [2, 3, 17, 64, 100, 255, 256, 301, 512])
-@pytest.mark.parametrize("method", [1, 2])
+@pytest.mark.parametrize("method", [1, 2, 3])
 def test_eigh_routes(env, kind, n, method):
     T, torch, ctx = env
     _check(T, torch, ctx, CASES[kind](n, 7 * n + len(kind)), method)
