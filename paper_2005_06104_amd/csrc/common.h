@@ -153,6 +153,8 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
 // scratch holds tridiag_eig_scratch_bytes(n).  Returns the launch status.
 size_t tridiag_eig_scratch_bytes(int n);
 hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double* Z, void* scratch);
+// G <- G - frac * trace(G) * I (Hermitian complex128 n x n)
+void shift_by_trace(hipStream_t s, void* G, int n, double frac);
 // out[j][m] = Z[m][n-1-j] (complex), Z column-major real n x n
 void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n);
 // Arithmetic of the complex64 GEMMs issued from the calling host thread:
@@ -196,16 +198,13 @@ void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long
 void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n,
            void* partial, int n_partial_blocks, void* out, bool conjugate = true);
 int zdots_blocks(long long n);
-// The conjugated dot products of zdots in one launch: the block that finishes
-// last adds the partial sums in block order.  counter: a device unsigned that
-// is zero before the call and is left at zero.
-void zdots_fused(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
-                 int n_partial_blocks, unsigned* counter, void* out);
 // w[x] += sign * sum_j c[j] V[j*ldv + x]   (c complex128 on device)
 void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c,
               double sign, long long n);
-// zcombine, then out[0] = |w|^2 (real part) in the same launch; partial holds
-// zcombine_norm_blocks(n) complex entries, counter as for zdots_fused
+// zcombine, then out[0] = |w|^2 (real part) in the same launch (the block that
+// finishes last reduces); partial holds zcombine_norm_blocks(n) complex
+// entries; counter: a device unsigned that is zero before the call and is
+// left at zero
 int zcombine_norm_blocks(long long n);
 void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
                    long long n, void* partial, unsigned* counter, void* out);
@@ -256,9 +255,21 @@ double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth
 // C (rows >= cols) = A R by two Cholesky-QR passes, A orthonormal columns,
 // R = A^dagger C (cols x cols, not triangular); false (A, R undefined) when
 // the Gram matrix is numerically singular or A fails the orthonormality check.
-bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work);
+bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
+                      const void* first = nullptr);
 // C (rows <= cols) = L B with B orthonormal rows, L = C B^dagger (rows x rows).
-bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work);
+bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
+                           const void* first = nullptr);
+// True when the smallest eigenvalue of the Hermitian positive semidefinite
+// n x n matrix G provably exceeds frac * trace(G): the Cholesky factorisation
+// of G - (frac + 4 n u) trace(G) I succeeds (u the unit roundoff; the margin
+// covers the rounding of the factorisation).  G is overwritten.
+// On success G holds that factor (upper, or lower when `lower`, in the
+// column-major view used by the Cholesky-QR2 routines), which they accept as
+// their first pass (shifted Cholesky-QR: the shifted factor leaves the first
+// iterate's condition number below ~10, and the second pass restores
+// orthonormality).
+bool gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, DBuf& work);
 // thin SVD of row-major C (rows x cols): U (rows x k), S (k, host), Vh (k x cols); k = min.
 void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
                   void* Vh, DBuf& work, DBuf& work2);

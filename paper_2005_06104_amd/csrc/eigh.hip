@@ -318,6 +318,21 @@ __global__ void zrows_from_real_kernel(double2* __restrict__ out, const double* 
   out[idx] = double2{Z[(size_t)(n - 1 - j) * n + m], 0.0};
 }
 
+// G <- G - frac * tr(G) I for a Hermitian n x n matrix (one workgroup)
+__global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* __restrict__ G, int n, double frac) {
+  __shared__ double red[TNT / 64];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += TNT) t += G[(size_t)i * n + i].x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  double tr = 0.0;
+  for (int w = 0; w < TNT / 64; ++w) tr += red[w];
+  const double mu = frac * tr;
+  for (int i = threadIdx.x; i < n; i += TNT) G[(size_t)i * n + i].x -= mu;
+}
+
 __global__ void u32_fill_kernel(unsigned* p, unsigned v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -366,6 +381,11 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
   hipLaunchKernelGGL(u32_fill_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(err), 0u, 1);
   void* args[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_kernel), dim3(G), dim3(TNT), args, 0, s);
+}
+
+void shift_by_trace(hipStream_t s, void* G, int n, double frac) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(shift_by_trace_kernel, dim3(1), dim3(TNT), 0, s, static_cast<double2*>(G), n, frac);
 }
 
 void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n) {

@@ -72,8 +72,8 @@ struct Lanczos {
     scal.ensure(256 * ZB);
     double2* S = scal.as<double2>();
     // S: [0, 64) and [64, 128) the two projection passes, 128 |w|^2, 192.. the
-    // result coefficients, 255 the completion counter of the fused reductions
-    unsigned* counter = reinterpret_cast<unsigned*>(S + 255);
+    // result coefficients, 255 the completion counter of the fused norm
+    unsigned* ncounter = reinterpret_cast<unsigned*>(S + 255);
     kern::zfill(ctx->stream, S + 255, zc(0.0, 0.0), 1, ZB);
     char* Vb = static_cast<char*>(V.ensure((size_t)(maxit + 1) * n * ZB));
     auto vec = [&](int j) { return static_cast<void*>(Vb + (size_t)j * n * ZB); };
@@ -117,10 +117,10 @@ struct Lanczos {
       void* w = vec(j + 1);
       if (timer) timer->cur = j & 1;
       mv(vec(j), w);
-      kern::zdots_fused(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, counter, S);
+      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S);
       kern::zcombine(ctx->stream, w, Vb, n, j + 1, S, -1.0, n);
-      kern::zdots_fused(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, counter, S + 64);
-      kern::zcombine_norm(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n, partial.p, counter, S + 128);
+      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S + 64);
+      kern::zcombine_norm(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n, partial.p, ncounter, S + 128);
       // the first-pass projections (alpha_j = <v_j|H v_j>) and |w|^2
       staged[j & 1] = static_cast<const zc*>(ctx->stage_async(j & 1, S, 129 * ZB));
       kern::zscale_invnorm(ctx->stream, w, S + 128, n);
@@ -479,6 +479,17 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   W.tmpA.ensure((size_t)cols * cols * ZB);
   W.tmpB.ensure((size_t)cols * cols * ZB);
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, cols, cols, rows, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, cols, 0, 1);
+  // Nothing is cut when the smallest weight exceeds max(eps, floor) times
+  // their sum (the cap does not bind: kk <= chi_max); a Cholesky factorisation
+  // certifies it, and the exact factorisation is then the split.
+  if (kk == cols && kk <= chi_max) {
+    HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)cols * cols * ZB, hipMemcpyDeviceToDevice, s));
+    if (la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false, W.work)) {
+      A.ensure((size_t)rows * kk * ZB);
+      R.ensure((size_t)kk * cols * ZB);
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tmpB.p)) return kk;
+    }
+  }
   std::vector<double> lam;
   la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
@@ -522,6 +533,15 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   W.tmpA.ensure((size_t)rows * rows * ZB);
   W.tmpB.ensure((size_t)rows * rows * ZB);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, rows, 0, 1);
+  // certified "nothing to cut" as in split_left
+  if (kk == rows && kk <= chi_max) {
+    HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)rows * rows * ZB, hipMemcpyDeviceToDevice, s));
+    if (la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true, W.work)) {
+      L.ensure((size_t)rows * kk * ZB);
+      B.ensure((size_t)kk * cols * ZB);
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tmpB.p)) return kk;
+    }
+  }
   std::vector<double> lam;
   la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
@@ -1037,10 +1057,24 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     W.tmpA.ensure((size_t)ml * ml * ZB);
     W.tmpB.ensure((size_t)ml * ml * ZB);
     kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, ml, ml, D, 1.0, C, D, 0, C, D, 0, 0.0, W.tmpA.p, ml, 0, 1);
-    la::eigh_rows_desc(ctx, W.tmpA.p, ml, S, W.tmpB.p, W.work2);
     int r = 0;
     Vh.ensure((size_t)std::min(ml, D) * D * ZB);
-    if (ml <= D && !S.empty() && S[0] > 0.0 && S[ml - 1] > 1e-10 * S[0]) {
+    // Full row rank is certified without the eigendecomposition when the
+    // smallest weight exceeds 1e-10 times their sum (hence 1e-10 times the
+    // largest, the criterion below); B is then the LQ factor's Q.
+    bool done = false;
+    if (ml <= D) {
+      HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)ml * ml * ZB, hipMemcpyDeviceToDevice, s));
+      if (la::gram_floor_certified(ctx, W.tmpB.p, ml, 1e-10, true, W.work)) {
+        W.tmpC.ensure((size_t)ml * ml * ZB);
+        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, W.tmpB.p);
+        if (done) r = ml;
+      }
+    }
+    if (!done) la::eigh_rows_desc(ctx, W.tmpA.p, ml, S, W.tmpB.p, W.work2);
+    if (done) {
+      // B from the certified LQ factorisation
+    } else if (ml <= D && !S.empty() && S[0] > 0.0 && S[ml - 1] > 1e-10 * S[0]) {
       r = ml;
       // B = S^-1 U^dagger C, polished by Newton-Schulz
       W.tmpC.ensure((size_t)ml * D * ZB);

@@ -583,7 +583,7 @@ __global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T
 
 // ---------------------------------------------------------------- vectors
 constexpr int VNT = 256;
-constexpr int DOT_CHUNK = 4096;
+constexpr int DOT_CHUNK = 1024;
 
 __device__ inline double warp_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -628,71 +628,25 @@ __global__ __launch_bounds__(VNT) void zdots_partial_kernel(const double2* __res
   if (threadIdx.x == 0) partial[(long long)blockIdx.x * nv + j] = make_double2(tr, ti);
 }
 
-__global__ void zdots_final_kernel(const double2* __restrict__ partial, int nb, int nv,
-                                   double2* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nv) return;
+// one block per vector: out[j] = sum over the blocks' partials (fixed tree)
+__global__ __launch_bounds__(VNT) void zdots_final_kernel(const double2* __restrict__ partial, int nb, int nv,
+                                                           double2* __restrict__ out) {
+  __shared__ double sh[VNT / 64];
+  const int j = blockIdx.x;
   double sr = 0.0, si = 0.0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += VNT) {
     const double2 p = partial[(long long)b * nv + j];
     sr += p.x;
     si += p.y;
   }
-  out[j] = make_double2(sr, si);
-}
-
-// The same dot products with the reduction in the same launch: every block
-// stores its partial sum, and the block that finishes last (a counter that
-// starts at zero and is left at zero) adds them in block order, so the result
-// is the same as that of the two-launch form.
-template <bool CONJ>
-__global__ __launch_bounds__(VNT) void zdots_fused_kernel(const double2* __restrict__ V, long long ldv, int nv,
-                                                           const double2* __restrict__ w, long long n,
-                                                           double2* __restrict__ partial, unsigned* counter,
-                                                           double2* __restrict__ out) {
-  __shared__ double sh[VNT / 64];
-  __shared__ int s_last;
-  const int j = blockIdx.y;
-  const long long beg = (long long)blockIdx.x * DOT_CHUNK;
-  const long long end = min(n, beg + DOT_CHUNK);
-  double sr = 0.0, si = 0.0;
-  const double2* v = V + (long long)j * ldv;
-  for (long long x = beg + threadIdx.x; x < end; x += VNT) {
-    const double2 a = v[x], b = w[x];
-    if (CONJ) {
-      sr += a.x * b.x + a.y * b.y;
-      si += a.x * b.y - a.y * b.x;
-    } else {
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
-    }
-  }
   const double tr = block_sum(sr, sh);
   const double ti = block_sum(si, sh);
-  if (threadIdx.x == 0) {
-    partial[(long long)blockIdx.x * nv + j] = make_double2(tr, ti);
-    __threadfence();
-    const unsigned total = gridDim.x * gridDim.y;
-    s_last = atomicAdd(counter, 1u) == total - 1 ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  for (int jj = threadIdx.x; jj < nv; jj += VNT) {
-    double ar = 0.0, ai = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double2 p = partial[(long long)b * nv + jj];
-      ar += p.x;
-      ai += p.y;
-    }
-    out[jj] = make_double2(ar, ai);
-  }
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) out[j] = make_double2(tr, ti);
 }
 
-// w += sign * V c, then |w|^2 into out (real part), reduced in the same launch
-// as zdots_fused_kernel (one partial per block of VNT entries).
+// w += sign * V c, then |w|^2 into out (real part), in the same launch: every
+// block stores its partial sum, and the block that finishes last (a counter
+// that starts at zero and is left at zero) adds them with a fixed tree.
 __global__ __launch_bounds__(VNT) void zcombine_norm_kernel(double2* __restrict__ w, const double2* __restrict__ V,
                                                              long long ldv, int nv, const double2* __restrict__ c,
                                                              double sign, long long n, double2* __restrict__ partial,
@@ -964,17 +918,8 @@ void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, l
   else
     hipLaunchKernelGGL(zdots_partial_kernel<false>, dim3(nb, nv), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
                        nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
-  hipLaunchKernelGGL(zdots_final_kernel, dim3(nblk(nv, 64)), dim3(64), 0, s,
+  hipLaunchKernelGGL(zdots_final_kernel, dim3(nv), dim3(VNT), 0, s,
                      static_cast<const double2*>(partial), nb, nv, static_cast<double2*>(out));
-  HIP_CHECK(hipGetLastError());
-}
-
-void zdots_fused(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
-                 int nb, unsigned* counter, void* out) {
-  if (nv <= 0) return;
-  hipLaunchKernelGGL(zdots_fused_kernel<true>, dim3(nb, nv), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
-                     nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial), counter,
-                     static_cast<double2*>(out));
   HIP_CHECK(hipGetLastError());
 }
 

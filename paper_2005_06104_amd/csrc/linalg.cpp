@@ -82,81 +82,186 @@ double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth
   return std::isfinite(dev.real()) ? dev.real() : HUGE_VAL;
 }
 
-// Two passes of Cholesky QR (CholeskyQR2: Yamamoto, Nakatsukasa, Yanagisawa
-// and Fukaya, 2015): X <- X R^-1 with X^H X = R^H R, twice; the second pass
-// restores orthonormality to rounding when cond(C) < ~1e7.  A row-major
-// n x n Gram matrix read column-major is its conjugate M; potrf gives
-// M = U^H U, so R = conj(U) and the row-major solve X R = Y is, column-major,
-// U^H X^T = Y^T.  The result is accepted when both factorisations succeed and
-// ||A^H A - I||_F <= 1e-10; the caller then factors by Householder QR.
-bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work) {
-  if (cols < 1 || rows < cols) return false;
-  const int n = cols;
+bool gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, DBuf& work) {
+  if (n < 1) return false;
+  int* dinfo = static_cast<int*>(work.ensure(64));
+  kern::shift_by_trace(ctx->stream, G, n, frac * 1.01 + 4.0 * n * 2.220446049250313e-16);
+  // row-major G read column-major is conj(G): definite exactly when G is
+  blas_check(rocsolver_zpotrf(ctx->blas, lower ? rocblas_fill_lower : rocblas_fill_upper, n, static_cast<rz*>(G), n,
+                              dinfo),
+             "zpotrf");
+  return *static_cast<const int*>(ctx->fetch(dinfo, sizeof(int))) == 0;
+}
+
+// Cholesky QR in two steps (after CholeskyQR2: Yamamoto, Nakatsukasa,
+// Yanagisawa and Fukaya, 2015): X <- X R^-1 with X^H X = R^H R restores
+// orthonormality to ~u cond(C)^2, and a second step to rounding when
+// cond(C) < ~1e7.  The second step is chosen by the measured defect
+// delta = ||X^H X - I||_F of the first: none when delta <= 1e-10; Newton-
+// Schulz steps X <- X (I - (X^H X - I) / 2) when delta < 1/4 (each squares
+// the defect; GEMMs only, the number of steps set from delta); a second
+// Cholesky step otherwise.  A row-major n x n Gram matrix read column-major
+// is its conjugate M; potrf gives M = U^H U, so R = conj(U) and the
+// row-major solve X R = Y is, column-major, U^H X^T = Y^T.  The result is
+// accepted when the factorisations succeed and ||A^H A - I||_F <= 1e-10; the
+// caller then factors by Householder QR.  `first` (may be NULL) is a factor
+// to use in the first step instead of the Cholesky factor of the Gram
+// matrix (the shifted factor of gram_floor_certified).
+namespace {
+
+int ns_steps(double dev) {   // dev = delta^2; steps until delta^(2^s) <= 1e-11
+  const double d = std::sqrt(dev);
+  int st = 1;
+  for (double x = d * d; x > 1e-11 && st < 6; x *= x) ++st;
+  return st;
+}
+
+struct CqrSpace {
+  rz* G;
+  rz* dpart;
+  rz* dsum;
+  int* dinfo;
+  rz* T;
+  int nb;
+};
+
+CqrSpace cqr_space(DBuf& work, int n, long long mat) {
   const size_t nn = (size_t)n * n;
   const int nb = kern::zdots_blocks((long long)nn);
-  char* base = static_cast<char*>(work.ensure(sizeof(rz) * (nn + (size_t)nb + 2) + 64));
-  rz* G = reinterpret_cast<rz*>(base);
-  rz* dpart = G + nn;
-  rz* dsum = dpart + nb;
-  int* dinfo = reinterpret_cast<int*>(dsum + 1);
-  hipStream_t s = ctx->stream;
-  HIP_CHECK(hipMemcpyAsync(A, C, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
-  const rz one{1.0, 0.0};
-  for (int pass = 0; pass < 2; ++pass) {
-    kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, G, n, 0, 1);
-    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_upper, n, G, n, dinfo + pass), "zpotrf");
-    blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
-                             rocblas_diagonal_non_unit, n, rows, &one, G, n, static_cast<rz*>(A), n),
-               "ztrsm");
-  }
-  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, G, n, 0, 1);
-  kern::zshift_diag(s, G, n, 1.0, -1.0);
-  kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
-  // one download: the defect (complex) and the two factorisation flags after it
-  const char* hs = static_cast<const char*>(ctx->fetch(dsum, sizeof(rz) + 2 * sizeof(int)));
-  int info[2];
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  char* base = static_cast<char*>(
+      work.ensure(up(sizeof(rz) * nn) + up(sizeof(rz) * ((size_t)nb + 2)) + up(sizeof(rz) * (size_t)mat)));
+  CqrSpace c;
+  c.G = reinterpret_cast<rz*>(base);
+  c.dpart = reinterpret_cast<rz*>(base + up(sizeof(rz) * nn));
+  c.dsum = c.dpart + nb;
+  c.dinfo = reinterpret_cast<int*>(c.dsum + 1);
+  c.T = reinterpret_cast<rz*>(base + up(sizeof(rz) * nn) + up(sizeof(rz) * ((size_t)nb + 2)));
+  c.nb = nb;
+  return c;
+}
+
+// ||G - I||_F^2 with G <- G - I, and the factorisation flag; one download
+double defect(tdvp_ctx_s* ctx, const CqrSpace& c, int n, int* info) {
+  const size_t nn = (size_t)n * n;
+  kern::zshift_diag(ctx->stream, c.G, n, 1.0, -1.0);
+  kern::zdots(ctx->stream, c.G, (long long)nn, 1, c.G, (long long)nn, c.dpart, c.nb, c.dsum);
+  const char* hs = static_cast<const char*>(ctx->fetch(c.dsum, sizeof(rz) + sizeof(int)));
   zc dev;
   std::memcpy(&dev, hs, sizeof(rz));
-  std::memcpy(info, hs + sizeof(rz), 2 * sizeof(int));
-  if (info[0] != 0 || info[1] != 0 || !(dev.real() <= 1e-20)) return false;
-  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, C, n, 0, 0.0, R, n, 0, 1);
+  std::memcpy(info, hs + sizeof(rz), sizeof(int));
+  return std::isfinite(dev.real()) ? dev.real() : HUGE_VAL;
+}
+
+}  // namespace
+
+bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
+                      const void* first) {
+  if (cols < 1 || rows < cols) return false;
+  const int n = cols;
+  const CqrSpace c = cqr_space(work, n, (long long)rows * n);
+  hipStream_t s = ctx->stream;
+  rz* X = static_cast<rz*>(A);
+  const rz one{1.0, 0.0};
+  auto gram = [&] { kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, 0, X, n, 0, 0.0, c.G, n, 0, 1); };
+  auto chol_step = [&](const rz* F) {
+    blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                             rocblas_diagonal_non_unit, n, rows, &one, F, n, X, n),
+               "ztrsm");
+  };
+  HIP_CHECK(hipMemcpyAsync(X, C, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+  kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
+  if (first) {
+    chol_step(static_cast<const rz*>(first));
+  } else {
+    gram();
+    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_upper, n, c.G, n, c.dinfo), "zpotrf");
+    chol_step(c.G);
+  }
+  int info = 0;
+  gram();
+  double dev = defect(ctx, c, n, &info);
+  if (info != 0) return false;
+  if (dev > 1e-20 && dev < 0.0625) {
+    // Newton-Schulz: X <- X (I - D / 2) with D = X^H X - I (in c.G)
+    const int st = ns_steps(dev);
+    for (int k = 0; k < st; ++k) {
+      kern::zshift_diag(s, c.G, n, -0.5, 1.0);
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, X, n, 0, c.G, n, 0, 0.0, c.T, n, 0, 1);
+      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+      gram();
+      if (k + 1 < st) kern::zshift_diag(s, c.G, n, 1.0, -1.0);
+    }
+    dev = defect(ctx, c, n, &info);
+  }
+  if (dev > 1e-20) {
+    // a second Cholesky step (G holds X^H X - I)
+    kern::zshift_diag(s, c.G, n, 1.0, 1.0);
+    kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
+    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_upper, n, c.G, n, c.dinfo), "zpotrf");
+    chol_step(c.G);
+    gram();
+    dev = defect(ctx, c, n, &info);
+    if (info != 0 || !(dev <= 1e-20)) return false;
+  }
+  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, 0, C, n, 0, 0.0, R, n, 0, 1);
   return true;
 }
 
 // The same for orthonormal rows (rows <= cols): C = L B, C C^H = L L^H; the
 // row-major Gram read column-major is M = Lc Lc^H with L = conj(Lc), and
-// B = L^-1 C is, column-major, B^T Lc^H = C^T.
-bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work) {
+// B = L^-1 C is, column-major, B^T Lc^H = C^T; Newton-Schulz steps are
+// B <- (I - (B B^H - I) / 2) B.
+bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
+                           const void* first) {
   if (rows < 1 || cols < rows) return false;
   const int n = rows;
-  const size_t nn = (size_t)n * n;
-  const int nb = kern::zdots_blocks((long long)nn);
-  char* base = static_cast<char*>(work.ensure(sizeof(rz) * (nn + (size_t)nb + 2) + 64));
-  rz* G = reinterpret_cast<rz*>(base);
-  rz* dpart = G + nn;
-  rz* dsum = dpart + nb;
-  int* dinfo = reinterpret_cast<int*>(dsum + 1);
+  const CqrSpace c = cqr_space(work, n, (long long)n * cols);
   hipStream_t s = ctx->stream;
-  HIP_CHECK(hipMemcpyAsync(B, C, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+  rz* X = static_cast<rz*>(B);
   const rz one{1.0, 0.0};
-  for (int pass = 0; pass < 2; ++pass) {
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, G, n, 0, 1);
-    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, G, n, dinfo + pass), "zpotrf");
+  auto gram = [&] {
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, X, cols, 0, X, cols, 0, 0.0, c.G, n, 0, 1);
+  };
+  auto chol_step = [&](const rz* F) {
     blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                             rocblas_diagonal_non_unit, cols, n, &one, G, n, static_cast<rz*>(B), cols),
+                             rocblas_diagonal_non_unit, cols, n, &one, F, n, X, cols),
                "ztrsm");
+  };
+  HIP_CHECK(hipMemcpyAsync(X, C, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+  kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
+  if (first) {
+    chol_step(static_cast<const rz*>(first));
+  } else {
+    gram();
+    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, c.G, n, c.dinfo), "zpotrf");
+    chol_step(c.G);
   }
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, G, n, 0, 1);
-  kern::zshift_diag(s, G, n, 1.0, -1.0);
-  kern::zdots(s, G, (long long)nn, 1, G, (long long)nn, dpart, nb, dsum);
-  // one download: the defect (complex) and the two factorisation flags after it
-  const char* hs = static_cast<const char*>(ctx->fetch(dsum, sizeof(rz) + 2 * sizeof(int)));
-  int info[2];
-  zc dev;
-  std::memcpy(&dev, hs, sizeof(rz));
-  std::memcpy(info, hs + sizeof(rz), 2 * sizeof(int));
-  if (info[0] != 0 || info[1] != 0 || !(dev.real() <= 1e-20)) return false;
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, 0, B, cols, 0, 0.0, L, n, 0, 1);
+  int info = 0;
+  gram();
+  double dev = defect(ctx, c, n, &info);
+  if (info != 0) return false;
+  if (dev > 1e-20 && dev < 0.0625) {
+    const int st = ns_steps(dev);
+    for (int k = 0; k < st; ++k) {
+      kern::zshift_diag(s, c.G, n, -0.5, 1.0);
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, c.G, n, 0, X, cols, 0, 0.0, c.T, cols, 0, 1);
+      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+      gram();
+      if (k + 1 < st) kern::zshift_diag(s, c.G, n, 1.0, -1.0);
+    }
+    dev = defect(ctx, c, n, &info);
+  }
+  if (dev > 1e-20) {
+    kern::zshift_diag(s, c.G, n, 1.0, 1.0);
+    kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
+    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, c.G, n, c.dinfo), "zpotrf");
+    chol_step(c.G);
+    gram();
+    dev = defect(ctx, c, n, &info);
+    if (info != 0 || !(dev <= 1e-20)) return false;
+  }
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, 0, X, cols, 0, 0.0, L, n, 0, 1);
   return true;
 }
 

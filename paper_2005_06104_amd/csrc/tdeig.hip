@@ -12,7 +12,8 @@
 //  * The secular equation 1 + rho sum_j z_j^2 / (d_j - lambda) = 0 on each
 //    interval between poles, solved for tau = lambda - d_o relative to the
 //    nearer pole d_o (so that lambda - d_j is known to high relative
-//    accuracy) by Newton steps on tau f(tau), safeguarded by bisection.
+//    accuracy) by Newton steps on tau f(tau), safeguarded by bisection, until
+//    f vanishes to within the rounding of its terms.
 //  * Eigenvectors from the Loewner-type recomputation of z (Gu & Eisenstat
 //    1995): zhat_j^2 = prod_i (lambda_i - d_j) / (rho prod_{i != j} (d_i - d_j)),
 //    v_i = (zhat_j / (d_j - lambda_i))_j, normalised; numerically orthogonal
@@ -35,6 +36,7 @@ constexpr int DC_PREP_NT = 512;   // threads of the per-node preparation kernel
 constexpr int DC_WNT = 256;       // four waves: one (node, index) pair each
 constexpr int DC_PMAX = 512;
 constexpr int DC_SECULAR_MAXIT = 200;
+static_assert(DC_PREP_NT >= DC_PMAX, "the preparation kernel holds one entry per thread");
 
 struct DcArgs {
   int P, s;                 // padded size, node size at this level
@@ -118,11 +120,16 @@ __global__ __launch_bounds__(1024) void dc_init_kernel(const double* __restrict_
 
 // ---------------------------------------------------------------- level kernels
 // Preparation, one workgroup per node: z, sign, sort by merging the two
-// sorted children, deflation (one thread, in sorted order).
+// sorted children, deflation: small z entries in parallel, then one thread
+// walks the remaining entries in sorted order (the pair tests precomputed,
+// recomputed only after a rotation changed the left entry).
 __global__ __launch_bounds__(DC_PREP_NT) void dc_prep_kernel(DcArgs a) {
   __shared__ double s_ds[DC_PMAX], s_zs[DC_PMAX];
   __shared__ int s_nd[DC_PMAX], s_inv[DC_PMAX];
   __shared__ double s_max[DC_PREP_NT / 64];
+  __shared__ int s_lst[DC_PMAX], s_pd[DC_PMAX];
+  __shared__ double s_pc[DC_PMAX], s_ps[DC_PMAX], s_pt[DC_PMAX];
+  __shared__ int s_wcnt[DC_PREP_NT / 64];
   __shared__ int s_K;
   const int b = blockIdx.x, s = a.s, h = s / 2, P = a.P, tid = threadIdx.x;
   const int base = b * s;
@@ -158,25 +165,60 @@ __global__ __launch_bounds__(DC_PREP_NT) void dc_prep_kernel(DcArgs a) {
     lmax = fmax(lmax, fabs(v));
   }
   lmax = wave_max(lmax);
-  if ((tid & 63) == 0) s_max[tid >> 6] = lmax;
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) s_max[wv] = lmax;
+  __syncthreads();
+  double dm = 0.0;
+  for (int w = 0; w < DC_PREP_NT / 64; ++w) dm = fmax(dm, s_max[w]);
+  const double tol = 8.0 * 2.220446049250313e-16 * fmax(dm, r);
+  // entries that keep a z component, compacted in sorted order (s <= the
+  // number of threads: one entry each)
+  const bool live = tid < s && r * fabs(s_zs[tid]) > tol;
+  const unsigned long long bal = __ballot(live);
+  if (lane == 0) s_wcnt[wv] = __popcll(bal);
+  if (tid < s) s_inv[tid] = -1;
+  __syncthreads();
+  int off = 0, L = 0;
+  for (int w = 0; w < DC_PREP_NT / 64; ++w) {
+    if (w < wv) off += s_wcnt[w];
+    L += s_wcnt[w];
+  }
+  if (live) s_lst[off + __popcll(bal & ((1ull << lane) - 1))] = tid;
+  __syncthreads();
+  // the test of each neighbouring pair with the values before any rotation;
+  // it stands unless the left entry has just received a rotation
+  if (tid + 1 < L) {
+    const int p = s_lst[tid], q = s_lst[tid + 1];
+    const double sv = s_zs[p], cv = s_zs[q];
+    const double ta = hypot(cv, sv);
+    const double c = cv / ta, sn = -sv / ta;
+    s_pc[tid] = c;
+    s_ps[tid] = sn;
+    s_pt[tid] = ta;
+    s_pd[tid] = fabs((s_ds[q] - s_ds[p]) * c * sn) <= tol ? 1 : 0;
+  }
   __syncthreads();
   if (tid == 0) {
-    double dm = 0.0;
-    for (int w = 0; w < DC_PREP_NT / 64; ++w) dm = fmax(dm, s_max[w]);
-    const double tol = 8.0 * 2.220446049250313e-16 * fmax(dm, r);
-    int K = 0, m = 0, pj = -1;
-    for (int j = 0; j < s; ++j) {
-      s_inv[j] = -1;
-      if (r * fabs(s_zs[j]) <= tol) continue;
-      if (pj < 0) {
-        pj = j;
-        continue;
+    int K = 0, m = 0;
+    bool rotated = false;
+    int pj = L > 0 ? s_lst[0] : -1;
+    for (int k = 1; k < L; ++k) {
+      const int j = s_lst[k];
+      double c, sn, ta;
+      bool defl;
+      if (!rotated) {
+        c = s_pc[k - 1];
+        sn = s_ps[k - 1];
+        ta = s_pt[k - 1];
+        defl = s_pd[k - 1] != 0;
+      } else {
+        const double sv = s_zs[pj], cv = s_zs[j];
+        ta = hypot(cv, sv);
+        c = cv / ta;
+        sn = -sv / ta;
+        defl = fabs((s_ds[j] - s_ds[pj]) * c * sn) <= tol;
       }
-      const double sv = s_zs[pj], cv = s_zs[j];
-      const double t = s_ds[j] - s_ds[pj];
-      const double ta = hypot(cv, sv);
-      const double c = cv / ta, sn = -sv / ta;
-      if (fabs(t * c * sn) <= tol) {
+      if (defl) {
         // rotate (pj, j): z_pj -> 0, z_j -> ta; pj keeps the mixed pole
         s_zs[j] = ta;
         s_zs[pj] = 0.0;
@@ -188,10 +230,12 @@ __global__ __launch_bounds__(DC_PREP_NT) void dc_prep_kernel(DcArgs a) {
         const double dp = s_ds[pj], dj = s_ds[j];
         s_ds[pj] = dp * c * c + dj * sn * sn;
         s_ds[j] = dp * sn * sn + dj * c * c;
+        rotated = true;
       } else {
         s_nd[K] = pj;
         s_inv[pj] = K;
         ++K;
+        rotated = false;
       }
       pj = j;
     }
@@ -265,16 +309,20 @@ __global__ __launch_bounds__(DC_WNT) void dc_secular_kernel(DcArgs a) {
   }
   double tau = 0.5 * (lo + hi);
   for (int it = 0; it < DC_SECULAR_MAXIT; ++it) {
-    double f = 0.0, fp = 0.0;
+    double f = 0.0, fp = 0.0, fa = 0.0;
 #pragma unroll
     for (int t = 0; t < PL; ++t) {
       const double q = 1.0 / (dj[t] - tau);
       const double tt = z2[t] * q;
       f += tt;
       fp += tt * q;
+      fa += fabs(tt);
     }
     f = 1.0 + r * wave_sum(f);
     fp = r * wave_sum(fp);
+    fa = 1.0 + r * wave_sum(fa);
+    // f vanishes to within the rounding of its terms
+    if (fabs(f) <= 8.0 * 2.220446049250313e-16 * fa) break;
     if (f > 0.0) hi = tau;
     else lo = tau;
     if (hi - lo <= 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi))) break;
