@@ -18,6 +18,8 @@
 // that makes every workgroup leave, and the caller then uses another solver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -344,14 +346,15 @@ namespace kern {
 
 int tridiag_groups(int n) {
   if (n < 1 || n > TD_NMAX) return 0;
-  // smallest G with 2 ceil(n/G) n <= TD_LDS complex slots (A and Q rows) and
-  // ceil(n/G) within the row-sum slots
-  // (the partial sums are combined by one wave: G <= 64)
-  for (int G = 1; G <= 64; ++G) {
-    const int R = (n + G - 1) / G;
-    if (2 * R * n <= TD_LDS && R <= TD_ROWS) return G;
-  }
-  return 0;
+  // The per-column work of a workgroup grows with its share of the rows and
+  // the barrier with the number of workgroups: about eight rows per
+  // workgroup is fastest (measured from n = 48 to 512); small matrices stay
+  // in one workgroup.  At most 64 workgroups (the partial sums are combined
+  // by one wave), and 2 R n complex slots of LDS for the A and Q rows.
+  if (n <= 32) return 1;
+  const int G = std::min(64, (n + 7) / 8);
+  const int R = (n + G - 1) / G;
+  return (2 * R * n <= TD_LDS && R <= TD_ROWS) ? G : 0;
 }
 
 size_t tridiag_scratch_bytes(int n) {

@@ -89,7 +89,7 @@ def _check(T, torch, ctx, H, method):
 
 
 @pytest.mark.parametrize("kind", sorted(CASES))
-@pytest.mark.parametrize("n", [2, 3, 17, 64, 100, 255, 256, 301, 512])
+@pytest.mark.parametrize("n", [2, 3, 17, 32, 33, 64, 100, 255, 256, 301, 512])
 @pytest.mark.parametrize("method", [1, 2, 3])
 def test_eigh_routes(env, kind, n, method):
     T, torch, ctx = env
