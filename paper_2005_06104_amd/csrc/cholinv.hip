@@ -1,0 +1,305 @@
+// Cholesky factorisation G = L L^H of a Hermitian positive definite n x n
+// matrix (n <= 512, row-major complex128) together with L^-1, in one
+// cooperative launch of ceil(n / 32) workgroups.
+//
+// Blocks are 32 x 32.  Workgroup i first forms block row i of L (the row
+// form of the blocked algorithm):
+//     L_ik = (G_ik - sum_{j<k} L_ij L_kj^H) (L_kk^-1)^H    for k < i,
+//     L_ii = chol(G_ii - sum_{j<i} L_ij L_ij^H),
+// waiting for each earlier block row k as it needs it, and publishes L_ii^-1
+// with its row.  It then forms block column i of the inverse,
+//     Linv_ri = -Linv_rr sum_{k=i}^{r-1} L_rk Linv_ki    for r > i,
+// from its own column and the published rows r.  Workgroups only wait on
+// rows of lower index, so the waits form a chain that always ends; every
+// wait is bounded, and a wait that runs out makes the call report failure.
+// The factorisation reports failure when a pivot is not positive and finite.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int CB = 32;            // block size
+constexpr int CNT = 256;          // threads per workgroup
+constexpr int CMAXB = 16;         // block rows at most
+constexpr int CFLAG = 16;         // one 64-byte line per flag
+constexpr unsigned CSPIN = 1u << 22;
+
+struct CholArgs {
+  const double2* G;   // n x n, Hermitian (the lower blocks are read)
+  double2* L;         // n x n out: the lower blocks of L
+  double2* Li;        // n x n out: L^-1 (lower blocks; the upper blocks are zeroed)
+  unsigned* flags;    // CMAXB * CFLAG, zero at launch: row i of L and L_ii^-1 published
+  int* info;          // 0 at launch; 1 not positive definite, 2 a wait ran out
+  int n, nb;
+};
+
+__device__ inline double2 cm(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline double2 cmc(double2 a, double2 b) {   // a * conj(b)
+  return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+__device__ inline int bsize(const CholArgs& a, int i) { return min(CB, a.n - i * CB); }
+
+// wait until block row k has been published; false when the wait ran out or
+// another workgroup gave up
+__device__ bool wait_row(const CholArgs& a, int k, int* s_ok) {
+  if (threadIdx.x == 0) {
+    unsigned polls = 0;
+    int ok = 1;
+    while (__hip_atomic_load(&a.flags[k * CFLAG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      if (__hip_atomic_load(a.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2 || ++polls > CSPIN) {
+        __hip_atomic_store(a.info, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// tile[r][c] = M[(r0 + r) * n + c0 + c] for r < rows, c < cols; zero elsewhere
+__device__ void load_tile(double2 (*t)[CB + 1], const double2* M, int n, int r0, int rows, int c0, int cols) {
+  for (int e = threadIdx.x; e < CB * CB; e += CNT) {
+    const int r = e / CB, c = e % CB;
+    t[r][c] = (r < rows && c < cols) ? M[(size_t)(r0 + r) * n + c0 + c] : double2{0.0, 0.0};
+  }
+}
+
+__device__ void store_tile(const double2 (*t)[CB + 1], double2* M, int n, int r0, int rows, int c0, int cols) {
+  for (int e = threadIdx.x; e < CB * CB; e += CNT) {
+    const int r = e / CB, c = e % CB;
+    if (r < rows && c < cols) M[(size_t)(r0 + r) * n + c0 + c] = t[r][c];
+  }
+}
+
+// acc[q] (the thread's four entries of a 32 x 32 tile: row tid / 8, columns
+// (tid % 8) + 8 q) += sign * (X Y^H) or sign * (X Y)
+template <bool HERM>
+__device__ void tile_mma(double2 acc[4], const double2 (*X)[CB + 1], const double2 (*Y)[CB + 1], double sign) {
+  const int r = threadIdx.x / 8, c0 = threadIdx.x % 8;
+#pragma unroll 4
+  for (int k = 0; k < CB; ++k) {
+    const double2 x = X[r][k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + 8 * q;
+      const double2 p = HERM ? cmc(x, Y[c][k]) : cm(x, Y[k][c]);
+      acc[q].x += sign * p.x;
+      acc[q].y += sign * p.y;
+    }
+  }
+}
+
+__device__ void acc_to_tile(const double2 acc[4], double2 (*t)[CB + 1]) {
+  const int r = threadIdx.x / 8, c0 = threadIdx.x % 8;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[r][c0 + 8 * q] = acc[q];
+}
+
+__device__ void tile_to_acc(const double2 (*t)[CB + 1], double2 acc[4]) {
+  const int r = threadIdx.x / 8, c0 = threadIdx.x % 8;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = t[r][c0 + 8 * q];
+}
+
+__global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
+  __shared__ double2 tS[CB][CB + 1], tX[CB][CB + 1], tY[CB][CB + 1];
+  __shared__ int s_ok, s_fail;
+  const int i = blockIdx.x, n = a.n;
+  const int mi = bsize(a, i), r0 = i * CB;
+  double2 acc[4], accD[4];
+  // the diagonal block's update, accumulated as each L_ik is formed
+  load_tile(tS, a.G, n, r0, mi, r0, mi);
+  __syncthreads();
+  tile_to_acc(tS, accD);
+  __syncthreads();
+
+  // ---- block row i of L
+  for (int k = 0; k < i; ++k) {
+    if (!wait_row(a, k, &s_ok)) return;
+    const int mk = bsize(a, k);
+    load_tile(tS, a.G, n, r0, mi, k * CB, mk);
+    __syncthreads();
+    tile_to_acc(tS, acc);
+    for (int j = 0; j < k; ++j) {
+      load_tile(tX, a.L, n, r0, mi, j * CB, CB);        // L_ij
+      load_tile(tY, a.L, n, k * CB, mk, j * CB, CB);    // L_kj
+      __syncthreads();
+      tile_mma<true>(acc, tX, tY, -1.0);
+      __syncthreads();
+    }
+    acc_to_tile(acc, tS);
+    load_tile(tY, a.Li, n, k * CB, mk, k * CB, mk);     // L_kk^-1
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+    tile_mma<true>(acc, tS, tY, 1.0);                   // S (L_kk^-1)^H
+    __syncthreads();
+    acc_to_tile(acc, tX);
+    __syncthreads();
+    store_tile(tX, a.L, n, r0, mi, k * CB, mk);
+    tile_mma<true>(accD, tX, tX, -1.0);                 // D -= L_ik L_ik^H
+    __syncthreads();
+  }
+  acc_to_tile(accD, tS);
+  if (threadIdx.x == 0) s_fail = 0;
+  __syncthreads();
+  // Wave 0 factorises the block (lower, in tS; the strict upper part still
+  // holds D) and forms its inverse (in tY); the lanes of one wave see each
+  // other's LDS stores in program order, so the steps need no workgroup
+  // barrier.
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int bad = 0;
+    // left-looking: column c of L from the dot products of the rows r >= c
+    // with row c over the finished columns (row r on lanes r and r + 32, each
+    // adding every other term)
+    const int rr = lane & 31, part = lane >> 5;
+    for (int c = 0; c < mi; ++c) {
+      double2 t{0.0, 0.0};
+      if (rr >= c && rr < mi)
+        for (int k = part; k < c; k += 2) {
+          const double2 p = cmc(tS[rr][k], tS[c][k]);
+          t.x += p.x;
+          t.y += p.y;
+        }
+      t.x += __shfl_xor(t.x, 32);
+      t.y += __shfl_xor(t.y, 32);
+      const double d = tS[c][c].x - __shfl(t.x, c);
+      const bool good = d > 0.0 && isfinite(d);
+      bad |= good ? 0 : 1;
+      const double l = good ? sqrt(d) : 1.0, il = 1.0 / l;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (part == 0 && rr > c && rr < mi) {
+        const double2 v = tS[rr][c];
+        tS[rr][c] = double2{(v.x - t.x) * il, (v.y - t.y) * il};
+      }
+      if (lane == c) tS[c][c] = double2{l, 0.0};
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // zero above the diagonal and outside the block
+    for (int e = lane; e < CB * CB; e += 64) {
+      const int r = e / CB, c = e % CB;
+      if (c > r || r >= mi || c >= mi) tS[r][c] = double2{0.0, 0.0};
+      tY[r][c] = double2{0.0, 0.0};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // L^-1 by forward substitution, column j on lanes j and j + 32 (each
+    // lane adds every other term; a shuffle joins the halves)
+    {
+      const int j = lane & 31, part = lane >> 5;
+      const bool act = j < mi;
+      double2 xj = double2{0.0, 0.0};
+      if (act && part == 0) {
+        xj = double2{1.0 / tS[j][j].x, 0.0};
+        tY[j][j] = xj;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int r = 1; r < mi; ++r) {
+        // x_r (column j, r > j) = -(sum_{s=j}^{r-1} L[r][s] x_s) / L[r][r]
+        double2 t{0.0, 0.0};
+        if (act && r > j)
+          for (int q = j + part; q < r; q += 2) {
+            const double2 p = cm(tS[r][q], tY[q][j]);
+            t.x += p.x;
+            t.y += p.y;
+          }
+        t.x += __shfl_xor(t.x, 32);
+        t.y += __shfl_xor(t.y, 32);
+        if (act && r > j && part == 0) {
+          const double ir = 1.0 / tS[r][r].x;
+          tY[r][j] = double2{-t.x * ir, -t.y * ir};
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    if (lane == 0) s_fail = bad;
+  }
+  __syncthreads();
+  store_tile(tS, a.L, n, r0, mi, r0, mi);
+  store_tile(tY, a.Li, n, r0, mi, r0, mi);
+  if (s_fail && threadIdx.x == 0) __hip_atomic_store(a.info, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&a.flags[i * CFLAG], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+
+  // ---- block column i of L^-1 (zero above the diagonal block)
+  for (int r = 0; r < i; ++r) {
+    for (int e = threadIdx.x; e < CB * CB; e += CNT) {
+      const int y = e / CB, x = e % CB;
+      if (y < bsize(a, r) && x < mi) a.Li[(size_t)(r * CB + y) * n + r0 + x] = double2{0.0, 0.0};
+    }
+  }
+  for (int r = i + 1; r < a.nb; ++r) {
+    if (!wait_row(a, r, &s_ok)) return;
+    const int mr = bsize(a, r);
+    for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+    for (int k = i; k < r; ++k) {
+      const int mk = bsize(a, k);
+      load_tile(tX, a.L, n, r * CB, mr, k * CB, mk);    // L_rk
+      load_tile(tY, a.Li, n, k * CB, mk, r0, mi);       // Linv_ki (own column)
+      __syncthreads();
+      tile_mma<false>(acc, tX, tY, 1.0);
+      __syncthreads();
+    }
+    acc_to_tile(acc, tS);
+    load_tile(tX, a.Li, n, r * CB, mr, r * CB, mr);     // Linv_rr
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+    tile_mma<false>(acc, tX, tS, -1.0);
+    __syncthreads();
+    acc_to_tile(acc, tY);
+    __syncthreads();
+    store_tile(tY, a.Li, n, r * CB, mr, r0, mi);
+    __syncthreads();
+  }
+}
+
+__global__ void cholinv_reset_kernel(unsigned* flags, int nf, int* info) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nf) flags[t] = 0u;
+  if (t == 0) *info = 0;
+}
+
+}  // namespace
+
+namespace kern {
+
+int cholinv_max_n() { return CB * CMAXB; }
+
+size_t cholinv_scratch_bytes() { return sizeof(unsigned) * CMAXB * CFLAG + 256; }
+
+hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int* info, void* scratch) {
+  if (n < 1 || n > CB * CMAXB || !scratch || !info) return hipErrorInvalidValue;
+  CholArgs a{};
+  a.G = static_cast<const double2*>(G);
+  a.L = static_cast<double2*>(L);
+  a.Li = static_cast<double2*>(Linv);
+  a.flags = static_cast<unsigned*>(scratch);
+  a.info = info;
+  a.n = n;
+  a.nb = (n + CB - 1) / CB;
+  const int nf = CMAXB * CFLAG;
+  hipLaunchKernelGGL(cholinv_reset_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.flags, nf, a.info);
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(cholinv_kernel), dim3(a.nb), dim3(CNT), args, 0,
+                                    s);
+}
+
+}  // namespace kern

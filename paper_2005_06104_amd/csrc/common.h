@@ -153,6 +153,15 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
 // scratch holds tridiag_eig_scratch_bytes(n).  Returns the launch status.
 size_t tridiag_eig_scratch_bytes(int n);
 hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double* Z, void* scratch);
+// Cholesky factorisation G = L L^H of a Hermitian positive definite n x n
+// matrix (row-major complex128, the lower blocks read; n <= cholinv_max_n())
+// with L^-1, in one cooperative launch: L (may be G itself) receives the
+// lower blocks of L, Linv all of L^-1 (zero above the diagonal).  *info
+// (device) becomes 0 on success, 1 when a pivot is not positive and finite,
+// 2 when a wait ran out.  scratch: cholinv_scratch_bytes().
+int cholinv_max_n();
+size_t cholinv_scratch_bytes();
+hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int* info, void* scratch);
 // G <- G - frac * trace(G) * I (Hermitian complex128 n x n)
 void shift_by_trace(hipStream_t s, void* G, int n, double frac);
 // out[j][m] = Z[m][n-1-j] (complex), Z column-major real n x n
@@ -260,16 +269,17 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
 // C (rows <= cols) = L B with B orthonormal rows, L = C B^dagger (rows x rows).
 bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
                            const void* first = nullptr);
-// True when the smallest eigenvalue of the Hermitian positive semidefinite
-// n x n matrix G provably exceeds frac * trace(G): the Cholesky factorisation
-// of G - (frac + 4 n u) trace(G) I succeeds (u the unit roundoff; the margin
-// covers the rounding of the factorisation).  G is overwritten.
-// On success G holds that factor (upper, or lower when `lower`, in the
-// column-major view used by the Cholesky-QR2 routines), which they accept as
-// their first pass (shifted Cholesky-QR: the shifted factor leaves the first
-// iterate's condition number below ~10, and the second pass restores
-// orthonormality).
-bool gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, DBuf& work);
+// Certifies that the smallest eigenvalue of the Hermitian positive
+// semidefinite n x n matrix G exceeds frac * trace(G): the Cholesky
+// factorisation of G - (1.01 frac + 4 n u) trace(G) I succeeds (u the unit
+// roundoff; the margin covers the rounding of the factorisation).  G is
+// overwritten.  Returns NULL when the factorisation fails, else that factor
+// in the form the Cholesky-QR routines take for their first step (shifted
+// Cholesky QR: the shifted factor leaves the first iterate's condition
+// number small, and the second step restores orthonormality): L^-1 in Finv
+// (n x n) for n <= kern::cholinv_max_n(), else rocSOLVER's factor in G
+// (upper, or lower when `lower`, in the column-major view).
+const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work);
 // thin SVD of row-major C (rows x cols): U (rows x k), S (k, host), Vh (k x cols); k = min.
 void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
                   void* Vh, DBuf& work, DBuf& work2);

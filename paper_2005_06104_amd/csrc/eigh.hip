@@ -1,7 +1,8 @@
 // Hermitian eigendecomposition for the mid-size Gram and density matrices of
 // the method (n <= 512): Householder reduction to real tridiagonal form by one
-// cooperative launch, tridiagonal divide and conquer (rocSOLVER), and one
-// MFMA GEMM for the back transformation.
+// cooperative launch, the tridiagonal eigenproblem by divide and conquer
+// (tdeig.hip; rocSOLVER's on request), and one MFMA GEMM for the back
+// transformation.
 //
 // The reduction is the unblocked Householder algorithm (Golub & Van Loan,
 // Matrix Computations, Sec. 8.3.1; the LAPACK xHETD2 scheme with lower

@@ -379,12 +379,12 @@ namespace {
 struct Work {
   tdvp_ctx_s* ctx;
   kern::SplitWorkspaceScope gws;   // split-K scratch of the products issued below
-  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst;
+  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv;
   Scalars sc;
   Lanczos lz;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
-        dvec(c), wsk(c), nsg(c), nst(c), sc(c), lz(c) {}
+        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), sc(c), lz(c) {}
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {
     const size_t b = (size_t)16 * 2 * ml * mr * cb;
@@ -484,10 +484,12 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // certifies it, and the exact factorisation is then the split.
   if (kk == cols && kk <= chi_max) {
     HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)cols * cols * ZB, hipMemcpyDeviceToDevice, s));
-    if (la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false, W.work)) {
+    const void* F = la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false,
+                                             W.cinv.ensure((size_t)cols * cols * ZB), W.work);
+    if (F) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tmpB.p)) return kk;
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F)) return kk;
     }
   }
   std::vector<double> lam;
@@ -536,10 +538,12 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   // certified "nothing to cut" as in split_left
   if (kk == rows && kk <= chi_max) {
     HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)rows * rows * ZB, hipMemcpyDeviceToDevice, s));
-    if (la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true, W.work)) {
+    const void* F = la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true,
+                                             W.cinv.ensure((size_t)rows * rows * ZB), W.work);
+    if (F) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tmpB.p)) return kk;
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F)) return kk;
     }
   }
   std::vector<double> lam;
@@ -1065,9 +1069,11 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     bool done = false;
     if (ml <= D) {
       HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)ml * ml * ZB, hipMemcpyDeviceToDevice, s));
-      if (la::gram_floor_certified(ctx, W.tmpB.p, ml, 1e-10, true, W.work)) {
+      const void* F = la::gram_floor_certified(ctx, W.tmpB.p, ml, 1e-10, true,
+                                               W.cinv.ensure((size_t)ml * ml * ZB), W.work);
+      if (F) {
         W.tmpC.ensure((size_t)ml * ml * ZB);
-        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, W.tmpB.p);
+        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F);
         if (done) r = ml;
       }
     }

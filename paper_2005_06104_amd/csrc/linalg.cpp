@@ -82,15 +82,38 @@ double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth
   return std::isfinite(dev.real()) ? dev.real() : HUGE_VAL;
 }
 
-bool gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, DBuf& work) {
-  if (n < 1) return false;
-  int* dinfo = static_cast<int*>(work.ensure(64));
+namespace {
+
+// One Cholesky factorisation for a Cholesky-QR step: n <= kern::cholinv_max_n()
+// uses the cooperative factorisation with the inverse (L in place of G,
+// L^-1 in Finv; the step is then a GEMM), larger n rocSOLVER zpotrf in place
+// (the step a triangular solve; `lower` selects the factor the row variant
+// needs).  *dinfo (device) is 0 on success.
+bool own_chol(int n) { return n <= kern::cholinv_max_n(); }
+
+void chol_factor(tdvp_ctx_s* ctx, rz* G, int n, rz* Finv, int* dinfo, void* cscr, bool lower) {
+  if (own_chol(n)) {
+    if (kern::cholinv(ctx->stream, G, n, G, Finv, dinfo, cscr) != hipSuccess) {
+      (void)hipGetLastError();
+      TDVP_THROW(TDVP_ERR_DEVICE, "Cholesky factorisation launch failed");
+    }
+  } else {
+    blas_check(rocsolver_zpotrf(ctx->blas, lower ? rocblas_fill_lower : rocblas_fill_upper, n, G, n, dinfo),
+               "zpotrf");
+  }
+}
+
+}  // namespace
+
+const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work) {
+  if (n < 1) return nullptr;
+  char* base = static_cast<char*>(work.ensure(256 + kern::cholinv_scratch_bytes()));
+  int* dinfo = reinterpret_cast<int*>(base);
   kern::shift_by_trace(ctx->stream, G, n, frac * 1.01 + 4.0 * n * 2.220446049250313e-16);
-  // row-major G read column-major is conj(G): definite exactly when G is
-  blas_check(rocsolver_zpotrf(ctx->blas, lower ? rocblas_fill_lower : rocblas_fill_upper, n, static_cast<rz*>(G), n,
-                              dinfo),
-             "zpotrf");
-  return *static_cast<const int*>(ctx->fetch(dinfo, sizeof(int))) == 0;
+  // (row-major G read column-major is conj(G): definite exactly when G is)
+  chol_factor(ctx, static_cast<rz*>(G), n, static_cast<rz*>(Finv), dinfo, base + 256, lower);
+  if (*static_cast<const int*>(ctx->fetch(dinfo, sizeof(int))) != 0) return nullptr;
+  return own_chol(n) ? Finv : G;
 }
 
 // Cholesky QR in two steps (after CholeskyQR2: Yamamoto, Nakatsukasa,
@@ -122,6 +145,8 @@ struct CqrSpace {
   rz* dsum;
   int* dinfo;
   rz* T;
+  rz* Finv;
+  void* cscr;
   int nb;
 };
 
@@ -129,14 +154,18 @@ CqrSpace cqr_space(DBuf& work, int n, long long mat) {
   const size_t nn = (size_t)n * n;
   const int nb = kern::zdots_blocks((long long)nn);
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-  char* base = static_cast<char*>(
-      work.ensure(up(sizeof(rz) * nn) + up(sizeof(rz) * ((size_t)nb + 2)) + up(sizeof(rz) * (size_t)mat)));
+  const size_t oG = 0, oP = oG + up(sizeof(rz) * nn), oT = oP + up(sizeof(rz) * ((size_t)nb + 2)),
+               oF = oT + up(sizeof(rz) * (size_t)mat), oS = oF + up(sizeof(rz) * nn),
+               tot = oS + up(kern::cholinv_scratch_bytes());
+  char* base = static_cast<char*>(work.ensure(tot));
   CqrSpace c;
-  c.G = reinterpret_cast<rz*>(base);
-  c.dpart = reinterpret_cast<rz*>(base + up(sizeof(rz) * nn));
+  c.G = reinterpret_cast<rz*>(base + oG);
+  c.dpart = reinterpret_cast<rz*>(base + oP);
   c.dsum = c.dpart + nb;
   c.dinfo = reinterpret_cast<int*>(c.dsum + 1);
-  c.T = reinterpret_cast<rz*>(base + up(sizeof(rz) * nn) + up(sizeof(rz) * ((size_t)nb + 2)));
+  c.T = reinterpret_cast<rz*>(base + oT);
+  c.Finv = reinterpret_cast<rz*>(base + oF);
+  c.cscr = base + oS;
   c.nb = nb;
   return c;
 }
@@ -164,10 +193,22 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
   rz* X = static_cast<rz*>(A);
   const rz one{1.0, 0.0};
   auto gram = [&] { kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, 0, X, n, 0, 0.0, c.G, n, 0, 1); };
+  // X <- X R^-1 with X^H X = R^H R: X (L^-1)^H by a GEMM with the own factor,
+  // a triangular solve with rocSOLVER's
   auto chol_step = [&](const rz* F) {
-    blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
-                             rocblas_diagonal_non_unit, n, rows, &one, F, n, X, n),
-               "ztrsm");
+    if (own_chol(n)) {
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, n, 1.0, X, n, 0, F, n, 0, 0.0, c.T, n, 0, 1);
+      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper,
+                               rocblas_operation_conjugate_transpose, rocblas_diagonal_non_unit, n, rows, &one, F, n,
+                               X, n),
+                 "ztrsm");
+    }
+  };
+  auto factor = [&]() -> const rz* {
+    chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, false);
+    return own_chol(n) ? c.Finv : c.G;
   };
   HIP_CHECK(hipMemcpyAsync(X, C, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
   kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
@@ -175,8 +216,7 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
     chol_step(static_cast<const rz*>(first));
   } else {
     gram();
-    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_upper, n, c.G, n, c.dinfo), "zpotrf");
-    chol_step(c.G);
+    chol_step(factor());
   }
   int info = 0;
   gram();
@@ -198,8 +238,7 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
     // a second Cholesky step (G holds X^H X - I)
     kern::zshift_diag(s, c.G, n, 1.0, 1.0);
     kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
-    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_upper, n, c.G, n, c.dinfo), "zpotrf");
-    chol_step(c.G);
+    chol_step(factor());
     gram();
     dev = defect(ctx, c, n, &info);
     if (info != 0 || !(dev <= 1e-20)) return false;
@@ -223,10 +262,22 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   auto gram = [&] {
     kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, X, cols, 0, X, cols, 0, 0.0, c.G, n, 0, 1);
   };
+  // X <- L^-1 X with X X^H = L L^H: a GEMM with the own factor's inverse, a
+  // triangular solve with rocSOLVER's
   auto chol_step = [&](const rz* F) {
-    blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_conjugate_transpose,
-                             rocblas_diagonal_non_unit, cols, n, &one, F, n, X, cols),
-               "ztrsm");
+    if (own_chol(n)) {
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, F, n, 0, X, cols, 0, 0.0, c.T, cols, 0, 1);
+      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+    } else {
+      blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower,
+                               rocblas_operation_conjugate_transpose, rocblas_diagonal_non_unit, cols, n, &one, F, n,
+                               X, cols),
+                 "ztrsm");
+    }
+  };
+  auto factor = [&]() -> const rz* {
+    chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, true);
+    return own_chol(n) ? c.Finv : c.G;
   };
   HIP_CHECK(hipMemcpyAsync(X, C, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
   kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
@@ -234,8 +285,7 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
     chol_step(static_cast<const rz*>(first));
   } else {
     gram();
-    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, c.G, n, c.dinfo), "zpotrf");
-    chol_step(c.G);
+    chol_step(factor());
   }
   int info = 0;
   gram();
@@ -255,8 +305,7 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   if (dev > 1e-20) {
     kern::zshift_diag(s, c.G, n, 1.0, 1.0);
     kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
-    blas_check(rocsolver_zpotrf(ctx->blas, rocblas_fill_lower, n, c.G, n, c.dinfo), "zpotrf");
-    chol_step(c.G);
+    chol_step(factor());
     gram();
     dev = defect(ctx, c, n, &info);
     if (info != 0 || !(dev <= 1e-20)) return false;
