@@ -1,18 +1,18 @@
 // Cholesky factorisation G = L L^H of a Hermitian positive definite n x n
 // matrix (n <= 512, row-major complex128) together with L^-1, in one
-// cooperative launch of ceil(n / 32) workgroups.
-//
-// Blocks are 32 x 32.  Workgroup i first forms block row i of L (the row
-// form of the blocked algorithm):
-//     L_ik = (G_ik - sum_{j<k} L_ij L_kj^H) (L_kk^-1)^H    for k < i,
-//     L_ii = chol(G_ii - sum_{j<i} L_ij L_ij^H),
-// waiting for each earlier block row k as it needs it, and publishes L_ii^-1
-// with its row.  It then forms block column i of the inverse,
-//     Linv_ri = -Linv_rr sum_{k=i}^{r-1} L_rk Linv_ki    for r > i,
-// from its own column and the published rows r.  Workgroups only wait on
-// rows of lower index, so the waits form a chain that always ends; every
-// wait is bounded, and a wait that runs out makes the call report failure.
-// The factorisation reports failure when a pivot is not positive and finite.
+// cooperative launch with one workgroup per 32 x 32 block (i, k), k <= i, of
+// the lower triangle (tiled right-looking order, each update applied as soon
+// as its operands exist):
+//     L_ik = (G_ik - sum_{j<k} L_ij L_kj^H) (L_kk^-1)^H           k < i,
+//     L_ii = chol(G_ii - sum_{j<i} L_ij L_ij^H),  with L_ii^-1,
+//     Linv_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij Linv_jk              k < i.
+// A block is published with a flag once written; a workgroup waits only for
+// blocks of lower column index (or, for L^-1, of lower row index in its own
+// column) and for diagonal blocks, so the waits form chains that end.  Only
+// the diagonal chain (one factorisation and inversion of a 32 x 32 block and
+// two block products per block row) is sequential.  Every wait is bounded;
+// one that runs out makes the call report failure.  The factorisation
+// reports failure when a pivot is not positive and finite.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,9 +29,10 @@ constexpr unsigned CSPIN = 1u << 22;
 
 struct CholArgs {
   const double2* G;   // n x n, Hermitian (the lower blocks are read)
-  double2* L;         // n x n out: the lower blocks of L
-  double2* Li;        // n x n out: L^-1 (lower blocks; the upper blocks are zeroed)
-  unsigned* flags;    // CMAXB * CFLAG, zero at launch: row i of L and L_ii^-1 published
+  double2* L;         // n x n out: the lower blocks of L (may be G)
+  double2* Li;        // n x n out: L^-1 (zero above the diagonal)
+  unsigned* fl;       // CMAXB^2 flags, zero at launch: block (i, k) of L published (k = i: with L_ii^-1)
+  unsigned* fi;       // CMAXB^2 flags, zero at launch: block (i, k) of L^-1 published (i > k)
   int* info;          // 0 at launch; 1 not positive definite, 2 a wait ran out
   int n, nb;
 };
@@ -43,13 +44,16 @@ __device__ inline double2 cmc(double2 a, double2 b) {   // a * conj(b)
 
 __device__ inline int bsize(const CholArgs& a, int i) { return min(CB, a.n - i * CB); }
 
-// wait until block row k has been published; false when the wait ran out or
+__device__ inline unsigned* flag_at(unsigned* f, int r, int c) { return f + (r * CMAXB + c) * CFLAG; }
+
+// wait until the flags f1 and f2 are set; false when a wait ran out or
 // another workgroup gave up
-__device__ bool wait_row(const CholArgs& a, int k, int* s_ok) {
+__device__ bool wait_flags(const CholArgs& a, const unsigned* f1, const unsigned* f2, int* s_ok) {
   if (threadIdx.x == 0) {
     unsigned polls = 0;
     int ok = 1;
-    while (__hip_atomic_load(&a.flags[k * CFLAG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+    while (__hip_atomic_load(f1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u ||
+           __hip_atomic_load(f2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
       if (__hip_atomic_load(a.info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2 || ++polls > CSPIN) {
         __hip_atomic_store(a.info, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
@@ -62,6 +66,12 @@ __device__ bool wait_row(const CholArgs& a, int k, int* s_ok) {
   }
   __syncthreads();
   return *s_ok != 0;
+}
+
+// set flag f once the workgroup's stores before the call are done
+__device__ void publish(unsigned* f) {
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // tile[r][c] = M[(r0 + r) * n + c0 + c] for r < rows, c < cols; zero elsewhere
@@ -109,51 +119,12 @@ __device__ void tile_to_acc(const double2 (*t)[CB + 1], double2 acc[4]) {
   for (int q = 0; q < 4; ++q) acc[q] = t[r][c0 + 8 * q];
 }
 
-__global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
-  __shared__ double2 tS[CB][CB + 1], tX[CB][CB + 1], tY[CB][CB + 1];
-  __shared__ int s_ok, s_fail;
-  const int i = blockIdx.x, n = a.n;
-  const int mi = bsize(a, i), r0 = i * CB;
-  double2 acc[4], accD[4];
-  // the diagonal block's update, accumulated as each L_ik is formed
-  load_tile(tS, a.G, n, r0, mi, r0, mi);
-  __syncthreads();
-  tile_to_acc(tS, accD);
-  __syncthreads();
-
-  // ---- block row i of L
-  for (int k = 0; k < i; ++k) {
-    if (!wait_row(a, k, &s_ok)) return;
-    const int mk = bsize(a, k);
-    load_tile(tS, a.G, n, r0, mi, k * CB, mk);
-    __syncthreads();
-    tile_to_acc(tS, acc);
-    for (int j = 0; j < k; ++j) {
-      load_tile(tX, a.L, n, r0, mi, j * CB, CB);        // L_ij
-      load_tile(tY, a.L, n, k * CB, mk, j * CB, CB);    // L_kj
-      __syncthreads();
-      tile_mma<true>(acc, tX, tY, -1.0);
-      __syncthreads();
-    }
-    acc_to_tile(acc, tS);
-    load_tile(tY, a.Li, n, k * CB, mk, k * CB, mk);     // L_kk^-1
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
-    tile_mma<true>(acc, tS, tY, 1.0);                   // S (L_kk^-1)^H
-    __syncthreads();
-    acc_to_tile(acc, tX);
-    __syncthreads();
-    store_tile(tX, a.L, n, r0, mi, k * CB, mk);
-    tile_mma<true>(accD, tX, tX, -1.0);                 // D -= L_ik L_ik^H
-    __syncthreads();
-  }
-  acc_to_tile(accD, tS);
-  if (threadIdx.x == 0) s_fail = 0;
-  __syncthreads();
-  // Wave 0 factorises the block (lower, in tS; the strict upper part still
-  // holds D) and forms its inverse (in tY); the lanes of one wave see each
-  // other's LDS stores in program order, so the steps need no workgroup
-  // barrier.
+// Wave 0 factorises the mi x mi block in tS (the lower part; the strict upper
+// part holds the matrix) in place and forms its inverse in tY; *s_fail
+// becomes 1 when a pivot is not positive and finite.  The lanes of one wave
+// see each other's LDS stores in program order, so the steps need no
+// workgroup barrier.
+__device__ void diag_chol_inv(double2 (*tS)[CB + 1], double2 (*tY)[CB + 1], int mi, int* s_fail) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     int bad = 0;
@@ -229,46 +200,84 @@ __global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    if (lane == 0) s_fail = bad;
+    if (lane == 0) *s_fail = bad;
   }
-  __syncthreads();
-  store_tile(tS, a.L, n, r0, mi, r0, mi);
-  store_tile(tY, a.Li, n, r0, mi, r0, mi);
-  if (s_fail && threadIdx.x == 0) __hip_atomic_store(a.info, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&a.flags[i * CFLAG], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-  // ---- block column i of L^-1 (zero above the diagonal block)
-  for (int r = 0; r < i; ++r) {
-    for (int e = threadIdx.x; e < CB * CB; e += CNT) {
-      const int y = e / CB, x = e % CB;
-      if (y < bsize(a, r) && x < mi) a.Li[(size_t)(r * CB + y) * n + r0 + x] = double2{0.0, 0.0};
-    }
+__global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
+  __shared__ double2 tS[CB][CB + 1], tX[CB][CB + 1], tY[CB][CB + 1];
+  __shared__ int s_ok, s_fail;
+  int i = 0;
+  while ((i + 1) * (i + 2) / 2 <= (int)blockIdx.x) ++i;
+  const int k = (int)blockIdx.x - i * (i + 1) / 2;
+  const int n = a.n, mi = bsize(a, i), mk = bsize(a, k), ri = i * CB, rk = k * CB;
+  double2 acc[4];
+
+  // ---- S = G_ik - sum_{j<k} L_ij L_kj^H (blocks j < k are full)
+  load_tile(tS, a.G, n, ri, mi, rk, mk);
+  __syncthreads();
+  tile_to_acc(tS, acc);
+  for (int j = 0; j < k; ++j) {
+    if (!wait_flags(a, flag_at(a.fl, i, j), flag_at(a.fl, k, j), &s_ok)) return;
+    load_tile(tX, a.L, n, ri, mi, j * CB, CB);                     // L_ij
+    if (i != k) load_tile(tY, a.L, n, rk, mk, j * CB, CB);         // L_kj
+    __syncthreads();
+    tile_mma<true>(acc, tX, i == k ? tX : tY, -1.0);
+    __syncthreads();
   }
-  for (int r = i + 1; r < a.nb; ++r) {
-    if (!wait_row(a, r, &s_ok)) return;
-    const int mr = bsize(a, r);
-    for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
-    for (int k = i; k < r; ++k) {
-      const int mk = bsize(a, k);
-      load_tile(tX, a.L, n, r * CB, mr, k * CB, mk);    // L_rk
-      load_tile(tY, a.Li, n, k * CB, mk, r0, mi);       // Linv_ki (own column)
-      __syncthreads();
-      tile_mma<false>(acc, tX, tY, 1.0);
-      __syncthreads();
-    }
+
+  if (i == k) {
+    // ---- diagonal block: L_ii and L_ii^-1
     acc_to_tile(acc, tS);
-    load_tile(tX, a.Li, n, r * CB, mr, r * CB, mr);     // Linv_rr
+    if (threadIdx.x == 0) s_fail = 0;
     __syncthreads();
-    for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
-    tile_mma<false>(acc, tX, tS, -1.0);
+    diag_chol_inv(tS, tY, mi, &s_fail);
     __syncthreads();
-    acc_to_tile(acc, tY);
+    store_tile(tS, a.L, n, ri, mi, ri, mi);
+    store_tile(tY, a.Li, n, ri, mi, ri, mi);
+    if (s_fail && threadIdx.x == 0) __hip_atomic_store(a.info, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    publish(flag_at(a.fl, i, i));
+    return;
+  }
+
+  // ---- L_ik = S (L_kk^-1)^H, kept in tX
+  if (!wait_flags(a, flag_at(a.fl, k, k), flag_at(a.fl, k, k), &s_ok)) return;
+  acc_to_tile(acc, tS);
+  load_tile(tY, a.Li, n, rk, mk, rk, mk);                            // L_kk^-1
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  tile_mma<true>(acc, tS, tY, 1.0);
+  acc_to_tile(acc, tX);
+  __syncthreads();
+  store_tile(tX, a.L, n, ri, mi, rk, mk);
+  publish(flag_at(a.fl, i, k));
+  for (int e = threadIdx.x; e < CB * CB; e += CNT) {                   // block (k, i) of L^-1
+    const int y = e / CB, x = e % CB;
+    if (y < mk && x < mi) a.Li[(size_t)(rk + y) * n + ri + x] = double2{0.0, 0.0};
+  }
+
+  // ---- Linv_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij Linv_jk (blocks j < i are full)
+  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  tile_mma<false>(acc, tX, tY, 1.0);                                 // j = k: L_ik L_kk^-1
+  __syncthreads();
+  for (int j = k + 1; j < i; ++j) {
+    if (!wait_flags(a, flag_at(a.fl, i, j), flag_at(a.fi, j, k), &s_ok)) return;
+    load_tile(tX, a.L, n, ri, mi, j * CB, CB);                       // L_ij
+    load_tile(tY, a.Li, n, j * CB, CB, rk, mk);                      // Linv_jk
     __syncthreads();
-    store_tile(tY, a.Li, n, r * CB, mr, r0, mi);
+    tile_mma<false>(acc, tX, tY, 1.0);
     __syncthreads();
   }
+  if (!wait_flags(a, flag_at(a.fl, i, i), flag_at(a.fl, i, i), &s_ok)) return;
+  acc_to_tile(acc, tS);
+  load_tile(tX, a.Li, n, ri, mi, ri, mi);                            // L_ii^-1
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  tile_mma<false>(acc, tX, tS, -1.0);
+  acc_to_tile(acc, tY);
+  __syncthreads();
+  store_tile(tY, a.Li, n, ri, mi, rk, mk);
+  publish(flag_at(a.fi, i, k));
 }
 
 __global__ void cholinv_reset_kernel(unsigned* flags, int nf, int* info) {
@@ -283,7 +292,7 @@ namespace kern {
 
 int cholinv_max_n() { return CB * CMAXB; }
 
-size_t cholinv_scratch_bytes() { return sizeof(unsigned) * CMAXB * CFLAG + 256; }
+size_t cholinv_scratch_bytes() { return sizeof(unsigned) * 2 * CMAXB * CMAXB * CFLAG + 256; }
 
 hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int* info, void* scratch) {
   if (n < 1 || n > CB * CMAXB || !scratch || !info) return hipErrorInvalidValue;
@@ -291,15 +300,16 @@ hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int
   a.G = static_cast<const double2*>(G);
   a.L = static_cast<double2*>(L);
   a.Li = static_cast<double2*>(Linv);
-  a.flags = static_cast<unsigned*>(scratch);
+  a.fl = static_cast<unsigned*>(scratch);
+  a.fi = a.fl + CMAXB * CMAXB * CFLAG;
   a.info = info;
   a.n = n;
   a.nb = (n + CB - 1) / CB;
-  const int nf = CMAXB * CFLAG;
-  hipLaunchKernelGGL(cholinv_reset_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.flags, nf, a.info);
+  const int nf = 2 * CMAXB * CMAXB * CFLAG;
+  hipLaunchKernelGGL(cholinv_reset_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.fl, nf, a.info);
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(cholinv_kernel), dim3(a.nb), dim3(CNT), args, 0,
-                                    s);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(cholinv_kernel),
+                                    dim3(a.nb * (a.nb + 1) / 2), dim3(CNT), args, 0, s);
 }
 
 }  // namespace kern
