@@ -13,10 +13,14 @@
 //
 // A library call per column costs a few microseconds of dispatch on this GPU,
 // so the whole reduction is one launch: G workgroups keep the matrix rows
-// (row r on workgroup r % G) and the matching rows of Q in LDS and meet at
-// one grid barrier per column (one flag per workgroup, no shared counter).
-// Every barrier wait is bounded; a wait that runs out raises an error flag
-// that makes every workgroup leave, and the caller then uses another solver.
+// (row r on workgroup r % G) and the matching rows of Q in LDS and exchange
+// per column the vector x = tau A v, the next pivot row and partial sums.
+// The exchange needs no barrier: every published complex is stored as four
+// 64-bit words, each holding 32 bits of the value and the column's tag, and
+// a reader polls the words it needs until all carry the current tag (one
+// memory round trip instead of a flag round trip followed by the data).
+// Every wait is bounded; a wait that runs out raises an error flag that
+// makes every workgroup leave, and the caller then uses another solver.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +33,6 @@ constexpr int TNT = 256;            // threads per workgroup
 constexpr int TD_LDS = 8192;        // complex128 slots for the A and Q rows (128 KiB)
 constexpr int TD_NMAX = 512;
 constexpr int TD_ROWS = 128;        // rows per workgroup at most
-constexpr int FLAG_STRIDE = 16;     // one 64-byte line per workgroup flag
 constexpr unsigned SPIN_LIMIT = 1u << 22;
 
 struct TdArgs {
@@ -37,11 +40,11 @@ struct TdArgs {
   double2* Q;         // n x n out, row-major
   double* D;          // n out
   double* E;          // n-1 out
-  double2* xv;        // 2n scratch: published x = tau A v (two buffers)
-  double2* prow;      // 2n scratch: published pivot row (two buffers)
-  double2* p2;        // 2G scratch: partial x^H v (two buffers)
-  unsigned* flags;    // G * FLAG_STRIDE, zero at launch
-  int* err;           // 0 at launch; 1 when a barrier wait ran out
+  // tagged words (four per complex, zero at launch), two buffers each:
+  unsigned long long* xv;     // published x = tau A v, 2 x n
+  unsigned long long* prow;   // published pivot row, 2 x n
+  unsigned long long* p2;     // partial x^H v per workgroup, 2 x G
+  int* err;                   // 0 at launch; 1 when a wait ran out
   int n, G, R;
 };
 
@@ -59,37 +62,30 @@ __device__ inline double2 wave_sum(double2 v) {
   return v;
 }
 
-// grid barrier, split into arrive and wait
-__device__ inline void bar_arrive(const TdArgs& a, unsigned epoch) {
-  __syncthreads();
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&a.flags[blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Publish v under tag t: the low and high halves of both parts, each with
+// the tag in the upper 32 bits of its word.
+__device__ inline void put_tagged(unsigned long long* w, double2 v, unsigned t) {
+  const unsigned long long tag = (unsigned long long)t << 32;
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(v.x);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(v.y);
+  __hip_atomic_store(w + 0, tag | (bx & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 1, tag | (bx >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 2, tag | (by & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 3, tag | (by >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// wave 0 polls the flags with relaxed loads and orders the later reads of
-// the published data by one acquire fence once every flag has arrived
-__device__ inline bool bar_wait(const TdArgs& a, unsigned epoch, int* s_fail) {
-  if (threadIdx.x < 64) {
-    unsigned polls = 0;
-    bool fail = false;
-    while (true) {
-      bool mine = true;
-      for (int j = threadIdx.x; j < a.G; j += 64)
-        mine = mine && (__hip_atomic_load(&a.flags[j * FLAG_STRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch);
-      if (__all(mine)) break;
-      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++polls > SPIN_LIMIT) {
-        fail = true;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x == 0) {
-      if (fail) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      *s_fail = fail ? 1 : 0;
-    }
-  }
-  __syncthreads();
-  return *s_fail == 0;
+// Read a value published under tag t; false (v untouched) while any of its
+// words still holds an older tag.
+__device__ inline bool get_tagged(const unsigned long long* w, unsigned t, double2* v) {
+  const unsigned long long w0 = __hip_atomic_load(w + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long w1 = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long w2 = __hip_atomic_load(w + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long w3 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((unsigned)(w0 >> 32) != t || (unsigned)(w1 >> 32) != t || (unsigned)(w2 >> 32) != t ||
+      (unsigned)(w3 >> 32) != t)
+    return false;
+  v->x = __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
+  v->y = __longlong_as_double((long long)(((w3 & 0xffffffffull) << 32) | (w2 & 0xffffffffull)));
+  return true;
 }
 
 // Reflector of column k from the pivot row: alpha = conj(row[k+1]),
@@ -122,14 +118,15 @@ __device__ inline double2 hh_v(int c, int k, double2 row_c, double2 sc) {
   return c == k + 1 ? double2{1.0, 0.0} : cmul(double2{row_c.x, -row_c.y}, sc);
 }
 
-// One grid barrier per column.  Every workgroup holds the current pivot row k
+// One exchange per column.  Every workgroup holds the current pivot row k
 // (row k of the partly reduced matrix; column k below the diagonal is its
-// conjugate) and derives the reflector H_k from it.  The barrier gathers
-// x = tau A v from the row owners; the owner of row k+1 also publishes that
-// row, from which every workgroup forms the next pivot row by the rank-2
-// update (and, in the same pass, the norm that the next reflector needs).
-// Published buffers alternate between two copies: a workgroup can be one
-// barrier ahead of the slowest one.
+// conjugate) and derives the reflector H_k from it.  The row owners publish
+// x = tau A v; the owner of row k+1 also publishes that row, from which every
+// workgroup forms the next pivot row by the rank-2 update (and, in the same
+// pass, the norm that the next reflector needs).  Published buffers alternate
+// between two copies, tagged k + 1: a workgroup publishes column k + 1 only
+// after it has read everything of column k, so no copy is overwritten while
+// a reader still needs it.
 __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
   __shared__ double2 sM[TD_LDS];        // A rows [R][n], then Q rows [R][n]
   __shared__ double2 sv[TD_NMAX], sw[TD_NMAX], srow[TD_NMAX];
@@ -167,9 +164,9 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     for (int o = 32; o > 0; o >>= 1) ssq += __shfl_xor(ssq, o);
     if (lane == 0) sred[wave] = ssq;
   }
+  if (tid == 0) s_fail = 0;
   __syncthreads();
 
-  unsigned epoch = 0;
   bool alive = true;
   for (int k = 0; k + 1 < n; ++k) {
     const int par = k & 1;
@@ -187,9 +184,10 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     // rows >= k+1 and tau (Q v) for the accumulation of Q; partial x^H v.
     // v is formed on the fly (the threads of local row 0 also store it).
     // The owner of row k+1 publishes it (before this column's update).
-    double2* xvp = a.xv + (size_t)par * n;
-    double2* rowp = a.prow + (size_t)par * n;
-    double2* p2p = a.p2 + (size_t)par * G;
+    const unsigned tag = (unsigned)k + 1u;
+    unsigned long long* xvp = a.xv + (size_t)par * 4 * n;
+    unsigned long long* rowp = a.prow + (size_t)par * 4 * n;
+    unsigned long long* p2p = a.p2 + (size_t)par * 4 * G;
     double2 tqs{0.0, 0.0};
     if (rj < nrow) {
       double2 sa{0.0, 0.0}, sq{0.0, 0.0};
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         double2 contrib{0.0, 0.0};
         if (r >= k + 1) {
           const double2 x = cmul(tau, sa), vr = hh_v(r, k, srow[r], sc);
-          xvp[r] = x;
+          put_tagged(xvp + 4 * (size_t)r, x, tag);
           contrib = double2{x.x * vr.x + x.y * vr.y, x.x * vr.y - x.y * vr.x};   // conj(x) v
         }
         s_part[rj] = contrib;
@@ -223,7 +221,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     }
     if ((k + 1) % G == g) {
       const int j = (k + 1) / G;
-      for (int c = k + 1 + tid; c < n; c += TNT) rowp[c] = sA[j * n + c];
+      for (int c = k + 1 + tid; c < n; c += TNT) put_tagged(rowp + 4 * (size_t)c, sA[j * n + c], tag);
     }
     __syncthreads();
     if (tid == 0) {
@@ -232,9 +230,8 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         t.x += s_part[j].x;
         t.y += s_part[j].y;
       }
-      p2p[g] = t;
+      put_tagged(p2p + 4 * (size_t)g, t, tag);
     }
-    bar_arrive(a, ++epoch);
 
     // ---- while the others arrive: Q <- Q H_k = Q - tau (Q v) v^H on the own rows
     if (rj < nrow) {
@@ -245,7 +242,42 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         qrow[c].y -= d.y;
       }
     }
-    if (!bar_wait(a, epoch, &s_fail)) {
+    // ---- gather this column's x, pivot row and partial sums as they arrive
+    constexpr int NQ = (TD_NMAX + TNT - 1) / TNT;
+    double2 xq[NQ], rq[NQ], tp{0.0, 0.0};
+    {
+      bool gx[NQ], gr[NQ], gp = lane >= G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c = k + 1 + tid + q * TNT;
+        gx[q] = gr[q] = c >= n;
+        xq[q] = rq[q] = double2{0.0, 0.0};
+      }
+      unsigned polls = 0;
+      while (true) {
+        bool done = true;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int c = k + 1 + tid + q * TNT;
+          if (!gx[q]) gx[q] = get_tagged(xvp + 4 * (size_t)c, tag, &xq[q]);
+          if (!gr[q]) gr[q] = get_tagged(rowp + 4 * (size_t)c, tag, &rq[q]);
+          done = done && gx[q] && gr[q];
+        }
+        if (!gp) gp = get_tagged(p2p + 4 * (size_t)lane, tag, &tp);
+        done = done && gp;
+        if (done) break;
+        ++polls;
+        if (polls > SPIN_LIMIT ||
+            ((polls & 63u) == 0 && __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+          __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_fail = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+    if (s_fail) {
       alive = false;
       break;
     }
@@ -253,16 +285,8 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     // ---- w = x - (tau/2)(x^H v) v; next pivot row and its norm beyond
     // column k+2; A <- A - v w^H - w v^H on the own rows
     {
-      double2 xq[(TD_NMAX + TNT - 1) / TNT], rq[(TD_NMAX + TNT - 1) / TNT];
-#pragma unroll
-      for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
-        const int c = k + 1 + tid + q * TNT;
-        xq[q] = c < n ? xvp[c] : double2{0.0, 0.0};
-        rq[q] = c < n ? rowp[c] : double2{0.0, 0.0};
-      }
       // x^H v: every wave sums the published partials in the same order
-      double2 t = lane < G ? p2p[lane] : double2{0.0, 0.0};
-      t = wave_sum(t);
+      const double2 t = wave_sum(tp);
       const double2 a2x = cmul(tau, t);
       const double2 a2{-0.5 * a2x.x, -0.5 * a2x.y};
 #pragma unroll
@@ -336,9 +360,10 @@ __global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* __restrict
   for (int i = threadIdx.x; i < n; i += TNT) G[(size_t)i * n + i].x -= mu;
 }
 
-__global__ void u32_fill_kernel(unsigned* p, unsigned v, int n) {
+__global__ void td_reset_kernel(unsigned* w, int nw, int* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  if (i < nw) w[i] = 0u;
+  if (i == 0) *err = 0;
 }
 
 }  // namespace
@@ -360,7 +385,7 @@ int tridiag_groups(int n) {
 
 size_t tridiag_scratch_bytes(int n) {
   const int G = tridiag_groups(n);
-  return sizeof(double2) * (4 * (size_t)n + 2 * (size_t)G) + sizeof(unsigned) * (size_t)G * FLAG_STRIDE + 256;
+  return sizeof(unsigned long long) * 4 * (4 * (size_t)n + 2 * (size_t)G) + 256;
 }
 
 hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err) {
@@ -372,17 +397,16 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
   a.Q = static_cast<double2*>(Q);
   a.D = D;
   a.E = E;
-  a.xv = reinterpret_cast<double2*>(p);     // two buffers of n each
-  a.prow = a.xv + 2 * (size_t)n;
-  a.p2 = a.prow + 2 * (size_t)n;            // two buffers of G
-  a.flags = reinterpret_cast<unsigned*>(a.p2 + 2 * (size_t)G);
+  a.xv = reinterpret_cast<unsigned long long*>(p);     // two buffers of n complex each
+  a.prow = a.xv + 8 * (size_t)n;
+  a.p2 = a.prow + 8 * (size_t)n;                        // two buffers of G
   a.err = err;
   a.n = n;
   a.G = G;
   a.R = (n + G - 1) / G;
-  const int nf = G * FLAG_STRIDE;
-  hipLaunchKernelGGL(u32_fill_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.flags, 0u, nf);
-  hipLaunchKernelGGL(u32_fill_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(err), 0u, 1);
+  const int nw = 2 * 4 * (4 * n + 2 * G);   // 32-bit halves of the tagged words
+  hipLaunchKernelGGL(td_reset_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, reinterpret_cast<unsigned*>(a.xv), nw,
+                     err);
   void* args[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_kernel), dim3(G), dim3(TNT), args, 0, s);
 }
