@@ -8,12 +8,22 @@
 
 #define TDVP_VERSION "tdvp-mi355x 0.1 (gfx950)"
 
+thread_local tdvp_ctx_s* tl_exec_ctx = nullptr;
+
+// free the buffers the workers dropped while their streams still ran
+static void flush_deferred(tdvp_ctx_s* ctx) {
+  for (tdvp_ctx_s* w : ctx->workers) {
+    for (auto& f : w->deferred_frees) f.first->dfree(f.second);
+    w->deferred_frees.clear();
+  }
+}
+
 void* tdvp_ctx_s::dalloc(size_t bytes) {
   void* p = nullptr;
   if (async_alloc) {
-    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    hipError_t e = hipMallocFromPoolAsync(&p, bytes, pool, stream);
     if (e != hipSuccess || !p)
-      TDVP_THROW(TDVP_ERR_ALLOC, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+      TDVP_THROW(TDVP_ERR_ALLOC, "stream-ordered allocation of " + std::to_string(bytes) + " bytes failed");
   } else if (alloc) {
     p = alloc(bytes, user);
     if (!p) TDVP_THROW(TDVP_ERR_ALLOC, "device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -33,18 +43,23 @@ void tdvp_ctx_s::dfree(void* p) {
 }
 
 void tdvp_ctx_s::ensure_workers(int n) {
-  if (workers.empty() && n > 0) {
-    // keep freed stream-ordered memory in the pool between calls
-    hipMemPool_t pool = nullptr;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
-      uint64_t thr = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
+  if (!worker_pool && n > 0) {
+    // one stream-ordered pool of the context's own for its workers, keeping
+    // freed memory between calls; destroyed with the workers (the device's
+    // default pool is left untouched)
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    HIP_CHECK(hipMemPoolCreate(&worker_pool, &props));
+    uint64_t thr = UINT64_MAX;
+    HIP_CHECK(hipMemPoolSetAttribute(worker_pool, hipMemPoolAttrReleaseThreshold, &thr));
   }
   while ((int)workers.size() < n) {
     auto* w = new tdvp_ctx_s();
     w->device = device;
     w->async_alloc = true;
+    w->pool = worker_pool;
     w->owns_stream = true;
     workers.push_back(w);
     HIP_CHECK(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
@@ -60,6 +75,9 @@ void tdvp_ctx_s::ensure_workers(int n) {
 }
 
 void tdvp_ctx_s::destroy_workers() {
+  for (tdvp_ctx_s* w : workers)
+    if (w->stream) (void)hipStreamSynchronize(w->stream);
+  flush_deferred(this);
   for (tdvp_ctx_s* w : workers) {
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     w->dfree(w->split_ws);
@@ -76,6 +94,11 @@ void tdvp_ctx_s::destroy_workers() {
     delete w;
   }
   workers.clear();
+  if (worker_pool) {
+    (void)hipMemPoolTrimTo(worker_pool, 0);
+    (void)hipMemPoolDestroy(worker_pool);
+    worker_pool = nullptr;
+  }
 }
 
 void tdvp_ctx_s::sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
@@ -144,7 +167,9 @@ void for_instances(tdvp_ctx_s* ctx, int n, F&& f) {
   for (int w = 0; w < nw; ++w) {
     threads.emplace_back([&, w] {
       tdvp_ctx_s* wc = ctx->workers[w];
+      tl_exec_ctx = wc;
       if (hipSetDevice(ctx->device) != hipSuccess) {
+        tl_exec_ctx = nullptr;
         for (int j = w; j < n; j += nw) errs[j] = std::make_exception_ptr(TdvpError(TDVP_ERR_DEVICE, "hipSetDevice"));
         return;
       }
@@ -159,9 +184,11 @@ void for_instances(tdvp_ctx_s* ctx, int n, F&& f) {
         }
       }
       (void)hipStreamSynchronize(wc->stream);
+      tl_exec_ctx = nullptr;
     });
   }
   for (auto& t : threads) t.join();
+  flush_deferred(ctx);
   for (auto& e : errs)
     if (e) std::rethrow_exception(e);
 }

@@ -42,10 +42,12 @@ struct tdvp_ctx_s {
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
   // Worker contexts for calls on several independent instances: each owns a
   // stream, a rocBLAS handle and events, and allocates stream-ordered memory
-  // (hipMallocAsync on its own stream).  Created on first use, kept until the
+  // (on its own stream, from a pool the parent owns).  Created on first use, kept until the
   // parent is destroyed.
   bool owns_stream = false;
   bool async_alloc = false;
+  hipMemPool_t pool = nullptr;          // the pool async allocations come from (workers)
+  hipMemPool_t worker_pool = nullptr;   // the parent's own pool for its workers
   std::vector<tdvp_ctx_s*> workers;
   // Split-K partial products of the GEMMs issued for this context: one
   // buffer of SPLIT_WS_BYTES, allocated on first use, freed with the context.
@@ -75,7 +77,21 @@ struct tdvp_ctx_s {
   void sync();
   void ensure_workers(int n);
   void destroy_workers();
+  // Buffers of other contexts released while this worker context runs an
+  // instance: their memory may still be in use on this context's stream, so
+  // they are freed (through their own context) only after that stream has
+  // been synchronised.
+  std::vector<std::pair<tdvp_ctx_s*, void*>> deferred_frees;
 };
+
+// The worker context the calling host thread runs an instance on (null
+// outside worker threads).  Device buffers owned by another context (a
+// state's tensors, which the parent context allocated) may be read by work
+// still queued on the worker's stream when the worker drops them; the
+// parent's allocator does not see that stream, so such buffers are freed
+// only after the worker's stream has finished, and a buffer regrown on a
+// worker thread is allocated from the worker's own stream-ordered pool.
+extern thread_local tdvp_ctx_s* tl_exec_ctx;
 
 // Growable device buffer owned through the context's allocator.
 struct DBuf {
@@ -93,7 +109,12 @@ struct DBuf {
   }
   ~DBuf() { release(); }
   void release() {
-    if (p && ctx) ctx->dfree(p);
+    if (p && ctx) {
+      if (tl_exec_ctx && tl_exec_ctx != ctx)
+        tl_exec_ctx->deferred_frees.emplace_back(ctx, p);
+      else
+        ctx->dfree(p);
+    }
     p = nullptr;
     cap = 0;
   }
@@ -102,6 +123,7 @@ struct DBuf {
     if (bytes == 0) bytes = 16;
     if (bytes > cap) {
       release();
+      if (tl_exec_ctx) ctx = tl_exec_ctx;
       p = ctx->dalloc(bytes);
       cap = bytes;
     }
@@ -210,13 +232,11 @@ int zdots_blocks(long long n);
 // w[x] += sign * sum_j c[j] V[j*ldv + x]   (c complex128 on device)
 void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c,
               double sign, long long n);
-// zcombine, then out[0] = |w|^2 (real part) in the same launch (the block that
-// finishes last reduces); partial holds zcombine_norm_blocks(n) complex
-// entries; counter: a device unsigned that is zero before the call and is
-// left at zero
+// zcombine, with the per-block partial sums of |w|^2 (real parts) left in
+// partial[0 .. zcombine_norm_blocks(n))
 int zcombine_norm_blocks(long long n);
 void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
-                   long long n, void* partial, unsigned* counter, void* out);
+                   long long n, void* partial);
 // dst = a * src (complex scalar a)
 void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n);
 // precision conversions (complex)
@@ -235,8 +255,9 @@ void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long l
 void zhermitize(hipStream_t s, void* A, long long n);
 // fill complex with value
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
-// w /= sqrt(Re nrm2[0]) with nrm2 on the device (complex128)
-void zscale_invnorm(hipStream_t s, void* w, const void* nrm2, long long n);
+// w /= |w| with |w|^2 the sum of the np partial sums left by zcombine_norm
+// (real parts); out[0] receives |w|^2 (complex128, imaginary part zero)
+void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
 // G = a G + b I (n x n complex128)

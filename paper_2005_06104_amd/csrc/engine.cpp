@@ -72,9 +72,8 @@ struct Lanczos {
     scal.ensure(256 * ZB);
     double2* S = scal.as<double2>();
     // S: [0, 64) and [64, 128) the two projection passes, 128 |w|^2, 192.. the
-    // result coefficients, 255 the completion counter of the fused norm
-    unsigned* ncounter = reinterpret_cast<unsigned*>(S + 255);
-    kern::zfill(ctx->stream, S + 255, zc(0.0, 0.0), 1, ZB);
+    // result coefficients
+    const int nnp = kern::zcombine_norm_blocks(n);
     char* Vb = static_cast<char*>(V.ensure((size_t)(maxit + 1) * n * ZB));
     auto vec = [&](int j) { return static_cast<void*>(Vb + (size_t)j * n * ZB); };
 
@@ -107,8 +106,9 @@ struct Lanczos {
     };
     auto phase = [&](int e) { return std::exp(zc(0.0, -1.0) * dt * dd[e]); };
     // Iteration j on the device: w = H v_j, classical Gram-Schmidt twice
-    // against v_0..v_j, |w|^2, an asynchronous copy of the scalars to the
-    // host, and v_{j+1} = w / |w| with the norm read on the device.  The next
+    // against v_0..v_j (the second pass leaves per-block sums of |w|^2),
+    // v_{j+1} = w / |w| with |w|^2 summed by the scaling kernel itself, and an
+    // asynchronous copy of the scalars to the host.  The next
     // iteration is enqueued before the host reads this one's scalars, so the
     // device never waits for the convergence test; when the test stops the
     // recurrence, the one extra iteration is discarded.
@@ -120,10 +120,10 @@ struct Lanczos {
       kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S);
       kern::zcombine(ctx->stream, w, Vb, n, j + 1, S, -1.0, n);
       kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S + 64);
-      kern::zcombine_norm(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n, partial.p, ncounter, S + 128);
+      kern::zcombine_norm(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n, partial.p);
+      kern::zscale_invnorm(ctx->stream, w, partial.p, nnp, S + 128, n);
       // the first-pass projections (alpha_j = <v_j|H v_j>) and |w|^2
       staged[j & 1] = static_cast<const zc*>(ctx->stage_async(j & 1, S, 129 * ZB));
-      kern::zscale_invnorm(ctx->stream, w, S + 128, n);
     };
     enqueue(0);
     for (int j = 0; j < maxit; ++j) {

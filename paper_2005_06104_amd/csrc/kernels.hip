@@ -649,10 +649,8 @@ __global__ __launch_bounds__(VNT) void zdots_final_kernel(const double2* __restr
 // that starts at zero and is left at zero) adds them with a fixed tree.
 __global__ __launch_bounds__(VNT) void zcombine_norm_kernel(double2* __restrict__ w, const double2* __restrict__ V,
                                                              long long ldv, int nv, const double2* __restrict__ c,
-                                                             double sign, long long n, double2* __restrict__ partial,
-                                                             unsigned* counter, double2* __restrict__ out) {
+                                                             double sign, long long n, double2* __restrict__ partial) {
   __shared__ double sh[VNT / 64];
-  __shared__ int s_last;
   const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
   double sq = 0.0;
   if (x < n) {
@@ -670,21 +668,7 @@ __global__ __launch_bounds__(VNT) void zcombine_norm_kernel(double2* __restrict_
     sq = o.x * o.x + o.y * o.y;
   }
   const double t = block_sum(sq, sh);
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = make_double2(t, 0.0);
-    __threadfence();
-    s_last = atomicAdd(counter, 1u) == gridDim.x - 1 ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += VNT) acc += partial[b].x;
-  const double tot = block_sum(acc, sh);
-  if (threadIdx.x == 0) {
-    out[0] = make_double2(tot, 0.0);
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(t, 0.0);
 }
 
 __global__ __launch_bounds__(VNT) void zcombine_kernel(double2* __restrict__ w, const double2* __restrict__ V,
@@ -714,10 +698,24 @@ __global__ void zscale_kernel(double2* __restrict__ dst, const double2* __restri
 }
 
 // dst = src / sqrt(Re *nrm2): normalisation by a norm that is still on the device
-__global__ void zscale_invnorm_kernel(double2* __restrict__ w, const double2* __restrict__ nrm2, long long n) {
-  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// every block sums the np partial norms in the same fixed order, so all
+// agree on |w|^2; block 0 also stores it
+__global__ __launch_bounds__(VNT) void zscale_invnorm_kernel(double2* __restrict__ w,
+                                                              const double2* __restrict__ partial, int np,
+                                                              double2* __restrict__ out, long long n) {
+  __shared__ double sh[VNT / 64];
+  __shared__ double s_tot;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < np; b += VNT) acc += partial[b].x;
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    s_tot = t;
+    if (blockIdx.x == 0) out[0] = make_double2(t, 0.0);
+  }
+  __syncthreads();
+  const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
   if (x >= n) return;
-  const double inv = 1.0 / sqrt(fmax(nrm2->x, 0.0));
+  const double inv = 1.0 / sqrt(fmax(s_tot, 0.0));
   const double2 v = w[x];
   w[x] = make_double2(v.x * inv, v.y * inv);
 }
@@ -926,11 +924,11 @@ void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, l
 int zcombine_norm_blocks(long long n) { return (int)std::max<long long>(1, nblk(n, VNT)); }
 
 void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
-                   long long n, void* partial, unsigned* counter, void* out) {
+                   long long n, void* partial) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zcombine_norm_kernel, dim3(zcombine_norm_blocks(n)), dim3(VNT), 0, s, static_cast<double2*>(w),
                      static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(c), sign, n,
-                     static_cast<double2*>(partial), counter, static_cast<double2*>(out));
+                     static_cast<double2*>(partial));
   HIP_CHECK(hipGetLastError());
 }
 
@@ -949,10 +947,10 @@ void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n) {
   HIP_CHECK(hipGetLastError());
 }
 
-void zscale_invnorm(hipStream_t s, void* w, const void* nrm2, long long n) {
+void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(zscale_invnorm_kernel, dim3(nblk(n)), dim3(256), 0, s, static_cast<double2*>(w),
-                     static_cast<const double2*>(nrm2), n);
+  hipLaunchKernelGGL(zscale_invnorm_kernel, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
+                     static_cast<const double2*>(partial), np, static_cast<double2*>(out), n);
   HIP_CHECK(hipGetLastError());
 }
 
