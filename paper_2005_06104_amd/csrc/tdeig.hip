@@ -82,7 +82,8 @@ __device__ inline double wave_max(double v) {
 
 // ---------------------------------------------------------------- set-up
 // Scaled, torn, padded diagonal (the leaves' eigenvalues), couplings and
-// Z = I.  One workgroup.
+// Z = I.  Every workgroup finds the same scale (the same reduction order);
+// workgroup 0 writes the vectors, all share the rows of Z.
 __global__ __launch_bounds__(1024) void dc_init_kernel(const double* __restrict__ D, const double* __restrict__ E,
                                                        int n, int P, double* __restrict__ d, double* __restrict__ Ep,
                                                        double* __restrict__ Z, double* __restrict__ scale_out) {
@@ -107,15 +108,19 @@ __global__ __launch_bounds__(1024) void dc_init_kernel(const double* __restrict_
   if (!(scale > 0.0)) scale = 1.0;   // zero matrix (or NaN: caught by the caller's checks)
   const double inv = 1.0 / scale;
   const double bound = md * inv + 2.0 * me * inv;
-  if (tid == 0) *scale_out = scale;
-  for (int i = tid; i < P; i += blockDim.x) {
-    const double e = i < n - 1 ? E[i] * inv : 0.0;
-    const double em = (i >= 1 && i - 1 < n - 1) ? E[i - 1] * inv : 0.0;
-    Ep[i] = e;
-    // every m in [1, P) is a cut of exactly one level: subtract both couplings
-    d[i] = i < n ? D[i] * inv - e - em : 2.0 * bound + 1.0;
+  if (blockIdx.x == 0) {
+    if (tid == 0) *scale_out = scale;
+    for (int i = tid; i < P; i += blockDim.x) {
+      const double e = i < n - 1 ? E[i] * inv : 0.0;
+      const double em = (i >= 1 && i - 1 < n - 1) ? E[i - 1] * inv : 0.0;
+      Ep[i] = e;
+      // every m in [1, P) is a cut of exactly one level: subtract both couplings
+      d[i] = i < n ? D[i] * inv - e - em : 2.0 * bound + 1.0;
+    }
   }
-  for (long long k = tid; k < (long long)P * P; k += blockDim.x) Z[k] = (k / P == k % P) ? 1.0 : 0.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + tid; k < (long long)P * P;
+       k += (long long)gridDim.x * blockDim.x)
+    Z[k] = (k / P == k % P) ? 1.0 : 0.0;
 }
 
 // ---------------------------------------------------------------- level kernels
@@ -556,7 +561,8 @@ hipError_t tridiag_eig(hipStream_t st, double* D, const double* E, int n, double
   a.colpos = take_i(P);
   a.cnt = take_i(2 * (size_t)P);
   a.E = Ep;
-  hipLaunchKernelGGL(dc_init_kernel, dim3(1), dim3(1024), 0, st, D, E, n, P, dA, Ep, Z0, scale);
+  const int init_blocks = std::max(1, std::min(64, P * P / 4096));
+  hipLaunchKernelGGL(dc_init_kernel, dim3(init_blocks), dim3(1024), 0, st, D, E, n, P, dA, Ep, Z0, scale);
   double* zc = Z0;
   double* zn = Z1;
   double* dc = dA;
