@@ -1,6 +1,6 @@
 // Cholesky factorisation G = L L^H of a Hermitian positive definite n x n
 // matrix (n <= 512, row-major complex128) together with L^-1, in one
-// cooperative launch with one workgroup per 32 x 32 block (i, k), k <= i, of
+// cooperative launch with one workgroup per 16 x 16 block (i, k), k <= i, of
 // the lower triangle (tiled right-looking order, each update applied as soon
 // as its operands exist):
 //     L_ik = (G_ik - sum_{j<k} L_ij L_kj^H) (L_kk^-1)^H           k < i,
@@ -9,8 +9,9 @@
 // A block is published with a flag once written; a workgroup waits only for
 // blocks of lower column index (or, for L^-1, of lower row index in its own
 // column) and for diagonal blocks, so the waits form chains that end.  Only
-// the diagonal chain (one factorisation and inversion of a 32 x 32 block and
-// two block products per block row) is sequential.  Every wait is bounded;
+// the diagonal chain (one factorisation and inversion of a 16 x 16 block and
+// two block products per block row) is sequential: small blocks keep its
+// column steps few and short.  Every wait is bounded;
 // one that runs out makes the call report failure.  The factorisation
 // reports failure when a pivot is not positive and finite.
 #include <hip/hip_runtime.h>
@@ -21,9 +22,13 @@
 
 namespace {
 
-constexpr int CB = 32;            // block size
+constexpr int CB = 16;            // block size
 constexpr int CNT = 256;          // threads per workgroup
-constexpr int CMAXB = 16;         // block rows at most
+constexpr int CMAXB = 32;         // block rows at most
+constexpr int CENT = CB * CB / CNT;   // tile entries per thread
+constexpr int CPR = CNT / CB;         // threads per tile row
+constexpr int NPART = 64 / CB;        // lanes per row in the one-wave steps
+static_assert(CENT >= 1 && CB * CB == CENT * CNT && NPART >= 1, "tile mapping");
 constexpr int CFLAG = 16;         // one 64-byte line per flag
 constexpr unsigned CSPIN = 1u << 22;
 
@@ -89,17 +94,17 @@ __device__ void store_tile(const double2 (*t)[CB + 1], double2* M, int n, int r0
   }
 }
 
-// acc[q] (the thread's four entries of a 32 x 32 tile: row tid / 8, columns
-// (tid % 8) + 8 q) += sign * (X Y^H) or sign * (X Y)
+// acc[q] (the thread's entries of a tile: row tid / CPR, columns
+// (tid % CPR) + CPR q) += sign * (X Y^H) or sign * (X Y)
 template <bool HERM>
-__device__ void tile_mma(double2 acc[4], const double2 (*X)[CB + 1], const double2 (*Y)[CB + 1], double sign) {
-  const int r = threadIdx.x / 8, c0 = threadIdx.x % 8;
+__device__ void tile_mma(double2 acc[CENT], const double2 (*X)[CB + 1], const double2 (*Y)[CB + 1], double sign) {
+  const int r = threadIdx.x / CPR, c0 = threadIdx.x % CPR;
 #pragma unroll 4
   for (int k = 0; k < CB; ++k) {
     const double2 x = X[r][k];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = c0 + 8 * q;
+    for (int q = 0; q < CENT; ++q) {
+      const int c = c0 + CPR * q;
       const double2 p = HERM ? cmc(x, Y[c][k]) : cm(x, Y[k][c]);
       acc[q].x += sign * p.x;
       acc[q].y += sign * p.y;
@@ -107,16 +112,16 @@ __device__ void tile_mma(double2 acc[4], const double2 (*X)[CB + 1], const doubl
   }
 }
 
-__device__ void acc_to_tile(const double2 acc[4], double2 (*t)[CB + 1]) {
-  const int r = threadIdx.x / 8, c0 = threadIdx.x % 8;
+__device__ void acc_to_tile(const double2 acc[CENT], double2 (*t)[CB + 1]) {
+  const int r = threadIdx.x / CPR, c0 = threadIdx.x % CPR;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) t[r][c0 + 8 * q] = acc[q];
+  for (int q = 0; q < CENT; ++q) t[r][c0 + CPR * q] = acc[q];
 }
 
-__device__ void tile_to_acc(const double2 (*t)[CB + 1], double2 acc[4]) {
-  const int r = threadIdx.x / 8, c0 = threadIdx.x % 8;
+__device__ void tile_to_acc(const double2 (*t)[CB + 1], double2 acc[CENT]) {
+  const int r = threadIdx.x / CPR, c0 = threadIdx.x % CPR;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = t[r][c0 + 8 * q];
+  for (int q = 0; q < CENT; ++q) acc[q] = t[r][c0 + CPR * q];
 }
 
 // Wave 0 factorises the mi x mi block in tS (the lower part; the strict upper
@@ -129,19 +134,22 @@ __device__ void diag_chol_inv(double2 (*tS)[CB + 1], double2 (*tY)[CB + 1], int 
     const int lane = threadIdx.x;
     int bad = 0;
     // left-looking: column c of L from the dot products of the rows r >= c
-    // with row c over the finished columns (row r on lanes r and r + 32, each
-    // adding every other term)
-    const int rr = lane & 31, part = lane >> 5;
+    // with row c over the finished columns (row r on the NPART lanes
+    // r + CB p, each adding every NPART-th term)
+    const int rr = lane % CB, part = lane / CB;
     for (int c = 0; c < mi; ++c) {
       double2 t{0.0, 0.0};
       if (rr >= c && rr < mi)
-        for (int k = part; k < c; k += 2) {
+        for (int k = part; k < c; k += NPART) {
           const double2 p = cmc(tS[rr][k], tS[c][k]);
           t.x += p.x;
           t.y += p.y;
         }
-      t.x += __shfl_xor(t.x, 32);
-      t.y += __shfl_xor(t.y, 32);
+#pragma unroll
+      for (int o = CB; o < 64; o <<= 1) {
+        t.x += __shfl_xor(t.x, o);
+        t.y += __shfl_xor(t.y, o);
+      }
       const double d = tS[c][c].x - __shfl(t.x, c);
       const bool good = d > 0.0 && isfinite(d);
       bad |= good ? 0 : 1;
@@ -167,10 +175,10 @@ __device__ void diag_chol_inv(double2 (*tS)[CB + 1], double2 (*tY)[CB + 1], int 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // L^-1 by forward substitution, column j on lanes j and j + 32 (each
-    // lane adds every other term; a shuffle joins the halves)
+    // L^-1 by forward substitution, column j on the NPART lanes j + CB p
+    // (each adds every NPART-th term; shuffles join them)
     {
-      const int j = lane & 31, part = lane >> 5;
+      const int j = lane % CB, part = lane / CB;
       const bool act = j < mi;
       double2 xj = double2{0.0, 0.0};
       if (act && part == 0) {
@@ -184,13 +192,16 @@ __device__ void diag_chol_inv(double2 (*tS)[CB + 1], double2 (*tY)[CB + 1], int 
         // x_r (column j, r > j) = -(sum_{s=j}^{r-1} L[r][s] x_s) / L[r][r]
         double2 t{0.0, 0.0};
         if (act && r > j)
-          for (int q = j + part; q < r; q += 2) {
+          for (int q = j + part; q < r; q += NPART) {
             const double2 p = cm(tS[r][q], tY[q][j]);
             t.x += p.x;
             t.y += p.y;
           }
-        t.x += __shfl_xor(t.x, 32);
-        t.y += __shfl_xor(t.y, 32);
+#pragma unroll
+        for (int o = CB; o < 64; o <<= 1) {
+          t.x += __shfl_xor(t.x, o);
+          t.y += __shfl_xor(t.y, o);
+        }
         if (act && r > j && part == 0) {
           const double ir = 1.0 / tS[r][r].x;
           tY[r][j] = double2{-t.x * ir, -t.y * ir};
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
   while ((i + 1) * (i + 2) / 2 <= (int)blockIdx.x) ++i;
   const int k = (int)blockIdx.x - i * (i + 1) / 2;
   const int n = a.n, mi = bsize(a, i), mk = bsize(a, k), ri = i * CB, rk = k * CB;
-  double2 acc[4];
+  double2 acc[CENT];
 
   // ---- S = G_ik - sum_{j<k} L_ij L_kj^H (blocks j < k are full)
   load_tile(tS, a.G, n, ri, mi, rk, mk);
@@ -245,7 +256,7 @@ __global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
   acc_to_tile(acc, tS);
   load_tile(tY, a.Li, n, rk, mk, rk, mk);                            // L_kk^-1
   __syncthreads();
-  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  for (int q = 0; q < CENT; ++q) acc[q] = double2{0.0, 0.0};
   tile_mma<true>(acc, tS, tY, 1.0);
   acc_to_tile(acc, tX);
   __syncthreads();
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
   }
 
   // ---- Linv_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij Linv_jk (blocks j < i are full)
-  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  for (int q = 0; q < CENT; ++q) acc[q] = double2{0.0, 0.0};
   tile_mma<false>(acc, tX, tY, 1.0);                                 // j = k: L_ik L_kk^-1
   __syncthreads();
   for (int j = k + 1; j < i; ++j) {
@@ -272,7 +283,7 @@ __global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
   acc_to_tile(acc, tS);
   load_tile(tX, a.Li, n, ri, mi, ri, mi);                            // L_ii^-1
   __syncthreads();
-  for (int q = 0; q < 4; ++q) acc[q] = double2{0.0, 0.0};
+  for (int q = 0; q < CENT; ++q) acc[q] = double2{0.0, 0.0};
   tile_mma<false>(acc, tX, tS, -1.0);
   acc_to_tile(acc, tY);
   __syncthreads();
