@@ -55,8 +55,13 @@ def cpu_baseline(w, seconds: float, chi_probe: int):
     t0 = time.perf_counter()
     n = 0
     bonds = 1
-    while time.perf_counter() - t0 < seconds and n < w.n_steps:
+    last = 0.0
+    # whole steps only; another step is started only when it should end within
+    # the budget (steps grow with the bond dimension: taken as twice the last)
+    while n < w.n_steps and (n == 0 or time.perf_counter() - t0 + 2.0 * last <= seconds):
+        ts = time.perf_counter()
         psi, _ = gse.gse_step(psi, Ws, Wop, w.dt, w.k, w.eps_K, w.eps_M, w.eps, w.chi_max, 1e-12, 30, w.normalize)
+        last = time.perf_counter() - ts
         n += 1
         bonds = max(t.shape[2] for t in psi)
     el = time.perf_counter() - t0
