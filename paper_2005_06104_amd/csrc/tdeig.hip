@@ -22,10 +22,12 @@
 // The size is padded to a power of two P with decoupled diagonal entries
 // above the Gershgorin bound (their couplings are zero, so they deflate in
 // every merge and end up as the top P - n eigenvalues).  The matrix is scaled
-// by max(|D|, |E|) first.  Every level is five launches over all the nodes of
-// the level: preparation (z, sort, deflation), secular roots, zhat and final
-// order, eigenvector columns, and the block-diagonal product with the
-// children's eigenvectors.  Nothing waits on another workgroup.
+// by max(|D|, |E|) first.  The levels with nodes of up to 32 entries run in
+// one launch (one workgroup per 32 leaves, in LDS); every larger level is
+// five launches over all the nodes of the level: preparation (z, sort,
+// deflation), secular roots, zhat and final order, eigenvector columns, and
+// the block-diagonal product with the children's eigenvectors.  Nothing waits
+// on another workgroup.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -503,6 +505,254 @@ __global__ void dc_finish_kernel(const double* __restrict__ d, const double* __r
   Zout[idx] = Z[(size_t)m * P + j];
 }
 
+// ---------------------------------------------------------------- small levels
+// Levels with nodes of 2 .. DC_LEAF entries, all in one launch: one workgroup
+// per block of DC_LEAF leaves, everything in LDS, one thread per entry, root or
+// node (the same steps as the level kernels, with the sums over a node's at
+// most DC_LEAF poles taken serially by one thread).  On return d holds each
+// block's eigenvalues (ascending) and Z its diagonal block of eigenvectors
+// (the rest of Z is the identity's zeros).
+constexpr int DC_LEAF = 32;
+constexpr int DC_LNT = 256;
+static_assert(DC_LNT >= DC_LEAF * 2, "leaf kernel thread count");
+
+__global__ __launch_bounds__(DC_LNT) void dc_leaf_kernel(double* __restrict__ dg, const double* __restrict__ E,
+                                                         double* __restrict__ Z, int P, int S0) {
+  __shared__ double sZ[DC_LEAF][DC_LEAF + 1], sZn[DC_LEAF][DC_LEAF + 1], sM[DC_LEAF][DC_LEAF + 1];
+  __shared__ double sY[DC_LEAF][DC_LEAF + 1];
+  __shared__ double sd[DC_LEAF], sdn[DC_LEAF], s_ds[DC_LEAF], s_zs[DC_LEAF], s_dk[DC_LEAF], s_zk[DC_LEAF];
+  __shared__ double s_rc[DC_LEAF], s_rs[DC_LEAF], s_tau[DC_LEAF], s_zhat[DC_LEAF];
+  __shared__ int s_perm[DC_LEAF], s_inv[DC_LEAF], s_nd[DC_LEAF], s_rp[DC_LEAF], s_rq[DC_LEAF], s_orig[DC_LEAF];
+  __shared__ int s_col[DC_LEAF];
+  __shared__ int s_K[DC_LEAF], s_m[DC_LEAF];
+  __shared__ double s_sgn[DC_LEAF], s_r[DC_LEAF];
+  const int tid = threadIdx.x, g0 = blockIdx.x * S0;
+  constexpr double EPS = 2.220446049250313e-16;
+  for (int e = tid; e < S0 * S0; e += DC_LNT) sZ[e / S0][e % S0] = (e / S0 == e % S0) ? 1.0 : 0.0;
+  for (int j = tid; j < S0; j += DC_LNT) sd[j] = dg[g0 + j];
+  __syncthreads();
+  for (int s = 2; s <= S0; s *= 2) {
+    const int h = s / 2, nn = S0 / s;
+    // ---- node constants; merge the two sorted children; z
+    if (tid < nn) {
+      const double coupling = E[g0 + tid * s + h - 1];
+      s_sgn[tid] = coupling >= 0.0 ? 1.0 : -1.0;
+      s_r[tid] = 2.0 * fabs(coupling);
+    }
+    __syncthreads();
+    if (tid < S0) {
+      const int b = tid / s, j = tid % s, base = b * s;
+      const double sgn = s_sgn[b];
+      const bool left = j < h;
+      const double v = sgn * sd[base + j];
+      const int jo = left ? j : j - h;
+      const int po = sgn > 0.0 ? jo : h - 1 - jo;
+      const int ob = left ? base + h : base;
+      int lo = 0, hi = h;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int idx = sgn > 0.0 ? mid : h - 1 - mid;
+        const double w = sgn * sd[ob + idx];
+        const bool before = left ? (w < v) : (w <= v);
+        if (before) lo = mid + 1;
+        else hi = mid;
+      }
+      const int rank = po + lo;
+      const int zrow = left ? base + h - 1 : base + h;
+      s_ds[base + rank] = v;
+      s_zs[base + rank] = sZ[zrow][base + j] * 0.70710678118654752440;
+      s_perm[base + rank] = j;
+      s_inv[base + rank] = -1;
+    }
+    __syncthreads();
+    // ---- deflation, one thread per node (at most DC_LEAF entries)
+    if (tid < nn) {
+      const int base = tid * s;
+      const double r = s_r[tid];
+      double dm = 0.0;
+      for (int j = 0; j < s; ++j) dm = fmax(dm, fabs(s_ds[base + j]));
+      const double tol = 8.0 * EPS * fmax(dm, r);
+      int K = 0, m = 0, pj = -1;
+      for (int j = 0; j < s; ++j) {
+        if (!(r * fabs(s_zs[base + j]) > tol)) continue;   // z entry deflated
+        if (pj < 0) {
+          pj = j;
+          continue;
+        }
+        const double sv = s_zs[base + pj], cv = s_zs[base + j];
+        const double ta = hypot(cv, sv);
+        const double c = cv / ta, sn = -sv / ta;
+        if (fabs((s_ds[base + j] - s_ds[base + pj]) * c * sn) <= tol) {
+          s_zs[base + j] = ta;
+          s_zs[base + pj] = 0.0;
+          s_rp[base + m] = pj;
+          s_rq[base + m] = j;
+          s_rc[base + m] = c;
+          s_rs[base + m] = sn;
+          ++m;
+          const double dp = s_ds[base + pj], dj = s_ds[base + j];
+          s_ds[base + pj] = dp * c * c + dj * sn * sn;
+          s_ds[base + j] = dp * sn * sn + dj * c * c;
+        } else {
+          s_nd[base + K] = pj;
+          s_inv[base + pj] = K;
+          ++K;
+        }
+        pj = j;
+      }
+      if (pj >= 0) {
+        s_nd[base + K] = pj;
+        s_inv[base + pj] = K;
+        ++K;
+      }
+      for (int i = 0; i < K; ++i) {
+        s_dk[base + i] = s_ds[base + s_nd[base + i]];
+        s_zk[base + i] = s_zs[base + s_nd[base + i]];
+      }
+      s_K[tid] = K;
+      s_m[tid] = m;
+    }
+    __syncthreads();
+    // ---- secular roots, one thread per (node, root)
+    if (tid < S0) {
+      const int b = tid / s, i = tid % s, base = b * s;
+      const int K = s_K[b];
+      if (i < K) {
+        const double r = s_r[b];
+        const double* dk = s_dk + base;
+        const double* zk = s_zk + base;
+        double zsum = 0.0;
+        for (int j = 0; j < K; ++j) zsum += zk[j] * zk[j];
+        const bool last = i + 1 == K;
+        const double lo_abs = dk[i];
+        const double hi_abs = last ? dk[i] + r * zsum : dk[i + 1];
+        const double mid = 0.5 * (lo_abs + hi_abs);
+        double fm = 0.0;
+        for (int j = 0; j < K; ++j) fm += zk[j] * zk[j] / (dk[j] - mid);
+        fm = 1.0 + r * fm;
+        const int o = (!last && fm <= 0.0) ? i + 1 : i;
+        const double dorg = dk[o];
+        double lo, hi;
+        if (o == i) {
+          lo = 0.0;
+          hi = last ? r * zsum : mid - dorg;
+        } else {
+          lo = mid - dorg;
+          hi = 0.0;
+        }
+        double tau = 0.5 * (lo + hi);
+        for (int it = 0; it < DC_SECULAR_MAXIT; ++it) {
+          double f = 0.0, fp = 0.0, fa = 0.0;
+          for (int j = 0; j < K; ++j) {
+            const double q = 1.0 / ((dk[j] - dorg) - tau);
+            const double tt = zk[j] * zk[j] * q;
+            f += tt;
+            fp += tt * q;
+            fa += fabs(tt);
+          }
+          f = 1.0 + r * f;
+          fp = r * fp;
+          fa = 1.0 + r * fa;
+          if (fabs(f) <= 8.0 * EPS * fa) break;
+          if (f > 0.0) hi = tau;
+          else lo = tau;
+          if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+          double tn = tau - tau * f / (f + tau * fp);
+          if (!(isfinite(tn) && tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+          if (fabs(tn - tau) <= 2.0 * EPS * fabs(tau)) {
+            tau = tn;
+            break;
+          }
+          tau = tn;
+        }
+        s_orig[base + i] = o;
+        s_tau[base + i] = tau;
+      }
+    }
+    __syncthreads();
+    // ---- zhat_j (j < K) and the final column of every sorted position
+    if (tid < S0) {
+      const int b = tid / s, j = tid % s, base = b * s;
+      const int K = s_K[b];
+      const double sgn = s_sgn[b], r = s_r[b];
+      const double* dk = s_dk + base;
+      if (j < K) {
+        const double dj = dk[j];
+        double p = 1.0;
+        for (int i = 0; i < K; ++i) {
+          const double num = (dk[s_orig[base + i]] - dj) + s_tau[base + i];
+          p *= i == j ? num / r : num / (dk[i] - dj);
+        }
+        s_zhat[base + j] = copysign(sqrt(fabs(p)), s_zk[base + j]);
+      }
+      auto value = [&](int q) {
+        const int ri = s_inv[base + q];
+        const double l = ri >= 0 ? dk[s_orig[base + ri]] + s_tau[base + ri] : s_ds[base + q];
+        return sgn * l;
+      };
+      const double vj = value(j);
+      int c = 0;
+      for (int q = 0; q < s; ++q) {
+        const double vq = value(q);
+        c += (vq < vj || (vq == vj && q < j)) ? 1 : 0;
+      }
+      s_col[base + j] = c;
+      sdn[base + c] = vj;
+    }
+    __syncthreads();
+    // ---- eigenvector columns (rotations undone), scattered into the node block of M
+    if (tid < S0) {
+      const int b = tid / s, p = tid % s, base = b * s;
+      double* y = sY[tid];
+      for (int q = 0; q < s; ++q) y[q] = 0.0;
+      const int ri = s_inv[base + p];
+      if (ri < 0) {
+        y[p] = 1.0;
+      } else {
+        const int K = s_K[b];
+        const double* dk = s_dk + base;
+        const double dorg = dk[s_orig[base + ri]], ta = s_tau[base + ri];
+        double nrm = 0.0;
+        for (int j = 0; j < K; ++j) {
+          const double v = s_zhat[base + j] / ((dk[j] - dorg) - ta);
+          y[s_nd[base + j]] = v;
+          nrm += v * v;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int j = 0; j < K; ++j) y[s_nd[base + j]] *= inv;
+      }
+      for (int t = s_m[b] - 1; t >= 0; --t) {
+        const int pp = s_rp[base + t], qq = s_rq[base + t];
+        const double c = s_rc[base + t], sn = s_rs[base + t];
+        const double yp = y[pp], yq = y[qq];
+        y[pp] = c * yp - sn * yq;
+        y[qq] = sn * yp + c * yq;
+      }
+      const int col = s_col[base + p];
+      for (int q = 0; q < s; ++q) sM[base + s_perm[base + q]][base + col] = y[q];
+    }
+    __syncthreads();
+    // ---- Zn = blockdiag(children) M on each node block
+    for (int e = tid; e < S0 * s; e += DC_LNT) {
+      const int row = e / s, cl = e % s;
+      const int base = row / s * s;
+      const int k0 = base + ((row - base) < h ? 0 : h);
+      double acc = 0.0;
+      for (int k = k0; k < k0 + h; ++k) acc += sZ[row][k] * sM[k][base + cl];
+      sZn[row][base + cl] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < S0 * S0; e += DC_LNT) {
+      const int row = e / S0, cl = e % S0;
+      if (row / s == cl / s) sZ[row][cl] = sZn[row][cl];
+    }
+    for (int j = tid; j < S0; j += DC_LNT) sd[j] = sdn[j];
+    __syncthreads();
+  }
+  for (int j = tid; j < S0; j += DC_LNT) dg[g0 + j] = sd[j];
+  for (int e = tid; e < S0 * S0; e += DC_LNT) Z[(size_t)(g0 + e / S0) * P + g0 + e % S0] = sZ[e / S0][e % S0];
+}
+
 int dc_pad(int n) {
   int P = 1;
   while (P < n) P *= 2;
@@ -567,7 +817,9 @@ hipError_t tridiag_eig(hipStream_t st, double* D, const double* E, int n, double
   double* zn = Z1;
   double* dc = dA;
   double* dn = dB;
-  for (int s = 2; s <= P; s *= 2) {
+  const int S0 = std::min(DC_LEAF, P);
+  if (P >= 2) hipLaunchKernelGGL(dc_leaf_kernel, dim3(P / S0), dim3(DC_LNT), 0, st, dA, Ep, Z0, P, S0);
+  for (int s = 2 * S0; s <= P; s *= 2) {
     a.s = s;
     a.d = dc;
     a.dnew = dn;
