@@ -232,11 +232,17 @@ int zdots_blocks(long long n);
 // w[x] += sign * sum_j c[j] V[j*ldv + x]   (c complex128 on device)
 void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c,
               double sign, long long n);
-// zcombine, with the per-block partial sums of |w|^2 (real parts) left in
-// partial[0 .. zcombine_norm_blocks(n))
+// number of blocks (and of partial sums of |w|^2) of zcombine_p over n entries
 int zcombine_norm_blocks(long long n);
-void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
-                   long long n, void* partial);
+// the first stage of zdots alone: partial[b * nv + j] over chunks b < nb
+void zdots_partial(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
+                   int nb);
+// w[x] += sign * sum_j c_j V[j*ldv + x] with c_j = sum_b partial[b * nv + j]
+// (zdots_partial's output, summed by every block in the same order; nv <= 64);
+// cout (may be null) receives c; npart (may be null) the per-block partial
+// sums of |w|^2 (zcombine_norm_blocks(n) entries, for zscale_invnorm)
+void zcombine_p(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* partial, int nb,
+                double sign, long long n, void* cout, void* npart);
 // dst = a * src (complex scalar a)
 void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n);
 // precision conversions (complex)
@@ -255,7 +261,7 @@ void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long l
 void zhermitize(hipStream_t s, void* A, long long n);
 // fill complex with value
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
-// w /= |w| with |w|^2 the sum of the np partial sums left by zcombine_norm
+// w /= |w| with |w|^2 the sum of the np partial sums left by zcombine_p
 // (real parts); out[0] receives |w|^2 (complex128, imaginary part zero)
 void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128

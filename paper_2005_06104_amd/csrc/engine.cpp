@@ -68,12 +68,14 @@ struct Lanczos {
     *unconv = false;
     if (n <= 0) return 0;
     const int nb = kern::zdots_blocks(n);
-    partial.ensure((size_t)std::max<long long>((long long)nb * (maxit + 1), kern::zcombine_norm_blocks(n)) * ZB);
+    const int nnp = kern::zcombine_norm_blocks(n);
+    // the dot-product partials, then the partial sums of |w|^2
+    partial.ensure(((size_t)nb * (maxit + 1) + (size_t)nnp) * ZB);
+    double2* npart = partial.as<double2>() + (size_t)nb * (maxit + 1);
     scal.ensure(256 * ZB);
     double2* S = scal.as<double2>();
     // S: [0, 64) and [64, 128) the two projection passes, 128 |w|^2, 192.. the
     // result coefficients
-    const int nnp = kern::zcombine_norm_blocks(n);
     char* Vb = static_cast<char*>(V.ensure((size_t)(maxit + 1) * n * ZB));
     auto vec = [&](int j) { return static_cast<void*>(Vb + (size_t)j * n * ZB); };
 
@@ -106,7 +108,9 @@ struct Lanczos {
     };
     auto phase = [&](int e) { return std::exp(zc(0.0, -1.0) * dt * dd[e]); };
     // Iteration j on the device: w = H v_j, classical Gram-Schmidt twice
-    // against v_0..v_j (the second pass leaves per-block sums of |w|^2),
+    // against v_0..v_j (each pass: partial dot products, then the update,
+    // whose blocks sum the partials themselves; the second pass leaves
+    // per-block sums of |w|^2),
     // v_{j+1} = w / |w| with |w|^2 summed by the scaling kernel itself, and an
     // asynchronous copy of the scalars to the host.  The next
     // iteration is enqueued before the host reads this one's scalars, so the
@@ -117,11 +121,11 @@ struct Lanczos {
       void* w = vec(j + 1);
       if (timer) timer->cur = j & 1;
       mv(vec(j), w);
-      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S);
-      kern::zcombine(ctx->stream, w, Vb, n, j + 1, S, -1.0, n);
-      kern::zdots(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb, S + 64);
-      kern::zcombine_norm(ctx->stream, w, Vb, n, j + 1, S + 64, -1.0, n, partial.p);
-      kern::zscale_invnorm(ctx->stream, w, partial.p, nnp, S + 128, n);
+      kern::zdots_partial(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb);
+      kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S, nullptr);
+      kern::zdots_partial(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb);
+      kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S + 64, npart);
+      kern::zscale_invnorm(ctx->stream, w, npart, nnp, S + 128, n);
       // the first-pass projections (alpha_j = <v_j|H v_j>) and |w|^2
       staged[j & 1] = static_cast<const zc*>(ctx->stage_async(j & 1, S, 129 * ZB));
     };

@@ -644,33 +644,6 @@ __global__ __launch_bounds__(VNT) void zdots_final_kernel(const double2* __restr
   if (threadIdx.x == 0) out[j] = make_double2(tr, ti);
 }
 
-// w += sign * V c, then |w|^2 into out (real part), in the same launch: every
-// block stores its partial sum, and the block that finishes last (a counter
-// that starts at zero and is left at zero) adds them with a fixed tree.
-__global__ __launch_bounds__(VNT) void zcombine_norm_kernel(double2* __restrict__ w, const double2* __restrict__ V,
-                                                             long long ldv, int nv, const double2* __restrict__ c,
-                                                             double sign, long long n, double2* __restrict__ partial) {
-  __shared__ double sh[VNT / 64];
-  const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
-  double sq = 0.0;
-  if (x < n) {
-    double sr = 0.0, si = 0.0;
-    for (int j = 0; j < nv; ++j) {
-      const double2 cj = c[j];
-      const double2 v = V[(long long)j * ldv + x];
-      sr += cj.x * v.x - cj.y * v.y;
-      si += cj.x * v.y + cj.y * v.x;
-    }
-    double2 o = w[x];
-    o.x += sign * sr;
-    o.y += sign * si;
-    w[x] = o;
-    sq = o.x * o.x + o.y * o.y;
-  }
-  const double t = block_sum(sq, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(t, 0.0);
-}
-
 __global__ __launch_bounds__(VNT) void zcombine_kernel(double2* __restrict__ w, const double2* __restrict__ V,
                                                         long long ldv, int nv, const double2* __restrict__ c,
                                                         double sign, long long n) {
@@ -698,6 +671,56 @@ __global__ void zscale_kernel(double2* __restrict__ dst, const double2* __restri
 }
 
 // dst = src / sqrt(Re *nrm2): normalisation by a norm that is still on the device
+// w += sign * V c with c_j the sum of the nb partial dot products
+// partial[b * nv + j] (zdots_partial_kernel's layout): every block forms c
+// itself, in the same fixed order, so no separate reduction launch is
+// needed; block 0 also stores c in cout.  With NORM, the block's partial sum
+// of |w|^2 goes to npart.
+constexpr int ZC_MAXV = 64;
+template <bool NORM>
+__global__ __launch_bounds__(VNT) void zcombine_p_kernel(double2* __restrict__ w, const double2* __restrict__ V,
+                                                         long long ldv, int nv, const double2* __restrict__ partial,
+                                                         int nb, double sign, long long n, double2* __restrict__ cout,
+                                                         double2* __restrict__ npart) {
+  __shared__ double2 sc[ZC_MAXV];
+  __shared__ double sh[VNT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = wv; j < nv; j += VNT / 64) {
+    double re = 0.0, im = 0.0;
+    for (int b = lane; b < nb; b += 64) {
+      const double2 p = partial[(long long)b * nv + j];
+      re += p.x;
+      im += p.y;
+    }
+    re = warp_sum(re);
+    im = warp_sum(im);
+    if (lane == 0) sc[j] = make_double2(re, im);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && cout)
+    for (int j = threadIdx.x; j < nv; j += VNT) cout[j] = sc[j];
+  const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
+  double sq = 0.0;
+  if (x < n) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      const double2 cj = sc[j];
+      const double2 v = V[(long long)j * ldv + x];
+      sr += cj.x * v.x - cj.y * v.y;
+      si += cj.x * v.y + cj.y * v.x;
+    }
+    double2 o = w[x];
+    o.x += sign * sr;
+    o.y += sign * si;
+    w[x] = o;
+    sq = o.x * o.x + o.y * o.y;
+  }
+  if (NORM) {
+    const double t = block_sum(sq, sh);
+    if (threadIdx.x == 0) npart[blockIdx.x] = make_double2(t, 0.0);
+  }
+}
+
 // every block sums the np partial norms in the same fixed order, so all
 // agree on |w|^2; block 0 also stores it
 __global__ __launch_bounds__(VNT) void zscale_invnorm_kernel(double2* __restrict__ w,
@@ -923,12 +946,26 @@ void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, l
 
 int zcombine_norm_blocks(long long n) { return (int)std::max<long long>(1, nblk(n, VNT)); }
 
-void zcombine_norm(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c, double sign,
-                   long long n, void* partial) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(zcombine_norm_kernel, dim3(zcombine_norm_blocks(n)), dim3(VNT), 0, s, static_cast<double2*>(w),
-                     static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(c), sign, n,
-                     static_cast<double2*>(partial));
+void zdots_partial(hipStream_t s, const void* V, long long ldv, int nv, const void* w, long long n, void* partial,
+                   int nb) {
+  if (nv <= 0) return;
+  hipLaunchKernelGGL(zdots_partial_kernel<true>, dim3(nb, nv), dim3(VNT), 0, s, static_cast<const double2*>(V), ldv,
+                     nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
+  HIP_CHECK(hipGetLastError());
+}
+
+void zcombine_p(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* partial, int nb,
+                double sign, long long n, void* cout, void* npart) {
+  if (n <= 0 || nv <= 0) return;
+  if (nv > ZC_MAXV) TDVP_THROW(TDVP_ERR_ARG, "zcombine_p: at most 64 vectors");
+  if (npart)
+    hipLaunchKernelGGL(zcombine_p_kernel<true>, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
+                       static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(partial), nb, sign, n,
+                       static_cast<double2*>(cout), static_cast<double2*>(npart));
+  else
+    hipLaunchKernelGGL(zcombine_p_kernel<false>, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
+                       static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(partial), nb, sign, n,
+                       static_cast<double2*>(cout), nullptr);
   HIP_CHECK(hipGetLastError());
 }
 
