@@ -22,8 +22,8 @@
 // The size is padded to a power of two P with decoupled diagonal entries
 // above the Gershgorin bound (their couplings are zero, so they deflate in
 // every merge and end up as the top P - n eigenvalues).  The matrix is scaled
-// by max(|D|, |E|) first.  The levels with nodes of up to 32 entries run in
-// one launch (one workgroup per 32 leaves, in LDS); every larger level is
+// by max(|D|, |E|) first.  The levels with nodes of up to 16 entries run in
+// one launch (one workgroup per 16 leaves, in LDS); every larger level is
 // five launches over all the nodes of the level: preparation (z, sort,
 // deflation), secular roots, zhat and final order, eigenvector columns, and
 // the block-diagonal product with the children's eigenvectors.  Nothing waits
@@ -512,7 +512,7 @@ __global__ void dc_finish_kernel(const double* __restrict__ d, const double* __r
 // most DC_LEAF poles taken serially by one thread).  On return d holds each
 // block's eigenvalues (ascending) and Z its diagonal block of eigenvectors
 // (the rest of Z is the identity's zeros).
-constexpr int DC_LEAF = 32;
+constexpr int DC_LEAF = 16;
 constexpr int DC_LNT = 256;
 static_assert(DC_LNT >= DC_LEAF * 2, "leaf kernel thread count");
 
