@@ -103,9 +103,23 @@ void tdvp_ctx_s::destroy_workers() {
 
 void tdvp_ctx_s::sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
 
+void tdvp_ctx_s::ensure_hstage() {
+  if (hstage) return;
+  void* h = nullptr;
+  void* d = nullptr;
+  HIP_CHECK(hipHostMalloc(&h, HSTAGE_BYTES, hipHostMallocDefault));
+  if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess || !d) {
+    (void)hipGetLastError();
+    (void)hipHostFree(h);
+    TDVP_THROW(TDVP_ERR_DEVICE, "pinned staging buffer has no device address");
+  }
+  hstage = h;
+  hstage_dev = d;
+}
+
 const void* tdvp_ctx_s::fetch(const void* dev, size_t bytes) {
   if (bytes > HSTAGE_BYTES / 2) TDVP_THROW(TDVP_ERR_ARG, "staged download too large");
-  if (!hstage) HIP_CHECK(hipHostMalloc(&hstage, HSTAGE_BYTES, hipHostMallocDefault));
+  ensure_hstage();
   HIP_CHECK(hipMemcpyAsync(hstage, dev, bytes, hipMemcpyDeviceToHost, stream));
   HIP_CHECK(hipStreamSynchronize(stream));
   return hstage;
@@ -113,12 +127,24 @@ const void* tdvp_ctx_s::fetch(const void* dev, size_t bytes) {
 
 const void* tdvp_ctx_s::stage_async(int k, const void* dev, size_t bytes) {
   if (bytes > HSTAGE_BYTES / 4 || k < 0 || k > 1) TDVP_THROW(TDVP_ERR_ARG, "staged download too large");
-  if (!hstage) HIP_CHECK(hipHostMalloc(&hstage, HSTAGE_BYTES, hipHostMallocDefault));
+  ensure_hstage();
   if (!ev_stage[k]) HIP_CHECK(hipEventCreateWithFlags(&ev_stage[k], hipEventDisableTiming));
   char* slot = static_cast<char*>(hstage) + HSTAGE_BYTES / 2 + (size_t)k * (HSTAGE_BYTES / 4);
   HIP_CHECK(hipMemcpyAsync(slot, dev, bytes, hipMemcpyDeviceToHost, stream));
   HIP_CHECK(hipEventRecord(ev_stage[k], stream));
   return slot;
+}
+
+void* tdvp_ctx_s::stage_slot_dev(int k) {
+  if (k < 0 || k > 1) TDVP_THROW(TDVP_ERR_ARG, "bad staging slot");
+  ensure_hstage();
+  if (!ev_stage[k]) HIP_CHECK(hipEventCreateWithFlags(&ev_stage[k], hipEventDisableTiming));
+  return static_cast<char*>(hstage_dev) + HSTAGE_BYTES / 2 + (size_t)k * (HSTAGE_BYTES / 4);
+}
+
+const void* tdvp_ctx_s::stage_mark(int k) {
+  HIP_CHECK(hipEventRecord(ev_stage[k], stream));
+  return static_cast<char*>(hstage) + HSTAGE_BYTES / 2 + (size_t)k * (HSTAGE_BYTES / 4);
 }
 
 void tdvp_ctx_s::wait_stage(int k) { HIP_CHECK(hipEventSynchronize(ev_stage[k])); }

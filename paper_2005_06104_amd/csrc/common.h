@@ -71,6 +71,14 @@ struct tdvp_ctx_s {
   hipEvent_t ev_stage[2] = {nullptr, nullptr};
   const void* stage_async(int k, const void* dev, size_t bytes);
   void wait_stage(int k);
+  // Slot k written by a kernel instead of a copy: stage_slot_dev(k) is the
+  // slot's device address (HSTAGE_BYTES / 4 bytes); after enqueueing the
+  // kernel that writes it, stage_mark(k) records the event wait_stage(k)
+  // waits for and returns the slot's host address.
+  void* hstage_dev = nullptr;
+  void ensure_hstage();
+  void* stage_slot_dev(int k);
+  const void* stage_mark(int k);
 
   void* dalloc(size_t bytes);
   void dfree(void* p);
@@ -262,8 +270,11 @@ void zhermitize(hipStream_t s, void* A, long long n);
 // fill complex with value
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
 // w /= |w| with |w|^2 the sum of the np partial sums left by zcombine_p
-// (real parts); out[0] receives |w|^2 (complex128, imaginary part zero)
-void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n);
+// (real parts); out[0] receives |w|^2 (complex128, imaginary part zero).
+// With host (a mapped host address), the first block also writes
+// host[0 .. ncoef) = coeffs[0 .. ncoef) and host[host_norm_at] = |w|^2.
+void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n,
+                    void* host = nullptr, const void* coeffs = nullptr, int ncoef = 0, int host_norm_at = 0);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
 // G = a G + b I (n x n complex128)

@@ -125,9 +125,10 @@ struct Lanczos {
       kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S, nullptr);
       kern::zdots_partial(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb);
       kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S + 64, npart);
-      kern::zscale_invnorm(ctx->stream, w, npart, nnp, S + 128, n);
-      // the first-pass projections (alpha_j = <v_j|H v_j>) and |w|^2
-      staged[j & 1] = static_cast<const zc*>(ctx->stage_async(j & 1, S, 129 * ZB));
+      // the normalisation also writes the first-pass projections (alpha_j =
+      // <v_j|H v_j>) and |w|^2 into the pinned slot the host reads
+      kern::zscale_invnorm(ctx->stream, w, npart, nnp, S + 128, n, ctx->stage_slot_dev(j & 1), S, j + 1, 128);
+      staged[j & 1] = static_cast<const zc*>(ctx->stage_mark(j & 1));
     };
     enqueue(0);
     for (int j = 0; j < maxit; ++j) {

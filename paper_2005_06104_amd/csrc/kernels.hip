@@ -725,7 +725,9 @@ __global__ __launch_bounds__(VNT) void zcombine_p_kernel(double2* __restrict__ w
 // agree on |w|^2; block 0 also stores it
 __global__ __launch_bounds__(VNT) void zscale_invnorm_kernel(double2* __restrict__ w,
                                                               const double2* __restrict__ partial, int np,
-                                                              double2* __restrict__ out, long long n) {
+                                                              double2* __restrict__ out, long long n,
+                                                              double2* host, const double2* __restrict__ coeffs,
+                                                              int ncoef, int host_norm_at) {
   __shared__ double sh[VNT / 64];
   __shared__ double s_tot;
   double acc = 0.0;
@@ -733,8 +735,13 @@ __global__ __launch_bounds__(VNT) void zscale_invnorm_kernel(double2* __restrict
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) {
     s_tot = t;
-    if (blockIdx.x == 0) out[0] = make_double2(t, 0.0);
+    if (blockIdx.x == 0) {
+      out[0] = make_double2(t, 0.0);
+      if (host) host[host_norm_at] = make_double2(t, 0.0);
+    }
   }
+  if (blockIdx.x == 0 && host)
+    for (int j = threadIdx.x; j < ncoef; j += VNT) host[j] = coeffs[j];
   __syncthreads();
   const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
   if (x >= n) return;
@@ -984,10 +991,12 @@ void zscale(hipStream_t s, void* dst, const void* src, zc a, long long n) {
   HIP_CHECK(hipGetLastError());
 }
 
-void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n) {
+void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n, void* host,
+                    const void* coeffs, int ncoef, int host_norm_at) {
   if (n <= 0) return;
   hipLaunchKernelGGL(zscale_invnorm_kernel, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
-                     static_cast<const double2*>(partial), np, static_cast<double2*>(out), n);
+                     static_cast<const double2*>(partial), np, static_cast<double2*>(out), n,
+                     static_cast<double2*>(host), static_cast<const double2*>(coeffs), ncoef, host_norm_at);
   HIP_CHECK(hipGetLastError());
 }
 
