@@ -111,8 +111,8 @@ struct Lanczos {
     // against v_0..v_j (each pass: partial dot products, then the update,
     // whose blocks sum the partials themselves; the second pass leaves
     // per-block sums of |w|^2),
-    // v_{j+1} = w / |w| with |w|^2 summed by the scaling kernel itself, and an
-    // asynchronous copy of the scalars to the host.  The next
+    // v_{j+1} = w / |w| with |w|^2 summed by the scaling kernel itself, which
+    // also writes the scalars into pinned host memory.  The next
     // iteration is enqueued before the host reads this one's scalars, so the
     // device never waits for the convergence test; when the test stops the
     // recurrence, the one extra iteration is discarded.

@@ -190,16 +190,27 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
   const int n = cols;
   const CqrSpace c = cqr_space(work, n, (long long)rows * n);
   hipStream_t s = ctx->stream;
-  rz* X = static_cast<rz*>(A);
+  const bool own = own_chol(n);
+  rz* const X = static_cast<rz*>(A);
+  const rz* Cz = static_cast<const rz*>(C);
+  // the current iterate: C itself before the first step, then X or c.T (the
+  // steps with the own factor are GEMMs that write the other buffer)
+  const rz* cur = Cz;
+  auto other = [&] { return cur == X ? c.T : X; };
   const rz one{1.0, 0.0};
-  auto gram = [&] { kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, 0, X, n, 0, 0.0, c.G, n, 0, 1); };
+  auto gram = [&] { kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, cur, n, 0, cur, n, 0, 0.0, c.G, n, 0, 1); };
   // X <- X R^-1 with X^H X = R^H R: X (L^-1)^H by a GEMM with the own factor,
-  // a triangular solve with rocSOLVER's
+  // a triangular solve in place with rocSOLVER's
   auto chol_step = [&](const rz* F) {
-    if (own_chol(n)) {
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, n, 1.0, X, n, 0, F, n, 0, 0.0, c.T, n, 0, 1);
-      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+    if (own) {
+      rz* dst = other();
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, n, 1.0, cur, n, 0, F, n, 0, 0.0, dst, n, 0, 1);
+      cur = dst;
     } else {
+      if (cur != X) {
+        HIP_CHECK(hipMemcpyAsync(X, cur, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+        cur = X;
+      }
       blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_left, rocblas_fill_upper,
                                rocblas_operation_conjugate_transpose, rocblas_diagonal_non_unit, n, rows, &one, F, n,
                                X, n),
@@ -208,11 +219,10 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
   };
   auto factor = [&]() -> const rz* {
     chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, false);
-    return own_chol(n) ? c.Finv : c.G;
+    return own ? c.Finv : c.G;
   };
-  HIP_CHECK(hipMemcpyAsync(X, C, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
-  kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
   if (first) {
+    kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);   // no factorisation here sets it
     chol_step(static_cast<const rz*>(first));
   } else {
     gram();
@@ -227,8 +237,9 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
     const int st = ns_steps(dev);
     for (int k = 0; k < st; ++k) {
       kern::zshift_diag(s, c.G, n, -0.5, 1.0);
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, X, n, 0, c.G, n, 0, 0.0, c.T, n, 0, 1);
-      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
+      rz* dst = other();
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, cur, n, 0, c.G, n, 0, 0.0, dst, n, 0, 1);
+      cur = dst;
       gram();
       if (k + 1 < st) kern::zshift_diag(s, c.G, n, 1.0, -1.0);
     }
@@ -237,12 +248,12 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
   if (dev > 1e-20) {
     // a second Cholesky step (G holds X^H X - I)
     kern::zshift_diag(s, c.G, n, 1.0, 1.0);
-    kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
     chol_step(factor());
     gram();
     dev = defect(ctx, c, n, &info);
     if (info != 0 || !(dev <= 1e-20)) return false;
   }
+  if (cur != X) HIP_CHECK(hipMemcpyAsync(X, cur, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, 0, C, n, 0, 0.0, R, n, 0, 1);
   return true;
 }
@@ -257,18 +268,27 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   const int n = rows;
   const CqrSpace c = cqr_space(work, n, (long long)n * cols);
   hipStream_t s = ctx->stream;
-  rz* X = static_cast<rz*>(B);
+  const bool own = own_chol(n);
+  rz* const X = static_cast<rz*>(B);
+  const rz* Cz = static_cast<const rz*>(C);
+  const rz* cur = Cz;
+  auto other = [&] { return cur == X ? c.T : X; };
   const rz one{1.0, 0.0};
   auto gram = [&] {
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, X, cols, 0, X, cols, 0, 0.0, c.G, n, 0, 1);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, cur, cols, 0, cur, cols, 0, 0.0, c.G, n, 0, 1);
   };
   // X <- L^-1 X with X X^H = L L^H: a GEMM with the own factor's inverse, a
-  // triangular solve with rocSOLVER's
+  // triangular solve in place with rocSOLVER's
   auto chol_step = [&](const rz* F) {
-    if (own_chol(n)) {
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, F, n, 0, X, cols, 0, 0.0, c.T, cols, 0, 1);
-      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+    if (own) {
+      rz* dst = other();
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, F, n, 0, cur, cols, 0, 0.0, dst, cols, 0, 1);
+      cur = dst;
     } else {
+      if (cur != X) {
+        HIP_CHECK(hipMemcpyAsync(X, cur, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+        cur = X;
+      }
       blas_check(rocblas_ztrsm(ctx->blas, rocblas_side_right, rocblas_fill_lower,
                                rocblas_operation_conjugate_transpose, rocblas_diagonal_non_unit, cols, n, &one, F, n,
                                X, cols),
@@ -277,11 +297,10 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   };
   auto factor = [&]() -> const rz* {
     chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, true);
-    return own_chol(n) ? c.Finv : c.G;
+    return own ? c.Finv : c.G;
   };
-  HIP_CHECK(hipMemcpyAsync(X, C, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
-  kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
   if (first) {
+    kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);   // no factorisation here sets it
     chol_step(static_cast<const rz*>(first));
   } else {
     gram();
@@ -295,8 +314,9 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
     const int st = ns_steps(dev);
     for (int k = 0; k < st; ++k) {
       kern::zshift_diag(s, c.G, n, -0.5, 1.0);
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, c.G, n, 0, X, cols, 0, 0.0, c.T, cols, 0, 1);
-      HIP_CHECK(hipMemcpyAsync(X, c.T, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
+      rz* dst = other();
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, c.G, n, 0, cur, cols, 0, 0.0, dst, cols, 0, 1);
+      cur = dst;
       gram();
       if (k + 1 < st) kern::zshift_diag(s, c.G, n, 1.0, -1.0);
     }
@@ -304,12 +324,12 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   }
   if (dev > 1e-20) {
     kern::zshift_diag(s, c.G, n, 1.0, 1.0);
-    kern::zfill(s, c.dinfo, zc(0.0, 0.0), 1, 16);
     chol_step(factor());
     gram();
     dev = defect(ctx, c, n, &info);
     if (info != 0 || !(dev <= 1e-20)) return false;
   }
+  if (cur != X) HIP_CHECK(hipMemcpyAsync(X, cur, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, 0, X, cols, 0, 0.0, L, n, 0, 1);
   return true;
 }
