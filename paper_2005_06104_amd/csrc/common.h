@@ -192,8 +192,8 @@ hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double*
 int cholinv_max_n();
 size_t cholinv_scratch_bytes();
 hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int* info, void* scratch);
-// G <- G - frac * trace(G) * I (Hermitian complex128 n x n)
-void shift_by_trace(hipStream_t s, void* G, int n, double frac);
+// G <- S - frac * trace(S) * I (Hermitian complex128 n x n; S null: S = G)
+void shift_by_trace(hipStream_t s, void* G, int n, double frac, const void* S = nullptr);
 // out[j][m] = Z[m][n-1-j] (complex), Z column-major real n x n
 void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n);
 // Arithmetic of the complex64 GEMMs issued from the calling host thread:
@@ -267,6 +267,8 @@ void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long l
                 long long rows, long long cols);
 // Hermitian part in place: A = (A + A^H)/2, n x n complex128
 void zhermitize(hipStream_t s, void* A, long long n);
+// A = (S + S^H) / 2 (A may be S), and zero[0 .. nzero) = 0 in the same launch
+void zhermitize_to(hipStream_t s, void* A, const void* S, long long n, int* zero = nullptr, int nzero = 0);
 // fill complex with value
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
 // w /= |w| with |w|^2 the sum of the np partial sums left by zcombine_p
@@ -311,13 +313,16 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
 // semidefinite n x n matrix G exceeds frac * trace(G): the Cholesky
 // factorisation of G - (1.01 frac + 4 n u) trace(G) I succeeds (u the unit
 // roundoff; the margin covers the rounding of the factorisation).  G is
-// overwritten.  Returns NULL when the factorisation fails, else that factor
+// overwritten; with src (may be null) the matrix is read from src instead and
+// G receives the shifted copy.  Returns NULL when the factorisation fails,
+// else that factor
 // in the form the Cholesky-QR routines take for their first step (shifted
 // Cholesky QR: the shifted factor leaves the first iterate's condition
 // number small, and the second step restores orthonormality): L^-1 in Finv
 // (n x n) for n <= kern::cholinv_max_n(), else rocSOLVER's factor in G
 // (upper, or lower when `lower`, in the column-major view).
-const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work);
+const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work,
+                                 const void* src = nullptr);
 // thin SVD of row-major C (rows x cols): U (rows x k), S (k, host), Vh (k x cols); k = min.
 void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
                   void* Vh, DBuf& work, DBuf& work2);

@@ -346,10 +346,13 @@ __global__ void zrows_from_real_kernel(double2* __restrict__ out, const double* 
 }
 
 // G <- G - frac * tr(G) I for a Hermitian n x n matrix (one workgroup)
-__global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* __restrict__ G, int n, double frac) {
+// G = S - frac trace(S) I.  With G == S one workgroup shifts the diagonal;
+// otherwise every workgroup finds the same trace (the same order) and copies
+// its share of the entries, shifting those on the diagonal.
+__global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* G, const double2* S, int n, double frac) {
   __shared__ double red[TNT / 64];
   double t = 0.0;
-  for (int i = threadIdx.x; i < n; i += TNT) t += G[(size_t)i * n + i].x;
+  for (int i = threadIdx.x; i < n; i += TNT) t += S[(size_t)i * n + i].x;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
@@ -357,7 +360,16 @@ __global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* __restrict
   double tr = 0.0;
   for (int w = 0; w < TNT / 64; ++w) tr += red[w];
   const double mu = frac * tr;
-  for (int i = threadIdx.x; i < n; i += TNT) G[(size_t)i * n + i].x -= mu;
+  if (G == S) {
+    for (int i = threadIdx.x; i < n; i += TNT) G[(size_t)i * n + i].x -= mu;
+    return;
+  }
+  const long long nn = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * TNT + threadIdx.x; e < nn; e += (long long)gridDim.x * TNT) {
+    double2 v = S[e];
+    if (e / n == e % n) v.x -= mu;
+    G[e] = v;
+  }
 }
 
 __global__ void td_reset_kernel(unsigned* w, int nw, int* err) {
@@ -411,9 +423,12 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_kernel), dim3(G), dim3(TNT), args, 0, s);
 }
 
-void shift_by_trace(hipStream_t s, void* G, int n, double frac) {
+void shift_by_trace(hipStream_t s, void* G, int n, double frac, const void* S) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(shift_by_trace_kernel, dim3(1), dim3(TNT), 0, s, static_cast<double2*>(G), n, frac);
+  const double2* src = S ? static_cast<const double2*>(S) : static_cast<const double2*>(G);
+  const long long nn = (long long)n * n;
+  const unsigned blocks = src == G ? 1u : (unsigned)std::min<long long>(256, (nn + TNT - 1) / TNT);
+  hipLaunchKernelGGL(shift_by_trace_kernel, dim3(blocks), dim3(TNT), 0, s, static_cast<double2*>(G), src, n, frac);
 }
 
 void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n) {

@@ -488,9 +488,8 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // their sum (the cap does not bind: kk <= chi_max); a Cholesky factorisation
   // certifies it, and the exact factorisation is then the split.
   if (kk == cols && kk <= chi_max) {
-    HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)cols * cols * ZB, hipMemcpyDeviceToDevice, s));
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false,
-                                             W.cinv.ensure((size_t)cols * cols * ZB), W.work);
+                                             W.cinv.ensure((size_t)cols * cols * ZB), W.work, W.tmpA.p);
     if (F) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
@@ -542,9 +541,8 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, rows, 0, 1);
   // certified "nothing to cut" as in split_left
   if (kk == rows && kk <= chi_max) {
-    HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)rows * rows * ZB, hipMemcpyDeviceToDevice, s));
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true,
-                                             W.cinv.ensure((size_t)rows * rows * ZB), W.work);
+                                             W.cinv.ensure((size_t)rows * rows * ZB), W.work, W.tmpA.p);
     if (F) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
@@ -1073,9 +1071,8 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     // largest, the criterion below); B is then the LQ factor's Q.
     bool done = false;
     if (ml <= D) {
-      HIP_CHECK(hipMemcpyAsync(W.tmpB.p, W.tmpA.p, (size_t)ml * ml * ZB, hipMemcpyDeviceToDevice, s));
       const void* F = la::gram_floor_certified(ctx, W.tmpB.p, ml, 1e-10, true,
-                                               W.cinv.ensure((size_t)ml * ml * ZB), W.work);
+                                               W.cinv.ensure((size_t)ml * ml * ZB), W.work, W.tmpA.p);
       if (F) {
         W.tmpC.ensure((size_t)ml * ml * ZB);
         done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F);

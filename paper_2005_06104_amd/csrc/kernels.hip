@@ -791,12 +791,16 @@ __global__ void zconjtrans_kernel(double2* __restrict__ dst, long long ldd, cons
   dst[i * ldd + j] = make_double2(v.x, -v.y);
 }
 
-__global__ void zhermitize_kernel(double2* __restrict__ A, long long n) {
+// A = (S + S^H) / 2 (A may be S: each pair (i, j), j >= i, belongs to one
+// thread); thread 0 also clears zero[0 .. nzero)
+__global__ void zhermitize_kernel(double2* A, const double2* S, long long n, int* zero, int nzero) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx == 0)
+    for (int k = 0; k < nzero; ++k) zero[k] = 0;
   if (idx >= n * n) return;
   const long long i = idx / n, j = idx % n;
   if (j < i) return;
-  const double2 a = A[i * n + j], b = A[j * n + i];
+  const double2 a = S[i * n + j], b = S[j * n + i];
   if (i == j) {
     A[i * n + j] = make_double2(a.x, 0.0);
   } else {
@@ -1042,9 +1046,12 @@ void zconjtrans(hipStream_t s, void* dst, long long ldd, const void* src, long l
   HIP_CHECK(hipGetLastError());
 }
 
-void zhermitize(hipStream_t s, void* A, long long n) {
+void zhermitize(hipStream_t s, void* A, long long n) { zhermitize_to(s, A, A, n); }
+
+void zhermitize_to(hipStream_t s, void* A, const void* S, long long n, int* zero, int nzero) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(zhermitize_kernel, dim3(nblk(n * n)), dim3(256), 0, s, static_cast<double2*>(A), n);
+  hipLaunchKernelGGL(zhermitize_kernel, dim3(nblk(n * n)), dim3(256), 0, s, static_cast<double2*>(A),
+                     static_cast<const double2*>(S), n, zero, nzero);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -105,11 +105,12 @@ void chol_factor(tdvp_ctx_s* ctx, rz* G, int n, rz* Finv, int* dinfo, void* cscr
 
 }  // namespace
 
-const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work) {
+const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work,
+                                 const void* src) {
   if (n < 1) return nullptr;
   char* base = static_cast<char*>(work.ensure(256 + kern::cholinv_scratch_bytes()));
   int* dinfo = reinterpret_cast<int*>(base);
-  kern::shift_by_trace(ctx->stream, G, n, frac * 1.01 + 4.0 * n * 2.220446049250313e-16);
+  kern::shift_by_trace(ctx->stream, G, n, frac * 1.01 + 4.0 * n * 2.220446049250313e-16, src);
   // (row-major G read column-major is conj(G): definite exactly when G is)
   chol_factor(ctx, static_cast<rz*>(G), n, static_cast<rz*>(Finv), dinfo, base + 256, lower);
   if (*static_cast<const int*>(ctx->fetch(dinfo, sizeof(int))) != 0) return nullptr;
@@ -395,9 +396,8 @@ bool eigh_rows_desc_tridiag(tdvp_ctx_s* ctx, const void* H, int n, std::vector<d
   double* dE = reinterpret_cast<double*>(take(sizeof(double) * (size_t)n));
   char* scratch = take(scr);
   double* Z = reinterpret_cast<double*>(take(sizeof(double) * nn));
-  HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
-  kern::zhermitize(ctx->stream, X, n);
-  kern::zfill(ctx->stream, dinfo, zc(0.0, 0.0), 1, 16);   // info and barrier error
+  // Hermitian part, and the info and barrier-error words cleared
+  kern::zhermitize_to(ctx->stream, X, H, n, dinfo, 4);
   const hipError_t le = kern::tridiag(ctx->stream, X, n, Q, dD, dE, scratch, derr);
   if (le != hipSuccess) {
     (void)hipGetLastError();
@@ -442,8 +442,7 @@ void eigh_rows_desc_heevd(tdvp_ctx_s* ctx, const void* H, int n, std::vector<dou
   double* dres = dE + n + 1;
   int* dinfo = reinterpret_cast<int*>(dres + 2);
   int* dsweeps = dinfo + 1;
-  HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
-  kern::zhermitize(ctx->stream, X, n);
+  kern::zhermitize_to(ctx->stream, X, H, n);
   blas_check(rocsolver_zheevd(ctx->blas, rocblas_evect_original, rocblas_fill_upper, n, X, n, dD, dE, dinfo),
              "zheevd");
   // validate: orthonormal eigenvectors have sum |v|^2 = n, eigenvalues finite
@@ -474,8 +473,7 @@ void eigh_rows_desc_heevd(tdvp_ctx_s* ctx, const void* H, int n, std::vector<dou
       lam.assign(n, 0.0);
       return;
     }
-    HIP_CHECK(hipMemcpyAsync(X, H, sizeof(rz) * nn, hipMemcpyDeviceToDevice, ctx->stream));
-    kern::zhermitize(ctx->stream, X, n);
+    kern::zhermitize_to(ctx->stream, X, H, n);
     blas_check(rocsolver_zheevj(ctx->blas, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper, n, X,
                                 n, 0.0, dres, 100, dsweeps, dD, dinfo),
                "zheevj");
