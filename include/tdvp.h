@@ -292,6 +292,20 @@ tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int m
  * and conquer (TDVP_ERR_NUMERIC when not applicable).  Synchronous. */
 tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows, double* lam);
 
+/* Cholesky factorisation with the inverse of the factor, as used by the gauge
+ * moves (the orthonormal centre moves of eq. (3) and of the sweep, section
+ * I.C item 3: the Cholesky-QR steps and the test that a truncation has
+ * nothing to cut): G = L L^H for a Hermitian positive definite G.  G: device
+ * complex128 n x n row-major, its lower triangle read, 1 <= n <= 512; L,
+ * Linv: device complex128 n x n row-major out, L lower triangular (the
+ * entries above the diagonal in the 16 x 16 blocks off the diagonal are not
+ * written; those of the diagonal blocks are set to zero), Linv = L^-1 with
+ * zeros above the diagonal.  L may be G; Linv must overlap neither.  info:
+ * host out, 0 on success, 1 when a pivot is not positive and finite (G not
+ * numerically positive definite; L and Linv are then undefined), 2 when an
+ * internal wait ran out.  Synchronous. */
+tdvp_status tdvp_cholesky(tdvp_ctx ctx, int n, const void* G, void* L, void* Linv, int* info);
+
 /* Wait for all work issued on the context's stream. */
 tdvp_status tdvp_synchronize(tdvp_ctx ctx);
 

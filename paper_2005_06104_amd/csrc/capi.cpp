@@ -596,6 +596,23 @@ tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows
   });
 }
 
+tdvp_status tdvp_cholesky(tdvp_ctx ctx, int n, const void* G, void* L, void* Linv, int* info) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && n <= kern::cholinv_max_n() && G && L && Linv && info, "bad arguments");
+    ARG_CHECK(Linv != G && Linv != L, "Linv must not be G or L");
+    bind(ctx);
+    DBuf work(ctx);
+    char* base = static_cast<char*>(work.ensure(256 + kern::cholinv_scratch_bytes()));
+    int* dinfo = reinterpret_cast<int*>(base);
+    if (kern::cholinv(ctx->stream, G, n, L, Linv, dinfo, base + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      TDVP_THROW(TDVP_ERR_DEVICE, "Cholesky factorisation launch failed");
+    }
+    *info = *static_cast<const int*>(ctx->fetch(dinfo, sizeof(int)));
+  });
+}
+
 tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
                             const void* L, const void* Rt, const void* C, void* Y, void* workspace) {
   if (!W_host) return TDVP_ERR_ARG;

@@ -117,6 +117,7 @@ def load():
         "tdvp_env_left": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
         "tdvp_env_right": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
         "tdvp_eigh": (i, [vp, i, i, vp, vp, C.POINTER(d)]),
+        "tdvp_cholesky": (i, [vp, i, vp, vp, vp, C.POINTER(C.c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -427,6 +428,16 @@ def tdvp_eigh(ctx: Context, H, rows, method: int = 0) -> np.ndarray:
     lam = np.zeros(n)
     ctx.check(ctx.lib.tdvp_eigh(ctx.h, int(method), n, _tp(H), _tp(rows), _dptr(lam)), "tdvp_eigh")
     return lam
+
+
+def tdvp_cholesky(ctx: Context, G, L, Linv) -> int:
+    """Cholesky factor L (lower) and L^-1 of the Hermitian positive definite
+    complex128 device matrix G (n x n, n <= 512); returns the info code (0 ok,
+    1 not positive definite)."""
+    n = G.shape[0]
+    info = C.c_int(-1)
+    ctx.check(ctx.lib.tdvp_cholesky(ctx.h, n, _tp(G), _tp(L), _tp(Linv), C.byref(info)), "tdvp_cholesky")
+    return int(info.value)
 
 
 def _w_host(W: np.ndarray):
