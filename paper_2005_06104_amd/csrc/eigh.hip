@@ -244,9 +244,9 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     }
     // ---- gather this column's x, pivot row and partial sums as they arrive
     constexpr int NQ = (TD_NMAX + TNT - 1) / TNT;
-    double2 xq[NQ], rq[NQ], tp{0.0, 0.0};
+    double2 xq[NQ], rq[NQ], tp{0.0, 0.0}, tp2{0.0, 0.0};
     {
-      bool gx[NQ], gr[NQ], gp = lane >= G;
+      bool gx[NQ], gr[NQ], gp = lane >= G, gp2 = lane + 64 >= G;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int c = k + 1 + tid + q * TNT;
@@ -264,7 +264,8 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
           done = done && gx[q] && gr[q];
         }
         if (!gp) gp = get_tagged(p2p + 4 * (size_t)lane, tag, &tp);
-        done = done && gp;
+        if (!gp2) gp2 = get_tagged(p2p + 4 * (size_t)(lane + 64), tag, &tp2);
+        done = done && gp && gp2;
         if (done) break;
         ++polls;
         if (polls > SPIN_LIMIT ||
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     // column k+2; A <- A - v w^H - w v^H on the own rows
     {
       // x^H v: every wave sums the published partials in the same order
-      const double2 t = wave_sum(tp);
+      const double2 t = wave_sum(double2{tp.x + tp2.x, tp.y + tp2.y});
       const double2 a2x = cmul(tau, t);
       const double2 a2{-0.5 * a2x.x, -0.5 * a2x.y};
 #pragma unroll
@@ -385,12 +386,13 @@ namespace kern {
 int tridiag_groups(int n) {
   if (n < 1 || n > TD_NMAX) return 0;
   // The per-column work of a workgroup grows with its share of the rows and
-  // the barrier with the number of workgroups: about eight rows per
-  // workgroup is fastest (measured from n = 48 to 512); small matrices stay
-  // in one workgroup.  At most 64 workgroups (the partial sums are combined
-  // by one wave), and 2 R n complex slots of LDS for the A and Q rows.
+  // the exchange with the number of workgroups: about eight rows per
+  // workgroup is fastest from n = 48 to 448, four above (measured); small
+  // matrices stay in one workgroup.  At most 128 workgroups (each lane of a
+  // wave combines two partial sums), and 2 R n complex slots of LDS for the
+  // A and Q rows.
   if (n <= 32) return 1;
-  const int G = std::min(64, (n + 7) / 8);
+  const int G = n > 448 ? std::min(128, (n + 3) / 4) : std::min(64, (n + 7) / 8);
   const int R = (n + G - 1) / G;
   return (2 * R * n <= TD_LDS && R <= TD_ROWS) ? G : 0;
 }
