@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "wave.h"
 
 namespace {
 
@@ -53,46 +54,7 @@ __device__ inline double2 cmulc(double2 a, double2 b) {  // a * conj(b)
   return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-// Sums across lanes with DPP moves inside each row of 16 lanes (quad swaps,
-// then the half-row and row mirrors: every lane ends with its row's sum)
-// and readlane for the four rows; every lane gets the same total, formed in
-// the same order in every wave.  All 64 lanes must be active.
-template <int CTRL>
-__device__ inline double dpp_mov(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-__device__ inline double row16_sum(double v) {
-  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
-  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
-  v += dpp_mov<0x141>(v);   // row_half_mirror
-  v += dpp_mov<0x140>(v);   // row_mirror
-  return v;
-}
-__device__ inline double lane_of(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-__device__ inline double wave_sum1(double v) {
-  v = row16_sum(v);
-  return (lane_of(v, 0) + lane_of(v, 16)) + (lane_of(v, 32) + lane_of(v, 48));
-}
-// sum over the T consecutive lanes of each group (T a power of two <= 64)
-__device__ inline double group_sum(double v, int T) {
-  if (T == 64) return wave_sum1(v);
-  if (T >= 16) {
-    v = row16_sum(v);
-    if (T == 32) v += __shfl_xor(v, 16);
-    return v;
-  }
-  for (int o = T >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ inline double2 wave_sum(double2 v) { return double2{wave_sum1(v.x), wave_sum1(v.y)}; }
+__device__ inline double2 wave_sum(double2 v) { return double2{wave::sum(v.x), wave::sum(v.y)}; }
 
 // Publish v under tag t: the low and high halves of both parts, each with
 // the tag in the upper 32 bits of its word.
@@ -192,7 +154,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       srow[c] = h;
       if (c >= 2) ssq += h.x * h.x + h.y * h.y;
     }
-    ssq = wave_sum1(ssq);
+    ssq = wave::sum(ssq);
     if (lane == 0) sred[wave] = ssq;
   }
   if (tid == 0) s_fail = 0;
@@ -232,10 +194,10 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         sq.x += q.x * v.x - q.y * v.y;
         sq.y += q.x * v.y + q.y * v.x;
       }
-      sa.x = group_sum(sa.x, T);
-      sa.y = group_sum(sa.y, T);
-      sq.x = group_sum(sq.x, T);
-      sq.y = group_sum(sq.y, T);
+      sa.x = wave::group_sum(sa.x, T);
+      sa.y = wave::group_sum(sa.y, T);
+      sq.x = wave::group_sum(sq.x, T);
+      sq.y = wave::group_sum(sq.y, T);
       tqs = cmul(tau, sq);
       const int r = g + rj * G;
       if (rt == 0) {
@@ -340,7 +302,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
           if (c >= k + 3) ssq += nr.x * nr.x + nr.y * nr.y;
         }
       }
-      ssq = wave_sum1(ssq);
+      ssq = wave::sum(ssq);
       if (lane == 0) sred[wave] = ssq;
     }
     if (rj < nrow && g + rj * G >= k + 2) {   // rows <= k+1 are finished

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "wave.h"
 
 namespace {
 
@@ -585,10 +586,8 @@ __global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T
 constexpr int VNT = 256;
 constexpr int DOT_CHUNK = 1024;
 
-__device__ inline double warp_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
+// sum over the wave (all 64 lanes active; every lane gets the total)
+__device__ inline double warp_sum(double v) { return wave::sum(v); }
 
 __device__ inline double block_sum(double v, double* sh) {
   v = warp_sum(v);

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.h"
+#include "wave.h"
 
 namespace {
 
@@ -66,21 +67,10 @@ struct DcArgs {
   double* par;              // per node: sign of the coupling, rho = 2 |coupling|
 };
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-__device__ inline double wave_prod(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o);
-  return v;
-}
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
+// whole-wave reductions (every lane gets the result; all 64 lanes active)
+__device__ inline double wave_sum(double v) { return wave::sum(v); }
+__device__ inline double wave_prod(double v) { return wave::prod(v); }
+__device__ inline double wave_max(double v) { return wave::max(v); }
 
 // ---------------------------------------------------------------- set-up
 // Scaled, torn, padded diagonal (the leaves' eigenvalues), couplings and
