@@ -125,6 +125,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
   __shared__ double2 sM[TD_LDS];        // A rows [R][n], then Q rows [R][n]
   __shared__ double2 sv[TD_NMAX], sw[TD_NMAX], srow[TD_NMAX];
   __shared__ double sred[TNT / 64];     // per-wave |row[k+2:]|^2 of the pivot row
+  __shared__ double2 s_t;               // x^H v of the current column
   __shared__ double2 s_part[TD_ROWS];
   __shared__ int s_fail;
 
@@ -234,10 +235,13 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       }
     }
     // ---- gather this column's x, pivot row and partial sums as they arrive
+    // (every thread its own entries of x and the row; the partial sums by
+    // wave 0 only: polls from all waves slowed the publishers down, 7% at
+    // n = 512)
     constexpr int NQ = (TD_NMAX + TNT - 1) / TNT;
     double2 xq[NQ], rq[NQ], tp{0.0, 0.0}, tp2{0.0, 0.0};
     {
-      bool gx[NQ], gr[NQ], gp = lane >= G, gp2 = lane + 64 >= G;
+      bool gx[NQ], gr[NQ], gp = wave != 0 || lane >= G, gp2 = wave != 0 || lane + 64 >= G;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int c = k + 1 + tid + q * TNT;
@@ -268,6 +272,10 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
+    if (wave == 0) {   // x^H v from the published partials, in a fixed order
+      const double2 t = wave_sum(double2{tp.x + tp2.x, tp.y + tp2.y});
+      if (lane == 0) s_t = t;
+    }
     __syncthreads();
     if (s_fail) {
       alive = false;
@@ -277,8 +285,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     // ---- w = x - (tau/2)(x^H v) v; next pivot row and its norm beyond
     // column k+2; A <- A - v w^H - w v^H on the own rows
     {
-      // x^H v: every wave sums the published partials in the same order
-      const double2 t = wave_sum(double2{tp.x + tp2.x, tp.y + tp2.y});
+      const double2 t = s_t;
       const double2 a2x = cmul(tau, t);
       const double2 a2{-0.5 * a2x.x, -0.5 * a2x.y};
 #pragma unroll
@@ -376,13 +383,12 @@ namespace kern {
 int tridiag_groups(int n) {
   if (n < 1 || n > TD_NMAX) return 0;
   // The per-column work of a workgroup grows with its share of the rows and
-  // the exchange with the number of workgroups: about eight rows per
-  // workgroup is fastest from n = 48 to 448, four above (measured); small
-  // matrices stay in one workgroup.  At most 128 workgroups (each lane of a
-  // wave combines two partial sums), and 2 R n complex slots of LDS for the
-  // A and Q rows.
-  if (n <= 32) return 1;
-  const int G = n > 448 ? std::min(128, (n + 3) / 4) : std::min(64, (n + 7) / 8);
+  // the exchange with the number of workgroups: four rows per workgroup (one
+  // wave per row) is fastest at every n measured, 8 to 512 (eight rows are
+  // 8-15% slower from n = 64 on, two no faster, one workgroup for n <= 32 up
+  // to 25% slower).  At most 128 workgroups (each lane of a wave combines
+  // two partial sums), and 2 R n complex slots of LDS for the A and Q rows.
+  const int G = std::min(128, (n + 3) / 4);
   const int R = (n + G - 1) / G;
   return (2 * R * n <= TD_LDS && R <= TD_ROWS) ? G : 0;
 }
