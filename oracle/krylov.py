@@ -119,11 +119,16 @@ def svd_compress(mps, eps, chi_max):
     return psi, disc
 
 
-def krylov_vectors(psi, Ws_op, k, eps_K, chi_max):
-    """[(1 - i tau H)^l psi, l = 1..k-1], each normalised and truncated."""
+def krylov_vectors(psi, Ws_op, k, eps_K, chi_max, apply="denmat", fit_passes=3):
+    """[(1 - i tau H)^l psi, l = 1..k-1], each normalised and truncated, by
+    the density-matrix route or (apply="fit") by variational fitting."""
+    from .fit import apply_mpo_variational
     out = []
     cur = psi
     for _ in range(k - 1):
-        cur, _ = apply_mpo_denmat(cur, Ws_op, eps_K, chi_max)
+        if apply == "fit":
+            cur, _ = apply_mpo_variational(cur, Ws_op, eps_K, chi_max, fit_passes)
+        else:
+            cur, _ = apply_mpo_denmat(cur, Ws_op, eps_K, chi_max)
         out.append(cur)
     return out
