@@ -81,6 +81,12 @@ typedef enum {
  * R = conjugated (not transposed). */
 typedef enum { TDVP_OP_N = 0, TDVP_OP_T = 1, TDVP_OP_C = 2, TDVP_OP_R = 3 } tdvp_op;
 
+/* How an MPO is applied to an MPS (section I.C offers both): the
+ * density-matrix algorithm (exact before the cut; cost O(m^3 w^2 d) per
+ * site) or variational two-site fitting (Paeckel et al. 2019; O(m^3 w d) per
+ * site and pass, converged after a few passes). */
+typedef enum { TDVP_APPLY_DENMAT = 0, TDVP_APPLY_FIT = 1 } tdvp_apply_method;
+
 /* Device memory callbacks (e.g. PyTorch's caching allocator).  alloc returns
  * NULL on failure; memory freed by free_ may be reused by later work on the
  * context's stream only.  Both may be NULL: the library then uses hipMalloc
@@ -146,6 +152,27 @@ tdvp_status tdvp_mps_bond_dims(tdvp_mps mps, int* n_sites, int* bond_dims, int c
 tdvp_status tdvp_mps_to_host(tdvp_mps mps, double* tensors, size_t capacity);
 void tdvp_mps_destroy(tdvp_mps mps);
 
+/* *out = O|in>, normalised and truncated (section I.C, the MPO application
+ * that produces each global Krylov vector of eq. (10)).
+ *   method  TDVP_APPLY_DENMAT: density-matrix algorithm, one left-to-right
+ *           pass over reduced density matrices built from right double-layer
+ *           environments; the cut drops the smallest eigenvalues while their
+ *           sum stays <= eps * Tr(rho).
+ *           TDVP_APPLY_FIT: two-site variational fitting, `passes` >= 1
+ *           alternating passes starting from the left with |in> as the first
+ *           guess; each two-site tensor is the exact projection of O|in> in
+ *           the current bases, split by a truncated decomposition with the
+ *           same relative cut (eps on the squared singular values).
+ *   chi_max caps every bond.  Both methods compute in FP64.
+ * The result is a new MPS (release with tdvp_mps_destroy), left-canonical
+ * with its centre on the last site; `in` is left unchanged.  *discarded (may
+ * be NULL) receives the weight dropped by the cut (the last pass for FIT).
+ * Errors: TDVP_ERR_ARG (NULL handle, site counts differ, eps < 0,
+ * chi_max < 1, unknown method, passes < 1 or fewer than two sites for FIT),
+ * TDVP_ERR_NUMERIC (zero or non-finite result). */
+tdvp_status tdvp_apply_mpo(tdvp_ctx ctx, tdvp_mps in, tdvp_mpo op, int method, double eps, int chi_max,
+                           int passes, tdvp_mps* out, double* discarded);
+
 /* ------------------------------------------------------- GSE-TDVP1 step */
 
 typedef struct {
@@ -157,6 +184,8 @@ typedef struct {
   int prec;          /* tdvp_prec of the contractions                               */
   int skip_if_full;  /* 1: skip steps 1-2 when every bond is already at its largest
                         useful size min(chi_max, 2^(i+1), 2^(N-i-1))                */
+  int apply_method;  /* tdvp_apply_method of the Krylov vectors (0: density matrix) */
+  int fit_passes;    /* passes of TDVP_APPLY_FIT (values < 1 mean 1)                */
 } tdvp_expand_params;
 
 typedef struct {
@@ -173,7 +202,8 @@ typedef struct {
  * with its center on site 0 and represents the same state as before (up to
  * rounding).  stats may be NULL, else n entries.
  * Errors: TDVP_ERR_ARG (n < 1, site counts differ from the MPO, k < 1,
- * chi_max < 1, eps < 0, unknown prec). */
+ * chi_max < 1, eps < 0, unknown prec or apply_method, fewer than two sites
+ * with TDVP_APPLY_FIT). */
 tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* op,
                               const tdvp_expand_params* params, tdvp_expand_stats* stats);
 

@@ -439,6 +439,27 @@ void tdvp_mps_destroy(tdvp_mps mps) {
   delete mps;
 }
 
+tdvp_status tdvp_apply_mpo(tdvp_ctx ctx, tdvp_mps in, tdvp_mpo op, int method, double eps, int chi_max,
+                           int passes, tdvp_mps* out, double* discarded) {
+  if (!ctx || !out) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(in && op, "NULL handle");
+    ARG_CHECK(in->N == op->N(), "MPS and MPO site counts differ");
+    ARG_CHECK(std::isfinite(eps) && eps >= 0, "eps must be >= 0");
+    ARG_CHECK(chi_max >= 1, "chi_max must be >= 1");
+    ARG_CHECK(method == TDVP_APPLY_DENMAT || method == TDVP_APPLY_FIT, "unknown method");
+    if (method == TDVP_APPLY_FIT) {
+      ARG_CHECK(passes >= 1, "passes must be >= 1");
+      ARG_CHECK(in->N >= 2, "the variational route needs at least two sites");
+    }
+    if (!in->valid || !op->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
+    bind(ctx);
+    auto res = std::make_unique<tdvp_mps_s>();
+    run_apply_mpo(ctx, *in, *op, method, eps, chi_max, passes, *res, discarded);
+    *out = res.release();
+  });
+}
+
 // ------------------------------------------------------------ GSE-TDVP1
 tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* op,
                               const tdvp_expand_params* params, tdvp_expand_stats* stats) {
@@ -450,9 +471,11 @@ tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo
     ARG_CHECK(p.chi_max >= 1, "chi_max must be >= 1");
     ARG_CHECK(p.eps_K >= 0 && p.eps_M >= 0, "cutoffs must be >= 0");
     ARG_CHECK(p.prec >= TDVP_FP64 && p.prec <= TDVP_BF16X3_FP32ACC, "unknown precision");
+    ARG_CHECK(p.apply_method == TDVP_APPLY_DENMAT || p.apply_method == TDVP_APPLY_FIT, "unknown apply_method");
     for (int j = 0; j < n; ++j) {
       ARG_CHECK(psi[j] && op[j], "NULL handle");
       ARG_CHECK(psi[j]->N == op[j]->N(), "MPS and MPO site counts differ");
+      ARG_CHECK(p.apply_method != TDVP_APPLY_FIT || psi[j]->N >= 2, "the variational route needs at least two sites");
       if (!psi[j]->valid || !op[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
     bind(ctx);

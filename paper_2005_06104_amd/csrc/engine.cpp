@@ -1045,6 +1045,153 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
   return disc;
 }
 
+// ------------------------------------------------ variational MPO application
+// Two-site fitting of |phi> ~ O|psi> (the variational route of section I.C,
+// after Paeckel et al. 2019): mixed environments <phi|O|psi>, L[(a',al),a]
+// with a' on phi and a on psi, Rt[ga][b,b'] with b on psi and b' on phi.
+// Contractions in FP64.
+
+// Lout[b',(be,b)] = sum conj(bra[a',s',b']) L[(a',al),a] W[al,be,s',s] ket[a,s,b]
+void fit_env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
+                  const void* L, const void* bra, const void* ket, void* Lout, DBuf& f1, DBuf& f2) {
+  hipStream_t s = ctx->stream;
+  f1.ensure((size_t)mlo * wl * 2 * mri * ZB);
+  f2.ensure((size_t)mlo * 2 * wr * mri * ZB);
+  // T1[(a',al),(s,b)] = L[(a',al),a] ket[a,(s,b)]
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 2 * mri, mli, 1.0, L, mli, 0, ket, 2LL * mri, 0, 0.0, f1.p,
+                     2LL * mri, 0, 1);
+  // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
+  kern::wapply<double>(s, tb.F, f1.p, f2.p, mlo, mri, (long long)wl * 2 * mri, 1, 2LL * mri, mri,
+                       2LL * wr * mri, 1, mri, (long long)wr * mri);
+  // Lout[b',(be,b)] = sum_{(a',s')} conj(bra[(a',s'),b']) T2[(a',s'),(be,b)]
+  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mro, wr * mri, 2 * mlo, 1.0, bra, mro, 0, f2.p, (long long)wr * mri, 0,
+                     0.0, Lout, (long long)wr * mri, 0, 1);
+}
+
+// Rout[al][a,a'] = sum conj(bra[a',s',b']) W[al,be,s',s] Rt[be][b,b'] ket[a,s,b]
+void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
+                   const void* Rt, const void* bra, const void* ket, void* Rout, DBuf& f1, DBuf& f2) {
+  hipStream_t s = ctx->stream;
+  f1.ensure((size_t)wr * 2 * mli * mro * ZB);
+  f2.ensure((size_t)wl * 2 * mli * mro * ZB);
+  // U1[be][(a,s),b'] = ket[(a,s),b] Rt[be][b,b']   (batched over be)
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, mro, mri, 1.0, ket, mri, 0, Rt, mro, (long long)mri * mro, 0.0,
+                     f1.p, mro, 2LL * mli * mro, wr);
+  // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
+  kern::wapply<double>(s, tb.B, f1.p, f2.p, mli, mro, 2LL * mro, 1, 2LL * mli * mro, mro, 2LL * mro, 1,
+                       2LL * mli * mro, mro);
+  // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(bra[a',(s',b')])
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, wl * mli, mlo, 2 * mro, 1.0, f2.p, 2LL * mro, 0, bra, 2LL * mro, 0, 0.0,
+                     Rout, mlo, 0, 1);
+}
+
+// Y[(a',t),(u,b')] = sum L[(a',al),a] W1[al,be,t,s] W2[be,ga,u,v] P[a,s,v,b] Rt[ga][b,b']:
+// the two-site tensor of phi that is closest to O|psi> in the current bases.
+void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int mlo, int mli, int wl, int wm, int wr,
+                int mri, int mro, const void* L, const void* Rt, const void* P, void* Y, DBuf& f1, DBuf& f2) {
+  hipStream_t s = ctx->stream;
+  const long long big = std::max({(long long)mlo * wl * 4 * mri, (long long)mlo * 2 * wm * 2 * mri,
+                                  (long long)mlo * 2 * 2 * wr * mri});
+  f1.ensure((size_t)big * ZB);
+  f2.ensure((size_t)big * ZB);
+  // T1[(a',al),(s,v,b)] = L[(a',al),a] P[a,(s,v,b)]
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 4 * mri, mli, 1.0, L, mli, 0, P, 4LL * mri, 0, 0.0, f1.p,
+                     4LL * mri, 0, 1);
+  // T2[a',t,be,(v,b)] = sum W1[al,be,t,s] T1[a',al,s,(v,b)]
+  kern::wapply<double>(s, t1.F, f1.p, f2.p, mlo, 2LL * mri, (long long)wl * 4 * mri, 1, 4LL * mri, 2LL * mri,
+                       (long long)2 * wm * 2 * mri, 1, 2LL * mri, (long long)wm * 2 * mri);
+  // T3[(a',t),u,ga,b] = sum W2[be,ga,u,v] T2[(a',t),be,v,b]
+  kern::wapply<double>(s, t2.F, f2.p, f1.p, 2LL * mlo, mri, (long long)wm * 2 * mri, 1, 2LL * mri, mri,
+                       (long long)2 * wr * mri, 1, mri, (long long)wr * mri);
+  // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b']
+  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 4 * mlo, mro, wr * mri, 1.0, f1.p, (long long)wr * mri, 0, Rt, mro, 0,
+                     0.0, Y, mro, 0, 1);
+}
+
+// out = normalise(fit of O|in>): `passes` alternating two-site passes from
+// the left, starting from |in> brought to right-canonical form; every split
+// takes the eps / chi_max cut of the gauge moves.  The result is
+// left-canonical with its centre on the last site.  Returns the weight
+// discarded in the last pass.
+double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps, int chi_max, int passes,
+                 tdvp_mps_s& out) {
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  const int N = in.N;
+  if (N < 2) TDVP_THROW(TDVP_ERR_ARG, "variational MPO application needs at least two sites");
+  if (passes < 1) TDVP_THROW(TDVP_ERR_ARG, "variational MPO application needs at least one pass");
+  const double in_norm = W.sc.norm(in.site(N - 1), in.elems(N - 1));
+  if (!std::isfinite(in_norm)) TDVP_THROW(TDVP_ERR_NUMERIC, "MPS with non-finite entries");
+  out.ctx = ctx;
+  out.N = N;
+  out.m = in.m;
+  out.t.clear();
+  for (int i = 0; i < N; ++i) {
+    out.t.emplace_back(ctx);
+    out.t[i].ensure((size_t)in.elems(i) * ZB);
+    HIP_CHECK(hipMemcpyAsync(out.t[i].p, in.site(i), (size_t)in.elems(i) * ZB, hipMemcpyDeviceToDevice, s));
+  }
+  right_canonicalize(W, out);
+  std::vector<DBuf> Ls, Rs;
+  for (int i = 0; i <= N; ++i) {
+    Ls.emplace_back(ctx);
+    Rs.emplace_back(ctx);
+  }
+  set_one(ctx, Ls[0], ZB);
+  set_one(ctx, Rs[N], ZB);
+  DBuf f1(ctx), f2(ctx), P(ctx), Th(ctx), X(ctx), Y(ctx);
+  for (int i = N - 1; i >= 2; --i) {
+    Rs[i].ensure((size_t)op.w(i) * in.m[i] * out.m[i] * ZB);
+    fit_env_right(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1], Rs[i + 1].p,
+                  out.site(i), in.site(i), Rs[i].p, f1, f2);
+  }
+  // two-site tensor of phi at (i, i+1) from the current environments
+  auto local = [&](int i) {
+    const int mli = in.m[i], mc = in.m[i + 1], mri = in.m[i + 2], mlo = out.m[i], mro = out.m[i + 2];
+    P.ensure((size_t)mli * 4 * mri * ZB);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, 2 * mri, mc, 1.0, in.site(i), mc, 0, in.site(i + 1),
+                       2LL * mri, 0, 0.0, P.p, 2LL * mri, 0, 1);
+    Th.ensure((size_t)mlo * 4 * mro * ZB);
+    fit_local2(ctx, op.tab[i], op.tab[i + 1], mlo, mli, op.w(i), op.w(i + 1), op.w(i + 2), mri, mro, Ls[i].p,
+               Rs[i + 2].p, P.p, Th.p, f1, f2);
+  };
+  double disc = 0.0;
+  for (int pass = 0; pass < passes; ++pass) {
+    disc = 0.0;
+    if (pass % 2 == 0) {   // left to right: phi_i left-canonical, centre moves on
+      for (int i = 0; i + 1 < N; ++i) {
+        local(i);
+        const int mlo = out.m[i], mro = out.m[i + 2];
+        const int k = split_left(W, Th.as<double>(), mlo, 2 * mro, eps, chi_max, X, Y, &disc);
+        std::swap(out.t[i], X);
+        std::swap(out.t[i + 1], Y);
+        out.m[i + 1] = k;
+        Ls[i + 1].ensure((size_t)k * op.w(i + 1) * in.m[i + 1] * ZB);
+        fit_env_left(ctx, op.tab[i], mlo, in.m[i], op.w(i), op.w(i + 1), k, in.m[i + 1], Ls[i].p, out.site(i),
+                     in.site(i), Ls[i + 1].p, f1, f2);
+      }
+    } else {               // right to left: phi_{i+1} right-canonical
+      for (int i = N - 2; i >= 0; --i) {
+        local(i);
+        const int mlo = out.m[i], mro = out.m[i + 2];
+        const int k = split_right(W, Th.as<double>(), 2 * mlo, mro, eps, chi_max, X, Y, &disc);
+        std::swap(out.t[i], X);
+        std::swap(out.t[i + 1], Y);
+        out.m[i + 1] = k;
+        Rs[i + 1].ensure((size_t)op.w(i + 1) * in.m[i + 1] * k * ZB);
+        fit_env_right(ctx, op.tab[i + 1], k, in.m[i + 1], op.w(i + 1), op.w(i + 2), mro, in.m[i + 2], Rs[i + 2].p,
+                      out.site(i + 1), in.site(i + 1), Rs[i + 1].p, f1, f2);
+      }
+    }
+  }
+  if (passes % 2 == 0) left_canonicalize(W, out);
+  const double nr = W.sc.norm(out.site(N - 1), out.elems(N - 1));
+  if (!(nr > 0.0) || !std::isfinite(nr)) TDVP_THROW(TDVP_ERR_NUMERIC, "MPO application vanished or is not finite");
+  kern::zscale(s, out.t[N - 1].p, out.t[N - 1].p, zc(1.0 / nr, 0.0), out.elems(N - 1));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return disc;
+}
+
 // ------------------------------------------------------ basis extension
 void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps_M, int chi_max, int* n_added) {
   tdvp_ctx_s* ctx = W.ctx;
@@ -1183,7 +1330,9 @@ void expand_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const t
     std::vector<tdvp_mps_s> kv(p.k - 1);
     const tdvp_mps_s* prev = &psi;
     for (int l = 0; l + 1 < p.k; ++l) {
-      st.discarded_K += denmat_apply<T>(W, *prev, op, p.eps_K, p.chi_max, kv[l]);
+      st.discarded_K += p.apply_method == TDVP_APPLY_FIT
+                            ? fit_apply(W, *prev, op, p.eps_K, p.chi_max, std::max(1, p.fit_passes), kv[l])
+                            : denmat_apply<T>(W, *prev, op, p.eps_K, p.chi_max, kv[l]);
       prev = &kv[l];
       for (int b = 0; b <= N; ++b) st.krylov_max_bond = std::max(st.krylov_max_bond, kv[l].m[b]);
     }
@@ -1233,6 +1382,31 @@ void run_expand(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const td
     kern::FloatModeScope mode(kern::float_mode_of(p.prec));
     expand_impl<float>(ctx, psi, op, p, st);
   }
+}
+
+void run_apply_mpo(tdvp_ctx_s* ctx, const tdvp_mps_s& in, const tdvp_mpo_s& op, int method, double eps, int chi_max,
+                   int passes, tdvp_mps_s& out, double* discarded) {
+  Work W(ctx);
+  double d;
+  if (method == TDVP_APPLY_FIT) {
+    d = fit_apply(W, in, op, eps, chi_max, passes, out);
+  } else {
+    // the density-matrix route reads the norm from the last site of a
+    // left-canonical input
+    tdvp_mps_s lc;
+    lc.ctx = ctx;
+    lc.N = in.N;
+    lc.m = in.m;
+    for (int i = 0; i < in.N; ++i) {
+      lc.t.emplace_back(ctx);
+      lc.t[i].ensure((size_t)in.elems(i) * ZB);
+      HIP_CHECK(hipMemcpyAsync(lc.t[i].p, in.site(i), (size_t)in.elems(i) * ZB, hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    }
+    left_canonicalize(W, lc);
+    d = denmat_apply<double>(W, lc, op, eps, chi_max, out);
+  }
+  if (discarded) *discarded = d;
 }
 
 // ------------------------------------------------------------ measurement

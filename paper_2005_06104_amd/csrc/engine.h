@@ -33,6 +33,8 @@ struct tdvp_mps_s {
 
 std::unique_ptr<tdvp_mpo_s> make_mpo(tdvp_ctx_s* ctx, HostMPO&& host);
 std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host);
+void run_apply_mpo(tdvp_ctx_s* ctx, const tdvp_mps_s& in, const tdvp_mpo_s& op, int method, double eps, int chi_max,
+                   int passes, tdvp_mps_s& out, double* discarded);
 
 void run_sweep(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
                tdvp_sweep_stats& st);

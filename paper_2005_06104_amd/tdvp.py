@@ -40,7 +40,7 @@ class tdvp_term(C.Structure):
 
 class tdvp_expand_params(C.Structure):
     _fields_ = [("k", C.c_int), ("eps_K", C.c_double), ("eps_M", C.c_double), ("chi_max", C.c_int),
-                ("prec", C.c_int), ("skip_if_full", C.c_int)]
+                ("prec", C.c_int), ("skip_if_full", C.c_int), ("apply_method", C.c_int), ("fit_passes", C.c_int)]
 
 
 class tdvp_expand_stats(C.Structure):
@@ -104,6 +104,7 @@ def load():
         "tdvp_mps_bond_dims": (i, [vp, C.POINTER(i), C.POINTER(i), i]),
         "tdvp_mps_to_host": (i, [vp, C.POINTER(d), C.c_size_t]),
         "tdvp_mps_destroy": (None, [vp]),
+        "tdvp_apply_mpo": (i, [vp, vp, vp, i, d, i, i, C.POINTER(vp), C.POINTER(d)]),
         "tdvp_expand_basis": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_expand_params),
                                   C.POINTER(tdvp_expand_stats)]),
         "tdvp_sweep": (i, [vp, i, C.POINTER(vp), C.POINTER(vp), C.POINTER(tdvp_sweep_params),
@@ -340,9 +341,24 @@ def _handles(objs):
     return arr
 
 
+APPLY = {"denmat": 0, "fit": 1}
+
+
+def tdvp_apply_mpo(ctx: Context, psi: MPS, op: MPO, method: str = "fit", eps: float = 0.0,
+                   chi_max: int = 1 << 30, passes: int = 3):
+    """(new MPS = op|psi>, normalised and truncated; discarded weight)."""
+    h = C.c_void_p()
+    disc = C.c_double()
+    ctx.check(ctx.lib.tdvp_apply_mpo(ctx.h, psi.h, op.h, APPLY[method], float(eps), int(chi_max), int(passes),
+                                     C.byref(h), C.byref(disc)), "tdvp_apply_mpo")
+    return MPS(ctx, h, psi.n_sites), disc.value
+
+
 def tdvp_expand_basis(ctx: Context, psi: Sequence[MPS], op: Sequence[MPO], k: int, eps_K: float, eps_M: float,
-                      chi_max: int, prec: str = "fp64", skip_if_full: bool = True) -> List[dict]:
-    p = tdvp_expand_params(int(k), float(eps_K), float(eps_M), int(chi_max), PREC[prec], int(bool(skip_if_full)))
+                      chi_max: int, prec: str = "fp64", skip_if_full: bool = True, apply: str = "denmat",
+                      fit_passes: int = 3) -> List[dict]:
+    p = tdvp_expand_params(int(k), float(eps_K), float(eps_M), int(chi_max), PREC[prec], int(bool(skip_if_full)),
+                           APPLY[apply], int(fit_passes))
     stats = (tdvp_expand_stats * len(psi))()
     ctx.check(ctx.lib.tdvp_expand_basis(ctx.h, len(psi), _handles(psi), _handles(op), C.byref(p), stats),
               "tdvp_expand_basis")

@@ -69,6 +69,8 @@ def test_null_handles_are_rejected():
     assert lib.tdvp_sweep(None, 1, None, None, None, None) == T.TDVP_ERR_ARG
     assert lib.tdvp_expand_basis(None, 1, None, None, None, None) == T.TDVP_ERR_ARG
     assert lib.tdvp_measure(None, 1, None, None, None, None) == T.TDVP_ERR_ARG
+    out, disc = C.c_void_p(), C.c_double()
+    assert lib.tdvp_apply_mpo(None, None, None, 1, 1e-8, 8, 1, C.byref(out), C.byref(disc)) == T.TDVP_ERR_ARG
     assert lib.tdvp_synchronize(None) == T.TDVP_ERR_ARG
     h = C.c_void_p()
     assert lib.tdvp_ctx_create(0, None, T.ALLOC_FN(), T.FREE_FN(), None, None) == T.TDVP_ERR_ARG
