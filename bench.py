@@ -239,6 +239,51 @@ def oat_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def apply_compare_mode(args):
+    """The two MPO applications of section I.C on the state of the main bench
+    (64-site ladder brought to chi = 256 by four imaginary-time GSE steps):
+    one Krylov vector (1 - i tau H)|psi> with the bench's eps_K and chi_max by
+    the density-matrix algorithm and by variational fitting with 1 and 3
+    passes, each timed K times, with the fidelity between the results."""
+    import numpy as np
+    import torch
+
+    from paper_2005_06104_amd import inputs as I
+    from paper_2005_06104_amd import tdvp as T
+    torch.cuda.set_device(0)
+    ctx = T.Context(0)
+    w = I.workload(1)
+    N = w.lattice.n_sites
+    H = T.tdvp_create_mpo(ctx, N, w.terms)
+    op = T.tdvp_create_mpo(ctx, N, w.terms, 1.0, -1j * w.tau)
+    psi = T.tdvp_mps_from_host(ctx, w.initial_mps())
+    for i in range(4):
+        T.tdvp_expand_basis(ctx, [psi], [op], w.k, w.eps_K, w.eps_M, w.chi_max, "fp64")
+        T.tdvp_sweep(ctx, [psi], [H], w.dt, w.eps, w.chi_max, 1e-12, 30, "fp64", w.normalize)
+    log(f"[apply] state: max bond {max(psi.bond_dims())}, MPO bond dimension up to {max(op.dims)}")
+    rows, outs = {}, {}
+    for name, method, passes in (("denmat", "denmat", 1), ("fit1", "fit", 1), ("fit3", "fit", 3)):
+        times = []
+        for r in range(args.steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h, disc = T.tdvp_apply_mpo(ctx, psi, op, method, w.eps_K, w.chi_max, passes)
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(1e3 * (time.perf_counter() - t0))
+            if r < args.steps:
+                del h
+        outs[name] = h
+        rows[name] = {"ms": float(np.median(times)), "max_bond": max(h.bond_dims()), "discarded": disc}
+        log(f"[apply] {name}: {rows[name]['ms']:.1f} ms, max bond {rows[name]['max_bond']}, discarded {disc:.3e}")
+    for name in ("fit1", "fit3"):
+        o = T.tdvp_measure(ctx, [outs["denmat"]], None, [outs[name]])[0]
+        rows[name]["infidelity_vs_denmat"] = float(1.0 - abs(o["overlap"]) ** 2)
+        log(f"[apply] 1 - |<denmat|{name}>|^2 = {rows[name]['infidelity_vs_denmat']:.3e}")
+    print(json.dumps({"mode": "apply_compare", "workload": w.name, "chi_max": w.chi_max, "eps_K": w.eps_K,
+                      "steps": args.steps, "results": rows}))
+
+
 def tdvp2_compare_mode(args):
     """GSE-TDVP1 against two-site TDVP at the same bond dimension m' (the cost
     statement closing section I.C, made for real time with k = 5 and m' ~ 3m):
@@ -472,6 +517,8 @@ def main():
     ap.add_argument("--batch-serial", action="store_true", help="step the batch one instance per call")
     ap.add_argument("--tdvp2-compare", action="store_true",
                     help="GSE-TDVP1 step against a two-site TDVP step at the same bond dimension")
+    ap.add_argument("--apply-compare", action="store_true",
+                    help="one Krylov vector by the density-matrix and the variational MPO application")
     ap.add_argument("--kernel-chi", type=int, default=256)
     ap.add_argument("--kernel-w", type=int, default=8)
     ap.add_argument("--oat", action="store_true",
@@ -497,6 +544,9 @@ def main():
         return
     if args.tdvp2_compare:
         tdvp2_compare_mode(args)
+        return
+    if args.apply_compare:
+        apply_compare_mode(args)
         return
     import torch
 
