@@ -14,7 +14,9 @@
 // A library call per column costs a few microseconds of dispatch on this GPU,
 // so the whole reduction is one launch: G workgroups keep the matrix rows
 // (row r on workgroup r % G) and the matching rows of Q in LDS and exchange
-// per column the vector x = tau A v, the next pivot row and partial sums.
+// per column the vector x = tau A v and the next pivot row; every workgroup
+// then forms x^H v from the whole x itself (no exchange of partial sums,
+// whose publication after the row products was the last arrival).
 // The exchange needs no barrier: every published complex is stored as four
 // 64-bit words, each holding 32 bits of the value and the column's tag, and
 // a reader polls the words it needs until all carry the current tag (one
@@ -44,7 +46,6 @@ struct TdArgs {
   // tagged words (four per complex, zero at launch), two buffers each:
   unsigned long long* xv;     // published x = tau A v, 2 x n
   unsigned long long* prow;   // published pivot row, 2 x n
-  unsigned long long* p2;     // partial x^H v per workgroup, 2 x G
   int* err;                   // 0 at launch; 1 when a wait ran out
   int n, G, R;
 };
@@ -125,8 +126,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
   __shared__ double2 sM[TD_LDS];        // A rows [R][n], then Q rows [R][n]
   __shared__ double2 sv[TD_NMAX], sw[TD_NMAX], srow[TD_NMAX];
   __shared__ double sred[TNT / 64];     // per-wave |row[k+2:]|^2 of the pivot row
-  __shared__ double2 s_t;               // x^H v of the current column
-  __shared__ double2 s_part[TD_ROWS];
+  __shared__ double2 s_xv[TNT / 64];    // per-wave parts of x^H v
   __shared__ int s_fail;
 
   const int n = a.n, G = a.G, R = a.R, g = blockIdx.x, tid = threadIdx.x;
@@ -181,7 +181,6 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     const unsigned tag = (unsigned)k + 1u;
     unsigned long long* xvp = a.xv + (size_t)par * 4 * n;
     unsigned long long* rowp = a.prow + (size_t)par * 4 * n;
-    unsigned long long* p2p = a.p2 + (size_t)par * 4 * G;
     double2 tqs{0.0, 0.0};
     if (rj < nrow) {
       double2 sa{0.0, 0.0}, sq{0.0, 0.0};
@@ -201,29 +200,13 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       sq.y = wave::group_sum(sq.y, T);
       tqs = cmul(tau, sq);
       const int r = g + rj * G;
-      if (rt == 0) {
-        double2 contrib{0.0, 0.0};
-        if (r >= k + 1) {
-          const double2 x = cmul(tau, sa), vr = hh_v(r, k, srow[r], sc);
-          put_tagged(xvp + 4 * (size_t)r, x, tag);
-          contrib = double2{x.x * vr.x + x.y * vr.y, x.x * vr.y - x.y * vr.x};   // conj(x) v
-        }
-        s_part[rj] = contrib;
-      }
+      if (rt == 0 && r >= k + 1) put_tagged(xvp + 4 * (size_t)r, cmul(tau, sa), tag);
     }
     if ((k + 1) % G == g) {
       const int j = (k + 1) / G;
       for (int c = k + 1 + tid; c < n; c += TNT) put_tagged(rowp + 4 * (size_t)c, sA[j * n + c], tag);
     }
     __syncthreads();
-    if (tid == 0) {
-      double2 t{0.0, 0.0};
-      for (int j = 0; j < nrow; ++j) {
-        t.x += s_part[j].x;
-        t.y += s_part[j].y;
-      }
-      put_tagged(p2p + 4 * (size_t)g, t, tag);
-    }
 
     // ---- while the others arrive: Q <- Q H_k = Q - tau (Q v) v^H on the own rows
     if (rj < nrow) {
@@ -234,14 +217,12 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         qrow[c].y -= d.y;
       }
     }
-    // ---- gather this column's x, pivot row and partial sums as they arrive
-    // (every thread its own entries of x and the row; the partial sums by
-    // wave 0 only: polls from all waves slowed the publishers down, 7% at
-    // n = 512)
+    // ---- gather this column's x and pivot row as they arrive (every thread
+    // its own entries)
     constexpr int NQ = (TD_NMAX + TNT - 1) / TNT;
-    double2 xq[NQ], rq[NQ], tp{0.0, 0.0}, tp2{0.0, 0.0};
+    double2 xq[NQ], rq[NQ];
     {
-      bool gx[NQ], gr[NQ], gp = wave != 0 || lane >= G, gp2 = wave != 0 || lane + 64 >= G;
+      bool gx[NQ], gr[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int c = k + 1 + tid + q * TNT;
@@ -258,9 +239,6 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
           if (!gr[q]) gr[q] = get_tagged(rowp + 4 * (size_t)c, tag, &rq[q]);
           done = done && gx[q] && gr[q];
         }
-        if (!gp) gp = get_tagged(p2p + 4 * (size_t)lane, tag, &tp);
-        if (!gp2) gp2 = get_tagged(p2p + 4 * (size_t)(lane + 64), tag, &tp2);
-        done = done && gp && gp2;
         if (done) break;
         ++polls;
         if (polls > SPIN_LIMIT ||
@@ -272,9 +250,19 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    if (wave == 0) {   // x^H v from the published partials, in a fixed order
-      const double2 t = wave_sum(double2{tp.x + tp2.x, tp.y + tp2.y});
-      if (lane == 0) s_t = t;
+    {   // x^H v from the gathered x: own entries, the wave, then the waves in order
+      double2 pv{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c = k + 1 + tid + q * TNT;
+        if (c < n) {
+          const double2 v = sv[c];
+          pv.x += xq[q].x * v.x + xq[q].y * v.y;
+          pv.y += xq[q].x * v.y - xq[q].y * v.x;
+        }
+      }
+      pv = wave_sum(pv);
+      if (lane == 0) s_xv[wave] = pv;
     }
     __syncthreads();
     if (s_fail) {
@@ -285,7 +273,12 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     // ---- w = x - (tau/2)(x^H v) v; next pivot row and its norm beyond
     // column k+2; A <- A - v w^H - w v^H on the own rows
     {
-      const double2 t = s_t;
+      double2 t = s_xv[0];
+#pragma unroll
+      for (int w = 1; w < TNT / 64; ++w) {
+        t.x += s_xv[w].x;
+        t.y += s_xv[w].y;
+      }
       const double2 a2x = cmul(tau, t);
       const double2 a2{-0.5 * a2x.x, -0.5 * a2x.y};
 #pragma unroll
@@ -386,8 +379,8 @@ int tridiag_groups(int n) {
   // the exchange with the number of workgroups: four rows per workgroup (one
   // wave per row) is fastest at every n measured, 8 to 512 (eight rows are
   // 8-15% slower from n = 64 on, two no faster, one workgroup for n <= 32 up
-  // to 25% slower).  At most 128 workgroups (each lane of a wave combines
-  // two partial sums), and 2 R n complex slots of LDS for the A and Q rows.
+  // to 25% slower).  At most 128 workgroups, and 2 R n complex slots of LDS
+  // for the A and Q rows.
   const int G = std::min(128, (n + 3) / 4);
   const int R = (n + G - 1) / G;
   return (2 * R * n <= TD_LDS && R <= TD_ROWS) ? G : 0;
@@ -395,7 +388,7 @@ int tridiag_groups(int n) {
 
 size_t tridiag_scratch_bytes(int n) {
   const int G = tridiag_groups(n);
-  return sizeof(unsigned long long) * 4 * (4 * (size_t)n + 2 * (size_t)G) + 256;
+  return G == 0 ? 0 : sizeof(unsigned long long) * 4 * 4 * (size_t)n + 256;
 }
 
 hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err) {
@@ -409,12 +402,11 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
   a.E = E;
   a.xv = reinterpret_cast<unsigned long long*>(p);     // two buffers of n complex each
   a.prow = a.xv + 8 * (size_t)n;
-  a.p2 = a.prow + 8 * (size_t)n;                        // two buffers of G
   a.err = err;
   a.n = n;
   a.G = G;
   a.R = (n + G - 1) / G;
-  const int nw = 2 * 4 * (4 * n + 2 * G);   // 32-bit halves of the tagged words
+  const int nw = 2 * 4 * 4 * n;   // 32-bit halves of the tagged words
   hipLaunchKernelGGL(td_reset_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, reinterpret_cast<unsigned*>(a.xv), nw,
                      err);
   void* args[] = {&a};
