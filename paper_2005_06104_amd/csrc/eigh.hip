@@ -175,7 +175,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     }
 
     // ---- one pass over the own rows (T threads per row): x = tau A v for
-    // rows >= k+1 and tau (Q v) for the accumulation of Q; partial x^H v.
+    // rows >= k+1 and tau (Q v) for the accumulation of Q.
     // v is formed on the fly (the threads of local row 0 also store it).
     // The owner of row k+1 publishes it (before this column's update).
     const unsigned tag = (unsigned)k + 1u;
