@@ -114,8 +114,10 @@ struct Lanczos {
     // v_{j+1} = w / |w| with |w|^2 summed by the scaling kernel itself, which
     // also writes the scalars into pinned host memory.  The next
     // iteration is enqueued before the host reads this one's scalars, so the
-    // device never waits for the convergence test; when the test stops the
-    // recurrence, the one extra iteration is discarded.
+    // device does not wait for the convergence test; when the test stops the
+    // recurrence, that extra iteration is discarded.  When the error
+    // estimates of the last two iterations extrapolate (geometrically) to
+    // convergence at this one, the next is enqueued only if the test fails.
     const zc* staged[2] = {nullptr, nullptr};
     auto enqueue = [&](int j) {
       void* w = vec(j + 1);
@@ -131,8 +133,11 @@ struct Lanczos {
       staged[j & 1] = static_cast<const zc*>(ctx->stage_mark(j & 1));
     };
     enqueue(0);
+    int queued = 0;                       // last iteration enqueued
+    double err1 = -1.0, err2 = -1.0;      // relative error estimates of j-1, j-2
     for (int j = 0; j < maxit; ++j) {
-      if (j + 1 < maxit) enqueue(j + 1);
+      const bool likely_last = err1 > 0.0 && err2 > 0.0 && err1 * (err1 / err2) <= tol;
+      if (queued < j + 1 && j + 1 < maxit && !likely_last) enqueue(queued = j + 1);
       ctx->wait_stage(j & 1);
       const zc* hv = staged[j & 1];
       if (timer) timer->collect(j & 1);
@@ -160,6 +165,9 @@ struct Lanczos {
         break;
       }
       beta.push_back(b);
+      if (queued < j + 1) enqueue(queued = j + 1);
+      err2 = err1;
+      err1 = cn2 > 0.0 ? b * std::abs(clast) / std::sqrt(cn2) : -1.0;
     }
     tridiag_eig(dim);
     c.assign(dim, zc(0.0, 0.0));
