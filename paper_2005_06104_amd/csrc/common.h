@@ -271,6 +271,10 @@ void zhermitize(hipStream_t s, void* A, long long n);
 void zhermitize_to(hipStream_t s, void* A, const void* S, long long n, int* zero = nullptr, int nzero = 0);
 // fill complex with value
 void zfill(hipStream_t s, void* dst, zc v, long long n, int esize);
+// zcombine_p's update, then the partial dot products conj(V[j]) . w of the
+// updated w per block (zcombine_norm_blocks(n) x nv, zcombine_p's layout)
+void zcombine_dots(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* partial, int nb,
+                   double sign, long long n, void* cout, void* dpart);
 // w /= |w| with |w|^2 the sum of the np partial sums left by zcombine_p
 // (real parts); out[0] receives |w|^2 (complex128, imaginary part zero).
 // With host (a mapped host address), the first block also writes

@@ -70,8 +70,9 @@ struct Lanczos {
     const int nb = kern::zdots_blocks(n);
     const int nnp = kern::zcombine_norm_blocks(n);
     // the dot-product partials, then the partial sums of |w|^2
-    partial.ensure(((size_t)nb * (maxit + 1) + (size_t)nnp) * ZB);
+    partial.ensure(((size_t)nb * (maxit + 1) + (size_t)nnp * (maxit + 2)) * ZB);
     double2* npart = partial.as<double2>() + (size_t)nb * (maxit + 1);
+    double2* dpart2 = npart + nnp;   // second-pass partial dot products, nnp x (j + 1)
     scal.ensure(256 * ZB);
     double2* S = scal.as<double2>();
     // S: [0, 64) and [64, 128) the two projection passes, 128 |w|^2, 192.. the
@@ -109,7 +110,8 @@ struct Lanczos {
     auto phase = [&](int e) { return std::exp(zc(0.0, -1.0) * dt * dd[e]); };
     // Iteration j on the device: w = H v_j, classical Gram-Schmidt twice
     // against v_0..v_j (each pass: partial dot products, then the update,
-    // whose blocks sum the partials themselves; the second pass leaves
+    // whose blocks sum the partials themselves; the first update also forms
+    // the second pass's partial products on its chunk, and the second leaves
     // per-block sums of |w|^2),
     // v_{j+1} = w / |w| with |w|^2 summed by the scaling kernel itself, which
     // also writes the scalars into pinned host memory.  The next
@@ -124,9 +126,8 @@ struct Lanczos {
       if (timer) timer->cur = j & 1;
       mv(vec(j), w);
       kern::zdots_partial(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb);
-      kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S, nullptr);
-      kern::zdots_partial(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb);
-      kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S + 64, npart);
+      kern::zcombine_dots(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S, dpart2);
+      kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, dpart2, nnp, -1.0, n, S + 64, npart);
       // the normalisation also writes the first-pass projections (alpha_j =
       // <v_j|H v_j>) and |w|^2 into the pinned slot the host reads
       kern::zscale_invnorm(ctx->stream, w, npart, nnp, S + 128, n, ctx->stage_slot_dev(j & 1), S, j + 1, 128);

@@ -720,6 +720,70 @@ __global__ __launch_bounds__(VNT) void zcombine_p_kernel(double2* __restrict__ w
   }
 }
 
+// The same update, then the block's partial dot products of the updated w
+// with every vector, dpart[blockIdx.x * nv + j] = sum over the block's x of
+// conj(V[j][x]) w[x] (the layout zcombine_p_kernel reads): the second
+// Gram-Schmidt pass gets its projections without another read of V.
+__global__ __launch_bounds__(VNT) void zcombine_dots_kernel(double2* __restrict__ w, const double2* __restrict__ V,
+                                                            long long ldv, int nv,
+                                                            const double2* __restrict__ partial, int nb,
+                                                            double sign, long long n, double2* __restrict__ cout,
+                                                            double2* __restrict__ dpart) {
+  __shared__ double2 sc[ZC_MAXV];
+  __shared__ double2 sd[VNT / 64][ZC_MAXV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = wv; j < nv; j += VNT / 64) {
+    double re = 0.0, im = 0.0;
+    for (int b = lane; b < nb; b += 64) {
+      const double2 p = partial[(long long)b * nv + j];
+      re += p.x;
+      im += p.y;
+    }
+    re = warp_sum(re);
+    im = warp_sum(im);
+    if (lane == 0) sc[j] = make_double2(re, im);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && cout)
+    for (int j = threadIdx.x; j < nv; j += VNT) cout[j] = sc[j];
+  const long long x = (long long)blockIdx.x * VNT + threadIdx.x;
+  double2 o = make_double2(0.0, 0.0);
+  if (x < n) {
+    double sr = 0.0, si = 0.0;
+    for (int j = 0; j < nv; ++j) {
+      const double2 cj = sc[j];
+      const double2 v = V[(long long)j * ldv + x];
+      sr += cj.x * v.x - cj.y * v.y;
+      si += cj.x * v.y + cj.y * v.x;
+    }
+    o = w[x];
+    o.x += sign * sr;
+    o.y += sign * si;
+    w[x] = o;
+  }
+  for (int j = 0; j < nv; ++j) {   // uniform loop: every lane takes part in the sums
+    double re = 0.0, im = 0.0;
+    if (x < n) {
+      const double2 v = V[(long long)j * ldv + x];
+      re = v.x * o.x + v.y * o.y;
+      im = v.x * o.y - v.y * o.x;
+    }
+    re = warp_sum(re);
+    im = warp_sum(im);
+    if (lane == 0) sd[wv][j] = make_double2(re, im);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nv; j += VNT) {
+    double2 t = sd[0][j];
+#pragma unroll
+    for (int q = 1; q < VNT / 64; ++q) {
+      t.x += sd[q][j].x;
+      t.y += sd[q][j].y;
+    }
+    dpart[(long long)blockIdx.x * nv + j] = t;
+  }
+}
+
 // every block sums the np partial norms in the same fixed order, so all
 // agree on |w|^2; block 0 also stores it
 __global__ __launch_bounds__(VNT) void zscale_invnorm_kernel(double2* __restrict__ w,
@@ -976,6 +1040,16 @@ void zcombine_p(hipStream_t s, void* w, const void* V, long long ldv, int nv, co
     hipLaunchKernelGGL(zcombine_p_kernel<false>, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
                        static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(partial), nb, sign, n,
                        static_cast<double2*>(cout), nullptr);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zcombine_dots(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* partial, int nb,
+                   double sign, long long n, void* cout, void* dpart) {
+  if (n <= 0 || nv <= 0) return;
+  if (nv > ZC_MAXV) TDVP_THROW(TDVP_ERR_ARG, "zcombine_dots: at most 64 vectors");
+  hipLaunchKernelGGL(zcombine_dots_kernel, dim3(nblk(n, VNT)), dim3(VNT), 0, s, static_cast<double2*>(w),
+                     static_cast<const double2*>(V), ldv, nv, static_cast<const double2*>(partial), nb, sign, n,
+                     static_cast<double2*>(cout), static_cast<double2*>(dpart));
   HIP_CHECK(hipGetLastError());
 }
 
