@@ -530,7 +530,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the GSE-TDVP1 sweep of one MPS is sequential over sites and "
-              f"this build has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+              f"the library has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
     if args.kernel_only:
