@@ -209,8 +209,10 @@ tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo
 
 typedef struct {
   double dt_re, dt_im;   /* the sweep evolves exp(-i H dt); imaginary dtau: dt = -i dtau */
-  double eps;            /* gauge-move cutoff (0 = QR, unitary)                           */
-  int chi_max;           /* cap on bonds when eps > 0                                     */
+  double eps;            /* gauge-move cutoff (0 = exact moves, unitary)                  */
+  int chi_max;           /* cap on bonds when eps > 0 (tdvp_sweep with eps = 0 never
+                            truncates, whatever the bonds; tdvp_sweep2 caps its
+                            two-site splits at chi_max also when eps = 0)                 */
   double krylov_tol;     /* Lanczos stop: beta_j |c_j| <= tol |c|                          */
   int krylov_max;        /* at most this many Lanczos vectors (<= 64)                      */
   int prec;              /* tdvp_prec of the contractions                                  */
@@ -238,8 +240,11 @@ typedef struct {
  * dt/2 per site, right to left by dt/2; the last site takes dt at once).
  * Precondition: center at site 0, sites 1..N-1 right-canonical (the state
  * tdvp_expand_basis leaves).  Postcondition: the same gauge.
- * Errors: TDVP_ERR_ARG (bad parameters, MPO/MPS mismatch), TDVP_ERR_NOCONV
- * (strict mode), TDVP_ERR_NUMERIC (non-finite values). */
+ * Errors: TDVP_ERR_ARG (bad parameters, MPO/MPS mismatch, the same state
+ * twice in psi[]), TDVP_ERR_NOCONV (strict mode: some local Lanczos run
+ * reached krylov_max; the sweep was completed with those unconverged local
+ * results, every state stays valid and stats are filled in),
+ * TDVP_ERR_NUMERIC (non-finite values). */
 tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H,
                        const tdvp_sweep_params* params, tdvp_sweep_stats* stats);
 
@@ -266,9 +271,30 @@ tdvp_status tdvp_sweep2(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H,
                         const tdvp_sweep_params* params, tdvp_sweep_stats* stats);
 
 /* Measure psi[j] (any gauge) for j < n; H and other may be NULL (then n
- * entries each when given). */
+ * entries each when given).  The observables are those the benchmarks of
+ * section II report: the energy <H> (section II.A: its convergence in
+ * imaginary time; section II.B: its conservation in real time, relative
+ * error below 1e-10), the local magnetisations, the norm, the bond
+ * dimensions, and the overlap <other|psi> from which fidelities follow.  Any
+ * MPO may be passed as H, e.g. the total-spin moments of eqs. (13)-(15).
+ * Errors: TDVP_ERR_ARG (NULL handles, H or other with another site count),
+ * TDVP_ERR_STATE (an invalidated handle). */
 tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mpo* H,
                          const tdvp_mps* other, tdvp_observables* out);
+
+/* Spin-squeezing parameter of eq. (14) in the closed form of eq. (15), from
+ * measured total-spin moments (host only, needs no device): with
+ * V_aa = <(S^a)^2> - <S^a>^2 and V_yz = <S^y S^z + S^z S^y>/2 - <S^y><S^z>,
+ * the smallest variance in the y-z plane is
+ * v = (V_yy + V_zz - sqrt((V_yy - V_zz)^2 + 4 V_yz^2)) / 2 and
+ * *xi2 = n_spins * v / <S^x>^2 (the mean spin points along x, as in the
+ * one-axis-twisting benchmark of section II.B).  Arguments: the first
+ * moments sx, sy, sz, the second moments syy = <(S^y)^2>, szz = <(S^z)^2>,
+ * and syz_sym = <S^y S^z + S^z S^y>.
+ * Errors: TDVP_ERR_ARG for n_spins < 1, NULL xi2, non-finite moments or
+ * sx = 0. */
+tdvp_status tdvp_squeezing_xi2(int n_spins, double sx, double sy, double sz, double syy, double szz,
+                               double syz_sym, double* xi2);
 
 /* ---------------------------------------------------- kernel-level calls
  * Device pointers, complex in the precision `prec` (complex128 or complex64),

@@ -3,6 +3,7 @@
 #include <cstring>
 #include <exception>
 #include <thread>
+#include <unordered_set>
 
 #include "engine.h"
 
@@ -217,6 +218,13 @@ void for_instances(tdvp_ctx_s* ctx, int n, F&& f) {
   flush_deferred(ctx);
   for (auto& e : errs)
     if (e) std::rethrow_exception(e);
+}
+
+// The instances of one batched call run concurrently and each mutates its
+// state, so a state may appear only once.
+void check_distinct(int n, const tdvp_mps* psi) {
+  std::unordered_set<const tdvp_mps_s*> seen;
+  for (int j = 0; j < n; ++j) ARG_CHECK(seen.insert(psi[j]).second, "the same MPS handle appears twice in psi[]");
 }
 
 bool all_finite(const double* x, size_t n) {
@@ -478,6 +486,7 @@ tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo
       ARG_CHECK(p.apply_method != TDVP_APPLY_FIT || psi[j]->N >= 2, "the variational route needs at least two sites");
       if (!psi[j]->valid || !op[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
+    check_distinct(n, psi);
     bind(ctx);
     for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
       tdvp_expand_stats st{};
@@ -509,19 +518,22 @@ tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, co
       ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
       if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
+    check_distinct(n, psi);
     bind(ctx);
     for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
       tdvp_sweep_stats st{};
       try {
         run_sweep(c, *psi[j], *H[j], p, st);
-      } catch (const TdvpError& e) {
-        if (e.code != TDVP_ERR_NOCONV) psi[j]->valid = false;
-        throw;
       } catch (...) {
         psi[j]->valid = false;
         throw;
       }
       if (stats) stats[j] = st;
+      // strict mode: the sweep has run to its end with the unconverged local
+      // results, so the state stays valid and the statistics are filled in
+      if (p.strict && st.n_unconverged > 0)
+        TDVP_THROW(TDVP_ERR_NOCONV, std::to_string(st.n_unconverged) +
+                                        " local Lanczos runs reached krylov_max without converging");
     });
   });
 }
@@ -544,19 +556,22 @@ tdvp_status tdvp_sweep2(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, c
       ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
       if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
+    check_distinct(n, psi);
     bind(ctx);
     for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
       tdvp_sweep_stats st{};
       try {
         run_sweep2(c, *psi[j], *H[j], p, st);
-      } catch (const TdvpError& e) {
-        if (e.code != TDVP_ERR_NOCONV) psi[j]->valid = false;
-        throw;
       } catch (...) {
         psi[j]->valid = false;
         throw;
       }
       if (stats) stats[j] = st;
+      // strict mode: the sweep has run to its end with the unconverged local
+      // results, so the state stays valid and the statistics are filled in
+      if (p.strict && st.n_unconverged > 0)
+        TDVP_THROW(TDVP_ERR_NOCONV, std::to_string(st.n_unconverged) +
+                                        " local Lanczos runs reached krylov_max without converging");
     });
   });
 }
@@ -576,6 +591,20 @@ tdvp_status tdvp_measure(tdvp_ctx ctx, int n, const tdvp_mps* psi, const tdvp_mp
     for_instances(ctx, n, [&](tdvp_ctx_s* c, int j) {
       run_measure(c, *psi[j], H ? H[j] : nullptr, other ? other[j] : nullptr, out[j]);
     });
+  });
+}
+
+tdvp_status tdvp_squeezing_xi2(int n_spins, double sx, double sy, double sz, double syy, double szz, double syz_sym,
+                               double* xi2) {
+  return guarded(nullptr, [&] {
+    ARG_CHECK(n_spins >= 1 && xi2, "bad arguments");
+    ARG_CHECK(std::isfinite(sx) && std::isfinite(sy) && std::isfinite(sz) && std::isfinite(syy) &&
+                  std::isfinite(szz) && std::isfinite(syz_sym),
+              "non-finite moment");
+    ARG_CHECK(sx != 0.0, "<S^x> must not vanish");
+    const double vyy = syy - sy * sy, vzz = szz - sz * sz, vyz = 0.5 * syz_sym - sy * sz;
+    const double v = 0.5 * (vyy + vzz - std::sqrt((vyy - vzz) * (vyy - vzz) + 4.0 * vyz * vyz));
+    *xi2 = n_spins * v / (sx * sx);
   });
 }
 

@@ -113,3 +113,8 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
                const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk = {});
 // CSR tables for a single host W (kernel-level calls); keeps the device copy in `buf`
 SiteTables upload_tables(tdvp_ctx_s* ctx, const std::vector<zc>& W, int wl, int wr, DBuf& buf);
+// The same tables written into caller-provided device memory (cap bytes at
+// dst, allocates nothing on the device): returns the bytes they take; when
+// that exceeds cap nothing is written and *out is left as it was.
+size_t write_tables(tdvp_ctx_s* ctx, const std::vector<zc>& W, int wl, int wr, void* dst, size_t cap,
+                    SiteTables* out);

@@ -119,6 +119,7 @@ def load():
         "tdvp_env_right": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
         "tdvp_eigh": (i, [vp, i, i, vp, vp, C.POINTER(d)]),
         "tdvp_cholesky": (i, [vp, i, vp, vp, vp, C.POINTER(C.c_int)]),
+        "tdvp_squeezing_xi2": (i, [i, d, d, d, d, d, d, C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -145,6 +146,22 @@ def terms_array(terms) -> "C.Array":
 
 
 # ------------------------------------------------------------------ context
+_live_contexts = weakref.WeakSet()
+_atexit_registered = False
+
+
+def _close_all_contexts():
+    """Destroy every live context (and its MPO/MPS handles) while torch and the
+    HIP runtime are still fully alive: the contexts free device memory through
+    torch's caching allocator, which must not be called back during
+    interpreter shutdown."""
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
     """tdvp_ctx bound to the current torch device and stream, allocating
     through torch's caching allocator."""
@@ -181,6 +198,14 @@ class Context:
         # MPO / MPS handles free their device memory through this context:
         # they are destroyed before it
         self._children = weakref.WeakSet()
+        # atexit handlers run last-registered first: registered after torch
+        # was imported, the contexts are closed before torch's own handlers
+        global _atexit_registered
+        _live_contexts.add(self)
+        if not _atexit_registered:
+            import atexit
+            atexit.register(_close_all_contexts)
+            _atexit_registered = True
 
     def check(self, st: int, what: str):
         if st != TDVP_OK:
@@ -194,6 +219,9 @@ class Context:
             self.h = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():   # torch may be gone: leave the memory to the process exit
+            return
         try:
             self.close()
         except Exception:
@@ -240,6 +268,9 @@ class MPO:
         self.h = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():
+            return
         try:
             self._destroy()
         except Exception:
@@ -303,6 +334,9 @@ class MPS:
         self.h = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():
+            return
         try:
             self._destroy()
         except Exception:
@@ -372,8 +406,14 @@ def tdvp_sweep(ctx: Context, psi: Sequence[MPS], H: Sequence[MPO], dt: complex, 
     p = tdvp_sweep_params(dt.real, dt.imag, float(eps), int(min(chi_max, 2 ** 31 - 1)), float(krylov_tol),
                           int(krylov_max), PREC[prec], int(bool(normalize)), int(bool(strict)))
     stats = (tdvp_sweep_stats * len(psi))()
-    ctx.check(ctx.lib.tdvp_sweep(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats), "tdvp_sweep")
-    return [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
+    st = ctx.lib.tdvp_sweep(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats)
+    out = [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
+    if st == TDVP_ERR_NOCONV:   # strict mode: the sweep completed; the statistics travel with the error
+        err = TdvpError(st, f"tdvp_sweep: {ctx.lib.tdvp_last_error(ctx.h).decode()}")
+        err.stats = out
+        raise err
+    ctx.check(st, "tdvp_sweep")
+    return out
 
 
 def tdvp_sweep2(ctx: Context, psi: Sequence[MPS], H: Sequence[MPO], dt: complex, eps: float = 0.0,
@@ -384,8 +424,14 @@ def tdvp_sweep2(ctx: Context, psi: Sequence[MPS], H: Sequence[MPO], dt: complex,
     p = tdvp_sweep_params(dt.real, dt.imag, float(eps), int(min(chi_max, 2 ** 31 - 1)), float(krylov_tol),
                           int(krylov_max), PREC[prec], int(bool(normalize)), int(bool(strict)))
     stats = (tdvp_sweep_stats * len(psi))()
-    ctx.check(ctx.lib.tdvp_sweep2(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats), "tdvp_sweep2")
-    return [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
+    st = ctx.lib.tdvp_sweep2(ctx.h, len(psi), _handles(psi), _handles(H), C.byref(p), stats)
+    out = [{f: getattr(s, f) for f, _ in tdvp_sweep_stats._fields_} for s in stats]
+    if st == TDVP_ERR_NOCONV:   # strict mode: the sweep completed; the statistics travel with the error
+        err = TdvpError(st, f"tdvp_sweep2: {ctx.lib.tdvp_last_error(ctx.h).decode()}")
+        err.stats = out
+        raise err
+    ctx.check(st, "tdvp_sweep2")
+    return out
 
 
 def tdvp_measure(ctx: Context, psi: Sequence[MPS], H: Optional[Sequence[MPO]] = None,
@@ -407,6 +453,17 @@ def tdvp_measure(ctx: Context, psi: Sequence[MPS], H: Optional[Sequence[MPO]] = 
                     "overlap": complex(obs[j].overlap_re, obs[j].overlap_im),
                     "sz": keep[j][0].copy(), "bond_dims": [int(x) for x in keep[j][1]]})
     return out
+
+
+def tdvp_squeezing_xi2(n_spins: int, sx: float, syy: float, szz: float, syz_sym: float, sy: float = 0.0,
+                       sz: float = 0.0) -> float:
+    """Squeezing parameter of eqs. (14)-(15) from measured total-spin moments."""
+    out = C.c_double()
+    st = load().tdvp_squeezing_xi2(int(n_spins), float(sx), float(sy), float(sz), float(syy), float(szz),
+                                   float(syz_sym), C.byref(out))
+    if st != TDVP_OK:
+        raise TdvpError(st, "tdvp_squeezing_xi2: bad moments")
+    return out.value
 
 
 # -------------------------------------------------------- kernel-level calls

@@ -77,3 +77,42 @@ def test_null_handles_are_rejected():
     lib.tdvp_ctx_destroy(None)
     lib.tdvp_mps_destroy(None)
     lib.tdvp_mpo_destroy(None)
+
+
+def test_squeezing_xi2_matches_eq14_scan():
+    """tdvp_squeezing_xi2 (eq. (15)) against eq. (14) evaluated directly (the
+    variance minimised over directions in the y-z plane by an angle scan) on
+    one-axis-twisted states and on random states whose mean spin also has y
+    and z components."""
+    from oracle import ed
+    from oracle.observables import xi2_dense
+
+    def moments(v, N):
+        S = {a: sum(ed.site_op(op, i, N) for i in range(N)) for a, op in (("x", ed.SX), ("y", ed.SY), ("z", ed.SZ))}
+        e = lambda A: ed.expect(A, v)
+        return (e(S["x"]).real, e(S["y"]).real, e(S["z"]).real, e(S["y"] @ S["y"]).real, e(S["z"] @ S["z"]).real,
+                e(S["y"] @ S["z"] + S["z"] @ S["y"]).real)
+
+    N = 6
+    Sz = sum(ed.site_op(ed.SZ, i, N) for i in range(N))
+    plus = np.ones(2 ** N, dtype=np.complex128) / np.sqrt(2 ** N)
+    szd = Sz.diagonal().real
+    states = [np.exp(-1j * t * szd ** 2) * plus for t in (0.05, 0.2, 0.45)]
+    rng = np.random.default_rng(11)
+    for _ in range(2):   # a random perturbation of the +x state: nonzero <S^y>, <S^z>
+        v = plus + 0.15 * (rng.normal(size=2 ** N) + 1j * rng.normal(size=2 ** N)) / np.sqrt(2 ** N)
+        states.append(v / np.linalg.norm(v))
+    for v in states:
+        sx, sy, sz, syy, szz, syz = moments(v, N)
+        got = T.tdvp_squeezing_xi2(N, sx, syy, szz, syz, sy=sy, sz=sz)
+        ref = xi2_dense(v, N)
+        assert abs(got - ref) <= 1e-6 * abs(ref) + 1e-12, (got, ref)
+
+
+def test_squeezing_xi2_rejects_bad_moments():
+    with pytest.raises(T.TdvpError):
+        T.tdvp_squeezing_xi2(10, 0.0, 1.0, 1.0, 0.0)
+    with pytest.raises(T.TdvpError):
+        T.tdvp_squeezing_xi2(0, 1.0, 1.0, 1.0, 0.0)
+    with pytest.raises(T.TdvpError):
+        T.tdvp_squeezing_xi2(4, 1.0, float("nan"), 1.0, 0.0)

@@ -272,27 +272,33 @@ def test_oat_squeezing_moments_on_device(env):
 
 
 def test_batched_instances_match_single_runs(env):
-    # several independent ladders of different sizes in one call (worker
-    # streams) give the same states as the same ladders run one by one
+    # several independent ladders of different sizes and couplings in one call
+    # (worker streams): each instance agrees with the oracle's run of that
+    # ladder, and with the same ladder stepped alone on the device
     T, ctx = env
-    from oracle import mps as M
+    from oracle import gse, mpo, mps as M, observables as O
     lats = [I.ladder(L, jl, jr, "snake") for (L, jl, jr) in ((4, 1.0, 0.6), (6, 0.8, 1.2), (5, 1.1, 0.9),
                                                              (3, 1.0, 1.0), (7, 0.7, 1.3))]
-    Hs, ops, batch, single = [], [], [], []
+    Hs, ops, batch, single, refs, cpu = [], [], [], [], [], []
     for j, lat in enumerate(lats):
         terms = I.heisenberg_terms(lat.couplings)
         lam = I.energy_scale(lat.couplings)
+        tau = -1j / lam
         Hs.append(T.tdvp_create_mpo(ctx, lat.n_sites, terms))
-        ops.append(T.tdvp_create_mpo(ctx, lat.n_sites, terms, 1.0, -1j * (-1j / lam)))
+        ops.append(T.tdvp_create_mpo(ctx, lat.n_sites, terms, 1.0, -1j * tau))
         psi0 = I.product_mps(lat.neel())
         batch.append(T.tdvp_mps_from_host(ctx, psi0))
         single.append(T.tdvp_mps_from_host(ctx, psi0))
+        refs.append(psi0)
+        cpu.append((mpo.build_mpo(lat.n_sites, terms), mpo.build_mpo(lat.n_sites, terms, 1.0, -1j * tau)))
     for _ in range(3):
         T.tdvp_expand_basis(ctx, batch, ops, 3, 1e-12, 1e-8, 32, "fp64")
         T.tdvp_sweep(ctx, batch, Hs, -0.2j, 1e-10, 32, 1e-12, 30, "fp64", True)
         for j in range(len(lats)):
             T.tdvp_expand_basis(ctx, [single[j]], [ops[j]], 3, 1e-12, 1e-8, 32, "fp64")
             T.tdvp_sweep(ctx, [single[j]], [Hs[j]], -0.2j, 1e-10, 32, 1e-12, 30, "fp64", True)
+            refs[j], _ = gse.gse_step(refs[j], cpu[j][0], cpu[j][1], -0.2j, 3, 1e-12, 1e-8, 1e-10, 32, 1e-12, 30,
+                                      True)
     mb = T.tdvp_measure(ctx, batch, Hs)
     ms = T.tdvp_measure(ctx, single, Hs)
     for j in range(len(lats)):
@@ -300,3 +306,35 @@ def test_batched_instances_match_single_runs(env):
         assert M.bond_dims(a) == M.bond_dims(b)
         assert 1 - M.fidelity(a, b) < 1e-12
         assert abs(mb[j]["energy"] - ms[j]["energy"]) < 1e-11
+        # against the oracle (imaginary time, 3 steps: fidelity loss < 1e-8 per unit time)
+        assert 1 - M.fidelity(a, refs[j]) < 1e-8 * 0.6 + 1e-12, j
+        assert abs(mb[j]["energy"] - O.energy(refs[j], cpu[j][0])) < 1e-9, j
+        assert np.abs(mb[j]["sz"] - O.sz(refs[j])).max() < 1e-7, j
+
+
+def test_expand_floor_reading_on_device(env):
+    # "SVD without truncation" (section I.A) reads as: directions with weight
+    # s^2 <= 1e-14 s_1^2 are not part of B.  On a state with two Schmidt
+    # values inside (1e-13, 1e-7) s_1 across one bond and a Krylov vector that
+    # does not carry them (the identity MPO: its density-matrix cut drops the
+    # same directions), psi changes by exactly their weight, as in the oracle.
+    import os, sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from states import mps_with_schmidt
+    T, ctx = env
+    from oracle import extension as X, krylov as K, mpo, mps as M
+    sch = [1.0, 0.6, 0.3, 2e-7, 2e-8, 5e-9]
+    pl = M.left_canonicalize(mps_with_schmidt(7, 3, sch, 3))
+    s = np.array(sch) / np.linalg.norm(sch)
+    dropped = float(np.sum(s[s ** 2 <= 1e-14 * s[0] ** 2] ** 2))
+    terms = I.heisenberg_terms(I.chain(7).couplings)
+    op = T.tdvp_create_mpo(ctx, 7, terms, 1.0, 0.0)
+    g = T.tdvp_mps_from_host(ctx, pl)
+    T.tdvp_expand_basis(ctx, [g], [op], 2, 0.0, 1e-8, 1 << 20, "fp64", skip_if_full=False)
+    out = T.tdvp_mps_to_host(g)
+    d = np.linalg.norm(M.to_dense(out) - M.to_dense(pl)) ** 2
+    assert abs(d - dropped) < 1e-2 * dropped, (d, dropped)
+    kv = K.krylov_vectors(pl, mpo.build_mpo(7, terms, 1.0, 0.0), 2, 0.0, 1 << 20)
+    ref, _ = X.basis_extension(pl, kv, 1e-8, 1 << 20)
+    assert M.bond_dims(out) == M.bond_dims(ref)
+    assert M.bond_dims(out)[2] == 4

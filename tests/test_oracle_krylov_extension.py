@@ -147,3 +147,55 @@ def test_extension_respects_cap():
     out, _ = X.basis_extension(psi, kv, 0.0, 5)
     assert max(M.bond_dims(out)) <= 5
     assert np.abs(M.to_dense(out) - M.to_dense(psi)).max() < 1e-13
+
+
+# The reading of "SVD without truncation" (section I.A): directions of the
+# centre whose weight s^2 is at most 1e-14 s_1^2 are not part of B.  Pinned
+# here on a state with prescribed Schmidt values across one bond, two of them
+# inside (1e-13, 1e-7) s_1 (weights 4e-16 and 2.5e-17 of s_1^2) and one just
+# above the floor (weight 4e-14): (a) when no Krylov vector carries the two
+# directions, the extension changes psi by exactly their weight (the bound
+# of the reading is attained, and nothing else moves); (b) when a Krylov
+# vector carries them, they return through rho_bar and psi is kept exactly.
+SCHMIDT = [1.0, 0.6, 0.3, 2e-7, 2e-8, 5e-9]
+
+
+def _schmidt_state(seed=3):
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from states import mps_with_schmidt
+    return M.left_canonicalize(mps_with_schmidt(7, 3, SCHMIDT, seed))
+
+
+def test_extension_floor_drops_exactly_the_subfloor_weight():
+    pl = _schmidt_state()
+    s = np.array(SCHMIDT) / np.linalg.norm(SCHMIDT)
+    dropped = float(np.sum(s[s ** 2 <= 1e-14 * s[0] ** 2] ** 2))
+    assert 1e-16 < dropped < 1e-15
+    out, _ = X.basis_extension(pl, [pl], 1e-8, 10 ** 6)
+    d = np.linalg.norm(M.to_dense(out) - M.to_dense(pl)) ** 2
+    assert abs(d - dropped) < 1e-3 * dropped, (d, dropped)
+    assert M.bond_dims(out)[2] == 4          # bond 3 keeps 4 of 6 directions (1e-7 s_1 is kept)
+    assert M.is_right_canonical(out, 1e-12)
+
+
+def test_extension_floor_directions_return_through_krylov_vectors():
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from states import mps_with_schmidt
+    pl = _schmidt_state()
+    # same isometries, flat Schmidt values: this Krylov vector carries the
+    # sub-floor directions with weight 1/3 of its norm
+    phi = M.left_canonicalize(mps_with_schmidt(7, 3, [1.0] * 6, 3))
+    out, st = X.basis_extension(pl, [phi], 1e-8, 10 ** 6)
+    d = np.linalg.norm(M.to_dense(out) - M.to_dense(pl)) ** 2
+    assert d < 1e-26, d
+    assert M.bond_dims(out)[2] == 6
+    # and the Krylov vector itself now lies in the extended bases
+    v = M.to_dense(phi)
+    T = out[6][:, :, 0]
+    for j in range(5, 2, -1):
+        T = np.tensordot(out[j], T, axes=(2, 0)).reshape(out[j].shape[0], -1)
+    q, _ = np.linalg.qr(T.conj().T)
+    V = v.reshape(-1, q.shape[0])
+    assert np.linalg.norm(V - (V @ q) @ q.conj().T) < 1e-12
