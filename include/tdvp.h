@@ -137,15 +137,36 @@ tdvp_status tdvp_mpo_to_host(tdvp_mpo mpo, double* out, size_t capacity);
 tdvp_status tdvp_build_mpo_host(int n_sites, const tdvp_term* terms, int n_terms, double c0_re,
                                 double c0_im, double c1_re, double c1_im, int* dims, double* out,
                                 size_t capacity);
+/* Host only: *conserves = 1 if the MPO of c0 * 1 + c1 * H conserves S^z,
+ * i.e. its channels carry charges qw with every nonzero W[al,be,s',s]
+ * satisfying qw(be) = qw(al) + q(s') - q(s) (q(up) = 1, q(down) = -1) and
+ * qw = 0 on both ends; charges (may be NULL, capacity in ints) then
+ * receives qw for the n_sites + 1 bonds. */
+tdvp_status tdvp_mpo_charges_host(int n_sites, const tdvp_term* terms, int n_terms, double c0_re,
+                                  double c0_im, double c1_re, double c1_im, int* conserves,
+                                  int* charges, size_t capacity);
 void tdvp_mpo_destroy(tdvp_mpo mpo);
 
 /* -------------------------------------------------------------------- MPS */
 
 /* Upload an MPS: bond_dims has n_sites + 1 entries (first and last 1);
  * tensors are the concatenated site tensors M_i[a,s,b] in complex128.
- * Errors: TDVP_ERR_ARG for inconsistent sizes or non-finite entries. */
+ * charges (may be NULL: no symmetry) gives a U(1) charge to every bond
+ * index, concatenated over the n_sites + 1 bonds (sum of bond_dims
+ * entries), ascending within each bond: twice the S^z of everything left
+ * of the bond, so M_i[a,s,b] may be nonzero only where q(b) = q(a) + 1 for
+ * s = up and q(a) - 1 for s = down.  Such a state conserves S^z under an
+ * MPO that does (a Hamiltonian of the benchmarks of section II), and every
+ * later call keeps it block-sparse: factorisations run charge by charge and
+ * new bonds carry the charges of their states.
+ * Errors: TDVP_ERR_ARG for inconsistent sizes, non-finite entries, charges
+ * not ascending within a bond, or a nonzero entry outside the blocks. */
 tdvp_status tdvp_mps_from_host(tdvp_ctx ctx, int n_sites, const int* bond_dims,
-                               const double* tensors, tdvp_mps* out);
+                               const double* tensors, const int* charges, tdvp_mps* out);
+/* *has_charges = 1 if the state carries U(1) charges; charges (may be NULL)
+ * receives them as in tdvp_mps_from_host, for the current bonds (capacity
+ * in ints). */
+tdvp_status tdvp_mps_charges(tdvp_mps mps, int* has_charges, int* charges, size_t capacity);
 /* Number of sites and current bond dims (n_sites + 1 entries). */
 tdvp_status tdvp_mps_bond_dims(tdvp_mps mps, int* n_sites, int* bond_dims, int capacity);
 /* Download the tensors (layout as in tdvp_mps_from_host); capacity in doubles. */
@@ -203,7 +224,8 @@ typedef struct {
  * rounding).  stats may be NULL, else n entries.
  * Errors: TDVP_ERR_ARG (n < 1, site counts differ from the MPO, k < 1,
  * chi_max < 1, eps < 0, unknown prec or apply_method, fewer than two sites
- * with TDVP_APPLY_FIT). */
+ * with TDVP_APPLY_FIT, the same state twice in psi[], a state with charges
+ * and an MPO that does not conserve S^z). */
 tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* op,
                               const tdvp_expand_params* params, tdvp_expand_stats* stats);
 
@@ -241,7 +263,8 @@ typedef struct {
  * Precondition: center at site 0, sites 1..N-1 right-canonical (the state
  * tdvp_expand_basis leaves).  Postcondition: the same gauge.
  * Errors: TDVP_ERR_ARG (bad parameters, MPO/MPS mismatch, the same state
- * twice in psi[]), TDVP_ERR_NOCONV (strict mode: some local Lanczos run
+ * twice in psi[], a state with charges and an MPO that does not conserve
+ * S^z), TDVP_ERR_NOCONV (strict mode: some local Lanczos run
  * reached krylov_max; the sweep was completed with those unconverged local
  * results, every state stays valid and stats are filled in),
  * TDVP_ERR_NUMERIC (non-finite values). */

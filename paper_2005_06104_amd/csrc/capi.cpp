@@ -355,6 +355,22 @@ tdvp_status tdvp_build_mpo_host(int n_sites, const tdvp_term* terms, int n_terms
   });
 }
 
+tdvp_status tdvp_mpo_charges_host(int n_sites, const tdvp_term* terms, int n_terms, double c0_re, double c0_im,
+                                  double c1_re, double c1_im, int* conserves, int* charges, size_t capacity) {
+  return guarded(nullptr, [&] {
+    ARG_CHECK(conserves != nullptr, "conserves must not be NULL");
+    HostMPO h = build_host_mpo(n_sites, terms, n_terms, zc(c0_re, c0_im), zc(c1_re, c1_im));
+    *conserves = h.u1 ? 1 : 0;
+    if (!h.u1 || !charges) return;
+    size_t need = 0;
+    for (int b = 0; b <= n_sites; ++b) need += h.w[b];
+    ARG_CHECK(capacity >= need, "capacity too small");
+    size_t off = 0;
+    for (auto& q : h.qw)
+      for (int v : q) charges[off++] = v;
+  });
+}
+
 tdvp_status tdvp_create_mpo(tdvp_ctx ctx, int n_sites, const tdvp_term* terms, int n_terms, double c0_re,
                             double c0_im, double c1_re, double c1_im, tdvp_mpo* out, int* w_out) {
   if (!ctx || !out) return TDVP_ERR_ARG;
@@ -394,7 +410,7 @@ void tdvp_mpo_destroy(tdvp_mpo mpo) {
 
 // ------------------------------------------------------------------ MPS
 tdvp_status tdvp_mps_from_host(tdvp_ctx ctx, int n_sites, const int* bond_dims, const double* tensors,
-                               tdvp_mps* out) {
+                               const int* charges, tdvp_mps* out) {
   if (!ctx || !out) return TDVP_ERR_ARG;
   return guarded(ctx, [&] {
     ARG_CHECK(n_sites >= 1, "n_sites must be >= 1");
@@ -404,8 +420,43 @@ tdvp_status tdvp_mps_from_host(tdvp_ctx ctx, int n_sites, const int* bond_dims, 
     for (int i = 0; i <= n_sites; ++i) ARG_CHECK(bond_dims[i] >= 1 && bond_dims[i] <= (1 << 16), "bad bond dimension");
     for (int i = 0; i < n_sites; ++i) total += (size_t)bond_dims[i] * 2 * bond_dims[i + 1];
     ARG_CHECK(all_finite(tensors, 2 * total), "non-finite tensor entry");
+    if (charges) {
+      // every bond ascending; entries outside q(b) = q(a) + q(s) exactly zero
+      std::vector<size_t> qoff(n_sites + 2, 0);
+      for (int b = 0; b <= n_sites; ++b) qoff[b + 1] = qoff[b] + bond_dims[b];
+      for (int b = 0; b <= n_sites; ++b)
+        for (size_t x = qoff[b] + 1; x < qoff[b + 1]; ++x)
+          ARG_CHECK(charges[x - 1] <= charges[x], "charges of a bond must ascend");
+      size_t off = 0;
+      for (int i = 0; i < n_sites; ++i) {
+        const int ml = bond_dims[i], mr = bond_dims[i + 1];
+        for (int a = 0; a < ml; ++a)
+          for (int sp = 0; sp < 2; ++sp)
+            for (int b = 0; b < mr; ++b) {
+              const size_t e = off + ((size_t)a * 2 + sp) * mr + b;
+              const bool allowed = charges[qoff[i + 1] + b] == charges[qoff[i] + a] + phys_charge(sp);
+              ARG_CHECK(allowed || (tensors[2 * e] == 0.0 && tensors[2 * e + 1] == 0.0),
+                        "tensor entry outside the charge blocks is not zero");
+            }
+        off += (size_t)ml * 2 * mr;
+      }
+    }
     bind(ctx);
-    *out = make_mps(ctx, n_sites, bond_dims, tensors).release();
+    *out = make_mps(ctx, n_sites, bond_dims, tensors, charges).release();
+  });
+}
+
+tdvp_status tdvp_mps_charges(tdvp_mps mps, int* has_charges, int* charges, size_t capacity) {
+  if (!mps || !has_charges) return TDVP_ERR_ARG;
+  return guarded(mps->ctx, [&] {
+    *has_charges = mps->u1() ? 1 : 0;
+    if (!mps->u1() || !charges) return;
+    size_t need = 0;
+    for (int b = 0; b <= mps->N; ++b) need += mps->m[b];
+    ARG_CHECK(capacity >= need, "capacity too small");
+    size_t off = 0;
+    for (int b = 0; b <= mps->N; ++b)
+      for (int v : mps->q[b]) charges[off++] = v;
   });
 }
 
@@ -453,6 +504,7 @@ tdvp_status tdvp_apply_mpo(tdvp_ctx ctx, tdvp_mps in, tdvp_mpo op, int method, d
   return guarded(ctx, [&] {
     ARG_CHECK(in && op, "NULL handle");
     ARG_CHECK(in->N == op->N(), "MPS and MPO site counts differ");
+    ARG_CHECK(!in->u1() || op->host.u1, "a state with charges needs an MPO that conserves S^z");
     ARG_CHECK(std::isfinite(eps) && eps >= 0, "eps must be >= 0");
     ARG_CHECK(chi_max >= 1, "chi_max must be >= 1");
     ARG_CHECK(method == TDVP_APPLY_DENMAT || method == TDVP_APPLY_FIT, "unknown method");
@@ -483,6 +535,7 @@ tdvp_status tdvp_expand_basis(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo
     for (int j = 0; j < n; ++j) {
       ARG_CHECK(psi[j] && op[j], "NULL handle");
       ARG_CHECK(psi[j]->N == op[j]->N(), "MPS and MPO site counts differ");
+      ARG_CHECK(!psi[j]->u1() || op[j]->host.u1, "a state with charges needs an MPO that conserves S^z");
       ARG_CHECK(p.apply_method != TDVP_APPLY_FIT || psi[j]->N >= 2, "the variational route needs at least two sites");
       if (!psi[j]->valid || !op[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
@@ -516,6 +569,7 @@ tdvp_status tdvp_sweep(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, co
     for (int j = 0; j < n; ++j) {
       ARG_CHECK(psi[j] && H[j], "NULL handle");
       ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
+      ARG_CHECK(!psi[j]->u1() || H[j]->host.u1, "a state with charges needs an MPO that conserves S^z");
       if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
     check_distinct(n, psi);
@@ -554,6 +608,7 @@ tdvp_status tdvp_sweep2(tdvp_ctx ctx, int n, tdvp_mps* psi, const tdvp_mpo* H, c
     for (int j = 0; j < n; ++j) {
       ARG_CHECK(psi[j] && H[j], "NULL handle");
       ARG_CHECK(psi[j]->N == H[j]->N(), "MPS and MPO site counts differ");
+      ARG_CHECK(!psi[j]->u1() || H[j]->host.u1, "a state with charges needs an MPO that conserves S^z");
       if (!psi[j]->valid || !H[j]->valid) TDVP_THROW(TDVP_ERR_STATE, "handle invalidated by an earlier failure");
     }
     check_distinct(n, psi);

@@ -281,6 +281,21 @@ void zcombine_dots(hipStream_t s, void* w, const void* V, long long ldv, int nv,
 // host[0 .. ncoef) = coeffs[0 .. ncoef) and host[host_norm_at] = |w|^2.
 void zscale_invnorm(hipStream_t s, void* w, const void* partial, int np, void* out, long long n,
                     void* host = nullptr, const void* coeffs = nullptr, int ncoef = 0, int host_norm_at = 0);
+// dst[i*ldd + j] = src[r(i)*lds + c(j)] for i < nr, j < nc, with r(i) = ridx[i]
+// (ridx null: r(i) = i) and c(j) likewise; complex128, index arrays on the device
+void zgather(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, const int* ridx, long long nr,
+             const int* cidx, long long nc);
+// dst[r(i)*ldd + c(j)] = src[i*lds + j] (other entries of dst untouched), complex128,
+// r and c as for zgather
+void zscatter(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, const int* ridx, long long nr,
+              const int* cidx, long long nc);
+// dst[i*ldd + cidx[j]] = src[i*lds + j] (other entries of dst untouched), complex128
+void zscatter_cols(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long nr,
+                   const int* cidx, long long nc);
+// 1 x 1 diagonal blocks of the n x n Hermitian H at indices idx[j]: diag[j] =
+// H[idx[j]][idx[j]] and rows[pos[j]][idx[j]] = 1 (their unit eigenvectors)
+void zunit_blocks(hipStream_t s, void* diag, const void* H, long long n, const int* idx, const int* pos, int cnt,
+                  void* rows);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
 // G = a G + b I (n x n complex128)
@@ -339,6 +354,30 @@ void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, s
 enum { EIGH_AUTO = 0, EIGH_TRIDIAG = 1, EIGH_HEEVD = 2, EIGH_TRIDIAG_LIB = 3 };
 void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows,
                     DBuf& work, int method = EIGH_AUTO);
+// eigh_rows_desc for a Hermitian H that is block diagonal under the index
+// charges q[0..n) (H[i][j] = 0 whenever q[i] != q[j]; the indices of one
+// charge need not be contiguous): each block is decomposed on its own, so
+// every eigenvector has a definite charge even where blocks share
+// eigenvalues.  lam is descending over all blocks (ties: lower charge
+// first), rows[j] the conjugated eigenvector (full length n, zero outside its
+// block) and qout[j] its charge.  q empty: eigh_rows_desc, qout cleared.
+void eigh_sectors(tdvp_ctx_s* ctx, const void* H, int n, const std::vector<int>& q, std::vector<double>& lam,
+                  void* rows, DBuf& work, std::vector<int>& qout);
+// Row-space basis of C (rows x cols) for C whose entry (i, j) vanishes unless
+// qrow[i] == qcol[j]: per charge, the thin SVD of the nonzero block; Vh
+// (min(rows, cols) rows of length cols) receives the right singular vectors
+// (zero outside their block) grouped by ascending charge, descending within
+// a charge, S their singular values and qout their charges.
+void svd_sectors(tdvp_ctx_s* ctx, const void* C, int rows, int cols, const std::vector<int>& qrow,
+                 const std::vector<int>& qcol, std::vector<double>& S, void* Vh, std::vector<int>& qout);
+// Exact factorisation of C (rows x cols) whose entry (i, j) vanishes unless
+// qrow[i] == qcol[j], block by block (Householder, nothing dropped): with
+// left = true, C = A R (QR), A rows x k, R k x cols; with left = false,
+// C = L B (LQ), L rows x k, B k x cols.  Per charge c the block has
+// k_c = min(rows of c, columns of c); the k = sum k_c new indices are grouped
+// by ascending charge, their charges go to qk.  X1/X2 receive A, R (or L, B).
+int factor_sectors(tdvp_ctx_s* ctx, bool left, const void* C, int rows, int cols, const std::vector<int>& qrow,
+                   const std::vector<int>& qcol, DBuf& X1, DBuf& X2, std::vector<int>& qk);
 // host: eigenvalues of the small symmetric tridiagonal matrix (diagonal d[n],
 // off-diagonal e[0..n-2]; e[n-1] is scratch) by implicit QL, returned in d
 // (unordered); each of the nr rows of Zr (nr x n, row-major) is multiplied by

@@ -386,11 +386,20 @@ std::unique_ptr<tdvp_mpo_s> make_mpo(tdvp_ctx_s* ctx, HostMPO&& host) {
   return m;
 }
 
-std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host) {
+std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host,
+                                     const int* charges) {
   auto p = std::make_unique<tdvp_mps_s>();
   p->ctx = ctx;
   p->N = N;
   p->m.assign(dims, dims + N + 1);
+  if (charges) {
+    p->q.resize(N + 1);
+    size_t off = 0;
+    for (int b = 0; b <= N; ++b) {
+      p->q[b].assign(charges + off, charges + off + dims[b]);
+      off += dims[b];
+    }
+  }
   size_t off = 0;
   for (int i = 0; i < N; ++i) {
     p->t.emplace_back(ctx);
@@ -409,12 +418,12 @@ namespace {
 struct Work {
   tdvp_ctx_s* ctx;
   kern::SplitWorkspaceScope gws;   // split-K scratch of the products issued below
-  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv;
+  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv, pidx, prow;
   Scalars sc;
   Lanczos lz;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
-        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), sc(c), lz(c) {}
+        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), sc(c), lz(c) {}
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {
     const size_t b = (size_t)16 * 2 * ml * mr * cb;
@@ -469,6 +478,53 @@ void ns_rows(Work& W, void* B, int n, int cols, int iters) {
   }
 }
 
+// rows[0..n) (each ncols complex128) permuted so that their charges q[0..n)
+// ascend (stable); lam[0..n) and q[0..n) follow.  The new bond a basis of
+// these rows spans then lists its charges in the order the states require.
+void sort_rows_by_charge(Work& W, void* rows, long long ncols, int n, std::vector<double>* lam, std::vector<int>& q) {
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return q[a] < q[b]; });
+  bool ident = true;
+  for (int j = 0; j < n; ++j) ident = ident && perm[j] == j;
+  if (!ident) {
+    W.pidx.ensure(sizeof(int) * std::max(n, 1));
+    upload(W.ctx, W.pidx.p, perm.data(), sizeof(int) * n);
+    W.prow.ensure((size_t)n * ncols * ZB);
+    kern::zgather(W.ctx->stream, W.prow.p, ncols, rows, ncols, W.pidx.as<int>(), n, nullptr, ncols);
+    HIP_CHECK(hipMemcpyAsync(rows, W.prow.p, (size_t)n * ncols * ZB, hipMemcpyDeviceToDevice, W.ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(W.ctx->stream));   // `perm` is pageable host memory
+  }
+  std::vector<int> q2(n);
+  std::vector<double> l2(n);
+  for (int j = 0; j < n; ++j) {
+    q2[j] = q[perm[j]];
+    if (lam) l2[j] = (*lam)[perm[j]];
+  }
+  for (int j = 0; j < n; ++j) {
+    q[j] = q2[j];
+    if (lam) (*lam)[j] = l2[j];
+  }
+  q.resize(n);
+}
+
+// charges of the fused index (x, s) (x major) and of (s, x) (s major) for
+// x with charges qx: q(x) + sign q(s)
+std::vector<int> fuse_xs(const std::vector<int>& qx, int sign) {
+  std::vector<int> out;
+  out.reserve(2 * qx.size());
+  for (int v : qx)
+    for (int s = 0; s < 2; ++s) out.push_back(v + sign * phys_charge(s));
+  return out;
+}
+std::vector<int> fuse_sx(const std::vector<int>& qx, int sign) {
+  std::vector<int> out;
+  out.reserve(2 * qx.size());
+  for (int s = 0; s < 2; ++s)
+    for (int v : qx) out.push_back(v + sign * phys_charge(s));
+  return out;
+}
+
 // 1/sqrt of the first n weights on the device
 const double* inv_sqrt_weights(Work& W, const std::vector<double>& lam, int n) {
   std::vector<double> f(n);
@@ -494,16 +550,40 @@ int trunc_count(const std::vector<double>& lam, double eps, int chi_max, double*
 }
 
 // Gauge move to the right: C (ml x 2 x mr) -> A (ml x 2 x k) and R (k x mr).
-int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& A, DBuf& R, double* disc) {
+// With charges: qc (mr entries) are the charges the columns of C carry as a
+// left bond (for a site tensor, those of its right bond); the new bond's
+// charges (ascending) go to *qk.  Every factorisation then respects the
+// blocks: the Cholesky-QR steps and Newton-Schulz keep zero blocks exactly
+// zero, and the Gram eigendecomposition runs charge by charge.
+int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& A, DBuf& R, double* disc,
+               const std::vector<int>* qa = nullptr, const std::vector<int>* qc = nullptr,
+               std::vector<int>* qk = nullptr) {
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int rows = 2 * ml, cols = mr, kk = std::min(rows, cols);
+  const bool sym = qc != nullptr;
+  // the exact moves keep the columns as the new bond: with charges only when
+  // they ascend and C has at least as many rows as columns
+  const bool keep_cols = !sym || (std::is_sorted(qc->begin(), qc->end()) && rows >= cols);
   if (eps == 0.0 && kk <= chi_max) {
-    A.ensure((size_t)rows * kk * ZB);
-    R.ensure((size_t)kk * cols * ZB);
-    if (!la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work))
+    if (keep_cols) {
+      A.ensure((size_t)rows * kk * ZB);
+      R.ensure((size_t)kk * cols * ZB);
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work)) {
+        if (sym) *qk = *qc;
+        return kk;
+      }
+    }
+    if (!sym) {
+      A.ensure((size_t)rows * kk * ZB);
+      R.ensure((size_t)kk * cols * ZB);
       la::qr_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, W.tau);
-    return kk;
+      return kk;
+    }
+    // rank-deficient (or not ordered by charge): Householder per charge
+    // block, which keeps every direction of the bond, weight or not (the
+    // extension's new directions carry none until the sweep evolves into them)
+    return la::factor_sectors(ctx, true, C, rows, cols, fuse_xs(*qa, 1), *qc, A, R, *qk);
   }
   // G = C^dagger C (cols x cols); rows of V^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)cols * cols * ZB);
@@ -512,18 +592,28 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // Nothing is cut when the smallest weight exceeds max(eps, floor) times
   // their sum (the cap does not bind: kk <= chi_max); a Cholesky factorisation
   // certifies it, and the exact factorisation is then the split.
-  if (kk == cols && kk <= chi_max) {
+  if (kk == cols && kk <= chi_max && keep_cols) {
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false,
                                              W.cinv.ensure((size_t)cols * cols * ZB), W.work, W.tmpA.p);
     if (F) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F)) return kk;
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F)) {
+        if (sym) *qk = *qc;
+        return kk;
+      }
     }
   }
   std::vector<double> lam;
-  la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
+  std::vector<int> qv;
+  if (sym) la::eigh_sectors(ctx, W.tmpA.p, cols, *qc, lam, W.tmpB.p, W.work2, qv);
+  else la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
+  const bool well_separated = lam[n - 1] > 1e-8 * lam[0];
+  if (sym) {
+    sort_rows_by_charge(W, W.tmpB.p, cols, n, &lam, qv);
+    *qk = qv;
+  }
   // A spans C V_n; R = A^dagger C.  When every kept weight is well above the
   // eigenvector accuracy (u lambda_1 / lambda_n << 1), C V_n S_n^-1 is
   // orthonormal up to rounding and Newton-Schulz polishes it; otherwise a QR
@@ -535,13 +625,17 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // (Newton-Schulz converges while the starting deviation is below ~1/2; for
   // small kept weights five steps and a check, with a QR when the check fails)
   kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
-  if (lam[n - 1] > 1e-8 * lam[0]) {
+  if (well_separated) {
     ns_cols(W, A.p, rows, n, 3);
   } else {
     ns_cols(W, A.p, rows, n, 5);
     if (!(la::orth_defect(ctx, A.p, rows, n, false, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
-      la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+      // with charges the Cholesky-QR steps keep the blocks (Householder
+      // reflections would mix them)
+      if (!sym) la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
+      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work))
+        TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, 0, C, cols, 0, 0.0, R.p, cols, 0, 1);
@@ -549,34 +643,62 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
 }
 
 // Gauge move to the left: C (ml x 2 x mr) -> L (ml x k) and B (k x 2 x mr).
-int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& L, DBuf& B, double* disc) {
+// With charges: qr (ml entries) are the charges the rows of C carry as a
+// right bond (for a site tensor, those of its left bond); the new bond's
+// charges (ascending) go to *qk.
+int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& L, DBuf& B, double* disc,
+                const std::vector<int>* qr = nullptr, const std::vector<int>* qb = nullptr,
+                std::vector<int>* qk = nullptr) {
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int rows = ml, cols = 2 * mr, kk = std::min(rows, cols);
+  const bool sym = qr != nullptr;
+  const bool keep_rows = !sym || (std::is_sorted(qr->begin(), qr->end()) && rows <= cols);
   if (eps == 0.0 && kk <= chi_max) {
-    L.ensure((size_t)rows * kk * ZB);
-    B.ensure((size_t)kk * cols * ZB);
-    if (!la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work))
+    if (keep_rows) {
+      L.ensure((size_t)rows * kk * ZB);
+      B.ensure((size_t)kk * cols * ZB);
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work)) {
+        if (sym) *qk = *qr;
+        return kk;
+      }
+    }
+    if (!sym) {
+      L.ensure((size_t)rows * kk * ZB);
+      B.ensure((size_t)kk * cols * ZB);
       la::lq_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, W.tau);
-    return kk;
+      return kk;
+    }
+    // as in split_left: LQ per charge block, every direction kept
+    return la::factor_sectors(ctx, false, C, rows, cols, *qr, fuse_sx(*qb, -1), L, B, *qk);
   }
   // G = C C^dagger (rows x rows); rows of U^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)rows * rows * ZB);
   W.tmpB.ensure((size_t)rows * rows * ZB);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, rows, 0, 1);
   // certified "nothing to cut" as in split_left
-  if (kk == rows && kk <= chi_max) {
+  if (kk == rows && kk <= chi_max && keep_rows) {
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true,
                                              W.cinv.ensure((size_t)rows * rows * ZB), W.work, W.tmpA.p);
     if (F) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F)) return kk;
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F)) {
+        if (sym) *qk = *qr;
+        return kk;
+      }
     }
   }
   std::vector<double> lam;
-  la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
+  std::vector<int> qv;
+  if (sym) la::eigh_sectors(ctx, W.tmpA.p, rows, *qr, lam, W.tmpB.p, W.work2, qv);
+  else la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
+  const bool well_separated = lam[n - 1] > 1e-8 * lam[0];
+  if (sym) {
+    sort_rows_by_charge(W, W.tmpB.p, rows, n, &lam, qv);
+    *qk = qv;
+  }
   // B spans the rows of U_n^dagger C; L = C B^dagger (Newton-Schulz on
   // S_n^-1 U_n^dagger C when the kept weights allow it, an LQ otherwise)
   W.tmpC.ensure((size_t)n * cols * ZB);
@@ -584,13 +706,15 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   L.ensure((size_t)rows * n * ZB);
   B.ensure((size_t)n * cols * ZB);
   kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
-  if (lam[n - 1] > 1e-8 * lam[0]) {
+  if (well_separated) {
     ns_rows(W, B.p, n, cols, 3);
   } else {
     ns_rows(W, B.p, n, cols, 5);
     if (!(la::orth_defect(ctx, B.p, n, cols, true, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
-      la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+      if (!sym) la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
+      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work))
+        TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, B.p, cols, 0, 0.0, L.p, n, 0, 1);
@@ -603,7 +727,10 @@ void left_canonicalize(Work& W, tdvp_mps_s& psi) {
   double disc = 0.0;
   for (int i = 0; i + 1 < psi.N; ++i) {
     const int ml = psi.m[i], mr = psi.m[i + 1];
-    const int k = split_left(W, psi.site(i), ml, mr, 0.0, 1 << 30, A, R, &disc);
+    std::vector<int> qk;
+    const int k = split_left(W, psi.site(i), ml, mr, 0.0, 1 << 30, A, R, &disc, psi.u1() ? &psi.q[i] : nullptr,
+                             psi.u1() ? &psi.q[i + 1] : nullptr, &qk);
+    if (psi.u1()) psi.q[i + 1] = qk;
     std::swap(psi.t[i], A);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, k, 2 * psi.m[i + 2], mr, R.p, mr, psi.site(i + 1), 2LL * psi.m[i + 2], nxt);
     std::swap(psi.t[i + 1], nxt);
@@ -617,7 +744,10 @@ void right_canonicalize(Work& W, tdvp_mps_s& psi) {
   double disc = 0.0;
   for (int i = psi.N - 1; i > 0; --i) {
     const int ml = psi.m[i], mr = psi.m[i + 1];
-    const int k = split_right(W, psi.site(i), ml, mr, 0.0, 1 << 30, Lm, B, &disc);
+    std::vector<int> qk;
+    const int k = split_right(W, psi.site(i), ml, mr, 0.0, 1 << 30, Lm, B, &disc, psi.u1() ? &psi.q[i] : nullptr,
+                              psi.u1() ? &psi.q[i + 1] : nullptr, &qk);
+    if (psi.u1()) psi.q[i] = qk;
     std::swap(psi.t[i], B);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], k, ml, psi.site(i - 1), ml, Lm.p, k, prv);
     std::swap(psi.t[i - 1], prv);
@@ -721,9 +851,12 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
   for (int i = 0; i + 1 < N; ++i) {
     evolve_site(i, half);
     const int ml = psi.m[i], mr = psi.m[i + 1];
-    const int k = split_left(W, psi.site(i), ml, mr, p.eps, cap, A, Rm, &st.discarded);
+    std::vector<int> qk;
+    const int k = split_left(W, psi.site(i), ml, mr, p.eps, cap, A, Rm, &st.discarded,
+                             psi.u1() ? &psi.q[i] : nullptr, psi.u1() ? &psi.q[i + 1] : nullptr, &qk);
     std::swap(psi.t[i], A);
     psi.m[i + 1] = k;  // site i is now ml x 2 x k; Rm is k x mr
+    if (psi.u1()) psi.q[i + 1] = qk;
     build_L(i);
     evolve_bond(i + 1, Rm.p, k, mr, -half);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, k, 2 * psi.m[i + 2], mr, Rm.p, mr, psi.site(i + 1), 2LL * psi.m[i + 2], nxt);
@@ -734,9 +867,12 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
   for (int i = N - 1; i >= 1; --i) {
     if (i < N - 1) evolve_site(i, half);
     const int ml = psi.m[i], mr = psi.m[i + 1];
-    const int k = split_right(W, psi.site(i), ml, mr, p.eps, cap, Rm, A, &st.discarded);
+    std::vector<int> qk;
+    const int k = split_right(W, psi.site(i), ml, mr, p.eps, cap, Rm, A, &st.discarded,
+                              psi.u1() ? &psi.q[i] : nullptr, psi.u1() ? &psi.q[i + 1] : nullptr, &qk);
     std::swap(psi.t[i], A);
     psi.m[i] = k;  // site i is now k x 2 x mr; Rm (the L factor) is ml x k
+    if (psi.u1()) psi.q[i] = qk;
     build_R(i);
     evolve_bond(i, Rm.p, ml, k, -half);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], k, ml, psi.site(i - 1), ml, Rm.p, k, nxt);
@@ -866,20 +1002,30 @@ void sweep2_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const td
     run_lanczos(C, n, step, ap, flops, false, &st.n_keff);
   };
   // split Th (pair i) with the center moving right: site i = A, site i+1 = S V^dagger
+  // with charges: the columns (s', b) of the pair carry q(b) - q(s') as a
+  // left bond, the rows (a, s) carry q(a) + q(s) as a right bond
   auto split_to_right = [&](int i) {
     const int ml = psi.m[i], mr = psi.m[i + 2];
-    const int k = split_left(W, Th.as<double>(), ml, 2 * mr, p.eps, p.chi_max, A, Cn, &st.discarded);
+    std::vector<int> qc, qk;
+    if (psi.u1()) qc = fuse_sx(psi.q[i + 2], -1);
+    const int k = split_left(W, Th.as<double>(), ml, 2 * mr, p.eps, p.chi_max, A, Cn, &st.discarded,
+                             psi.u1() ? &psi.q[i] : nullptr, psi.u1() ? &qc : nullptr, &qk);
     std::swap(psi.t[i], A);
     std::swap(psi.t[i + 1], Cn);
     psi.m[i + 1] = k;
+    if (psi.u1()) psi.q[i + 1] = qk;
   };
   // ... with the center moving left: site i = U S, site i+1 = V^dagger
   auto split_to_left = [&](int i) {
     const int ml = psi.m[i], mr = psi.m[i + 2];
-    const int k = split_right(W, Th.as<double>(), 2 * ml, mr, p.eps, p.chi_max, A, Cn, &st.discarded);
+    std::vector<int> qr, qk;
+    if (psi.u1()) qr = fuse_xs(psi.q[i], 1);
+    const int k = split_right(W, Th.as<double>(), 2 * ml, mr, p.eps, p.chi_max, A, Cn, &st.discarded,
+                              psi.u1() ? &qr : nullptr, psi.u1() ? &psi.q[i + 2] : nullptr, &qk);
     std::swap(psi.t[i], A);
     std::swap(psi.t[i + 1], Cn);
     psi.m[i + 1] = k;
+    if (psi.u1()) psi.q[i + 1] = qk;
   };
 
   for (int i = N - 1; i >= 2; --i) build_R(i);
@@ -999,6 +1145,15 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
   out.m.assign(N + 1, 1);
   out.t.clear();
   for (int i = 0; i < N; ++i) out.t.emplace_back(ctx);
+  // with charges: the output keeps the input's total charge; the bond k of
+  // X carries out.q[i], and rho is block diagonal in q(k) + q(t)
+  const bool sym = in.u1();
+  out.q.clear();
+  if (sym) {
+    out.q.assign(N + 1, std::vector<int>());
+    out.q[0] = in.q[0];
+    out.q[N] = in.q[N];
+  }
   DBuf X(ctx), Y(ctx), G(ctx), rho(ctx), rho64(ctx), rows(ctx), rowsT(ctx);
   set_one(ctx, X, cb);
   int kd = 1;
@@ -1040,11 +1195,17 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
       r64 = rho64.p;
     }
     rows.ensure((size_t)d2 * d2 * ZB);
-    la::eigh_rows_desc(ctx, r64, d2, lam, rows.p, W.work);
+    std::vector<int> qv;
+    if (sym) la::eigh_sectors(ctx, r64, d2, fuse_xs(out.q[i], 1), lam, rows.p, W.work, qv);
+    else la::eigh_rows_desc(ctx, r64, d2, lam, rows.p, W.work);
     double tr = 0.0;
     for (double v : lam) tr += v;
     const int n = keep_count(lam, eps, tr, chi_max, 1);
     for (int j = n; j < d2; ++j) disc += std::max(0.0, lam[j]);
+    if (sym) {
+      sort_rows_by_charge(W, rows.p, d2, n, &lam, qv);
+      out.q[i + 1] = qv;
+    }
     // A_i[(k,t),n] = v_n  (conjugate transpose of the first n rows)
     out.t[i].ensure((size_t)d2 * n * ZB);
     kern::zconjtrans(s, out.t[i].p, n, rows.p, d2, d2, n);
@@ -1147,6 +1308,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   out.ctx = ctx;
   out.N = N;
   out.m = in.m;
+  out.q = in.q;
   out.t.clear();
   for (int i = 0; i < N; ++i) {
     out.t.emplace_back(ctx);
@@ -1154,6 +1316,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
     HIP_CHECK(hipMemcpyAsync(out.t[i].p, in.site(i), (size_t)in.elems(i) * ZB, hipMemcpyDeviceToDevice, s));
   }
   right_canonicalize(W, out);
+  const bool sym = out.u1();
   std::vector<DBuf> Ls, Rs;
   for (int i = 0; i <= N; ++i) {
     Ls.emplace_back(ctx);
@@ -1184,10 +1347,14 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
       for (int i = 0; i + 1 < N; ++i) {
         local(i);
         const int mlo = out.m[i], mro = out.m[i + 2];
-        const int k = split_left(W, Th.as<double>(), mlo, 2 * mro, eps, chi_max, X, Y, &disc);
+        std::vector<int> qc, qk;
+        if (sym) qc = fuse_sx(out.q[i + 2], -1);
+        const int k = split_left(W, Th.as<double>(), mlo, 2 * mro, eps, chi_max, X, Y, &disc,
+                                 sym ? &out.q[i] : nullptr, sym ? &qc : nullptr, &qk);
         std::swap(out.t[i], X);
         std::swap(out.t[i + 1], Y);
         out.m[i + 1] = k;
+        if (sym) out.q[i + 1] = qk;
         Ls[i + 1].ensure((size_t)k * op.w(i + 1) * in.m[i + 1] * ZB);
         fit_env_left(ctx, op.tab[i], mlo, in.m[i], op.w(i), op.w(i + 1), k, in.m[i + 1], Ls[i].p, out.site(i),
                      in.site(i), Ls[i + 1].p, f1, f2);
@@ -1196,10 +1363,14 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
       for (int i = N - 2; i >= 0; --i) {
         local(i);
         const int mlo = out.m[i], mro = out.m[i + 2];
-        const int k = split_right(W, Th.as<double>(), 2 * mlo, mro, eps, chi_max, X, Y, &disc);
+        std::vector<int> qr, qk;
+        if (sym) qr = fuse_xs(out.q[i], 1);
+        const int k = split_right(W, Th.as<double>(), 2 * mlo, mro, eps, chi_max, X, Y, &disc, sym ? &qr : nullptr,
+                                  sym ? &out.q[i + 2] : nullptr, &qk);
         std::swap(out.t[i], X);
         std::swap(out.t[i + 1], Y);
         out.m[i + 1] = k;
+        if (sym) out.q[i + 1] = qk;
         Rs[i + 1].ensure((size_t)op.w(i + 1) * in.m[i + 1] * k * ZB);
         fit_env_right(ctx, op.tab[i + 1], k, in.m[i + 1], op.w(i + 1), op.w(i + 2), mro, in.m[i + 2], Rs[i + 2].p,
                       out.site(i + 1), in.site(i + 1), Rs[i + 1].p, f1, f2);
@@ -1215,15 +1386,23 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
 }
 
 // ------------------------------------------------------ basis extension
+// With charges: the rows of C (bond i) carry psi.q[i]; a column (s, b)
+// carries q(b) - q(s) as a left bond; B, B_bar and rho_bar are computed
+// charge by charge, and B' = [B; B_bar] is ordered by charge (stable: B's
+// rows first within a charge) so that the new bond lists its charges in
+// ascending order.
 void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps_M, int chi_max, int* n_added) {
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int N = psi.N;
+  const bool sym = psi.u1();
   DBuf Vh(ctx), Bp(ctx), Xs(ctx), P(ctx), rhob(ctx), rows(ctx), Pb(ctx), Mc(ctx), nxt(ctx), Mt(ctx);
   std::vector<double> S, lam;
   for (int i = N - 1; i >= 1; --i) {
     const int ml = psi.m[i], mr = psi.m[i + 1], D = 2 * mr;
     const void* C = psi.site(i);
+    std::vector<int> qD, qB;   // charges of the columns (s, b) and of the rows of B
+    if (sym) qD = fuse_sx(psi.q[i + 1], -1);
     // B: orthonormal rows spanning the row space of C ("SVD without
     // truncation"); directions whose weight is at round-off level
     // (s^2 <= 1e-14 s_1^2) are not part of it.  The eigenvalues of C C^dagger
@@ -1245,10 +1424,17 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       if (F) {
         W.tmpC.ensure((size_t)ml * ml * ZB);
         done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F);
-        if (done) r = ml;
+        if (done) {
+          r = ml;
+          if (sym) qB = psi.q[i];
+        }
       }
     }
-    if (!done) la::eigh_rows_desc(ctx, W.tmpA.p, ml, S, W.tmpB.p, W.work2);
+    std::vector<int> qv;
+    if (!done) {
+      if (sym) la::eigh_sectors(ctx, W.tmpA.p, ml, psi.q[i], S, W.tmpB.p, W.work2, qv);
+      else la::eigh_rows_desc(ctx, W.tmpA.p, ml, S, W.tmpB.p, W.work2);
+    }
     if (done) {
       // B from the certified LQ factorisation
     } else if (ml <= D && !S.empty() && S[0] > 0.0 && S[ml - 1] > 1e-10 * S[0]) {
@@ -1258,16 +1444,42 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, ml, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
       kern::zscale_rows(s, Vh.p, D, W.tmpC.p, D, ml, D, inv_sqrt_weights(W, S, ml));
       ns_rows(W, Vh.p, ml, D, 3);
-    } else {
+      if (sym) {
+        sort_rows_by_charge(W, Vh.p, D, ml, nullptr, qv);
+        qB = qv;
+      }
+    } else if (!sym) {
       la::svd_rowmajor(ctx, C, ml, D, nullptr, S, Vh.p, W.work, W.work2);
       if (!S.empty() && S[0] > 0.0)
         for (double v : S) r += (v * v > 1e-14 * S[0] * S[0]) ? 1 : 0;
+    } else {
+      // per charge; the rows above the floor (relative to the largest
+      // singular value of all charges) are gathered in charge order
+      la::svd_sectors(ctx, C, ml, D, psi.q[i], qD, S, Vh.p, qv);
+      double smax = 0.0;
+      for (double v : S) smax = std::max(smax, v);
+      std::vector<int> keep;
+      for (int j = 0; j < (int)S.size(); ++j)
+        if (smax > 0.0 && S[j] * S[j] > 1e-14 * smax * smax) {
+          keep.push_back(j);
+          qB.push_back(qv[j]);
+        }
+      r = (int)keep.size();
+      if (r > 0) {
+        W.pidx.ensure(sizeof(int) * r);
+        upload(ctx, W.pidx.p, keep.data(), sizeof(int) * r);
+        W.prow.ensure((size_t)r * D * ZB);
+        kern::zgather(s, W.prow.p, D, Vh.p, D, W.pidx.as<int>(), r, nullptr, D);
+        HIP_CHECK(hipMemcpyAsync(Vh.p, W.prow.p, (size_t)r * D * ZB, hipMemcpyDeviceToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));   // `keep` is pageable host memory
+      }
     }
     const int cap = std::min(chi_max - r, D - r);
     // B' rows: B (r x D) then B_bar
     Bp.ensure((size_t)D * D * ZB);  // r + n <= D rows
     kern::copy2d(s, Bp.p, D, Vh.p, D, r, D, ZB);
     int n = 0;
+    std::vector<int> qbar;
     if (cap > 0 && !kv.empty()) {
       // projected Krylov centers, stacked: X_l = Ct_l - (Ct_l B^dagger) B
       int rows_tot = 0;
@@ -1291,7 +1503,8 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       rhob.ensure((size_t)D * D * ZB);
       kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, D, D, rows_tot, 1.0, Xs.p, D, 0, Xs.p, D, 0, 0.0, rhob.p, D, 0, 1);
       rows.ensure((size_t)D * D * ZB);
-      la::eigh_rows_desc(ctx, rhob.p, D, lam, rows.p, W.work);
+      if (sym) la::eigh_sectors(ctx, rhob.p, D, qD, lam, rows.p, W.work, qbar);
+      else la::eigh_rows_desc(ctx, rhob.p, D, lam, rows.p, W.work);
       n = keep_count(lam, eps_M, tr_ref, cap, 0);
       int nz = 0;
       for (double v : lam) nz += (v > 1e-14 * std::max(tr_ref, 1e-300)) ? 1 : 0;
@@ -1310,6 +1523,12 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       }
     }
     const int mnew = r + n;
+    if (sym) {
+      std::vector<int> qall(qB.begin(), qB.begin() + r);
+      qall.insert(qall.end(), qbar.begin(), qbar.begin() + n);
+      sort_rows_by_charge(W, Bp.p, D, mnew, nullptr, qall);
+      psi.q[i] = qall;
+    }
     // center moves: C_{i-1} = A_{i-1} (C_i B'^dagger), same for every Krylov vector
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_C, ml, mnew, D, C, D, Bp.p, D, Mc);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], mnew, ml, psi.site(i - 1), ml, Mc.p, mnew, nxt);
@@ -1419,6 +1638,7 @@ void run_apply_mpo(tdvp_ctx_s* ctx, const tdvp_mps_s& in, const tdvp_mpo_s& op, 
     lc.ctx = ctx;
     lc.N = in.N;
     lc.m = in.m;
+    lc.q = in.q;
     for (int i = 0; i < in.N; ++i) {
       lc.t.emplace_back(ctx);
       lc.t[i].ensure((size_t)in.elems(i) * ZB);

@@ -21,18 +21,27 @@ struct tdvp_mpo_s {
   int w(int b) const { return host.w[b]; }
 };
 
+// U(1) charges (twice the total S^z of everything left of a bond, so up = +1
+// and down = -1 per site): M[a,s,b] may be nonzero only where
+// q(b) = q(a) + q(s).  Every bond of a state that carries charges lists them
+// in ascending order, so each charge's indices are contiguous.
+inline int phys_charge(int s) { return s == 0 ? 1 : -1; }
+
 struct tdvp_mps_s {
   tdvp_ctx_s* ctx = nullptr;
   int N = 0;
   std::vector<int> m;            // N + 1 bond dims; site i is m[i] x 2 x m[i+1]
   std::vector<DBuf> t;           // complex128 site tensors
+  std::vector<std::vector<int>> q;   // empty: no charges; else N + 1 bonds of m[b] charges
   bool valid = true;
+  bool u1() const { return !q.empty(); }
   long long elems(int i) const { return (long long)m[i] * 2 * m[i + 1]; }
   double* site(int i) const { return t[i].as<double>(); }
 };
 
 std::unique_ptr<tdvp_mpo_s> make_mpo(tdvp_ctx_s* ctx, HostMPO&& host);
-std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host);
+std::unique_ptr<tdvp_mps_s> make_mps(tdvp_ctx_s* ctx, int N, const int* dims, const double* host,
+                                     const int* charges = nullptr);
 void run_apply_mpo(tdvp_ctx_s* ctx, const tdvp_mps_s& in, const tdvp_mpo_s& op, int method, double eps, int chi_max,
                    int passes, tdvp_mps_s& out, double* discarded);
 

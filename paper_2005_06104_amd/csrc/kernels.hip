@@ -912,6 +912,39 @@ __global__ void zshift_diag_kernel(double2* __restrict__ G, long long n, double 
   G[idx] = v;
 }
 
+// dst[i*ldd + j] = src[r(i)*lds + c(j)], r(i) = ridx ? ridx[i] : i, c likewise
+__global__ void zgather_kernel(double2* __restrict__ dst, long long ldd, const double2* __restrict__ src,
+                               long long lds, const int* __restrict__ ridx, long long nr,
+                               const int* __restrict__ cidx, long long nc) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nr * nc) return;
+  const long long i = idx / nc, j = idx % nc;
+  const long long r = ridx ? ridx[i] : i, c = cidx ? cidx[j] : j;
+  dst[i * ldd + j] = src[r * lds + c];
+}
+
+// dst[r(i)*ldd + c(j)] = src[i*lds + j], r(i) = ridx ? ridx[i] : i, c likewise
+__global__ void zscatter_kernel(double2* __restrict__ dst, long long ldd, const double2* __restrict__ src,
+                                long long lds, const int* __restrict__ ridx, long long nr,
+                                const int* __restrict__ cidx, long long nc) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nr * nc) return;
+  const long long i = idx / nc, j = idx % nc;
+  const long long r = ridx ? ridx[i] : i, c = cidx ? cidx[j] : j;
+  dst[r * ldd + c] = src[i * lds + j];
+}
+
+// dst[j] = H[idx[j]*n + idx[j]]; rows[pos[j]*n + idx[j]] = 1 (unit eigenvector of a 1 x 1 block)
+__global__ void zunit_blocks_kernel(double2* __restrict__ dst, const double2* __restrict__ H, long long n,
+                                    const int* __restrict__ idx, const int* __restrict__ pos, int cnt,
+                                    double2* __restrict__ rows) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const long long i = idx[j];
+  dst[j] = H[i * n + i];
+  rows[(long long)pos[j] * n + i] = make_double2(1.0, 0.0);
+}
+
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -1165,6 +1198,35 @@ void zscale_cols(hipStream_t s, void* dst, long long ldd, const void* src, long 
   if (rows <= 0 || cols <= 0) return;
   hipLaunchKernelGGL(zscale_rc_kernel, dim3(nblk(rows * cols)), dim3(256), 0, s, static_cast<double2*>(dst), ldd,
                      static_cast<const double2*>(src), lds, rows, cols, f, 1);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zgather(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, const int* ridx, long long nr,
+             const int* cidx, long long nc) {
+  if (nr <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(zgather_kernel, dim3(nblk(nr * nc)), dim3(256), 0, s, static_cast<double2*>(dst), ldd,
+                     static_cast<const double2*>(src), lds, ridx, nr, cidx, nc);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscatter(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, const int* ridx, long long nr,
+              const int* cidx, long long nc) {
+  if (nr <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(zscatter_kernel, dim3(nblk(nr * nc)), dim3(256), 0, s, static_cast<double2*>(dst), ldd,
+                     static_cast<const double2*>(src), lds, ridx, nr, cidx, nc);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zscatter_cols(hipStream_t s, void* dst, long long ldd, const void* src, long long lds, long long nr,
+                   const int* cidx, long long nc) {
+  zscatter(s, dst, ldd, src, lds, nullptr, nr, cidx, nc);
+}
+
+void zunit_blocks(hipStream_t s, void* diag, const void* H, long long n, const int* idx, const int* pos, int cnt,
+                  void* rows) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(zunit_blocks_kernel, dim3(nblk(cnt)), dim3(256), 0, s, static_cast<double2*>(diag),
+                     static_cast<const double2*>(H), n, idx, pos, cnt, static_cast<double2*>(rows));
   HIP_CHECK(hipGetLastError());
 }
 

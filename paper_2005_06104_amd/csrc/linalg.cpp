@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <numeric>
 
 #include "common.h"
 
@@ -61,6 +63,30 @@ void lq_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, vo
   kern::ztri(ctx->stream, L, k, X, cols, rows, k, 1);
   blas_check(rocsolver_zungqr(ctx->blas, cols, k, k, X, cols, t), "zungqr");
   kern::copy2d(ctx->stream, Q, cols, X, cols, k, cols, 16);
+}
+
+// qr_rowmajor for rows >= cols with the whole orthonormal factor: Af (rows x
+// rows), its first cols columns are qr_rowmajor's A, the rest an
+// orthonormal completion; R (cols x cols).
+void qr_rowmajor_full(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* Af, void* R, DBuf& tau) {
+  rz* Y = static_cast<rz*>(Af);   // col-major rows x rows, lda = rows
+  rz* t = static_cast<rz*>(tau.ensure(sizeof(rz) * (size_t)std::max(cols, 1)));
+  kern::copy2d(ctx->stream, Y, rows, C, cols, rows, cols, 16);
+  blas_check(rocsolver_zgelqf(ctx->blas, cols, rows, Y, rows, t), "zgelqf");
+  kern::ztri(ctx->stream, R, cols, Y, rows, cols, cols, 0);
+  blas_check(rocsolver_zunglq(ctx->blas, rows, rows, cols, Y, rows, t), "zunglq");
+}
+
+// lq_rowmajor for rows <= cols with the whole orthonormal factor: Bf (cols x
+// cols), its first rows rows are lq_rowmajor's Q, the rest an orthonormal
+// completion; L (rows x rows).
+void lq_rowmajor_full(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* Bf, DBuf& tau) {
+  rz* Y = static_cast<rz*>(Bf);   // col-major cols x cols, lda = cols
+  rz* t = static_cast<rz*>(tau.ensure(sizeof(rz) * (size_t)std::max(rows, 1)));
+  kern::copy2d(ctx->stream, Y, cols, C, cols, rows, cols, 16);
+  blas_check(rocsolver_zgeqrf(ctx->blas, cols, rows, Y, cols, t), "zgeqrf");
+  kern::ztri(ctx->stream, L, rows, Y, cols, rows, rows, 1);
+  blas_check(rocsolver_zungqr(ctx->blas, cols, cols, rows, Y, cols, t), "zungqr");
 }
 
 double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth_rows, DBuf& work) {
@@ -498,6 +524,253 @@ void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& 
   if (method == EIGH_TRIDIAG || method == EIGH_TRIDIAG_LIB)
     TDVP_THROW(TDVP_ERR_NUMERIC, "cooperative tridiagonal eigensolver not applicable");
   eigh_rows_desc_heevd(ctx, H, n, lam, rows, work);
+}
+
+namespace {
+
+// index lists of each charge, in ascending charge order
+struct Sectors {
+  std::vector<int> charge, off, idx;   // sector c holds idx[off[c] .. off[c+1])
+};
+
+Sectors group_by_charge(const std::vector<int>& q) {
+  std::map<int, std::vector<int>> m;
+  for (int i = 0; i < (int)q.size(); ++i) m[q[i]].push_back(i);
+  Sectors s;
+  for (auto& kv : m) {
+    s.charge.push_back(kv.first);
+    s.off.push_back((int)s.idx.size());
+    s.idx.insert(s.idx.end(), kv.second.begin(), kv.second.end());
+  }
+  s.off.push_back((int)s.idx.size());
+  return s;
+}
+
+// host ints to the device (waits: `v` may be temporary)
+int* upload_ints(tdvp_ctx_s* ctx, DBuf& buf, const std::vector<int>& v) {
+  buf.ensure(sizeof(int) * std::max<size_t>(1, v.size()));
+  if (!v.empty())
+    HIP_CHECK(hipMemcpyAsync(buf.p, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  return buf.as<int>();
+}
+
+}  // namespace
+
+void eigh_sectors(tdvp_ctx_s* ctx, const void* H, int n, const std::vector<int>& q, std::vector<double>& lam,
+                  void* rows, DBuf& work, std::vector<int>& qout) {
+  if (q.empty()) {
+    eigh_rows_desc(ctx, H, n, lam, rows, work);
+    qout.clear();
+    return;
+  }
+  if ((int)q.size() != n) TDVP_THROW(TDVP_ERR_ARG, "eigh_sectors: one charge per index needed");
+  hipStream_t s = ctx->stream;
+  const Sectors sc = group_by_charge(q);
+  const int ns = (int)sc.charge.size();
+  int nmax = 1;
+  std::vector<int> unit_idx, unit_pos;    // 1 x 1 blocks
+  for (int c = 0; c < ns; ++c) {
+    const int nb = sc.off[c + 1] - sc.off[c];
+    nmax = std::max(nmax, nb);
+    if (nb == 1) {
+      unit_idx.push_back(sc.idx[sc.off[c]]);
+      unit_pos.push_back(sc.off[c]);
+    }
+  }
+  // one upload: the index lists, then the 1 x 1 blocks' indices and positions
+  std::vector<int> ints(sc.idx);
+  ints.insert(ints.end(), unit_idx.begin(), unit_idx.end());
+  ints.insert(ints.end(), unit_pos.begin(), unit_pos.end());
+  DBuf dints(ctx), blk(ctx), rb(ctx), sec(ctx), diag(ctx), w2(ctx);
+  const int* didx = upload_ints(ctx, dints, ints);
+  const int nu = (int)unit_idx.size();
+  // eigenvector rows in sector order (each of full length n)
+  sec.ensure(sizeof(zc) * (size_t)n * n);
+  kern::zfill(s, sec.p, zc(0.0, 0.0), (long long)n * n, 16);
+  blk.ensure(sizeof(zc) * (size_t)nmax * nmax);
+  rb.ensure(sizeof(zc) * (size_t)nmax * nmax);
+  std::vector<double> lam_sec(n, 0.0), lb;
+  for (int c = 0; c < ns; ++c) {
+    const int o = sc.off[c], nb = sc.off[c + 1] - o;
+    if (nb < 2) continue;
+    kern::zgather(s, blk.p, nb, H, n, didx + o, nb, didx + o, nb);
+    eigh_rows_desc(ctx, blk.p, nb, lb, rb.p, work);
+    kern::zscatter_cols(s, static_cast<char*>(sec.p) + sizeof(zc) * (size_t)o * n, n, rb.p, nb, nb, didx + o, nb);
+    for (int j = 0; j < nb; ++j) lam_sec[o + j] = lb[j];
+  }
+  if (nu > 0) {
+    diag.ensure(sizeof(zc) * nu);
+    kern::zunit_blocks(s, diag.p, H, n, didx + n, didx + n + nu, nu, sec.p);
+    std::vector<zc> d(nu);
+    HIP_CHECK(hipMemcpyAsync(d.data(), diag.p, sizeof(zc) * nu, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    for (int j = 0; j < nu; ++j) lam_sec[unit_pos[j]] = d[j].real();
+  }
+  // global order: descending eigenvalue, then ascending charge, then position
+  std::vector<int> sec_of(n);
+  for (int c = 0; c < ns; ++c)
+    for (int j = sc.off[c]; j < sc.off[c + 1]; ++j) sec_of[j] = c;
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+    if (lam_sec[a] != lam_sec[b]) return lam_sec[a] > lam_sec[b];
+    return sec_of[a] < sec_of[b];
+  });
+  const int* dperm = upload_ints(ctx, w2, perm);
+  kern::zgather(s, rows, n, sec.p, n, dperm, n, nullptr, n);
+  lam.resize(n);
+  qout.resize(n);
+  for (int j = 0; j < n; ++j) {
+    lam[j] = lam_sec[perm[j]];
+    qout[j] = sc.charge[sec_of[perm[j]]];
+  }
+  HIP_CHECK(hipStreamSynchronize(s));   // the local buffers die here
+}
+
+void svd_sectors(tdvp_ctx_s* ctx, const void* C, int rows, int cols, const std::vector<int>& qrow,
+                 const std::vector<int>& qcol, std::vector<double>& S, void* Vh, std::vector<int>& qout) {
+  if ((int)qrow.size() != rows || (int)qcol.size() != cols) TDVP_THROW(TDVP_ERR_ARG, "svd_sectors: bad charges");
+  hipStream_t s = ctx->stream;
+  const Sectors sr = group_by_charge(qrow), scl = group_by_charge(qcol);
+  std::map<int, int> col_sec;
+  for (int c = 0; c < (int)scl.charge.size(); ++c) col_sec[scl.charge[c]] = c;
+  std::vector<int> ints(sr.idx);
+  ints.insert(ints.end(), scl.idx.begin(), scl.idx.end());
+  DBuf dints(ctx), blk(ctx), vb(ctx), w1(ctx), w2(ctx);
+  const int* dr = upload_ints(ctx, dints, ints);
+  const int* dc = dr + rows;
+  const int k = std::min(rows, cols);
+  kern::zfill(s, Vh, zc(0.0, 0.0), (long long)k * cols, 16);
+  S.clear();
+  qout.clear();
+  int out = 0;
+  std::vector<double> sb;
+  for (int c = 0; c < (int)sr.charge.size(); ++c) {
+    auto it = col_sec.find(sr.charge[c]);
+    if (it == col_sec.end()) continue;     // rows of this charge vanish
+    const int ro = sr.off[c], nr = sr.off[c + 1] - ro;
+    const int co = scl.off[it->second], nc = scl.off[it->second + 1] - co;
+    const int kb = std::min(nr, nc);
+    blk.ensure(sizeof(zc) * (size_t)nr * nc);
+    vb.ensure(sizeof(zc) * (size_t)kb * nc);
+    kern::zgather(s, blk.p, nc, C, cols, dr + ro, nr, dc + co, nc);
+    svd_rowmajor(ctx, blk.p, nr, nc, nullptr, sb, vb.p, w1, w2);
+    kern::zscatter_cols(s, static_cast<char*>(Vh) + sizeof(zc) * (size_t)out * cols, cols, vb.p, nc, kb, dc + co,
+                        nc);
+    for (int j = 0; j < kb; ++j) {
+      S.push_back(sb[j]);
+      qout.push_back(sr.charge[c]);
+    }
+    out += kb;
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+int factor_sectors(tdvp_ctx_s* ctx, bool left, const void* C, int rows, int cols, const std::vector<int>& qrow,
+                   const std::vector<int>& qcol, DBuf& X1, DBuf& X2, std::vector<int>& qk) {
+  if ((int)qrow.size() != rows || (int)qcol.size() != cols) TDVP_THROW(TDVP_ERR_ARG, "factor_sectors: bad charges");
+  hipStream_t s = ctx->stream;
+  const Sectors sr = group_by_charge(qrow), scl = group_by_charge(qcol);
+  // every charge of either side, with its row and column counts
+  std::map<int, std::pair<int, int>> sec;   // charge -> (row sector, column sector), -1 if absent
+  for (int c = 0; c < (int)sr.charge.size(); ++c) sec[sr.charge[c]] = {c, -1};
+  for (int c = 0; c < (int)scl.charge.size(); ++c) {
+    auto it = sec.find(scl.charge[c]);
+    if (it == sec.end()) sec[scl.charge[c]] = {-1, c};
+    else it->second.second = c;
+  }
+  struct Blk { int q, r, c, nr, nc, kb, extra; };
+  std::vector<Blk> blks;
+  int deficit = 0;
+  for (auto& kv : sec) {
+    const int r = kv.second.first, c = kv.second.second;
+    Blk b{kv.first, r, c, r < 0 ? 0 : sr.off[r + 1] - sr.off[r], c < 0 ? 0 : scl.off[c + 1] - scl.off[c], 0, 0};
+    b.kb = std::min(b.nr, b.nc);
+    // the bond of the factorisation has the size min(rows, cols) of the
+    // dense one: where a charge has more bond states on one side than the
+    // other side can hold, the missing ones come from charges with room to
+    // spare, as orthonormal completions that carry no weight
+    deficit += left ? std::max(0, b.nc - b.nr) : std::max(0, b.nr - b.nc);
+    blks.push_back(b);
+  }
+  auto spare = [&](const Blk& b) { return (left ? b.nr - b.nc : b.nc - b.nr) - b.extra; };
+  while (deficit > 0) {
+    int best = -1;
+    for (int x = 0; x < (int)blks.size(); ++x)
+      if ((left ? blks[x].nr : blks[x].nc) > 0 && spare(blks[x]) > 0 && (best < 0 || spare(blks[x]) > spare(blks[best])))
+        best = x;
+    if (best < 0) break;
+    ++blks[best].extra;
+    --deficit;
+  }
+  int k = 0;
+  qk.clear();
+  for (auto& b : blks) {
+    for (int j = 0; j < b.kb + b.extra; ++j) qk.push_back(b.q);
+    k += b.kb + b.extra;
+  }
+  std::vector<int> ints(sr.idx);
+  ints.insert(ints.end(), scl.idx.begin(), scl.idx.end());
+  DBuf dints(ctx), blk(ctx), f1(ctx), f2(ctx), w(ctx), tau(ctx);
+  const int* dr = upload_ints(ctx, dints, ints);
+  const int* dc = dr + rows;
+  X1.ensure(sizeof(zc) * std::max<size_t>(1, (size_t)rows * k));
+  X2.ensure(sizeof(zc) * std::max<size_t>(1, (size_t)k * cols));
+  kern::zfill(s, X1.p, zc(0.0, 0.0), (long long)rows * k, 16);
+  kern::zfill(s, X2.p, zc(0.0, 0.0), (long long)k * cols, 16);
+  int off = 0;
+  for (auto& b : blks) {
+    const int kt = b.kb + b.extra;
+    if (kt == 0) continue;
+    const int* ri = b.r < 0 ? nullptr : dr + sr.off[b.r];
+    const int* ci = b.c < 0 ? nullptr : dc + scl.off[b.c];
+    if (b.nr > 0 && b.nc > 0) {
+      blk.ensure(sizeof(zc) * (size_t)b.nr * b.nc);
+      kern::zgather(s, blk.p, b.nc, C, cols, ri, b.nr, ci, b.nc);
+    }
+    if (left) {
+      // X1 = A (rows x k): columns off .. off + kt of the block's rows;
+      // X2 = R (k x cols): rows off .. off + kb of the block's columns
+      f1.ensure(sizeof(zc) * (size_t)b.nr * std::max(b.nr, 1));
+      f2.ensure(sizeof(zc) * (size_t)std::max(b.kb, 1) * std::max(b.nc, 1));
+      int lda = b.kb;
+      if (b.extra == 0) {
+        qr_rowmajor(ctx, blk.p, b.nr, b.nc, f1.p, f2.p, w, tau);
+      } else if (b.nc > 0) {
+        qr_rowmajor_full(ctx, blk.p, b.nr, b.nc, f1.p, f2.p, tau);
+        lda = b.nr;
+      } else {   // no column of this charge: completions only (an identity block)
+        kern::zfill(s, f1.p, zc(0.0, 0.0), (long long)b.nr * b.nr, 16);
+        kern::zshift_diag(s, f1.p, b.nr, 1.0, 1.0);
+        lda = b.nr;
+      }
+      kern::zscatter(s, static_cast<char*>(X1.p) + sizeof(zc) * off, k, f1.p, lda, ri, b.nr, nullptr, kt);
+      if (b.kb > 0)
+        kern::zscatter(s, static_cast<char*>(X2.p) + sizeof(zc) * (size_t)off * cols, cols, f2.p, b.nc, nullptr, b.kb,
+                       ci, b.nc);
+    } else {
+      // X1 = L (rows x k): columns off .. off + kb; X2 = B (k x cols): rows
+      // off .. off + kt of the block's columns
+      f1.ensure(sizeof(zc) * (size_t)std::max(b.nr, 1) * std::max(b.kb, 1));
+      f2.ensure(sizeof(zc) * (size_t)b.nc * std::max(b.nc, 1));
+      if (b.extra == 0) {
+        lq_rowmajor(ctx, blk.p, b.nr, b.nc, f1.p, f2.p, w, tau);
+      } else if (b.nr > 0) {
+        lq_rowmajor_full(ctx, blk.p, b.nr, b.nc, f1.p, f2.p, tau);
+      } else {
+        kern::zfill(s, f2.p, zc(0.0, 0.0), (long long)b.nc * b.nc, 16);
+        kern::zshift_diag(s, f2.p, b.nc, 1.0, 1.0);
+      }
+      if (b.kb > 0)
+        kern::zscatter(s, static_cast<char*>(X1.p) + sizeof(zc) * off, k, f1.p, b.kb, ri, b.nr, nullptr, b.kb);
+      kern::zscatter(s, static_cast<char*>(X2.p) + sizeof(zc) * (size_t)off * cols, cols, f2.p, b.nc, nullptr, kt, ci,
+                     b.nc);
+    }
+    off += kt;
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  return k;
 }
 
 bool tridiag_ql(double* d, double* e, int n, double* Zr, int nr) {

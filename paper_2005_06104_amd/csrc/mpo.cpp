@@ -154,6 +154,7 @@ HostMPO build_host_mpo(int N, const tdvp_term* terms, int n_terms, zc c0, zc c1)
       }
     }
   }
+  assign_mpo_charges(out);
   return out;
 }
 
@@ -192,4 +193,32 @@ long long site_nnz(const std::vector<zc>& W) {
   for (const zc& x : W)
     if (x != zc(0.0, 0.0)) ++n;
   return n;
+}
+
+void assign_mpo_charges(HostMPO& h) {
+  h.u1 = false;
+  h.qw.clear();
+  const int unset = 1 << 30;
+  std::vector<std::vector<int>> q(h.N + 1);
+  q[0].assign(h.w[0], 0);
+  for (int i = 0; i < h.N; ++i) {
+    const int wl = h.w[i], wr = h.w[i + 1];
+    q[i + 1].assign(wr, unset);
+    const std::vector<zc>& W = h.W[i];
+    for (int a = 0; a < wl; ++a)
+      for (int b = 0; b < wr; ++b)
+        for (int sp = 0; sp < 2; ++sp)
+          for (int sk = 0; sk < 2; ++sk) {
+            if (W[(((size_t)a * wr + b) * 2 + sp) * 2 + sk] == zc(0.0, 0.0)) continue;
+            const int qb = q[i][a] + (sp == 0 ? 1 : -1) - (sk == 0 ? 1 : -1);
+            if (q[i + 1][b] == unset) q[i + 1][b] = qb;
+            else if (q[i + 1][b] != qb) return;   // S^z not conserved
+          }
+    for (int& v : q[i + 1])
+      if (v == unset) v = 0;                       // an empty channel
+  }
+  for (int v : q[h.N])
+    if (v != 0) return;
+  h.qw = std::move(q);
+  h.u1 = true;
 }

@@ -213,6 +213,78 @@ def product_mps(states: Sequence[int]) -> List[np.ndarray]:
     return out
 
 
+def product_charges(states: Sequence[int]) -> List[np.ndarray]:
+    """U(1) bond charges of a product state: bond b carries twice the S^z of
+    sites 0..b-1 (up = +1, down = -1)."""
+    q = [0]
+    for s in states:
+        q.append(q[-1] + (1 if s == 0 else -1))
+    return [np.array([v], dtype=np.int32) for v in q]
+
+
+def u1_sector_dims(N: int, b: int, chi: int, total: int = 0) -> dict:
+    """States per charge at bond b (b sites on the left) of a random U(1) MPS
+    with total charge `total`: charge q is possible when both sides can
+    carry it; at most min(left count, right count) states, the chi states
+    spread in proportion to sqrt(left count * right count) (the weight of a
+    typical state), every possible charge getting at least one while chi
+    lasts, central charges first."""
+    def count(n, q):
+        if (n + q) % 2 or abs(q) > n:
+            return 0
+        return math.comb(n, (n + q) // 2)
+    qs = [q for q in range(-b, b + 1, 2) if count(b, q) and count(N - b, total - q)]
+    cap = {q: min(count(b, q), count(N - b, total - q)) for q in qs}
+    wts = {q: math.sqrt(count(b, q)) * math.sqrt(count(N - b, total - q)) for q in qs}
+    if sum(cap.values()) <= chi:
+        return dict(sorted(cap.items()))
+    order = sorted(qs, key=lambda q: -wts[q])
+    dims = {q: 0 for q in qs}
+    left = chi
+    for q in order:           # one state per charge, most probable first
+        if left == 0:
+            break
+        dims[q] = 1
+        left -= 1
+    tot_w = sum(wts[q] for q in qs)
+    while left > 0:
+        grew = False
+        for q in order:
+            want = max(1, int(round(chi * wts[q] / tot_w)))
+            if left > 0 and dims[q] < min(cap[q], want):
+                dims[q] += 1
+                left -= 1
+                grew = True
+        if not grew:
+            for q in order:
+                if left > 0 and dims[q] < cap[q]:
+                    dims[q] += 1
+                    left -= 1
+                    grew = True
+            if not grew:
+                break
+    return {q: d for q, d in sorted(dims.items()) if d > 0}
+
+
+def random_u1_mps(N: int, chi: int, seed: int, total: int = 0):
+    """Random MPS with U(1) charges (total charge `total`): bond sectors from
+    u1_sector_dims, entries N(0,1) + i N(0,1) inside the blocks q(b) = q(a) +
+    q(s) and zero outside.  Returns (tensors, charges)."""
+    rng = np.random.default_rng(seed)
+    charges = []
+    for b in range(N + 1):
+        sec = u1_sector_dims(N, b, chi, total)
+        charges.append(np.concatenate([np.full(d, q, dtype=np.int32) for q, d in sec.items()]))
+    out = []
+    for i in range(N):
+        ql, qr = charges[i], charges[i + 1]
+        t = rng.standard_normal((len(ql), 2, len(qr))) + 1j * rng.standard_normal((len(ql), 2, len(qr)))
+        for s, dq in ((0, 1), (1, -1)):
+            t[:, s, :] *= (qr[None, :] == ql[:, None] + dq)
+        out.append(t)
+    return out, charges
+
+
 def x_polarized_mps(N: int) -> List[np.ndarray]:
     """All spins along +x: each site (|up> + |down>)/sqrt(2)."""
     t = np.full((1, 2, 1), 1.0 / math.sqrt(2.0), dtype=np.complex128)

@@ -12,6 +12,7 @@ import ctypes as C
 import weakref
 import os
 import re
+import sys
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -100,7 +101,10 @@ def load():
         "tdvp_mpo_to_host": (i, [vp, C.POINTER(d), C.c_size_t]),
         "tdvp_build_mpo_host": (i, [i, C.POINTER(tdvp_term), i, d, d, d, d, C.POINTER(i), C.POINTER(d), C.c_size_t]),
         "tdvp_mpo_destroy": (None, [vp]),
-        "tdvp_mps_from_host": (i, [vp, i, C.POINTER(i), C.POINTER(d), C.POINTER(vp)]),
+        "tdvp_mps_from_host": (i, [vp, i, C.POINTER(i), C.POINTER(d), C.POINTER(i), C.POINTER(vp)]),
+        "tdvp_mps_charges": (i, [vp, C.POINTER(i), C.POINTER(i), C.c_size_t]),
+        "tdvp_mpo_charges_host": (i, [i, C.POINTER(tdvp_term), i, d, d, d, d, C.POINTER(i), C.POINTER(i),
+                                      C.c_size_t]),
         "tdvp_mps_bond_dims": (i, [vp, C.POINTER(i), C.POINTER(i), i]),
         "tdvp_mps_to_host": (i, [vp, C.POINTER(d), C.c_size_t]),
         "tdvp_mps_destroy": (None, [vp]),
@@ -218,11 +222,10 @@ class Context:
             self.lib.tdvp_ctx_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        import sys
-        if sys.is_finalizing():   # torch may be gone: leave the memory to the process exit
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
+            if _finalizing():   # torch may be gone: leave the memory to the process exit
+                return
             self.close()
         except Exception:
             pass
@@ -267,11 +270,10 @@ class MPO:
             self.ctx.lib.tdvp_mpo_destroy(self.h)
         self.h = None
 
-    def __del__(self):
-        import sys
-        if sys.is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
+            if _finalizing():
+                return
             self._destroy()
         except Exception:
             pass
@@ -333,24 +335,70 @@ class MPS:
             self.ctx.lib.tdvp_mps_destroy(self.h)
         self.h = None
 
-    def __del__(self):
-        import sys
-        if sys.is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
+            if _finalizing():
+                return
             self._destroy()
         except Exception:
             pass
 
 
-def tdvp_mps_from_host(ctx: Context, tensors: Sequence[np.ndarray]) -> MPS:
+def tdvp_mps_from_host(ctx: Context, tensors: Sequence[np.ndarray], charges=None) -> MPS:
+    """charges: None, or one integer array per bond (n_sites + 1), ascending."""
     N = len(tensors)
     dims = np.array([tensors[0].shape[0]] + [t.shape[2] for t in tensors], dtype=np.int32)
     flat = np.concatenate([np.ascontiguousarray(t, dtype=np.complex128).ravel() for t in tensors])
     buf = flat.view(np.float64)
+    qp = None
+    if charges is not None:
+        q = np.concatenate([np.asarray(c, dtype=np.int32).ravel() for c in charges]).astype(np.int32)
+        if len(charges) != N + 1 or q.size != int(dims.sum()):
+            raise ValueError("one charge per bond index needed")
+        qp = _iptr(q)
     h = C.c_void_p()
-    ctx.check(ctx.lib.tdvp_mps_from_host(ctx.h, N, _iptr(dims), _dptr(buf), C.byref(h)), "tdvp_mps_from_host")
+    ctx.check(ctx.lib.tdvp_mps_from_host(ctx.h, N, _iptr(dims), _dptr(buf), qp, C.byref(h)), "tdvp_mps_from_host")
     return MPS(ctx, h, N)
+
+
+def tdvp_mps_charges(mps: MPS):
+    """The bond charges (list of n_sites + 1 arrays) or None for a state without them."""
+    has = C.c_int()
+    mps.ctx.check(mps.ctx.lib.tdvp_mps_charges(mps.h, C.byref(has), None, 0), "tdvp_mps_charges")
+    if not has.value:
+        return None
+    dims = mps.bond_dims()
+    q = np.zeros(sum(dims), dtype=np.int32)
+    mps.ctx.check(mps.ctx.lib.tdvp_mps_charges(mps.h, C.byref(has), _iptr(q), q.size), "tdvp_mps_charges")
+    out, off = [], 0
+    for m in dims:
+        out.append(q[off:off + m].copy())
+        off += m
+    return out
+
+
+def tdvp_mpo_charges_host(n_sites: int, terms, c0: complex = 0.0, c1: complex = 1.0):
+    """Channel charges of the MPO of c0 + c1 H (list per bond), or None when it does not conserve S^z."""
+    lib = load()
+    arr = terms_array(terms)
+    c0, c1 = complex(c0), complex(c1)
+    dims = np.zeros(n_sites + 1, dtype=np.int32)
+    st = lib.tdvp_build_mpo_host(n_sites, arr, len(terms), c0.real, c0.imag, c1.real, c1.imag, _iptr(dims), None, 0)
+    if st != TDVP_OK:
+        raise TdvpError(st, "tdvp_build_mpo_host")
+    cons = C.c_int()
+    q = np.zeros(int(dims.sum()), dtype=np.int32)
+    st = lib.tdvp_mpo_charges_host(n_sites, arr, len(terms), c0.real, c0.imag, c1.real, c1.imag, C.byref(cons),
+                                   _iptr(q), q.size)
+    if st != TDVP_OK:
+        raise TdvpError(st, "tdvp_mpo_charges_host")
+    if not cons.value:
+        return None
+    out, off = [], 0
+    for m in dims:
+        out.append(q[off:off + m].copy())
+        off += m
+    return out
 
 
 def tdvp_mps_to_host(mps: MPS) -> List[np.ndarray]:

@@ -116,3 +116,31 @@ def test_squeezing_xi2_rejects_bad_moments():
         T.tdvp_squeezing_xi2(0, 1.0, 1.0, 1.0, 0.0)
     with pytest.raises(T.TdvpError):
         T.tdvp_squeezing_xi2(4, 1.0, float("nan"), 1.0, 0.0)
+
+
+@pytest.mark.parametrize("case", ["ladder", "cyl", "oat", "broken"])
+def test_mpo_channel_charges(case):
+    """Channel charges of the host MPO: every nonzero W[al,be,s',s] satisfies
+    qw(be) = qw(al) + q(s') - q(s) with q(up) = 1, q(down) = -1, and both
+    ends carry charge 0; a one-site S^+ term breaks the conservation."""
+    if case == "ladder":
+        lat = I.ladder(4, 1.0, 0.5, "zigzag"); N = lat.n_sites; terms = I.heisenberg_terms(lat.couplings)
+    elif case == "cyl":
+        lat = I.cylinder(4, 3, 1.0, 0.5); N = lat.n_sites; terms = I.heisenberg_terms(lat.couplings)
+    elif case == "oat":
+        N = 8; terms = I.oat_terms(N)
+    else:
+        lat = I.ladder(3, 1.0, 1.0, "snake"); N = lat.n_sites
+        terms = I.heisenberg_terms(lat.couplings) + [(1, -1, I.OP_SP, I.OP_I, 0.5)]
+    for c0, c1 in ((0.0, 1.0), (1.0, -0.1j)):
+        q = T.tdvp_mpo_charges_host(N, terms, c0, c1)
+        if case == "broken":
+            assert q is None
+            continue
+        Ws = T.tdvp_build_mpo_host(N, terms, c0, c1)
+        assert q[0].tolist() == [0] and q[-1].tolist() == [0]
+        qs = np.array([1, -1])
+        for i, W in enumerate(Ws):
+            allowed = (q[i + 1][None, :, None, None] == q[i][:, None, None, None] + qs[None, None, :, None]
+                       - qs[None, None, None, :])
+            assert np.all(W[~allowed] == 0), i
