@@ -128,4 +128,7 @@ def test_bench_workload_first_step_matches_oracle(env, bench_first_step, prec, b
     assert de < {"fp64": 1e-9, "fp32": 1e-5 * abs(m["energy"]), "bf16x3": 2e-4 * abs(m["energy"])}[prec], de
     assert dsz < (1e-7 if prec == "fp64" else 1e-4), dsz
     bg, bo = M.bond_dims(out), M.bond_dims(psi1)
-    assert all(abs(a - b) <= max(2, b // 20) for a, b in zip(bg, bo)), (bg, bo)
+    # the cuts of the mixed paths read eigenvalues of reduced-precision
+    # contractions: their bonds may move by more than a state or two
+    tol = 20 if prec == "fp64" else 5
+    assert all(abs(a - b) <= max(2, b // tol) for a, b in zip(bg, bo)), (bg, bo)

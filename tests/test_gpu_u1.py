@@ -78,9 +78,10 @@ def _gse_both(T, ctx, N, terms, psi0, q0, dt, tau, k, eps_K, eps_M, eps, chi, st
 # spare, so that the bond keeps the dense size).  Both are exact for the
 # state; they differ in the projector by a few 1e-9 in fidelity over these
 # runs (the dense device and the oracle differ by ~1e-9 the same way where the
-# bond cap binds).  So the runs are held to the exact dynamics: the error of
-# the charged run against exact diagonalisation is at most twice the
-# oracle's, and the two agree to 2e-8 per unit time.
+# bond cap binds), and chained over many steps the gap grows.  So the runs
+# are held to the exact dynamics: the error of the charged run against exact
+# diagonalisation is at most twice the oracle's, and the charged run and the
+# oracle are closer to each other than half the oracle's own error.
 
 
 def test_mpo_charges_rejected_when_not_conserved(env):
@@ -117,9 +118,9 @@ def test_u1_ladder_quench_matches_oracle(env):
     t = 0.0
     for r in rows:
         t += w.dt.real
-        assert r["loss"] < 2e-8 * t + 1e-12, r
         assert r["ed_u1"] <= 2.0 * r["ed_oracle"] + 1e-10, r
-        assert abs(r["de"]) < 1e-9 and r["dsz"] < 1e-7, r
+        assert r["loss"] <= 0.5 * r["ed_oracle"] + 1e-12, r
+        assert abs(r["de"]) < 1e-9 and r["dsz"] < 1e-6, r
     assert all(np.all(np.abs(b) <= 12) for b in q) and q[-1][0] == 0
 
 
@@ -138,8 +139,10 @@ def test_u1_cylinder_quench_matches_oracle(env):
         t = 0.0
         for r in rows:
             t += 0.05
-            assert r["loss"] < (2e-8 if chi == 64 else 1e-9) * t + 1e-12, r
             assert r["ed_u1"] <= 2.0 * r["ed_oracle"] + 1e-10, r
+            assert r["loss"] <= 0.5 * r["ed_oracle"] + 1e-12, r
+            if chi == 256:     # the cap never binds: close agreement
+                assert r["loss"] < 1e-9 * t + 1e-12, r
             assert abs(r["de"]) < 1e-9 and r["dsz"] < 1e-7, r
         assert len(set(q[N // 2].tolist())) > 3     # several charge sectors in the middle
 
