@@ -341,6 +341,25 @@ tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int 
                             const double* W_host, const void* L, const void* Rt, const void* C,
                             void* Y, void* workspace);
 
+/* tdvp_heff_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels on the same operands, with every piece of
+ * scratch (the MPO's CSR tables, the two intermediates and the split-K
+ * partial products) in one statically sized device array of 64 MiB that each
+ * GPU holds from the library's load until the process ends; nothing is
+ * allocated and no workspace is passed.  Sizes whose scratch,
+ * (4 max(wl, wr) + 32) ml mr elements of the precision plus the tables,
+ * exceeds 64 MiB are rejected with TDVP_ERR_ARG before any work.  Every call
+ * on one GPU uses the same array, which keeps the last call's contents:
+ * calls that overlap on one GPU (from several threads or streams) race.
+ * Returns once the MPO tables are in the array (they are copied from host
+ * memory: the call waits for the context's stream); the contraction itself
+ * runs asynchronously on that stream.  Arguments and layouts as
+ * tdvp_heff_apply. */
+tdvp_status tdvp_heff_apply_noalloc(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr,
+                                    const double* W_host, const void* L, const void* Rt,
+                                    const void* C, void* Y);
+
 /* Zero-site effective Hamiltonian on the bond: Y[a',b'] = sum L[a',al,a] X[a,b] Rt[al,b,b'].
  * Sizes: L ml*w*ml, Rt w*mr*mr, X and Y ml*mr; workspace as for tdvp_heff_apply. */
 tdvp_status tdvp_keff_apply(tdvp_ctx ctx, int prec, int ml, int w, int mr, const void* L,

@@ -574,6 +574,18 @@ def tdvp_heff_apply(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, workspace=None, 
                                       _tp(workspace)), "tdvp_heff_apply")
 
 
+def tdvp_heff_apply_noalloc(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, prec: Optional[str] = None):
+    ml, wl, _ = L.shape
+    wr, mr, _ = Rt.shape
+    Wc, wp = _w_host(W)
+    fn = ctx.lib.tdvp_heff_apply_noalloc
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_void_p,
+                   C.c_void_p, C.c_void_p, C.c_void_p]
+    ctx.check(fn(ctx.h, _prec_of(L, prec), ml, wl, wr, mr, wp, _tp(L), _tp(Rt), _tp(Cin), _tp(Y)),
+              "tdvp_heff_apply_noalloc")
+
+
 def tdvp_keff_apply(ctx: Context, L, Rt, X, Y, workspace=None, prec: Optional[str] = None):
     ml, w, _ = L.shape
     _, mr, _ = Rt.shape
