@@ -1,0 +1,200 @@
+// Block-sparse maps of the products whose operands carry U(1) charges.
+//
+// A product C[m, n] = sum_k A[m, k] B[k, n] between charged tensors has
+// nonzero terms only where the charge a row m needs on the summed index, the
+// charge of k, and the charge column n needs on it all agree.  For every
+// 64 x 64 output tile the map lists the K intervals holding the charges
+// that occur among both the tile's rows and its columns; the MFMA kernels
+// walk only those.  Intervals closer than a K step are joined (the skipped
+// entries between them are exact zeros, so including them changes nothing).
+#include <algorithm>
+#include <cstring>
+
+#include "engine.h"
+
+namespace {
+
+constexpr int TILE = 64;   // the GEMM kernels' output tile
+constexpr int GAP = 32;    // the largest K step of the kernels
+
+struct Run {
+  int b, e;
+};
+
+}  // namespace
+
+void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out) {
+  const int M = (int)rq.size(), K = (int)kq.size(), N = (int)cq.size();
+  int cmin = 1 << 30, cmax = -(1 << 30);
+  for (const auto* v : {&rq, &kq, &cq})
+    for (int x : *v) {
+      cmin = std::min(cmin, x);
+      cmax = std::max(cmax, x);
+    }
+  const int R = M && N && K ? cmax - cmin + 1 : 1;
+  // runs of equal charge along K, listed per charge in order
+  std::vector<std::vector<Run>> runs(R);
+  for (int k = 0; k < K;) {
+    int e = k + 1;
+    while (e < K && kq[e] == kq[k]) ++e;
+    runs[kq[k] - cmin].push_back({k, e});
+    k = e;
+  }
+  // distinct charges of each row tile and column tile
+  auto tile_sets = [&](const std::vector<int>& q, int n) {
+    const int nt = (n + TILE - 1) / TILE;
+    std::vector<std::vector<int>> sets(nt);
+    std::vector<int> stamp(R, -1);
+    for (int t = 0; t < nt; ++t)
+      for (int i = t * TILE; i < std::min(n, (t + 1) * TILE); ++i) {
+        const int c = q[i] - cmin;
+        if (stamp[c] != t) {
+          stamp[c] = t;
+          sets[t].push_back(c);
+        }
+      }
+    return sets;
+  };
+  const auto rs = tile_sets(rq, M), cs = tile_sets(cq, N);
+  const int tm = (int)rs.size(), tn = (int)cs.size();
+  out.off.assign((size_t)tm * tn + 1, 0);
+  out.iv.clear();
+  out.tile_macs = 0.0;
+  std::vector<int> mark(R, -1);
+  std::vector<Run> sel;
+  for (int a = 0; a < tm; ++a) {
+    for (int c : rs[a]) mark[c] = a;
+    const int rows = std::min(M, (a + 1) * TILE) - a * TILE;
+    for (int b = 0; b < tn; ++b) {
+      sel.clear();
+      for (int c : cs[b])
+        if (mark[c] == a) sel.insert(sel.end(), runs[c].begin(), runs[c].end());
+      std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
+      const int cols = std::min(N, (b + 1) * TILE) - b * TILE;
+      long long klen = 0;
+      for (size_t j = 0; j < sel.size();) {
+        Run cur = sel[j++];
+        while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
+        out.iv.push_back(cur.b);
+        out.iv.push_back(cur.e);
+        klen += cur.e - cur.b;
+      }
+      out.off[(size_t)a * tn + b + 1] = (int)(out.iv.size() / 2);
+      out.tile_macs += (double)rows * cols * klen;
+    }
+    for (int c : rs[a]) mark[c] = -1;
+  }
+  // nonzero multiply-adds: per charge, rows x columns x K indices of it
+  std::vector<double> nr(R, 0.0), nc(R, 0.0), nk(R, 0.0);
+  for (int x : rq) nr[x - cmin] += 1;
+  for (int x : cq) nc[x - cmin] += 1;
+  for (int x : kq) nk[x - cmin] += 1;
+  out.exact_macs = 0.0;
+  for (int c = 0; c < R && M && N && K; ++c) out.exact_macs += nr[c] * nc[c] * nk[c];
+  out.M = M;
+  out.N = N;
+  out.K = K;
+}
+
+void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
+  const size_t nb = sizeof(int) * (h.off.size() + h.iv.size());
+  buf.ensure(nb);
+  HIP_CHECK(hipMemcpyAsync(buf.p, h.off.data(), sizeof(int) * h.off.size(), hipMemcpyHostToDevice, ctx->stream));
+  if (!h.iv.empty())
+    HIP_CHECK(hipMemcpyAsync(buf.as<int>() + h.off.size(), h.iv.data(), sizeof(int) * h.iv.size(),
+                             hipMemcpyHostToDevice, ctx->stream));
+  HIP_CHECK(hipStreamSynchronize(ctx->stream));   // the host vectors may die
+  map.off = buf.as<int>();
+  map.iv = buf.as<int>() + h.off.size();
+  map.M = h.M;
+  map.N = h.N;
+  map.K = h.K;
+  map.batch = h.batch;
+  exact_flops = 8.0 * h.exact_macs;
+  tile_flops = 8.0 * h.tile_macs;
+}
+
+namespace {
+
+// charges of fused row-major indices (first index outer)
+std::vector<int> fuse2(const std::vector<int>& x, const std::vector<int>& y, int sx, int sy) {
+  std::vector<int> o;
+  o.reserve(x.size() * y.size());
+  for (int a : x)
+    for (int b : y) o.push_back(sx * a + sy * b);
+  return o;
+}
+const std::vector<int> kPhys = {1, -1};
+std::vector<int> phys2() { return {2, 0, 0, -2}; }   // (s, v): q(s) + q(v)
+
+}  // namespace
+
+namespace {
+
+// the maps of a batch of products, one per batch entry (batch outer)
+void join_batches(const std::vector<KMapHost>& parts, KMapHost& out) {
+  out = KMapHost();
+  out.off.assign(1, 0);
+  for (const auto& p : parts) {
+    const int base = (int)(out.iv.size() / 2);
+    for (size_t t = 1; t < p.off.size(); ++t) out.off.push_back(base + p.off[t]);
+    out.iv.insert(out.iv.end(), p.iv.begin(), p.iv.end());
+    out.exact_macs += p.exact_macs;
+    out.tile_macs += p.tile_macs;
+    out.M = p.M;
+    out.N = p.N;
+    out.K = p.K;
+  }
+  out.batch = (int)parts.size();
+}
+
+// rows a' of batch x need q(a') + sign * shift[x]
+void build_batched(const std::vector<int>& qrow, const std::vector<int>& shift, int sign, const std::vector<int>& kq,
+                   const std::vector<int>& cq, KMapHost& out) {
+  std::vector<KMapHost> parts(shift.size());
+  std::vector<int> rq(qrow.size());
+  for (size_t x = 0; x < shift.size(); ++x) {
+    for (size_t r = 0; r < qrow.size(); ++r) rq[r] = qrow[r] + sign * shift[x];
+    build_kmap(rq, kq, cq, parts[x]);
+  }
+  join_batches(parts, out);
+}
+
+}  // namespace
+
+// H_eff and the left environment: T1[(a',al),(s,b)] = L[(a',al),a] C[a,(s,b)]
+// batched over al (rows a' need q(a') - q(al), columns q(b) - q(s))
+void kmap_env_gemm1(const std::vector<int>& qlo, const std::vector<int>& qli, const std::vector<int>& qwl,
+                    const std::vector<int>& qri, KMapHost& out) {
+  build_batched(qlo, qwl, -1, qli, fuse2(kPhys, qri, -1, 1), out);
+}
+// H_eff: Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b'] batched over s'
+void kmap_heff_gemm2(const std::vector<int>& qlo, const std::vector<int>& qri, const std::vector<int>& qwr,
+                     const std::vector<int>& qro, KMapHost& out) {
+  build_batched(qlo, kPhys, 1, fuse2(qwr, qri, 1, 1), qro, out);
+}
+// bra^H[b',(a',s')] T2[(a',s'),(be,b)]
+void kmap_env_left_gemm2(const std::vector<int>& qlo, const std::vector<int>& qro, const std::vector<int>& qri,
+                         const std::vector<int>& qwr, KMapHost& out) {
+  build_kmap(qro, fuse2(qlo, kPhys, 1, 1), fuse2(qwr, qri, 1, 1), out);
+}
+// U2[(al,a),(s',b')] conj(bra[a',(s',b')])
+void kmap_env_right_gemm3(const std::vector<int>& qli, const std::vector<int>& qwl, const std::vector<int>& qro,
+                          const std::vector<int>& qlo, KMapHost& out) {
+  build_kmap(fuse2(qwl, qli, 1, 1), fuse2(kPhys, qro, -1, 1), qlo, out);
+}
+// K_eff: L[(a',al),a] X[a,b] batched over al, then Y1[a',(al,b)] Rt[(al,b),b']
+// (a, a' on the bond basis of L, b, b' on that of Rt; X pairs equal charges)
+void kmap_keff(const std::vector<int>& ql, const std::vector<int>& qr, const std::vector<int>& qw, KMapHost& g1,
+               KMapHost& g2) {
+  build_batched(ql, qw, -1, ql, qr, g1);
+  build_kmap(ql, fuse2(qw, qr, 1, 1), qr, g2);
+}
+// two-site: L[(a',al),a] P[a,(s,v,b)] batched over al, then
+// T3[(a',t,u),(ga,b)] Rt[(ga,b),b'] batched over (t, u)
+void kmap_two_site(const std::vector<int>& qlo, const std::vector<int>& qli, const std::vector<int>& qwl,
+                   const std::vector<int>& qri, const std::vector<int>& qwr, const std::vector<int>& qro,
+                   KMapHost& g1, KMapHost& g2) {
+  build_batched(qlo, qwl, -1, qli, fuse2(phys2(), qri, -1, 1), g1);
+  build_batched(qlo, phys2(), 1, fuse2(qwr, qri, 1, 1), qro, g2);
+}

@@ -151,6 +151,28 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
           long long lda, long long sa, const void* B, long long ldb, long long sb, zc beta, void* C,
           long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0);
 
+// Block-sparse map of an M x N x K product whose operands carry U(1)
+// charges: for every 64 x 64 output tile (row-major tile order) the K
+// intervals it needs, iv[off[t] .. off[t+1]) as (begin, end) pairs; device
+// arrays.  While set (set_kmap / KMapScope) on the calling host thread, the
+// products of that shape (batch 1) it issues walk only those intervals; any
+// other shape is an error.
+struct KMap {
+  const int* off = nullptr;
+  const int* iv = nullptr;     // pairs
+  int M = 0, N = 0, K = 0;
+  int batch = 1;               // batched products: one map per batch entry, batch outer
+};
+void set_kmap(const KMap* k);
+const KMap* current_kmap();
+struct KMapScope {
+  const KMap* saved;
+  explicit KMapScope(const KMap* k) : saved(current_kmap()) { set_kmap(k); }
+  ~KMapScope() { set_kmap(saved); }
+  KMapScope(const KMapScope&) = delete;
+  KMapScope& operator=(const KMapScope&) = delete;
+};
+
 // Split-K scratch used by gemm() calls from the calling host thread that
 // pass no ws of their own (NULL: none, products run unsplit).
 void set_split_workspace(void* p, size_t bytes);
@@ -212,6 +234,13 @@ struct FloatModeScope {
 inline int float_mode_of(int prec) {
   return prec == TDVP_BF16_FP32ACC ? 1 : prec == TDVP_BF16X3_FP32ACC ? 2 : 0;
 }
+// Batched NN product (alpha = 1, beta = 0, strides in elements) with the
+// one-site effective Hamiltonian's instantiation: with charges, its two
+// products run batched over the MPO channel (first) and the physical index
+// (second) so that every tile of a batch meets one charge.
+template <typename T>
+void gemm_heff_batched(hipStream_t s, int M, int N, int K, const void* A, long long lda, long long sa, const void* B,
+                       long long ldb, long long sb, void* C, long long ldc, long long sc, int batch);
 // Plain NN product with split-K scratch (environments, zero-site H_eff).
 template <typename T>
 void gemm_nn_ws(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <numeric>
 #include <cstring>
+#include <map>
 
 namespace {
 
@@ -198,54 +199,84 @@ struct Lanczos {
 // ------------------------------------------------------------ contractions
 template <typename T>
 void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm, SplitWS sk) {
+                const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm, SplitWS sk,
+                ProdMaps pm) {
   hipStream_t s = ctx->stream;
   if (tm) tm->mark(0);
-  // T1[(a',al),(s,b)] = L[(a',al),a] C[a,(s,b)]
-  kern::gemm_heff<T>(s, ml * wl, 2 * mr, ml, L, ml, C, 2 * mr, ws1, 2 * mr, sk.p, sk.bytes);
+  // T1[(a',al),(s,b)] = L[(a',al),a] C[a,(s,b)] (with charges: batched over al)
+  if (pm.g1) {
+    kern::KMapScope ks(pm.g1);
+    kern::gemm_heff_batched<T>(s, ml, 2 * mr, ml, L, (long long)wl * ml, ml, C, 2 * mr, 0, ws1, (long long)wl * 2 * mr,
+                               2 * mr, wl);
+  } else {
+    kern::gemm_heff<T>(s, ml * wl, 2 * mr, ml, L, ml, C, 2 * mr, ws1, 2 * mr, sk.p, sk.bytes);
+  }
   if (tm) tm->mark(1);
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
                   mr, (long long)wr * mr);
   if (tm) tm->mark(2);
-  // Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b']
-  kern::gemm_heff<T>(s, 2 * ml, mr, wr * mr, ws2, (long long)wr * mr, Rt, mr, Y, mr, sk.p, sk.bytes);
+  // Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b'] (with charges: batched over s')
+  if (pm.g2) {
+    kern::KMapScope ks(pm.g2);
+    kern::gemm_heff_batched<T>(s, ml, mr, wr * mr, ws2, 2LL * wr * mr, (long long)wr * mr, Rt, mr, 0, Y, 2LL * mr, mr,
+                               2);
+  } else {
+    kern::gemm_heff<T>(s, 2 * ml, mr, wr * mr, ws2, (long long)wr * mr, Rt, mr, Y, mr, sk.p, sk.bytes);
+  }
   if (tm) tm->mark(3);
-  if (tm) tm->gemm_flops += 8.0 * ((double)ml * wl * ml * 2 * mr + (double)2 * ml * wr * mr * mr);
+  if (tm)
+    tm->gemm_flops += pm.flops >= 0.0 ? pm.flops
+                                      : 8.0 * ((double)ml * wl * ml * 2 * mr + (double)2 * ml * wr * mr * mr);
 }
 
 template <typename T>
 void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
-                void* ws1, SplitWS sk) {
+                void* ws1, SplitWS sk, ProdMaps pm) {
   hipStream_t s = ctx->stream;
   // Y1[(a',al),b] = L[(a',al),a] X[a,b];  Y[a',b'] = Y1[a',(al,b)] Rt[(al,b),b']
-  kern::gemm_nn_ws<T>(s, ml * w, mr, ml, 1.0, L, ml, X, mr, 0.0, ws1, mr, sk.p, sk.bytes);
+  if (pm.g1) {   // with charges: batched over al
+    kern::KMapScope ks(pm.g1);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml, mr, ml, 1.0, L, (long long)w * ml, ml, X, mr, 0, 0.0, ws1,
+                  (long long)w * mr, mr, w);
+  } else {
+    kern::gemm_nn_ws<T>(s, ml * w, mr, ml, 1.0, L, ml, X, mr, 0.0, ws1, mr, sk.p, sk.bytes);
+  }
+  kern::KMapScope ks(pm.g2);
   kern::gemm_nn_ws<T>(s, ml, mr, w * mr, 1.0, ws1, (long long)w * mr, Rt, mr, 0.0, Y, mr, sk.p, sk.bytes);
 }
 
 template <typename T>
 void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L, const void* A,
-              void* Lout, void* ws1, void* ws2, SplitWS sk) {
+              void* Lout, void* ws1, void* ws2, SplitWS sk, ProdMaps pm) {
   hipStream_t s = ctx->stream;
-  kern::gemm_nn_ws<T>(s, ml * wl, 2 * mr, ml, 1.0, L, ml, A, 2 * mr, 0.0, ws1, 2 * mr, sk.p, sk.bytes);
+  if (pm.g1) {   // with charges: batched over al
+    kern::KMapScope ks(pm.g1);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, ml, 2 * mr, ml, 1.0, L, (long long)wl * ml, ml, A, 2 * mr, 0, 0.0, ws1,
+                  (long long)wl * 2 * mr, 2 * mr, wl);
+  } else {
+    kern::gemm_nn_ws<T>(s, ml * wl, 2 * mr, ml, 1.0, L, ml, A, 2 * mr, 0.0, ws1, 2 * mr, sk.p, sk.bytes);
+  }
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
                   mr, (long long)wr * mr);
   // Lout[b',(be,b)] = sum_{(a',s')} conj(A[(a',s'),b']) T2[(a',s'),(be,b)]
+  kern::KMapScope ks(pm.g2);
   kern::gemm<T>(s, TDVP_OP_C, TDVP_OP_N, mr, wr * mr, 2 * ml, 1.0, A, mr, 0, ws2, (long long)wr * mr, 0, 0.0, Lout,
                 (long long)wr * mr, 0, 1);
 }
 
 template <typename T>
 void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* Rt,
-               const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk) {
+               const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk, ProdMaps pm) {
   (void)sk;
   hipStream_t s = ctx->stream;
-  // U1[be][(a,s),b'] = B[(a,s),b] Rt[be][b,b']   (batched over be)
+  // U1[be][(a,s),b'] = B[(a,s),b] Rt[be][b,b']   (batched over be; dense)
   kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, mr, 1.0, B, mr, 0, Rt, mr, (long long)mr * mr, 0.0, ws1, mr,
                 2LL * ml * mr, wr);
   // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
   kern::wapply<T>(s, tb.B, ws1, ws2, ml, mr, 2LL * mr, 1, 2LL * ml * mr, mr, 2LL * mr, 1, 2LL * ml * mr, mr);
   // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(B[a',(s',b')])
+  kern::KMapScope ks(pm.g2);
   kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, wl * ml, ml, 2 * mr, 1.0, ws2, 2LL * mr, 0, B, 2LL * mr, 0, 0.0, Rout, ml,
                 0, 1);
 }
@@ -256,11 +287,14 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
 template <typename T>
 void heff2_apply(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int ml, int wl, int wm, int wr, int mr,
                  const void* L, const void* Rt, const void* Th, void* Y, void* ws1, void* ws2, MatvecTimer* tm,
-                 SplitWS sk) {
+                 SplitWS sk, ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
   if (tm) tm->mark(0);
   // T1[(a',al),(s,v,b)] = L[(a',al),a] Th[a,(s,v,b)]
-  kern::gemm_heff<T>(s, ml * wl, 4 * mr, ml, L, ml, Th, 4 * mr, ws1, 4 * mr, sk.p, sk.bytes);
+  {
+    kern::KMapScope ks(pm.g1);
+    kern::gemm_heff<T>(s, ml * wl, 4 * mr, ml, L, ml, Th, 4 * mr, ws1, 4 * mr, sk.p, sk.bytes);
+  }
   if (tm) tm->mark(1);
   // T2[a',t,be,(v,b)] = sum W1[al,be,t,s] T1[a',al,s,(v,b)]
   kern::wapply<T>(s, t1.F, ws1, ws2, ml, 2LL * mr, (long long)wl * 4 * mr, 1, 4LL * mr, 2LL * mr,
@@ -270,27 +304,32 @@ void heff2_apply(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, in
                   1, mr, (long long)wr * mr);
   if (tm) tm->mark(2);
   // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b']
-  kern::gemm_heff<T>(s, 4 * ml, mr, wr * mr, ws1, (long long)wr * mr, Rt, mr, Y, mr, sk.p, sk.bytes);
+  {
+    kern::KMapScope ks(pm.g2);
+    kern::gemm_heff<T>(s, 4 * ml, mr, wr * mr, ws1, (long long)wr * mr, Rt, mr, Y, mr, sk.p, sk.bytes);
+  }
   if (tm) tm->mark(3);
-  if (tm) tm->gemm_flops += 8.0 * ((double)ml * wl * ml * 4 * mr + (double)4 * ml * wr * mr * mr);
+  if (tm)
+    tm->gemm_flops += pm.flops >= 0.0 ? pm.flops
+                                      : 8.0 * ((double)ml * wl * ml * 4 * mr + (double)4 * ml * wr * mr * mr);
 }
 
 template void heff_apply<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
-                                 const void*, void*, void*, void*, MatvecTimer*, SplitWS);
+                                 const void*, void*, void*, void*, MatvecTimer*, SplitWS, ProdMaps);
 template void heff_apply<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*,
-                                const void*, void*, void*, void*, MatvecTimer*, SplitWS);
+                                const void*, void*, void*, void*, MatvecTimer*, SplitWS, ProdMaps);
 template void keff_apply<double>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*,
-                                 SplitWS);
+                                 SplitWS, ProdMaps);
 template void keff_apply<float>(tdvp_ctx_s*, int, int, int, const void*, const void*, const void*, void*, void*,
-                                SplitWS);
+                                SplitWS, ProdMaps);
 template void env_left<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                               void*, void*, SplitWS);
+                               void*, void*, SplitWS, ProdMaps);
 template void env_left<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                              void*, void*, SplitWS);
+                              void*, void*, SplitWS, ProdMaps);
 template void env_right<double>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                                void*, void*, SplitWS);
+                                void*, void*, SplitWS, ProdMaps);
 template void env_right<float>(tdvp_ctx_s*, const SiteTables&, int, int, int, int, const void*, const void*, void*,
-                               void*, void*, SplitWS);
+                               void*, void*, SplitWS, ProdMaps);
 
 // ------------------------------------------------------------ handles
 namespace {
@@ -755,6 +794,40 @@ void right_canonicalize(Work& W, tdvp_mps_s& psi) {
   }
 }
 
+// Nonzero multiply-adds of the sparse MPO stage T2[a',s',be,b] = sum
+// W[al,be,s',s] T1[a',al,s,b] when the bonds carry charges: per nonzero W
+// entry, the (a', b) pairs with q(b) - q(s) = q(a') - q(al).
+double wstage_macs(const std::vector<int>& ql, const std::vector<int>& qr, const std::vector<int>& qwl,
+                   const std::vector<zc>& Wt, int wl, int wr) {
+  std::map<int, double> nl, nr;
+  for (int v : ql) nl[v] += 1;
+  for (int v : qr) nr[v] += 1;
+  double macs = 0.0;
+  for (int a = 0; a < wl; ++a)
+    for (int b = 0; b < wr; ++b)
+      for (int sp = 0; sp < 2; ++sp)
+        for (int sk = 0; sk < 2; ++sk) {
+          if (Wt[(((size_t)a * wr + b) * 2 + sp) * 2 + sk] == zc(0.0, 0.0)) continue;
+          const int shift = -qwl[a] + phys_charge(sk);
+          for (auto& kv : nl) {
+            auto it = nr.find(kv.first + shift);
+            if (it != nr.end()) macs += kv.second * it->second;
+          }
+        }
+  return macs;
+}
+
+// Block-sparse maps of one contraction's two products, rebuilt per site.
+struct PairMaps {
+  DevKMap g1, g2;
+  explicit PairMaps(tdvp_ctx_s* c) : g1(c), g2(c) {}
+  ProdMaps set(tdvp_ctx_s* ctx, const KMapHost& a, const KMapHost& b) {
+    g1.set(ctx, a);
+    g2.set(ctx, b);
+    return ProdMaps{g1.get(), g2.get(), 8.0 * (a.exact_macs + b.exact_macs)};
+  }
+};
+
 template <typename T>
 void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdvp_sweep_params& p,
                 tdvp_sweep_stats& st) {
@@ -777,19 +850,37 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     W.ws1.ensure(need);
     W.ws2.ensure(need);
   };
+  // with charges, every product walks only its nonzero blocks
+  const bool sym = psi.u1();
+  PairMaps hmap(ctx), kmap(ctx), emap(ctx);
+  const auto& qw = H.host.qw;
   auto build_R = [&](int i) {  // Rt[i] from Rt[i+1] and site i
     const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
     ensure_ws(ml, wl, wr, mr);
     R[i].ensure((size_t)wl * ml * ml * cb);
     const void* Bt = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
-    env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p);
+    ProdMaps pm;
+    if (sym) {
+      KMapHost g3;
+      kmap_env_right_gemm3(psi.q[i], qw[i], psi.q[i + 1], psi.q[i], g3);
+      emap.g2.set(ctx, g3);
+      pm.g2 = emap.g2.get();
+    }
+    env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p, {}, pm);
   };
   auto build_L = [&](int i) {  // L[i+1] from L[i] and site i
     const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
     ensure_ws(ml, wl, wr, mr);
     L[i + 1].ensure((size_t)mr * wr * mr * cb);
     const void* At = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
-    env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p, W.split(ml, mr, cb));
+    ProdMaps pm;
+    if (sym) {
+      KMapHost g1, g2;
+      kmap_env_gemm1(psi.q[i], psi.q[i], qw[i], psi.q[i + 1], g1);
+      kmap_env_left_gemm2(psi.q[i], psi.q[i + 1], psi.q[i + 1], qw[i + 1], g2);
+      pm = emap.set(ctx, g1, g2);
+    }
+    env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p, W.split(ml, mr, cb), pm);
   };
   auto stepinfo = [&](int napp, bool unconv) {
     st.max_lanczos = std::max(st.max_lanczos, napp);
@@ -799,17 +890,26 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
     const long long n = psi.elems(i);
     ensure_ws(ml, wl, wr, mr);
-    const double flops = 8.0 * ((double)ml * wl * ml * 2 * mr + (double)H.tab[i].nnz * ml * mr +
-                                (double)2 * ml * wr * mr * mr);
+    double flops = 8.0 * ((double)ml * wl * ml * 2 * mr + (double)H.tab[i].nnz * ml * mr +
+                          (double)2 * ml * wr * mr * mr);
+    ProdMaps pm;
+    if (sym) {
+      KMapHost g1, g2;
+      kmap_env_gemm1(psi.q[i], psi.q[i], qw[i], psi.q[i + 1], g1);
+      kmap_heff_gemm2(psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1], g2);
+      pm = hmap.set(ctx, g1, g2);
+      flops = pm.flops + 8.0 * wstage_macs(psi.q[i], psi.q[i + 1], qw[i], H.host.W[i], wl, wr);
+    }
     const SplitWS sk = W.split(ml, mr, cb);
     auto mv = [&](const void* in, void* out) {
       if (sizeof(T) == 8) {
-        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, &timer, sk);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, &timer, sk, pm);
       } else {
         W.xf.ensure((size_t)n * 8);
         W.yf.ensure((size_t)n * 8);
         kern::z2c(ctx->stream, W.xf.p, in, n);
-        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p, &timer, sk);
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, W.xf.p, W.yf.p, W.ws1.p, W.ws2.p, &timer, sk,
+                      pm);
         kern::c2z(ctx->stream, out, W.yf.p, n);
       }
       st.flops_matvec += flops;
@@ -819,20 +919,29 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     st.n_matvec += napp;
     stepinfo(napp, unconv);
   };
-  auto evolve_bond = [&](int b, void* X, int ml, int mr, zc step) {
+  // X (ml x mr) pairs the bond basis of L[b] (charges qa) with that of Rt[b]
+  // (charges qb): one of them is the basis before the gauge move
+  auto evolve_bond = [&](int b, void* X, int ml, int mr, zc step, const std::vector<int>* qa,
+                         const std::vector<int>* qb) {
     // K_eff on bond b with L[b] (ml x w x ml) and Rt[b] (w x mr x mr)
     const int w = H.w(b);
     const long long n = (long long)ml * mr;
     W.ws1.ensure((size_t)ml * w * mr * cb);
     const SplitWS sk = W.split(ml, mr, cb);
+    ProdMaps pm;
+    if (sym) {
+      KMapHost g1, g2;
+      kmap_keff(*qa, *qb, qw[b], g1, g2);
+      pm = kmap.set(ctx, g1, g2);
+    }
     auto mv = [&](const void* in, void* out) {
       if (sizeof(T) == 8) {
-        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, in, out, W.ws1.p, sk);
+        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, in, out, W.ws1.p, sk, pm);
       } else {
         W.xf.ensure((size_t)n * 8);
         W.yf.ensure((size_t)n * 8);
         kern::z2c(ctx->stream, W.xf.p, in, n);
-        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, W.xf.p, W.yf.p, W.ws1.p, sk);
+        keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, W.xf.p, W.yf.p, W.ws1.p, sk, pm);
         kern::c2z(ctx->stream, out, W.yf.p, n);
       }
     };
@@ -851,14 +960,15 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
   for (int i = 0; i + 1 < N; ++i) {
     evolve_site(i, half);
     const int ml = psi.m[i], mr = psi.m[i + 1];
-    std::vector<int> qk;
+    std::vector<int> qk, qold;
+    if (sym) qold = psi.q[i + 1];
     const int k = split_left(W, psi.site(i), ml, mr, p.eps, cap, A, Rm, &st.discarded,
                              psi.u1() ? &psi.q[i] : nullptr, psi.u1() ? &psi.q[i + 1] : nullptr, &qk);
     std::swap(psi.t[i], A);
     psi.m[i + 1] = k;  // site i is now ml x 2 x k; Rm is k x mr
     if (psi.u1()) psi.q[i + 1] = qk;
     build_L(i);
-    evolve_bond(i + 1, Rm.p, k, mr, -half);
+    evolve_bond(i + 1, Rm.p, k, mr, -half, &qk, &qold);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, k, 2 * psi.m[i + 2], mr, Rm.p, mr, psi.site(i + 1), 2LL * psi.m[i + 2], nxt);
     std::swap(psi.t[i + 1], nxt);
   }
@@ -867,14 +977,15 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
   for (int i = N - 1; i >= 1; --i) {
     if (i < N - 1) evolve_site(i, half);
     const int ml = psi.m[i], mr = psi.m[i + 1];
-    std::vector<int> qk;
+    std::vector<int> qk, qold;
+    if (sym) qold = psi.q[i];
     const int k = split_right(W, psi.site(i), ml, mr, p.eps, cap, Rm, A, &st.discarded,
                               psi.u1() ? &psi.q[i] : nullptr, psi.u1() ? &psi.q[i + 1] : nullptr, &qk);
     std::swap(psi.t[i], A);
     psi.m[i] = k;  // site i is now k x 2 x mr; Rm (the L factor) is ml x k
     if (psi.u1()) psi.q[i] = qk;
     build_R(i);
-    evolve_bond(i, Rm.p, ml, k, -half);
+    evolve_bond(i, Rm.p, ml, k, -half, &qold, &qk);
     zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], k, ml, psi.site(i - 1), ml, Rm.p, k, nxt);
     std::swap(psi.t[i - 1], nxt);
   }
@@ -1236,24 +1347,32 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
 
 // Lout[b',(be,b)] = sum conj(bra[a',s',b']) L[(a',al),a] W[al,be,s',s] ket[a,s,b]
 void fit_env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
-                  const void* L, const void* bra, const void* ket, void* Lout, DBuf& f1, DBuf& f2) {
+                  const void* L, const void* bra, const void* ket, void* Lout, DBuf& f1, DBuf& f2, ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
   f1.ensure((size_t)mlo * wl * 2 * mri * ZB);
   f2.ensure((size_t)mlo * 2 * wr * mri * ZB);
   // T1[(a',al),(s,b)] = L[(a',al),a] ket[a,(s,b)]
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 2 * mri, mli, 1.0, L, mli, 0, ket, 2LL * mri, 0, 0.0, f1.p,
-                     2LL * mri, 0, 1);
+  if (pm.g1) {   // with charges: batched over al
+    kern::KMapScope ks(pm.g1);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo, 2 * mri, mli, 1.0, L, (long long)wl * mli, mli, ket, 2LL * mri, 0,
+                       0.0, f1.p, (long long)wl * 2 * mri, 2LL * mri, wl);
+  } else {
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 2 * mri, mli, 1.0, L, mli, 0, ket, 2LL * mri, 0, 0.0, f1.p,
+                       2LL * mri, 0, 1);
+  }
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
   kern::wapply<double>(s, tb.F, f1.p, f2.p, mlo, mri, (long long)wl * 2 * mri, 1, 2LL * mri, mri,
                        2LL * wr * mri, 1, mri, (long long)wr * mri);
   // Lout[b',(be,b)] = sum_{(a',s')} conj(bra[(a',s'),b']) T2[(a',s'),(be,b)]
+  kern::KMapScope ks(pm.g2);
   kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mro, wr * mri, 2 * mlo, 1.0, bra, mro, 0, f2.p, (long long)wr * mri, 0,
                      0.0, Lout, (long long)wr * mri, 0, 1);
 }
 
 // Rout[al][a,a'] = sum conj(bra[a',s',b']) W[al,be,s',s] Rt[be][b,b'] ket[a,s,b]
 void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
-                   const void* Rt, const void* bra, const void* ket, void* Rout, DBuf& f1, DBuf& f2) {
+                   const void* Rt, const void* bra, const void* ket, void* Rout, DBuf& f1, DBuf& f2,
+                   ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
   f1.ensure((size_t)wr * 2 * mli * mro * ZB);
   f2.ensure((size_t)wl * 2 * mli * mro * ZB);
@@ -1264,6 +1383,7 @@ void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int 
   kern::wapply<double>(s, tb.B, f1.p, f2.p, mli, mro, 2LL * mro, 1, 2LL * mli * mro, mro, 2LL * mro, 1,
                        2LL * mli * mro, mro);
   // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(bra[a',(s',b')])
+  kern::KMapScope ks(pm.g2);
   kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, wl * mli, mlo, 2 * mro, 1.0, f2.p, 2LL * mro, 0, bra, 2LL * mro, 0, 0.0,
                      Rout, mlo, 0, 1);
 }
@@ -1271,24 +1391,36 @@ void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int 
 // Y[(a',t),(u,b')] = sum L[(a',al),a] W1[al,be,t,s] W2[be,ga,u,v] P[a,s,v,b] Rt[ga][b,b']:
 // the two-site tensor of phi that is closest to O|psi> in the current bases.
 void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int mlo, int mli, int wl, int wm, int wr,
-                int mri, int mro, const void* L, const void* Rt, const void* P, void* Y, DBuf& f1, DBuf& f2) {
+                int mri, int mro, const void* L, const void* Rt, const void* P, void* Y, DBuf& f1, DBuf& f2,
+                ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
   const long long big = std::max({(long long)mlo * wl * 4 * mri, (long long)mlo * 2 * wm * 2 * mri,
                                   (long long)mlo * 2 * 2 * wr * mri});
   f1.ensure((size_t)big * ZB);
   f2.ensure((size_t)big * ZB);
   // T1[(a',al),(s,v,b)] = L[(a',al),a] P[a,(s,v,b)]
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 4 * mri, mli, 1.0, L, mli, 0, P, 4LL * mri, 0, 0.0, f1.p,
-                     4LL * mri, 0, 1);
+  if (pm.g1) {   // with charges: batched over al
+    kern::KMapScope ks(pm.g1);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo, 4 * mri, mli, 1.0, L, (long long)wl * mli, mli, P, 4LL * mri, 0,
+                       0.0, f1.p, (long long)wl * 4 * mri, 4LL * mri, wl);
+  } else {
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 4 * mri, mli, 1.0, L, mli, 0, P, 4LL * mri, 0, 0.0, f1.p,
+                       4LL * mri, 0, 1);
+  }
   // T2[a',t,be,(v,b)] = sum W1[al,be,t,s] T1[a',al,s,(v,b)]
   kern::wapply<double>(s, t1.F, f1.p, f2.p, mlo, 2LL * mri, (long long)wl * 4 * mri, 1, 4LL * mri, 2LL * mri,
                        (long long)2 * wm * 2 * mri, 1, 2LL * mri, (long long)wm * 2 * mri);
   // T3[(a',t),u,ga,b] = sum W2[be,ga,u,v] T2[(a',t),be,v,b]
   kern::wapply<double>(s, t2.F, f2.p, f1.p, 2LL * mlo, mri, (long long)wm * 2 * mri, 1, 2LL * mri, mri,
                        (long long)2 * wr * mri, 1, mri, (long long)wr * mri);
-  // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b']
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 4 * mlo, mro, wr * mri, 1.0, f1.p, (long long)wr * mri, 0, Rt, mro, 0,
-                     0.0, Y, mro, 0, 1);
+  // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b'] (with charges: batched over (t, u))
+  kern::KMapScope ks(pm.g2);
+  if (pm.g2)
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo, mro, wr * mri, 1.0, f1.p, 4LL * wr * mri, (long long)wr * mri, Rt,
+                       mro, 0, 0.0, Y, 4LL * mro, mro, 4);
+  else
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 4 * mlo, mro, wr * mri, 1.0, f1.p, (long long)wr * mri, 0, Rt, mro, 0,
+                       0.0, Y, mro, 0, 1);
 }
 
 // out = normalise(fit of O|in>): `passes` alternating two-site passes from
@@ -1325,10 +1457,33 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   set_one(ctx, Ls[0], ZB);
   set_one(ctx, Rs[N], ZB);
   DBuf f1(ctx), f2(ctx), P(ctx), Th(ctx), X(ctx), Y(ctx);
+  // with charges, the products walk their nonzero blocks
+  const auto& qw = op.host.qw;
+  PairMaps fm(ctx);
+  auto right_maps = [&](int i) -> ProdMaps {   // Rs[i] from site i
+    if (!sym) return {};
+    KMapHost g3;
+    kmap_env_right_gemm3(in.q[i], qw[i], out.q[i + 1], out.q[i], g3);
+    fm.g2.set(ctx, g3);
+    return ProdMaps{nullptr, fm.g2.get(), -1.0};
+  };
+  auto left_maps = [&](int i) -> ProdMaps {    // Ls[i+1] from site i
+    if (!sym) return {};
+    KMapHost g1, g2;
+    kmap_env_gemm1(out.q[i], in.q[i], qw[i], in.q[i + 1], g1);
+    kmap_env_left_gemm2(out.q[i], out.q[i + 1], in.q[i + 1], qw[i + 1], g2);
+    return fm.set(ctx, g1, g2);
+  };
+  auto local_maps = [&](int i) -> ProdMaps {   // the two-site tensor at (i, i+1)
+    if (!sym) return {};
+    KMapHost g1, g2;
+    kmap_two_site(out.q[i], in.q[i], qw[i], in.q[i + 2], qw[i + 2], out.q[i + 2], g1, g2);
+    return fm.set(ctx, g1, g2);
+  };
   for (int i = N - 1; i >= 2; --i) {
     Rs[i].ensure((size_t)op.w(i) * in.m[i] * out.m[i] * ZB);
     fit_env_right(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1], Rs[i + 1].p,
-                  out.site(i), in.site(i), Rs[i].p, f1, f2);
+                  out.site(i), in.site(i), Rs[i].p, f1, f2, right_maps(i));
   }
   // two-site tensor of phi at (i, i+1) from the current environments
   auto local = [&](int i) {
@@ -1338,7 +1493,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
                        2LL * mri, 0, 0.0, P.p, 2LL * mri, 0, 1);
     Th.ensure((size_t)mlo * 4 * mro * ZB);
     fit_local2(ctx, op.tab[i], op.tab[i + 1], mlo, mli, op.w(i), op.w(i + 1), op.w(i + 2), mri, mro, Ls[i].p,
-               Rs[i + 2].p, P.p, Th.p, f1, f2);
+               Rs[i + 2].p, P.p, Th.p, f1, f2, local_maps(i));
   };
   double disc = 0.0;
   for (int pass = 0; pass < passes; ++pass) {
@@ -1357,7 +1512,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
         if (sym) out.q[i + 1] = qk;
         Ls[i + 1].ensure((size_t)k * op.w(i + 1) * in.m[i + 1] * ZB);
         fit_env_left(ctx, op.tab[i], mlo, in.m[i], op.w(i), op.w(i + 1), k, in.m[i + 1], Ls[i].p, out.site(i),
-                     in.site(i), Ls[i + 1].p, f1, f2);
+                     in.site(i), Ls[i + 1].p, f1, f2, left_maps(i));
       }
     } else {               // right to left: phi_{i+1} right-canonical
       for (int i = N - 2; i >= 0; --i) {
@@ -1373,7 +1528,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
         if (sym) out.q[i + 1] = qk;
         Rs[i + 1].ensure((size_t)op.w(i + 1) * in.m[i + 1] * k * ZB);
         fit_env_right(ctx, op.tab[i + 1], k, in.m[i + 1], op.w(i + 1), op.w(i + 2), mro, in.m[i + 2], Rs[i + 2].p,
-                      out.site(i + 1), in.site(i + 1), Rs[i + 1].p, f1, f2);
+                      out.site(i + 1), in.site(i + 1), Rs[i + 1].p, f1, f2, right_maps(i + 1));
       }
     }
   }
@@ -1448,30 +1603,28 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
         sort_rows_by_charge(W, Vh.p, D, ml, nullptr, qv);
         qB = qv;
       }
-    } else if (!sym) {
-      la::svd_rowmajor(ctx, C, ml, D, nullptr, S, Vh.p, W.work, W.work2);
-      if (!S.empty() && S[0] > 0.0)
-        for (double v : S) r += (v * v > 1e-14 * S[0] * S[0]) ? 1 : 0;
-    } else {
-      // per charge; the rows above the floor (relative to the largest
-      // singular value of all charges) are gathered in charge order
-      la::svd_sectors(ctx, C, ml, D, psi.q[i], qD, S, Vh.p, qv);
-      double smax = 0.0;
-      for (double v : S) smax = std::max(smax, v);
-      std::vector<int> keep;
-      for (int j = 0; j < (int)S.size(); ++j)
-        if (smax > 0.0 && S[j] * S[j] > 1e-14 * smax * smax) {
-          keep.push_back(j);
-          qB.push_back(qv[j]);
-        }
-      r = (int)keep.size();
-      if (r > 0) {
-        W.pidx.ensure(sizeof(int) * r);
-        upload(ctx, W.pidx.p, keep.data(), sizeof(int) * r);
-        W.prow.ensure((size_t)r * D * ZB);
-        kern::zgather(s, W.prow.p, D, Vh.p, D, W.pidx.as<int>(), r, nullptr, D);
-        HIP_CHECK(hipMemcpyAsync(Vh.p, W.prow.p, (size_t)r * D * ZB, hipMemcpyDeviceToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));   // `keep` is pageable host memory
+    } else if (!S.empty() && S[0] > 0.0) {
+      // Weights spread over more than ten decades: the directions above the
+      // floor are those with lambda > 1e-14 lambda_1, which the Gram
+      // eigenvalues resolve (their error is ~1e-16 lambda_1).  The rows
+      // S^-1/2 U^dagger C of the small weights carry eigenvector errors up
+      // to ~1e-2, which two Cholesky-QR steps remove while keeping their
+      // span; the part of C outside that span is below 1e-18 of its weight.
+      for (double v : S) r += (v > 1e-14 * S[0]) ? 1 : 0;
+      W.tmpC.ensure((size_t)r * D * ZB);
+      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, r, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
+      kern::zscale_rows(s, W.tmpC.p, D, W.tmpC.p, D, r, D, inv_sqrt_weights(W, S, r));
+      W.tmpA.ensure((size_t)r * r * ZB);
+      if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, r, D, W.tmpA.p, Vh.p, W.work)) {
+        HIP_CHECK(hipMemcpyAsync(Vh.p, W.tmpC.p, (size_t)r * D * ZB, hipMemcpyDeviceToDevice, s));
+        ns_rows(W, Vh.p, r, D, 6);
+        if (!(la::orth_defect(ctx, Vh.p, r, D, true, W.work) <= 1e-20))
+          TDVP_THROW(TDVP_ERR_NUMERIC, "extension: no orthonormal basis of the row space");
+      }
+      if (sym) {
+        qv.resize(r);
+        sort_rows_by_charge(W, Vh.p, D, r, nullptr, qv);
+        qB = qv;
       }
     }
     const int cap = std::min(chi_max - r, D - r);

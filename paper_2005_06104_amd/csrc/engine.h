@@ -100,6 +100,51 @@ struct MatvecTimer {
   }
 };
 
+// ------------------------------------------------ block-sparse product maps
+// (blocks.cpp).  rq[m]: the charge row m of op(A) needs on the summed index,
+// kq[k]: the charge of summed index k, cq[n]: the charge column n of op(B)
+// needs on it.
+struct KMapHost {
+  std::vector<int> off, iv;
+  double exact_macs = 0.0, tile_macs = 0.0;   // nonzero multiply-adds; those the tiles perform
+  int M = 0, N = 0, K = 0, batch = 1;
+};
+void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out);
+// a map on the device
+struct DevKMap {
+  DBuf buf;
+  kern::KMap map;
+  double exact_flops = 0.0, tile_flops = 0.0;
+  explicit DevKMap(tdvp_ctx_s* c) : buf(c) {}
+  void set(tdvp_ctx_s* ctx, const KMapHost& h);
+  const kern::KMap* get() const { return map.off ? &map : nullptr; }
+};
+// the maps of the contractions (bra bonds qlo, qro; ket bonds qli, qri; MPO
+// channels qwl, qwr; equal bra and ket for the effective Hamiltonians).  The
+// first products of H_eff, K_eff, the left environments and the two-site
+// tensors, and the second of H_eff and the two-site tensor, are batched
+// (over the MPO channel, over the physical indices) so that each tile meets
+// one charge; the contractions issue them batched when given a map.
+void kmap_env_gemm1(const std::vector<int>& qlo, const std::vector<int>& qli, const std::vector<int>& qwl,
+                    const std::vector<int>& qri, KMapHost& out);
+void kmap_heff_gemm2(const std::vector<int>& qlo, const std::vector<int>& qri, const std::vector<int>& qwr,
+                     const std::vector<int>& qro, KMapHost& out);
+void kmap_env_left_gemm2(const std::vector<int>& qlo, const std::vector<int>& qro, const std::vector<int>& qri,
+                         const std::vector<int>& qwr, KMapHost& out);
+void kmap_env_right_gemm3(const std::vector<int>& qli, const std::vector<int>& qwl, const std::vector<int>& qro,
+                          const std::vector<int>& qlo, KMapHost& out);
+void kmap_keff(const std::vector<int>& ql, const std::vector<int>& qr, const std::vector<int>& qw, KMapHost& g1,
+               KMapHost& g2);
+void kmap_two_site(const std::vector<int>& qlo, const std::vector<int>& qli, const std::vector<int>& qwl,
+                   const std::vector<int>& qri, const std::vector<int>& qwr, const std::vector<int>& qro,
+                   KMapHost& g1, KMapHost& g2);
+// the maps of a contraction's products (null: dense)
+struct ProdMaps {
+  const kern::KMap* g1 = nullptr;
+  const kern::KMap* g2 = nullptr;
+  double flops = -1.0;   // nonzero flops of the two products (negative: dense count)
+};
+
 // kernel-level helpers used by the C-ABI
 // Split-K scratch for the contractions (may be empty: no K splitting).
 struct SplitWS {
@@ -110,16 +155,16 @@ struct SplitWS {
 template <typename T>
 void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
                 const void* Rt, const void* C, void* Y, void* ws1, void* ws2, MatvecTimer* tm = nullptr,
-                SplitWS sk = {});
+                SplitWS sk = {}, ProdMaps pm = {});
 template <typename T>
 void keff_apply(tdvp_ctx_s* ctx, int ml, int w, int mr, const void* L, const void* Rt, const void* X, void* Y,
-                void* ws1, SplitWS sk = {});
+                void* ws1, SplitWS sk = {}, ProdMaps pm = {});
 template <typename T>
 void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* L,
-              const void* A, void* Lout, void* ws1, void* ws2, SplitWS sk = {});
+              const void* A, void* Lout, void* ws1, void* ws2, SplitWS sk = {}, ProdMaps pm = {});
 template <typename T>
 void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int mr, const void* Rt,
-               const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk = {});
+               const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk = {}, ProdMaps pm = {});
 // CSR tables for a single host W (kernel-level calls); keeps the device copy in `buf`
 SiteTables upload_tables(tdvp_ctx_s* ctx, const std::vector<zc>& W, int wl, int wr, DBuf& buf);
 // The same tables written into caller-provided device memory (cap bytes at

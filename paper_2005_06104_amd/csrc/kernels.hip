@@ -47,12 +47,39 @@ template <typename T> constexpr int gemm_threads() { return WaveGrid<T>::WM * Wa
 // its own so that profilers and timers see it apart from the other GEMMs).
 // Split-K: blockIdx.z = batch * S + split; split s covers k in
 // [s*Kc, min(K, (s+1)*Kc)) and writes its partial product at C + s*sps.
+// Block-sparse products (operands with U(1) charges): koff/kiv list, for
+// every output tile (batch outer, then row-major tile order) the K intervals
+// [x, y) it needs (kiv[koff[t] .. koff[t+1])); koff null: the whole K range
+// (or one split-K part).  A tile with no interval writes alpha * 0 + beta * C.
+struct KIter {
+  const int2* iv;
+  int n;
+  int2 one;
+  __device__ int2 at(int v) const { return iv ? iv[v] : one; }
+};
+
+__device__ inline KIter tile_k_range(const int* __restrict__ koff, const int2* __restrict__ kiv, unsigned trem,
+                                     int kb, int ke) {
+  KIter r;
+  r.one = make_int2(kb, ke);
+  if (koff) {
+    const int a = koff[trem], b = koff[trem + 1];
+    r.iv = kiv + a;
+    r.n = b - a;
+  } else {
+    r.iv = nullptr;
+    r.n = kb < ke ? 1 : 0;
+  }
+  return r;
+}
+
 template <typename T, bool TA, bool CA, bool TB, bool CB, int TAG>
 __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, int K, T ar, T ai, const T* __restrict__ A,
                                                    long long lda, long long sa, const T* __restrict__ B,
                                                    long long ldb, long long sb, T br, T bi,
                                                    T* __restrict__ C, long long ldc, long long sc, int S, int Kc,
-                                                   long long sps) {
+                                                   long long sps, const int* __restrict__ koff,
+                                                   const int2* __restrict__ kiv) {
   using c2 = typename VT<T>::c2;
   using acc_t = typename VT<T>::acc;
   __shared__ T As_r[2][BK][BM + PAD], As_i[2][BK][BM + PAD];
@@ -85,7 +112,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
   constexpr int PER = (BM * BK) / NTH;  // complex elements per thread per operand
   c2 ra[PER], rb[PER];
 
-  auto load = [&](int k0) {
+  auto load = [&](int k0, int kend) {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
       const int idx = tid + it * NTH;
@@ -94,7 +121,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       const int gm = m0 + m, gk = k0 + k;
       c2 v;
       v.x = T(0); v.y = T(0);
-      if (gm < M && gk < ke) v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
+      if (gm < M && gk < kend) v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
       if (CA) v.y = -v.y;
       ra[it] = v;
     }
@@ -106,7 +133,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       const int gn = n0 + n, gk = k0 + k;
       c2 v;
       v.x = T(0); v.y = T(0);
-      if (gn < N && gk < ke) v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
+      if (gn < N && gk < kend) v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
       if (CB) v.y = -v.y;
       rb[it] = v;
     }
@@ -141,14 +168,31 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
 
   const int lr = lane & 15, lk = lane >> 4;
   // double-buffered LDS: compute on `cur` while the next tile's global loads
-  // are in flight, then store them into the other buffer; one barrier per tile
-  load(kb);
-  store(0);
+  // are in flight, then store them into the other buffer; one barrier per
+  // tile.  The K steps walk the tile's intervals in order.
+  const KIter kr_ = tile_k_range(koff, kiv, (unsigned)(bz * gx * gy) + trem, kb, ke);
+  int iv = 0, k0 = 0, kend = 0;
+  if (kr_.n > 0) {
+    const int2 I0 = kr_.at(0);
+    k0 = I0.x;
+    kend = I0.y;
+    load(k0, kend);
+    store(0);
+  }
   __syncthreads();
   int cur = 0;
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    const bool more = (k0 + BK) < ke;
-    if (more) load(k0 + BK);
+  for (bool go = kr_.n > 0; go;) {
+    int nk0 = k0 + BK, nkend = kend, niv = iv;
+    if (nk0 >= kend) {
+      ++niv;
+      if (niv < kr_.n) {
+        const int2 J = kr_.at(niv);
+        nk0 = J.x;
+        nkend = J.y;
+      }
+    }
+    const bool more = niv < kr_.n;
+    if (more) load(nk0, nkend);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
@@ -177,6 +221,10 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
     if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
+    go = more;
+    iv = niv;
+    k0 = nk0;
+    kend = nkend;
   }
 
   const bool has_beta = (br != T(0)) || (bi != T(0));
@@ -294,7 +342,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
                                                         const float* __restrict__ A, long long lda, long long sa,
                                                         const float* __restrict__ B, long long ldb, long long sb,
                                                         float br, float bi, float* __restrict__ C, long long ldc,
-                                                        long long sc, int S, int Kc, long long sps) {
+                                                        long long sc, int S, int Kc, long long sps,
+                                                        const int* __restrict__ koff, const int2* __restrict__ kiv) {
   constexpr int NPL = SPLIT ? 4 : 2;
   __shared__ __attribute__((aligned(16))) unsigned short As[2][NPL * PL2];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPL * PL2];
@@ -320,9 +369,9 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
   // A tile rows are m (k contiguous when A is not transposed); B tile rows
   // are n (k contiguous when B is transposed)
   float2 va[2][4], vb[2][4];
-  auto load = [&](int k0) {
-    bf_load<!TA, CA>(Ab, lda, m0, M, k0, ke, tid, va);
-    bf_load<TB, CB>(Bb, ldb, n0, N, k0, ke, tid, vb);
+  auto load = [&](int k0, int kend) {
+    bf_load<!TA, CA>(Ab, lda, m0, M, k0, kend, tid, va);
+    bf_load<TB, CB>(Bb, ldb, n0, N, k0, kend, tid, vb);
   };
   auto store = [&](int buf) {
     bf_store<!TA, SPLIT>(As[buf], tid, va);
@@ -339,13 +388,29 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     }
 
   const int lr = lane & 15, lk = lane >> 4;
-  load(kb);
-  store(0);
+  const KIter kr_ = tile_k_range(koff, kiv, (unsigned)(bz * gx * gy) + trem, kb, ke);
+  int iv = 0, k0 = 0, kend = 0;
+  if (kr_.n > 0) {
+    const int2 I0 = kr_.at(0);
+    k0 = I0.x;
+    kend = I0.y;
+    load(k0, kend);
+    store(0);
+  }
   __syncthreads();
   int cur = 0;
-  for (int k0 = kb; k0 < ke; k0 += BK2) {
-    const bool more = (k0 + BK2) < ke;
-    if (more) load(k0 + BK2);
+  for (bool go = kr_.n > 0; go;) {
+    int nk0 = k0 + BK2, nkend = kend, niv = iv;
+    if (nk0 >= kend) {
+      ++niv;
+      if (niv < kr_.n) {
+        const int2 J = kr_.at(niv);
+        nk0 = J.x;
+        nkend = J.y;
+      }
+    }
+    const bool more = niv < kr_.n;
+    if (more) load(nk0, nkend);
     const unsigned short* Ap = As[cur];
     const unsigned short* Bp = Bs[cur];
     uint4 a_hr[2], a_hi[2], a_lr[2], a_li[2], b_hr[2], b_hi[2], b_hn[2], b_lr[2], b_li[2], b_ln[2];
@@ -393,6 +458,10 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
+    go = more;
+    iv = niv;
+    k0 = nk0;
+    kend = nkend;
   }
 
   const bool has_beta = (br != 0.f) || (bi != 0.f);
@@ -463,16 +532,19 @@ inline int choose_splits(int M, int N, int K, int batch, size_t ws_bytes, size_t
 // 0 FP32 MFMA, 1 BF16 MFMA, 2 three-term BF16 split (see gemm_bf16_kernel).
 thread_local int tl_float_mode = 0;
 
+// block-sparse map of the next product issued from the calling host thread
+thread_local const kern::KMap* tl_kmap = nullptr;
+
 template <typename T, int MODE, bool TA, bool CA, bool TB, bool CB, int TAG>
 void launch_tiles(dim3 grid, hipStream_t s, int M, int N, int K, T ar, T ai, const T* A, long long lda,
                   long long sa, const T* B, long long ldb, long long sb, T br, T bi, T* C, long long ldc,
-                  long long sc, int S, int Kc, long long sps) {
+                  long long sc, int S, int Kc, long long sps, const int* koff = nullptr, const int2* kiv = nullptr) {
   if constexpr (MODE == 0) {
     hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(gemm_threads<T>()), 0, s, M, N, K, ar, ai, A,
-                       lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
+                       lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps, koff, kiv);
   } else {
     hipLaunchKernelGGL((gemm_bf16_kernel<MODE - 1, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, ar, ai,
-                       A, lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps);
+                       A, lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps, koff, kiv);
   }
 }
 
@@ -485,6 +557,15 @@ void launch_gemm_mode(hipStream_t s, int M, int N, int K, zc alpha, const void* 
   constexpr int KSTEP = MODE == 0 ? BK : BK2;
   const T* a = static_cast<const T*>(A);
   const T* b = static_cast<const T*>(B);
+  const kern::KMap* km = tl_kmap;
+  if (km && km->batch == batch) {
+    if (km->M != M || km->N != N || km->K != K) TDVP_THROW(TDVP_ERR_ARG, "block-sparse map does not fit the product");
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+    launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(alpha.real()), T(alpha.imag()), a, lda, sa, b,
+                                               ldb, sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc,
+                                               sc, 1, std::max(K, 1), 0LL, km->off, reinterpret_cast<const int2*>(km->iv));
+    return;
+  }
   const int S = choose_splits(M, N, K, batch, ws_bytes, sizeof(typename VT<T>::c2));
   if (S == 1) {
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
@@ -957,6 +1038,9 @@ void set_float_mode(int mode) {
 }
 int float_mode() { return tl_float_mode; }
 
+void set_kmap(const KMap* k) { tl_kmap = k; }
+const KMap* current_kmap() { return tl_kmap; }
+
 thread_local void* tl_split_ws = nullptr;
 thread_local size_t tl_split_wsb = 0;
 void set_split_workspace(void* p, size_t bytes) {
@@ -1000,6 +1084,18 @@ template void gemm_heff<double>(hipStream_t, int, int, int, const void*, long lo
                                 long long, void*, size_t);
 template void gemm_heff<float>(hipStream_t, int, int, int, const void*, long long, const void*, long long, void*,
                                long long, void*, size_t);
+
+template <typename T>
+void gemm_heff_batched(hipStream_t s, int M, int N, int K, const void* A, long long lda, long long sa, const void* B,
+                       long long ldb, long long sb, void* C, long long ldc, long long sc, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  launch_gemm<T, TDVP_OP_N, TDVP_OP_N, 1>(s, M, N, K, 1.0, A, lda, sa, B, ldb, sb, 0.0, C, ldc, sc, batch);
+  HIP_CHECK(hipGetLastError());
+}
+template void gemm_heff_batched<double>(hipStream_t, int, int, int, const void*, long long, long long, const void*,
+                                        long long, long long, void*, long long, long long, int);
+template void gemm_heff_batched<float>(hipStream_t, int, int, int, const void*, long long, long long, const void*,
+                                       long long, long long, void*, long long, long long, int);
 
 template <typename T>
 void gemm_nn_ws(hipStream_t s, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,
