@@ -535,12 +535,14 @@ def cylinder_mode(args):
     log(f"workload {w.name} (charges): N={N}, w={max(H.dims)}, chi_max={chi}, k={w.k}, dt={w.dt}")
     t_prep = time.perf_counter()
     prep_steps = 0
+    prep_elapsed = []    # cumulative time after each preparation step
     while prep_steps < 30:
         T.tdvp_expand_basis(ctx, [g], [op], w.k, w.eps_K, w.eps_M, chi, "fp32", apply="fit", fit_passes=passes)
         T.tdvp_sweep(ctx, [g], [H], w.dt, w.eps, chi, 1e-12, 30, "fp32", False)
         prep_steps += 1
         mb = max(g.bond_dims())
-        log(f"[prepare] step {prep_steps}: max bond {mb} ({time.perf_counter() - t_prep:.1f} s)")
+        prep_elapsed.append(time.perf_counter() - t_prep)
+        log(f"[prepare] step {prep_steps}: max bond {mb} ({prep_elapsed[-1]:.1f} s)")
         if mb >= chi:
             break
     snap, snapq = T.tdvp_mps_to_host(g), T.tdvp_mps_charges(g)
@@ -638,8 +640,13 @@ def cylinder_mode(args):
         del alt
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle for up to {args.cpu_seconds:.0f} s ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, chi)
-        out["cpu_baseline"]["sample"] += " (dense tensors: the oracle has no charges)"
+        cb = cpu_baseline(w, args.cpu_seconds, chi)
+        cb["sample"] += " (dense tensors: the oracle has no charges)"
+        n = cb["steps_timed"]
+        if 0 < n <= len(prep_elapsed):
+            # the device on the same sample: the first n preparation steps (FP32, charges)
+            cb["gpu_steps_per_s_same_sample"] = n / prep_elapsed[n - 1]
+        out["cpu_baseline"] = cb
     del main_run, ref_run
     ctx.close()
     print(json.dumps(out), flush=True)
