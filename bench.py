@@ -556,9 +556,13 @@ def cylinder_mode(args):
         acc = {"ms_heff_gemm": 0.0, "flops_heff_gemm": 0.0, "n_heff_gemm": 0, "ms_matvec": 0.0,
                "flops_matvec": 0.0, "n_matvec": 0, "ms_sweep": 0.0, "ms_krylov": 0.0, "ms_extend": 0.0}
         t0 = None
+        mark = args.mark_timed and p == prec
         for i in range(args.warmup + args.steps):
             if i == args.warmup:
                 torch.cuda.synchronize()
+                if mark:   # a kernel trace is cut to the dispatches between the two marks
+                    torch.cuda._sleep(1000)
+                    torch.cuda.synchronize()
                 t0 = time.perf_counter()
             ts = time.perf_counter()
             e = T.tdvp_expand_basis(ctx, [psi], [op], w.k, w.eps_K, w.eps_M, chi, p, apply="fit",
@@ -576,12 +580,15 @@ def cylinder_mode(args):
                 f"max bond {max(m['bond_dims'])}, E={m['energy']:.10f}")
         torch.cuda.synchronize()
         acc["elapsed"] = time.perf_counter() - (t0 if t0 is not None else time.perf_counter())
+        if mark:
+            torch.cuda._sleep(1000)
+            torch.cuda.synchronize()
         acc["final"] = T.tdvp_measure(ctx, [psi], [H])[0]
         acc["H"], acc["psi"] = H, psi
         return acc
 
     # the FP64 run is the reference every mixed run is compared with
-    ref_run = run("fp64") if prec != "fp64" else None
+    ref_run = run("fp64") if prec != "fp64" and args.fp64_ref else None
     main_run = run(prec)
     res = summarize(main_run, args.steps, prec)
     gemm_tf = res["heff_gemm_tflops"]
@@ -665,6 +672,11 @@ def main():
                          "(default: fp32,bf16x3,bf16 after fp64; fp64 after a mixed precision)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-ref", dest="fp64_ref", action="store_false",
+                    help="cylinder: skip the FP64 reference run (no fidelity or speedup figures)")
+    ap.add_argument("--mark-timed", action="store_true",
+                    help="cylinder: launch a short marker kernel (torch.cuda._sleep) right before and after "
+                         "the headline precision's timed steps, for cutting a kernel trace")
     ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
                     help="skip the runs in the other precisions (mixed vs FP64)")
     ap.add_argument("--batch", action="store_true",

@@ -96,20 +96,89 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
   out.K = K;
 }
 
+// A tile's K work is cut into parts when the nonempty tiles give fewer
+// than SPLIT_MIN_TILES workgroups: parts of about equal length (a multiple
+// of the K step, at least SPLIT_MIN_K) so that about SPLIT_TARGET parts are
+// nonempty, at most SPLIT_MAX per tile.  Long-K products with charges (the
+// second product of the effective Hamiltonian: 2 x 16 x 16 tiles at a bond
+// of 1024, a third of them nonempty, with 2000-11000 of K each) would
+// otherwise leave most compute units idle.
+void split_kmap(KMapHost& h) {
+  constexpr int SPLIT_MIN_TILES = 768, SPLIT_TARGET = 1024, SPLIT_MAX = 16, SPLIT_MIN_K = 256;
+  h.splits = 1;
+  h.nsplit.clear();
+  const int E = (int)h.off.size() - 1;
+  if (E <= 0 || h.batch <= 0 || E % h.batch) return;
+  std::vector<long long> klen(E, 0);
+  long long sum = 0, kmax = 0;
+  int active = 0;
+  for (int e = 0; e < E; ++e) {
+    for (int v = h.off[e]; v < h.off[e + 1]; ++v) klen[e] += h.iv[2 * v + 1] - h.iv[2 * v];
+    sum += klen[e];
+    kmax = std::max(kmax, klen[e]);
+    active += klen[e] > 0;
+  }
+  if (active >= SPLIT_MIN_TILES || kmax < 2 * SPLIT_MIN_K) return;
+  auto up = [](long long x) { return (x + GAP - 1) / GAP * GAP; };
+  long long chunk = std::max<long long>(SPLIT_MIN_K, up((sum + SPLIT_TARGET - 1) / SPLIT_TARGET));
+  long long S = (kmax + chunk - 1) / chunk;
+  if (S > SPLIT_MAX) {
+    S = SPLIT_MAX;
+    chunk = up((kmax + S - 1) / S);
+  }
+  if (S <= 1) return;
+  const int tiles = E / h.batch;
+  std::vector<int> off(1, 0), iv;
+  iv.reserve(h.iv.size() + (size_t)2 * E);
+  h.nsplit.assign(E, 0);
+  for (int b = 0; b < h.batch; ++b)
+    for (int sp = 0; sp < S; ++sp)
+      for (int t = 0; t < tiles; ++t) {
+        const int e = b * tiles + t;
+        const long long lo = sp * chunk, hi = std::min(klen[e], lo + chunk);
+        long long pos = 0;   // K entries of the tile before interval v
+        for (int v = h.off[e]; v < h.off[e + 1] && pos < hi; ++v) {
+          const int x = h.iv[2 * v], y = h.iv[2 * v + 1];
+          const long long a = std::max(lo, pos), z = std::min(hi, pos + (y - x));
+          if (a < z) {
+            iv.push_back(x + (int)(a - pos));
+            iv.push_back(x + (int)(z - pos));
+          }
+          pos += y - x;
+        }
+        off.push_back((int)(iv.size() / 2));
+        if (lo < klen[e]) h.nsplit[e] = sp + 1;
+      }
+  h.off.swap(off);
+  h.iv.swap(iv);
+  h.splits = (int)S;
+}
+
 void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
-  const size_t nb = sizeof(int) * (h.off.size() + h.iv.size());
+  const size_t nb = sizeof(int) * (h.off.size() + h.iv.size() + h.nsplit.size());
   buf.ensure(nb);
   HIP_CHECK(hipMemcpyAsync(buf.p, h.off.data(), sizeof(int) * h.off.size(), hipMemcpyHostToDevice, ctx->stream));
   if (!h.iv.empty())
     HIP_CHECK(hipMemcpyAsync(buf.as<int>() + h.off.size(), h.iv.data(), sizeof(int) * h.iv.size(),
                              hipMemcpyHostToDevice, ctx->stream));
+  if (!h.nsplit.empty())
+    HIP_CHECK(hipMemcpyAsync(buf.as<int>() + h.off.size() + h.iv.size(), h.nsplit.data(),
+                             sizeof(int) * h.nsplit.size(), hipMemcpyHostToDevice, ctx->stream));
+  map.part = nullptr;
+  map.part_bytes = 0;
+  if (h.splits > 1) {   // partial products, sized for complex128
+    map.part_bytes = (size_t)h.splits * h.batch * h.M * h.N * 16;
+    map.part = part.ensure(map.part_bytes);
+  }
   HIP_CHECK(hipStreamSynchronize(ctx->stream));   // the host vectors may die
   map.off = buf.as<int>();
   map.iv = buf.as<int>() + h.off.size();
+  map.nsplit = h.splits > 1 ? buf.as<int>() + h.off.size() + h.iv.size() : nullptr;
   map.M = h.M;
   map.N = h.N;
   map.K = h.K;
   map.batch = h.batch;
+  map.splits = h.splits;
   exact_flops = 8.0 * h.exact_macs;
   tile_flops = 8.0 * h.tile_macs;
 }
@@ -167,21 +236,25 @@ void build_batched(const std::vector<int>& qrow, const std::vector<int>& shift, 
 void kmap_env_gemm1(const std::vector<int>& qlo, const std::vector<int>& qli, const std::vector<int>& qwl,
                     const std::vector<int>& qri, KMapHost& out) {
   build_batched(qlo, qwl, -1, qli, fuse2(kPhys, qri, -1, 1), out);
+  split_kmap(out);
 }
 // H_eff: Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b'] batched over s'
 void kmap_heff_gemm2(const std::vector<int>& qlo, const std::vector<int>& qri, const std::vector<int>& qwr,
                      const std::vector<int>& qro, KMapHost& out) {
   build_batched(qlo, kPhys, 1, fuse2(qwr, qri, 1, 1), qro, out);
+  split_kmap(out);
 }
 // bra^H[b',(a',s')] T2[(a',s'),(be,b)]
 void kmap_env_left_gemm2(const std::vector<int>& qlo, const std::vector<int>& qro, const std::vector<int>& qri,
                          const std::vector<int>& qwr, KMapHost& out) {
   build_kmap(qro, fuse2(qlo, kPhys, 1, 1), fuse2(qwr, qri, 1, 1), out);
+  split_kmap(out);
 }
 // U2[(al,a),(s',b')] conj(bra[a',(s',b')])
 void kmap_env_right_gemm3(const std::vector<int>& qli, const std::vector<int>& qwl, const std::vector<int>& qro,
                           const std::vector<int>& qlo, KMapHost& out) {
   build_kmap(fuse2(qwl, qli, 1, 1), fuse2(kPhys, qro, -1, 1), qlo, out);
+  split_kmap(out);
 }
 // K_eff: L[(a',al),a] X[a,b] batched over al, then Y1[a',(al,b)] Rt[(al,b),b']
 // (a, a' on the bond basis of L, b, b' on that of Rt; X pairs equal charges)
@@ -189,6 +262,8 @@ void kmap_keff(const std::vector<int>& ql, const std::vector<int>& qr, const std
                KMapHost& g2) {
   build_batched(ql, qw, -1, ql, qr, g1);
   build_kmap(ql, fuse2(qw, qr, 1, 1), qr, g2);
+  split_kmap(g1);
+  split_kmap(g2);
 }
 // two-site: L[(a',al),a] P[a,(s,v,b)] batched over al, then
 // T3[(a',t,u),(ga,b)] Rt[(ga,b),b'] batched over (t, u)
@@ -197,4 +272,6 @@ void kmap_two_site(const std::vector<int>& qlo, const std::vector<int>& qli, con
                    KMapHost& g1, KMapHost& g2) {
   build_batched(qlo, qwl, -1, qli, fuse2(phys2(), qri, -1, 1), g1);
   build_batched(qlo, phys2(), 1, fuse2(qwr, qri, 1, 1), qro, g2);
+  split_kmap(g1);
+  split_kmap(g2);
 }

@@ -14,6 +14,10 @@
 // column steps few and short.  Every wait is bounded;
 // one that runs out makes the call report failure.  The factorisation
 // reports failure when a pivot is not positive and finite.
+// Block-diagonal matrices (the Gram matrices of charged tensors, whose
+// charge sectors are contiguous) are factorised sector by sector in the same
+// launch: each sector has its own workgroups and flags, and the blocks
+// between sectors are never read.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,15 +35,29 @@ constexpr int NPART = 64 / CB;        // lanes per row in the one-wave steps
 static_assert(CENT >= 1 && CB * CB == CENT * CNT && NPART >= 1, "tile mapping");
 constexpr int CFLAG = 16;         // one 64-byte line per flag
 constexpr unsigned CSPIN = 1u << 22;
+constexpr int CMAXSEC = 64;       // sectors per launch
+constexpr int CMAXWG = 1024;      // workgroups per launch (all co-resident)
+constexpr size_t CSEC_FLAGS = 2 * CMAXB * CMAXB * CFLAG;   // flag words per sector
 
 struct CholArgs {
-  const double2* G;   // n x n, Hermitian (the lower blocks are read)
-  double2* L;         // n x n out: the lower blocks of L (may be G)
-  double2* Li;        // n x n out: L^-1 (zero above the diagonal)
-  unsigned* fl;       // CMAXB^2 flags, zero at launch: block (i, k) of L published (k = i: with L_ii^-1)
-  unsigned* fi;       // CMAXB^2 flags, zero at launch: block (i, k) of L^-1 published (i > k)
+  const double2* G;   // ld x ld, Hermitian (the lower blocks of each sector are read)
+  double2* L;         // out: the lower blocks of L in each sector (may be G)
+  double2* Li;        // out: L^-1 in each sector (zero above the diagonal)
+  unsigned* flags;    // CSEC_FLAGS per sector, zero at launch
   int* info;          // 0 at launch; 1 not positive definite, 2 a wait ran out
-  int n, nb;
+  int ld, nsec;
+  int off[CMAXSEC], size[CMAXSEC], wg0[CMAXSEC + 1];   // sector s: rows off..off+size, workgroups wg0[s]..
+};
+
+// one sector as the workgroup sees it
+struct Sec {
+  const double2* G;
+  double2* L;
+  double2* Li;
+  unsigned* fl;       // block (i, k) of L published (k = i: with L_ii^-1)
+  unsigned* fi;       // block (i, k) of L^-1 published (i > k)
+  int* info;
+  int n, ld;
 };
 
 __device__ inline double2 cm(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
@@ -47,13 +65,13 @@ __device__ inline double2 cmc(double2 a, double2 b) {   // a * conj(b)
   return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-__device__ inline int bsize(const CholArgs& a, int i) { return min(CB, a.n - i * CB); }
+__device__ inline int bsize(const Sec& a, int i) { return min(CB, a.n - i * CB); }
 
 __device__ inline unsigned* flag_at(unsigned* f, int r, int c) { return f + (r * CMAXB + c) * CFLAG; }
 
 // wait until the flags f1 and f2 are set; false when a wait ran out or
 // another workgroup gave up
-__device__ bool wait_flags(const CholArgs& a, const unsigned* f1, const unsigned* f2, int* s_ok) {
+__device__ bool wait_flags(const Sec& a, const unsigned* f1, const unsigned* f2, int* s_ok) {
   if (threadIdx.x == 0) {
     unsigned polls = 0;
     int ok = 1;
@@ -215,13 +233,28 @@ __device__ void diag_chol_inv(double2 (*tS)[CB + 1], double2 (*tY)[CB + 1], int 
   }
 }
 
-__global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
+__global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs args) {
   __shared__ double2 tS[CB][CB + 1], tX[CB][CB + 1], tY[CB][CB + 1];
   __shared__ int s_ok, s_fail;
+  int sec = 0;
+  while (sec + 1 < args.nsec && args.wg0[sec + 1] <= (int)blockIdx.x) ++sec;
+  const int wg = (int)blockIdx.x - args.wg0[sec];
+  Sec a;
+  {
+    const size_t o = (size_t)args.off[sec] * args.ld + args.off[sec];
+    a.G = args.G + o;
+    a.L = args.L + o;
+    a.Li = args.Li + o;
+    a.fl = args.flags + sec * CSEC_FLAGS;
+    a.fi = a.fl + CMAXB * CMAXB * CFLAG;
+    a.info = args.info;
+    a.n = args.size[sec];
+    a.ld = args.ld;
+  }
   int i = 0;
-  while ((i + 1) * (i + 2) / 2 <= (int)blockIdx.x) ++i;
-  const int k = (int)blockIdx.x - i * (i + 1) / 2;
-  const int n = a.n, mi = bsize(a, i), mk = bsize(a, k), ri = i * CB, rk = k * CB;
+  while ((i + 1) * (i + 2) / 2 <= wg) ++i;
+  const int k = wg - i * (i + 1) / 2;
+  const int n = a.ld, mi = bsize(a, i), mk = bsize(a, k), ri = i * CB, rk = k * CB;
   double2 acc[CENT];
 
   // ---- S = G_ik - sum_{j<k} L_ij L_kj^H (blocks j < k are full)
@@ -294,7 +327,7 @@ __global__ __launch_bounds__(CNT) void cholinv_kernel(CholArgs a) {
 __global__ void cholinv_reset_kernel(unsigned* flags, int nf, int* info) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nf) flags[t] = 0u;
-  if (t == 0) *info = 0;
+  if (t == 0 && info) *info = 0;
 }
 
 }  // namespace
@@ -303,24 +336,55 @@ namespace kern {
 
 int cholinv_max_n() { return CB * CMAXB; }
 
-size_t cholinv_scratch_bytes() { return sizeof(unsigned) * 2 * CMAXB * CMAXB * CFLAG + 256; }
+size_t cholinv_scratch_bytes() { return sizeof(unsigned) * CSEC_FLAGS + 256; }
+
+size_t cholinv_blocks_scratch_bytes() { return sizeof(unsigned) * CSEC_FLAGS * CMAXSEC + 256; }
 
 hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int* info, void* scratch) {
-  if (n < 1 || n > CB * CMAXB || !scratch || !info) return hipErrorInvalidValue;
-  CholArgs a{};
-  a.G = static_cast<const double2*>(G);
-  a.L = static_cast<double2*>(L);
-  a.Li = static_cast<double2*>(Linv);
-  a.fl = static_cast<unsigned*>(scratch);
-  a.fi = a.fl + CMAXB * CMAXB * CFLAG;
-  a.info = info;
-  a.n = n;
-  a.nb = (n + CB - 1) / CB;
-  const int nf = 2 * CMAXB * CMAXB * CFLAG;
-  hipLaunchKernelGGL(cholinv_reset_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.fl, nf, a.info);
-  void* args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(cholinv_kernel),
-                                    dim3(a.nb * (a.nb + 1) / 2), dim3(CNT), args, 0, s);
+  const int off = 0;
+  return cholinv_blocks(s, G, n, &off, &n, 1, L, Linv, info, scratch, false);
+}
+
+hipError_t cholinv_blocks(hipStream_t s, const void* G, int ld, const int* off, const int* size, int nsec, void* L,
+                          void* Linv, int* info, void* scratch, bool keep_info) {
+  if (ld < 1 || nsec < 1 || !scratch || !info) return hipErrorInvalidValue;
+  for (int q = 0; q < nsec; ++q)
+    if (size[q] < 1 || size[q] > CB * CMAXB || off[q] < 0 || off[q] + size[q] > ld) return hipErrorInvalidValue;
+  // sectors go to launches of at most CMAXSEC sectors and CMAXWG workgroups
+  bool first = true;
+  for (int q0 = 0; q0 < nsec;) {
+    CholArgs a{};
+    a.G = static_cast<const double2*>(G);
+    a.L = static_cast<double2*>(L);
+    a.Li = static_cast<double2*>(Linv);
+    a.flags = static_cast<unsigned*>(scratch);
+    a.info = info;
+    a.ld = ld;
+    int wg = 0, q = q0;
+    while (q < nsec && a.nsec < CMAXSEC) {
+      const int nb = (size[q] + CB - 1) / CB, w = nb * (nb + 1) / 2;
+      if (a.nsec > 0 && wg + w > CMAXWG) break;
+      a.off[a.nsec] = off[q];
+      a.size[a.nsec] = size[q];
+      a.wg0[a.nsec] = wg;
+      wg += w;
+      ++a.nsec;
+      ++q;
+    }
+    a.wg0[a.nsec] = wg;
+    // flags of the sectors used; info once per call (a failure in an earlier
+    // launch stays reported) unless the caller cleared it
+    const int nf = (int)(CSEC_FLAGS * a.nsec);
+    hipLaunchKernelGGL(cholinv_reset_kernel, dim3((nf + 255) / 256), dim3(256), 0, s, a.flags, nf,
+                       first && !keep_info ? a.info : nullptr);
+    void* args[] = {&a};
+    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(cholinv_kernel), dim3(wg),
+                                                    dim3(CNT), args, 0, s);
+    if (e != hipSuccess) return e;
+    first = false;
+    q0 = q;
+  }
+  return hipSuccess;
 }
 
 }  // namespace kern

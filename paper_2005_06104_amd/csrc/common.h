@@ -155,13 +155,22 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
 // charges: for every 64 x 64 output tile (row-major tile order) the K
 // intervals it needs, iv[off[t] .. off[t+1]) as (begin, end) pairs; device
 // arrays.  While set (set_kmap / KMapScope) on the calling host thread, the
-// products of that shape (batch 1) it issues walk only those intervals; any
-// other shape is an error.
+// products of that shape and batch count it issues walk only those
+// intervals; any other shape is an error.
+// Split K (splits > 1): entry (b * splits + s) * tiles + t holds part s of
+// tile t of batch entry b; the first nsplit[b * tiles + t] parts are
+// nonempty, the rest empty.  Each part writes its partial product into
+// `part` (splits x batch x M x N complex of the product's type, at most
+// part_bytes), and one reduction sums the nonempty parts of every tile.
 struct KMap {
   const int* off = nullptr;
   const int* iv = nullptr;     // pairs
   int M = 0, N = 0, K = 0;
   int batch = 1;               // batched products: one map per batch entry, batch outer
+  int splits = 1;
+  const int* nsplit = nullptr;
+  void* part = nullptr;
+  size_t part_bytes = 0;
 };
 void set_kmap(const KMap* k);
 const KMap* current_kmap();
@@ -214,6 +223,14 @@ hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double*
 int cholinv_max_n();
 size_t cholinv_scratch_bytes();
 hipError_t cholinv(hipStream_t s, const void* G, int n, void* L, void* Linv, int* info, void* scratch);
+// The same for the nsec diagonal blocks (rows and columns off[q] ..
+// off[q] + size[q], size[q] <= cholinv_max_n()) of a ld x ld matrix, all in
+// one launch where they fit (several launches otherwise); entries outside
+// the blocks are neither read nor written.  *info is reset first unless
+// keep_info.  scratch: cholinv_blocks_scratch_bytes().
+size_t cholinv_blocks_scratch_bytes();
+hipError_t cholinv_blocks(hipStream_t s, const void* G, int ld, const int* off, const int* size, int nsec, void* L,
+                          void* Linv, int* info, void* scratch, bool keep_info = false);
 // G <- S - frac * trace(S) * I (Hermitian complex128 n x n; S null: S = G)
 void shift_by_trace(hipStream_t s, void* G, int n, double frac, const void* S = nullptr);
 // out[j][m] = Z[m][n-1-j] (complex), Z column-major real n x n
@@ -269,6 +286,8 @@ int zdots_blocks(long long n);
 // w[x] += sign * sum_j c[j] V[j*ldv + x]   (c complex128 on device)
 void zcombine(hipStream_t s, void* w, const void* V, long long ldv, int nv, const void* c,
               double sign, long long n);
+// out[j] = sum_b partial[b * nv + j] for j < nv (complex128; fixed order)
+void zsum_partials(hipStream_t s, const void* partial, int nb, int nv, void* out);
 // number of blocks (and of partial sums of |w|^2) of zcombine_p over n entries
 int zcombine_norm_blocks(long long n);
 // the first stage of zdots alone: partial[b * nv + j] over chunks b < nb
@@ -352,11 +371,14 @@ double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth
 // C (rows >= cols) = A R by two Cholesky-QR passes, A orthonormal columns,
 // R = A^dagger C (cols x cols, not triangular); false (A, R undefined) when
 // the Gram matrix is numerically singular or A fails the orthonormality check.
+// With q (the charges of the columns, ascending; may be null) the Gram
+// matrix is factorised charge block by charge block.
 bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
-                      const void* first = nullptr);
-// C (rows <= cols) = L B with B orthonormal rows, L = C B^dagger (rows x rows).
+                      const void* first = nullptr, const std::vector<int>* q = nullptr);
+// C (rows <= cols) = L B with B orthonormal rows, L = C B^dagger (rows x rows);
+// q: the charges of the rows.
 bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
-                           const void* first = nullptr);
+                           const void* first = nullptr, const std::vector<int>* q = nullptr);
 // Certifies that the smallest eigenvalue of the Hermitian positive
 // semidefinite n x n matrix G exceeds frac * trace(G): the Cholesky
 // factorisation of G - (1.01 frac + 4 n u) trace(G) I succeeds (u the unit
@@ -367,10 +389,11 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
 // in the form the Cholesky-QR routines take for their first step (shifted
 // Cholesky QR: the shifted factor leaves the first iterate's condition
 // number small, and the second step restores orthonormality): L^-1 in Finv
-// (n x n) for n <= kern::cholinv_max_n(), else rocSOLVER's factor in G
+// (n x n) for n <= kern::cholinv_max_n() or, with charges q (ascending) on
+// the index, when every charge block fits it, else rocSOLVER's factor in G
 // (upper, or lower when `lower`, in the column-major view).
 const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work,
-                                 const void* src = nullptr);
+                                 const void* src = nullptr, const std::vector<int>* q = nullptr);
 // thin SVD of row-major C (rows x cols): U (rows x k), S (k, host), Vh (k x cols); k = min.
 void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, std::vector<double>& S,
                   void* Vh, DBuf& work, DBuf& work2);

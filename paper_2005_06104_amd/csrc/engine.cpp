@@ -74,10 +74,11 @@ struct Lanczos {
     partial.ensure(((size_t)nb * (maxit + 1) + (size_t)nnp * (maxit + 2)) * ZB);
     double2* npart = partial.as<double2>() + (size_t)nb * (maxit + 1);
     double2* dpart2 = npart + nnp;   // second-pass partial dot products, nnp x (j + 1)
-    scal.ensure(256 * ZB);
+    scal.ensure(320 * ZB);
     double2* S = scal.as<double2>();
     // S: [0, 64) and [64, 128) the two projection passes, 128 |w|^2, 192.. the
-    // result coefficients
+    // result coefficients, 256 the summed partial norms of long vectors
+    constexpr int FOLD = 64;
     char* Vb = static_cast<char*>(V.ensure((size_t)(maxit + 1) * n * ZB));
     auto vec = [&](int j) { return static_cast<void*>(Vb + (size_t)j * n * ZB); };
 
@@ -127,11 +128,26 @@ struct Lanczos {
       if (timer) timer->cur = j & 1;
       mv(vec(j), w);
       kern::zdots_partial(ctx->stream, Vb, n, j + 1, w, n, partial.p, nb);
-      kern::zcombine_dots(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S, dpart2);
-      kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, dpart2, nnp, -1.0, n, S + 64, npart);
+      // Every block of the update kernels sums all partials itself; above
+      // FOLD partials (long vectors) that work grows as (n / block)^2, so
+      // they are first summed once by a separate launch (same fixed order).
+      if (nb > FOLD) {
+        kern::zsum_partials(ctx->stream, partial.p, nb, j + 1, S);
+        kern::zcombine_dots(ctx->stream, w, Vb, n, j + 1, S, 1, -1.0, n, nullptr, dpart2);
+      } else {
+        kern::zcombine_dots(ctx->stream, w, Vb, n, j + 1, partial.p, nb, -1.0, n, S, dpart2);
+      }
       // the normalisation also writes the first-pass projections (alpha_j =
       // <v_j|H v_j>) and |w|^2 into the pinned slot the host reads
-      kern::zscale_invnorm(ctx->stream, w, npart, nnp, S + 128, n, ctx->stage_slot_dev(j & 1), S, j + 1, 128);
+      if (nnp > FOLD) {
+        kern::zsum_partials(ctx->stream, dpart2, nnp, j + 1, S + 64);
+        kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, S + 64, 1, -1.0, n, nullptr, npart);
+        kern::zsum_partials(ctx->stream, npart, nnp, 1, S + 256);
+        kern::zscale_invnorm(ctx->stream, w, S + 256, 1, S + 128, n, ctx->stage_slot_dev(j & 1), S, j + 1, 128);
+      } else {
+        kern::zcombine_p(ctx->stream, w, Vb, n, j + 1, dpart2, nnp, -1.0, n, S + 64, npart);
+        kern::zscale_invnorm(ctx->stream, w, npart, nnp, S + 128, n, ctx->stage_slot_dev(j & 1), S, j + 1, 128);
+      }
       staged[j & 1] = static_cast<const zc*>(ctx->stage_mark(j & 1));
     };
     enqueue(0);
@@ -608,7 +624,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     if (keep_cols) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work)) {
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, nullptr, qc)) {
         if (sym) *qk = *qc;
         return kk;
       }
@@ -633,11 +649,11 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // certifies it, and the exact factorisation is then the split.
   if (kk == cols && kk <= chi_max && keep_cols) {
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false,
-                                             W.cinv.ensure((size_t)cols * cols * ZB), W.work, W.tmpA.p);
+                                             W.cinv.ensure((size_t)cols * cols * ZB), W.work, W.tmpA.p, qc);
     if (F) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F)) {
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F, qc)) {
         if (sym) *qk = *qc;
         return kk;
       }
@@ -673,7 +689,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
       // with charges the Cholesky-QR steps keep the blocks (Householder
       // reflections would mix them)
       if (!sym) la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
-      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work))
+      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, nullptr, qk))
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
@@ -697,7 +713,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (keep_rows) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work)) {
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, nullptr, qr)) {
         if (sym) *qk = *qr;
         return kk;
       }
@@ -718,11 +734,11 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   // certified "nothing to cut" as in split_left
   if (kk == rows && kk <= chi_max && keep_rows) {
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true,
-                                             W.cinv.ensure((size_t)rows * rows * ZB), W.work, W.tmpA.p);
+                                             W.cinv.ensure((size_t)rows * rows * ZB), W.work, W.tmpA.p, qr);
     if (F) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F)) {
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F, qr)) {
         if (sym) *qk = *qr;
         return kk;
       }
@@ -752,7 +768,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (!(la::orth_defect(ctx, B.p, n, cols, true, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
       if (!sym) la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
-      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work))
+      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, nullptr, qk))
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
@@ -1574,11 +1590,12 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     // largest, the criterion below); B is then the LQ factor's Q.
     bool done = false;
     if (ml <= D) {
+      const std::vector<int>* qm = sym ? &psi.q[i] : nullptr;
       const void* F = la::gram_floor_certified(ctx, W.tmpB.p, ml, 1e-10, true,
-                                               W.cinv.ensure((size_t)ml * ml * ZB), W.work, W.tmpA.p);
+                                               W.cinv.ensure((size_t)ml * ml * ZB), W.work, W.tmpA.p, qm);
       if (F) {
         W.tmpC.ensure((size_t)ml * ml * ZB);
-        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F);
+        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F, qm);
         if (done) {
           r = ml;
           if (sym) qB = psi.q[i];

@@ -106,16 +106,20 @@ struct MatvecTimer {
 // needs on it.
 struct KMapHost {
   std::vector<int> off, iv;
+  std::vector<int> nsplit;                    // with splits > 1: nonempty parts per tile
   double exact_macs = 0.0, tile_macs = 0.0;   // nonzero multiply-adds; those the tiles perform
-  int M = 0, N = 0, K = 0, batch = 1;
+  int M = 0, N = 0, K = 0, batch = 1, splits = 1;
 };
 void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out);
+// Split the K intervals of a map whose nonempty tiles are too few to fill
+// the GPU into parts of about equal length (see kern::KMap).
+void split_kmap(KMapHost& h);
 // a map on the device
 struct DevKMap {
-  DBuf buf;
+  DBuf buf, part;   // the map; the partial products of a split map (complex128-sized)
   kern::KMap map;
   double exact_flops = 0.0, tile_flops = 0.0;
-  explicit DevKMap(tdvp_ctx_s* c) : buf(c) {}
+  explicit DevKMap(tdvp_ctx_s* c) : buf(c), part(c) {}
   void set(tdvp_ctx_s* ctx, const KMapHost& h);
   const kern::KMap* get() const { return map.off ? &map : nullptr; }
 };

@@ -48,9 +48,11 @@ template <typename T> constexpr int gemm_threads() { return WaveGrid<T>::WM * Wa
 // Split-K: blockIdx.z = batch * S + split; split s covers k in
 // [s*Kc, min(K, (s+1)*Kc)) and writes its partial product at C + s*sps.
 // Block-sparse products (operands with U(1) charges): koff/kiv list, for
-// every output tile (batch outer, then row-major tile order) the K intervals
-// [x, y) it needs (kiv[koff[t] .. koff[t+1])); koff null: the whole K range
-// (or one split-K part).  A tile with no interval writes alpha * 0 + beta * C.
+// every output tile (batch, then split part, then row-major tile order) the
+// K intervals [x, y) it needs (kiv[koff[t] .. koff[t+1])); koff null: the whole K
+// range (or one split-K part).  A tile with no interval writes
+// alpha * 0 + beta * C; an empty split part writes nothing (the reduction
+// reads only the nonempty parts).
 struct KIter {
   const int2* iv;
   int n;
@@ -170,7 +172,8 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
   // double-buffered LDS: compute on `cur` while the next tile's global loads
   // are in flight, then store them into the other buffer; one barrier per
   // tile.  The K steps walk the tile's intervals in order.
-  const KIter kr_ = tile_k_range(koff, kiv, (unsigned)(bz * gx * gy) + trem, kb, ke);
+  const KIter kr_ = tile_k_range(koff, kiv, t, kb, ke);
+  if (S > 1 && kr_.n == 0) return;
   int iv = 0, k0 = 0, kend = 0;
   if (kr_.n > 0) {
     const int2 I0 = kr_.at(0);
@@ -388,7 +391,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     }
 
   const int lr = lane & 15, lk = lane >> 4;
-  const KIter kr_ = tile_k_range(koff, kiv, (unsigned)(bz * gx * gy) + trem, kb, ke);
+  const KIter kr_ = tile_k_range(koff, kiv, t, kb, ke);
+  if (S > 1 && kr_.n == 0) return;
   int iv = 0, k0 = 0, kend = 0;
   if (kr_.n > 0) {
     const int2 I0 = kr_.at(0);
@@ -515,6 +519,38 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ P, int S, long long M
   Cc[m * ldc + n] = o;
 }
 
+// Split-K reduction of a block-sparse product: C[b] = alpha * sum of the
+// nonempty parts of each tile + beta * C[b]; the parts are P[s][b][m][n].
+template <typename T>
+__global__ void splitk_reduce_map_kernel(const T* __restrict__ P, int batch, long long M, long long N, int gx,
+                                         const int* __restrict__ nsplit, T ar, T ai, T br, T bi, T* __restrict__ C,
+                                         long long ldc, long long sc) {
+  using c2 = typename VT<T>::c2;
+  const long long MN = M * N;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= MN * batch) return;
+  const long long b = idx / MN, r = idx % MN, m = r / N, n = r % N;
+  const long long tiles = ((M + BM - 1) / BM) * (long long)gx;
+  const int ns = nsplit[b * tiles + (m / BM) * gx + n / BN];
+  const c2* Pc = reinterpret_cast<const c2*>(P);
+  T xr = T(0), xi = T(0);
+  for (int s = 0; s < ns; ++s) {
+    const c2 v = Pc[(long long)s * batch * MN + idx];
+    xr += v.x;
+    xi += v.y;
+  }
+  c2* Cc = reinterpret_cast<c2*>(C) + b * sc + m * ldc + n;
+  c2 o;
+  o.x = ar * xr - ai * xi;
+  o.y = ar * xi + ai * xr;
+  if (br != T(0) || bi != T(0)) {
+    const c2 old = *Cc;
+    o.x += br * old.x - bi * old.y;
+    o.y += br * old.y + bi * old.x;
+  }
+  *Cc = o;
+}
+
 // Number of K splits: about one workgroup per CU when the output has few
 // tiles (Gram matrices, back transformations: 16-64 tiles would leave most
 // of the 256 CUs idle), each split keeping >= 64 of K.  The partial products
@@ -560,7 +596,23 @@ void launch_gemm_mode(hipStream_t s, int M, int N, int K, zc alpha, const void* 
   const kern::KMap* km = tl_kmap;
   if (km && km->batch == batch) {
     if (km->M != M || km->N != N || km->K != K) TDVP_THROW(TDVP_ERR_ARG, "block-sparse map does not fit the product");
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+    const int gx = (N + BN - 1) / BN;
+    if (km->splits > 1) {
+      using c2 = typename VT<T>::c2;
+      const long long MN = (long long)M * N;
+      if (!km->part || km->part_bytes < (size_t)km->splits * batch * MN * sizeof(c2))
+        TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without room for its partial products");
+      T* P = static_cast<T*>(km->part);
+      dim3 grid(gx, (M + BM - 1) / BM, batch * km->splits);
+      launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(1), T(0), a, lda, sa, b, ldb, sb, T(0), T(0), P,
+                                                 (long long)N, MN, km->splits, std::max(K, 1), MN * batch, km->off,
+                                                 reinterpret_cast<const int2*>(km->iv));
+      hipLaunchKernelGGL(splitk_reduce_map_kernel<T>, dim3((unsigned)((MN * batch + 255) / 256)), dim3(256), 0, s, P,
+                         batch, (long long)M, (long long)N, gx, km->nsplit, T(alpha.real()), T(alpha.imag()),
+                         T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
+      return;
+    }
+    dim3 grid(gx, (M + BM - 1) / BM, batch);
     launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(alpha.real()), T(alpha.imag()), a, lda, sa, b,
                                                ldb, sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc,
                                                sc, 1, std::max(K, 1), 0LL, km->off, reinterpret_cast<const int2*>(km->iv));
@@ -1144,6 +1196,13 @@ void zdots(hipStream_t s, const void* V, long long ldv, int nv, const void* w, l
                        nv, static_cast<const double2*>(w), n, static_cast<double2*>(partial));
   hipLaunchKernelGGL(zdots_final_kernel, dim3(nv), dim3(VNT), 0, s,
                      static_cast<const double2*>(partial), nb, nv, static_cast<double2*>(out));
+  HIP_CHECK(hipGetLastError());
+}
+
+void zsum_partials(hipStream_t s, const void* partial, int nb, int nv, void* out) {
+  if (nv <= 0) return;
+  hipLaunchKernelGGL(zdots_final_kernel, dim3(nv), dim3(VNT), 0, s, static_cast<const double2*>(partial), nb, nv,
+                     static_cast<double2*>(out));
   HIP_CHECK(hipGetLastError());
 }
 

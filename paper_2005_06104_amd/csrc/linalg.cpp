@@ -115,10 +115,45 @@ namespace {
 // L^-1 in Finv; the step is then a GEMM), larger n rocSOLVER zpotrf in place
 // (the step a triangular solve; `lower` selects the factor the row variant
 // needs).  *dinfo (device) is 0 on success.
-bool own_chol(int n) { return n <= kern::cholinv_max_n(); }
+// With charges q (ascending) on the Gram matrix's index, the matrix is block
+// diagonal (entries between different charges are exact zeros), and the
+// factorisation runs block by block in one launch when every block fits the
+// cooperative kernel: L^-1 is then block diagonal too.
+struct CholBlocks {
+  std::vector<int> off, size;
+  bool use = false;
+};
 
-void chol_factor(tdvp_ctx_s* ctx, rz* G, int n, rz* Finv, int* dinfo, void* cscr, bool lower) {
-  if (own_chol(n)) {
+CholBlocks chol_blocks(int n, const std::vector<int>* q) {
+  CholBlocks b;
+  if (!q || (int)q->size() != n || n < 1 || !std::is_sorted(q->begin(), q->end())) return b;
+  for (int i = 0; i < n;) {
+    int e = i + 1;
+    while (e < n && (*q)[e] == (*q)[i]) ++e;
+    if (e - i > kern::cholinv_max_n()) return CholBlocks{};
+    b.off.push_back(i);
+    b.size.push_back(e - i);
+    i = e;
+  }
+  b.use = b.off.size() > 1 || n <= kern::cholinv_max_n();
+  return b;
+}
+
+bool own_chol(int n, const std::vector<int>* q = nullptr) {
+  return n <= kern::cholinv_max_n() || chol_blocks(n, q).use;
+}
+
+void chol_factor(tdvp_ctx_s* ctx, rz* G, int n, rz* Finv, int* dinfo, void* cscr, bool lower,
+                 const std::vector<int>* q = nullptr) {
+  const CholBlocks cb = chol_blocks(n, q);
+  if (cb.use && cb.off.size() > 1) {
+    kern::zfill(ctx->stream, Finv, zc(0.0, 0.0), (long long)n * n, 16);   // the blocks between sectors
+    if (kern::cholinv_blocks(ctx->stream, G, n, cb.off.data(), cb.size.data(), (int)cb.off.size(), G, Finv, dinfo,
+                             cscr) != hipSuccess) {
+      (void)hipGetLastError();
+      TDVP_THROW(TDVP_ERR_DEVICE, "Cholesky factorisation launch failed");
+    }
+  } else if (own_chol(n)) {
     if (kern::cholinv(ctx->stream, G, n, G, Finv, dinfo, cscr) != hipSuccess) {
       (void)hipGetLastError();
       TDVP_THROW(TDVP_ERR_DEVICE, "Cholesky factorisation launch failed");
@@ -132,15 +167,15 @@ void chol_factor(tdvp_ctx_s* ctx, rz* G, int n, rz* Finv, int* dinfo, void* cscr
 }  // namespace
 
 const void* gram_floor_certified(tdvp_ctx_s* ctx, void* G, int n, double frac, bool lower, void* Finv, DBuf& work,
-                                 const void* src) {
+                                 const void* src, const std::vector<int>* q) {
   if (n < 1) return nullptr;
-  char* base = static_cast<char*>(work.ensure(256 + kern::cholinv_scratch_bytes()));
+  char* base = static_cast<char*>(work.ensure(256 + kern::cholinv_blocks_scratch_bytes()));
   int* dinfo = reinterpret_cast<int*>(base);
   kern::shift_by_trace(ctx->stream, G, n, frac * 1.01 + 4.0 * n * 2.220446049250313e-16, src);
   // (row-major G read column-major is conj(G): definite exactly when G is)
-  chol_factor(ctx, static_cast<rz*>(G), n, static_cast<rz*>(Finv), dinfo, base + 256, lower);
+  chol_factor(ctx, static_cast<rz*>(G), n, static_cast<rz*>(Finv), dinfo, base + 256, lower, q);
   if (*static_cast<const int*>(ctx->fetch(dinfo, sizeof(int))) != 0) return nullptr;
-  return own_chol(n) ? Finv : G;
+  return own_chol(n, q) ? Finv : G;
 }
 
 // Cholesky QR in two steps (after CholeskyQR2: Yamamoto, Nakatsukasa,
@@ -183,7 +218,7 @@ CqrSpace cqr_space(DBuf& work, int n, long long mat) {
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t oG = 0, oP = oG + up(sizeof(rz) * nn), oT = oP + up(sizeof(rz) * ((size_t)nb + 2)),
                oF = oT + up(sizeof(rz) * (size_t)mat), oS = oF + up(sizeof(rz) * nn),
-               tot = oS + up(kern::cholinv_scratch_bytes());
+               tot = oS + up(kern::cholinv_blocks_scratch_bytes());
   char* base = static_cast<char*>(work.ensure(tot));
   CqrSpace c;
   c.G = reinterpret_cast<rz*>(base + oG);
@@ -212,12 +247,12 @@ double defect(tdvp_ctx_s* ctx, const CqrSpace& c, int n, int* info) {
 }  // namespace
 
 bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
-                      const void* first) {
+                      const void* first, const std::vector<int>* q) {
   if (cols < 1 || rows < cols) return false;
   const int n = cols;
   const CqrSpace c = cqr_space(work, n, (long long)rows * n);
   hipStream_t s = ctx->stream;
-  const bool own = own_chol(n);
+  const bool own = own_chol(n, q);
   rz* const X = static_cast<rz*>(A);
   const rz* Cz = static_cast<const rz*>(C);
   // the current iterate: C itself before the first step, then X or c.T (the
@@ -245,7 +280,7 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
     }
   };
   auto factor = [&]() -> const rz* {
-    chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, false);
+    chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, false, q);
     return own ? c.Finv : c.G;
   };
   if (first) {
@@ -290,12 +325,12 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
 // B = L^-1 C is, column-major, B^T Lc^H = C^T; Newton-Schulz steps are
 // B <- (I - (B B^H - I) / 2) B.
 bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
-                           const void* first) {
+                           const void* first, const std::vector<int>* q) {
   if (rows < 1 || cols < rows) return false;
   const int n = rows;
   const CqrSpace c = cqr_space(work, n, (long long)n * cols);
   hipStream_t s = ctx->stream;
-  const bool own = own_chol(n);
+  const bool own = own_chol(n, q);
   rz* const X = static_cast<rz*>(B);
   const rz* Cz = static_cast<const rz*>(C);
   const rz* cur = Cz;
@@ -323,7 +358,7 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
     }
   };
   auto factor = [&]() -> const rz* {
-    chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, true);
+    chol_factor(ctx, c.G, n, c.Finv, c.dinfo, c.cscr, true, q);
     return own ? c.Finv : c.G;
   };
   if (first) {

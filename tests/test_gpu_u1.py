@@ -203,3 +203,58 @@ def test_u1_two_site_sweep_matches_oracle(env):
         out = T.tdvp_mps_to_host(g)
         assert 1 - M.fidelity(out, ref) < 1e-10
     _check_blocks(T, g)
+
+
+def _right_canonical_u1(tensors, charges):
+    """Bring a charged MPS to the sweep's precondition (sites 1..N-1
+    right-canonical, centre at site 0) by an LQ factorisation of each charge
+    block: the rows of site i with left charge c live on the columns (s, b)
+    with q(b) - q(s) = c only, so every block factorises on its own and the
+    entries outside the blocks stay exactly zero."""
+    t = [x.copy() for x in tensors]
+    for i in range(len(t) - 1, 0, -1):
+        ml, d, mr = t[i].shape
+        ql, qr = charges[i], charges[i + 1]
+        m = t[i].reshape(ml, d * mr)
+        qcol = np.concatenate([qr - 1, qr + 1])     # q(b) - q(s) for s = up, down
+        for c in np.unique(ql):
+            r, k = np.nonzero(ql == c)[0], np.nonzero(qcol == c)[0]
+            assert len(r) <= len(k)
+            Q, R = np.linalg.qr(m[np.ix_(r, k)].conj().T)
+            m[np.ix_(r, k)] = Q.conj().T
+            t[i - 1][:, :, r] = t[i - 1][:, :, r] @ R.conj().T
+        t[i] = m.reshape(ml, d, mr)
+    t[0] /= np.linalg.norm(t[0])
+    return t
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_u1_split_k_products_sweep_matches_oracle(env, prec):
+    # A random charged state with bonds up to 256 on the 4x4 J1-J2 cylinder
+    # (MPO bond dimension 20): the second product of H_eff and of K_eff then
+    # has 2 x 2 x 4 output tiles with thousands of K entries each, too few
+    # tiles to fill the GPU, so their K intervals run split into parts with
+    # a reduction.  Two real-time sweeps against the oracle's.
+    T, ctx = env
+    from oracle import mpo, mps as M, observables as O, tdvp as TD
+    lat = I.cylinder(4, 4, 1.0, 0.5)
+    N = lat.n_sites
+    terms = I.heisenberg_terms(lat.couplings)
+    psi0, q0 = I.random_u1_mps(N, 256, 11)
+    psi = _right_canonical_u1(psi0, q0)
+    assert max(M.bond_dims(psi)) == 256
+    Ws = mpo.build_mpo(N, terms)
+    H = T.tdvp_create_mpo(ctx, N, terms)
+    g = T.tdvp_mps_from_host(ctx, psi, q0)
+    dt, t = 0.05, 0.0
+    tol = {"fp64": (1e-8, 1e-10), "fp32": (1e-5, 1e-5), "bf16x3": (2e-5, 2e-4)}[prec]
+    for _ in range(2):
+        psi, _ = TD.tdvp1_sweep(psi, Ws, dt, 0.0, 256)
+        T.tdvp_sweep(ctx, [g], [H], dt, 0.0, 256, 1e-12, 30, prec, False)
+        t += dt
+        out = T.tdvp_mps_to_host(g)
+        e_ref = O.energy(psi, Ws)
+        m = T.tdvp_measure(ctx, [g], [H])[0]
+        assert 1 - M.fidelity(out, psi) < tol[0] * t, prec
+        assert abs(m["energy"] - e_ref) < tol[1] * max(1.0, abs(e_ref)), (prec, m["energy"], e_ref)
+    _check_blocks(T, g)
