@@ -155,15 +155,35 @@ void split_kmap(KMapHost& h) {
 }
 
 void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
-  const size_t nb = sizeof(int) * (h.off.size() + h.iv.size() + h.nsplit.size());
-  buf.ensure(nb);
-  HIP_CHECK(hipMemcpyAsync(buf.p, h.off.data(), sizeof(int) * h.off.size(), hipMemcpyHostToDevice, ctx->stream));
-  if (!h.iv.empty())
-    HIP_CHECK(hipMemcpyAsync(buf.as<int>() + h.off.size(), h.iv.data(), sizeof(int) * h.iv.size(),
-                             hipMemcpyHostToDevice, ctx->stream));
-  if (!h.nsplit.empty())
-    HIP_CHECK(hipMemcpyAsync(buf.as<int>() + h.off.size() + h.iv.size(), h.nsplit.data(),
-                             sizeof(int) * h.nsplit.size(), hipMemcpyHostToDevice, ctx->stream));
+  // work items (tile, part, first interval, end), longest K first
+  const int E = (int)h.off.size() - 1, S = std::max(h.splits, 1);
+  const int tiles = h.batch > 0 ? E / (h.batch * S) : 0;
+  std::vector<int> items;
+  std::vector<std::pair<long long, int>> order;
+  order.reserve(E);
+  for (int e = 0; e < E; ++e) {
+    long long kl = 0;
+    for (int v = h.off[e]; v < h.off[e + 1]; ++v) kl += h.iv[2 * v + 1] - h.iv[2 * v];
+    if (S > 1 && kl == 0) continue;   // empty parts: the reduction skips them
+    order.push_back({-kl, e});
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<long long, int>& x, const std::pair<long long, int>& y) { return x.first < y.first; });
+  items.reserve(4 * order.size());
+  for (const auto& o : order) {
+    const int e = o.second, t = e % tiles, bs = e / tiles, b = bs / S, s = bs % S;
+    items.push_back(b * tiles + t);
+    items.push_back(s);
+    items.push_back(h.off[e]);
+    items.push_back(h.off[e + 1]);
+  }
+  const size_t ni = items.size(), nv = h.iv.size(), ns = h.nsplit.size();
+  buf.ensure(sizeof(int) * (ni + nv + ns + 4));
+  int* base = buf.as<int>();   // items first (16-byte aligned)
+  if (ni) HIP_CHECK(hipMemcpyAsync(base, items.data(), sizeof(int) * ni, hipMemcpyHostToDevice, ctx->stream));
+  if (nv) HIP_CHECK(hipMemcpyAsync(base + ni, h.iv.data(), sizeof(int) * nv, hipMemcpyHostToDevice, ctx->stream));
+  if (ns)
+    HIP_CHECK(hipMemcpyAsync(base + ni + nv, h.nsplit.data(), sizeof(int) * ns, hipMemcpyHostToDevice, ctx->stream));
   map.part = nullptr;
   map.part_bytes = 0;
   if (h.splits > 1) {   // partial products, sized for complex128
@@ -171,9 +191,10 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
     map.part = part.ensure(map.part_bytes);
   }
   HIP_CHECK(hipStreamSynchronize(ctx->stream));   // the host vectors may die
-  map.off = buf.as<int>();
-  map.iv = buf.as<int>() + h.off.size();
-  map.nsplit = h.splits > 1 ? buf.as<int>() + h.off.size() + h.iv.size() : nullptr;
+  map.items = reinterpret_cast<const int4*>(base);
+  map.n_items = (int)(ni / 4);
+  map.iv = base + ni;
+  map.nsplit = h.splits > 1 ? base + ni + nv : nullptr;
   map.M = h.M;
   map.N = h.N;
   map.K = h.K;

@@ -152,18 +152,23 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
           long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0);
 
 // Block-sparse map of an M x N x K product whose operands carry U(1)
-// charges: for every 64 x 64 output tile (row-major tile order) the K
-// intervals it needs, iv[off[t] .. off[t+1]) as (begin, end) pairs; device
+// charges, as a list of work items, one workgroup each: item
+// {tile, part, a, b} computes output tile `tile` (batch entry outer, then
+// 64 x 64 tiles in row-major order) over the K intervals iv[a .. b) ((begin,
+// end) pairs).  The items are sorted by decreasing K length, so the longest
+// are dispatched first and consecutive ones go to different XCDs; device
 // arrays.  While set (set_kmap / KMapScope) on the calling host thread, the
 // products of that shape and batch count it issues walk only those
 // intervals; any other shape is an error.
-// Split K (splits > 1): entry (b * splits + s) * tiles + t holds part s of
-// tile t of batch entry b; the first nsplit[b * tiles + t] parts are
-// nonempty, the rest empty.  Each part writes its partial product into
-// `part` (splits x batch x M x N complex of the product's type, at most
-// part_bytes), and one reduction sums the nonempty parts of every tile.
+// Unsplit maps (splits = 1) hold every tile (a tile without intervals writes
+// alpha * 0 + beta * C).  Split maps (splits > 1) hold the nonempty parts
+// only: part s of a tile writes its partial product into `part` (splits x
+// batch x M x N complex of the product's type, at most part_bytes), the
+// first nsplit[tile] parts of every tile are nonempty, and one reduction
+// sums them.
 struct KMap {
-  const int* off = nullptr;
+  const int4* items = nullptr;
+  int n_items = 0;
   const int* iv = nullptr;     // pairs
   int M = 0, N = 0, K = 0;
   int batch = 1;               // batched products: one map per batch entry, batch outer

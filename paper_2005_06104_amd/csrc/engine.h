@@ -121,7 +121,7 @@ struct DevKMap {
   double exact_flops = 0.0, tile_flops = 0.0;
   explicit DevKMap(tdvp_ctx_s* c) : buf(c), part(c) {}
   void set(tdvp_ctx_s* ctx, const KMapHost& h);
-  const kern::KMap* get() const { return map.off ? &map : nullptr; }
+  const kern::KMap* get() const { return map.items ? &map : nullptr; }
 };
 // the maps of the contractions (bra bonds qlo, qro; ket bonds qli, qri; MPO
 // channels qwl, qwr; equal bra and ket for the effective Hamiltonians).  The

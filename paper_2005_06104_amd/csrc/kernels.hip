@@ -47,12 +47,12 @@ template <typename T> constexpr int gemm_threads() { return WaveGrid<T>::WM * Wa
 // its own so that profilers and timers see it apart from the other GEMMs).
 // Split-K: blockIdx.z = batch * S + split; split s covers k in
 // [s*Kc, min(K, (s+1)*Kc)) and writes its partial product at C + s*sps.
-// Block-sparse products (operands with U(1) charges): koff/kiv list, for
-// every output tile (batch, then split part, then row-major tile order) the
-// K intervals [x, y) it needs (kiv[koff[t] .. koff[t+1])); koff null: the whole K
-// range (or one split-K part).  A tile with no interval writes
-// alpha * 0 + beta * C; an empty split part writes nothing (the reduction
-// reads only the nonempty parts).
+// Block-sparse products (operands with U(1) charges): a linear grid over
+// the work items kit (kern::KMap): item {tile, part, a, b} is output tile
+// `tile` (batch entry outer) over the K intervals kiv[a .. b) as [x, y)
+// pairs, its partial product at C + part * sps.  kit null: the dense tile
+// grid over the whole K range (or one split-K part).  A tile with no
+// interval writes alpha * 0 + beta * C.
 struct KIter {
   const int2* iv;
   int n;
@@ -60,19 +60,49 @@ struct KIter {
   __device__ int2 at(int v) const { return iv ? iv[v] : one; }
 };
 
-__device__ inline KIter tile_k_range(const int* __restrict__ koff, const int2* __restrict__ kiv, unsigned trem,
-                                     int kb, int ke) {
-  KIter r;
-  r.one = make_int2(kb, ke);
-  if (koff) {
-    const int a = koff[trem], b = koff[trem + 1];
-    r.iv = kiv + a;
-    r.n = b - a;
-  } else {
-    r.iv = nullptr;
-    r.n = kb < ke ? 1 : 0;
+// the output tile, batch entry, split part and K range of this workgroup
+struct TileJob {
+  int m0, n0, split;
+  long long bz;
+  KIter kr;
+};
+
+__device__ inline TileJob tile_job(int M, int N, int K, int S, int Kc, const int4* __restrict__ kit,
+                                   const int2* __restrict__ kiv) {
+  TileJob j;
+  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if (kit) {
+    // items in decreasing K length: dispatch order (and the XCD round robin
+    // of consecutive workgroups) spreads the long ones
+    const int4 it = kit[lin];
+    const int gxt = (N + BN - 1) / BN, tpb = gxt * ((M + BM - 1) / BM);
+    j.bz = it.x / tpb;
+    const int trem = it.x % tpb;
+    j.m0 = (trem / gxt) * BM;
+    j.n0 = (trem % gxt) * BN;
+    j.split = it.y;
+    j.kr.iv = kiv + it.z;
+    j.kr.n = it.w - it.z;
+    j.kr.one = make_int2(0, 0);
+    return j;
   }
-  return r;
+  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+  // linear id g runs on XCD g % 8.  Give each XCD a contiguous band of tiles
+  // (z-slice, then tile row, then tile column) so that the operand panels a
+  // band needs stay in that XCD's L2.
+  const unsigned tot = gx * gy * gz;
+  const unsigned t = (tot % 8u == 0u) ? (lin % 8u) * (tot / 8u) + lin / 8u : lin;
+  const unsigned tz = t / (gx * gy), trem = t % (gx * gy);
+  j.m0 = (int)(trem / gx) * BM;
+  j.n0 = (int)(trem % gx) * BN;
+  j.bz = tz / S;
+  j.split = tz % S;
+  const int kb = j.split * Kc, ke = min(K, kb + Kc);
+  j.kr.iv = nullptr;
+  j.kr.n = kb < ke ? 1 : 0;
+  j.kr.one = make_int2(kb, ke);
+  return j;
 }
 
 template <typename T, bool TA, bool CA, bool TB, bool CB, int TAG>
@@ -80,7 +110,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
                                                    long long lda, long long sa, const T* __restrict__ B,
                                                    long long ldb, long long sb, T br, T bi,
                                                    T* __restrict__ C, long long ldc, long long sc, int S, int Kc,
-                                                   long long sps, const int* __restrict__ koff,
+                                                   long long sps, const int4* __restrict__ kit,
                                                    const int2* __restrict__ kiv) {
   using c2 = typename VT<T>::c2;
   using acc_t = typename VT<T>::acc;
@@ -93,20 +123,9 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // linear id g runs on XCD g % 8.  Give each XCD a contiguous band of tiles
-  // (z-slice, then tile row, then tile column) so that the operand panels a
-  // band needs stay in that XCD's L2.
-  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
-  const unsigned tot = gx * gy * gz;
-  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  const unsigned t = (tot % 8u == 0u) ? (lin % 8u) * (tot / 8u) + lin / 8u : lin;
-  const unsigned tz = t / (gx * gy), trem = t % (gx * gy);
-  const int m0 = (int)(trem / gx) * BM, n0 = (int)(trem % gx) * BN;
-  const long long bz = tz / S;
-  const int split = tz % S;
-  const int kb = split * Kc;
-  const int ke = min(K, kb + Kc);
+  const TileJob job = tile_job(M, N, K, S, Kc, kit, kiv);
+  const int m0 = job.m0, n0 = job.n0, split = job.split;
+  const long long bz = job.bz;
   const c2* Ab = reinterpret_cast<const c2*>(A) + bz * sa;
   const c2* Bb = reinterpret_cast<const c2*>(B) + bz * sb;
   c2* Cb = reinterpret_cast<c2*>(C) + bz * sc + split * sps;
@@ -172,8 +191,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
   // double-buffered LDS: compute on `cur` while the next tile's global loads
   // are in flight, then store them into the other buffer; one barrier per
   // tile.  The K steps walk the tile's intervals in order.
-  const KIter kr_ = tile_k_range(koff, kiv, t, kb, ke);
-  if (S > 1 && kr_.n == 0) return;
+  const KIter kr_ = job.kr;
   int iv = 0, k0 = 0, kend = 0;
   if (kr_.n > 0) {
     const int2 I0 = kr_.at(0);
@@ -346,7 +364,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
                                                         const float* __restrict__ B, long long ldb, long long sb,
                                                         float br, float bi, float* __restrict__ C, long long ldc,
                                                         long long sc, int S, int Kc, long long sps,
-                                                        const int* __restrict__ koff, const int2* __restrict__ kiv) {
+                                                        const int4* __restrict__ kit, const int2* __restrict__ kiv) {
   constexpr int NPL = SPLIT ? 4 : 2;
   __shared__ __attribute__((aligned(16))) unsigned short As[2][NPL * PL2];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NPL * PL2];
@@ -355,16 +373,9 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
-  const unsigned tot = gx * gy * gz;
-  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  const unsigned t = (tot % 8u == 0u) ? (lin % 8u) * (tot / 8u) + lin / 8u : lin;
-  const unsigned tz = t / (gx * gy), trem = t % (gx * gy);
-  const int m0 = (int)(trem / gx) * BM, n0 = (int)(trem % gx) * BN;
-  const long long bz = tz / S;
-  const int split = tz % S;
-  const int kb = split * Kc;
-  const int ke = min(K, kb + Kc);
+  const TileJob job = tile_job(M, N, K, S, Kc, kit, kiv);
+  const int m0 = job.m0, n0 = job.n0, split = job.split;
+  const long long bz = job.bz;
   const float2* Ab = reinterpret_cast<const float2*>(A) + bz * sa;
   const float2* Bb = reinterpret_cast<const float2*>(B) + bz * sb;
   float2* Cb = reinterpret_cast<float2*>(C) + bz * sc + split * sps;
@@ -391,8 +402,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     }
 
   const int lr = lane & 15, lk = lane >> 4;
-  const KIter kr_ = tile_k_range(koff, kiv, t, kb, ke);
-  if (S > 1 && kr_.n == 0) return;
+  const KIter kr_ = job.kr;
   int iv = 0, k0 = 0, kend = 0;
   if (kr_.n > 0) {
     const int2 I0 = kr_.at(0);
@@ -574,13 +584,13 @@ thread_local const kern::KMap* tl_kmap = nullptr;
 template <typename T, int MODE, bool TA, bool CA, bool TB, bool CB, int TAG>
 void launch_tiles(dim3 grid, hipStream_t s, int M, int N, int K, T ar, T ai, const T* A, long long lda,
                   long long sa, const T* B, long long ldb, long long sb, T br, T bi, T* C, long long ldc,
-                  long long sc, int S, int Kc, long long sps, const int* koff = nullptr, const int2* kiv = nullptr) {
+                  long long sc, int S, int Kc, long long sps, const int4* kit = nullptr, const int2* kiv = nullptr) {
   if constexpr (MODE == 0) {
     hipLaunchKernelGGL((gemm_kernel<T, TA, CA, TB, CB, TAG>), grid, dim3(gemm_threads<T>()), 0, s, M, N, K, ar, ai, A,
-                       lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps, koff, kiv);
+                       lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps, kit, kiv);
   } else {
     hipLaunchKernelGGL((gemm_bf16_kernel<MODE - 1, TA, CA, TB, CB, TAG>), grid, dim3(NT), 0, s, M, N, K, ar, ai,
-                       A, lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps, koff, kiv);
+                       A, lda, sa, B, ldb, sb, br, bi, C, ldc, sc, S, Kc, sps, kit, kiv);
   }
 }
 
@@ -603,19 +613,20 @@ void launch_gemm_mode(hipStream_t s, int M, int N, int K, zc alpha, const void* 
       if (!km->part || km->part_bytes < (size_t)km->splits * batch * MN * sizeof(c2))
         TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without room for its partial products");
       T* P = static_cast<T*>(km->part);
-      dim3 grid(gx, (M + BM - 1) / BM, batch * km->splits);
-      launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(1), T(0), a, lda, sa, b, ldb, sb, T(0), T(0), P,
-                                                 (long long)N, MN, km->splits, std::max(K, 1), MN * batch, km->off,
-                                                 reinterpret_cast<const int2*>(km->iv));
+      if (km->n_items > 0)
+        launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(dim3(km->n_items), s, M, N, K, T(1), T(0), a, lda, sa, b, ldb, sb,
+                                                   T(0), T(0), P, (long long)N, MN, km->splits, std::max(K, 1),
+                                                   MN * batch, km->items, reinterpret_cast<const int2*>(km->iv));
       hipLaunchKernelGGL(splitk_reduce_map_kernel<T>, dim3((unsigned)((MN * batch + 255) / 256)), dim3(256), 0, s, P,
                          batch, (long long)M, (long long)N, gx, km->nsplit, T(alpha.real()), T(alpha.imag()),
                          T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
       return;
     }
-    dim3 grid(gx, (M + BM - 1) / BM, batch);
-    launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(grid, s, M, N, K, T(alpha.real()), T(alpha.imag()), a, lda, sa, b,
-                                               ldb, sb, T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc,
-                                               sc, 1, std::max(K, 1), 0LL, km->off, reinterpret_cast<const int2*>(km->iv));
+    if (km->n_items != batch * gx * ((M + BM - 1) / BM)) TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without every tile");
+    launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(dim3(km->n_items), s, M, N, K, T(alpha.real()), T(alpha.imag()), a,
+                                               lda, sa, b, ldb, sb, T(beta.real()), T(beta.imag()),
+                                               static_cast<T*>(C), ldc, sc, 1, std::max(K, 1), 0LL, km->items,
+                                               reinterpret_cast<const int2*>(km->iv));
     return;
   }
   const int S = choose_splits(M, N, K, batch, ws_bytes, sizeof(typename VT<T>::c2));

@@ -48,7 +48,8 @@ def summarize(path, marker="spin_kernel", split_grid=None, top=40):
     sel = [r for r in _rows(path) if lo < r[1] < hi and marker not in r[0]]
     by = defaultdict(lambda: [0, 0])
     for n, s, e, g in sel:
-        key = n if not (split_grid and split_grid in n) else f"{n} [grid {'x'.join(g)}]"
+        short = n if len(n) <= 100 else n[:97] + "..."
+        key = short if not (split_grid and split_grid in n) else f"{short} [grid {'x'.join(g)}]"
         by[key][0] += 1
         by[key][1] += e - s
     total = sum(v[1] for v in by.values())
@@ -69,8 +70,7 @@ def summarize(path, marker="spin_kernel", split_grid=None, top=40):
            "| kernel | calls | total ms | avg us | % of kernel time |",
            "|---|---:|---:|---:|---:|"]
     for key, (c, t) in sorted(by.items(), key=lambda kv: -kv[1][1])[:top]:
-        short = key if len(key) <= 110 else key[:107] + "..."
-        out.append(f"| `{short}` | {c} | {1e-6 * t:.1f} | {1e-3 * t / c:.1f} | {100.0 * t / total:.2f} |")
+        out.append(f"| `{key}` | {c} | {1e-6 * t:.1f} | {1e-3 * t / c:.1f} | {100.0 * t / total:.2f} |")
     return "\n".join(out)
 
 
