@@ -620,7 +620,7 @@ def cylinder_mode(args):
         "data": "synthetic",
         "config": {"workload": w.name + " (U(1) S^z charges)", "n_sites": N, "chi_max": chi, "k": w.k,
                    "dt": [w.dt.real, w.dt.imag], "eps_K": w.eps_K, "eps_M": w.eps_M, "eps": w.eps,
-                   "mpo_w_max": int(max(H.dims)), "krylov_route": f"variational fitting, {passes} passes (FP64)",
+                   "mpo_w_max": int(max(H.dims)), "krylov_route": f"variational fitting, {passes} passes (contractions in the run's precision, splits FP64)",
                    "prepared_by": f"{prep_steps} FP32 GSE-TDVP1 steps from Neel (untimed)",
                    "charge_sectors_mid_bond": sectors, "parallelism": "single GPU"},
     }

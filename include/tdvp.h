@@ -202,7 +202,8 @@ typedef struct {
   double eps_M;      /* cutoff on states added by the extension (relative to
                         sum_l |C~_l|^2)                                             */
   int chi_max;       /* cap on every bond (Krylov vectors and extended psi)         */
-  int prec;          /* tdvp_prec of the contractions                               */
+  int prec;          /* tdvp_prec of the MPO applications' contractions (either
+                        route); their factorisations and the extension stay FP64  */
   int skip_if_full;  /* 1: skip steps 1-2 when every bond is already at its largest
                         useful size min(chi_max, 2^(i+1), 2^(N-i-1))                */
   int apply_method;  /* tdvp_apply_method of the Krylov vectors (0: density matrix) */

@@ -1359,83 +1359,90 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
 // Two-site fitting of |phi> ~ O|psi> (the variational route of section I.C,
 // after Paeckel et al. 2019): mixed environments <phi|O|psi>, L[(a',al),a]
 // with a' on phi and a on psi, Rt[ga][b,b'] with b on psi and b' on phi.
-// Contractions in FP64.
+// Contractions in the working precision (FP64, or FP32 / BF16 inputs on
+// the mixed paths); the two-site tensors are split in FP64.
 
 // Lout[b',(be,b)] = sum conj(bra[a',s',b']) L[(a',al),a] W[al,be,s',s] ket[a,s,b]
+template <typename T>
 void fit_env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
                   const void* L, const void* bra, const void* ket, void* Lout, DBuf& f1, DBuf& f2, ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
-  f1.ensure((size_t)mlo * wl * 2 * mri * ZB);
-  f2.ensure((size_t)mlo * 2 * wr * mri * ZB);
+  const int cb = cbytes<T>();
+  f1.ensure((size_t)mlo * wl * 2 * mri * cb);
+  f2.ensure((size_t)mlo * 2 * wr * mri * cb);
   // T1[(a',al),(s,b)] = L[(a',al),a] ket[a,(s,b)]
   if (pm.g1) {   // with charges: batched over al
     kern::KMapScope ks(pm.g1);
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo, 2 * mri, mli, 1.0, L, (long long)wl * mli, mli, ket, 2LL * mri, 0,
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, mlo, 2 * mri, mli, 1.0, L, (long long)wl * mli, mli, ket, 2LL * mri, 0,
                        0.0, f1.p, (long long)wl * 2 * mri, 2LL * mri, wl);
   } else {
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 2 * mri, mli, 1.0, L, mli, 0, ket, 2LL * mri, 0, 0.0, f1.p,
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 2 * mri, mli, 1.0, L, mli, 0, ket, 2LL * mri, 0, 0.0, f1.p,
                        2LL * mri, 0, 1);
   }
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
-  kern::wapply<double>(s, tb.F, f1.p, f2.p, mlo, mri, (long long)wl * 2 * mri, 1, 2LL * mri, mri,
+  kern::wapply<T>(s, tb.F, f1.p, f2.p, mlo, mri, (long long)wl * 2 * mri, 1, 2LL * mri, mri,
                        2LL * wr * mri, 1, mri, (long long)wr * mri);
   // Lout[b',(be,b)] = sum_{(a',s')} conj(bra[(a',s'),b']) T2[(a',s'),(be,b)]
   kern::KMapScope ks(pm.g2);
-  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mro, wr * mri, 2 * mlo, 1.0, bra, mro, 0, f2.p, (long long)wr * mri, 0,
+  kern::gemm<T>(s, TDVP_OP_C, TDVP_OP_N, mro, wr * mri, 2 * mlo, 1.0, bra, mro, 0, f2.p, (long long)wr * mri, 0,
                      0.0, Lout, (long long)wr * mri, 0, 1);
 }
 
 // Rout[al][a,a'] = sum conj(bra[a',s',b']) W[al,be,s',s] Rt[be][b,b'] ket[a,s,b]
+template <typename T>
 void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
                    const void* Rt, const void* bra, const void* ket, void* Rout, DBuf& f1, DBuf& f2,
                    ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
-  f1.ensure((size_t)wr * 2 * mli * mro * ZB);
-  f2.ensure((size_t)wl * 2 * mli * mro * ZB);
+  const int cb = cbytes<T>();
+  f1.ensure((size_t)wr * 2 * mli * mro * cb);
+  f2.ensure((size_t)wl * 2 * mli * mro * cb);
   // U1[be][(a,s),b'] = ket[(a,s),b] Rt[be][b,b']   (batched over be)
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, mro, mri, 1.0, ket, mri, 0, Rt, mro, (long long)mri * mro, 0.0,
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, mro, mri, 1.0, ket, mri, 0, Rt, mro, (long long)mri * mro, 0.0,
                      f1.p, mro, 2LL * mli * mro, wr);
   // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
-  kern::wapply<double>(s, tb.B, f1.p, f2.p, mli, mro, 2LL * mro, 1, 2LL * mli * mro, mro, 2LL * mro, 1,
+  kern::wapply<T>(s, tb.B, f1.p, f2.p, mli, mro, 2LL * mro, 1, 2LL * mli * mro, mro, 2LL * mro, 1,
                        2LL * mli * mro, mro);
   // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(bra[a',(s',b')])
   kern::KMapScope ks(pm.g2);
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, wl * mli, mlo, 2 * mro, 1.0, f2.p, 2LL * mro, 0, bra, 2LL * mro, 0, 0.0,
+  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, wl * mli, mlo, 2 * mro, 1.0, f2.p, 2LL * mro, 0, bra, 2LL * mro, 0, 0.0,
                      Rout, mlo, 0, 1);
 }
 
 // Y[(a',t),(u,b')] = sum L[(a',al),a] W1[al,be,t,s] W2[be,ga,u,v] P[a,s,v,b] Rt[ga][b,b']:
 // the two-site tensor of phi that is closest to O|psi> in the current bases.
+template <typename T>
 void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int mlo, int mli, int wl, int wm, int wr,
                 int mri, int mro, const void* L, const void* Rt, const void* P, void* Y, DBuf& f1, DBuf& f2,
                 ProdMaps pm = {}) {
   hipStream_t s = ctx->stream;
+  const int cb = cbytes<T>();
   const long long big = std::max({(long long)mlo * wl * 4 * mri, (long long)mlo * 2 * wm * 2 * mri,
                                   (long long)mlo * 2 * 2 * wr * mri});
-  f1.ensure((size_t)big * ZB);
-  f2.ensure((size_t)big * ZB);
+  f1.ensure((size_t)big * cb);
+  f2.ensure((size_t)big * cb);
   // T1[(a',al),(s,v,b)] = L[(a',al),a] P[a,(s,v,b)]
   if (pm.g1) {   // with charges: batched over al
     kern::KMapScope ks(pm.g1);
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo, 4 * mri, mli, 1.0, L, (long long)wl * mli, mli, P, 4LL * mri, 0,
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, mlo, 4 * mri, mli, 1.0, L, (long long)wl * mli, mli, P, 4LL * mri, 0,
                        0.0, f1.p, (long long)wl * 4 * mri, 4LL * mri, wl);
   } else {
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 4 * mri, mli, 1.0, L, mli, 0, P, 4LL * mri, 0, 0.0, f1.p,
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, mlo * wl, 4 * mri, mli, 1.0, L, mli, 0, P, 4LL * mri, 0, 0.0, f1.p,
                        4LL * mri, 0, 1);
   }
   // T2[a',t,be,(v,b)] = sum W1[al,be,t,s] T1[a',al,s,(v,b)]
-  kern::wapply<double>(s, t1.F, f1.p, f2.p, mlo, 2LL * mri, (long long)wl * 4 * mri, 1, 4LL * mri, 2LL * mri,
+  kern::wapply<T>(s, t1.F, f1.p, f2.p, mlo, 2LL * mri, (long long)wl * 4 * mri, 1, 4LL * mri, 2LL * mri,
                        (long long)2 * wm * 2 * mri, 1, 2LL * mri, (long long)wm * 2 * mri);
   // T3[(a',t),u,ga,b] = sum W2[be,ga,u,v] T2[(a',t),be,v,b]
-  kern::wapply<double>(s, t2.F, f2.p, f1.p, 2LL * mlo, mri, (long long)wm * 2 * mri, 1, 2LL * mri, mri,
+  kern::wapply<T>(s, t2.F, f2.p, f1.p, 2LL * mlo, mri, (long long)wm * 2 * mri, 1, 2LL * mri, mri,
                        (long long)2 * wr * mri, 1, mri, (long long)wr * mri);
   // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b'] (with charges: batched over (t, u))
   kern::KMapScope ks(pm.g2);
   if (pm.g2)
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mlo, mro, wr * mri, 1.0, f1.p, 4LL * wr * mri, (long long)wr * mri, Rt,
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, mlo, mro, wr * mri, 1.0, f1.p, 4LL * wr * mri, (long long)wr * mri, Rt,
                        mro, 0, 0.0, Y, 4LL * mro, mro, 4);
   else
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 4 * mlo, mro, wr * mri, 1.0, f1.p, (long long)wr * mri, 0, Rt, mro, 0,
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 4 * mlo, mro, wr * mri, 1.0, f1.p, (long long)wr * mri, 0, Rt, mro, 0,
                        0.0, Y, mro, 0, 1);
 }
 
@@ -1444,6 +1451,7 @@ void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int
 // takes the eps / chi_max cut of the gauge moves.  The result is
 // left-canonical with its centre on the last site.  Returns the weight
 // discarded in the last pass.
+template <typename T>
 double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps, int chi_max, int passes,
                  tdvp_mps_s& out) {
   tdvp_ctx_s* ctx = W.ctx;
@@ -1453,6 +1461,37 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   if (passes < 1) TDVP_THROW(TDVP_ERR_ARG, "variational MPO application needs at least one pass");
   const double in_norm = W.sc.norm(in.site(N - 1), in.elems(N - 1));
   if (!std::isfinite(in_norm)) TDVP_THROW(TDVP_ERR_NUMERIC, "MPS with non-finite entries");
+  const int cb = cbytes<T>();
+  // working-precision copies of the ket (the input, left-canonical: its norm
+  // sits in the last site, which enters scaled to unit norm so that FP32
+  // cannot overflow; the result is normalised and every cut is relative)
+  std::vector<DBuf> Kt;
+  std::vector<const void*> Kp(N);
+  for (int i = 0; i < N; ++i) {
+    if (sizeof(T) == 8) {
+      Kp[i] = in.site(i);
+      continue;
+    }
+    Kt.emplace_back(ctx);
+    Kt.back().ensure((size_t)in.elems(i) * cb);
+    if (i == N - 1 && in_norm > 0.0) {
+      W.tmpC.ensure((size_t)in.elems(i) * ZB);
+      kern::zscale(s, W.tmpC.p, in.site(i), zc(1.0 / in_norm, 0.0), in.elems(i));
+      kern::z2c(s, Kt.back().p, W.tmpC.p, in.elems(i));
+    } else {
+      kern::z2c(s, Kt.back().p, in.site(i), in.elems(i));
+    }
+    Kp[i] = Kt.back().p;
+  }
+  // the bra's sites (FP64 masters, changing as the passes go) in the working
+  // precision, converted where an environment reads them
+  DBuf braT(ctx);
+  auto bra = [&](int i) -> const void* {
+    if (sizeof(T) == 8) return out.site(i);
+    braT.ensure((size_t)out.elems(i) * cb);
+    kern::z2c(s, braT.p, out.site(i), out.elems(i));
+    return braT.p;
+  };
   out.ctx = ctx;
   out.N = N;
   out.m = in.m;
@@ -1470,9 +1509,9 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
     Ls.emplace_back(ctx);
     Rs.emplace_back(ctx);
   }
-  set_one(ctx, Ls[0], ZB);
-  set_one(ctx, Rs[N], ZB);
-  DBuf f1(ctx), f2(ctx), P(ctx), Th(ctx), X(ctx), Y(ctx);
+  set_one(ctx, Ls[0], cb);
+  set_one(ctx, Rs[N], cb);
+  DBuf f1(ctx), f2(ctx), P(ctx), Th(ctx), Th64(ctx), X(ctx), Y(ctx);
   // with charges, the products walk their nonzero blocks
   const auto& qw = op.host.qw;
   PairMaps fm(ctx);
@@ -1497,54 +1536,59 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
     return fm.set(ctx, g1, g2);
   };
   for (int i = N - 1; i >= 2; --i) {
-    Rs[i].ensure((size_t)op.w(i) * in.m[i] * out.m[i] * ZB);
-    fit_env_right(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1], Rs[i + 1].p,
-                  out.site(i), in.site(i), Rs[i].p, f1, f2, right_maps(i));
+    Rs[i].ensure((size_t)op.w(i) * in.m[i] * out.m[i] * cb);
+    fit_env_right<T>(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1], Rs[i + 1].p,
+                     bra(i), Kp[i], Rs[i].p, f1, f2, right_maps(i));
   }
-  // two-site tensor of phi at (i, i+1) from the current environments
-  auto local = [&](int i) {
+  // two-site tensor of phi at (i, i+1) from the current environments (FP64
+  // for the split)
+  auto local = [&](int i) -> double* {
     const int mli = in.m[i], mc = in.m[i + 1], mri = in.m[i + 2], mlo = out.m[i], mro = out.m[i + 2];
-    P.ensure((size_t)mli * 4 * mri * ZB);
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, 2 * mri, mc, 1.0, in.site(i), mc, 0, in.site(i + 1),
-                       2LL * mri, 0, 0.0, P.p, 2LL * mri, 0, 1);
-    Th.ensure((size_t)mlo * 4 * mro * ZB);
-    fit_local2(ctx, op.tab[i], op.tab[i + 1], mlo, mli, op.w(i), op.w(i + 1), op.w(i + 2), mri, mro, Ls[i].p,
-               Rs[i + 2].p, P.p, Th.p, f1, f2, local_maps(i));
+    P.ensure((size_t)mli * 4 * mri * cb);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, 2 * mri, mc, 1.0, Kp[i], mc, 0, Kp[i + 1], 2LL * mri, 0, 0.0, P.p,
+                  2LL * mri, 0, 1);
+    Th.ensure((size_t)mlo * 4 * mro * cb);
+    fit_local2<T>(ctx, op.tab[i], op.tab[i + 1], mlo, mli, op.w(i), op.w(i + 1), op.w(i + 2), mri, mro, Ls[i].p,
+                  Rs[i + 2].p, P.p, Th.p, f1, f2, local_maps(i));
+    if (sizeof(T) == 8) return Th.as<double>();
+    Th64.ensure((size_t)mlo * 4 * mro * ZB);
+    kern::c2z(s, Th64.p, Th.p, (long long)mlo * 4 * mro);
+    return Th64.as<double>();
   };
   double disc = 0.0;
   for (int pass = 0; pass < passes; ++pass) {
     disc = 0.0;
     if (pass % 2 == 0) {   // left to right: phi_i left-canonical, centre moves on
       for (int i = 0; i + 1 < N; ++i) {
-        local(i);
+        const double* th = local(i);
         const int mlo = out.m[i], mro = out.m[i + 2];
         std::vector<int> qc, qk;
         if (sym) qc = fuse_sx(out.q[i + 2], -1);
-        const int k = split_left(W, Th.as<double>(), mlo, 2 * mro, eps, chi_max, X, Y, &disc,
+        const int k = split_left(W, th, mlo, 2 * mro, eps, chi_max, X, Y, &disc,
                                  sym ? &out.q[i] : nullptr, sym ? &qc : nullptr, &qk);
         std::swap(out.t[i], X);
         std::swap(out.t[i + 1], Y);
         out.m[i + 1] = k;
         if (sym) out.q[i + 1] = qk;
-        Ls[i + 1].ensure((size_t)k * op.w(i + 1) * in.m[i + 1] * ZB);
-        fit_env_left(ctx, op.tab[i], mlo, in.m[i], op.w(i), op.w(i + 1), k, in.m[i + 1], Ls[i].p, out.site(i),
-                     in.site(i), Ls[i + 1].p, f1, f2, left_maps(i));
+        Ls[i + 1].ensure((size_t)k * op.w(i + 1) * in.m[i + 1] * cb);
+        fit_env_left<T>(ctx, op.tab[i], mlo, in.m[i], op.w(i), op.w(i + 1), k, in.m[i + 1], Ls[i].p, bra(i), Kp[i],
+                        Ls[i + 1].p, f1, f2, left_maps(i));
       }
     } else {               // right to left: phi_{i+1} right-canonical
       for (int i = N - 2; i >= 0; --i) {
-        local(i);
+        const double* th = local(i);
         const int mlo = out.m[i], mro = out.m[i + 2];
         std::vector<int> qr, qk;
         if (sym) qr = fuse_xs(out.q[i], 1);
-        const int k = split_right(W, Th.as<double>(), 2 * mlo, mro, eps, chi_max, X, Y, &disc, sym ? &qr : nullptr,
+        const int k = split_right(W, th, 2 * mlo, mro, eps, chi_max, X, Y, &disc, sym ? &qr : nullptr,
                                   sym ? &out.q[i + 2] : nullptr, &qk);
         std::swap(out.t[i], X);
         std::swap(out.t[i + 1], Y);
         out.m[i + 1] = k;
         if (sym) out.q[i + 1] = qk;
-        Rs[i + 1].ensure((size_t)op.w(i + 1) * in.m[i + 1] * k * ZB);
-        fit_env_right(ctx, op.tab[i + 1], k, in.m[i + 1], op.w(i + 1), op.w(i + 2), mro, in.m[i + 2], Rs[i + 2].p,
-                      out.site(i + 1), in.site(i + 1), Rs[i + 1].p, f1, f2, right_maps(i + 1));
+        Rs[i + 1].ensure((size_t)op.w(i + 1) * in.m[i + 1] * k * cb);
+        fit_env_right<T>(ctx, op.tab[i + 1], k, in.m[i + 1], op.w(i + 1), op.w(i + 2), mro, in.m[i + 2], Rs[i + 2].p,
+                         bra(i + 1), Kp[i + 1], Rs[i + 1].p, f1, f2, right_maps(i + 1));
       }
     }
   }
@@ -1742,7 +1786,7 @@ void expand_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const t
     const tdvp_mps_s* prev = &psi;
     for (int l = 0; l + 1 < p.k; ++l) {
       st.discarded_K += p.apply_method == TDVP_APPLY_FIT
-                            ? fit_apply(W, *prev, op, p.eps_K, p.chi_max, std::max(1, p.fit_passes), kv[l])
+                            ? fit_apply<T>(W, *prev, op, p.eps_K, p.chi_max, std::max(1, p.fit_passes), kv[l])
                             : denmat_apply<T>(W, *prev, op, p.eps_K, p.chi_max, kv[l]);
       prev = &kv[l];
       for (int b = 0; b <= N; ++b) st.krylov_max_bond = std::max(st.krylov_max_bond, kv[l].m[b]);
@@ -1800,7 +1844,7 @@ void run_apply_mpo(tdvp_ctx_s* ctx, const tdvp_mps_s& in, const tdvp_mpo_s& op, 
   Work W(ctx);
   double d;
   if (method == TDVP_APPLY_FIT) {
-    d = fit_apply(W, in, op, eps, chi_max, passes, out);
+    d = fit_apply<double>(W, in, op, eps, chi_max, passes, out);
   } else {
     // the density-matrix route reads the norm from the last site of a
     // left-canonical input

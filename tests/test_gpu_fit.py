@@ -123,10 +123,14 @@ def test_apply_rejects_bad_arguments(env):
     assert lib.tdvp_apply_mpo(ctx.h, g.h, other.h, 1, 1e-8, 8, 1, C.byref(h), C.byref(d)) == T.TDVP_ERR_ARG
 
 
-def test_gse_with_fitted_krylov_vectors_matches_oracle(env):
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_gse_with_fitted_krylov_vectors_matches_oracle(env, prec):
     """2x6 ladder, Neel quench, k = 3 with the Krylov vectors fitted (three
-    passes) on both sides: fidelity, energy and bonds follow the oracle."""
+    passes) on both sides: fidelity, energy and bonds follow the oracle.  The
+    mixed paths run the fit's contractions (and the sweep's) in FP32 or with
+    BF16 inputs; their splits stay FP64."""
     T, ctx = env
+    tol_f, tol_e, bond_frac = {"fp64": (1e-8, 1e-9, 10), "fp32": (1e-5, 1e-5, 5), "bf16x3": (2e-5, 2e-4, 5)}[prec]
     from oracle import gse, mpo, mps as M, observables as O
     w = I.workload(0)
     N = w.lattice.n_sites
@@ -140,11 +144,12 @@ def test_gse_with_fitted_krylov_vectors_matches_oracle(env):
     for step in range(6):
         psi, _ = gse.gse_step(psi, Ws, Wop, w.dt, 3, w.eps_K, w.eps_M, w.eps, w.chi_max, 1e-12, 30, w.normalize,
                               apply="fit", fit_passes=3)
-        T.tdvp_expand_basis(ctx, [g], [op], 3, w.eps_K, w.eps_M, w.chi_max, "fp64", apply="fit", fit_passes=3)
-        T.tdvp_sweep(ctx, [g], [H], w.dt, w.eps, w.chi_max, 1e-12, 30, "fp64", w.normalize)
+        T.tdvp_expand_basis(ctx, [g], [op], 3, w.eps_K, w.eps_M, w.chi_max, prec, apply="fit", fit_passes=3)
+        T.tdvp_sweep(ctx, [g], [H], w.dt, w.eps, w.chi_max, 1e-12, 30, prec, w.normalize)
         out = T.tdvp_mps_to_host(g)
         t += abs(w.dt)
-        assert 1 - M.fidelity(out, psi) < 1e-8 * t + 1e-12
-        assert abs(O.energy(out, Ws) - O.energy(psi, Ws)) < 1e-9
+        e_ref = O.energy(psi, Ws)
+        assert 1 - M.fidelity(out, psi) < tol_f * t + 1e-12, prec
+        assert abs(O.energy(out, Ws) - e_ref) < tol_e * max(1.0, abs(e_ref)), prec
         bg, bo = M.bond_dims(out), M.bond_dims(psi)
-        assert all(abs(a - b) <= max(2, b // 10) for a, b in zip(bg, bo)), (bg, bo)
+        assert all(abs(a - b) <= max(2, b // bond_frac) for a, b in zip(bg, bo)), (prec, bg, bo)
