@@ -385,7 +385,9 @@ tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int m
  * is the conjugated eigenvector v_j^dagger for the j-th largest eigenvalue;
  * lam: host double[n] out, descending.  method: 0 automatic (cooperative
  * tridiagonalisation and tridiagonal divide and conquer for 2 <= n <= 512,
- * rocSOLVER zheevd otherwise or when the first fails its check), 1 the
+ * the same reduction with rocSOLVER's tridiagonal divide and conquer for
+ * 512 < n <= 1024, rocSOLVER zheevd otherwise or when the first fails its
+ * check), 1 the
  * first only (TDVP_ERR_NUMERIC when not applicable), 2 rocSOLVER zheevd
  * only, 3 cooperative tridiagonalisation with rocSOLVER's tridiagonal divide
  * and conquer (TDVP_ERR_NUMERIC when not applicable).  Synchronous. */

@@ -9,6 +9,7 @@
 // entries between them are exact zeros, so including them changes nothing).
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "engine.h"
 
@@ -62,25 +63,41 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
   out.tile_macs = 0.0;
   std::vector<int> mark(R, -1);
   std::vector<Run> sel;
+  // the merged intervals depend only on the set of charges a tile meets, and
+  // most tiles meet one or two: merge once per distinct set
+  struct Merged {
+    std::vector<int> iv;
+    long long klen = 0;
+  };
+  std::map<std::vector<int>, Merged> cache;
+  std::vector<int> common;
   for (int a = 0; a < tm; ++a) {
     for (int c : rs[a]) mark[c] = a;
     const int rows = std::min(M, (a + 1) * TILE) - a * TILE;
     for (int b = 0; b < tn; ++b) {
-      sel.clear();
+      common.clear();
       for (int c : cs[b])
-        if (mark[c] == a) sel.insert(sel.end(), runs[c].begin(), runs[c].end());
-      std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
-      const int cols = std::min(N, (b + 1) * TILE) - b * TILE;
-      long long klen = 0;
-      for (size_t j = 0; j < sel.size();) {
-        Run cur = sel[j++];
-        while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
-        out.iv.push_back(cur.b);
-        out.iv.push_back(cur.e);
-        klen += cur.e - cur.b;
+        if (mark[c] == a) common.push_back(c);
+      std::sort(common.begin(), common.end());
+      auto it = cache.find(common);
+      if (it == cache.end()) {
+        Merged m;
+        sel.clear();
+        for (int c : common) sel.insert(sel.end(), runs[c].begin(), runs[c].end());
+        std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
+        for (size_t j = 0; j < sel.size();) {
+          Run cur = sel[j++];
+          while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
+          m.iv.push_back(cur.b);
+          m.iv.push_back(cur.e);
+          m.klen += cur.e - cur.b;
+        }
+        it = cache.emplace(common, std::move(m)).first;
       }
+      const int cols = std::min(N, (b + 1) * TILE) - b * TILE;
+      out.iv.insert(out.iv.end(), it->second.iv.begin(), it->second.iv.end());
       out.off[(size_t)a * tn + b + 1] = (int)(out.iv.size() / 2);
-      out.tile_macs += (double)rows * cols * klen;
+      out.tile_macs += (double)rows * cols * it->second.klen;
     }
     for (int c : rs[a]) mark[c] = -1;
   }
@@ -154,6 +171,15 @@ void split_kmap(KMapHost& h) {
   h.splits = (int)S;
 }
 
+DevKMap::~DevKMap() {
+  // the last upload may still be in flight out of the staging buffer
+  if (uploaded) {
+    (void)hipEventSynchronize(uploaded);
+    (void)hipEventDestroy(uploaded);
+  }
+  if (stage) (void)hipHostFree(stage);
+}
+
 void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
   // work items (tile, part, first interval, end), longest K first
   const int E = (int)h.off.size() - 1, S = std::max(h.splits, 1);
@@ -177,20 +203,33 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
     items.push_back(h.off[e]);
     items.push_back(h.off[e + 1]);
   }
-  const size_t ni = items.size(), nv = h.iv.size(), ns = h.nsplit.size();
-  buf.ensure(sizeof(int) * (ni + nv + ns + 4));
+  const size_t ni = items.size(), nv = h.iv.size(), ns = h.nsplit.size(), nt = ni + nv + ns;
+  // one upload from pinned memory, ordered on the stream after the products
+  // that still read the previous map; the host waits only for the previous
+  // upload out of the staging buffer (long done in the common case)
+  if (uploaded) HIP_CHECK(hipEventSynchronize(uploaded));
+  else HIP_CHECK(hipEventCreateWithFlags(&uploaded, hipEventDisableTiming));
+  if (stage_cap < nt) {
+    if (stage) HIP_CHECK(hipHostFree(stage));
+    stage = nullptr;
+    stage_cap = 0;
+    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&stage), sizeof(int) * std::max<size_t>(nt, 1024),
+                            hipHostMallocDefault));
+    stage_cap = std::max<size_t>(nt, 1024);
+  }
+  std::copy(items.begin(), items.end(), stage);
+  std::copy(h.iv.begin(), h.iv.end(), stage + ni);
+  std::copy(h.nsplit.begin(), h.nsplit.end(), stage + ni + nv);
+  buf.ensure(sizeof(int) * (nt + 4));
   int* base = buf.as<int>();   // items first (16-byte aligned)
-  if (ni) HIP_CHECK(hipMemcpyAsync(base, items.data(), sizeof(int) * ni, hipMemcpyHostToDevice, ctx->stream));
-  if (nv) HIP_CHECK(hipMemcpyAsync(base + ni, h.iv.data(), sizeof(int) * nv, hipMemcpyHostToDevice, ctx->stream));
-  if (ns)
-    HIP_CHECK(hipMemcpyAsync(base + ni + nv, h.nsplit.data(), sizeof(int) * ns, hipMemcpyHostToDevice, ctx->stream));
+  if (nt) HIP_CHECK(hipMemcpyAsync(base, stage, sizeof(int) * nt, hipMemcpyHostToDevice, ctx->stream));
+  HIP_CHECK(hipEventRecord(uploaded, ctx->stream));
   map.part = nullptr;
   map.part_bytes = 0;
   if (h.splits > 1) {   // partial products, sized for complex128
     map.part_bytes = (size_t)h.splits * h.batch * h.M * h.N * 16;
     map.part = part.ensure(map.part_bytes);
   }
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));   // the host vectors may die
   map.items = reinterpret_cast<const int4*>(base);
   map.n_items = (int)(ni / 4);
   map.iv = base + ni;

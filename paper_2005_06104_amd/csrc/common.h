@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -102,6 +103,15 @@ struct tdvp_ctx_s {
 extern thread_local tdvp_ctx_s* tl_exec_ctx;
 
 // Growable device buffer owned through the context's allocator.
+// Named host range of a phase (shown by rocprofv3 --marker-trace; a few
+// nanoseconds when no tool listens).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 struct DBuf {
   tdvp_ctx_s* ctx = nullptr;
   void* p = nullptr;
@@ -206,7 +216,7 @@ template <typename T>
 void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda, const void* B, long long ldb,
                void* C, long long ldc, void* ws = nullptr, size_t ws_bytes = 0);
 // Householder tridiagonalisation of a Hermitian n x n complex128 matrix
-// (row-major, full storage; n <= 512) in one cooperative launch:
+// (row-major, full storage; n <= 1024) in one cooperative launch:
 // H = Q T Q^H with T real tridiagonal (diagonal D[n], off-diagonal E[n-1]) and
 // Q (row-major) unitary.  scratch holds tridiag_scratch_bytes(n); *err is set
 // nonzero when a grid barrier wait ran out.  Returns the launch status.
@@ -405,7 +415,8 @@ void svd_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* U, s
 // eigh of row-major Hermitian H (n x n): eigenvalues descending (host) and the
 // matrix of eigenvectors-as-rows-conjugated: rows[j] = v_j^dagger (row-major n x n).
 // method: EIGH_AUTO (cooperative tridiagonalisation and tridiagonal divide
-// and conquer for 2 <= n <= 512, rocSOLVER zheevd otherwise or when the first
+// and conquer for 2 <= n <= 512, with rocSOLVER's tridiagonal divide and
+// conquer for 512 < n <= 1024, rocSOLVER zheevd otherwise or when the first
 // fails validation), EIGH_TRIDIAG (the first only), EIGH_HEEVD (rocSOLVER
 // only), EIGH_TRIDIAG_LIB (cooperative tridiagonalisation, rocSOLVER dstedc).
 enum { EIGH_AUTO = 0, EIGH_TRIDIAG = 1, EIGH_HEEVD = 2, EIGH_TRIDIAG_LIB = 3 };

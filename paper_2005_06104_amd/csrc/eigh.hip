@@ -1,5 +1,5 @@
 // Hermitian eigendecomposition for the mid-size Gram and density matrices of
-// the method (n <= 512): Householder reduction to real tridiagonal form by one
+// the method (n <= 1024; above 512 with the Q rows outside LDS): Householder reduction to real tridiagonal form by one
 // cooperative launch, the tridiagonal eigenproblem by divide and conquer
 // (tdeig.hip; rocSOLVER's on request), and one MFMA GEMM for the back
 // transformation.
@@ -35,6 +35,13 @@ namespace {
 constexpr int TNT = 256;            // threads per workgroup
 constexpr int TD_LDS = 8192;        // complex128 slots for the A and Q rows (128 KiB)
 constexpr int TD_NMAX = 512;
+// Larger matrices (512 < n <= 1024): four rows per workgroup, up to 256
+// workgroups (one per CU); the A rows stay in LDS (64 KiB) and the Q rows of
+// the workgroup are accumulated in place in the output (each row read and
+// written only by the threads that own it, from L2).
+constexpr int TD_LDS_BIG = 4096;
+constexpr int TD_NMAX_BIG = 1024;
+constexpr int TD_G_BIG = 256;
 constexpr int TD_ROWS = 128;        // rows per workgroup at most
 constexpr unsigned SPIN_LIMIT = 1u << 22;
 
@@ -122,9 +129,10 @@ __device__ inline double2 hh_v(int c, int k, double2 row_c, double2 sc) {
 // between two copies, tagged k + 1: a workgroup publishes column k + 1 only
 // after it has read everything of column k, so no copy is overwritten while
 // a reader still needs it.
+template <int NMAX, int LDS, bool QLDS>
 __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
-  __shared__ double2 sM[TD_LDS];        // A rows [R][n], then Q rows [R][n]
-  __shared__ double2 sv[TD_NMAX], sw[TD_NMAX], srow[TD_NMAX];
+  __shared__ double2 sM[LDS];           // A rows [R][n], then (QLDS) Q rows [R][n]
+  __shared__ double2 sv[NMAX], sw[NMAX], srow[NMAX];
   __shared__ double sred[TNT / 64];     // per-wave |row[k+2:]|^2 of the pivot row
   __shared__ double2 s_xv[TNT / 64];    // per-wave parts of x^H v
   __shared__ int s_fail;
@@ -132,7 +140,10 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
   const int n = a.n, G = a.G, R = a.R, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   double2* sA = sM;
-  double2* sQ = sM + (size_t)R * n;
+  // Q row j of this workgroup: in LDS, or row g + j G of the output
+  auto qrow_at = [&](int j) -> double2* {
+    return QLDS ? sM + (size_t)R * n + (size_t)j * n : a.Q + (size_t)(g + j * G) * n;
+  };
   const int nrow = (n - g + G - 1) / G;   // rows r = g + j G < n
   // T threads per own row (a power of two, within one wave): thread tid works
   // on local row rj = tid / T, columns rt, rt + T, ...
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     const int r = g + j * G;
     for (int c = tid; c < n; c += TNT) {
       sA[j * n + c] = a.H[(size_t)r * n + c];
-      sQ[j * n + c] = double2{r == c ? 1.0 : 0.0, 0.0};
+      qrow_at(j)[c] = double2{r == c ? 1.0 : 0.0, 0.0};
     }
   }
   {
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     if (rj < nrow) {
       double2 sa{0.0, 0.0}, sq{0.0, 0.0};
       const double2* arow = sA + rj * n;
-      const double2* qrow = sQ + rj * n;
+      const double2* qrow = qrow_at(rj);
       for (int c = k + 1 + rt; c < n; c += T) {
         const double2 v = hh_v(c, k, srow[c], sc), m = arow[c], q = qrow[c];
         if (rj == 0) sv[c] = v;
@@ -210,7 +221,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
 
     // ---- while the others arrive: Q <- Q H_k = Q - tau (Q v) v^H on the own rows
     if (rj < nrow) {
-      double2* qrow = sQ + rj * n;
+      double2* qrow = qrow_at(rj);
       for (int c = k + 1 + rt; c < n; c += T) {
         const double2 d = cmulc(tqs, sv[c]);
         qrow[c].x -= d.x;
@@ -219,7 +230,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
     }
     // ---- gather this column's x and pivot row as they arrive (every thread
     // its own entries)
-    constexpr int NQ = (TD_NMAX + TNT - 1) / TNT;
+    constexpr int NQ = (NMAX + TNT - 1) / TNT;
     double2 xq[NQ], rq[NQ];
     {
       bool gx[NQ], gr[NQ];
@@ -282,7 +293,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       const double2 a2x = cmul(tau, t);
       const double2 a2{-0.5 * a2x.x, -0.5 * a2x.y};
 #pragma unroll
-      for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
+      for (int q = 0; q < (NMAX + TNT - 1) / TNT; ++q) {
         const int c = k + 1 + tid + q * TNT;
         if (c < n) {
           const double2 tv = cmul(a2, sv[c]);
@@ -293,7 +304,7 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
       const double2 v1 = sv[k + 1], w1 = sw[k + 1];
       double ssq = 0.0;
 #pragma unroll
-      for (int q = 0; q < (TD_NMAX + TNT - 1) / TNT; ++q) {
+      for (int q = 0; q < (NMAX + TNT - 1) / TNT; ++q) {
         const int c = k + 1 + tid + q * TNT;
         if (c < n) {
           const double2 d1 = cmulc(v1, sw[c]), d2 = cmulc(w1, sv[c]);
@@ -320,10 +331,11 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
 
   if (alive) {
     if (g == 0 && tid == 0) a.D[n - 1] = srow[n - 1].x;
-    for (int j = 0; j < nrow; ++j) {
-      const int r = g + j * G;
-      for (int c = tid; c < n; c += TNT) a.Q[(size_t)r * n + c] = sQ[j * n + c];
-    }
+    if (QLDS)
+      for (int j = 0; j < nrow; ++j) {
+        const int r = g + j * G;
+        for (int c = tid; c < n; c += TNT) a.Q[(size_t)r * n + c] = qrow_at(j)[c];
+      }
   }
 }
 
@@ -374,6 +386,11 @@ __global__ void td_reset_kernel(unsigned* w, int nw, int* err) {
 namespace kern {
 
 int tridiag_groups(int n) {
+  if (n > TD_NMAX && n <= TD_NMAX_BIG) {
+    const int G = std::min(TD_G_BIG, (n + 3) / 4);
+    const int R = (n + G - 1) / G;
+    return R * n <= TD_LDS_BIG ? G : 0;
+  }
   if (n < 1 || n > TD_NMAX) return 0;
   // The per-column work of a workgroup grows with its share of the rows and
   // the exchange with the number of workgroups: four rows per workgroup (one
@@ -410,7 +427,9 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
   hipLaunchKernelGGL(td_reset_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, reinterpret_cast<unsigned*>(a.xv), nw,
                      err);
   void* args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tridiag_kernel), dim3(G), dim3(TNT), args, 0, s);
+  const void* kfn = n > TD_NMAX ? reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX_BIG, TD_LDS_BIG, false>)
+                                : reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX, TD_LDS, true>);
+  return hipLaunchCooperativeKernel(kfn, dim3(G), dim3(TNT), args, 0, s);
 }
 
 void shift_by_trace(hipStream_t s, void* G, int n, double frac, const void* S) {

@@ -616,6 +616,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int rows = 2 * ml, cols = mr, kk = std::min(rows, cols);
+  Range r_("gauge.split_left");
   const bool sym = qc != nullptr;
   // the exact moves keep the columns as the new bond: with charges only when
   // they ascend and C has at least as many rows as columns
@@ -704,6 +705,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
 int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_max, DBuf& L, DBuf& B, double* disc,
                 const std::vector<int>* qr = nullptr, const std::vector<int>* qb = nullptr,
                 std::vector<int>* qk = nullptr) {
+  Range r_("gauge.split_right");
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int rows = ml, cols = 2 * mr, kk = std::min(rows, cols);
@@ -777,6 +779,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
 }
 
 void left_canonicalize(Work& W, tdvp_mps_s& psi) {
+  Range r_("canonicalize.left");
   tdvp_ctx_s* ctx = W.ctx;
   DBuf A(ctx), R(ctx), nxt(ctx);
   double disc = 0.0;
@@ -794,6 +797,7 @@ void left_canonicalize(Work& W, tdvp_mps_s& psi) {
 }
 
 void right_canonicalize(Work& W, tdvp_mps_s& psi) {
+  Range r_("canonicalize.right");
   tdvp_ctx_s* ctx = W.ctx;
   DBuf Lm(ctx), B(ctx), prv(ctx);
   double disc = 0.0;
@@ -871,6 +875,7 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
   PairMaps hmap(ctx), kmap(ctx), emap(ctx);
   const auto& qw = H.host.qw;
   auto build_R = [&](int i) {  // Rt[i] from Rt[i+1] and site i
+    Range r_("sweep.env_right");
     const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
     ensure_ws(ml, wl, wr, mr);
     R[i].ensure((size_t)wl * ml * ml * cb);
@@ -885,6 +890,7 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p, {}, pm);
   };
   auto build_L = [&](int i) {  // L[i+1] from L[i] and site i
+    Range r_("sweep.env_left");
     const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
     ensure_ws(ml, wl, wr, mr);
     L[i + 1].ensure((size_t)mr * wr * mr * cb);
@@ -903,6 +909,7 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     if (unconv) ++st.n_unconverged;   // strict mode reports it once the sweep is complete
   };
   auto evolve_site = [&](int i, zc step) {
+    Range r_("sweep.site_evolution");
     const int ml = psi.m[i], mr = psi.m[i + 1], wl = H.w(i), wr = H.w(i + 1);
     const long long n = psi.elems(i);
     ensure_ws(ml, wl, wr, mr);
@@ -939,6 +946,7 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
   // (charges qb): one of them is the basis before the gauge move
   auto evolve_bond = [&](int b, void* X, int ml, int mr, zc step, const std::vector<int>* qa,
                          const std::vector<int>* qb) {
+    Range r_("sweep.bond_evolution");
     // K_eff on bond b with L[b] (ml x w x ml) and Rt[b] (w x mr x mr)
     const int w = H.w(b);
     const long long n = (long long)ml * mr;
@@ -1366,6 +1374,7 @@ double denmat_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double 
 template <typename T>
 void fit_env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
                   const void* L, const void* bra, const void* ket, void* Lout, DBuf& f1, DBuf& f2, ProdMaps pm = {}) {
+  Range r_("fit.env_left");
   hipStream_t s = ctx->stream;
   const int cb = cbytes<T>();
   f1.ensure((size_t)mlo * wl * 2 * mri * cb);
@@ -1393,6 +1402,7 @@ template <typename T>
 void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int wl, int wr, int mro, int mri,
                    const void* Rt, const void* bra, const void* ket, void* Rout, DBuf& f1, DBuf& f2,
                    ProdMaps pm = {}) {
+  Range r_("fit.env_right");
   hipStream_t s = ctx->stream;
   const int cb = cbytes<T>();
   f1.ensure((size_t)wr * 2 * mli * mro * cb);
@@ -1415,6 +1425,7 @@ template <typename T>
 void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int mlo, int mli, int wl, int wm, int wr,
                 int mri, int mro, const void* L, const void* Rt, const void* P, void* Y, DBuf& f1, DBuf& f2,
                 ProdMaps pm = {}) {
+  Range r_("fit.local");
   hipStream_t s = ctx->stream;
   const int cb = cbytes<T>();
   const long long big = std::max({(long long)mlo * wl * 4 * mri, (long long)mlo * 2 * wm * 2 * mri,
@@ -1454,6 +1465,7 @@ void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int
 template <typename T>
 double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps, int chi_max, int passes,
                  tdvp_mps_s& out) {
+  Range r_("fit.apply");
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int N = in.N;
@@ -1607,6 +1619,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
 // rows first within a charge) so that the new bond lists its charges in
 // ascending order.
 void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps_M, int chi_max, int* n_added) {
+  Range r_("expand.extension");
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   const int N = psi.N;

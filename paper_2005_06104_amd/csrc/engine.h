@@ -119,7 +119,14 @@ struct DevKMap {
   DBuf buf, part;   // the map; the partial products of a split map (complex128-sized)
   kern::KMap map;
   double exact_flops = 0.0, tile_flops = 0.0;
+  // pinned staging of the upload (reused once the previous upload is done)
+  int* stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t uploaded = nullptr;
   explicit DevKMap(tdvp_ctx_s* c) : buf(c), part(c) {}
+  ~DevKMap();
+  DevKMap(const DevKMap&) = delete;
+  DevKMap& operator=(const DevKMap&) = delete;
   void set(tdvp_ctx_s* ctx, const KMapHost& h);
   const kern::KMap* get() const { return map.items ? &map : nullptr; }
 };

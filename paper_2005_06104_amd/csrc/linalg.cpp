@@ -464,7 +464,8 @@ bool eigh_rows_desc_tridiag(tdvp_ctx_s* ctx, const void* H, int n, std::vector<d
     (void)hipGetLastError();
     return false;
   }
-  if (lib_tridiagonal) {
+  // the own divide and conquer takes n <= 512; above, rocSOLVER's
+  if (lib_tridiagonal || kern::tridiag_eig_scratch_bytes(n) == 0) {
     blas_check(rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, n, dD, dE, Z, n, dinfo), "dstedc");
   } else if (kern::tridiag_eig(ctx->stream, dD, dE, n, Z, scratch) != hipSuccess) {
     (void)hipGetLastError();
@@ -553,7 +554,7 @@ void eigh_rows_desc_heevd(tdvp_ctx_s* ctx, const void* H, int n, std::vector<dou
 void eigh_rows_desc(tdvp_ctx_s* ctx, const void* H, int n, std::vector<double>& lam, void* rows, DBuf& work,
                     int method) {
   // the cooperative reduction is at least as fast as the library route for
-  // every size it supports (n <= 512)
+  // every size it supports (n <= 1024)
   const bool try_tridiag = method == EIGH_TRIDIAG || method == EIGH_AUTO || method == EIGH_TRIDIAG_LIB;
   if (try_tridiag && eigh_rows_desc_tridiag(ctx, H, n, lam, rows, work, method == EIGH_TRIDIAG_LIB)) return;
   if (method == EIGH_TRIDIAG || method == EIGH_TRIDIAG_LIB)

@@ -1,6 +1,6 @@
 """Hermitian eigendecomposition on the device (tdvp_eigh): the cooperative
 Householder tridiagonalisation with the own tridiagonal divide and conquer
-(method 1) or rocSOLVER's (method 3), and the rocSOLVER route (2), against the
+(method 1; rocSOLVER's above n = 512) or rocSOLVER's (method 3), and the rocSOLVER route (2), against the
 eigenvalues of numpy's LAPACK eigensolver, orthonormality and reconstruction,
 on Gram matrices with decaying spectra, exact multiplets, rank deficiency,
 graded spectra, tight clusters, the zero matrix and already-reduced (diagonal /
@@ -96,7 +96,18 @@ def test_eigh_routes(env, kind, n, method):
     _check(T, torch, ctx, CASES[kind](n, 7 * n + len(kind)), method)
 
 
-@pytest.mark.parametrize("n", [1, 513, 700])
+@pytest.mark.parametrize("kind", sorted(CASES))
+@pytest.mark.parametrize("n", [513, 700, 1024])
+@pytest.mark.parametrize("method", [1, 3])
+def test_eigh_routes_large(env, kind, n, method):
+    # above 512 the reduction keeps its Q rows in the output (four rows per
+    # workgroup, up to 256 workgroups) and the tridiagonal problem goes to
+    # rocSOLVER's divide and conquer
+    T, torch, ctx = env
+    _check(T, torch, ctx, CASES[kind](n, 7 * n + len(kind)), method)
+
+
+@pytest.mark.parametrize("n", [1, 513, 700, 1025])
 def test_eigh_auto_outside_cooperative_range(env, n):
     T, torch, ctx = env
     _check(T, torch, ctx, _gram(n, n), 0)
@@ -104,7 +115,7 @@ def test_eigh_auto_outside_cooperative_range(env, n):
 
 def test_eigh_cooperative_route_refuses_large(env):
     T, torch, ctx = env
-    H = _gram(513, 1)
+    H = _gram(1025, 1)
     dH = torch.from_numpy(H).cuda()
     with pytest.raises(T.TdvpError):
         T.tdvp_eigh(ctx, dH, torch.zeros_like(dH), 1)
