@@ -310,6 +310,19 @@ void kmap_env_left_gemm2(const std::vector<int>& qlo, const std::vector<int>& qr
   build_kmap(qro, fuse2(qlo, kPhys, 1, 1), fuse2(qwr, qri, 1, 1), out);
   split_kmap(out);
 }
+// ket[(a,s),b] Rt[be][b,b'] batched over be: columns b' need q(b') - q(be)
+void kmap_env_right_gemm1(const std::vector<int>& qli, const std::vector<int>& qri, const std::vector<int>& qwr,
+                          const std::vector<int>& qro, KMapHost& out) {
+  const std::vector<int> rq = fuse2(qli, kPhys, 1, 1);
+  std::vector<KMapHost> parts(qwr.size());
+  std::vector<int> cq(qro.size());
+  for (size_t x = 0; x < qwr.size(); ++x) {
+    for (size_t c = 0; c < qro.size(); ++c) cq[c] = qro[c] - qwr[x];
+    build_kmap(rq, qri, cq, parts[x]);
+  }
+  join_batches(parts, out);
+  split_kmap(out);
+}
 // U2[(al,a),(s',b')] conj(bra[a',(s',b')])
 void kmap_env_right_gemm3(const std::vector<int>& qli, const std::vector<int>& qwl, const std::vector<int>& qro,
                           const std::vector<int>& qlo, KMapHost& out) {

@@ -286,9 +286,12 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
                const void* B, void* Rout, void* ws1, void* ws2, SplitWS sk, ProdMaps pm) {
   (void)sk;
   hipStream_t s = ctx->stream;
-  // U1[be][(a,s),b'] = B[(a,s),b] Rt[be][b,b']   (batched over be; dense)
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, mr, 1.0, B, mr, 0, Rt, mr, (long long)mr * mr, 0.0, ws1, mr,
-                2LL * ml * mr, wr);
+  // U1[be][(a,s),b'] = B[(a,s),b] Rt[be][b,b']   (batched over be)
+  {
+    kern::KMapScope ks(pm.g1);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * ml, mr, mr, 1.0, B, mr, 0, Rt, mr, (long long)mr * mr, 0.0, ws1, mr,
+                  2LL * ml * mr, wr);
+  }
   // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
   kern::wapply<T>(s, tb.B, ws1, ws2, ml, mr, 2LL * mr, 1, 2LL * ml * mr, mr, 2LL * mr, 1, 2LL * ml * mr, mr);
   // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(B[a',(s',b')])
@@ -882,10 +885,10 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const void* Bt = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
     ProdMaps pm;
     if (sym) {
-      KMapHost g3;
+      KMapHost g1, g3;
+      kmap_env_right_gemm1(psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1], g1);
       kmap_env_right_gemm3(psi.q[i], qw[i], psi.q[i + 1], psi.q[i], g3);
-      emap.g2.set(ctx, g3);
-      pm.g2 = emap.g2.get();
+      pm = emap.set(ctx, g1, g3);
     }
     env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p, {}, pm);
   };
@@ -1408,8 +1411,11 @@ void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int 
   f1.ensure((size_t)wr * 2 * mli * mro * cb);
   f2.ensure((size_t)wl * 2 * mli * mro * cb);
   // U1[be][(a,s),b'] = ket[(a,s),b] Rt[be][b,b']   (batched over be)
-  kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, mro, mri, 1.0, ket, mri, 0, Rt, mro, (long long)mri * mro, 0.0,
-                     f1.p, mro, 2LL * mli * mro, wr);
+  {
+    kern::KMapScope ks(pm.g1);
+    kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_N, 2 * mli, mro, mri, 1.0, ket, mri, 0, Rt, mro, (long long)mri * mro, 0.0,
+                  f1.p, mro, 2LL * mli * mro, wr);
+  }
   // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
   kern::wapply<T>(s, tb.B, f1.p, f2.p, mli, mro, 2LL * mro, 1, 2LL * mli * mro, mro, 2LL * mro, 1,
                        2LL * mli * mro, mro);
@@ -1529,10 +1535,10 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   PairMaps fm(ctx);
   auto right_maps = [&](int i) -> ProdMaps {   // Rs[i] from site i
     if (!sym) return {};
-    KMapHost g3;
+    KMapHost g1, g3;
+    kmap_env_right_gemm1(in.q[i], in.q[i + 1], qw[i + 1], out.q[i + 1], g1);
     kmap_env_right_gemm3(in.q[i], qw[i], out.q[i + 1], out.q[i], g3);
-    fm.g2.set(ctx, g3);
-    return ProdMaps{nullptr, fm.g2.get(), -1.0};
+    return fm.set(ctx, g1, g3);
   };
   auto left_maps = [&](int i) -> ProdMaps {    // Ls[i+1] from site i
     if (!sym) return {};
@@ -1932,13 +1938,25 @@ void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, co
     envs.emplace_back(ctx);
     envs.emplace_back(ctx);
     set_one(ctx, envs[0], ZB);
+    // with charges (and an MPO that conserves them) the products walk their
+    // nonzero blocks
+    const bool sym = psi.u1() && H->host.u1;
+    PairMaps emap(ctx);
     for (int i = 0; i < N; ++i) {
       const int ml = psi.m[i], mr = psi.m[i + 1], wl = H->w(i), wr = H->w(i + 1);
       const size_t need = (size_t)2 * ml * mr * std::max(wl, wr) * ZB;
       W.ws1.ensure(need);
       W.ws2.ensure(need);
       envs[1].ensure((size_t)mr * wr * mr * ZB);
-      env_left<double>(ctx, H->tab[i], ml, wl, wr, mr, envs[0].p, psi.site(i), envs[1].p, W.ws1.p, W.ws2.p);
+      ProdMaps pm;
+      if (sym) {
+        KMapHost g1, g2;
+        kmap_env_gemm1(psi.q[i], psi.q[i], H->host.qw[i], psi.q[i + 1], g1);
+        kmap_env_left_gemm2(psi.q[i], psi.q[i + 1], psi.q[i + 1], H->host.qw[i + 1], g2);
+        pm = emap.set(ctx, g1, g2);
+      }
+      env_left<double>(ctx, H->tab[i], ml, wl, wr, mr, envs[0].p, psi.site(i), envs[1].p, W.ws1.p, W.ws2.p,
+                       W.split(ml, mr, 16), pm);
       std::swap(envs[0], envs[1]);
     }
     zc e;

@@ -142,6 +142,10 @@ void kmap_heff_gemm2(const std::vector<int>& qlo, const std::vector<int>& qri, c
                      const std::vector<int>& qro, KMapHost& out);
 void kmap_env_left_gemm2(const std::vector<int>& qlo, const std::vector<int>& qro, const std::vector<int>& qri,
                          const std::vector<int>& qwr, KMapHost& out);
+// U1[be][(a,s),b'] = ket[(a,s),b] Rt[be][b,b'] batched over be (ket bonds
+// qli, qri; bra right bond qro; channels qwr)
+void kmap_env_right_gemm1(const std::vector<int>& qli, const std::vector<int>& qri, const std::vector<int>& qwr,
+                          const std::vector<int>& qro, KMapHost& out);
 void kmap_env_right_gemm3(const std::vector<int>& qli, const std::vector<int>& qwl, const std::vector<int>& qro,
                           const std::vector<int>& qlo, KMapHost& out);
 void kmap_keff(const std::vector<int>& ql, const std::vector<int>& qr, const std::vector<int>& qw, KMapHost& g1,
