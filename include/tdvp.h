@@ -180,8 +180,9 @@ void tdvp_mps_destroy(tdvp_mps mps);
  *           environments; the cut drops the smallest eigenvalues while their
  *           sum stays <= eps * Tr(rho).
  *           TDVP_APPLY_FIT: two-site variational fitting, `passes` >= 1
- *           alternating passes starting from the left with |in> as the first
- *           guess; each two-site tensor is the exact projection of O|in> in
+ *           alternating passes with |in> as the first guess, the last pass
+ *           from left to right (odd counts start from the left, even counts
+ *           from the right); each two-site tensor is the exact projection of O|in> in
  *           the current bases, split by a truncated decomposition with the
  *           same relative cut (eps on the squared singular values).
  *   chi_max caps every bond.  Both methods compute in FP64.

@@ -14,6 +14,7 @@
 #include <numeric>
 #include <cstring>
 #include <map>
+#include <memory>
 
 namespace {
 
@@ -479,9 +480,19 @@ struct Work {
   DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv, pidx, prow;
   Scalars sc;
   Lanczos lz;
+  // maps of the charge-aware products issued one after another (a ring, so
+  // that the host can build the next map while the device runs the last)
+  std::vector<std::unique_ptr<DevKMap>> ring;
+  size_t ring_pos = 0;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
         dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), sc(c), lz(c) {}
+  DevKMap& next_map() {
+    constexpr size_t RING = 8;
+    if (ring.size() < RING) ring.emplace_back(new DevKMap(ctx));
+    else ring_pos = (ring_pos + 1) % RING;
+    return *ring[ring.size() < RING ? ring.size() - 1 : ring_pos];
+  }
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {
     const size_t b = (size_t)16 * 2 * ml * mr * cb;
@@ -506,32 +517,58 @@ void zmatmul(tdvp_ctx_s* ctx, int opa, int opb, int M, int N, int K, const void*
   kern::gemm<double>(ctx->stream, opa, opb, M, N, K, 1.0, A, lda, 0, B, ldb, 0, 0.0, out.p, N, 0, 1);
 }
 
+// C = alpha op(A) op(B) + beta C (complex128, row-major) where the logical
+// rows, summed index and columns carry the charges qm, qk, qn (any may be
+// null: dense).  With all three, the product walks only the blocks of equal
+// charge (the operands' other entries are exact zeros).
+void qgemm(Work& W, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,
+           long long ldb, zc beta, void* C, long long ldc, const std::vector<int>* qm, const std::vector<int>* qk,
+           const std::vector<int>* qn) {
+  hipStream_t s = W.ctx->stream;
+  if (qm && qk && qn && (int)qm->size() == M && (int)qk->size() == K && (int)qn->size() == N && M > 0 && N > 0 &&
+      (double)M * N * K >= double(1 << 21)) {
+    KMapHost h;
+    build_kmap(*qm, *qk, *qn, h);
+    split_kmap(h);
+    DevKMap& dm = W.next_map();
+    dm.set(W.ctx, h);
+    kern::KMapScope ks(dm.get());
+    kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+    return;
+  }
+  kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+}
+
 // Newton-Schulz orthonormalisation: for A with nearly orthonormal columns,
 // A <- A (3 I - A^dagger A) / 2 keeps the column span and squares the
 // deviation from orthonormality at every step (GEMMs only).
-void ns_cols(Work& W, void* A, int rows, int n, int iters) {
+// With charges: qr those of the rows, qc of the columns.
+void ns_cols(Work& W, void* A, int rows, int n, int iters, const std::vector<int>* qr = nullptr,
+             const std::vector<int>* qc = nullptr) {
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   W.nsg.ensure((size_t)n * n * ZB);
   W.nst.ensure((size_t)rows * n * ZB);
   for (int it = 0; it < iters; ++it) {
-    kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, 0, A, n, 0, 0.0, W.nsg.p, n, 0, 1);
+    qgemm(W, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, A, n, A, n, 0.0, W.nsg.p, n, qc, qr, qc);
     kern::zshift_diag(s, W.nsg.p, n, -0.5, 1.5);
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, A, n, 0, W.nsg.p, n, 0, 0.0, W.nst.p, n, 0, 1);
+    qgemm(W, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, A, n, W.nsg.p, n, 0.0, W.nst.p, n, qr, qc, qc);
     HIP_CHECK(hipMemcpyAsync(A, W.nst.p, (size_t)rows * n * ZB, hipMemcpyDeviceToDevice, s));
   }
 }
 
 // Same for nearly orthonormal rows: B <- (3 I - B B^dagger) B / 2.
-void ns_rows(Work& W, void* B, int n, int cols, int iters) {
+// With charges: qr those of the rows, qc of the columns.
+void ns_rows(Work& W, void* B, int n, int cols, int iters, const std::vector<int>* qr = nullptr,
+             const std::vector<int>* qc = nullptr) {
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
   W.nsg.ensure((size_t)n * n * ZB);
   W.nst.ensure((size_t)n * cols * ZB);
   for (int it = 0; it < iters; ++it) {
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, 0, B, cols, 0, 0.0, W.nsg.p, n, 0, 1);
+    qgemm(W, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, B, cols, B, cols, 0.0, W.nsg.p, n, qr, qc, qr);
     kern::zshift_diag(s, W.nsg.p, n, -0.5, 1.5);
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, W.nsg.p, n, 0, B, cols, 0, 0.0, W.nst.p, cols, 0, 1);
+    qgemm(W, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, W.nsg.p, n, B, cols, 0.0, W.nst.p, cols, qr, qr, qc);
     HIP_CHECK(hipMemcpyAsync(B, W.nst.p, (size_t)n * cols * ZB, hipMemcpyDeviceToDevice, s));
   }
 }
@@ -625,6 +662,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // they ascend and C has at least as many rows as columns
   const bool keep_cols = !sym || (std::is_sorted(qc->begin(), qc->end()) && rows >= cols);
   if (eps == 0.0 && kk <= chi_max) {
+    Range r1_("split_left.exact");
     if (keep_cols) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
@@ -647,11 +685,18 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // G = C^dagger C (cols x cols); rows of V^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)cols * cols * ZB);
   W.tmpB.ensure((size_t)cols * cols * ZB);
-  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, cols, cols, rows, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, cols, 0, 1);
+  std::vector<int> qrow;   // charges of the rows (a, s) of C
+  if (sym) qrow = fuse_xs(*qa, 1);
+  const std::vector<int>* qrp = sym ? &qrow : nullptr;
+  {
+    Range r1_("split_left.gram");
+    qgemm(W, TDVP_OP_C, TDVP_OP_N, cols, cols, rows, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, cols, qc, qrp, qc);
+  }
   // Nothing is cut when the smallest weight exceeds max(eps, floor) times
   // their sum (the cap does not bind: kk <= chi_max); a Cholesky factorisation
   // certifies it, and the exact factorisation is then the split.
   if (kk == cols && kk <= chi_max && keep_cols) {
+    Range r1_("split_left.certified");
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, cols, std::max(eps, 1e-14), false,
                                              W.cinv.ensure((size_t)cols * cols * ZB), W.work, W.tmpA.p, qc);
     if (F) {
@@ -665,6 +710,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   }
   std::vector<double> lam;
   std::vector<int> qv;
+  Range r2_("split_left.eigh");
   if (sym) la::eigh_sectors(ctx, W.tmpA.p, cols, *qc, lam, W.tmpB.p, W.work2, qv);
   else la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
@@ -673,21 +719,23 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     sort_rows_by_charge(W, W.tmpB.p, cols, n, &lam, qv);
     *qk = qv;
   }
+  Range r3_("split_left.basis");
   // A spans C V_n; R = A^dagger C.  When every kept weight is well above the
   // eigenvector accuracy (u lambda_1 / lambda_n << 1), C V_n S_n^-1 is
   // orthonormal up to rounding and Newton-Schulz polishes it; otherwise a QR
   // of C V_n gives the orthonormal basis.
   W.tmpC.ensure((size_t)rows * n * ZB);
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, W.tmpB.p, cols, 0, 0.0, W.tmpC.p, n, 0, 1);
+  const std::vector<int>* qkp = sym ? qk : nullptr;
+  qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, W.tmpB.p, cols, 0.0, W.tmpC.p, n, qrp, qc, qkp);
   A.ensure((size_t)rows * n * ZB);
   R.ensure((size_t)n * cols * ZB);
   // (Newton-Schulz converges while the starting deviation is below ~1/2; for
   // small kept weights five steps and a check, with a QR when the check fails)
   kern::zscale_cols(s, A.p, n, W.tmpC.p, n, rows, n, inv_sqrt_weights(W, lam, n));
   if (well_separated) {
-    ns_cols(W, A.p, rows, n, 3);
+    ns_cols(W, A.p, rows, n, 3, qrp, qkp);
   } else {
-    ns_cols(W, A.p, rows, n, 5);
+    ns_cols(W, A.p, rows, n, 5, qrp, qkp);
     if (!(la::orth_defect(ctx, A.p, rows, n, false, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
       // with charges the Cholesky-QR steps keep the blocks (Householder
@@ -697,7 +745,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
-  kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, 0, C, cols, 0, 0.0, R.p, cols, 0, 1);
+  qgemm(W, TDVP_OP_C, TDVP_OP_N, n, cols, rows, 1.0, A.p, n, C, cols, 0.0, R.p, cols, qkp, qrp, qc);
   return n;
 }
 
@@ -715,6 +763,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   const bool sym = qr != nullptr;
   const bool keep_rows = !sym || (std::is_sorted(qr->begin(), qr->end()) && rows <= cols);
   if (eps == 0.0 && kk <= chi_max) {
+    Range r1_("split_right.exact");
     if (keep_rows) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
@@ -735,9 +784,16 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   // G = C C^dagger (rows x rows); rows of U^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)rows * rows * ZB);
   W.tmpB.ensure((size_t)rows * rows * ZB);
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, 0, C, cols, 0, 0.0, W.tmpA.p, rows, 0, 1);
+  std::vector<int> qcol;   // charges of the columns (s, b) of C as a left bond
+  if (sym) qcol = fuse_sx(*qb, -1);
+  const std::vector<int>* qcp = sym ? &qcol : nullptr;
+  {
+    Range r1_("split_right.gram");
+    qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, rows, qr, qcp, qr);
+  }
   // certified "nothing to cut" as in split_left
   if (kk == rows && kk <= chi_max && keep_rows) {
+    Range r1_("split_right.certified");
     const void* F = la::gram_floor_certified(ctx, W.tmpB.p, rows, std::max(eps, 1e-14), true,
                                              W.cinv.ensure((size_t)rows * rows * ZB), W.work, W.tmpA.p, qr);
     if (F) {
@@ -751,6 +807,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   }
   std::vector<double> lam;
   std::vector<int> qv;
+  Range r2_("split_right.eigh");
   if (sym) la::eigh_sectors(ctx, W.tmpA.p, rows, *qr, lam, W.tmpB.p, W.work2, qv);
   else la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
   const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
@@ -759,17 +816,19 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     sort_rows_by_charge(W, W.tmpB.p, rows, n, &lam, qv);
     *qk = qv;
   }
+  Range r3_("split_right.basis");
   // B spans the rows of U_n^dagger C; L = C B^dagger (Newton-Schulz on
   // S_n^-1 U_n^dagger C when the kept weights allow it, an LQ otherwise)
   W.tmpC.ensure((size_t)n * cols * ZB);
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, 0, C, cols, 0, 0.0, W.tmpC.p, cols, 0, 1);
+  const std::vector<int>* qkp = sym ? qk : nullptr;
+  qgemm(W, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, C, cols, 0.0, W.tmpC.p, cols, qkp, qr, qcp);
   L.ensure((size_t)rows * n * ZB);
   B.ensure((size_t)n * cols * ZB);
   kern::zscale_rows(s, B.p, cols, W.tmpC.p, cols, n, cols, inv_sqrt_weights(W, lam, n));
   if (well_separated) {
-    ns_rows(W, B.p, n, cols, 3);
+    ns_rows(W, B.p, n, cols, 3, qkp, qcp);
   } else {
-    ns_rows(W, B.p, n, cols, 5);
+    ns_rows(W, B.p, n, cols, 5, qkp, qcp);
     if (!(la::orth_defect(ctx, B.p, n, cols, true, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
       if (!sym) la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
@@ -777,7 +836,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
-  kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, 0, B.p, cols, 0, 0.0, L.p, n, 0, 1);
+  qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, B.p, cols, 0.0, L.p, n, qr, qcp, qkp);
   return n;
 }
 
@@ -1463,14 +1522,16 @@ void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int
                        0.0, Y, mro, 0, 1);
 }
 
-// out = normalise(fit of O|in>): `passes` alternating two-site passes from
-// the left, starting from |in> brought to right-canonical form; every split
-// takes the eps / chi_max cut of the gauge moves.  The result is
+// out = normalise(fit of O|in>): `passes` alternating two-site passes, the
+// last from left to right (odd counts start from the left with |in> brought
+// to right-canonical form, even counts from the right with |in>
+// left-canonical, which in_left_canonical declares it already is); every
+// split takes the eps / chi_max cut of the gauge moves.  The result is
 // left-canonical with its centre on the last site.  Returns the weight
 // discarded in the last pass.
 template <typename T>
 double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps, int chi_max, int passes,
-                 tdvp_mps_s& out) {
+                 tdvp_mps_s& out, bool in_left_canonical = false) {
   Range r_("fit.apply");
   tdvp_ctx_s* ctx = W.ctx;
   hipStream_t s = ctx->stream;
@@ -1520,7 +1581,12 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
     out.t[i].ensure((size_t)in.elems(i) * ZB);
     HIP_CHECK(hipMemcpyAsync(out.t[i].p, in.site(i), (size_t)in.elems(i) * ZB, hipMemcpyDeviceToDevice, s));
   }
-  right_canonicalize(W, out);
+  // the last pass runs left to right (result left-canonical, centre on the
+  // last site): an even count starts from the right with a left-canonical
+  // guess, an odd count from the left with a right-canonical one
+  const bool from_right = passes % 2 == 0;
+  if (!from_right) right_canonicalize(W, out);
+  else if (!in_left_canonical) left_canonicalize(W, out);
   const bool sym = out.u1();
   std::vector<DBuf> Ls, Rs;
   for (int i = 0; i <= N; ++i) {
@@ -1553,10 +1619,18 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
     kmap_two_site(out.q[i], in.q[i], qw[i], in.q[i + 2], qw[i + 2], out.q[i + 2], g1, g2);
     return fm.set(ctx, g1, g2);
   };
-  for (int i = N - 1; i >= 2; --i) {
-    Rs[i].ensure((size_t)op.w(i) * in.m[i] * out.m[i] * cb);
-    fit_env_right<T>(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1], Rs[i + 1].p,
-                     bra(i), Kp[i], Rs[i].p, f1, f2, right_maps(i));
+  if (from_right) {
+    for (int i = 0; i + 2 < N; ++i) {
+      Ls[i + 1].ensure((size_t)out.m[i + 1] * op.w(i + 1) * in.m[i + 1] * cb);
+      fit_env_left<T>(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1], Ls[i].p,
+                      bra(i), Kp[i], Ls[i + 1].p, f1, f2, left_maps(i));
+    }
+  } else {
+    for (int i = N - 1; i >= 2; --i) {
+      Rs[i].ensure((size_t)op.w(i) * in.m[i] * out.m[i] * cb);
+      fit_env_right<T>(ctx, op.tab[i], out.m[i], in.m[i], op.w(i), op.w(i + 1), out.m[i + 1], in.m[i + 1],
+                       Rs[i + 1].p, bra(i), Kp[i], Rs[i].p, f1, f2, right_maps(i));
+    }
   }
   // two-site tensor of phi at (i, i+1) from the current environments (FP64
   // for the split)
@@ -1576,7 +1650,7 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   double disc = 0.0;
   for (int pass = 0; pass < passes; ++pass) {
     disc = 0.0;
-    if (pass % 2 == 0) {   // left to right: phi_i left-canonical, centre moves on
+    if ((pass % 2 == 0) != from_right) {   // left to right: phi_i left-canonical, centre moves on
       for (int i = 0; i + 1 < N; ++i) {
         const double* th = local(i);
         const int mlo = out.m[i], mro = out.m[i + 2];
@@ -1610,7 +1684,6 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
       }
     }
   }
-  if (passes % 2 == 0) left_canonicalize(W, out);
   const double nr = W.sc.norm(out.site(N - 1), out.elems(N - 1));
   if (!(nr > 0.0) || !std::isfinite(nr)) TDVP_THROW(TDVP_ERR_NUMERIC, "MPO application vanished or is not finite");
   kern::zscale(s, out.t[N - 1].p, out.t[N - 1].p, zc(1.0 / nr, 0.0), out.elems(N - 1));
@@ -1805,7 +1878,7 @@ void expand_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& op, const t
     const tdvp_mps_s* prev = &psi;
     for (int l = 0; l + 1 < p.k; ++l) {
       st.discarded_K += p.apply_method == TDVP_APPLY_FIT
-                            ? fit_apply<T>(W, *prev, op, p.eps_K, p.chi_max, std::max(1, p.fit_passes), kv[l])
+                            ? fit_apply<T>(W, *prev, op, p.eps_K, p.chi_max, std::max(1, p.fit_passes), kv[l], true)
                             : denmat_apply<T>(W, *prev, op, p.eps_K, p.chi_max, kv[l]);
       prev = &kv[l];
       for (int b = 0; b <= N; ++b) st.krylov_max_bond = std::max(st.krylov_max_bond, kv[l].m[b]);

@@ -11,6 +11,9 @@ kernels by total time (calls, total, average, share of kernel time), the
 window length and the fraction of it the device spent in kernels.  With
 --split-grid, kernels whose name contains SUBSTRING are listed once per
 grid size (the two products of the effective Hamiltonian share a kernel).
+With --ranges (the marker_api_trace.csv of the same run, taken with
+--marker-trace) the host time of each named range inside the window is
+listed too.
 """
 from __future__ import annotations
 
@@ -39,7 +42,18 @@ def _rows(path):
             yield r[i_name], int(r[i_start]), int(r[i_end]), tuple(r[i] for i in i_grid)
 
 
-def summarize(path, marker="spin_kernel", split_grid=None, top=40):
+def _ranges(path):
+    with open(path, newline="") as f:
+        rows = csv.reader(f)
+        header = next(rows)
+        i_name = _col(header, "Function", "Message", "Name")
+        i_start = _col(header, "Start_Timestamp", "Start")
+        i_end = _col(header, "End_Timestamp", "End")
+        for r in rows:
+            yield r[i_name], int(r[i_start]), int(r[i_end])
+
+
+def summarize(path, marker="spin_kernel", split_grid=None, top=40, ranges=None):
     # two passes over the file (traces of long runs hold millions of rows)
     marks = sorted(s for n, s, e, g in _rows(path) if marker in n)
     if len(marks) < 2:
@@ -71,6 +85,17 @@ def summarize(path, marker="spin_kernel", split_grid=None, top=40):
            "|---|---:|---:|---:|---:|"]
     for key, (c, t) in sorted(by.items(), key=lambda kv: -kv[1][1])[:top]:
         out.append(f"| `{key}` | {c} | {1e-6 * t:.1f} | {1e-3 * t / c:.1f} | {100.0 * t / total:.2f} |")
+    if ranges:
+        # host time of the named ranges (inclusive of nested ones) in the window
+        hr = defaultdict(lambda: [0, 0])
+        for n, s, e in _ranges(ranges):
+            if lo < s < hi:
+                hr[n][0] += 1
+                hr[n][1] += e - s
+        out += ["", f"host ranges ({ranges.split('/')[-1]}), inclusive:", "",
+                "| range | calls | total ms | avg us | % of window |", "|---|---:|---:|---:|---:|"]
+        for key, (c, t) in sorted(hr.items(), key=lambda kv: -kv[1][1]):
+            out.append(f"| `{key}` | {c} | {1e-6 * t:.1f} | {1e-3 * t / c:.1f} | {100.0 * t / (hi - lo):.2f} |")
     return "\n".join(out)
 
 
@@ -80,8 +105,9 @@ def main(argv=None):
     ap.add_argument("--marker", default="spin_kernel")
     ap.add_argument("--split-grid", default=None)
     ap.add_argument("--top", type=int, default=40)
+    ap.add_argument("--ranges", default=None, help="a marker_api_trace.csv of the same run: host time per range")
     a = ap.parse_args(argv)
-    print(summarize(a.trace, a.marker, a.split_grid, a.top))
+    print(summarize(a.trace, a.marker, a.split_grid, a.top, a.ranges))
 
 
 if __name__ == "__main__":
