@@ -223,6 +223,18 @@ void gemm_heff(hipStream_t s, int M, int N, int K, const void* A, long long lda,
 int tridiag_groups(int n);
 size_t tridiag_scratch_bytes(int n);
 hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err);
+// The same for nsec independent matrices (2 <= n <= 1024 each, own scratch
+// of tridiag_scratch_bytes(n)), reduced side by side in as few launches as
+// fit; *err is shared.
+struct TdSector {
+  const void* H;
+  void* Q;
+  double* D;
+  double* E;
+  void* scratch;
+  int n;
+};
+hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* err);
 // Eigen-decomposition of the real symmetric tridiagonal matrix (diagonal D[n],
 // off-diagonal E[n-1]; 1 <= n <= 512) by divide and conquer: on return D holds
 // the eigenvalues ascending and Z (column-major n x n) the eigenvectors.

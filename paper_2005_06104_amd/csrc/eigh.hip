@@ -57,6 +57,16 @@ struct TdArgs {
   int n, G, R;
 };
 
+// Several independent matrices in one launch: sector s owns workgroups
+// wg0[s] .. wg0[s+1] - 1 and its own exchange buffers, so the sectors (the
+// charge blocks of a block-diagonal matrix) are reduced side by side.
+constexpr int TD_MAXSEC = 16;
+struct TdBatch {
+  TdArgs sec[TD_MAXSEC];
+  int wg0[TD_MAXSEC + 1];
+  int nsec;
+};
+
 __device__ inline double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ inline double2 cmulc(double2 a, double2 b) {  // a * conj(b)
   return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
@@ -130,14 +140,17 @@ __device__ inline double2 hh_v(int c, int k, double2 row_c, double2 sc) {
 // after it has read everything of column k, so no copy is overwritten while
 // a reader still needs it.
 template <int NMAX, int LDS, bool QLDS>
-__global__ __launch_bounds__(TNT) void tridiag_kernel(TdArgs a) {
+__global__ __launch_bounds__(TNT) void tridiag_kernel(TdBatch batch) {
   __shared__ double2 sM[LDS];           // A rows [R][n], then (QLDS) Q rows [R][n]
   __shared__ double2 sv[NMAX], sw[NMAX], srow[NMAX];
   __shared__ double sred[TNT / 64];     // per-wave |row[k+2:]|^2 of the pivot row
   __shared__ double2 s_xv[TNT / 64];    // per-wave parts of x^H v
   __shared__ int s_fail;
 
-  const int n = a.n, G = a.G, R = a.R, g = blockIdx.x, tid = threadIdx.x;
+  int sec = 0;
+  while (sec + 1 < batch.nsec && batch.wg0[sec + 1] <= (int)blockIdx.x) ++sec;
+  const TdArgs a = batch.sec[sec];
+  const int n = a.n, G = a.G, R = a.R, g = (int)blockIdx.x - batch.wg0[sec], tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   double2* sA = sM;
   // Q row j of this workgroup: in LDS, or row g + j G of the output
@@ -378,7 +391,7 @@ __global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* G, const d
 __global__ void td_reset_kernel(unsigned* w, int nw, int* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nw) w[i] = 0u;
-  if (i == 0) *err = 0;
+  if (i == 0 && err) *err = 0;
 }
 
 }  // namespace
@@ -409,27 +422,90 @@ size_t tridiag_scratch_bytes(int n) {
 }
 
 hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, double* E, void* scratch, int* err) {
-  const int G = tridiag_groups(n);
-  if (G == 0) return hipErrorInvalidValue;
-  char* p = static_cast<char*>(scratch);
-  TdArgs a{};
-  a.H = static_cast<const double2*>(H);
-  a.Q = static_cast<double2*>(Q);
-  a.D = D;
-  a.E = E;
-  a.xv = reinterpret_cast<unsigned long long*>(p);     // two buffers of n complex each
-  a.prow = a.xv + 8 * (size_t)n;
-  a.err = err;
-  a.n = n;
-  a.G = G;
-  a.R = (n + G - 1) / G;
-  const int nw = 2 * 4 * 4 * n;   // 32-bit halves of the tagged words
-  hipLaunchKernelGGL(td_reset_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, reinterpret_cast<unsigned*>(a.xv), nw,
-                     err);
-  void* args[] = {&a};
-  const void* kfn = n > TD_NMAX ? reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX_BIG, TD_LDS_BIG, false>)
-                                : reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX, TD_LDS, true>);
-  return hipLaunchCooperativeKernel(kfn, dim3(G), dim3(TNT), args, 0, s);
+  if (tridiag_groups(n) == 0) return hipErrorInvalidValue;
+  const TdSector one{H, Q, D, E, scratch, n};
+  return tridiag_batched(s, &one, 1, err);
+}
+
+// Workgroups of the sectors of one launch (every workgroup holds one CU's
+// worth of LDS, so at most TD_WG_LAUNCH): each sector gets at least the
+// workgroups its LDS share needs, the rest go where the work per workgroup
+// (~ n^3 / G) is largest, up to four rows per workgroup.
+namespace {
+constexpr int TD_WG_LAUNCH = 256;
+int td_rmax(int n) { return n > TD_NMAX ? TD_LDS_BIG / n : std::min(TD_ROWS, TD_LDS / (2 * n)); }
+int td_gmin(int n) { return (n + td_rmax(n) - 1) / td_rmax(n); }
+int td_gpref(int n) { return std::min(n > TD_NMAX ? TD_G_BIG : 128, (n + 3) / 4); }
+}  // namespace
+
+hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* err) {
+  if (nsec < 1 || !err) return hipErrorInvalidValue;
+  for (int i = 0; i < nsec; ++i)
+    if (sec[i].n < 2 || sec[i].n > TD_NMAX_BIG || !sec[i].scratch) return hipErrorInvalidValue;
+  // the tagged words of every sector, and the error flag once
+  for (int i = 0; i < nsec; ++i) {
+    const int nw = 2 * 4 * 4 * sec[i].n;   // 32-bit halves of the tagged words
+    hipLaunchKernelGGL(td_reset_kernel, dim3((nw + 255) / 256), dim3(256), 0, s,
+                       static_cast<unsigned*>(sec[i].scratch), nw, i == 0 ? err : nullptr);
+  }
+  // two variants (Q rows in LDS up to n = 512, in the output above); in
+  // each, sectors in decreasing size packed into launches
+  for (int big = 0; big < 2; ++big) {
+    std::vector<int> ids;
+    for (int i = 0; i < nsec; ++i)
+      if ((sec[i].n > TD_NMAX) == (big == 1)) ids.push_back(i);
+    std::stable_sort(ids.begin(), ids.end(), [&](int x, int y) { return sec[x].n > sec[y].n; });
+    for (size_t k = 0; k < ids.size();) {
+      std::vector<int> grp, G;
+      int tot = 0;
+      while (k < ids.size() && (int)grp.size() < TD_MAXSEC &&
+             (grp.empty() || tot + td_gmin(sec[ids[k]].n) <= TD_WG_LAUNCH)) {
+        grp.push_back(ids[k]);
+        G.push_back(td_gmin(sec[ids[k]].n));
+        tot += G.back();
+        ++k;
+      }
+      for (int spare = TD_WG_LAUNCH - tot; spare > 0; --spare) {
+        int best = -1;
+        double wbest = 0.0;
+        for (size_t j = 0; j < grp.size(); ++j) {
+          const double nn = sec[grp[j]].n, w = nn * nn * nn / G[j];
+          if (G[j] < td_gpref(sec[grp[j]].n) && w > wbest) {
+            wbest = w;
+            best = (int)j;
+          }
+        }
+        if (best < 0) break;
+        ++G[best];
+      }
+      TdBatch b{};
+      int wg = 0;
+      for (size_t j = 0; j < grp.size(); ++j) {
+        const TdSector& x = sec[grp[j]];
+        TdArgs& a = b.sec[j];
+        a.H = static_cast<const double2*>(x.H);
+        a.Q = static_cast<double2*>(x.Q);
+        a.D = x.D;
+        a.E = x.E;
+        a.xv = static_cast<unsigned long long*>(x.scratch);   // two buffers of n complex each
+        a.prow = a.xv + 8 * (size_t)x.n;
+        a.err = err;
+        a.n = x.n;
+        a.G = G[j];
+        a.R = (x.n + G[j] - 1) / G[j];
+        b.wg0[j] = wg;
+        wg += G[j];
+      }
+      b.wg0[grp.size()] = wg;
+      b.nsec = (int)grp.size();
+      void* args[] = {&b};
+      const void* kfn = big ? reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX_BIG, TD_LDS_BIG, false>)
+                            : reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX, TD_LDS, true>);
+      const hipError_t e = hipLaunchCooperativeKernel(kfn, dim3(wg), dim3(TNT), args, 0, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 void shift_by_trace(hipStream_t s, void* G, int n, double frac, const void* S) {

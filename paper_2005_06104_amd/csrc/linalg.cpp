@@ -591,6 +591,102 @@ int* upload_ints(tdvp_ctx_s* ctx, DBuf& buf, const std::vector<int>& v) {
   return buf.as<int>();
 }
 
+// The charge blocks (2 <= size <= 1024) of a block-diagonal Hermitian
+// matrix, all at once: every block gathered, all tridiagonalised side by
+// side (kern::tridiag_batched), each tridiagonal problem by the own divide
+// and conquer (rocSOLVER's above 512), the back transformations, and one
+// download for the checks of all blocks.  Block b (indices idx[off[b] ..
+// off[b] + nb[b]) of H) leaves its eigenvector rows, descending, scattered
+// into rows off[b] .. of `sec` (n wide) and its eigenvalues in lam[off[b] ..].
+// Returns false for the blocks that fail (bad[b] = 1): the caller redoes them.
+bool eigh_blocks(tdvp_ctx_s* ctx, const void* H, int n, const int* didx, const std::vector<int>& off,
+                 const std::vector<int>& nbv, void* sec, std::vector<double>& lam, std::vector<char>& bad,
+                 DBuf& work) {
+  hipStream_t s = ctx->stream;
+  const int B = (int)off.size();
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  // layout: per block X | Q | R | Z | E | scratch, then dots partials, then the staged block
+  std::vector<size_t> oX(B), oQ(B), oR(B), oZ(B), oE(B), oS(B);
+  size_t tot = 0, nd = 0, maxnn = 1;
+  for (int b = 0; b < B; ++b) {
+    const size_t m = nbv[b], mm = m * m;
+    maxnn = std::max(maxnn, mm);
+    oX[b] = tot; tot += up(sizeof(rz) * mm);
+    oQ[b] = tot; tot += up(sizeof(rz) * mm);
+    oR[b] = tot; tot += up(sizeof(rz) * mm);
+    oZ[b] = tot; tot += up(sizeof(double) * mm);
+    oE[b] = tot; tot += up(sizeof(double) * m);
+    oS[b] = tot; tot += up(std::max(kern::tridiag_scratch_bytes((int)m), kern::tridiag_eig_scratch_bytes((int)m)));
+    nd += m;
+  }
+  const int nbd = kern::zdots_blocks((long long)maxnn);
+  const size_t oP = tot;
+  tot += up(sizeof(rz) * (size_t)nbd);
+  // staged: error word and per-block info (ints, 16-byte padded), sums |v|^2, eigenvalues
+  const size_t ints = (size_t)(1 + B + 3) / 4 * 4;
+  const size_t stage_bytes = sizeof(int) * ints + sizeof(rz) * B + sizeof(double) * nd;
+  const size_t oT = tot;
+  tot += up(stage_bytes);
+  char* base = static_cast<char*>(work.ensure(tot));
+  char* stage = base + oT;
+  int* derr = reinterpret_cast<int*>(stage);
+  int* dinfo = derr + 1;
+  rz* dsum = reinterpret_cast<rz*>(stage + sizeof(int) * ints);
+  double* dD = reinterpret_cast<double*>(dsum + B);
+  kern::zfill(s, stage, zc(0.0, 0.0), (long long)(sizeof(int) * ints / 16), 16);   // error and info words
+  std::vector<kern::TdSector> td(B);
+  size_t od = 0;
+  std::vector<size_t> oDv(B);
+  for (int b = 0; b < B; ++b) {
+    const int m = nbv[b];
+    rz* X = reinterpret_cast<rz*>(base + oX[b]);
+    kern::zgather(s, X, m, H, n, didx + off[b], m, didx + off[b], m);
+    kern::zhermitize_to(s, X, X, m);
+    oDv[b] = od;
+    td[b] = kern::TdSector{X, base + oQ[b], dD + od, reinterpret_cast<double*>(base + oE[b]), base + oS[b], m};
+    od += m;
+  }
+  if (kern::tridiag_batched(s, td.data(), B, derr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  for (int b = 0; b < B; ++b) {
+    const int m = nbv[b];
+    double* Z = reinterpret_cast<double*>(base + oZ[b]);
+    double* E = reinterpret_cast<double*>(base + oE[b]);
+    if (kern::tridiag_eig_scratch_bytes(m) == 0) {
+      blas_check(rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, m, dD + oDv[b], E, Z, m, dinfo + b), "dstedc");
+    } else if (kern::tridiag_eig(s, dD + oDv[b], E, m, Z, base + oS[b]) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    rz* X = reinterpret_cast<rz*>(base + oX[b]);
+    rz* R = reinterpret_cast<rz*>(base + oR[b]);
+    kern::zrows_from_real_desc(s, X, Z, m);
+    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, m, m, m, 1.0, X, m, 0, base + oQ[b], m, 0, 0.0, R, m, 0, 1);
+    kern::zdots(s, R, (long long)m * m, 1, R, (long long)m * m, base + oP, kern::zdots_blocks((long long)m * m),
+                dsum + b);
+    kern::zscatter_cols(s, static_cast<char*>(sec) + sizeof(zc) * (size_t)off[b] * n, n, R, m, m, didx + off[b], m);
+  }
+  const char* hs = static_cast<const char*>(ctx->fetch(stage, stage_bytes));
+  int herr;
+  std::memcpy(&herr, hs, sizeof(int));
+  const int* hinfo = reinterpret_cast<const int*>(hs) + 1;
+  const rz* hsum = reinterpret_cast<const rz*>(hs + sizeof(int) * ints);
+  const double* hD = reinterpret_cast<const double*>(hsum + B);
+  if (herr != 0) return false;
+  bad.assign(B, 0);
+  for (int b = 0; b < B; ++b) {
+    const int m = nbv[b];
+    const double v = hsum[b].real();
+    bool ok = hinfo[b] == 0 && std::isfinite(v) && std::fabs(v - m) <= 1e-6 * m;
+    for (int j = 0; j < m; ++j) ok = ok && std::isfinite(hD[oDv[b] + j]);
+    bad[b] = ok ? 0 : 1;
+    for (int j = 0; j < m; ++j) lam[off[b] + j] = hD[oDv[b] + m - 1 - j];
+  }
+  return true;
+}
+
 }  // namespace
 
 void eigh_sectors(tdvp_ctx_s* ctx, const void* H, int n, const std::vector<int>& q, std::vector<double>& lam,
@@ -627,9 +723,24 @@ void eigh_sectors(tdvp_ctx_s* ctx, const void* H, int n, const std::vector<int>&
   blk.ensure(sizeof(zc) * (size_t)nmax * nmax);
   rb.ensure(sizeof(zc) * (size_t)nmax * nmax);
   std::vector<double> lam_sec(n, 0.0), lb;
+  // blocks up to 1024 side by side; the rest (and any block that fails its
+  // check) one at a time
+  std::vector<int> boff, bnb;
   for (int c = 0; c < ns; ++c) {
+    const int nb = sc.off[c + 1] - sc.off[c];
+    if (nb >= 2 && nb <= 1024) {
+      boff.push_back(sc.off[c]);
+      bnb.push_back(nb);
+    }
+  }
+  std::vector<char> bad;
+  const bool batched = boff.size() > 1 && eigh_blocks(ctx, H, n, didx, boff, bnb, sec.p, lam_sec, bad, work);
+  for (int c = 0, b = 0; c < ns; ++c) {
     const int o = sc.off[c], nb = sc.off[c + 1] - o;
     if (nb < 2) continue;
+    const bool in_batch = b < (int)boff.size() && boff[b] == o;
+    if (in_batch) ++b;
+    if (batched && in_batch && !bad[b - 1]) continue;
     kern::zgather(s, blk.p, nb, H, n, didx + o, nb, didx + o, nb);
     eigh_rows_desc(ctx, blk.p, nb, lb, rb.p, work);
     kern::zscatter_cols(s, static_cast<char*>(sec.p) + sizeof(zc) * (size_t)o * n, n, rb.p, nb, nb, didx + o, nb);
