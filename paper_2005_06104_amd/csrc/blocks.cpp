@@ -243,6 +243,34 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
   tile_flops = 8.0 * h.tile_macs;
 }
 
+DevKMap& MapRing::next() {
+  constexpr size_t RING = 8;
+  if (ring.size() < RING) {
+    ring.emplace_back(new DevKMap(ctx));
+    return *ring.back();
+  }
+  pos = (pos + 1) % RING;
+  return *ring[pos];
+}
+
+void qgemm(tdvp_ctx_s* ctx, MapRing* ring, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
+           long long lda, const void* B, long long ldb, zc beta, void* C, long long ldc, const std::vector<int>* qm,
+           const std::vector<int>* qk, const std::vector<int>* qn) {
+  hipStream_t s = ctx->stream;
+  if (ring && qm && qk && qn && (int)qm->size() == M && (int)qk->size() == K && (int)qn->size() == N && M > 0 &&
+      N > 0 && (double)M * N * K >= double(1 << 21)) {
+    KMapHost h;
+    build_kmap(*qm, *qk, *qn, h);
+    split_kmap(h);
+    DevKMap& dm = ring->next();
+    dm.set(ctx, h);
+    kern::KMapScope ks(dm.get());
+    kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+    return;
+  }
+  kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+}
+
 namespace {
 
 // charges of fused row-major indices (first index outer)

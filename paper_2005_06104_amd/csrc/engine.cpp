@@ -480,19 +480,11 @@ struct Work {
   DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv, pidx, prow;
   Scalars sc;
   Lanczos lz;
-  // maps of the charge-aware products issued one after another (a ring, so
-  // that the host can build the next map while the device runs the last)
-  std::vector<std::unique_ptr<DevKMap>> ring;
-  size_t ring_pos = 0;
+  // maps of the charge-aware products issued one after another
+  MapRing ring;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
-        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), sc(c), lz(c) {}
-  DevKMap& next_map() {
-    constexpr size_t RING = 8;
-    if (ring.size() < RING) ring.emplace_back(new DevKMap(ctx));
-    else ring_pos = (ring_pos + 1) % RING;
-    return *ring[ring.size() < RING ? ring.size() - 1 : ring_pos];
-  }
+        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), sc(c), lz(c), ring(c) {}
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {
     const size_t b = (size_t)16 * 2 * ml * mr * cb;
@@ -524,19 +516,7 @@ void zmatmul(tdvp_ctx_s* ctx, int opa, int opb, int M, int N, int K, const void*
 void qgemm(Work& W, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,
            long long ldb, zc beta, void* C, long long ldc, const std::vector<int>* qm, const std::vector<int>* qk,
            const std::vector<int>* qn) {
-  hipStream_t s = W.ctx->stream;
-  if (qm && qk && qn && (int)qm->size() == M && (int)qk->size() == K && (int)qn->size() == N && M > 0 && N > 0 &&
-      (double)M * N * K >= double(1 << 21)) {
-    KMapHost h;
-    build_kmap(*qm, *qk, *qn, h);
-    split_kmap(h);
-    DevKMap& dm = W.next_map();
-    dm.set(W.ctx, h);
-    kern::KMapScope ks(dm.get());
-    kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
-    return;
-  }
-  kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+  ::qgemm(W.ctx, &W.ring, opa, opb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, qm, qk, qn);
 }
 
 // Newton-Schulz orthonormalisation: for A with nearly orthonormal columns,
@@ -661,12 +641,15 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
   // the exact moves keep the columns as the new bond: with charges only when
   // they ascend and C has at least as many rows as columns
   const bool keep_cols = !sym || (std::is_sorted(qc->begin(), qc->end()) && rows >= cols);
+  std::vector<int> qrow;   // charges of the rows (a, s) of C
+  if (sym) qrow = fuse_xs(*qa, 1);
+  const std::vector<int>* qrp = sym ? &qrow : nullptr;
   if (eps == 0.0 && kk <= chi_max) {
     Range r1_("split_left.exact");
     if (keep_cols) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, nullptr, qc)) {
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, nullptr, qc, qrp, &W.ring)) {
         if (sym) *qk = *qc;
         return kk;
       }
@@ -680,14 +663,12 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     // rank-deficient (or not ordered by charge): Householder per charge
     // block, which keeps every direction of the bond, weight or not (the
     // extension's new directions carry none until the sweep evolves into them)
+    Range r2_("split_left.sectors");
     return la::factor_sectors(ctx, true, C, rows, cols, fuse_xs(*qa, 1), *qc, A, R, *qk);
   }
   // G = C^dagger C (cols x cols); rows of V^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)cols * cols * ZB);
   W.tmpB.ensure((size_t)cols * cols * ZB);
-  std::vector<int> qrow;   // charges of the rows (a, s) of C
-  if (sym) qrow = fuse_xs(*qa, 1);
-  const std::vector<int>* qrp = sym ? &qrow : nullptr;
   {
     Range r1_("split_left.gram");
     qgemm(W, TDVP_OP_C, TDVP_OP_N, cols, cols, rows, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, cols, qc, qrp, qc);
@@ -702,7 +683,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     if (F) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F, qc)) {
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F, qc, qrp, &W.ring)) {
         if (sym) *qk = *qc;
         return kk;
       }
@@ -741,7 +722,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
       // with charges the Cholesky-QR steps keep the blocks (Householder
       // reflections would mix them)
       if (!sym) la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
-      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, nullptr, qk))
+      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, nullptr, qk, qrp, &W.ring))
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
@@ -762,12 +743,15 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
   const int rows = ml, cols = 2 * mr, kk = std::min(rows, cols);
   const bool sym = qr != nullptr;
   const bool keep_rows = !sym || (std::is_sorted(qr->begin(), qr->end()) && rows <= cols);
+  std::vector<int> qcol;   // charges of the columns (s, b) of C as a left bond
+  if (sym) qcol = fuse_sx(*qb, -1);
+  const std::vector<int>* qcp = sym ? &qcol : nullptr;
   if (eps == 0.0 && kk <= chi_max) {
     Range r1_("split_right.exact");
     if (keep_rows) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, nullptr, qr)) {
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, nullptr, qr, qcp, &W.ring)) {
         if (sym) *qk = *qr;
         return kk;
       }
@@ -779,14 +763,12 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
       return kk;
     }
     // as in split_left: LQ per charge block, every direction kept
+    Range r2_("split_right.sectors");
     return la::factor_sectors(ctx, false, C, rows, cols, *qr, fuse_sx(*qb, -1), L, B, *qk);
   }
   // G = C C^dagger (rows x rows); rows of U^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)rows * rows * ZB);
   W.tmpB.ensure((size_t)rows * rows * ZB);
-  std::vector<int> qcol;   // charges of the columns (s, b) of C as a left bond
-  if (sym) qcol = fuse_sx(*qb, -1);
-  const std::vector<int>* qcp = sym ? &qcol : nullptr;
   {
     Range r1_("split_right.gram");
     qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, rows, qr, qcp, qr);
@@ -799,7 +781,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (F) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F, qr)) {
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F, qr, qcp, &W.ring)) {
         if (sym) *qk = *qr;
         return kk;
       }
@@ -832,7 +814,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (!(la::orth_defect(ctx, B.p, n, cols, true, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
       if (!sym) la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
-      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, nullptr, qk))
+      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, nullptr, qk, qcp, &W.ring))
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
@@ -1731,7 +1713,7 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
                                                W.cinv.ensure((size_t)ml * ml * ZB), W.work, W.tmpA.p, qm);
       if (F) {
         W.tmpC.ensure((size_t)ml * ml * ZB);
-        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F, qm);
+        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F, qm, sym ? &qD : nullptr, &W.ring);
         if (done) {
           r = ml;
           if (sym) qB = psi.q[i];

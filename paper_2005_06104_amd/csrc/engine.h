@@ -130,6 +130,13 @@ struct DevKMap {
   void set(tdvp_ctx_s* ctx, const KMapHost& h);
   const kern::KMap* get() const { return map.items ? &map : nullptr; }
 };
+struct MapRing {
+  tdvp_ctx_s* ctx;
+  std::vector<std::unique_ptr<DevKMap>> ring;
+  size_t pos = 0;
+  explicit MapRing(tdvp_ctx_s* c) : ctx(c) {}
+  DevKMap& next();
+};
 // the maps of the contractions (bra bonds qlo, qro; ket bonds qli, qri; MPO
 // channels qwl, qwr; equal bra and ket for the effective Hamiltonians).  The
 // first products of H_eff, K_eff, the left environments and the two-site
