@@ -371,6 +371,10 @@ void zscatter_cols(hipStream_t s, void* dst, long long ldd, const void* src, lon
 // H[idx[j]][idx[j]] and rows[pos[j]][idx[j]] = 1 (their unit eigenvectors)
 void zunit_blocks(hipStream_t s, void* diag, const void* H, long long n, const int* idx, const int* pos, int cnt,
                   void* rows);
+// E (R x C, complex128 row-major) with E[i][j] seeded pseudo-random (each part
+// uniform in [-1, 1), from a counter hash of seed, i and j) where qr[i] ==
+// qc[j] and zero elsewhere; charge arrays on the device
+void zrandom_blocks(hipStream_t s, void* E, int R, int C, const int* qr, const int* qc, unsigned long long seed);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
 // G = a G + b I (n x n complex128)

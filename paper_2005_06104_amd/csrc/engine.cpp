@@ -624,6 +624,173 @@ int trunc_count(const std::vector<double>& lam, double eps, int chi_max, double*
   return n;
 }
 
+// Exact gauge move of a charged C for which the Cholesky-QR steps failed (C
+// rank deficient or badly conditioned; after a basis extension the new
+// directions carry no weight).  left: C (rows x cols) = A R with A
+// orthonormal columns (rows x k); right: C = L B with B orthonormal rows
+// (k x cols).  The bond keeps, charge by charge, min(n_rows, n_cols) states
+// plus completions borrowed from charges with room to spare, so that k =
+// min(rows, cols) as in the dense move.  Its states: the range of C from the
+// Gram eigendecomposition charge by charge (weights above 1e-14 of the
+// largest, the numerical-zero rule), orthonormalised by Cholesky-QR, then
+// for the rest of each charge seeded random vectors of that charge,
+// projected out of the range twice and orthonormalised; every product walks
+// the charge blocks only.  Returns k, or -1 when a step fails (the caller
+// then factorises block by block with Householder reflections).
+int factor_exact_u1(Work& W, bool left, const void* C, int rows, int cols, const std::vector<int>& qrow,
+                    const std::vector<int>& qcol, DBuf& X1, DBuf& X2, std::vector<int>& qk) {
+  Range r_(left ? "exact_u1.left" : "exact_u1.right");
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  // the Gram index (its charges qg, size ng) and the other one (qo, no)
+  const std::vector<int>& qg = left ? qcol : qrow;
+  const std::vector<int>& qo = left ? qrow : qcol;
+  const int ng = left ? cols : rows, no = left ? rows : cols;
+  // states per charge: kb = min(count on the Gram side, count on the other),
+  // plus completions where the Gram side has more than the other can hold
+  std::map<int, int> cg, co, kt;
+  for (int x : qg) ++cg[x];
+  for (int x : qo) ++co[x];
+  int deficit = 0;
+  for (auto& kv : cg) deficit += std::max(0, kv.second - co[kv.first]);
+  for (auto& kv : co) kt[kv.first] = std::min(kv.second, cg.count(kv.first) ? cg[kv.first] : 0);
+  while (deficit > 0) {   // one at a time to the charge with the most room left
+    int best = 0, room = 0;
+    bool any = false;
+    for (auto& kv : co) {
+      const int r = kv.second - kt[kv.first];
+      if (r > room) {
+        room = r;
+        best = kv.first;
+        any = true;
+      }
+    }
+    if (!any) break;
+    ++kt[best];
+    --deficit;
+  }
+  int k = 0;
+  qk.clear();
+  for (auto& kv : kt) {
+    for (int j = 0; j < kv.second; ++j) qk.push_back(kv.first);
+    k += kv.second;
+  }
+  if (k == 0) return -1;
+  // Gram matrix and its eigendecomposition, charge by charge
+  W.tmpA.ensure((size_t)ng * ng * ZB);
+  W.tmpB.ensure((size_t)ng * ng * ZB);
+  if (left) qgemm(W, TDVP_OP_C, TDVP_OP_N, ng, ng, no, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, ng, &qg, &qo, &qg);
+  else qgemm(W, TDVP_OP_N, TDVP_OP_C, ng, ng, no, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, ng, &qg, &qo, &qg);
+  std::vector<double> lam;
+  std::vector<int> qv;
+  la::eigh_sectors(ctx, W.tmpA.p, ng, qg, lam, W.tmpB.p, W.work2, qv);
+  // range: weights above the floor, at most kt of each charge, ascending charge
+  const double floor = 1e-14 * (lam.empty() ? 0.0 : std::max(lam[0], 0.0));
+  std::map<int, int> used;
+  std::vector<int> sel;
+  for (int j = 0; j < ng; ++j)
+    if (lam[j] > floor && lam[j] > 0.0 && used[qv[j]] < kt[qv[j]]) {
+      ++used[qv[j]];
+      sel.push_back(j);
+    }
+  std::stable_sort(sel.begin(), sel.end(), [&](int a, int b) { return qv[a] < qv[b]; });
+  const int r = (int)sel.size();
+  std::vector<int> qsel(r), qE;
+  std::vector<double> lsel(r);
+  for (int j = 0; j < r; ++j) {
+    qsel[j] = qv[sel[j]];
+    lsel[j] = lam[sel[j]];
+  }
+  for (auto& kv : kt)
+    for (int j = used[kv.first]; j < kv.second; ++j) qE.push_back(kv.first);
+  const int m = (int)qE.size();
+  // positions of the range and random states in the bond (ascending charge,
+  // range first within a charge)
+  std::vector<int> pos_r(r), pos_e(m);
+  {
+    int p = 0, a = 0, b = 0;
+    for (auto& kv : kt) {
+      for (; a < r && qsel[a] == kv.first; ++a) pos_r[a] = p++;
+      for (; b < m && qE[b] == kv.first; ++b) pos_e[b] = p++;
+    }
+  }
+  std::vector<int> ints(sel);
+  ints.insert(ints.end(), pos_r.begin(), pos_r.end());
+  ints.insert(ints.end(), pos_e.begin(), pos_e.end());
+  ints.insert(ints.end(), qo.begin(), qo.end());
+  ints.insert(ints.end(), qE.begin(), qE.end());
+  W.pidx.ensure(sizeof(int) * std::max<size_t>(1, ints.size()));
+  upload(ctx, W.pidx.p, ints.data(), sizeof(int) * ints.size());
+  const int* dsel = W.pidx.as<int>();
+  const int* dpos_r = dsel + r;
+  const int* dpos_e = dpos_r + r;
+  const int* dqo = dpos_e + m;
+  const int* dqE = dqo + no;
+  // basis tensors: the range part Y (r states) and the random part E (m)
+  const long long sz = (long long)std::max(r, m) * no;
+  DBuf& Y = W.nst;
+  W.prow.ensure((size_t)std::max(sz, 1LL) * ZB);
+  W.tmpC.ensure((size_t)std::max(sz, 1LL) * ZB);
+  Y.ensure((size_t)std::max(sz, 1LL) * ZB);
+  DBuf Vs(ctx), Pm(ctx), Q(ctx), Rt(ctx);
+  if (r > 0) {
+    Vs.ensure((size_t)r * ng * ZB);
+    kern::zgather(s, Vs.p, ng, W.tmpB.p, ng, dsel, r, nullptr, ng);
+    const double* f = inv_sqrt_weights(W, lsel, r);
+    if (left) {   // Y = C V_sel^dagger S^-1 (rows x r), then orthonormal columns
+      qgemm(W, TDVP_OP_N, TDVP_OP_C, no, r, ng, 1.0, C, cols, Vs.p, ng, 0.0, W.tmpC.p, r, &qo, &qg, &qsel);
+      kern::zscale_cols(s, W.tmpC.p, r, W.tmpC.p, r, no, r, f);
+      Rt.ensure((size_t)r * r * ZB);
+      if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, no, r, Y.p, Rt.p, W.work, nullptr, &qsel, &qo, &W.ring)) return -1;
+    } else {      // Y = S^-1 U_sel^dagger C (r x cols), then orthonormal rows
+      qgemm(W, TDVP_OP_N, TDVP_OP_N, r, no, ng, 1.0, Vs.p, ng, C, cols, 0.0, W.tmpC.p, no, &qsel, &qg, &qo);
+      kern::zscale_rows(s, W.tmpC.p, no, W.tmpC.p, no, r, no, f);
+      Rt.ensure((size_t)r * r * ZB);
+      if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, r, no, Rt.p, Y.p, W.work, nullptr, &qsel, &qo, &W.ring)) return -1;
+    }
+  }
+  X1.ensure((size_t)(left ? no : rows) * k * ZB);
+  X2.ensure((size_t)k * (left ? cols : no) * ZB);
+  void* basis = left ? X1.p : X2.p;   // A (rows x k) or B (k x cols)
+  kern::zfill(s, basis, zc(0.0, 0.0), (long long)no * k, 16);
+  if (r > 0) {
+    if (left) kern::zscatter_cols(s, basis, k, Y.p, r, no, dpos_r, r);
+    else kern::zscatter(s, basis, no, Y.p, no, dpos_r, r, nullptr, no);
+  }
+  if (m > 0) {
+    // random states of each charge, projected out of the range twice
+    Q.ensure((size_t)m * no * ZB);
+    const unsigned long long seed = 0x5eedull ^ ((unsigned long long)no << 32) ^ (unsigned long long)(k * 131 + m);
+    if (left) kern::zrandom_blocks(s, W.prow.p, no, m, dqo, dqE, seed);
+    else kern::zrandom_blocks(s, W.prow.p, m, no, dqE, dqo, seed);
+    if (r > 0) {
+      Pm.ensure((size_t)r * m * ZB);
+      for (int pass = 0; pass < 2; ++pass) {
+        if (left) {
+          qgemm(W, TDVP_OP_C, TDVP_OP_N, r, m, no, 1.0, Y.p, r, W.prow.p, m, 0.0, Pm.p, m, &qsel, &qo, &qE);
+          qgemm(W, TDVP_OP_N, TDVP_OP_N, no, m, r, -1.0, Y.p, r, Pm.p, m, 1.0, W.prow.p, m, &qo, &qsel, &qE);
+        } else {
+          qgemm(W, TDVP_OP_N, TDVP_OP_C, m, r, no, 1.0, W.prow.p, no, Y.p, no, 0.0, Pm.p, r, &qE, &qo, &qsel);
+          qgemm(W, TDVP_OP_N, TDVP_OP_N, m, no, r, -1.0, Pm.p, r, Y.p, no, 1.0, W.prow.p, no, &qE, &qsel, &qo);
+        }
+      }
+    }
+    Rt.ensure((size_t)m * m * ZB);
+    if (left) {
+      if (!la::cholqr2_rowmajor(ctx, W.prow.p, no, m, Q.p, Rt.p, W.work, nullptr, &qE, &qo, &W.ring)) return -1;
+      kern::zscatter_cols(s, basis, k, Q.p, m, no, dpos_e, m);
+    } else {
+      if (!la::cholqr2_rows_rowmajor(ctx, W.prow.p, m, no, Rt.p, Q.p, W.work, nullptr, &qE, &qo, &W.ring)) return -1;
+      kern::zscatter(s, basis, no, Q.p, no, dpos_e, m, nullptr, no);
+    }
+  }
+  // the other factor: R = A^dagger C, or L = C B^dagger
+  if (left) qgemm(W, TDVP_OP_C, TDVP_OP_N, k, cols, rows, 1.0, X1.p, k, C, cols, 0.0, X2.p, cols, &qk, &qo, &qg);
+  else qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, k, cols, 1.0, C, cols, X2.p, cols, 0.0, X1.p, k, &qg, &qo, &qk);
+  HIP_CHECK(hipStreamSynchronize(s));   // the local buffers die here
+  return k;
+}
+
 // Gauge move to the right: C (ml x 2 x mr) -> A (ml x 2 x k) and R (k x mr).
 // With charges: qc (mr entries) are the charges the columns of C carry as a
 // left bond (for a site tensor, those of its right bond); the new bond's
@@ -663,6 +830,8 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     // rank-deficient (or not ordered by charge): Householder per charge
     // block, which keeps every direction of the bond, weight or not (the
     // extension's new directions carry none until the sweep evolves into them)
+    const int kx = factor_exact_u1(W, true, C, rows, cols, qrow, *qc, A, R, *qk);
+    if (kx > 0) return kx;
     Range r2_("split_left.sectors");
     return la::factor_sectors(ctx, true, C, rows, cols, fuse_xs(*qa, 1), *qc, A, R, *qk);
   }
@@ -763,6 +932,8 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
       return kk;
     }
     // as in split_left: LQ per charge block, every direction kept
+    const int kx = factor_exact_u1(W, false, C, rows, cols, *qr, qcol, L, B, *qk);
+    if (kx > 0) return kx;
     Range r2_("split_right.sectors");
     return la::factor_sectors(ctx, false, C, rows, cols, *qr, fuse_sx(*qb, -1), L, B, *qk);
   }

@@ -1079,6 +1079,28 @@ __global__ void zscatter_kernel(double2* __restrict__ dst, long long ldd, const 
 }
 
 // dst[j] = H[idx[j]*n + idx[j]]; rows[pos[j]*n + idx[j]] = 1 (unit eigenvector of a 1 x 1 block)
+// splitmix64 (Steele, Lea and Flood 2014) as a counter-based generator
+__device__ inline unsigned long long mix64(unsigned long long z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__global__ void zrandom_blocks_kernel(double2* __restrict__ E, int R, int C, const int* __restrict__ qr,
+                                      const int* __restrict__ qc, unsigned long long seed) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)R * C) return;
+  const int i = (int)(idx / C), j = (int)(idx % C);
+  double2 v{0.0, 0.0};
+  if (qr[i] == qc[j]) {
+    const unsigned long long a = mix64(seed ^ (2ull * (unsigned long long)idx)),
+                             b = mix64(seed ^ (2ull * (unsigned long long)idx + 1ull));
+    v.x = (double)(a >> 11) * 0x1.0p-52 - 1.0;
+    v.y = (double)(b >> 11) * 0x1.0p-52 - 1.0;
+  }
+  E[idx] = v;
+}
+
 __global__ void zunit_blocks_kernel(double2* __restrict__ dst, const double2* __restrict__ H, long long n,
                                     const int* __restrict__ idx, const int* __restrict__ pos, int cnt,
                                     double2* __restrict__ rows) {
@@ -1335,6 +1357,14 @@ void zfill(hipStream_t s, void* dst, zc v, long long n, int esize) {
   else
     hipLaunchKernelGGL(fill_kernel<float2>, dim3(nblk(n)), dim3(256), 0, s, static_cast<float2*>(dst),
                        make_float2(float(v.real()), float(v.imag())), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+void zrandom_blocks(hipStream_t s, void* E, int R, int C, const int* qr, const int* qc, unsigned long long seed) {
+  const long long n = (long long)R * C;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zrandom_blocks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, static_cast<double2*>(E),
+                     R, C, qr, qc, seed);
   HIP_CHECK(hipGetLastError());
 }
 
