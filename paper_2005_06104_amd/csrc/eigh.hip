@@ -141,8 +141,6 @@ __device__ inline double2 hh_v(int c, int k, double2 row_c, double2 sc) {
 // a reader still needs it.
 template <int NMAX, int LDS, bool QLDS>
 __global__ __launch_bounds__(TNT) void tridiag_kernel(TdBatch batch) {
-  __shared__ double2 sM[LDS];           // A rows [R][n], then (QLDS) Q rows [R][n]
-  __shared__ double2 sv[NMAX], sw[NMAX], srow[NMAX];
   __shared__ double sred[TNT / 64];     // per-wave |row[k+2:]|^2 of the pivot row
   __shared__ double2 s_xv[TNT / 64];    // per-wave parts of x^H v
   __shared__ int s_fail;
@@ -150,6 +148,25 @@ __global__ __launch_bounds__(TNT) void tridiag_kernel(TdBatch batch) {
   int sec = 0;
   while (sec + 1 < batch.nsec && batch.wg0[sec + 1] <= (int)blockIdx.x) ++sec;
   const TdArgs a = batch.sec[sec];
+  // A rows [R][n] (then, QLDS, Q rows [R][n]) and the vectors v, w and the
+  // pivot row: fixed arrays for n <= 512; for the larger matrices sized to
+  // the launch (R n + 3 n complex), so that two workgroups share a CU up to
+  // n ~ 730
+  double2 *sM, *sv, *sw, *srow;
+  if constexpr (QLDS) {
+    __shared__ double2 fM[LDS];
+    __shared__ double2 fv[NMAX], fw[NMAX], frow[NMAX];
+    sM = fM;
+    sv = fv;
+    sw = fw;
+    srow = frow;
+  } else {
+    extern __shared__ double2 td_dyn[];
+    sM = td_dyn;
+    sv = td_dyn + (size_t)a.R * a.n;
+    sw = sv + a.n;
+    srow = sw + a.n;
+  }
   const int n = a.n, G = a.G, R = a.R, g = (int)blockIdx.x - batch.wg0[sec], tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   double2* sA = sM;
@@ -433,9 +450,17 @@ hipError_t tridiag(hipStream_t s, const void* H, int n, void* Q, double* D, doub
 // (~ n^3 / G) is largest, up to four rows per workgroup.
 namespace {
 constexpr int TD_WG_LAUNCH = 256;
-int td_rmax(int n) { return n > TD_NMAX ? TD_LDS_BIG / n : std::min(TD_ROWS, TD_LDS / (2 * n)); }
+int td_rmax(int n) { return n > TD_NMAX ? 4 : std::min(TD_ROWS, TD_LDS / (2 * n)); }
 int td_gmin(int n) { return (n + td_rmax(n) - 1) / td_rmax(n); }
 int td_gpref(int n) { return std::min(n > TD_NMAX ? TD_G_BIG : 128, (n + 3) / 4); }
+// the larger variant: four rows per workgroup, LDS of R n + 3 n complex; as
+// many workgroups per launch as fit the CUs' LDS (160 KiB each, at most 8
+// workgroups of 256 threads)
+size_t td_big_lds(int n) { return sizeof(double2) * (size_t)(4 * n + 3 * n); }
+int td_big_cap(size_t lds) {
+  const size_t per_cu = std::min<size_t>(8, (160 * 1024 - 256) / lds);
+  return (int)(256 * std::max<size_t>(per_cu, 1));
+}
 }  // namespace
 
 hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* err) {
@@ -458,14 +483,17 @@ hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* er
     for (size_t k = 0; k < ids.size();) {
       std::vector<int> grp, G;
       int tot = 0;
+      // the first (largest) sector sets the LDS of the launch
+      const size_t lds = big ? td_big_lds(sec[ids[k]].n) : 0;
+      const int cap = big ? td_big_cap(lds) : TD_WG_LAUNCH;
       while (k < ids.size() && (int)grp.size() < TD_MAXSEC &&
-             (grp.empty() || tot + td_gmin(sec[ids[k]].n) <= TD_WG_LAUNCH)) {
+             (grp.empty() || tot + td_gmin(sec[ids[k]].n) <= cap)) {
         grp.push_back(ids[k]);
         G.push_back(td_gmin(sec[ids[k]].n));
         tot += G.back();
         ++k;
       }
-      for (int spare = TD_WG_LAUNCH - tot; spare > 0; --spare) {
+      for (int spare = (big ? 0 : TD_WG_LAUNCH - tot); spare > 0; --spare) {
         int best = -1;
         double wbest = 0.0;
         for (size_t j = 0; j < grp.size(); ++j) {
@@ -501,7 +529,7 @@ hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* er
       void* args[] = {&b};
       const void* kfn = big ? reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX_BIG, TD_LDS_BIG, false>)
                             : reinterpret_cast<const void*>(tridiag_kernel<TD_NMAX, TD_LDS, true>);
-      const hipError_t e = hipLaunchCooperativeKernel(kfn, dim3(wg), dim3(TNT), args, 0, s);
+      const hipError_t e = hipLaunchCooperativeKernel(kfn, dim3(wg), dim3(TNT), args, (unsigned)lds, s);
       if (e != hipSuccess) return e;
     }
   }
