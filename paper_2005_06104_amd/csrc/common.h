@@ -375,6 +375,15 @@ void zunit_blocks(hipStream_t s, void* diag, const void* H, long long n, const i
 // uniform in [-1, 1), from a counter hash of seed, i and j) where qr[i] ==
 // qc[j] and zero elsewhere; charge arrays on the device
 void zrandom_blocks(hipStream_t s, void* E, int R, int C, const int* qr, const int* qc, unsigned long long seed);
+// Row segments of a dense row-major matrix (leading dimension ld): row r
+// holds len[r] entries from column b0[r]; packed, they sit at off[r] ..
+// (seg = b0[rows], len[rows], off[rows] on the device).  pack: packed =
+// dense segments; unpack: dense segments = packed (other entries untouched).
+// Complex of esize 16 (complex128) or 8 (complex64) on either side.
+void pack_rows(hipStream_t s, void* packed, int packed_esize, const void* dense, int dense_esize, int rows, long long ld,
+               const int* seg, int maxlen);
+void unpack_rows(hipStream_t s, void* dense, int dense_esize, const void* packed, int packed_esize, int rows,
+                 long long ld, const int* seg, int maxlen);
 // per-physical-index scaling of rows of G[(x,s),q]: G *= f[s], complex128
 void zscale_phys(hipStream_t s, void* G, long long nx, long long nq, double f0, double f1);
 // G = a G + b I (n x n complex128)

@@ -477,14 +477,14 @@ namespace {
 struct Work {
   tdvp_ctx_s* ctx;
   kern::SplitWorkspaceScope gws;   // split-K scratch of the products issued below
-  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv, pidx, prow;
+  DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv, pidx, prow, xp, segd;
   Scalars sc;
   Lanczos lz;
   // maps of the charge-aware products issued one after another
   MapRing ring;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
-        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), sc(c), lz(c), ring(c) {}
+        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), xp(c), segd(c), sc(c), lz(c), ring(c) {}
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {
     const size_t b = (size_t)16 * 2 * ml * mr * cb;
@@ -1053,6 +1053,74 @@ double wstage_macs(const std::vector<int>& ql, const std::vector<int>& qr, const
 }
 
 // Block-sparse maps of one contraction's two products, rebuilt per site.
+// The allowed entries of a charged tensor viewed as rows x ncols: row r
+// holds the columns of charge target[r], one contiguous range when the
+// column charges qcol ascend.  host = b0[rows], len[rows], off[rows];
+// np = total; ok false when qcol does not ascend.
+struct RowSegments {
+  std::vector<int> host;
+  int rows = 0, maxlen = 0;
+  long long np = 0;
+  bool ok = false;
+};
+RowSegments row_segments(const std::vector<int>& target, const std::vector<int>& qcol) {
+  RowSegments g;
+  if (!std::is_sorted(qcol.begin(), qcol.end())) return g;
+  std::map<int, std::pair<int, int>> rng;
+  for (int b = 0; b < (int)qcol.size();) {
+    int e = b + 1;
+    while (e < (int)qcol.size() && qcol[e] == qcol[b]) ++e;
+    rng[qcol[b]] = {b, e};
+    b = e;
+  }
+  g.rows = (int)target.size();
+  g.host.assign(3 * (size_t)g.rows, 0);
+  long long off = 0;
+  for (int r = 0; r < g.rows; ++r) {
+    const auto it = rng.find(target[r]);
+    const int b0 = it == rng.end() ? 0 : it->second.first, len = it == rng.end() ? 0 : it->second.second - b0;
+    g.host[r] = b0;
+    g.host[g.rows + r] = len;
+    g.host[2 * g.rows + r] = (int)off;
+    off += len;
+    g.maxlen = std::max(g.maxlen, len);
+  }
+  g.np = off;
+  g.ok = off < (1LL << 31);
+  return g;
+}
+
+// Lanczos exponential of a charged tensor x (rows x ld, dense, exact zeros
+// outside its blocks) on the allowed entries only: the Krylov vectors hold
+// g.np entries (about a third of the dense size for the cylinder bonds);
+// each product unpacks its input into a dense buffer of the working
+// precision (zero outside the blocks, cleared once), applies `dense_mv`
+// and packs the result.
+template <typename T, class MV>
+int lanczos_packed(Work& W, const RowSegments& g, void* x, long long n, long long ld, MV&& dense_mv, zc step,
+                   double tol, int maxit, bool normalize, bool* unconv, MatvecTimer* timer) {
+  tdvp_ctx_s* ctx = W.ctx;
+  hipStream_t s = ctx->stream;
+  const int cb = cbytes<T>();
+  W.segd.ensure(sizeof(int) * g.host.size());
+  upload(ctx, W.segd.p, g.host.data(), sizeof(int) * g.host.size());
+  const int* seg = W.segd.as<int>();
+  W.xp.ensure((size_t)g.np * ZB);
+  W.xf.ensure((size_t)n * cb);
+  W.yf.ensure((size_t)n * cb);
+  kern::zfill(s, W.xf.p, zc(0.0, 0.0), n, cb);
+  kern::pack_rows(s, W.xp.p, ZB, x, ZB, g.rows, ld, seg, g.maxlen);
+  auto mv = [&](const void* in, void* out) {
+    kern::unpack_rows(s, W.xf.p, cb, in, ZB, g.rows, ld, seg, g.maxlen);
+    dense_mv(W.xf.p, W.yf.p);
+    kern::pack_rows(s, out, ZB, W.yf.p, cb, g.rows, ld, seg, g.maxlen);
+  };
+  const int napp = W.lz.run(mv, W.xp.p, g.np, step, tol, maxit, normalize, unconv, timer);
+  kern::unpack_rows(s, x, ZB, W.xp.p, ZB, g.rows, ld, seg, g.maxlen);
+  HIP_CHECK(hipStreamSynchronize(s));   // `g.host` may be pageable memory that dies after the return
+  return napp;
+}
+
 struct PairMaps {
   DevKMap g1, g2;
   explicit PairMaps(tdvp_ctx_s* c) : g1(c), g2(c) {}
@@ -1153,7 +1221,24 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
       st.flops_matvec += flops;
     };
     bool unconv = false;
-    const int napp = W.lz.run(mv, psi.site(i), n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv, &timer);
+    int napp;
+    RowSegments g;
+    if (sym) {
+      std::vector<int> tgt(2 * (size_t)ml);
+      for (int a = 0; a < ml; ++a)
+        for (int s2 = 0; s2 < 2; ++s2) tgt[2 * (size_t)a + s2] = psi.q[i][a] + phys_charge(s2);
+      g = row_segments(tgt, psi.q[i + 1]);
+    }
+    if (g.ok && g.np > 0 && g.np < n) {
+      auto dmv = [&](const void* in, void* out) {
+        heff_apply<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, R[i + 1].p, in, out, W.ws1.p, W.ws2.p, &timer, sk, pm);
+        st.flops_matvec += flops;
+      };
+      napp = lanczos_packed<T>(W, g, psi.site(i), n, mr, dmv, step, p.krylov_tol, p.krylov_max, p.normalize != 0,
+                               &unconv, &timer);
+    } else {
+      napp = W.lz.run(mv, psi.site(i), n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv, &timer);
+    }
     st.n_matvec += napp;
     stepinfo(napp, unconv);
   };
@@ -1185,7 +1270,16 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
       }
     };
     bool unconv = false;
-    const int napp = W.lz.run(mv, X, n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv, nullptr);
+    int napp;
+    RowSegments g;
+    if (sym) g = row_segments(*qa, *qb);
+    if (g.ok && g.np > 0 && g.np < n) {
+      auto dmv = [&](const void* in, void* out) { keff_apply<T>(ctx, ml, w, mr, L[b].p, R[b].p, in, out, W.ws1.p, sk, pm); };
+      napp = lanczos_packed<T>(W, g, X, n, mr, dmv, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv,
+                               nullptr);
+    } else {
+      napp = W.lz.run(mv, X, n, step, p.krylov_tol, p.krylov_max, p.normalize != 0, &unconv, nullptr);
+    }
     st.n_keff += napp;
     stepinfo(napp, unconv);
   };

@@ -1079,6 +1079,25 @@ __global__ void zscatter_kernel(double2* __restrict__ dst, long long ldd, const 
 }
 
 // dst[j] = H[idx[j]*n + idx[j]]; rows[pos[j]*n + idx[j]] = 1 (unit eigenvector of a 1 x 1 block)
+template <typename D, typename S>
+__device__ inline D cconv(S v) {
+  D d;
+  d.x = v.x;
+  d.y = v.y;
+  return d;
+}
+// block (x, r): entries x * 256 + t of row segment r
+template <typename P, typename Dn, bool PACK>
+__global__ void rows_pack_kernel(P* __restrict__ packed, Dn* __restrict__ dense, int rows, long long ld,
+                                 const int* __restrict__ seg) {
+  const int r = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b0 = seg[r], len = seg[rows + r], off = seg[2 * rows + r];
+  if (j >= len) return;
+  if (PACK) packed[(long long)off + j] = cconv<P>(dense[(long long)r * ld + b0 + j]);
+  else dense[(long long)r * ld + b0 + j] = cconv<Dn>(packed[(long long)off + j]);
+}
+
 // splitmix64 (Steele, Lea and Flood 2014) as a counter-based generator
 __device__ inline unsigned long long mix64(unsigned long long z) {
   z += 0x9e3779b97f4a7c15ull;
@@ -1358,6 +1377,31 @@ void zfill(hipStream_t s, void* dst, zc v, long long n, int esize) {
     hipLaunchKernelGGL(fill_kernel<float2>, dim3(nblk(n)), dim3(256), 0, s, static_cast<float2*>(dst),
                        make_float2(float(v.real()), float(v.imag())), n);
   HIP_CHECK(hipGetLastError());
+}
+
+template <bool PACK>
+void rows_pack_dispatch(hipStream_t s, void* packed, int pe, void* dense, int de, int rows, long long ld, const int* seg,
+                        int maxlen) {
+  if (rows <= 0 || maxlen <= 0) return;
+  if (rows > 65535) TDVP_THROW(TDVP_ERR_ARG, "row segments: too many rows");
+  const dim3 grid((unsigned)((maxlen + 255) / 256), (unsigned)rows);
+  if (pe == 16 && de == 16)
+    hipLaunchKernelGGL((rows_pack_kernel<double2, double2, PACK>), grid, dim3(256), 0, s, static_cast<double2*>(packed),
+                       static_cast<double2*>(dense), rows, ld, seg);
+  else if (pe == 16 && de == 8)
+    hipLaunchKernelGGL((rows_pack_kernel<double2, float2, PACK>), grid, dim3(256), 0, s, static_cast<double2*>(packed),
+                       static_cast<float2*>(dense), rows, ld, seg);
+  else
+    TDVP_THROW(TDVP_ERR_ARG, "row segments: unsupported element sizes");
+  HIP_CHECK(hipGetLastError());
+}
+void pack_rows(hipStream_t s, void* packed, int packed_esize, const void* dense, int dense_esize, int rows, long long ld,
+               const int* seg, int maxlen) {
+  rows_pack_dispatch<true>(s, packed, packed_esize, const_cast<void*>(dense), dense_esize, rows, ld, seg, maxlen);
+}
+void unpack_rows(hipStream_t s, void* dense, int dense_esize, const void* packed, int packed_esize, int rows,
+                 long long ld, const int* seg, int maxlen) {
+  rows_pack_dispatch<false>(s, const_cast<void*>(packed), packed_esize, dense, dense_esize, rows, ld, seg, maxlen);
 }
 
 void zrandom_blocks(hipStream_t s, void* E, int R, int C, const int* qr, const int* qc, unsigned long long seed) {
