@@ -835,6 +835,30 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     Range r2_("split_left.sectors");
     return la::factor_sectors(ctx, true, C, rows, cols, fuse_xs(*qa, 1), *qc, A, R, *qk);
   }
+  if (rows < cols) {
+    // fewer rows: the left singular vectors straight from the eigenvectors
+    // of G = C C^dagger (rows x rows), A = U_n, R = A^dagger C (orthonormal
+    // to rounding; no weights divided out)
+    Range r1_("split_left.rows_gram");
+    W.tmpA.ensure((size_t)rows * rows * ZB);
+    W.tmpB.ensure((size_t)rows * rows * ZB);
+    qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, rows, cols, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, rows, qrp, qc, qrp);
+    std::vector<double> lam;
+    std::vector<int> qv;
+    if (sym) la::eigh_sectors(ctx, W.tmpA.p, rows, qrow, lam, W.tmpB.p, W.work2, qv);
+    else la::eigh_rows_desc(ctx, W.tmpA.p, rows, lam, W.tmpB.p, W.work2);
+    const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
+    if (sym) {
+      sort_rows_by_charge(W, W.tmpB.p, rows, n, &lam, qv);
+      *qk = qv;
+    }
+    const std::vector<int>* qkp = sym ? qk : nullptr;
+    A.ensure((size_t)rows * n * ZB);
+    R.ensure((size_t)n * cols * ZB);
+    kern::zconjtrans(s, A.p, n, W.tmpB.p, rows, rows, n);   // A[:, j] = (row j of U^dagger)^dagger
+    qgemm(W, TDVP_OP_N, TDVP_OP_N, n, cols, rows, 1.0, W.tmpB.p, rows, C, cols, 0.0, R.p, cols, qkp, qrp, qc);
+    return n;
+  }
   // G = C^dagger C (cols x cols); rows of V^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)cols * cols * ZB);
   W.tmpB.ensure((size_t)cols * cols * ZB);
@@ -936,6 +960,30 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (kx > 0) return kx;
     Range r2_("split_right.sectors");
     return la::factor_sectors(ctx, false, C, rows, cols, *qr, fuse_sx(*qb, -1), L, B, *qk);
+  }
+  if (cols < rows) {
+    // fewer columns: the right singular vectors straight from the
+    // eigenvectors of G = C^dagger C (cols x cols), B = V_n^dagger,
+    // L = C B^dagger (orthonormal to rounding; no weights divided out)
+    Range r1_("split_right.cols_gram");
+    W.tmpA.ensure((size_t)cols * cols * ZB);
+    W.tmpB.ensure((size_t)cols * cols * ZB);
+    qgemm(W, TDVP_OP_C, TDVP_OP_N, cols, cols, rows, 1.0, C, cols, C, cols, 0.0, W.tmpA.p, cols, qcp, qr, qcp);
+    std::vector<double> lam;
+    std::vector<int> qv;
+    if (sym) la::eigh_sectors(ctx, W.tmpA.p, cols, qcol, lam, W.tmpB.p, W.work2, qv);
+    else la::eigh_rows_desc(ctx, W.tmpA.p, cols, lam, W.tmpB.p, W.work2);
+    const int n = std::min(trunc_count(lam, eps, chi_max, disc), kk);
+    if (sym) {
+      sort_rows_by_charge(W, W.tmpB.p, cols, n, &lam, qv);
+      *qk = qv;
+    }
+    const std::vector<int>* qkp = sym ? qk : nullptr;
+    L.ensure((size_t)rows * n * ZB);
+    B.ensure((size_t)n * cols * ZB);
+    HIP_CHECK(hipMemcpyAsync(B.p, W.tmpB.p, (size_t)n * cols * ZB, hipMemcpyDeviceToDevice, s));
+    qgemm(W, TDVP_OP_N, TDVP_OP_C, rows, n, cols, 1.0, C, cols, B.p, cols, 0.0, L.p, n, qr, qcp, qkp);
+    return n;
   }
   // G = C C^dagger (rows x rows); rows of U^dagger from its eigendecomposition
   W.tmpA.ensure((size_t)rows * rows * ZB);

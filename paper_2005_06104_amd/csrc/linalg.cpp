@@ -736,13 +736,18 @@ void eigh_sectors(tdvp_ctx_s* ctx, const void* H, int n, const std::vector<int>&
     }
   }
   std::vector<char> bad;
-  const bool batched = boff.size() > 1 && eigh_blocks(ctx, H, n, didx, boff, bnb, sec.p, lam_sec, bad, work);
+  bool batched = false;
+  if (boff.size() > 1) {
+    Range r_("eigh.blocks");
+    batched = eigh_blocks(ctx, H, n, didx, boff, bnb, sec.p, lam_sec, bad, work);
+  }
   for (int c = 0, b = 0; c < ns; ++c) {
     const int o = sc.off[c], nb = sc.off[c + 1] - o;
     if (nb < 2) continue;
     const bool in_batch = b < (int)boff.size() && boff[b] == o;
     if (in_batch) ++b;
     if (batched && in_batch && !bad[b - 1]) continue;
+    Range r_(nb > 1024 ? "eigh.block_large" : batched && in_batch ? "eigh.block_redo" : "eigh.block_single");
     kern::zgather(s, blk.p, nb, H, n, didx + o, nb, didx + o, nb);
     eigh_rows_desc(ctx, blk.p, nb, lb, rb.p, work);
     kern::zscatter_cols(s, static_cast<char*>(sec.p) + sizeof(zc) * (size_t)o * n, n, rb.p, nb, nb, didx + o, nb);
