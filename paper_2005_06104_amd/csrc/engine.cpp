@@ -2013,7 +2013,9 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     // otherwise a Jacobi SVD resolves the small singular values.
     W.tmpA.ensure((size_t)ml * ml * ZB);
     W.tmpB.ensure((size_t)ml * ml * ZB);
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, ml, ml, D, 1.0, C, D, 0, C, D, 0, 0.0, W.tmpA.p, ml, 0, 1);
+    const std::vector<int>* qi = sym ? &psi.q[i] : nullptr;
+    const std::vector<int>* qDp = sym ? &qD : nullptr;
+    qgemm(W, TDVP_OP_N, TDVP_OP_C, ml, ml, D, 1.0, C, D, C, D, 0.0, W.tmpA.p, ml, qi, qDp, qi);
     int r = 0;
     Vh.ensure((size_t)std::min(ml, D) * D * ZB);
     // Full row rank is certified without the eigendecomposition when the
@@ -2044,7 +2046,7 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       r = ml;
       // B = S^-1 U^dagger C, polished by Newton-Schulz
       W.tmpC.ensure((size_t)ml * D * ZB);
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, ml, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
+      qgemm(W, TDVP_OP_N, TDVP_OP_N, ml, D, ml, 1.0, W.tmpB.p, ml, C, D, 0.0, W.tmpC.p, D, sym ? &qv : nullptr, qi, qDp);
       kern::zscale_rows(s, Vh.p, D, W.tmpC.p, D, ml, D, inv_sqrt_weights(W, S, ml));
       ns_rows(W, Vh.p, ml, D, 3);
       if (sym) {
@@ -2060,7 +2062,9 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       // span; the part of C outside that span is below 1e-18 of its weight.
       for (double v : S) r += (v > 1e-14 * S[0]) ? 1 : 0;
       W.tmpC.ensure((size_t)r * D * ZB);
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, r, D, ml, 1.0, W.tmpB.p, ml, 0, C, D, 0, 0.0, W.tmpC.p, D, 0, 1);
+      std::vector<int> qvr;
+      if (sym) qvr.assign(qv.begin(), qv.begin() + r);
+      qgemm(W, TDVP_OP_N, TDVP_OP_N, r, D, ml, 1.0, W.tmpB.p, ml, C, D, 0.0, W.tmpC.p, D, sym ? &qvr : nullptr, qi, qDp);
       kern::zscale_rows(s, W.tmpC.p, D, W.tmpC.p, D, r, D, inv_sqrt_weights(W, S, r));
       W.tmpA.ensure((size_t)r * r * ZB);
       if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, r, D, W.tmpA.p, Vh.p, W.work)) {
@@ -2080,7 +2084,9 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
     Bp.ensure((size_t)D * D * ZB);  // r + n <= D rows
     kern::copy2d(s, Bp.p, D, Vh.p, D, r, D, ZB);
     int n = 0;
-    std::vector<int> qbar;
+    std::vector<int> qbar, qBr, qstack;   // charges of B's r rows, of the stacked Krylov rows
+    if (sym) qBr.assign(qB.begin(), qB.begin() + r);
+    const std::vector<int>* qBp = sym ? &qBr : nullptr;
     if (cap > 0 && !kv.empty()) {
       // projected Krylov centers, stacked: X_l = Ct_l - (Ct_l B^dagger) B
       int rows_tot = 0;
@@ -2092,17 +2098,20 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
         const int mt = k.m[i];
         void* Xl = static_cast<char*>(Xs.p) + (size_t)off * D * ZB;
         HIP_CHECK(hipMemcpyAsync(Xl, k.site(i), (size_t)mt * D * ZB, hipMemcpyDeviceToDevice, s));
+        const std::vector<int>* qt = sym && k.u1() ? &k.q[i] : nullptr;
+        if (qt) qstack.insert(qstack.end(), qt->begin(), qt->end());
         if (r > 0) {
           P.ensure((size_t)mt * r * ZB);
-          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, mt, r, D, 1.0, k.site(i), D, 0, Bp.p, D, 0, 0.0, P.p, r, 0, 1);
-          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, mt, D, r, -1.0, P.p, r, 0, Bp.p, D, 0, 1.0, Xl, D, 0, 1);
+          qgemm(W, TDVP_OP_N, TDVP_OP_C, mt, r, D, 1.0, k.site(i), D, Bp.p, D, 0.0, P.p, r, qt, qDp, qBp);
+          qgemm(W, TDVP_OP_N, TDVP_OP_N, mt, D, r, -1.0, P.p, r, Bp.p, D, 1.0, Xl, D, qt, qBp, qDp);
         }
         tr_ref += W.sc.dot(k.site(i), k.site(i), (long long)mt * D).real();
         off += mt;
       }
       // rho_bar = sum_l X_l^dagger X_l   (D x D)
       rhob.ensure((size_t)D * D * ZB);
-      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, D, D, rows_tot, 1.0, Xs.p, D, 0, Xs.p, D, 0, 0.0, rhob.p, D, 0, 1);
+      const std::vector<int>* qsp = (int)qstack.size() == rows_tot ? &qstack : nullptr;
+      qgemm(W, TDVP_OP_C, TDVP_OP_N, D, D, rows_tot, 1.0, Xs.p, D, Xs.p, D, 0.0, rhob.p, D, qDp, qsp, qDp);
       rows.ensure((size_t)D * D * ZB);
       if (sym) la::eigh_sectors(ctx, rhob.p, D, qD, lam, rows.p, W.work, qbar);
       else la::eigh_rows_desc(ctx, rhob.p, D, lam, rows.p, W.work);
@@ -2113,17 +2122,22 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       if (n > 0) {
         void* Bbar = static_cast<char*>(Bp.p) + (size_t)r * D * ZB;
         kern::copy2d(s, Bbar, D, rows.p, D, n, D, ZB);
+        std::vector<int> qbn;
+        if (sym) qbn.assign(qbar.begin(), qbar.begin() + n);
+        const std::vector<int>* qbp = sym ? &qbn : nullptr;
         if (r > 0) {
           Pb.ensure((size_t)n * r * ZB);
-          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, n, r, D, 1.0, Bbar, D, 0, Bp.p, D, 0, 0.0, Pb.p, r, 0, 1);
-          kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, n, D, r, -1.0, Pb.p, r, 0, Bp.p, D, 0, 1.0, Bbar, D, 0, 1);
+          qgemm(W, TDVP_OP_N, TDVP_OP_C, n, r, D, 1.0, Bbar, D, Bp.p, D, 0.0, Pb.p, r, qbp, qDp, qBp);
+          qgemm(W, TDVP_OP_N, TDVP_OP_N, n, D, r, -1.0, Pb.p, r, Bp.p, D, 1.0, Bbar, D, qbp, qBp, qDp);
         }
         // the eigenvector rows stay orthonormal up to the projection above;
         // Newton-Schulz restores orthonormality within their span
-        ns_rows(W, Bbar, n, D, 2);
+        ns_rows(W, Bbar, n, D, 2, qbp, qDp);
       }
     }
     const int mnew = r + n;
+    std::vector<int> qi_old;
+    if (sym) qi_old = psi.q[i];
     if (sym) {
       std::vector<int> qall(qB.begin(), qB.begin() + r);
       qall.insert(qall.end(), qbar.begin(), qbar.begin() + n);
@@ -2131,14 +2145,23 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
       psi.q[i] = qall;
     }
     // center moves: C_{i-1} = A_{i-1} (C_i B'^dagger), same for every Krylov vector
-    zmatmul(ctx, TDVP_OP_N, TDVP_OP_C, ml, mnew, D, C, D, Bp.p, D, Mc);
-    zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * psi.m[i - 1], mnew, ml, psi.site(i - 1), ml, Mc.p, mnew, nxt);
-    std::swap(psi.t[i - 1], nxt);
+    // (with charges: old bond i charges qi for psi, the Krylov vector's own
+    // for it; rows of site i-1 fused (a, s))
+    const std::vector<int>* qn = sym ? &psi.q[i] : nullptr;   // the new bond (sorted above)
+    auto move = [&](tdvp_mps_s& x, const std::vector<int>* qold) {
+      const int mo = x.m[i];
+      Mc.ensure((size_t)mo * mnew * ZB);
+      qgemm(W, TDVP_OP_N, TDVP_OP_C, mo, mnew, D, 1.0, x.site(i), D, Bp.p, D, 0.0, Mc.p, mnew, qold, qDp, qn);
+      std::vector<int> qrow;
+      if (sym && qold && x.u1()) qrow = fuse_xs(x.q[i - 1], 1);
+      nxt.ensure((size_t)2 * x.m[i - 1] * mnew * ZB);
+      qgemm(W, TDVP_OP_N, TDVP_OP_N, 2 * x.m[i - 1], mnew, mo, 1.0, x.site(i - 1), mo, Mc.p, mnew, 0.0, nxt.p, mnew,
+            qrow.empty() ? nullptr : &qrow, qold, qn);
+      std::swap(x.t[i - 1], nxt);
+    };
+    move(psi, qi_old.empty() ? nullptr : &qi_old);
     for (auto& k : kv) {
-      const int mt = k.m[i];
-      zmatmul(ctx, TDVP_OP_N, TDVP_OP_C, mt, mnew, D, k.site(i), D, Bp.p, D, Mc);
-      zmatmul(ctx, TDVP_OP_N, TDVP_OP_N, 2 * k.m[i - 1], mnew, mt, k.site(i - 1), mt, Mc.p, mnew, nxt);
-      std::swap(k.t[i - 1], nxt);
+      move(k, sym && k.u1() ? &k.q[i] : nullptr);
       k.m[i] = mnew;
     }
     // the new right-orthonormal tensor of psi at site i
