@@ -306,11 +306,19 @@ void join_batches(const std::vector<KMapHost>& parts, KMapHost& out) {
 }
 
 // rows a' of batch x need q(a') + sign * shift[x]
+// (the channels take few distinct charges: one map per distinct shift)
 void build_batched(const std::vector<int>& qrow, const std::vector<int>& shift, int sign, const std::vector<int>& kq,
                    const std::vector<int>& cq, KMapHost& out) {
   std::vector<KMapHost> parts(shift.size());
+  std::map<int, size_t> first;
   std::vector<int> rq(qrow.size());
   for (size_t x = 0; x < shift.size(); ++x) {
+    const auto it = first.find(shift[x]);
+    if (it != first.end()) {
+      parts[x] = parts[it->second];
+      continue;
+    }
+    first[shift[x]] = x;
     for (size_t r = 0; r < qrow.size(); ++r) rq[r] = qrow[r] + sign * shift[x];
     build_kmap(rq, kq, cq, parts[x]);
   }
@@ -343,8 +351,15 @@ void kmap_env_right_gemm1(const std::vector<int>& qli, const std::vector<int>& q
                           const std::vector<int>& qro, KMapHost& out) {
   const std::vector<int> rq = fuse2(qli, kPhys, 1, 1);
   std::vector<KMapHost> parts(qwr.size());
+  std::map<int, size_t> first;
   std::vector<int> cq(qro.size());
   for (size_t x = 0; x < qwr.size(); ++x) {
+    const auto it = first.find(qwr[x]);
+    if (it != first.end()) {
+      parts[x] = parts[it->second];
+      continue;
+    }
+    first[qwr[x]] = x;
     for (size_t c = 0; c < qro.size(); ++c) cq[c] = qro[c] - qwr[x];
     build_kmap(rq, qri, cq, parts[x]);
   }
