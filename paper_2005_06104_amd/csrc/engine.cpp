@@ -2286,16 +2286,24 @@ void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, co
   for (int i = 0; i <= N; ++i) Rtr.emplace_back(ctx);
   set_one(ctx, Rtr[N], ZB);
   DBuf G(ctx), Tn(ctx), Tz(ctx), Tl(ctx);
+  // with charges every transfer is block diagonal and the products walk the
+  // charge blocks: rows (a, s) of a site carry q(a) + q(s), columns (s, b)
+  // as a left bond q(b) - q(s)
+  const bool qs = psi.u1();
+  auto qxs = [&](int i) { return qs ? fuse_xs(psi.q[i], 1) : std::vector<int>(); };
+  auto qsx = [&](int i) { return qs ? fuse_sx(psi.q[i + 1], -1) : std::vector<int>(); };
+  auto qp = [&](const std::vector<int>& v) { return qs ? &v : nullptr; };
   for (int i = N - 1; i >= 0; --i) {
     const int ml = psi.m[i], mr = psi.m[i + 1];
     G.ensure((size_t)2 * ml * mr * ZB);
+    const std::vector<int> qrow = qxs(i), qcol = qsx(i);
     // G[(y,s),p] = sum_q M[(y,s),q] Rtr[p,q]
-    kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_T, 2 * ml, mr, mr, 1.0, psi.site(i), mr, 0, Rtr[i + 1].p, mr, 0, 0.0, G.p,
-                       mr, 0, 1);
+    qgemm(W, TDVP_OP_N, TDVP_OP_T, 2 * ml, mr, mr, 1.0, psi.site(i), mr, Rtr[i + 1].p, mr, 0.0, G.p, mr, qp(qrow),
+          qs ? &psi.q[i + 1] : nullptr, qs ? &psi.q[i + 1] : nullptr);
     // Rtr[x,y] = sum_{(s,p)} conj(M[x,(s,p)]) G[y,(s,p)]
     Rtr[i].ensure((size_t)ml * ml * ZB);
-    kern::gemm<double>(s, TDVP_OP_R, TDVP_OP_T, ml, ml, 2 * mr, 1.0, psi.site(i), 2LL * mr, 0, G.p, 2LL * mr, 0, 0.0,
-                       Rtr[i].p, ml, 0, 1);
+    qgemm(W, TDVP_OP_R, TDVP_OP_T, ml, ml, 2 * mr, 1.0, psi.site(i), 2LL * mr, G.p, 2LL * mr, 0.0, Rtr[i].p, ml,
+          qs ? &psi.q[i] : nullptr, qp(qcol), qs ? &psi.q[i] : nullptr);
   }
   zc nn;
   download(ctx, &nn, Rtr[0].p, ZB);
@@ -2309,16 +2317,17 @@ void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, co
     for (int i = 0; i < N; ++i) {
       const int ml = psi.m[i], mr = psi.m[i + 1];
       G.ensure((size_t)ml * 2 * mr * ZB);
+      const std::vector<int> qrow = qxs(i), qcol = qsx(i);
+      const std::vector<int>* ql = qs ? &psi.q[i] : nullptr;
+      const std::vector<int>* qr = qs ? &psi.q[i + 1] : nullptr;
       // G[x,(s,q)] = sum_y T[x,y] M[y,(s,q)]
-      kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_N, ml, 2 * mr, ml, 1.0, Tl.p, ml, 0, psi.site(i), 2LL * mr, 0, 0.0, G.p,
-                         2LL * mr, 0, 1);
+      qgemm(W, TDVP_OP_N, TDVP_OP_N, ml, 2 * mr, ml, 1.0, Tl.p, ml, psi.site(i), 2LL * mr, 0.0, G.p, 2LL * mr, ql, ql,
+            qp(qcol));
       Tn.ensure((size_t)mr * mr * ZB);
       Tz.ensure((size_t)mr * mr * ZB);
-      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mr, mr, 2 * ml, 1.0, psi.site(i), mr, 0, G.p, mr, 0, 0.0, Tn.p, mr, 0,
-                         1);
+      qgemm(W, TDVP_OP_C, TDVP_OP_N, mr, mr, 2 * ml, 1.0, psi.site(i), mr, G.p, mr, 0.0, Tn.p, mr, qr, qp(qrow), qr);
       kern::zscale_phys(s, G.p, ml, mr, 0.5, -0.5);
-      kern::gemm<double>(s, TDVP_OP_C, TDVP_OP_N, mr, mr, 2 * ml, 1.0, psi.site(i), mr, 0, G.p, mr, 0, 0.0, Tz.p, mr, 0,
-                         1);
+      qgemm(W, TDVP_OP_C, TDVP_OP_N, mr, mr, 2 * ml, 1.0, psi.site(i), mr, G.p, mr, 0.0, Tz.p, mr, qr, qp(qrow), qr);
       const zc v = W.sc.dot(Tz.p, Rtr[i + 1].p, (long long)mr * mr, false);
       out.sz[i] = v.real() / norm2;
       std::swap(Tl, Tn);
