@@ -2,11 +2,15 @@
 //
 // A product C[m, n] = sum_k A[m, k] B[k, n] between charged tensors has
 // nonzero terms only where the charge a row m needs on the summed index, the
-// charge of k, and the charge column n needs on it all agree.  For every
-// 64 x 64 output tile the map lists the K intervals holding the charges
-// that occur among both the tile's rows and its columns; the MFMA kernels
-// walk only those.  Intervals closer than a K step are joined (the skipped
-// entries between them are exact zeros, so including them changes nothing).
+// charge of k, and the charge column n needs on it all agree.  Each 64 x 64
+// output tile is cut where the charge of its rows (and of its columns)
+// changes, into at most 2 x 2 sub-blocks of one charge each (a tile whose
+// rows or columns change charge more than once keeps them as one segment
+// with all their charges); every sub-block lists the K intervals of the
+// charges its rows and columns share, and the MFMA kernels walk only those,
+// skipping the 16 x 16 pieces of the tile outside the sub-block.  Intervals
+// closer than a K step are joined (the skipped entries between them are
+// exact zeros, so including them changes nothing).
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -22,6 +26,38 @@ struct Run {
   int b, e;
 };
 
+// segments of a tile's rows (or columns): each run of one charge when there
+// are at most two, else one segment with every charge of the tile
+struct Seg {
+  int b, e;
+  std::vector<int> q;   // sorted distinct charges (offset by cmin)
+};
+
+std::vector<std::vector<Seg>> tile_segments(const std::vector<int>& q, int n, int cmin) {
+  const int nt = (n + TILE - 1) / TILE;
+  std::vector<std::vector<Seg>> out(nt);
+  for (int t = 0; t < nt; ++t) {
+    const int b = t * TILE, e = std::min(n, b + TILE);
+    std::vector<Seg> runs;
+    for (int i = b; i < e;) {
+      int j = i + 1;
+      while (j < e && q[j] == q[i]) ++j;
+      runs.push_back({i, j, {q[i] - cmin}});
+      i = j;
+    }
+    if (runs.size() <= 2 && (runs.size() < 2 || runs[0].q[0] != runs[1].q[0])) {
+      out[t] = runs;
+    } else {
+      Seg all{b, e, {}};
+      for (int i = b; i < e; ++i) all.q.push_back(q[i] - cmin);
+      std::sort(all.q.begin(), all.q.end());
+      all.q.erase(std::unique(all.q.begin(), all.q.end()), all.q.end());
+      out[t].push_back(all);
+    }
+  }
+  return out;
+}
+
 }  // namespace
 
 void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out) {
@@ -33,6 +69,7 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
       cmax = std::max(cmax, x);
     }
   const int R = M && N && K ? cmax - cmin + 1 : 1;
+  if (!(M && N && K)) cmin = 0;
   // runs of equal charge along K, listed per charge in order
   std::vector<std::vector<Run>> runs(R);
   for (int k = 0; k < K;) {
@@ -41,66 +78,53 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
     runs[kq[k] - cmin].push_back({k, e});
     k = e;
   }
-  // distinct charges of each row tile and column tile
-  auto tile_sets = [&](const std::vector<int>& q, int n) {
-    const int nt = (n + TILE - 1) / TILE;
-    std::vector<std::vector<int>> sets(nt);
-    std::vector<int> stamp(R, -1);
-    for (int t = 0; t < nt; ++t)
-      for (int i = t * TILE; i < std::min(n, (t + 1) * TILE); ++i) {
-        const int c = q[i] - cmin;
-        if (stamp[c] != t) {
-          stamp[c] = t;
-          sets[t].push_back(c);
-        }
-      }
-    return sets;
-  };
-  const auto rs = tile_sets(rq, M), cs = tile_sets(cq, N);
+  const auto rs = tile_segments(rq, M, cmin), cs = tile_segments(cq, N, cmin);
   const int tm = (int)rs.size(), tn = (int)cs.size();
-  out.off.assign((size_t)tm * tn + 1, 0);
-  out.iv.clear();
-  out.tile_macs = 0.0;
-  std::vector<int> mark(R, -1);
-  std::vector<Run> sel;
-  // the merged intervals depend only on the set of charges a tile meets, and
-  // most tiles meet one or two: merge once per distinct set
+  out = KMapHost();
+  out.off.assign(1, 0);
+  out.tiles = tm * tn;
+  out.tinfo.assign((size_t)6 * tm * tn, 0);
+  // the merged intervals depend only on the set of charges a sub-block
+  // meets: merge once per distinct set
   struct Merged {
     std::vector<int> iv;
     long long klen = 0;
   };
   std::map<std::vector<int>, Merged> cache;
   std::vector<int> common;
-  for (int a = 0; a < tm; ++a) {
-    for (int c : rs[a]) mark[c] = a;
-    const int rows = std::min(M, (a + 1) * TILE) - a * TILE;
+  std::vector<Run> sel;
+  for (int a = 0; a < tm; ++a)
     for (int b = 0; b < tn; ++b) {
-      common.clear();
-      for (int c : cs[b])
-        if (mark[c] == a) common.push_back(c);
-      std::sort(common.begin(), common.end());
-      auto it = cache.find(common);
-      if (it == cache.end()) {
-        Merged m;
-        sel.clear();
-        for (int c : common) sel.insert(sel.end(), runs[c].begin(), runs[c].end());
-        std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
-        for (size_t j = 0; j < sel.size();) {
-          Run cur = sel[j++];
-          while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
-          m.iv.push_back(cur.b);
-          m.iv.push_back(cur.e);
-          m.klen += cur.e - cur.b;
+      const int t = a * tn + b;
+      out.tinfo[6 * (size_t)t] = rs[a].size() == 2 ? rs[a][1].b - a * TILE : TILE;
+      out.tinfo[6 * (size_t)t + 1] = cs[b].size() == 2 ? cs[b][1].b - b * TILE : TILE;
+      for (const Seg& r : rs[a])
+        for (const Seg& c : cs[b]) {
+          common.clear();
+          std::set_intersection(r.q.begin(), r.q.end(), c.q.begin(), c.q.end(), std::back_inserter(common));
+          auto it = cache.find(common);
+          if (it == cache.end()) {
+            Merged m;
+            sel.clear();
+            for (int x : common) sel.insert(sel.end(), runs[x].begin(), runs[x].end());
+            std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
+            for (size_t j = 0; j < sel.size();) {
+              Run cur = sel[j++];
+              while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
+              m.iv.push_back(cur.b);
+              m.iv.push_back(cur.e);
+              m.klen += cur.e - cur.b;
+            }
+            it = cache.emplace(common, std::move(m)).first;
+          }
+          out.iv.insert(out.iv.end(), it->second.iv.begin(), it->second.iv.end());
+          out.off.push_back((int)(out.iv.size() / 2));
+          out.etile.push_back(t);
+          out.erng.insert(out.erng.end(), {r.b - a * TILE, r.e - a * TILE, c.b - b * TILE, c.e - b * TILE});
+          out.epart.push_back(0);
+          out.tile_macs += (double)(r.e - r.b) * (c.e - c.b) * it->second.klen;
         }
-        it = cache.emplace(common, std::move(m)).first;
-      }
-      const int cols = std::min(N, (b + 1) * TILE) - b * TILE;
-      out.iv.insert(out.iv.end(), it->second.iv.begin(), it->second.iv.end());
-      out.off[(size_t)a * tn + b + 1] = (int)(out.iv.size() / 2);
-      out.tile_macs += (double)rows * cols * it->second.klen;
     }
-    for (int c : rs[a]) mark[c] = -1;
-  }
   // nonzero multiply-adds: per charge, rows x columns x K indices of it
   std::vector<double> nr(R, 0.0), nc(R, 0.0), nk(R, 0.0);
   for (int x : rq) nr[x - cmin] += 1;
@@ -113,19 +137,19 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
   out.K = K;
 }
 
-// A tile's K work is cut into parts when the nonempty tiles give fewer
-// than SPLIT_MIN_TILES workgroups: parts of about equal length (a multiple
-// of the K step, at least SPLIT_MIN_K) so that about SPLIT_TARGET parts are
-// nonempty, at most SPLIT_MAX per tile.  Long-K products with charges (the
-// second product of the effective Hamiltonian: 2 x 16 x 16 tiles at a bond
-// of 1024, a third of them nonempty, with 2000-11000 of K each) would
-// otherwise leave most compute units idle.
+// A sub-block's K work is cut into parts when the nonempty sub-blocks give
+// fewer than SPLIT_MIN_TILES workgroups: parts of about equal length (a
+// multiple of the K step, at least SPLIT_MIN_K) so that about SPLIT_TARGET
+// parts are nonempty, at most SPLIT_MAX per sub-block.  Long-K products
+// with charges (the second product of the effective Hamiltonian: 2 x 16 x 16
+// tiles at a bond of 1024, a third of them nonempty, with 2000-11000 of K
+// each) would otherwise leave most compute units idle.  Only nonempty parts
+// stay; tinfo records how many each sub-block has, for the reduction.
 void split_kmap(KMapHost& h) {
   constexpr int SPLIT_MIN_TILES = 768, SPLIT_TARGET = 1024, SPLIT_MAX = 16, SPLIT_MIN_K = 256;
   h.splits = 1;
-  h.nsplit.clear();
   const int E = (int)h.off.size() - 1;
-  if (E <= 0 || h.batch <= 0 || E % h.batch) return;
+  if (E <= 0) return;
   std::vector<long long> klen(E, 0);
   long long sum = 0, kmax = 0;
   int active = 0;
@@ -144,30 +168,39 @@ void split_kmap(KMapHost& h) {
     chunk = up((kmax + S - 1) / S);
   }
   if (S <= 1) return;
-  const int tiles = E / h.batch;
-  std::vector<int> off(1, 0), iv;
+  std::vector<int> off(1, 0), iv, etile, erng, epart;
   iv.reserve(h.iv.size() + (size_t)2 * E);
-  h.nsplit.assign(E, 0);
-  for (int b = 0; b < h.batch; ++b)
-    for (int sp = 0; sp < S; ++sp)
-      for (int t = 0; t < tiles; ++t) {
-        const int e = b * tiles + t;
-        const long long lo = sp * chunk, hi = std::min(klen[e], lo + chunk);
-        long long pos = 0;   // K entries of the tile before interval v
-        for (int v = h.off[e]; v < h.off[e + 1] && pos < hi; ++v) {
-          const int x = h.iv[2 * v], y = h.iv[2 * v + 1];
-          const long long a = std::max(lo, pos), z = std::min(hi, pos + (y - x));
-          if (a < z) {
-            iv.push_back(x + (int)(a - pos));
-            iv.push_back(x + (int)(z - pos));
-          }
-          pos += y - x;
+  for (int e = 0; e < E; ++e) {
+    const int t = h.etile[e];
+    const int* rg = &h.erng[4 * (size_t)e];
+    const int sub = (rg[0] >= h.tinfo[6 * (size_t)t] ? 2 : 0) + (rg[2] >= h.tinfo[6 * (size_t)t + 1] ? 1 : 0);
+    int parts = 0;
+    for (int sp = 0; sp < S; ++sp) {
+      const long long lo = sp * chunk, hi = std::min(klen[e], lo + chunk);
+      if (lo >= hi) break;
+      long long pos = 0;   // K entries of the sub-block before interval v
+      for (int v = h.off[e]; v < h.off[e + 1] && pos < hi; ++v) {
+        const int x = h.iv[2 * v], y = h.iv[2 * v + 1];
+        const long long a = std::max(lo, pos), z = std::min(hi, pos + (y - x));
+        if (a < z) {
+          iv.push_back(x + (int)(a - pos));
+          iv.push_back(x + (int)(z - pos));
         }
-        off.push_back((int)(iv.size() / 2));
-        if (lo < klen[e]) h.nsplit[e] = sp + 1;
+        pos += y - x;
       }
+      off.push_back((int)(iv.size() / 2));
+      etile.push_back(t);
+      erng.insert(erng.end(), rg, rg + 4);
+      epart.push_back(sp);
+      ++parts;
+    }
+    h.tinfo[6 * (size_t)t + 2 + sub] = parts;
+  }
   h.off.swap(off);
   h.iv.swap(iv);
+  h.etile.swap(etile);
+  h.erng.swap(erng);
+  h.epart.swap(epart);
   h.splits = (int)S;
 }
 
@@ -181,29 +214,26 @@ DevKMap::~DevKMap() {
 }
 
 void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
-  // work items (tile, part, first interval, end), longest K first
-  const int E = (int)h.off.size() - 1, S = std::max(h.splits, 1);
-  const int tiles = h.batch > 0 ? E / (h.batch * S) : 0;
+  // work items {tile, part, first interval, end}, {r0, r1, c0, c1}, longest K first
+  const int E = (int)h.off.size() - 1;
   std::vector<int> items;
   std::vector<std::pair<long long, int>> order;
   order.reserve(E);
   for (int e = 0; e < E; ++e) {
     long long kl = 0;
     for (int v = h.off[e]; v < h.off[e + 1]; ++v) kl += h.iv[2 * v + 1] - h.iv[2 * v];
-    if (S > 1 && kl == 0) continue;   // empty parts: the reduction skips them
+    if (h.splits > 1 && kl == 0) continue;   // the reduction covers empty sub-blocks
     order.push_back({-kl, e});
   }
   std::stable_sort(order.begin(), order.end(),
                    [](const std::pair<long long, int>& x, const std::pair<long long, int>& y) { return x.first < y.first; });
-  items.reserve(4 * order.size());
+  items.reserve(8 * order.size());
   for (const auto& o : order) {
-    const int e = o.second, t = e % tiles, bs = e / tiles, b = bs / S, s = bs % S;
-    items.push_back(b * tiles + t);
-    items.push_back(s);
-    items.push_back(h.off[e]);
-    items.push_back(h.off[e + 1]);
+    const int e = o.second;
+    items.insert(items.end(), {h.etile[e], h.epart[e], h.off[e], h.off[e + 1]});
+    items.insert(items.end(), h.erng.begin() + 4 * (size_t)e, h.erng.begin() + 4 * (size_t)e + 4);
   }
-  const size_t ni = items.size(), nv = h.iv.size(), ns = h.nsplit.size(), nt = ni + nv + ns;
+  const size_t ni = items.size(), nv = h.iv.size(), ns = h.splits > 1 ? h.tinfo.size() : 0, nt = ni + nv + ns;
   // one upload from pinned memory, ordered on the stream after the products
   // that still read the previous map; the host waits only for the previous
   // upload out of the staging buffer (long done in the common case)
@@ -219,7 +249,7 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
   }
   std::copy(items.begin(), items.end(), stage);
   std::copy(h.iv.begin(), h.iv.end(), stage + ni);
-  std::copy(h.nsplit.begin(), h.nsplit.end(), stage + ni + nv);
+  if (ns) std::copy(h.tinfo.begin(), h.tinfo.end(), stage + ni + nv);
   buf.ensure(sizeof(int) * (nt + 4));
   int* base = buf.as<int>();   // items first (16-byte aligned)
   if (nt) HIP_CHECK(hipMemcpyAsync(base, stage, sizeof(int) * nt, hipMemcpyHostToDevice, ctx->stream));
@@ -231,9 +261,9 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
     map.part = part.ensure(map.part_bytes);
   }
   map.items = reinterpret_cast<const int4*>(base);
-  map.n_items = (int)(ni / 4);
+  map.n_items = (int)(ni / 8);
   map.iv = base + ni;
-  map.nsplit = h.splits > 1 ? base + ni + nv : nullptr;
+  map.tinfo = h.splits > 1 ? base + ni + nv : nullptr;
   map.M = h.M;
   map.N = h.N;
   map.K = h.K;
@@ -292,15 +322,21 @@ namespace {
 void join_batches(const std::vector<KMapHost>& parts, KMapHost& out) {
   out = KMapHost();
   out.off.assign(1, 0);
-  for (const auto& p : parts) {
+  for (size_t x = 0; x < parts.size(); ++x) {
+    const KMapHost& p = parts[x];
     const int base = (int)(out.iv.size() / 2);
     for (size_t t = 1; t < p.off.size(); ++t) out.off.push_back(base + p.off[t]);
     out.iv.insert(out.iv.end(), p.iv.begin(), p.iv.end());
+    for (int t : p.etile) out.etile.push_back((int)x * p.tiles + t);
+    out.erng.insert(out.erng.end(), p.erng.begin(), p.erng.end());
+    out.epart.insert(out.epart.end(), p.epart.begin(), p.epart.end());
+    out.tinfo.insert(out.tinfo.end(), p.tinfo.begin(), p.tinfo.end());
     out.exact_macs += p.exact_macs;
     out.tile_macs += p.tile_macs;
     out.M = p.M;
     out.N = p.N;
     out.K = p.K;
+    out.tiles = p.tiles;
   }
   out.batch = (int)parts.size();
 }

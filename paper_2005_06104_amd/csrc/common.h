@@ -162,20 +162,22 @@ void gemm(hipStream_t s, int opa, int opb, int M, int N, int K, zc alpha, const 
           long long ldc, long long sc, int batch, void* ws = nullptr, size_t ws_bytes = 0);
 
 // Block-sparse map of an M x N x K product whose operands carry U(1)
-// charges, as a list of work items, one workgroup each: item
-// {tile, part, a, b} computes output tile `tile` (batch entry outer, then
-// 64 x 64 tiles in row-major order) over the K intervals iv[a .. b) ((begin,
-// end) pairs).  The items are sorted by decreasing K length, so the longest
-// are dispatched first and consecutive ones go to different XCDs; device
+// charges, as a list of work items, one workgroup each: item (two int4)
+// {tile, part, a, b}, {r0, r1, c0, c1} computes rows r0 .. r1 and columns
+// c0 .. c1 of output tile `tile` (batch entry outer, then 64 x 64 tiles in
+// row-major order) over the K intervals iv[a .. b) ((begin, end) pairs).
+// The items are sorted by decreasing K length, so the longest are
+// dispatched first and consecutive ones go to different XCDs; device
 // arrays.  While set (set_kmap / KMapScope) on the calling host thread, the
 // products of that shape and batch count it issues walk only those
 // intervals; any other shape is an error.
-// Unsplit maps (splits = 1) hold every tile (a tile without intervals writes
-// alpha * 0 + beta * C).  Split maps (splits > 1) hold the nonempty parts
-// only: part s of a tile writes its partial product into `part` (splits x
-// batch x M x N complex of the product's type, at most part_bytes), the
-// first nsplit[tile] parts of every tile are nonempty, and one reduction
-// sums them.
+// Unsplit maps (splits = 1) cover every tile (a sub-block without intervals
+// writes alpha * 0 + beta * C).  Split maps (splits > 1) hold the nonempty
+// parts only: part s of a sub-block writes its partial product into `part`
+// (splits x batch x M x N complex of the product's type, at most
+// part_bytes); tinfo (6 per tile: the row and column where the second
+// segment starts, the nonempty parts of each of the four sub-blocks) tells
+// the reduction which parts to sum.
 struct KMap {
   const int4* items = nullptr;
   int n_items = 0;
@@ -183,7 +185,7 @@ struct KMap {
   int M = 0, N = 0, K = 0;
   int batch = 1;               // batched products: one map per batch entry, batch outer
   int splits = 1;
-  const int* nsplit = nullptr;
+  const int* tinfo = nullptr;
   void* part = nullptr;
   size_t part_bytes = 0;
 };

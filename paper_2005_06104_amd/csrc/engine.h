@@ -104,11 +104,16 @@ struct MatvecTimer {
 // (blocks.cpp).  rq[m]: the charge row m of op(A) needs on the summed index,
 // kq[k]: the charge of summed index k, cq[n]: the charge column n of op(B)
 // needs on it.
+// Entries are sub-blocks of the 64 x 64 output tiles: tile etile[e] (batch
+// entry outer, then row-major tiles), rows erng[4e] .. erng[4e+1] and
+// columns erng[4e+2] .. erng[4e+3] inside the tile, split part epart[e], K
+// intervals iv[off[e] .. off[e+1]).  tinfo (6 per tile): the row and column
+// where the tile's second segment starts (64 if none), then the nonempty
+// parts of each of its up to four sub-blocks (split maps).
 struct KMapHost {
-  std::vector<int> off, iv;
-  std::vector<int> nsplit;                    // with splits > 1: nonempty parts per tile
+  std::vector<int> off, iv, etile, erng, epart, tinfo;
   double exact_macs = 0.0, tile_macs = 0.0;   // nonzero multiply-adds; those the tiles perform
-  int M = 0, N = 0, K = 0, batch = 1, splits = 1;
+  int M = 0, N = 0, K = 0, batch = 1, splits = 1, tiles = 0;
 };
 void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out);
 // Split the K intervals of a map whose nonempty tiles are too few to fill

@@ -60,9 +60,11 @@ struct KIter {
   __device__ int2 at(int v) const { return iv ? iv[v] : one; }
 };
 
-// the output tile, batch entry, split part and K range of this workgroup
+// the output tile, batch entry, split part and K range of this workgroup,
+// and the rows r0 .. r1, columns c0 .. c1 of the tile it computes
 struct TileJob {
   int m0, n0, split;
+  int r0, r1, c0, c1;
   long long bz;
   KIter kr;
 };
@@ -75,13 +77,17 @@ __device__ inline TileJob tile_job(int M, int N, int K, int S, int Kc, const int
   if (kit) {
     // items in decreasing K length: dispatch order (and the XCD round robin
     // of consecutive workgroups) spreads the long ones
-    const int4 it = kit[lin];
+    const int4 it = kit[2 * (size_t)lin], rg = kit[2 * (size_t)lin + 1];
     const int gxt = (N + BN - 1) / BN, tpb = gxt * ((M + BM - 1) / BM);
     j.bz = it.x / tpb;
     const int trem = it.x % tpb;
     j.m0 = (trem / gxt) * BM;
     j.n0 = (trem % gxt) * BN;
     j.split = it.y;
+    j.r0 = rg.x;
+    j.r1 = rg.y;
+    j.c0 = rg.z;
+    j.c1 = rg.w;
     j.kr.iv = kiv + it.z;
     j.kr.n = it.w - it.z;
     j.kr.one = make_int2(0, 0);
@@ -98,6 +104,10 @@ __device__ inline TileJob tile_job(int M, int N, int K, int S, int Kc, const int
   j.n0 = (int)(trem % gx) * BN;
   j.bz = tz / S;
   j.split = tz % S;
+  j.r0 = 0;
+  j.r1 = BM;
+  j.c0 = 0;
+  j.c1 = BN;
   const int kb = j.split * Kc, ke = min(K, kb + Kc);
   j.kr.iv = nullptr;
   j.kr.n = kb < ke ? 1 : 0;
@@ -142,7 +152,9 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       const int gm = m0 + m, gk = k0 + k;
       c2 v;
       v.x = T(0); v.y = T(0);
-      if (gm < M && gk < kend) v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
+      // rows outside the sub-block are not needed (their products are not stored)
+      if (gm < M && gk < kend && m >= job.r0 && m < job.r1)
+        v = TA ? Ab[(long long)gk * lda + gm] : Ab[(long long)gm * lda + gk];
       if (CA) v.y = -v.y;
       ra[it] = v;
     }
@@ -154,7 +166,8 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       const int gn = n0 + n, gk = k0 + k;
       c2 v;
       v.x = T(0); v.y = T(0);
-      if (gn < N && gk < kend) v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
+      if (gn < N && gk < kend && n >= job.c0 && n < job.c1)
+        v = TB ? Bb[(long long)gn * ldb + gk] : Bb[(long long)gk * ldb + gn];
       if (CB) v.y = -v.y;
       rb[it] = v;
     }
@@ -188,6 +201,19 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
     }
 
   const int lr = lane & 15, lk = lane >> 4;
+  // the wave's 16 x 16 pieces that meet the sub-block (the others skip their
+  // products and are not stored)
+  bool act_i[SI], act_j[SJ];
+#pragma unroll
+  for (int i = 0; i < SI; ++i) {
+    const int r = wm * (BM / WM) + i * 16;
+    act_i[i] = r < job.r1 && r + 16 > job.r0;
+  }
+#pragma unroll
+  for (int j = 0; j < SJ; ++j) {
+    const int c = wn * (BN / WN) + j * 16;
+    act_j[j] = c < job.c1 && c + 16 > job.c0;
+  }
   // double-buffered LDS: compute on `cur` while the next tile's global loads
   // are in flight, then store them into the other buffer; one barrier per
   // tile.  The K steps walk the tile's intervals in order.
@@ -233,6 +259,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       for (int i = 0; i < SI; ++i)
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
+          if (!(act_i[i] && act_j[j])) continue;
           cr[i][j] = mfma(a_r[i], b_r[j], cr[i][j]);
           cr[i][j] = mfma(a_n[i], b_i[j], cr[i][j]);
           ci[i][j] = mfma(a_r[i], b_i[j], ci[i][j]);
@@ -258,9 +285,10 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
         // output row inside the 16x16 tile: the f32 MFMA puts rows 4*(lane/16)+r
         // in a lane, the f64 MFMA rows (lane/16)+4*r (columns are lane%16 for both)
         const int tr = sizeof(T) == 8 ? (lk + 4 * r) : (lk * 4 + r);
-        const int gm = m0 + wm * (BM / WM) + i * 16 + tr;
-        const int gn = n0 + wn * (BN / WN) + j * 16 + lr;
-        if (gm < M && gn < N) {
+        const int lm = wm * (BM / WM) + i * 16 + tr, ln = wn * (BN / WN) + j * 16 + lr;
+        const int gm = m0 + lm;
+        const int gn = n0 + ln;
+        if (gm < M && gn < N && lm >= job.r0 && lm < job.r1 && ln >= job.c0 && ln < job.c1) {
           const T xr = cr[i][j][r], xi = ci[i][j][r];
           c2 o;
           o.x = ar * xr - ai * xi;
@@ -308,9 +336,10 @@ __device__ inline uint4 bf16_neg(uint4 v) {
 // quads of four consecutive k per thread.  KC: k is the contiguous index in
 // memory.  Planes (real, imaginary; and the residual terms with SPLIT) of
 // ROWS x BKP2 bf16 each, k contiguous.
+// (rows lo .. hi of the tile only: the others are not needed)
 template <bool KC, bool CONJ, int ROWS = 64>
 __device__ inline void bf_load(const float2* __restrict__ X, long long ld, int r0, int R, int k0, int ke, int tid,
-                               float2 (&v)[ROWS / 32][4]) {
+                               float2 (&v)[ROWS / 32][4], int lo = 0, int hi = ROWS) {
 #pragma unroll
   for (int it = 0; it < ROWS / 32; ++it) {
     const int q = tid + it * NT;
@@ -323,7 +352,7 @@ __device__ inline void bf_load(const float2* __restrict__ X, long long ld, int r
       float2 e;
       e.x = 0.f;
       e.y = 0.f;
-      if (gr < R && gk < ke) e = KC ? X[(long long)gr * ld + gk] : X[(long long)gk * ld + gr];
+      if (gr < R && gk < ke && row >= lo && row < hi) e = KC ? X[(long long)gr * ld + gk] : X[(long long)gk * ld + gr];
       if (CONJ) e.y = -e.y;
       v[it][j] = e;
     }
@@ -384,8 +413,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
   // are n (k contiguous when B is transposed)
   float2 va[2][4], vb[2][4];
   auto load = [&](int k0, int kend) {
-    bf_load<!TA, CA>(Ab, lda, m0, M, k0, kend, tid, va);
-    bf_load<TB, CB>(Bb, ldb, n0, N, k0, kend, tid, vb);
+    bf_load<!TA, CA>(Ab, lda, m0, M, k0, kend, tid, va, job.r0, job.r1);
+    bf_load<TB, CB>(Bb, ldb, n0, N, k0, kend, tid, vb, job.c0, job.c1);
   };
   auto store = [&](int buf) {
     bf_store<!TA, SPLIT>(As[buf], tid, va);
@@ -402,6 +431,13 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     }
 
   const int lr = lane & 15, lk = lane >> 4;
+  bool act_i[2], act_j[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int r = wm * 32 + i * 16, c = wn * 32 + i * 16;
+    act_i[i] = r < job.r1 && r + 16 > job.r0;
+    act_j[i] = c < job.c1 && c + 16 > job.c0;
+  }
   const KIter kr_ = job.kr;
   int iv = 0, k0 = 0, kend = 0;
   if (kr_.n > 0) {
@@ -454,6 +490,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
+        if (!(act_i[i] && act_j[j])) continue;
         if (SPLIT) {
           cr[i][j] = mfma_bf16(a_hr[i], b_lr[j], cr[i][j]);
           cr[i][j] = mfma_bf16(a_lr[i], b_hr[j], cr[i][j]);
@@ -485,9 +522,10 @@ __global__ __launch_bounds__(NT) void gemm_bf16_kernel(int M, int N, int K, floa
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * 32 + i * 16 + lk * 4 + r;
-        const int gn = n0 + wn * 32 + j * 16 + lr;
-        if (gm < M && gn < N) {
+        const int lm = wm * 32 + i * 16 + lk * 4 + r, ln = wn * 32 + j * 16 + lr;
+        const int gm = m0 + lm;
+        const int gn = n0 + ln;
+        if (gm < M && gn < N && lm >= job.r0 && lm < job.r1 && ln >= job.c0 && ln < job.c1) {
           const float xr = cr[i][j][r], xi = ci[i][j][r];
           float2 o;
           o.x = ar * xr - ai * xi;
@@ -533,7 +571,7 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ P, int S, long long M
 // nonempty parts of each tile + beta * C[b]; the parts are P[s][b][m][n].
 template <typename T>
 __global__ void splitk_reduce_map_kernel(const T* __restrict__ P, int batch, long long M, long long N, int gx,
-                                         const int* __restrict__ nsplit, T ar, T ai, T br, T bi, T* __restrict__ C,
+                                         const int* __restrict__ tinfo, T ar, T ai, T br, T bi, T* __restrict__ C,
                                          long long ldc, long long sc) {
   using c2 = typename VT<T>::c2;
   const long long MN = M * N;
@@ -541,7 +579,8 @@ __global__ void splitk_reduce_map_kernel(const T* __restrict__ P, int batch, lon
   if (idx >= MN * batch) return;
   const long long b = idx / MN, r = idx % MN, m = r / N, n = r % N;
   const long long tiles = ((M + BM - 1) / BM) * (long long)gx;
-  const int ns = nsplit[b * tiles + (m / BM) * gx + n / BN];
+  const int* ti = tinfo + 6 * (b * tiles + (m / BM) * gx + n / BN);
+  const int ns = ti[2 + ((m % BM) >= ti[0] ? 2 : 0) + ((n % BN) >= ti[1] ? 1 : 0)];
   const c2* Pc = reinterpret_cast<const c2*>(P);
   T xr = T(0), xi = T(0);
   for (int s = 0; s < ns; ++s) {
@@ -618,11 +657,11 @@ void launch_gemm_mode(hipStream_t s, int M, int N, int K, zc alpha, const void* 
                                                    T(0), T(0), P, (long long)N, MN, km->splits, std::max(K, 1),
                                                    MN * batch, km->items, reinterpret_cast<const int2*>(km->iv));
       hipLaunchKernelGGL(splitk_reduce_map_kernel<T>, dim3((unsigned)((MN * batch + 255) / 256)), dim3(256), 0, s, P,
-                         batch, (long long)M, (long long)N, gx, km->nsplit, T(alpha.real()), T(alpha.imag()),
+                         batch, (long long)M, (long long)N, gx, km->tinfo, T(alpha.real()), T(alpha.imag()),
                          T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
       return;
     }
-    if (km->n_items != batch * gx * ((M + BM - 1) / BM)) TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without every tile");
+    if (km->n_items < batch * gx * ((M + BM - 1) / BM)) TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without every tile");
     launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(dim3(km->n_items), s, M, N, K, T(alpha.real()), T(alpha.imag()), a,
                                                lda, sa, b, ldb, sb, T(beta.real()), T(beta.imag()),
                                                static_cast<T*>(C), ldc, sc, 1, std::max(K, 1), 0LL, km->items,
