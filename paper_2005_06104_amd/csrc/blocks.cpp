@@ -12,6 +12,8 @@
 // closer than a K step are joined (the skipped entries between them are
 // exact zeros, so including them changes nothing).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -61,6 +63,7 @@ std::vector<std::vector<Seg>> tile_segments(const std::vector<int>& q, int n, in
 }  // namespace
 
 void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out) {
+  Range r_("maps.build");
   const int M = (int)rq.size(), K = (int)kq.size(), N = (int)cq.size();
   int cmin = 1 << 30, cmax = -(1 << 30);
   for (const auto* v : {&rq, &kq, &cq})
@@ -146,6 +149,7 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
 // each) would otherwise leave most compute units idle.  Only nonempty parts
 // stay; tinfo records how many each sub-block has, for the reduction.
 void split_kmap(KMapHost& h) {
+  Range r_("maps.split");
   constexpr int SPLIT_MIN_TILES = 768, SPLIT_TARGET = 1024, SPLIT_MAX = 16, SPLIT_MIN_K = 256;
   h.splits = 1;
   const int E = (int)h.off.size() - 1;
@@ -204,19 +208,105 @@ void split_kmap(KMapHost& h) {
   h.splits = (int)S;
 }
 
-DevKMap::~DevKMap() {
-  // the last upload may still be in flight out of the staging buffer
-  if (uploaded) {
-    (void)hipEventSynchronize(uploaded);
-    (void)hipEventDestroy(uploaded);
+// ------------------------------------------------------------ map cache
+namespace {
+
+unsigned long long key_hash(const std::vector<int>& k) {
+  unsigned long long h = 1469598103934665603ull;   // FNV-1a over the 32-bit words
+  for (int x : k) {
+    h ^= (unsigned)x;
+    h *= 1099511628211ull;
   }
-  if (stage) (void)hipHostFree(stage);
+  return h;
 }
 
-void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
+}  // namespace
+
+std::vector<int> map_key(int kind, std::initializer_list<const std::vector<int>*> qs) {
+  size_t n = 1;
+  for (const auto* q : qs) n += 1 + q->size();
+  std::vector<int> k;
+  k.reserve(n);
+  k.push_back(kind);
+  for (const auto* q : qs) {
+    k.push_back((int)q->size());
+    k.insert(k.end(), q->begin(), q->end());
+  }
+  return k;
+}
+
+MapCache& map_cache(tdvp_ctx_s* ctx) {
+  if (!ctx->maps) ctx->maps = new MapCache(ctx);
+  return *ctx->maps;
+}
+
+void tdvp_ctx_s::destroy_maps() {
+  delete maps;
+  maps = nullptr;
+}
+
+MapCache::~MapCache() {
+  // uploads may still be in flight out of the staging buffers
+  for (int i = 0; i < NSTAGE; ++i) {
+    if (ev[i]) {
+      (void)hipEventSynchronize(ev[i]);
+      (void)hipEventDestroy(ev[i]);
+    }
+    if (stage[i]) (void)hipHostFree(stage[i]);
+  }
+  if (const char* v = std::getenv("TDVP_MAP_STATS"); v && *v == '1')
+    std::fprintf(stderr, "map cache: %zu hits, %zu misses, %zu evicted, %zu entries, %.1f MiB\n", hits, misses,
+                 evicted, [&] {
+                   size_t n = 0;
+                   for (const auto& b : tab) n += b.second.size();
+                   return n;
+                 }(),
+                 bytes / 1048576.0);
+}
+
+MapCache::Entry* MapCache::find(const std::vector<int>& key, unsigned long long h) {
+  auto it = tab.find(h);
+  if (it == tab.end()) return nullptr;
+  for (auto& e : it->second)
+    if (e->key == key) return e.get();
+  return nullptr;
+}
+
+const MapCache::Entry& MapCache::get(std::vector<int>&& key, const std::function<void(KMapHost&)>& build) {
+  const unsigned long long h = key_hash(key);
+  if (Entry* e = find(key, h)) {
+    ++hits;
+    e->last = ++clock;
+    return *e;
+  }
+  ++misses;
+  KMapHost m;
+  build(m);
+  return insert(std::move(key), h, m);
+}
+
+std::pair<const MapCache::Entry*, const MapCache::Entry*> MapCache::get2(
+    std::vector<int>&& k1, std::vector<int>&& k2, const std::function<void(KMapHost&, KMapHost&)>& build) {
+  const unsigned long long h1 = key_hash(k1), h2 = key_hash(k2);
+  Entry* e1 = find(k1, h1);
+  Entry* e2 = find(k2, h2);
+  if (e1 && e2) {
+    hits += 2;
+    e1->last = ++clock;
+    e2->last = ++clock;
+    return {e1, e2};
+  }
+  KMapHost m1, m2;
+  build(m1, m2);
+  if (e1) { ++hits; e1->last = ++clock; } else { ++misses; e1 = &insert(std::move(k1), h1, m1); }
+  if (e2) { ++hits; e2->last = ++clock; } else { ++misses; e2 = &insert(std::move(k2), h2, m2); }
+  return {e1, e2};
+}
+
+MapCache::Entry& MapCache::insert(std::vector<int>&& key, unsigned long long hk, const KMapHost& h) {
+  Range r_("maps.upload");
   // work items {tile, part, first interval, end}, {r0, r1, c0, c1}, longest K first
   const int E = (int)h.off.size() - 1;
-  std::vector<int> items;
   std::vector<std::pair<long long, int>> order;
   order.reserve(E);
   for (int e = 0; e < E; ++e) {
@@ -227,39 +317,43 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
   }
   std::stable_sort(order.begin(), order.end(),
                    [](const std::pair<long long, int>& x, const std::pair<long long, int>& y) { return x.first < y.first; });
-  items.reserve(8 * order.size());
+  const size_t ni = 8 * order.size(), nv = h.iv.size(), ns = h.splits > 1 ? h.tinfo.size() : 0, nt = ni + nv + ns;
+  // one upload from pinned memory, ordered on the stream; the host waits
+  // only for the copy that last used this staging buffer (long done in the
+  // common case)
+  const int si = spos;
+  spos = (spos + 1) % NSTAGE;
+  if (ev[si]) HIP_CHECK(hipEventSynchronize(ev[si]));
+  else HIP_CHECK(hipEventCreateWithFlags(&ev[si], hipEventDisableTiming));
+  if (stage_cap[si] < nt) {
+    if (stage[si]) HIP_CHECK(hipHostFree(stage[si]));
+    stage[si] = nullptr;
+    stage_cap[si] = 0;
+    const size_t cap = std::max<size_t>(nt + nt / 2, 4096);
+    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&stage[si]), sizeof(int) * cap, hipHostMallocDefault));
+    stage_cap[si] = cap;
+  }
+  int* st = stage[si];
   for (const auto& o : order) {
     const int e = o.second;
-    items.insert(items.end(), {h.etile[e], h.epart[e], h.off[e], h.off[e + 1]});
-    items.insert(items.end(), h.erng.begin() + 4 * (size_t)e, h.erng.begin() + 4 * (size_t)e + 4);
+    st[0] = h.etile[e];
+    st[1] = h.epart[e];
+    st[2] = h.off[e];
+    st[3] = h.off[e + 1];
+    std::copy(h.erng.begin() + 4 * (size_t)e, h.erng.begin() + 4 * (size_t)e + 4, st + 4);
+    st += 8;
   }
-  const size_t ni = items.size(), nv = h.iv.size(), ns = h.splits > 1 ? h.tinfo.size() : 0, nt = ni + nv + ns;
-  // one upload from pinned memory, ordered on the stream after the products
-  // that still read the previous map; the host waits only for the previous
-  // upload out of the staging buffer (long done in the common case)
-  if (uploaded) HIP_CHECK(hipEventSynchronize(uploaded));
-  else HIP_CHECK(hipEventCreateWithFlags(&uploaded, hipEventDisableTiming));
-  if (stage_cap < nt) {
-    if (stage) HIP_CHECK(hipHostFree(stage));
-    stage = nullptr;
-    stage_cap = 0;
-    HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&stage), sizeof(int) * std::max<size_t>(nt, 1024),
-                            hipHostMallocDefault));
-    stage_cap = std::max<size_t>(nt, 1024);
-  }
-  std::copy(items.begin(), items.end(), stage);
-  std::copy(h.iv.begin(), h.iv.end(), stage + ni);
-  if (ns) std::copy(h.tinfo.begin(), h.tinfo.end(), stage + ni + nv);
-  buf.ensure(sizeof(int) * (nt + 4));
-  int* base = buf.as<int>();   // items first (16-byte aligned)
-  if (nt) HIP_CHECK(hipMemcpyAsync(base, stage, sizeof(int) * nt, hipMemcpyHostToDevice, ctx->stream));
-  HIP_CHECK(hipEventRecord(uploaded, ctx->stream));
-  map.part = nullptr;
-  map.part_bytes = 0;
-  if (h.splits > 1) {   // partial products, sized for complex128
-    map.part_bytes = (size_t)h.splits * h.batch * h.M * h.N * 16;
-    map.part = part.ensure(map.part_bytes);
-  }
+  std::copy(h.iv.begin(), h.iv.end(), stage[si] + ni);
+  if (ns) std::copy(h.tinfo.begin(), h.tinfo.end(), stage[si] + ni + nv);
+  evict();
+  auto ent = std::make_unique<Entry>(ctx);
+  Entry& en = *ent;
+  en.key = std::move(key);
+  en.buf.ensure(sizeof(int) * (nt + 4));
+  int* base = en.buf.as<int>();   // items first (16-byte aligned)
+  if (nt) HIP_CHECK(hipMemcpyAsync(base, stage[si], sizeof(int) * nt, hipMemcpyHostToDevice, ctx->stream));
+  HIP_CHECK(hipEventRecord(ev[si], ctx->stream));
+  kern::KMap& map = en.map;
   map.items = reinterpret_cast<const int4*>(base);
   map.n_items = (int)(ni / 8);
   map.iv = base + ni;
@@ -269,32 +363,76 @@ void DevKMap::set(tdvp_ctx_s* ctx, const KMapHost& h) {
   map.K = h.K;
   map.batch = h.batch;
   map.splits = h.splits;
-  exact_flops = 8.0 * h.exact_macs;
-  tile_flops = 8.0 * h.tile_macs;
+  map.part = nullptr;
+  map.part_bytes = 0;
+  en.part_bytes = h.splits > 1 ? (size_t)h.splits * h.batch * h.M * h.N * 16 : 0;
+  en.exact_flops = 8.0 * h.exact_macs;
+  en.tile_flops = 8.0 * h.tile_macs;
+  en.last = ++clock;
+  bytes += en.buf.cap;
+  tab[hk].push_back(std::move(ent));
+  return en;
 }
 
-DevKMap& MapRing::next() {
-  constexpr size_t RING = 8;
-  if (ring.size() < RING) {
-    ring.emplace_back(new DevKMap(ctx));
-    return *ring.back();
+void MapCache::evict() {
+  if (bytes <= MAX_BYTES) return;
+  // least recently used first, down to three quarters of the limit
+  std::vector<std::pair<unsigned long long, Entry*>> old;
+  for (auto& b : tab)
+    for (auto& e : b.second)
+      if (e->last + PROTECT < clock) old.push_back({e->last, e.get()});
+  std::sort(old.begin(), old.end(),
+            [](const std::pair<unsigned long long, Entry*>& x, const std::pair<unsigned long long, Entry*>& y) {
+              return x.first < y.first;
+            });
+  size_t drop = 0;
+  std::vector<Entry*> gone;
+  for (const auto& o : old) {
+    if (bytes - drop <= MAX_BYTES / 4 * 3) break;
+    drop += o.second->buf.cap;
+    gone.push_back(o.second);
   }
-  pos = (pos + 1) % RING;
-  return *ring[pos];
+  if (gone.empty()) return;
+  std::sort(gone.begin(), gone.end());
+  for (auto it = tab.begin(); it != tab.end();) {
+    auto& v = it->second;
+    v.erase(std::remove_if(v.begin(), v.end(),
+                           [&](const std::unique_ptr<Entry>& e) {
+                             return std::binary_search(gone.begin(), gone.end(), e.get());
+                           }),
+            v.end());
+    it = v.empty() ? tab.erase(it) : std::next(it);
+  }
+  bytes -= drop;
+  evicted += gone.size();
 }
 
-void qgemm(tdvp_ctx_s* ctx, MapRing* ring, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
+kern::KMap MapCache::use(const Entry& e) {
+  kern::KMap m = e.map;
+  if (e.part_bytes) {
+    if (part.cap < e.part_bytes) {
+      if (part.p) retired.push_back(std::move(part));
+      part = DBuf(ctx);
+      part.ensure(e.part_bytes);
+    }
+    m.part = part.p;
+    m.part_bytes = part.cap;
+  }
+  return m;
+}
+
+void qgemm(tdvp_ctx_s* ctx, MapCache* maps, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
            long long lda, const void* B, long long ldb, zc beta, void* C, long long ldc, const std::vector<int>* qm,
            const std::vector<int>* qk, const std::vector<int>* qn) {
   hipStream_t s = ctx->stream;
-  if (ring && qm && qk && qn && (int)qm->size() == M && (int)qk->size() == K && (int)qn->size() == N && M > 0 &&
+  if (maps && qm && qk && qn && (int)qm->size() == M && (int)qk->size() == K && (int)qn->size() == N && M > 0 &&
       N > 0 && (double)M * N * K >= double(1 << 21)) {
-    KMapHost h;
-    build_kmap(*qm, *qk, *qn, h);
-    split_kmap(h);
-    DevKMap& dm = ring->next();
-    dm.set(ctx, h);
-    kern::KMapScope ks(dm.get());
+    const MapCache::Entry& e = maps->get(map_key(1 /* qgemm */, {qm, qk, qn}), [&](KMapHost& h) {
+      build_kmap(*qm, *qk, *qn, h);
+      split_kmap(h);
+    });
+    const kern::KMap m = maps->use(e);
+    kern::KMapScope ks(&m);
     kern::gemm<double>(s, opa, opb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
     return;
   }
@@ -426,4 +564,52 @@ void kmap_two_site(const std::vector<int>& qlo, const std::vector<int>& qli, con
   build_batched(qlo, phys2(), 1, fuse2(qwr, qri, 1, 1), qro, g2);
   split_kmap(g1);
   split_kmap(g2);
+}
+
+// ------------------------------------------------------------ cached maps
+namespace {
+enum MapKind {
+  MK_QGEMM = 1,   // qgemm's own key
+  MK_ENV_GEMM1,
+  MK_HEFF_GEMM2,
+  MK_ENV_LEFT_GEMM2,
+  MK_ENV_RIGHT_GEMM1,
+  MK_ENV_RIGHT_GEMM3,
+  MK_KEFF1,
+  MK_KEFF2,
+  MK_TWO1,
+  MK_TWO2,
+};
+using VI = std::vector<int>;
+}  // namespace
+
+const MapEntry& cmap_env_gemm1(MapCache& c, const VI& qlo, const VI& qli, const VI& qwl, const VI& qri) {
+  return c.get(map_key(MK_ENV_GEMM1, {&qlo, &qli, &qwl, &qri}),
+               [&](KMapHost& h) { kmap_env_gemm1(qlo, qli, qwl, qri, h); });
+}
+const MapEntry& cmap_heff_gemm2(MapCache& c, const VI& qlo, const VI& qri, const VI& qwr, const VI& qro) {
+  return c.get(map_key(MK_HEFF_GEMM2, {&qlo, &qri, &qwr, &qro}),
+               [&](KMapHost& h) { kmap_heff_gemm2(qlo, qri, qwr, qro, h); });
+}
+const MapEntry& cmap_env_left_gemm2(MapCache& c, const VI& qlo, const VI& qro, const VI& qri, const VI& qwr) {
+  return c.get(map_key(MK_ENV_LEFT_GEMM2, {&qlo, &qro, &qri, &qwr}),
+               [&](KMapHost& h) { kmap_env_left_gemm2(qlo, qro, qri, qwr, h); });
+}
+const MapEntry& cmap_env_right_gemm1(MapCache& c, const VI& qli, const VI& qri, const VI& qwr, const VI& qro) {
+  return c.get(map_key(MK_ENV_RIGHT_GEMM1, {&qli, &qri, &qwr, &qro}),
+               [&](KMapHost& h) { kmap_env_right_gemm1(qli, qri, qwr, qro, h); });
+}
+const MapEntry& cmap_env_right_gemm3(MapCache& c, const VI& qli, const VI& qwl, const VI& qro, const VI& qlo) {
+  return c.get(map_key(MK_ENV_RIGHT_GEMM3, {&qli, &qwl, &qro, &qlo}),
+               [&](KMapHost& h) { kmap_env_right_gemm3(qli, qwl, qro, qlo, h); });
+}
+std::pair<const MapEntry*, const MapEntry*> cmap_keff(MapCache& c, const VI& ql, const VI& qr, const VI& qw) {
+  return c.get2(map_key(MK_KEFF1, {&ql, &qr, &qw}), map_key(MK_KEFF2, {&ql, &qr, &qw}),
+                [&](KMapHost& g1, KMapHost& g2) { kmap_keff(ql, qr, qw, g1, g2); });
+}
+std::pair<const MapEntry*, const MapEntry*> cmap_two_site(MapCache& c, const VI& qlo, const VI& qli, const VI& qwl,
+                                                          const VI& qri, const VI& qwr, const VI& qro) {
+  return c.get2(map_key(MK_TWO1, {&qlo, &qli, &qwl, &qri, &qwr, &qro}),
+                map_key(MK_TWO2, {&qlo, &qli, &qwl, &qri, &qwr, &qro}),
+                [&](KMapHost& g1, KMapHost& g2) { kmap_two_site(qlo, qli, qwl, qri, qwr, qro, g1, g2); });
 }

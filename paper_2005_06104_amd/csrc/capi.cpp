@@ -81,6 +81,7 @@ void tdvp_ctx_s::destroy_workers() {
   flush_deferred(this);
   for (tdvp_ctx_s* w : workers) {
     if (w->stream) (void)hipStreamSynchronize(w->stream);
+    w->destroy_maps();
     w->dfree(w->split_ws);
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     if (w->hstage) (void)hipHostFree(w->hstage);
@@ -314,6 +315,7 @@ void tdvp_ctx_destroy(tdvp_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->destroy_workers();
+  ctx->destroy_maps();
   ctx->dfree(ctx->split_ws);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->hstage) (void)hipHostFree(ctx->hstage);

@@ -32,6 +32,7 @@ struct TdvpError : std::runtime_error {
     if (!(cond)) TDVP_THROW(TDVP_ERR_ARG, msg); \
   } while (0)
 
+struct MapCache;
 struct tdvp_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -91,6 +92,10 @@ struct tdvp_ctx_s {
   // they are freed (through their own context) only after that stream has
   // been synchronised.
   std::vector<std::pair<tdvp_ctx_s*, void*>> deferred_frees;
+  // the block-sparse maps of the products issued on this context (created
+  // on first use; destroy_maps() frees them, before the stream goes)
+  MapCache* maps = nullptr;
+  void destroy_maps();
 };
 
 // The worker context the calling host thread runs an instance on (null
@@ -399,14 +404,13 @@ void zscale_cols(hipStream_t s, void* dst, long long ldd, const void* src, long 
 }  // namespace kern
 
 // ------------------------------------------------------------ linear algebra (FP64)
-// A ring of block-sparse maps for products issued one after another (the
-// host builds the next map while the device runs the last); see engine.h.
-struct MapRing;
+// A context's block-sparse maps on the device (engine.h).
+struct MapCache;
 // C = alpha op(A) op(B) + beta C (complex128, row-major) where the logical
 // rows, summed index and columns carry the charges qm, qk, qn (any null, or
-// ring null: dense).  With all three, the product walks only the blocks of
+// maps null: dense).  With all three, the product walks only the blocks of
 // equal charge (the operands' other entries are exact zeros).
-void qgemm(tdvp_ctx_s* ctx, MapRing* ring, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
+void qgemm(tdvp_ctx_s* ctx, MapCache* maps, int opa, int opb, int M, int N, int K, zc alpha, const void* A,
            long long lda, const void* B, long long ldb, zc beta, void* C, long long ldc, const std::vector<int>* qm,
            const std::vector<int>* qk, const std::vector<int>* qn);
 
@@ -426,15 +430,16 @@ double orth_defect(tdvp_ctx_s* ctx, const void* X, int rows, int cols, bool orth
 // the Gram matrix is numerically singular or A fails the orthonormality check.
 // With q (the charges of the columns, ascending; may be null) the Gram
 // matrix is factorised charge block by charge block; with qo (those of the
-// rows) and a map ring as well, every product walks only its charge blocks.
+// rows) and the context's maps as well, every product walks only its charge
+// blocks.
 bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
                       const void* first = nullptr, const std::vector<int>* q = nullptr,
-                      const std::vector<int>* qo = nullptr, MapRing* ring = nullptr);
+                      const std::vector<int>* qo = nullptr, MapCache* maps = nullptr);
 // C (rows <= cols) = L B with B orthonormal rows, L = C B^dagger (rows x rows);
 // q: the charges of the rows, qo those of the columns.
 bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
                            const void* first = nullptr, const std::vector<int>* q = nullptr,
-                           const std::vector<int>* qo = nullptr, MapRing* ring = nullptr);
+                           const std::vector<int>* qo = nullptr, MapCache* maps = nullptr);
 // Certifies that the smallest eigenvalue of the Hermitian positive
 // semidefinite n x n matrix G exceeds frac * trace(G): the Cholesky
 // factorisation of G - (1.01 frac + 4 n u) trace(G) I succeeds (u the unit

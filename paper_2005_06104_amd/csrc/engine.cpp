@@ -480,11 +480,11 @@ struct Work {
   DBuf ws1, ws2, xf, yf, conv, work, work2, tau, tmpA, tmpB, tmpC, dvec, wsk, nsg, nst, cinv, pidx, prow, xp, segd;
   Scalars sc;
   Lanczos lz;
-  // maps of the charge-aware products issued one after another
-  MapRing ring;
+  // the context's block-sparse maps
+  MapCache* maps;
   explicit Work(tdvp_ctx_s* c)
       : ctx(c), gws(c->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES), ws1(c), ws2(c), xf(c), yf(c), conv(c), work(c), work2(c), tau(c), tmpA(c), tmpB(c), tmpC(c),
-        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), xp(c), segd(c), sc(c), lz(c), ring(c) {}
+        dvec(c), wsk(c), nsg(c), nst(c), cinv(c), pidx(c), prow(c), xp(c), segd(c), sc(c), lz(c), maps(&map_cache(c)) {}
   // split-K scratch for products whose output is ml x mr (or smaller)
   SplitWS split(long long ml, long long mr, int cb) {
     const size_t b = (size_t)16 * 2 * ml * mr * cb;
@@ -516,7 +516,7 @@ void zmatmul(tdvp_ctx_s* ctx, int opa, int opb, int M, int N, int K, const void*
 void qgemm(Work& W, int opa, int opb, int M, int N, int K, zc alpha, const void* A, long long lda, const void* B,
            long long ldb, zc beta, void* C, long long ldc, const std::vector<int>* qm, const std::vector<int>* qk,
            const std::vector<int>* qn) {
-  ::qgemm(W.ctx, &W.ring, opa, opb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, qm, qk, qn);
+  ::qgemm(W.ctx, W.maps, opa, opb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, qm, qk, qn);
 }
 
 // Newton-Schulz orthonormalisation: for A with nearly orthonormal columns,
@@ -741,12 +741,12 @@ int factor_exact_u1(Work& W, bool left, const void* C, int rows, int cols, const
       qgemm(W, TDVP_OP_N, TDVP_OP_C, no, r, ng, 1.0, C, cols, Vs.p, ng, 0.0, W.tmpC.p, r, &qo, &qg, &qsel);
       kern::zscale_cols(s, W.tmpC.p, r, W.tmpC.p, r, no, r, f);
       Rt.ensure((size_t)r * r * ZB);
-      if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, no, r, Y.p, Rt.p, W.work, nullptr, &qsel, &qo, &W.ring)) return -1;
+      if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, no, r, Y.p, Rt.p, W.work, nullptr, &qsel, &qo, W.maps)) return -1;
     } else {      // Y = S^-1 U_sel^dagger C (r x cols), then orthonormal rows
       qgemm(W, TDVP_OP_N, TDVP_OP_N, r, no, ng, 1.0, Vs.p, ng, C, cols, 0.0, W.tmpC.p, no, &qsel, &qg, &qo);
       kern::zscale_rows(s, W.tmpC.p, no, W.tmpC.p, no, r, no, f);
       Rt.ensure((size_t)r * r * ZB);
-      if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, r, no, Rt.p, Y.p, W.work, nullptr, &qsel, &qo, &W.ring)) return -1;
+      if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, r, no, Rt.p, Y.p, W.work, nullptr, &qsel, &qo, W.maps)) return -1;
     }
   }
   X1.ensure((size_t)(left ? no : rows) * k * ZB);
@@ -777,10 +777,10 @@ int factor_exact_u1(Work& W, bool left, const void* C, int rows, int cols, const
     }
     Rt.ensure((size_t)m * m * ZB);
     if (left) {
-      if (!la::cholqr2_rowmajor(ctx, W.prow.p, no, m, Q.p, Rt.p, W.work, nullptr, &qE, &qo, &W.ring)) return -1;
+      if (!la::cholqr2_rowmajor(ctx, W.prow.p, no, m, Q.p, Rt.p, W.work, nullptr, &qE, &qo, W.maps)) return -1;
       kern::zscatter_cols(s, basis, k, Q.p, m, no, dpos_e, m);
     } else {
-      if (!la::cholqr2_rows_rowmajor(ctx, W.prow.p, m, no, Rt.p, Q.p, W.work, nullptr, &qE, &qo, &W.ring)) return -1;
+      if (!la::cholqr2_rows_rowmajor(ctx, W.prow.p, m, no, Rt.p, Q.p, W.work, nullptr, &qE, &qo, W.maps)) return -1;
       kern::zscatter(s, basis, no, Q.p, no, dpos_e, m, nullptr, no);
     }
   }
@@ -816,7 +816,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     if (keep_cols) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, nullptr, qc, qrp, &W.ring)) {
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, nullptr, qc, qrp, W.maps)) {
         if (sym) *qk = *qc;
         return kk;
       }
@@ -876,7 +876,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
     if (F) {
       A.ensure((size_t)rows * kk * ZB);
       R.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F, qc, qrp, &W.ring)) {
+      if (la::cholqr2_rowmajor(ctx, C, rows, cols, A.p, R.p, W.work, F, qc, qrp, W.maps)) {
         if (sym) *qk = *qc;
         return kk;
       }
@@ -915,7 +915,7 @@ int split_left(Work& W, const double* C, int ml, int mr, double eps, int chi_max
       // with charges the Cholesky-QR steps keep the blocks (Householder
       // reflections would mix them)
       if (!sym) la::qr_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, W.tau);
-      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, nullptr, qk, qrp, &W.ring))
+      else if (!la::cholqr2_rowmajor(ctx, W.tmpC.p, rows, n, A.p, W.tmpA.p, W.work, nullptr, qk, qrp, W.maps))
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
@@ -944,7 +944,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (keep_rows) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, nullptr, qr, qcp, &W.ring)) {
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, nullptr, qr, qcp, W.maps)) {
         if (sym) *qk = *qr;
         return kk;
       }
@@ -1000,7 +1000,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (F) {
       L.ensure((size_t)rows * kk * ZB);
       B.ensure((size_t)kk * cols * ZB);
-      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F, qr, qcp, &W.ring)) {
+      if (la::cholqr2_rows_rowmajor(ctx, C, rows, cols, L.p, B.p, W.work, F, qr, qcp, W.maps)) {
         if (sym) *qk = *qr;
         return kk;
       }
@@ -1033,7 +1033,7 @@ int split_right(Work& W, const double* C, int ml, int mr, double eps, int chi_ma
     if (!(la::orth_defect(ctx, B.p, n, cols, true, W.work) <= 1e-20)) {
       W.tmpA.ensure((size_t)n * n * ZB);
       if (!sym) la::lq_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, W.tau);
-      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, nullptr, qk, qcp, &W.ring))
+      else if (!la::cholqr2_rows_rowmajor(ctx, W.tmpC.p, n, cols, W.tmpA.p, B.p, W.work, nullptr, qk, qcp, W.maps))
         TDVP_THROW(TDVP_ERR_NUMERIC, "gauge move: no orthonormal basis of the kept space");
     }
   }
@@ -1169,14 +1169,18 @@ int lanczos_packed(Work& W, const RowSegments& g, void* x, long long n, long lon
   return napp;
 }
 
+// launchable copies of the two maps of a contraction (valid while the
+// entries stay in the cache: for the next MapCache::PROTECT lookups)
 struct PairMaps {
-  DevKMap g1, g2;
-  explicit PairMaps(tdvp_ctx_s* c) : g1(c), g2(c) {}
-  ProdMaps set(tdvp_ctx_s* ctx, const KMapHost& a, const KMapHost& b) {
-    g1.set(ctx, a);
-    g2.set(ctx, b);
-    return ProdMaps{g1.get(), g2.get(), 8.0 * (a.exact_macs + b.exact_macs)};
+  kern::KMap g1, g2;
+  explicit PairMaps(tdvp_ctx_s*) {}
+  ProdMaps set(tdvp_ctx_s* ctx, const MapEntry& a, const MapEntry& b) {
+    MapCache& c = map_cache(ctx);
+    g1 = c.use(a);
+    g2 = c.use(b);
+    return ProdMaps{&g1, &g2, a.exact_flops + b.exact_flops};
   }
+  ProdMaps set(tdvp_ctx_s* ctx, std::pair<const MapEntry*, const MapEntry*> ab) { return set(ctx, *ab.first, *ab.second); }
 };
 
 template <typename T>
@@ -1213,10 +1217,9 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const void* Bt = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
     ProdMaps pm;
     if (sym) {
-      KMapHost g1, g3;
-      kmap_env_right_gemm1(psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1], g1);
-      kmap_env_right_gemm3(psi.q[i], qw[i], psi.q[i + 1], psi.q[i], g3);
-      pm = emap.set(ctx, g1, g3);
+      MapCache& mc = map_cache(ctx);
+      pm = emap.set(ctx, cmap_env_right_gemm1(mc, psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1]),
+                    cmap_env_right_gemm3(mc, psi.q[i], qw[i], psi.q[i + 1], psi.q[i]));
     }
     env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p, {}, pm);
   };
@@ -1228,10 +1231,9 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const void* At = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
     ProdMaps pm;
     if (sym) {
-      KMapHost g1, g2;
-      kmap_env_gemm1(psi.q[i], psi.q[i], qw[i], psi.q[i + 1], g1);
-      kmap_env_left_gemm2(psi.q[i], psi.q[i + 1], psi.q[i + 1], qw[i + 1], g2);
-      pm = emap.set(ctx, g1, g2);
+      MapCache& mc = map_cache(ctx);
+      pm = emap.set(ctx, cmap_env_gemm1(mc, psi.q[i], psi.q[i], qw[i], psi.q[i + 1]),
+                    cmap_env_left_gemm2(mc, psi.q[i], psi.q[i + 1], psi.q[i + 1], qw[i + 1]));
     }
     env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p, W.split(ml, mr, cb), pm);
   };
@@ -1248,10 +1250,9 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
                           (double)2 * ml * wr * mr * mr);
     ProdMaps pm;
     if (sym) {
-      KMapHost g1, g2;
-      kmap_env_gemm1(psi.q[i], psi.q[i], qw[i], psi.q[i + 1], g1);
-      kmap_heff_gemm2(psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1], g2);
-      pm = hmap.set(ctx, g1, g2);
+      MapCache& mc = map_cache(ctx);
+      pm = hmap.set(ctx, cmap_env_gemm1(mc, psi.q[i], psi.q[i], qw[i], psi.q[i + 1]),
+                    cmap_heff_gemm2(mc, psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1]));
       flops = pm.flops + 8.0 * wstage_macs(psi.q[i], psi.q[i + 1], qw[i], H.host.W[i], wl, wr);
     }
     const SplitWS sk = W.split(ml, mr, cb);
@@ -1302,9 +1303,7 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     const SplitWS sk = W.split(ml, mr, cb);
     ProdMaps pm;
     if (sym) {
-      KMapHost g1, g2;
-      kmap_keff(*qa, *qb, qw[b], g1, g2);
-      pm = kmap.set(ctx, g1, g2);
+      pm = kmap.set(ctx, cmap_keff(map_cache(ctx), *qa, *qb, qw[b]));
     }
     auto mv = [&](const void* in, void* out) {
       if (sizeof(T) == 8) {
@@ -1896,23 +1895,19 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   PairMaps fm(ctx);
   auto right_maps = [&](int i) -> ProdMaps {   // Rs[i] from site i
     if (!sym) return {};
-    KMapHost g1, g3;
-    kmap_env_right_gemm1(in.q[i], in.q[i + 1], qw[i + 1], out.q[i + 1], g1);
-    kmap_env_right_gemm3(in.q[i], qw[i], out.q[i + 1], out.q[i], g3);
-    return fm.set(ctx, g1, g3);
+    MapCache& mc = map_cache(ctx);
+    return fm.set(ctx, cmap_env_right_gemm1(mc, in.q[i], in.q[i + 1], qw[i + 1], out.q[i + 1]),
+                  cmap_env_right_gemm3(mc, in.q[i], qw[i], out.q[i + 1], out.q[i]));
   };
   auto left_maps = [&](int i) -> ProdMaps {    // Ls[i+1] from site i
     if (!sym) return {};
-    KMapHost g1, g2;
-    kmap_env_gemm1(out.q[i], in.q[i], qw[i], in.q[i + 1], g1);
-    kmap_env_left_gemm2(out.q[i], out.q[i + 1], in.q[i + 1], qw[i + 1], g2);
-    return fm.set(ctx, g1, g2);
+    MapCache& mc = map_cache(ctx);
+    return fm.set(ctx, cmap_env_gemm1(mc, out.q[i], in.q[i], qw[i], in.q[i + 1]),
+                  cmap_env_left_gemm2(mc, out.q[i], out.q[i + 1], in.q[i + 1], qw[i + 1]));
   };
   auto local_maps = [&](int i) -> ProdMaps {   // the two-site tensor at (i, i+1)
     if (!sym) return {};
-    KMapHost g1, g2;
-    kmap_two_site(out.q[i], in.q[i], qw[i], in.q[i + 2], qw[i + 2], out.q[i + 2], g1, g2);
-    return fm.set(ctx, g1, g2);
+    return fm.set(ctx, cmap_two_site(map_cache(ctx), out.q[i], in.q[i], qw[i], in.q[i + 2], qw[i + 2], out.q[i + 2]));
   };
   if (from_right) {
     for (int i = 0; i + 2 < N; ++i) {
@@ -2028,7 +2023,7 @@ void extension(Work& W, tdvp_mps_s& psi, std::vector<tdvp_mps_s>& kv, double eps
                                                W.cinv.ensure((size_t)ml * ml * ZB), W.work, W.tmpA.p, qm);
       if (F) {
         W.tmpC.ensure((size_t)ml * ml * ZB);
-        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F, qm, sym ? &qD : nullptr, &W.ring);
+        done = la::cholqr2_rows_rowmajor(ctx, C, ml, D, W.tmpC.p, Vh.p, W.work, F, qm, sym ? &qD : nullptr, W.maps);
         if (done) {
           r = ml;
           if (sym) qB = psi.q[i];
@@ -2350,10 +2345,9 @@ void run_measure(tdvp_ctx_s* ctx, const tdvp_mps_s& psi, const tdvp_mpo_s* H, co
       envs[1].ensure((size_t)mr * wr * mr * ZB);
       ProdMaps pm;
       if (sym) {
-        KMapHost g1, g2;
-        kmap_env_gemm1(psi.q[i], psi.q[i], H->host.qw[i], psi.q[i + 1], g1);
-        kmap_env_left_gemm2(psi.q[i], psi.q[i + 1], psi.q[i + 1], H->host.qw[i + 1], g2);
-        pm = emap.set(ctx, g1, g2);
+        MapCache& mc = map_cache(ctx);
+        pm = emap.set(ctx, cmap_env_gemm1(mc, psi.q[i], psi.q[i], H->host.qw[i], psi.q[i + 1]),
+                      cmap_env_left_gemm2(mc, psi.q[i], psi.q[i + 1], psi.q[i + 1], H->host.qw[i + 1]));
       }
       env_left<double>(ctx, H->tab[i], ml, wl, wr, mr, envs[0].p, psi.site(i), envs[1].p, W.ws1.p, W.ws2.p,
                        W.split(ml, mr, 16), pm);

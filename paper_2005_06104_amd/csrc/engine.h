@@ -1,7 +1,9 @@
 // MPS / MPO handles and the GSE-TDVP1 drivers.
 #pragma once
 
+#include <functional>
 #include <memory>
+#include <unordered_map>
 
 #include "common.h"
 #include "mpo_host.h"
@@ -119,29 +121,63 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
 // Split the K intervals of a map whose nonempty tiles are too few to fill
 // the GPU into parts of about equal length (see kern::KMap).
 void split_kmap(KMapHost& h);
-// a map on the device
-struct DevKMap {
-  DBuf buf, part;   // the map; the partial products of a split map (complex128-sized)
-  kern::KMap map;
-  double exact_flops = 0.0, tile_flops = 0.0;
-  // pinned staging of the upload (reused once the previous upload is done)
-  int* stage = nullptr;
-  size_t stage_cap = 0;
-  hipEvent_t uploaded = nullptr;
-  explicit DevKMap(tdvp_ctx_s* c) : buf(c), part(c) {}
-  ~DevKMap();
-  DevKMap(const DevKMap&) = delete;
-  DevKMap& operator=(const DevKMap&) = delete;
-  void set(tdvp_ctx_s* ctx, const KMapHost& h);
-  const kern::KMap* get() const { return map.items ? &map : nullptr; }
-};
-struct MapRing {
+// The block-sparse maps of a context on the device, kept between calls and
+// keyed by the builder and the charge lists it was given.  Products whose
+// operands keep their charges from one call to the next (a sweep's exact
+// gauge moves leave every bond's charges as they were; the fitting passes;
+// the Newton-Schulz steps of a gauge move) find their map instead of
+// building and uploading it again.  Entries never change once made.  Past
+// MAX_BYTES of maps the least recently used are dropped, never one of the
+// last PROTECT looked up (a caller may still hold those).  The partial
+// products of split maps share one buffer: all of a context's work is
+// ordered on its stream; a grown buffer replaces the old one, which stays
+// allocated (maps handed out earlier point at it) until the cache goes.
+struct MapCache {
+  struct Entry {
+    std::vector<int> key;
+    DBuf buf;                 // items, intervals, tile info
+    kern::KMap map;           // partials pointer unset
+    size_t part_bytes = 0;    // partial products of a split map (complex128-sized)
+    double exact_flops = 0.0, tile_flops = 0.0;
+    unsigned long long last = 0;
+    explicit Entry(tdvp_ctx_s* c) : buf(c) {}
+  };
+  static constexpr size_t MAX_BYTES = size_t(1) << 30;
+  static constexpr unsigned long long PROTECT = 256;
+  static constexpr int NSTAGE = 4;
   tdvp_ctx_s* ctx;
-  std::vector<std::unique_ptr<DevKMap>> ring;
-  size_t pos = 0;
-  explicit MapRing(tdvp_ctx_s* c) : ctx(c) {}
-  DevKMap& next();
+  std::unordered_map<unsigned long long, std::vector<std::unique_ptr<Entry>>> tab;
+  size_t bytes = 0;
+  unsigned long long clock = 0;
+  size_t hits = 0, misses = 0, evicted = 0;
+  DBuf part;
+  std::vector<DBuf> retired;
+  // pinned staging of the uploads, reused once their copy has run
+  int* stage[NSTAGE] = {};
+  size_t stage_cap[NSTAGE] = {};
+  hipEvent_t ev[NSTAGE] = {};
+  int spos = 0;
+  explicit MapCache(tdvp_ctx_s* c) : ctx(c), part(c) {}
+  ~MapCache();
+  MapCache(const MapCache&) = delete;
+  MapCache& operator=(const MapCache&) = delete;
+  // the entry of `key`; on a miss `build` fills the host map, which is uploaded
+  const Entry& get(std::vector<int>&& key, const std::function<void(KMapHost&)>& build);
+  // both entries of a builder that makes two maps at once
+  std::pair<const Entry*, const Entry*> get2(std::vector<int>&& k1, std::vector<int>&& k2,
+                                             const std::function<void(KMapHost&, KMapHost&)>& build);
+  // a launchable copy of e's map (a split map gets the shared partials buffer)
+  kern::KMap use(const Entry& e);
+
+ private:
+  Entry* find(const std::vector<int>& key, unsigned long long h);
+  Entry& insert(std::vector<int>&& key, unsigned long long h, const KMapHost& m);
+  void evict();
 };
+// the context's cache (made on first use)
+MapCache& map_cache(tdvp_ctx_s* ctx);
+// builder id, then each charge list's length and entries
+std::vector<int> map_key(int kind, std::initializer_list<const std::vector<int>*> qs);
 // the maps of the contractions (bra bonds qlo, qro; ket bonds qli, qri; MPO
 // channels qwl, qwr; equal bra and ket for the effective Hamiltonians).  The
 // first products of H_eff, K_eff, the left environments and the two-site
@@ -165,6 +201,24 @@ void kmap_keff(const std::vector<int>& ql, const std::vector<int>& qr, const std
 void kmap_two_site(const std::vector<int>& qlo, const std::vector<int>& qli, const std::vector<int>& qwl,
                    const std::vector<int>& qri, const std::vector<int>& qwr, const std::vector<int>& qro,
                    KMapHost& g1, KMapHost& g2);
+// the same maps out of the context's cache
+using MapEntry = MapCache::Entry;
+const MapEntry& cmap_env_gemm1(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qli,
+                               const std::vector<int>& qwl, const std::vector<int>& qri);
+const MapEntry& cmap_heff_gemm2(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qri,
+                                const std::vector<int>& qwr, const std::vector<int>& qro);
+const MapEntry& cmap_env_left_gemm2(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qro,
+                                    const std::vector<int>& qri, const std::vector<int>& qwr);
+const MapEntry& cmap_env_right_gemm1(MapCache& c, const std::vector<int>& qli, const std::vector<int>& qri,
+                                     const std::vector<int>& qwr, const std::vector<int>& qro);
+const MapEntry& cmap_env_right_gemm3(MapCache& c, const std::vector<int>& qli, const std::vector<int>& qwl,
+                                     const std::vector<int>& qro, const std::vector<int>& qlo);
+std::pair<const MapEntry*, const MapEntry*> cmap_keff(MapCache& c, const std::vector<int>& ql,
+                                                      const std::vector<int>& qr, const std::vector<int>& qw);
+std::pair<const MapEntry*, const MapEntry*> cmap_two_site(MapCache& c, const std::vector<int>& qlo,
+                                                          const std::vector<int>& qli, const std::vector<int>& qwl,
+                                                          const std::vector<int>& qri, const std::vector<int>& qwr,
+                                                          const std::vector<int>& qro);
 // the maps of a contraction's products (null: dense)
 struct ProdMaps {
   const kern::KMap* g1 = nullptr;

@@ -242,6 +242,9 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
     if (more) load(nk0, nkend);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      // the stage's entries past the interval end are zeros: skip their
+      // MFMA steps (K intervals of charge blocks end anywhere)
+      if (kk > 0 && k0 + kk >= kend) break;
       const int kr = kk + lk;
       T a_r[SI], a_i[SI], a_n[SI], b_r[SJ], b_i[SJ];
 #pragma unroll

@@ -248,7 +248,7 @@ double defect(tdvp_ctx_s* ctx, const CqrSpace& c, int n, int* info) {
 }  // namespace
 
 bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* A, void* R, DBuf& work,
-                      const void* first, const std::vector<int>* q, const std::vector<int>* qo, MapRing* ring) {
+                      const void* first, const std::vector<int>* q, const std::vector<int>* qo, MapCache* maps) {
   if (cols < 1 || rows < cols) return false;
   const int n = cols;
   const CqrSpace c = cqr_space(work, n, (long long)rows * n);
@@ -261,13 +261,13 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
   const rz* cur = Cz;
   auto other = [&] { return cur == X ? c.T : X; };
   const rz one{1.0, 0.0};
-  auto gram = [&] { qgemm(ctx, ring, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, cur, n, cur, n, 0.0, c.G, n, q, qo, q); };
+  auto gram = [&] { qgemm(ctx, maps, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, cur, n, cur, n, 0.0, c.G, n, q, qo, q); };
   // X <- X R^-1 with X^H X = R^H R: X (L^-1)^H by a GEMM with the own factor,
   // a triangular solve in place with rocSOLVER's
   auto chol_step = [&](const rz* F) {
     if (own) {
       rz* dst = other();
-      qgemm(ctx, ring, TDVP_OP_N, TDVP_OP_C, rows, n, n, 1.0, cur, n, F, n, 0.0, dst, n, qo, q, q);
+      qgemm(ctx, maps, TDVP_OP_N, TDVP_OP_C, rows, n, n, 1.0, cur, n, F, n, 0.0, dst, n, qo, q, q);
       cur = dst;
     } else {
       if (cur != X) {
@@ -301,7 +301,7 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
     for (int k = 0; k < st; ++k) {
       kern::zshift_diag(s, c.G, n, -0.5, 1.0);
       rz* dst = other();
-      qgemm(ctx, ring, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, cur, n, c.G, n, 0.0, dst, n, qo, q, q);
+      qgemm(ctx, maps, TDVP_OP_N, TDVP_OP_N, rows, n, n, 1.0, cur, n, c.G, n, 0.0, dst, n, qo, q, q);
       cur = dst;
       gram();
       if (k + 1 < st) kern::zshift_diag(s, c.G, n, 1.0, -1.0);
@@ -317,7 +317,7 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
     if (info != 0 || !(dev <= 1e-20)) return false;
   }
   if (cur != X) HIP_CHECK(hipMemcpyAsync(X, cur, sizeof(rz) * (size_t)rows * n, hipMemcpyDeviceToDevice, s));
-  qgemm(ctx, ring, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, C, n, 0.0, R, n, q, qo, q);
+  qgemm(ctx, maps, TDVP_OP_C, TDVP_OP_N, n, n, rows, 1.0, X, n, C, n, 0.0, R, n, q, qo, q);
   return true;
 }
 
@@ -327,7 +327,7 @@ bool cholqr2_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* 
 // B <- (I - (B B^H - I) / 2) B.
 bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, void* L, void* B, DBuf& work,
                            const void* first, const std::vector<int>* q, const std::vector<int>* qo,
-                           MapRing* ring) {
+                           MapCache* maps) {
   if (rows < 1 || cols < rows) return false;
   const int n = rows;
   const CqrSpace c = cqr_space(work, n, (long long)n * cols);
@@ -339,14 +339,14 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
   auto other = [&] { return cur == X ? c.T : X; };
   const rz one{1.0, 0.0};
   auto gram = [&] {
-    qgemm(ctx, ring, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, cur, cols, cur, cols, 0.0, c.G, n, q, qo, q);
+    qgemm(ctx, maps, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, cur, cols, cur, cols, 0.0, c.G, n, q, qo, q);
   };
   // X <- L^-1 X with X X^H = L L^H: a GEMM with the own factor's inverse, a
   // triangular solve in place with rocSOLVER's
   auto chol_step = [&](const rz* F) {
     if (own) {
       rz* dst = other();
-      qgemm(ctx, ring, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, F, n, cur, cols, 0.0, dst, cols, q, q, qo);
+      qgemm(ctx, maps, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, F, n, cur, cols, 0.0, dst, cols, q, q, qo);
       cur = dst;
     } else {
       if (cur != X) {
@@ -379,7 +379,7 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
     for (int k = 0; k < st; ++k) {
       kern::zshift_diag(s, c.G, n, -0.5, 1.0);
       rz* dst = other();
-      qgemm(ctx, ring, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, c.G, n, cur, cols, 0.0, dst, cols, q, q, qo);
+      qgemm(ctx, maps, TDVP_OP_N, TDVP_OP_N, n, cols, n, 1.0, c.G, n, cur, cols, 0.0, dst, cols, q, q, qo);
       cur = dst;
       gram();
       if (k + 1 < st) kern::zshift_diag(s, c.G, n, 1.0, -1.0);
@@ -394,7 +394,7 @@ bool cholqr2_rows_rowmajor(tdvp_ctx_s* ctx, const void* C, int rows, int cols, v
     if (info != 0 || !(dev <= 1e-20)) return false;
   }
   if (cur != X) HIP_CHECK(hipMemcpyAsync(X, cur, sizeof(rz) * (size_t)n * cols, hipMemcpyDeviceToDevice, s));
-  qgemm(ctx, ring, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, X, cols, 0.0, L, n, q, qo, q);
+  qgemm(ctx, maps, TDVP_OP_N, TDVP_OP_C, n, n, cols, 1.0, C, cols, X, cols, 0.0, L, n, q, qo, q);
   return true;
 }
 

@@ -13,7 +13,9 @@ window length and the fraction of it the device spent in kernels.  With
 grid size (the two products of the effective Hamiltonian share a kernel).
 With --ranges (the marker_api_trace.csv of the same run, taken with
 --marker-trace) the host time of each named range inside the window is
-listed too.
+listed too, and the device's idle time (the gaps between the dispatch
+intervals) is attributed to the innermost range the host was in at the
+middle of each gap, and to the kernel that ran before it.
 """
 from __future__ import annotations
 
@@ -88,7 +90,10 @@ def summarize(path, marker="spin_kernel", split_grid=None, top=40, ranges=None):
     if ranges:
         # host time of the named ranges (inclusive of nested ones) in the window
         hr = defaultdict(lambda: [0, 0])
+        rl = []
         for n, s, e in _ranges(ranges):
+            if s < hi and e > lo:
+                rl.append((s, e, n))
             if lo < s < hi:
                 hr[n][0] += 1
                 hr[n][1] += e - s
@@ -96,7 +101,62 @@ def summarize(path, marker="spin_kernel", split_grid=None, top=40, ranges=None):
                 "| range | calls | total ms | avg us | % of window |", "|---|---:|---:|---:|---:|"]
         for key, (c, t) in sorted(hr.items(), key=lambda kv: -kv[1][1]):
             out.append(f"| `{key}` | {c} | {1e-6 * t:.1f} | {1e-3 * t / c:.1f} | {100.0 * t / (hi - lo):.2f} |")
+        out += [""] + _gaps(sel, rl, lo, hi)
     return "\n".join(out)
+
+
+def _gaps(sel, rl, lo, hi):
+    """Idle device time between dispatches, by innermost host range and by
+    the kernel that ran before the gap (ranges nest on the one host thread)."""
+    ev = sorted(sel, key=lambda r: r[1])
+    gaps = []   # (start, end, kernel before)
+    cur_e, prev = lo, "(window start)"
+    for n, s, e, _ in ev:
+        if s > cur_e:
+            gaps.append((cur_e, s, prev))
+        if e > cur_e:
+            cur_e, prev = e, n
+    if hi > cur_e:
+        gaps.append((cur_e, hi, prev))
+    rl.sort()
+    by_r = defaultdict(lambda: [0, 0])
+    by_k = defaultdict(lambda: [0, 0])
+    hist = defaultdict(lambda: [0, 0])
+    stack, i = [], 0
+    for s, e, prev in gaps:
+        t = (s + e) // 2
+        while i < len(rl) and rl[i][0] <= t:
+            while stack and stack[-1][1] < rl[i][0]:
+                stack.pop()
+            stack.append(rl[i])
+            i += 1
+        while stack and stack[-1][1] < t:
+            stack.pop()
+        name = stack[-1][2] if stack else "(no range)"
+        d = e - s
+        by_r[name][0] += 1
+        by_r[name][1] += d
+        short = prev if len(prev) <= 80 else prev[:77] + "..."
+        by_k[short][0] += 1
+        by_k[short][1] += d
+        b = "< 5 us" if d < 5000 else "5-20 us" if d < 20000 else "20-100 us" if d < 100000 else ">= 100 us"
+        hist[b][0] += 1
+        hist[b][1] += d
+    tot = sum(g[1] - g[0] for g in gaps)
+    out = [f"device idle {1e-6 * tot:.1f} ms ({100.0 * tot / (hi - lo):.1f}% of the window) in {len(gaps)} gaps", "",
+           "| gap length | gaps | total ms |", "|---|---:|---:|"]
+    for b in ("< 5 us", "5-20 us", "20-100 us", ">= 100 us"):
+        if b in hist:
+            out.append(f"| {b} | {hist[b][0]} | {1e-6 * hist[b][1]:.1f} |")
+    out += ["", "idle time by the innermost host range at the middle of the gap:", "",
+            "| range | gaps | idle ms | % of window |", "|---|---:|---:|---:|"]
+    for key, (c, d) in sorted(by_r.items(), key=lambda kv: -kv[1][1])[:25]:
+        out.append(f"| `{key}` | {c} | {1e-6 * d:.1f} | {100.0 * d / (hi - lo):.2f} |")
+    out += ["", "idle time by the kernel before the gap:", "",
+            "| kernel | gaps | idle ms | % of window |", "|---|---:|---:|---:|"]
+    for key, (c, d) in sorted(by_k.items(), key=lambda kv: -kv[1][1])[:25]:
+        out.append(f"| `{key}` | {c} | {1e-6 * d:.1f} | {100.0 * d / (hi - lo):.2f} |")
+    return out
 
 
 def main(argv=None):
