@@ -34,8 +34,10 @@ METRIC = "TDVP sweep time/step & H_eff matvec TFLOP/s, mixed vs FP64, at fixed f
 # dense matrix-core peaks of the arithmetic each precision runs on
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
-# matrix-core products issued per algorithmic product (the split uses three)
-MFMA_PER_FLOP = {"fp64": 1, "fp32": 1, "bf16": 1, "bf16x3": 3}
+# matrix-core flops issued per algorithmic flop (8 per complex multiply-add):
+# the FP64 and FP32 GEMMs form a complex product from three real products
+# (6 flops), the BF16 kernel from four, the BF16X3 split from twelve
+MFMA_PER_FLOP = {"fp64": 0.75, "fp32": 0.75, "bf16": 1, "bf16x3": 3}
 
 
 def log(*a):

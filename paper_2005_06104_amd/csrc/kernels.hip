@@ -1,9 +1,10 @@
 // Device kernels of the GSE-TDVP1 hot path (gfx950 / CDNA4).
 //
 // * zgemm/cgemm: complex GEMM split into real MFMA products.  A complex
-//   product (Ar + i Ai)(Br + i Bi) is four real MFMA accumulations into the
-//   real and imaginary output tiles (Ar Br - Ai Bi, Ar Bi + Ai Br); operand
-//   tiles are de-interleaved into real and imaginary planes in LDS.
+//   product (Ar + i Ai)(Br + i Bi) is three real MFMA accumulations,
+//   Ar Br, Ai Bi and (Ar + Ai)(Br + Bi), combined into Ar Br - Ai Bi and
+//   Ar Bi + Ai Br at the store; operand tiles are de-interleaved into real
+//   and imaginary planes in LDS.
 //   FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32 (same lane
 //   layout).  These carry every contraction of the method: effective
 //   Hamiltonians, environments, MPO application, basis extension.
@@ -191,13 +192,19 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
     }
   };
 
-  acc_t cr[SI][SJ], ci[SI][SJ];
+  // Three real products per complex multiply-add (the 3M form):
+  // p1 = sum ar br, p2 = sum ai bi, p3 = sum (ar + ai)(br + bi); then
+  // Re = p1 - p2 and Im = p3 - p1 - p2.  The operand sums are formed in
+  // registers after the LDS reads, so the matrix cores issue 3/4 of the
+  // products of the four-product form at the same LDS traffic.
+  acc_t p1[SI][SJ], p2[SI][SJ], p3[SI][SJ];
 #pragma unroll
   for (int i = 0; i < SI; ++i)
 #pragma unroll
     for (int j = 0; j < SJ; ++j) {
-      cr[i][j] = acc_t{0, 0, 0, 0};
-      ci[i][j] = acc_t{0, 0, 0, 0};
+      p1[i][j] = acc_t{0, 0, 0, 0};
+      p2[i][j] = acc_t{0, 0, 0, 0};
+      p3[i][j] = acc_t{0, 0, 0, 0};
     }
 
   const int lr = lane & 15, lk = lane >> 4;
@@ -246,27 +253,27 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       // MFMA steps (K intervals of charge blocks end anywhere)
       if (kk > 0 && k0 + kk >= kend) break;
       const int kr = kk + lk;
-      T a_r[SI], a_i[SI], a_n[SI], b_r[SJ], b_i[SJ];
+      T a_r[SI], a_i[SI], a_s[SI], b_r[SJ], b_i[SJ], b_s[SJ];
 #pragma unroll
       for (int i = 0; i < SI; ++i) {
         a_r[i] = As_r[cur][kr][wm * (BM / WM) + i * 16 + lr];
         a_i[i] = As_i[cur][kr][wm * (BM / WM) + i * 16 + lr];
-        a_n[i] = -a_i[i];
+        a_s[i] = a_r[i] + a_i[i];
       }
 #pragma unroll
       for (int j = 0; j < SJ; ++j) {
         b_r[j] = Bs_r[cur][kr][wn * (BN / WN) + j * 16 + lr];
         b_i[j] = Bs_i[cur][kr][wn * (BN / WN) + j * 16 + lr];
+        b_s[j] = b_r[j] + b_i[j];
       }
 #pragma unroll
       for (int i = 0; i < SI; ++i)
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
           if (!(act_i[i] && act_j[j])) continue;
-          cr[i][j] = mfma(a_r[i], b_r[j], cr[i][j]);
-          cr[i][j] = mfma(a_n[i], b_i[j], cr[i][j]);
-          ci[i][j] = mfma(a_r[i], b_i[j], ci[i][j]);
-          ci[i][j] = mfma(a_i[i], b_r[j], ci[i][j]);
+          p1[i][j] = mfma(a_r[i], b_r[j], p1[i][j]);
+          p2[i][j] = mfma(a_i[i], b_i[j], p2[i][j]);
+          p3[i][j] = mfma(a_s[i], b_s[j], p3[i][j]);
         }
     }
     if (more) store(cur ^ 1);
@@ -292,7 +299,8 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
         const int gm = m0 + lm;
         const int gn = n0 + ln;
         if (gm < M && gn < N && lm >= job.r0 && lm < job.r1 && ln >= job.c0 && ln < job.c1) {
-          const T xr = cr[i][j][r], xi = ci[i][j][r];
+          const T q1 = p1[i][j][r], q2 = p2[i][j][r];
+          const T xr = q1 - q2, xi = p3[i][j][r] - q1 - q2;
           c2 o;
           o.x = ar * xr - ai * xi;
           o.y = ar * xi + ai * xr;
