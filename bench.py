@@ -40,6 +40,11 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}
 MFMA_PER_FLOP = {"fp64": 0.75, "fp32": 0.75, "bf16": 1, "bf16x3": 3}
 
 
+COPY_PROBE_BYTES = 64 * 1024 * 1024
+CSRC_KERNELS = os.path.join(ROOT, "paper_2005_06104_amd", "csrc", "kernels.hip")
+CSRC_BLOCKS = os.path.join(ROOT, "paper_2005_06104_amd", "csrc", "blocks.cpp")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -88,17 +93,27 @@ def cpu_baseline(w, seconds: float, chi_probe: int):
             "matvec_ms": mv_ms, "steps_timed": n, "max_bond_reached": int(bonds)}
 
 
-def traffic_from_profile(kernel_src: str):
-    """HBM bytes per H_eff GEMM launch from the committed counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def sources_sha256(paths):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "heff_gemm_traffic_ladder64_chi256.md")
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profile(name: str, sources):
+    """HBM bytes per H_eff GEMM launch from the committed counter summary
+    profiles/<name>, or None when the sources it names (the GEMM kernel, and
+    for charged states the block-sparse maps) changed since the counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    want = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    rec = dict(line.split(":", 1) for line in txt.splitlines() if line.startswith(("kernels_sha256:", "bytes_per_launch:")))
-    if rec.get("kernels_sha256", "").strip() != want:
+    rec = dict(line.split(":", 1) for line in txt.splitlines()
+               if line.startswith(("kernels_sha256:", "sources_sha256:", "bytes_per_launch:")))
+    got = rec.get("sources_sha256", rec.get("kernels_sha256", "")).strip()
+    if got != sources_sha256(sources):
         return None
     try:
         return float(rec["bytes_per_launch"])
@@ -585,6 +600,11 @@ def cylinder_mode(args):
         if mark:
             torch.cuda._sleep(1000)
             torch.cuda.synchronize()
+            # a plain device copy of known size (64 MiB read, 64 MiB written)
+            # after the window: the calibration of the HBM byte counters
+            src = torch.empty(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
         acc["final"] = T.tdvp_measure(ctx, [psi], [H])[0]
         acc["H"], acc["psi"] = H, psi
         return acc
@@ -629,9 +649,11 @@ def cylinder_mode(args):
     out.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step")})
     against_fp64(main_run, out)
     out["heff_gemm_flops_count"] = "nonzero charge blocks only (8 flops per complex MAC)"
+    traffic = traffic_from_profile(f"heff_gemm_counters_cyl4x16_chi1024_{prec}.md", [CSRC_KERNELS, CSRC_BLOCKS])
     out["roofline"] = {"bound": "mfma", "kernel": "one-site H_eff GEMM (TAG=1), block-sparse by charge",
                        "achieved": gemm_tf, "peak": peak, "unit": "TFLOP/s",
-                       "frac": (gemm_tf / peak) if gemm_tf else None, "traffic": None}
+                       "frac": (gemm_tf / peak) if gemm_tf else None, "traffic": traffic,
+                       "issued_mfma_frac": (gemm_tf * MFMA_PER_FLOP[prec] / peak) if gemm_tf else None}
     if ref_run is not None:
         rf = summarize(ref_run, args.steps, "fp64")
         out["speedup_vs_fp64"] = res["value"] / rf["value"]
@@ -678,7 +700,8 @@ def main():
                     help="cylinder: skip the FP64 reference run (no fidelity or speedup figures)")
     ap.add_argument("--mark-timed", action="store_true",
                     help="cylinder: launch a short marker kernel (torch.cuda._sleep) right before and after "
-                         "the headline precision's timed steps, for cutting a kernel trace")
+                         "the headline precision's timed steps, for cutting a kernel trace or counter file, "
+                         "and a plain 64 MiB device copy after them for calibrating the byte counters")
     ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
                     help="skip the runs in the other precisions (mixed vs FP64)")
     ap.add_argument("--batch", action="store_true",
@@ -740,7 +763,7 @@ def main():
     res = summarize(main_run, args.steps, prec)
     gemm_tf = res["heff_gemm_tflops"]
     peak = PEAK_TFLOPS[prec]
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2005_06104_amd", "csrc", "kernels.hip")) \
+    traffic = traffic_from_profile("heff_gemm_traffic_ladder64_chi256.md", [CSRC_KERNELS]) \
         if prec == "fp64" and args.workload == 1 else None
     out = {
         "metric": METRIC,

@@ -16,6 +16,16 @@ With --ranges (the marker_api_trace.csv of the same run, taken with
 listed too, and the device's idle time (the gaps between the dispatch
 intervals) is attributed to the innermost range the host was in at the
 middle of each gap, and to the kernel that ran before it.
+
+    python -m paper_2005_06104_amd.tracesum --counters <counter_collection.csv>
+        [--kernel SUBSTRING] [--marker NAME] [--calib SUBSTRING --calib-bytes N]
+
+With --counters the file is the counter output of a `rocprofv3 --pmc` run
+(one row per dispatch and counter): the dispatches between the first and
+the last marker dispatch whose name contains SUBSTRING are averaged per
+counter; --calib names a plain copy kernel of N bytes read and N written
+(anywhere in the file), whose FETCH_SIZE / WRITE_SIZE give the factors that
+turn those counters into bytes.
 """
 from __future__ import annotations
 
@@ -159,6 +169,55 @@ def _gaps(sel, rl, lo, hi):
     return out
 
 
+def _counter_rows(path):
+    """(dispatch id, kernel name, counter name, value) per row of a counter file."""
+    with open(path, newline="") as f:
+        rows = csv.reader(f)
+        header = next(rows)
+        i_id = _col(header, "Dispatch_Id", "Correlation_Id", "Index")
+        i_name = _col(header, "Kernel_Name", "KernelName", "Name")
+        i_cn = _col(header, "Counter_Name")
+        i_cv = _col(header, "Counter_Value")
+        for r in rows:
+            yield int(r[i_id]), r[i_name], r[i_cn], float(r[i_cv])
+
+
+def counters(path, kernel, marker="spin_kernel", calib=None, calib_bytes=None):
+    """Per-dispatch averages of every counter for the kernels containing
+    `kernel` inside the marked window, plus the copy calibration."""
+    # one dispatch may appear on several rows (one per counter, or per
+    # counter dimension): values of one dispatch and counter are summed
+    per = defaultdict(lambda: defaultdict(float))
+    names = {}
+    for d, n, c, v in _counter_rows(path):
+        per[d][c] += v
+        names[d] = n
+    marks = sorted(d for d, n in names.items() if marker in n)
+    if len(marks) < 2:
+        raise SystemExit(f"fewer than two marker dispatches ({marker!r}) in {path}")
+    lo, hi = marks[0], marks[-1]
+    sel = [d for d, n in names.items() if lo < d < hi and kernel in n]
+    if not sel:
+        raise SystemExit(f"no dispatch of {kernel!r} between the markers in {path}")
+    cn = sorted({c for d in sel for c in per[d]})
+    avg = {c: sum(per[d].get(c, 0.0) for d in sel) / len(sel) for c in cn}
+    out = {"dispatches": len(sel), "avg": avg}
+    if calib:
+        cal = [d for d, n in names.items() if calib in n]
+        if cal and calib_bytes:
+            kib = calib_bytes / 1024.0
+            fac = {}
+            for c in ("FETCH_SIZE", "WRITE_SIZE"):
+                vals = [per[d][c] for d in cal if c in per[d]]
+                if vals and max(vals) > 0:
+                    fac[c] = kib / max(vals)
+            out["calib"] = {"dispatches": len(cal), "factors": fac}
+            for c, f in fac.items():
+                if c in avg:
+                    out.setdefault("bytes_per_dispatch", {})[c] = avg[c] * f * 1024.0
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("trace")
@@ -166,7 +225,15 @@ def main(argv=None):
     ap.add_argument("--split-grid", default=None)
     ap.add_argument("--top", type=int, default=40)
     ap.add_argument("--ranges", default=None, help="a marker_api_trace.csv of the same run: host time per range")
+    ap.add_argument("--counters", action="store_true", help="the file is a rocprofv3 --pmc counter file")
+    ap.add_argument("--kernel", default="gemm_kernel<float, false, false, false, false, 1>")
+    ap.add_argument("--calib", default=None, help="name of a plain copy kernel in the same file")
+    ap.add_argument("--calib-bytes", type=float, default=None, help="bytes the copy reads (and writes)")
     a = ap.parse_args(argv)
+    if a.counters:
+        import json
+        print(json.dumps(counters(a.trace, a.kernel, a.marker, a.calib, a.calib_bytes), indent=1))
+        return
     print(summarize(a.trace, a.marker, a.split_grid, a.top, a.ranges))
 
 
