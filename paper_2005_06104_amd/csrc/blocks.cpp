@@ -125,6 +125,7 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
           out.etile.push_back(t);
           out.erng.insert(out.erng.end(), {r.b - a * TILE, r.e - a * TILE, c.b - b * TILE, c.e - b * TILE});
           out.epart.push_back(0);
+          out.enone.push_back(common.empty() ? 1 : 0);
           out.tile_macs += (double)(r.e - r.b) * (c.e - c.b) * it->second.klen;
         }
     }
@@ -312,7 +313,10 @@ MapCache::Entry& MapCache::insert(std::vector<int>&& key, unsigned long long hk,
   for (int e = 0; e < E; ++e) {
     long long kl = 0;
     for (int v = h.off[e]; v < h.off[e + 1]; ++v) kl += h.iv[2 * v + 1] - h.iv[2 * v];
-    if (h.splits > 1 && kl == 0) continue;   // the reduction covers empty sub-blocks
+    // the reduction covers empty sub-blocks; drop_empty maps leave those
+    // that share no charge unwritten
+    if (h.splits > 1 && kl == 0) continue;
+    if (h.splits == 1 && h.drop_empty && (size_t)e < h.enone.size() && h.enone[e]) continue;
     order.push_back({-kl, e});
   }
   std::stable_sort(order.begin(), order.end(),
@@ -365,6 +369,7 @@ MapCache::Entry& MapCache::insert(std::vector<int>&& key, unsigned long long hk,
   map.splits = h.splits;
   map.part = nullptr;
   map.part_bytes = 0;
+  map.partial = h.splits == 1 && h.drop_empty ? 1 : 0;
   en.part_bytes = h.splits > 1 ? (size_t)h.splits * h.batch * h.M * h.N * 16 : 0;
   en.exact_flops = 8.0 * h.exact_macs;
   en.tile_flops = 8.0 * h.tile_macs;
@@ -468,6 +473,7 @@ void join_batches(const std::vector<KMapHost>& parts, KMapHost& out) {
     for (int t : p.etile) out.etile.push_back((int)x * p.tiles + t);
     out.erng.insert(out.erng.end(), p.erng.begin(), p.erng.end());
     out.epart.insert(out.epart.end(), p.epart.begin(), p.epart.end());
+    out.enone.insert(out.enone.end(), p.enone.begin(), p.enone.end());
     out.tinfo.insert(out.tinfo.end(), p.tinfo.begin(), p.tinfo.end());
     out.exact_macs += p.exact_macs;
     out.tile_macs += p.tile_macs;
@@ -579,6 +585,8 @@ enum MapKind {
   MK_KEFF2,
   MK_TWO1,
   MK_TWO2,
+  MK_WSTAGE,
+  MK_ENV_GEMM1_NZ,
 };
 using VI = std::vector<int>;
 }  // namespace
@@ -602,6 +610,31 @@ const MapEntry& cmap_env_right_gemm1(MapCache& c, const VI& qli, const VI& qri, 
 const MapEntry& cmap_env_right_gemm3(MapCache& c, const VI& qli, const VI& qwl, const VI& qro, const VI& qlo) {
   return c.get(map_key(MK_ENV_RIGHT_GEMM3, {&qli, &qwl, &qro, &qlo}),
                [&](KMapHost& h) { kmap_env_right_gemm3(qli, qwl, qro, qlo, h); });
+}
+const MapEntry& cmap_env_gemm1_nz(MapCache& c, const VI& qlo, const VI& qli, const VI& qwl, const VI& qri) {
+  return c.get(map_key(MK_ENV_GEMM1_NZ, {&qlo, &qli, &qwl, &qri}), [&](KMapHost& h) {
+    kmap_env_gemm1(qlo, qli, qwl, qri, h);
+    h.drop_empty = true;
+  });
+}
+const MapEntry& cmap_wstage(MapCache& c, const VI& qlo, const VI& qri, const VI& qwl, const VI& qwr) {
+  return c.get(map_key(MK_WSTAGE, {&qlo, &qri, &qwl, &qwr}), [&](KMapHost& h) {
+    // no work items: the table rides in the interval array
+    h = KMapHost();
+    h.off.assign(1, 0);
+    h.iv = qlo;
+    h.iv.insert(h.iv.end(), qri.begin(), qri.end());
+    for (int w : qwl)
+      for (int s = 0; s < 2; ++s) h.iv.push_back(phys_charge(s) - w);
+    for (int w : qwr)
+      for (int s = 0; s < 2; ++s) h.iv.push_back(phys_charge(s) - w);
+    h.M = (int)qlo.size();
+    h.N = (int)qri.size();
+  });
+}
+kern::WCharges wc_of(const MapEntry& e, int ml, int mr, int wl) {
+  const int* b = e.map.iv;
+  return kern::WCharges{b, b + ml, b + ml + mr, b + ml + mr + 2 * wl, 0};
 }
 std::pair<const MapEntry*, const MapEntry*> cmap_keff(MapCache& c, const VI& ql, const VI& qr, const VI& qw) {
   return c.get2(map_key(MK_KEFF1, {&ql, &qr, &qw}), map_key(MK_KEFF2, {&ql, &qr, &qw}),

@@ -193,6 +193,7 @@ struct KMap {
   const int* tinfo = nullptr;
   void* part = nullptr;
   size_t part_bytes = 0;
+  int partial = 0;             // unsplit map without the sub-blocks that share no charge
 };
 void set_kmap(const KMap* k);
 const KMap* current_kmap();
@@ -306,10 +307,25 @@ struct WTable {
   const double* val;      // device, complex128 coefficients
   int n_in_ch, n_out_ch;
 };
+// Charges of the sparse-MPO stage of a charged contraction (device arrays):
+// element (p, q) of the stage pairs bra row p (charge ql[p]) with ket column
+// q (charge qr[q]); with d = qr[q] - ql[p], input channel c can be nonzero
+// only where din[c] == d and output channel o only where dout[o] == d.
+struct WCharges {
+  const int* ql;
+  const int* qr;
+  const int* din;
+  const int* dout;
+  int zeros_kept;   // the outputs that are zero by charge already hold zeros: not stored
+};
+// wc (may be NULL: dense) skips the loads of inputs that are zero by charge
+// and stores zero, without a sum, into the outputs that are (or, with
+// zeros_kept, leaves them as they are); the results are those of the dense
+// stage on inputs that hold those zeros.
 template <typename T>
 void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long nP, long long nQ,
             long long isP, long long isQ, long long is1, long long is2, long long osP,
-            long long osQ, long long os1, long long os2);
+            long long osQ, long long os1, long long os2, const WCharges* wc = nullptr);
 
 // complex128 vector helpers (n complex elements)
 // out[j] = sum_x conj(V[j*ldv + x]) w[x], j < nv (deterministic two-stage

@@ -231,7 +231,7 @@ void heff_apply(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, i
   if (tm) tm->mark(1);
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
-                  mr, (long long)wr * mr);
+                  mr, (long long)wr * mr, pm.wc);
   if (tm) tm->mark(2);
   // Y[(a',s'),b'] = T2[(a',s'),(be,b)] Rt[(be,b),b'] (with charges: batched over s')
   if (pm.g2) {
@@ -275,7 +275,7 @@ void env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, int
     kern::gemm_nn_ws<T>(s, ml * wl, 2 * mr, ml, 1.0, L, ml, A, 2 * mr, 0.0, ws1, 2 * mr, sk.p, sk.bytes);
   }
   kern::wapply<T>(s, tb.F, ws1, ws2, ml, mr, (long long)wl * 2 * mr, 1, 2LL * mr, mr, (long long)2 * wr * mr, 1,
-                  mr, (long long)wr * mr);
+                  mr, (long long)wr * mr, pm.wc);
   // Lout[b',(be,b)] = sum_{(a',s')} conj(A[(a',s'),b']) T2[(a',s'),(be,b)]
   kern::KMapScope ks(pm.g2);
   kern::gemm<T>(s, TDVP_OP_C, TDVP_OP_N, mr, wr * mr, 2 * ml, 1.0, A, mr, 0, ws2, (long long)wr * mr, 0, 0.0, Lout,
@@ -1230,10 +1230,13 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     L[i + 1].ensure((size_t)mr * wr * mr * cb);
     const void* At = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
     ProdMaps pm;
+    kern::WCharges wcs;
     if (sym) {
       MapCache& mc = map_cache(ctx);
-      pm = emap.set(ctx, cmap_env_gemm1(mc, psi.q[i], psi.q[i], qw[i], psi.q[i + 1]),
+      pm = emap.set(ctx, cmap_env_gemm1_nz(mc, psi.q[i], psi.q[i], qw[i], psi.q[i + 1]),
                     cmap_env_left_gemm2(mc, psi.q[i], psi.q[i + 1], psi.q[i + 1], qw[i + 1]));
+      wcs = wc_of(cmap_wstage(mc, psi.q[i], psi.q[i + 1], qw[i], qw[i + 1]), ml, mr, wl);
+      pm.wc = &wcs;
     }
     env_left<T>(ctx, H.tab[i], ml, wl, wr, mr, L[i].p, At, L[i + 1].p, W.ws1.p, W.ws2.p, W.split(ml, mr, cb), pm);
   };
@@ -1249,10 +1252,18 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     double flops = 8.0 * ((double)ml * wl * ml * 2 * mr + (double)H.tab[i].nnz * ml * mr +
                           (double)2 * ml * wr * mr * mr);
     ProdMaps pm;
+    kern::WCharges wcs;
     if (sym) {
       MapCache& mc = map_cache(ctx);
-      pm = hmap.set(ctx, cmap_env_gemm1(mc, psi.q[i], psi.q[i], qw[i], psi.q[i + 1]),
+      pm = hmap.set(ctx, cmap_env_gemm1_nz(mc, psi.q[i], psi.q[i], qw[i], psi.q[i + 1]),
                     cmap_heff_gemm2(mc, psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1]));
+      wcs = wc_of(cmap_wstage(mc, psi.q[i], psi.q[i + 1], qw[i], qw[i + 1]), ml, mr, wl);
+      // the stage's outputs of other charges are cleared once here and
+      // never stored by the matvecs of this site (nothing else writes ws2
+      // until the site's Lanczos run ends)
+      kern::zfill(ctx->stream, W.ws2.p, zc(0.0, 0.0), 2LL * ml * wr * mr, cb);
+      wcs.zeros_kept = 1;
+      pm.wc = &wcs;
       flops = pm.flops + 8.0 * wstage_macs(psi.q[i], psi.q[i + 1], qw[i], H.host.W[i], wl, wr);
     }
     const SplitWS sk = W.split(ml, mr, cb);

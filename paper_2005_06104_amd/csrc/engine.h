@@ -114,8 +114,15 @@ struct MatvecTimer {
 // parts of each of its up to four sub-blocks (split maps).
 struct KMapHost {
   std::vector<int> off, iv, etile, erng, epart, tinfo;
+  // per entry of an unsplit map: 1 when its rows and columns share no
+  // charge (every output of the sub-block is zero by charge)
+  std::vector<unsigned char> enone;
   double exact_macs = 0.0, tile_macs = 0.0;   // nonzero multiply-adds; those the tiles perform
   int M = 0, N = 0, K = 0, batch = 1, splits = 1, tiles = 0;
+  // unsplit maps: leave out the sub-blocks whose rows and columns share no
+  // charge (their output is then not written at all; for consumers that
+  // read by charge and never touch it)
+  bool drop_empty = false;
 };
 void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const std::vector<int>& cq, KMapHost& out);
 // Split the K intervals of a map whose nonempty tiles are too few to fill
@@ -224,7 +231,20 @@ struct ProdMaps {
   const kern::KMap* g1 = nullptr;
   const kern::KMap* g2 = nullptr;
   double flops = -1.0;   // nonzero flops of the two products (negative: dense count)
+  const kern::WCharges* wc = nullptr;   // charges of the sparse-MPO stage (null: dense)
 };
+// The charges of the sparse-MPO stage between the two products of H_eff and
+// of the left environment (bra bond qlo on the rows, ket bond qri on the
+// columns, MPO channels qwl in and qwr out) as one cached device table:
+// qlo, qri, then q(s) - qwl[al] for input channel 2 al + s and q(s') -
+// qwr[be] for output channel 2 be + s'.  wc_of fills the four pointers.
+// the first product of H_eff and of the left environment when the sparse-MPO
+// stage after it reads by charge: sub-blocks no charge reaches are not written
+const MapEntry& cmap_env_gemm1_nz(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qli,
+                                  const std::vector<int>& qwl, const std::vector<int>& qri);
+const MapEntry& cmap_wstage(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qri,
+                            const std::vector<int>& qwl, const std::vector<int>& qwr);
+kern::WCharges wc_of(const MapEntry& e, int ml, int mr, int wl);
 
 // kernel-level helpers used by the C-ABI
 // Split-K scratch for the contractions (may be empty: no K splitting).

@@ -672,7 +672,9 @@ void launch_gemm_mode(hipStream_t s, int M, int N, int K, zc alpha, const void* 
                          T(beta.real()), T(beta.imag()), static_cast<T*>(C), ldc, sc);
       return;
     }
-    if (km->n_items < batch * gx * ((M + BM - 1) / BM)) TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without every tile");
+    if (!km->partial && km->n_items < batch * gx * ((M + BM - 1) / BM))
+      TDVP_THROW(TDVP_ERR_ARG, "block-sparse map without every tile");
+    if (km->n_items == 0) return;   // a partial map with nothing to write
     launch_tiles<T, MODE, TA, CA, TB, CB, TAG>(dim3(km->n_items), s, M, N, K, T(alpha.real()), T(alpha.imag()), a,
                                                lda, sa, b, ldb, sb, T(beta.real()), T(beta.imag()),
                                                static_cast<T*>(C), ldc, sc, 1, std::max(K, 1), 0LL, km->items,
@@ -734,6 +736,7 @@ void dispatch_b(hipStream_t s, int opb, int M, int N, int K, zc alpha, const voi
 // ---------------------------------------------------------------- W apply
 constexpr int WQ = 64;      // q extent per block
 constexpr int WNT = 256;
+constexpr int WMAX_CH = 256;   // channels (MPO index x physical index) of a charged stage
 
 template <typename T>
 __global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T* __restrict__ out, long long nQ,
@@ -743,19 +746,31 @@ __global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T
                                                       const int* __restrict__ rowptr,
                                                       const int* __restrict__ col,
                                                       const double2* __restrict__ val, int n_in,
-                                                      int n_out) {
+                                                      int n_out, kern::WCharges wc) {
   using c2 = typename VT<T>::c2;
   extern __shared__ unsigned char smem_raw[];
   c2* lds = reinterpret_cast<c2*>(smem_raw);  // [n_in][WQ]
+  // charge difference of each column of the block and the channels' own
+  // (charged contractions only)
+  __shared__ int dq[WQ];
+  __shared__ int din_s[WMAX_CH], dout_s[WMAX_CH];
   const long long p = blockIdx.y;
   const long long q0 = (long long)blockIdx.x * WQ;
   const c2* inb = reinterpret_cast<const c2*>(in);
   c2* outb = reinterpret_cast<c2*>(out);
+  const bool charged = wc.ql != nullptr;
+  if (charged) {
+    for (int t = threadIdx.x; t < WQ; t += WNT) dq[t] = q0 + t < nQ ? wc.qr[q0 + t] - wc.ql[p] : 0;
+    for (int t = threadIdx.x; t < n_in; t += WNT) din_s[t] = wc.din[t];
+    for (int t = threadIdx.x; t < n_out; t += WNT) dout_s[t] = wc.dout[t];
+    __syncthreads();
+  }
   for (int idx = threadIdx.x; idx < n_in * WQ; idx += WNT) {
     const int c = idx / WQ, q = idx % WQ;
     c2 v;
     v.x = T(0); v.y = T(0);
-    if (q0 + q < nQ) v = inb[p * isP + (q0 + q) * isQ + (c >> 1) * is1 + (c & 1) * is2];
+    if (q0 + q < nQ && (!charged || din_s[c] == dq[q]))
+      v = inb[p * isP + (q0 + q) * isQ + (c >> 1) * is1 + (c & 1) * is2];
     lds[idx] = v;
   }
   __syncthreads();
@@ -763,7 +778,12 @@ __global__ __launch_bounds__(WNT) void wapply_kernel(const T* __restrict__ in, T
     const int o = idx / WQ, q = idx % WQ;
     if (q0 + q >= nQ) continue;
     T sr = T(0), si = T(0);
-    for (int e = rowptr[o]; e < rowptr[o + 1]; ++e) {
+    // an output of another charge is an exact zero (+0, as the sum of the
+    // zero inputs would give), stored unless the output already holds it
+    const bool zero = charged && dout_s[o] != dq[q];
+    if (zero && wc.zeros_kept) continue;
+    const int e_end = zero ? rowptr[o] : rowptr[o + 1];
+    for (int e = rowptr[o]; e < e_end; ++e) {
       const double2 w = val[e];
       const c2 x = lds[col[e] * WQ + q];
       sr += T(w.x) * x.x - T(w.y) * x.y;
@@ -1269,21 +1289,29 @@ template void gemm<float>(hipStream_t, int, int, int, int, int, zc, const void*,
 template <typename T>
 void wapply(hipStream_t s, const WTable& t, const void* in, void* out, long long nP, long long nQ,
             long long isP, long long isQ, long long is1, long long is2, long long osP, long long osQ,
-            long long os1, long long os2) {
+            long long os1, long long os2, const WCharges* wc) {
   if (nP <= 0 || nQ <= 0) return;
   if (nP > 65535) TDVP_THROW(TDVP_ERR_ARG, "wapply: P extent too large");
   dim3 grid((unsigned)((nQ + WQ - 1) / WQ), (unsigned)nP);
   const size_t sh = (size_t)t.n_in_ch * WQ * sizeof(typename VT<T>::c2);
   if (sh > 64 * 1024) TDVP_THROW(TDVP_ERR_ARG, "wapply: MPO bond dimension too large");
+  WCharges w{nullptr, nullptr, nullptr, nullptr, 0};
+  if (wc) {
+    if (t.n_in_ch > WMAX_CH || t.n_out_ch > WMAX_CH) TDVP_THROW(TDVP_ERR_ARG, "wapply: too many charged channels");
+    if (!wc->ql || !wc->qr || !wc->din || !wc->dout) TDVP_THROW(TDVP_ERR_ARG, "wapply: incomplete charge table");
+    w = *wc;
+  }
   hipLaunchKernelGGL(wapply_kernel<T>, grid, dim3(WNT), sh, s, static_cast<const T*>(in), static_cast<T*>(out),
                      nQ, isP, isQ, is1, is2, osP, osQ, os1, os2, t.rowptr, t.col,
-                     reinterpret_cast<const double2*>(t.val), t.n_in_ch, t.n_out_ch);
+                     reinterpret_cast<const double2*>(t.val), t.n_in_ch, t.n_out_ch, w);
   HIP_CHECK(hipGetLastError());
 }
 template void wapply<double>(hipStream_t, const WTable&, const void*, void*, long long, long long, long long,
-                             long long, long long, long long, long long, long long, long long, long long);
+                             long long, long long, long long, long long, long long, long long, long long,
+                             const WCharges*);
 template void wapply<float>(hipStream_t, const WTable&, const void*, void*, long long, long long, long long,
-                            long long, long long, long long, long long, long long, long long, long long);
+                            long long, long long, long long, long long, long long, long long, long long,
+                            const WCharges*);
 
 int zdots_blocks(long long n) { return (int)std::max<long long>(1, (n + DOT_CHUNK - 1) / DOT_CHUNK); }
 
