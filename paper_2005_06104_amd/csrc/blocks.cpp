@@ -587,6 +587,9 @@ enum MapKind {
   MK_TWO2,
   MK_WSTAGE,
   MK_ENV_GEMM1_NZ,
+  MK_ENV_RIGHT_GEMM1_NZ,
+  MK_TWO1_NZ,
+  MK_TWO2_NZ,
 };
 using VI = std::vector<int>;
 }  // namespace
@@ -617,24 +620,39 @@ const MapEntry& cmap_env_gemm1_nz(MapCache& c, const VI& qlo, const VI& qli, con
     h.drop_empty = true;
   });
 }
-const MapEntry& cmap_wstage(MapCache& c, const VI& qlo, const VI& qri, const VI& qwl, const VI& qwr) {
-  return c.get(map_key(MK_WSTAGE, {&qlo, &qri, &qwl, &qwr}), [&](KMapHost& h) {
+const MapEntry& cmap_env_right_gemm1_nz(MapCache& c, const VI& qli, const VI& qri, const VI& qwr, const VI& qro) {
+  return c.get(map_key(MK_ENV_RIGHT_GEMM1_NZ, {&qli, &qri, &qwr, &qro}), [&](KMapHost& h) {
+    kmap_env_right_gemm1(qli, qri, qwr, qro, h);
+    h.drop_empty = true;
+  });
+}
+std::pair<const MapEntry*, const MapEntry*> cmap_two_site_nz(MapCache& c, const VI& qlo, const VI& qli, const VI& qwl,
+                                                             const VI& qri, const VI& qwr, const VI& qro) {
+  return c.get2(map_key(MK_TWO1_NZ, {&qlo, &qli, &qwl, &qri, &qwr, &qro}),
+                map_key(MK_TWO2_NZ, {&qlo, &qli, &qwl, &qri, &qwr, &qro}), [&](KMapHost& g1, KMapHost& g2) {
+                  kmap_two_site(qlo, qli, qwl, qri, qwr, qro, g1, g2);
+                  g1.drop_empty = true;
+                });
+}
+const MapEntry& cmap_wstage(MapCache& c, const VI& qrow, const VI& qcol, const VI& qwin, const VI& qwout, int sign) {
+  const VI sg{sign};
+  return c.get(map_key(MK_WSTAGE, {&qrow, &qcol, &qwin, &qwout, &sg}), [&](KMapHost& h) {
     // no work items: the table rides in the interval array
     h = KMapHost();
     h.off.assign(1, 0);
-    h.iv = qlo;
-    h.iv.insert(h.iv.end(), qri.begin(), qri.end());
-    for (int w : qwl)
-      for (int s = 0; s < 2; ++s) h.iv.push_back(phys_charge(s) - w);
-    for (int w : qwr)
-      for (int s = 0; s < 2; ++s) h.iv.push_back(phys_charge(s) - w);
-    h.M = (int)qlo.size();
-    h.N = (int)qri.size();
+    h.iv = qrow;
+    h.iv.insert(h.iv.end(), qcol.begin(), qcol.end());
+    for (int w : qwin)
+      for (int s = 0; s < 2; ++s) h.iv.push_back(phys_charge(s) + sign * w);
+    for (int w : qwout)
+      for (int s = 0; s < 2; ++s) h.iv.push_back(phys_charge(s) + sign * w);
+    h.M = (int)qrow.size();
+    h.N = (int)qcol.size();
   });
 }
-kern::WCharges wc_of(const MapEntry& e, int ml, int mr, int wl) {
+kern::WCharges wc_of(const MapEntry& e, int nrow, int ncol, int win) {
   const int* b = e.map.iv;
-  return kern::WCharges{b, b + ml, b + ml + mr, b + ml + mr + 2 * wl, 0};
+  return kern::WCharges{b, b + nrow, b + nrow + ncol, b + nrow + ncol + 2 * win, 0};
 }
 std::pair<const MapEntry*, const MapEntry*> cmap_keff(MapCache& c, const VI& ql, const VI& qr, const VI& qw) {
   return c.get2(map_key(MK_KEFF1, {&ql, &qr, &qw}), map_key(MK_KEFF2, {&ql, &qr, &qw}),

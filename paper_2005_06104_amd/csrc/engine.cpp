@@ -294,7 +294,7 @@ void env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int ml, int wl, int wr, in
                   2LL * ml * mr, wr);
   }
   // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
-  kern::wapply<T>(s, tb.B, ws1, ws2, ml, mr, 2LL * mr, 1, 2LL * ml * mr, mr, 2LL * mr, 1, 2LL * ml * mr, mr);
+  kern::wapply<T>(s, tb.B, ws1, ws2, ml, mr, 2LL * mr, 1, 2LL * ml * mr, mr, 2LL * mr, 1, 2LL * ml * mr, mr, pm.wc);
   // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(B[a',(s',b')])
   kern::KMapScope ks(pm.g2);
   kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, wl * ml, ml, 2 * mr, 1.0, ws2, 2LL * mr, 0, B, 2LL * mr, 0, 0.0, Rout, ml,
@@ -1216,10 +1216,13 @@ void sweep_impl(tdvp_ctx_s* ctx, tdvp_mps_s& psi, const tdvp_mpo_s& H, const tdv
     R[i].ensure((size_t)wl * ml * ml * cb);
     const void* Bt = site_in<T>(ctx, psi.site(i), psi.elems(i), W.conv);
     ProdMaps pm;
+    kern::WCharges wcs;
     if (sym) {
       MapCache& mc = map_cache(ctx);
-      pm = emap.set(ctx, cmap_env_right_gemm1(mc, psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1]),
+      pm = emap.set(ctx, cmap_env_right_gemm1_nz(mc, psi.q[i], psi.q[i + 1], qw[i + 1], psi.q[i + 1]),
                     cmap_env_right_gemm3(mc, psi.q[i], qw[i], psi.q[i + 1], psi.q[i]));
+      wcs = wc_of(cmap_wstage(mc, psi.q[i], psi.q[i + 1], qw[i + 1], qw[i], +1), ml, mr, wr);
+      pm.wc = &wcs;
     }
     env_right<T>(ctx, H.tab[i], ml, wl, wr, mr, R[i + 1].p, Bt, R[i].p, W.ws1.p, W.ws2.p, {}, pm);
   };
@@ -1757,7 +1760,7 @@ void fit_env_left(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int w
   }
   // T2[a',s',be,b] = sum W[al,be,s',s] T1[a',al,s,b]
   kern::wapply<T>(s, tb.F, f1.p, f2.p, mlo, mri, (long long)wl * 2 * mri, 1, 2LL * mri, mri,
-                       2LL * wr * mri, 1, mri, (long long)wr * mri);
+                       2LL * wr * mri, 1, mri, (long long)wr * mri, pm.wc);
   // Lout[b',(be,b)] = sum_{(a',s')} conj(bra[(a',s'),b']) T2[(a',s'),(be,b)]
   kern::KMapScope ks(pm.g2);
   kern::gemm<T>(s, TDVP_OP_C, TDVP_OP_N, mro, wr * mri, 2 * mlo, 1.0, bra, mro, 0, f2.p, (long long)wr * mri, 0,
@@ -1782,7 +1785,7 @@ void fit_env_right(tdvp_ctx_s* ctx, const SiteTables& tb, int mlo, int mli, int 
   }
   // U2[al,a,s',b'] = sum W[al,be,s',s] U1[be,a,s,b']
   kern::wapply<T>(s, tb.B, f1.p, f2.p, mli, mro, 2LL * mro, 1, 2LL * mli * mro, mro, 2LL * mro, 1,
-                       2LL * mli * mro, mro);
+                       2LL * mli * mro, mro, pm.wc);
   // Rout[(al,a),a'] = sum_{(s',b')} U2[(al,a),(s',b')] conj(bra[a',(s',b')])
   kern::KMapScope ks(pm.g2);
   kern::gemm<T>(s, TDVP_OP_N, TDVP_OP_C, wl * mli, mlo, 2 * mro, 1.0, f2.p, 2LL * mro, 0, bra, 2LL * mro, 0, 0.0,
@@ -1813,10 +1816,10 @@ void fit_local2(tdvp_ctx_s* ctx, const SiteTables& t1, const SiteTables& t2, int
   }
   // T2[a',t,be,(v,b)] = sum W1[al,be,t,s] T1[a',al,s,(v,b)]
   kern::wapply<T>(s, t1.F, f1.p, f2.p, mlo, 2LL * mri, (long long)wl * 4 * mri, 1, 4LL * mri, 2LL * mri,
-                       (long long)2 * wm * 2 * mri, 1, 2LL * mri, (long long)wm * 2 * mri);
+                       (long long)2 * wm * 2 * mri, 1, 2LL * mri, (long long)wm * 2 * mri, pm.wc);
   // T3[(a',t),u,ga,b] = sum W2[be,ga,u,v] T2[(a',t),be,v,b]
   kern::wapply<T>(s, t2.F, f2.p, f1.p, 2LL * mlo, mri, (long long)wm * 2 * mri, 1, 2LL * mri, mri,
-                       (long long)2 * wr * mri, 1, mri, (long long)wr * mri);
+                       (long long)2 * wr * mri, 1, mri, (long long)wr * mri, pm.wc2);
   // Y[(a',t,u),b'] = T3[(a',t,u),(ga,b)] Rt[(ga,b),b'] (with charges: batched over (t, u))
   kern::KMapScope ks(pm.g2);
   if (pm.g2)
@@ -1904,21 +1907,49 @@ double fit_apply(Work& W, const tdvp_mps_s& in, const tdvp_mpo_s& op, double eps
   // with charges, the products walk their nonzero blocks
   const auto& qw = op.host.qw;
   PairMaps fm(ctx);
+  // the sparse-MPO stages read by charge; the first products leave out the
+  // sub-blocks that share no charge (never read by those stages)
+  kern::WCharges fwc1, fwc2;
   auto right_maps = [&](int i) -> ProdMaps {   // Rs[i] from site i
     if (!sym) return {};
     MapCache& mc = map_cache(ctx);
-    return fm.set(ctx, cmap_env_right_gemm1(mc, in.q[i], in.q[i + 1], qw[i + 1], out.q[i + 1]),
-                  cmap_env_right_gemm3(mc, in.q[i], qw[i], out.q[i + 1], out.q[i]));
+    ProdMaps pm = fm.set(ctx, cmap_env_right_gemm1_nz(mc, in.q[i], in.q[i + 1], qw[i + 1], out.q[i + 1]),
+                         cmap_env_right_gemm3(mc, in.q[i], qw[i], out.q[i + 1], out.q[i]));
+    fwc1 = wc_of(cmap_wstage(mc, in.q[i], out.q[i + 1], qw[i + 1], qw[i], +1), in.m[i], out.m[i + 1], op.w(i + 1));
+    pm.wc = &fwc1;
+    return pm;
   };
   auto left_maps = [&](int i) -> ProdMaps {    // Ls[i+1] from site i
     if (!sym) return {};
     MapCache& mc = map_cache(ctx);
-    return fm.set(ctx, cmap_env_gemm1(mc, out.q[i], in.q[i], qw[i], in.q[i + 1]),
-                  cmap_env_left_gemm2(mc, out.q[i], out.q[i + 1], in.q[i + 1], qw[i + 1]));
+    ProdMaps pm = fm.set(ctx, cmap_env_gemm1_nz(mc, out.q[i], in.q[i], qw[i], in.q[i + 1]),
+                         cmap_env_left_gemm2(mc, out.q[i], out.q[i + 1], in.q[i + 1], qw[i + 1]));
+    fwc1 = wc_of(cmap_wstage(mc, out.q[i], in.q[i + 1], qw[i], qw[i + 1]), out.m[i], in.m[i + 1], op.w(i));
+    pm.wc = &fwc1;
+    return pm;
   };
+  std::vector<int> qvb, qat;
   auto local_maps = [&](int i) -> ProdMaps {   // the two-site tensor at (i, i+1)
     if (!sym) return {};
-    return fm.set(ctx, cmap_two_site(map_cache(ctx), out.q[i], in.q[i], qw[i], in.q[i + 2], qw[i + 2], out.q[i + 2]));
+    MapCache& mc = map_cache(ctx);
+    ProdMaps pm =
+        fm.set(ctx, cmap_two_site_nz(mc, out.q[i], in.q[i], qw[i], in.q[i + 2], qw[i + 2], out.q[i + 2]));
+    // first stage: rows a' of phi, columns (v, b) with charge q(b) - q(v);
+    // its outputs of other charges are never read by the second stage,
+    // whose rows (a', t) carry q(a') + q(t)
+    const int mri = in.m[i + 2], mlo = out.m[i];
+    qvb.resize(2 * (size_t)mri);
+    for (int v = 0; v < 2; ++v)
+      for (int b = 0; b < mri; ++b) qvb[(size_t)v * mri + b] = in.q[i + 2][b] - phys_charge(v);
+    qat.resize(2 * (size_t)mlo);
+    for (int a = 0; a < mlo; ++a)
+      for (int t = 0; t < 2; ++t) qat[2 * (size_t)a + t] = out.q[i][a] + phys_charge(t);
+    fwc1 = wc_of(cmap_wstage(mc, out.q[i], qvb, qw[i], qw[i + 1]), mlo, 2 * mri, op.w(i));
+    fwc1.zeros_kept = 1;
+    fwc2 = wc_of(cmap_wstage(mc, qat, in.q[i + 2], qw[i + 1], qw[i + 2]), 2 * mlo, mri, op.w(i + 1));
+    pm.wc = &fwc1;
+    pm.wc2 = &fwc2;
+    return pm;
   };
   if (from_right) {
     for (int i = 0; i + 2 < N; ++i) {

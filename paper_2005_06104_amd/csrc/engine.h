@@ -232,19 +232,30 @@ struct ProdMaps {
   const kern::KMap* g2 = nullptr;
   double flops = -1.0;   // nonzero flops of the two products (negative: dense count)
   const kern::WCharges* wc = nullptr;   // charges of the sparse-MPO stage (null: dense)
+  const kern::WCharges* wc2 = nullptr;  // of the second stage of a two-site product
 };
-// The charges of the sparse-MPO stage between the two products of H_eff and
-// of the left environment (bra bond qlo on the rows, ket bond qri on the
-// columns, MPO channels qwl in and qwr out) as one cached device table:
-// qlo, qri, then q(s) - qwl[al] for input channel 2 al + s and q(s') -
-// qwr[be] for output channel 2 be + s'.  wc_of fills the four pointers.
-// the first product of H_eff and of the left environment when the sparse-MPO
-// stage after it reads by charge: sub-blocks no charge reaches are not written
+// The charges of a sparse-MPO stage (element (p, q): row charge qrow[p],
+// column charge qcol[q]; MPO channels qwin in, qwout out) as one cached
+// device table: qrow, qcol, then q(s) + sign * qwin[x] for input channel
+// 2 x + s and q(s') + sign * qwout[y] for output channel 2 y + s'.  The
+// stages after a left-side product (H_eff, left environments, two-site
+// tensors) take sign = -1, those after a right-side product sign = +1.
+// wc_of fills the four pointers.
+const MapEntry& cmap_wstage(MapCache& c, const std::vector<int>& qrow, const std::vector<int>& qcol,
+                            const std::vector<int>& qwin, const std::vector<int>& qwout, int sign = -1);
+kern::WCharges wc_of(const MapEntry& e, int nrow, int ncol, int win);
+// First products without the sub-blocks that share no charge, for a stage
+// after them that reads by charge (their outputs there are never written):
+// H_eff and the left environments, the right environments, the fitting's
+// two-site tensor (its second map as in cmap_two_site).
 const MapEntry& cmap_env_gemm1_nz(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qli,
                                   const std::vector<int>& qwl, const std::vector<int>& qri);
-const MapEntry& cmap_wstage(MapCache& c, const std::vector<int>& qlo, const std::vector<int>& qri,
-                            const std::vector<int>& qwl, const std::vector<int>& qwr);
-kern::WCharges wc_of(const MapEntry& e, int ml, int mr, int wl);
+const MapEntry& cmap_env_right_gemm1_nz(MapCache& c, const std::vector<int>& qli, const std::vector<int>& qri,
+                                        const std::vector<int>& qwr, const std::vector<int>& qro);
+std::pair<const MapEntry*, const MapEntry*> cmap_two_site_nz(MapCache& c, const std::vector<int>& qlo,
+                                                             const std::vector<int>& qli, const std::vector<int>& qwl,
+                                                             const std::vector<int>& qri, const std::vector<int>& qwr,
+                                                             const std::vector<int>& qro);
 
 // kernel-level helpers used by the C-ABI
 // Split-K scratch for the contractions (may be empty: no K splitting).
