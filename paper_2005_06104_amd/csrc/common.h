@@ -249,6 +249,16 @@ hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* er
 // scratch holds tridiag_eig_scratch_bytes(n).  Returns the launch status.
 size_t tridiag_eig_scratch_bytes(int n);
 hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double* Z, void* scratch);
+// Several such problems (each n <= 512 with its own scratch) side by side:
+// one launch per stage for all of them (results as from tridiag_eig).
+struct TdEigJob {
+  double* D;
+  const double* E;
+  int n;
+  double* Z;
+  void* scratch;
+};
+hipError_t tridiag_eig_batched(hipStream_t s, const TdEigJob* jobs, int n_jobs);
 // Cholesky factorisation G = L L^H of a Hermitian positive definite n x n
 // matrix (row-major complex128, the lower blocks read; n <= cholinv_max_n())
 // with L^-1, in one cooperative launch: L (may be G itself) receives the

@@ -652,16 +652,25 @@ bool eigh_blocks(tdvp_ctx_s* ctx, const void* H, int n, const int* didx, const s
     (void)hipGetLastError();
     return false;
   }
+  // the tridiagonal problems: the own divide and conquer for all blocks it
+  // takes (one launch per stage), rocSOLVER's for the larger ones
+  std::vector<kern::TdEigJob> jobs;
   for (int b = 0; b < B; ++b) {
     const int m = nbv[b];
     double* Z = reinterpret_cast<double*>(base + oZ[b]);
     double* E = reinterpret_cast<double*>(base + oE[b]);
-    if (kern::tridiag_eig_scratch_bytes(m) == 0) {
+    if (kern::tridiag_eig_scratch_bytes(m) == 0)
       blas_check(rocsolver_dstedc(ctx->blas, rocblas_evect_tridiagonal, m, dD + oDv[b], E, Z, m, dinfo + b), "dstedc");
-    } else if (kern::tridiag_eig(s, dD + oDv[b], E, m, Z, base + oS[b]) != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
-    }
+    else
+      jobs.push_back(kern::TdEigJob{dD + oDv[b], E, m, Z, base + oS[b]});
+  }
+  if (!jobs.empty() && kern::tridiag_eig_batched(s, jobs.data(), (int)jobs.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  for (int b = 0; b < B; ++b) {
+    const int m = nbv[b];
+    double* Z = reinterpret_cast<double*>(base + oZ[b]);
     rz* X = reinterpret_cast<rz*>(base + oX[b]);
     rz* R = reinterpret_cast<rz*>(base + oR[b]);
     kern::zrows_from_real_desc(s, X, Z, m);

@@ -30,6 +30,9 @@
 // on another workgroup.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 #include "wave.h"
 
@@ -67,6 +70,57 @@ struct DcArgs {
   double* par;              // per node: sign of the coupling, rho = 2 |coupling|
 };
 
+// Several independent tridiagonal problems (the charge blocks of one
+// block-diagonal matrix) run side by side: every launch takes the arguments
+// of up to DC_BMAX problems and finds its own in blockIdx.y (blockIdx.z for
+// the tiled product); the grid is sized for the largest problem and the
+// workgroups past a smaller problem's extent return at once.
+constexpr int DC_BMAX = 16;
+struct DcBatch {
+  int n;            // problems in the launch
+  int nodes_max;    // tiled product: z extent per problem
+  DcArgs a[DC_BMAX];
+};
+struct DcInit {
+  const double* D;
+  const double* E;
+  int n, P;
+  double* d;
+  double* Ep;
+  double* Z;
+  double* scale;
+};
+struct DcInitBatch {
+  int n;
+  DcInit b[DC_BMAX];
+};
+struct DcLeaf {
+  double* dg;
+  const double* E;
+  double* Z;
+  int P, S0;
+};
+struct DcLeafBatch {
+  int n;
+  DcLeaf b[DC_BMAX];
+};
+struct DcFinish {
+  const double* d;
+  const double* Z;
+  const double* scale;
+  int n, P;
+  double* D;
+  double* Zout;
+};
+struct DcFinishBatch {
+  int n;
+  DcFinish b[DC_BMAX];
+};
+// kernel arguments are limited to 4 KiB
+static_assert(sizeof(DcBatch) <= 4096 && sizeof(DcInitBatch) <= 4096 && sizeof(DcLeafBatch) <= 4096 &&
+                  sizeof(DcFinishBatch) <= 4096,
+              "batched divide-and-conquer arguments too large");
+
 // whole-wave reductions (every lane gets the result; all 64 lanes active)
 __device__ inline double wave_sum(double v) { return wave::sum(v); }
 __device__ inline double wave_prod(double v) { return wave::prod(v); }
@@ -76,9 +130,16 @@ __device__ inline double wave_max(double v) { return wave::max(v); }
 // Scaled, torn, padded diagonal (the leaves' eigenvalues), couplings and
 // Z = I.  Every workgroup finds the same scale (the same reduction order);
 // workgroup 0 writes the vectors, all share the rows of Z.
-__global__ __launch_bounds__(1024) void dc_init_kernel(const double* __restrict__ D, const double* __restrict__ E,
-                                                       int n, int P, double* __restrict__ d, double* __restrict__ Ep,
-                                                       double* __restrict__ Z, double* __restrict__ scale_out) {
+__global__ __launch_bounds__(1024) void dc_init_kernel(const DcInitBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcInit ar = bt.b[blockIdx.y];
+  const double* __restrict__ D = ar.D;
+  const double* __restrict__ E = ar.E;
+  const int n = ar.n, P = ar.P;
+  double* __restrict__ d = ar.d;
+  double* __restrict__ Ep = ar.Ep;
+  double* __restrict__ Z = ar.Z;
+  double* __restrict__ scale_out = ar.scale;
   __shared__ double red[2][16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double md = 0.0, me = 0.0;
@@ -120,7 +181,10 @@ __global__ __launch_bounds__(1024) void dc_init_kernel(const double* __restrict_
 // sorted children, deflation: small z entries in parallel, then one thread
 // walks the remaining entries in sorted order (the pair tests precomputed,
 // recomputed only after a rotation changed the left entry).
-__global__ __launch_bounds__(DC_PREP_NT) void dc_prep_kernel(DcArgs a) {
+__global__ __launch_bounds__(DC_PREP_NT) void dc_prep_kernel(const DcBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcArgs a = bt.a[blockIdx.y];
+  if ((int)blockIdx.x * a.s >= a.P) return;   // past this problem's nodes
   __shared__ double s_ds[DC_PMAX], s_zs[DC_PMAX];
   __shared__ int s_nd[DC_PMAX], s_inv[DC_PMAX];
   __shared__ double s_max[DC_PREP_NT / 64];
@@ -262,7 +326,9 @@ __global__ __launch_bounds__(DC_PREP_NT) void dc_prep_kernel(DcArgs a) {
 }
 
 // Secular roots, one wave per (node, root i < K).
-__global__ __launch_bounds__(DC_WNT) void dc_secular_kernel(DcArgs a) {
+__global__ __launch_bounds__(DC_WNT) void dc_secular_kernel(const DcBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcArgs a = bt.a[blockIdx.y];
   const int gw = (blockIdx.x * DC_WNT + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   const int s = a.s;
   const int b = gw / s, i = gw % s;
@@ -340,7 +406,9 @@ __global__ __launch_bounds__(DC_WNT) void dc_secular_kernel(DcArgs a) {
 
 // zhat_j (j < K) and the final column of sorted position j (all j < s), one
 // wave per (node, j).
-__global__ __launch_bounds__(DC_WNT) void dc_zhat_kernel(DcArgs a) {
+__global__ __launch_bounds__(DC_WNT) void dc_zhat_kernel(const DcBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcArgs a = bt.a[blockIdx.y];
   const int gw = (blockIdx.x * DC_WNT + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   const int s = a.s;
   const int b = gw / s, j = gw % s;
@@ -383,7 +451,9 @@ __global__ __launch_bounds__(DC_WNT) void dc_zhat_kernel(DcArgs a) {
 // (node, p): the secular eigenvector (or e_p when deflated) in the sorted
 // basis, the deflation rotations undone in reverse order, rows returned to the
 // children's order, stored at the final column.
-__global__ __launch_bounds__(DC_WNT) void dc_vectors_kernel(DcArgs a) {
+__global__ __launch_bounds__(DC_WNT) void dc_vectors_kernel(const DcBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcArgs a = bt.a[blockIdx.y];
   __shared__ double sy[DC_WNT / 64][DC_PMAX];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gw = (blockIdx.x * DC_WNT + threadIdx.x) >> 6;
@@ -434,7 +504,9 @@ __global__ __launch_bounds__(DC_WNT) void dc_vectors_kernel(DcArgs a) {
 // Zn[node] = blockdiag(Z1, Z2) M[node]: rows of the left child combine the
 // first s/2 rows of M, rows of the right child the last s/2.  Small nodes:
 // one thread per output entry.
-__global__ __launch_bounds__(256) void dc_gemm_small_kernel(DcArgs a) {
+__global__ __launch_bounds__(256) void dc_gemm_small_kernel(const DcBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcArgs a = bt.a[blockIdx.y];
   const int s = a.s, h = s / 2, P = a.P;
   const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (long long)P * s) return;
@@ -449,12 +521,16 @@ __global__ __launch_bounds__(256) void dc_gemm_small_kernel(DcArgs a) {
 
 // Nodes of 64 and more: 32 x 32 output tiles, 256 threads of 2 x 2 entries,
 // k in chunks of 32 through LDS.
-__global__ __launch_bounds__(256) void dc_gemm_tiled_kernel(DcArgs a) {
+__global__ __launch_bounds__(256) void dc_gemm_tiled_kernel(const DcBatch bt) {
   __shared__ double sa[32][33], sb[32][33];
+  // blockIdx.z = node + nodes_max * problem
+  const int pb = (int)blockIdx.z / bt.nodes_max;
+  if (pb >= bt.n) return;
+  const DcArgs a = bt.a[pb];
   const int s = a.s, h = s / 2, P = a.P;
   const int tiles = s / 32;
-  const int b = blockIdx.z, ti = blockIdx.y, tj = blockIdx.x;
-  if (ti >= tiles || tj >= tiles) return;
+  const int b = (int)blockIdx.z % bt.nodes_max, ti = blockIdx.y, tj = blockIdx.x;
+  if (ti >= tiles || tj >= tiles || b * s >= P) return;
   const int base = b * s;
   const int r0 = base + ti * 32, c0 = base + tj * 32;
   const int k0 = base + (ti * 32 < h ? 0 : h);
@@ -485,9 +561,15 @@ __global__ __launch_bounds__(256) void dc_gemm_tiled_kernel(DcArgs a) {
 }
 
 // D[j] = scale d[j], Zout (column-major n x n) = leading block of Z.
-__global__ void dc_finish_kernel(const double* __restrict__ d, const double* __restrict__ Z,
-                                 const double* __restrict__ scale, int n, int P, double* __restrict__ D,
-                                 double* __restrict__ Zout) {
+__global__ void dc_finish_kernel(const DcFinishBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcFinish ar = bt.b[blockIdx.y];
+  const double* __restrict__ d = ar.d;
+  const double* __restrict__ Z = ar.Z;
+  const double* __restrict__ scale = ar.scale;
+  const int n = ar.n, P = ar.P;
+  double* __restrict__ D = ar.D;
+  double* __restrict__ Zout = ar.Zout;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < n) D[idx] = d[idx] * *scale;
   if (idx >= (long long)n * n) return;
@@ -506,8 +588,14 @@ constexpr int DC_LEAF = 16;
 constexpr int DC_LNT = 256;
 static_assert(DC_LNT >= DC_LEAF * 2, "leaf kernel thread count");
 
-__global__ __launch_bounds__(DC_LNT) void dc_leaf_kernel(double* __restrict__ dg, const double* __restrict__ E,
-                                                         double* __restrict__ Z, int P, int S0) {
+__global__ __launch_bounds__(DC_LNT) void dc_leaf_kernel(const DcLeafBatch bt) {
+  if ((int)blockIdx.y >= bt.n) return;
+  const DcLeaf ar = bt.b[blockIdx.y];
+  double* __restrict__ dg = ar.dg;
+  const double* __restrict__ E = ar.E;
+  double* __restrict__ Z = ar.Z;
+  const int P = ar.P, S0 = ar.S0;
+  if ((int)blockIdx.x * S0 >= P) return;   // past this problem's leaves
   __shared__ double sZ[DC_LEAF][DC_LEAF + 1], sZn[DC_LEAF][DC_LEAF + 1], sM[DC_LEAF][DC_LEAF + 1];
   __shared__ double sY[DC_LEAF][DC_LEAF + 1];
   __shared__ double sd[DC_LEAF], sdn[DC_LEAF], s_ds[DC_LEAF], s_zs[DC_LEAF], s_dk[DC_LEAF], s_zk[DC_LEAF];
@@ -760,29 +848,49 @@ size_t tridiag_eig_scratch_bytes(int n) {
   return sizeof(double) * (3 * P * P + 14 * P + 8) + sizeof(int) * (11 * P) + 32 * 256;
 }
 
-hipError_t tridiag_eig(hipStream_t st, double* D, const double* E, int n, double* Z, void* scratch) {
-  if (n < 1 || n > DC_PMAX || !scratch) return hipErrorInvalidValue;
-  const int P = dc_pad(n);
+namespace {
+
+// one problem's buffers, carved out of its scratch
+struct DcPlan {
+  int n = 0, P = 0, S0 = 0;
+  double* D = nullptr;
+  const double* E = nullptr;
+  double* Zout = nullptr;
+  double *Z0 = nullptr, *Z1 = nullptr, *dA = nullptr, *dB = nullptr, *Ep = nullptr, *scale = nullptr;
+  DcArgs a{};   // the level-independent fields
+  // current and next eigenvalue / eigenvector buffers (swapped per level)
+  double *dc = nullptr, *dn = nullptr, *zc = nullptr, *zn = nullptr;
+};
+
+DcPlan dc_plan(double* D, const double* E, int n, double* Z, void* scratch) {
+  DcPlan q;
+  q.n = n;
+  q.P = dc_pad(n);
+  q.S0 = std::min(DC_LEAF, q.P);
+  q.D = D;
+  q.E = E;
+  q.Zout = Z;
+  const int P = q.P;
   char* p = static_cast<char*>(scratch);
   auto take_d = [&](size_t count) {
-    double* q = reinterpret_cast<double*>(p);
+    double* r = reinterpret_cast<double*>(p);
     p += (count * sizeof(double) + 255) / 256 * 256;
-    return q;
+    return r;
   };
   auto take_i = [&](size_t count) {
-    int* q = reinterpret_cast<int*>(p);
+    int* r = reinterpret_cast<int*>(p);
     p += (count * sizeof(int) + 255) / 256 * 256;
-    return q;
+    return r;
   };
   const size_t PP = (size_t)P * P;
-  double* Z0 = take_d(PP);
-  double* Z1 = take_d(PP);
-  DcArgs a{};
+  q.Z0 = take_d(PP);
+  q.Z1 = take_d(PP);
+  DcArgs& a = q.a;
   a.P = P;
   a.M = take_d(PP);
-  double* dA = take_d(P);
-  double* dB = take_d(P);
-  double* Ep = take_d(P);
+  q.dA = take_d(P);
+  q.dB = take_d(P);
+  q.Ep = take_d(P);
   a.ds = take_d(P);
   a.dk = take_d(P);
   a.zk = take_d(P);
@@ -791,7 +899,7 @@ hipError_t tridiag_eig(hipStream_t st, double* D, const double* E, int n, double
   a.tau = take_d(P);
   a.zhat = take_d(P);
   a.par = take_d(2 * (size_t)P);
-  double* scale = take_d(8);
+  q.scale = take_d(8);
   a.perm = take_i(P);
   a.ndinv = take_i(P);
   a.nd = take_i(P);
@@ -800,40 +908,105 @@ hipError_t tridiag_eig(hipStream_t st, double* D, const double* E, int n, double
   a.orig = take_i(P);
   a.colpos = take_i(P);
   a.cnt = take_i(2 * (size_t)P);
-  a.E = Ep;
-  const int init_blocks = std::max(1, std::min(64, P * P / 4096));
-  hipLaunchKernelGGL(dc_init_kernel, dim3(init_blocks), dim3(1024), 0, st, D, E, n, P, dA, Ep, Z0, scale);
-  double* zc = Z0;
-  double* zn = Z1;
-  double* dc = dA;
-  double* dn = dB;
-  const int S0 = std::min(DC_LEAF, P);
-  if (P >= 2) hipLaunchKernelGGL(dc_leaf_kernel, dim3(P / S0), dim3(DC_LNT), 0, st, dA, Ep, Z0, P, S0);
-  for (int s = 2 * S0; s <= P; s *= 2) {
-    a.s = s;
-    a.d = dc;
-    a.dnew = dn;
-    a.Zo = zc;
-    a.Zn = zn;
-    const int nodes = P / s;
-    const int wblocks = (P * 64 + DC_WNT - 1) / DC_WNT;   // one wave per index of every node
-    hipLaunchKernelGGL(dc_prep_kernel, dim3(nodes), dim3(DC_PREP_NT), 0, st, a);
-    hipLaunchKernelGGL(dc_secular_kernel, dim3(wblocks), dim3(DC_WNT), 0, st, a);
-    hipLaunchKernelGGL(dc_zhat_kernel, dim3(wblocks), dim3(DC_WNT), 0, st, a);
-    hipLaunchKernelGGL(dc_vectors_kernel, dim3(wblocks), dim3(DC_WNT), 0, st, a);
-    if (s < 64) {
-      const long long tot = (long long)P * s;
-      hipLaunchKernelGGL(dc_gemm_small_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
-    } else {
-      hipLaunchKernelGGL(dc_gemm_tiled_kernel, dim3(s / 32, s / 32, nodes), dim3(256), 0, st, a);
-    }
-    std::swap(zc, zn);
-    std::swap(dc, dn);
+  a.E = q.Ep;
+  q.zc = q.Z0;
+  q.zn = q.Z1;
+  q.dc = q.dA;
+  q.dn = q.dB;
+  return q;
+}
+
+// up to DC_BMAX problems side by side
+void dc_run_group(hipStream_t st, std::vector<DcPlan>& pl) {
+  const int nb = (int)pl.size();
+  // set-up: scaled, torn, padded diagonals and Z = I
+  DcInitBatch ib{};
+  ib.n = nb;
+  int init_x = 1;
+  for (int j = 0; j < nb; ++j) {
+    const DcPlan& q = pl[j];
+    ib.b[j] = DcInit{q.D, q.E, q.n, q.P, q.dA, q.Ep, q.Z0, q.scale};
+    init_x = std::max(init_x, std::max(1, std::min(64, q.P * q.P / 4096)));
   }
-  const long long tot = std::max<long long>((long long)n * n, n);
-  hipLaunchKernelGGL(dc_finish_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, dc, zc, scale, n, P,
-                     D, Z);
+  hipLaunchKernelGGL(dc_init_kernel, dim3(init_x, nb), dim3(1024), 0, st, ib);
+  // the levels of up to DC_LEAF entries in one launch
+  DcLeafBatch lb{};
+  int leaf_x = 0;
+  for (const DcPlan& q : pl) {
+    if (q.P < 2) continue;
+    lb.b[lb.n++] = DcLeaf{q.dA, q.Ep, q.Z0, q.P, q.S0};
+    leaf_x = std::max(leaf_x, q.P / q.S0);
+  }
+  if (lb.n > 0) hipLaunchKernelGGL(dc_leaf_kernel, dim3(leaf_x, lb.n), dim3(DC_LNT), 0, st, lb);
+  // larger levels: the problems whose padded size reaches s, in lock step
+  int maxP = 0;
+  for (const DcPlan& q : pl) maxP = std::max(maxP, q.P);
+  for (int s = 2 * DC_LEAF; s <= maxP; s *= 2) {
+    DcBatch bt{};
+    std::vector<int> act;
+    int pmax = 0;
+    for (int j = 0; j < nb; ++j) {
+      DcPlan& q = pl[j];
+      if (q.S0 != DC_LEAF || q.P < s) continue;
+      DcArgs a = q.a;
+      a.s = s;
+      a.d = q.dc;
+      a.dnew = q.dn;
+      a.Zo = q.zc;
+      a.Zn = q.zn;
+      bt.a[bt.n++] = a;
+      act.push_back(j);
+      pmax = std::max(pmax, q.P);
+    }
+    if (bt.n == 0) continue;
+    const int nodes_max = pmax / s;
+    bt.nodes_max = nodes_max;
+    const int wblocks = (pmax * 64 + DC_WNT - 1) / DC_WNT;   // one wave per index of every node
+    hipLaunchKernelGGL(dc_prep_kernel, dim3(nodes_max, bt.n), dim3(DC_PREP_NT), 0, st, bt);
+    hipLaunchKernelGGL(dc_secular_kernel, dim3(wblocks, bt.n), dim3(DC_WNT), 0, st, bt);
+    hipLaunchKernelGGL(dc_zhat_kernel, dim3(wblocks, bt.n), dim3(DC_WNT), 0, st, bt);
+    hipLaunchKernelGGL(dc_vectors_kernel, dim3(wblocks, bt.n), dim3(DC_WNT), 0, st, bt);
+    if (s < 64) {
+      const long long tot = (long long)pmax * s;
+      hipLaunchKernelGGL(dc_gemm_small_kernel, dim3((unsigned)((tot + 255) / 256), bt.n), dim3(256), 0, st, bt);
+    } else {
+      hipLaunchKernelGGL(dc_gemm_tiled_kernel, dim3(s / 32, s / 32, nodes_max * bt.n), dim3(256), 0, st, bt);
+    }
+    for (int j : act) {
+      std::swap(pl[j].zc, pl[j].zn);
+      std::swap(pl[j].dc, pl[j].dn);
+    }
+  }
+  // eigenvalues unscaled, eigenvectors column-major
+  DcFinishBatch fb{};
+  fb.n = nb;
+  long long fmax = 1;
+  for (int j = 0; j < nb; ++j) {
+    const DcPlan& q = pl[j];
+    fb.b[j] = DcFinish{q.dc, q.zc, q.scale, q.n, q.P, q.D, q.Zout};
+    fmax = std::max(fmax, std::max<long long>((long long)q.n * q.n, q.n));
+  }
+  hipLaunchKernelGGL(dc_finish_kernel, dim3((unsigned)((fmax + 255) / 256), nb), dim3(256), 0, st, fb);
+}
+
+}  // namespace
+
+hipError_t tridiag_eig_batched(hipStream_t st, const TdEigJob* jobs, int n_jobs) {
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return hipErrorInvalidValue;
+  for (int j = 0; j < n_jobs; ++j)
+    if (jobs[j].n < 1 || jobs[j].n > DC_PMAX || !jobs[j].scratch) return hipErrorInvalidValue;
+  for (int g = 0; g < n_jobs; g += DC_BMAX) {
+    std::vector<DcPlan> pl;
+    for (int j = g; j < std::min(n_jobs, g + DC_BMAX); ++j)
+      pl.push_back(dc_plan(jobs[j].D, jobs[j].E, jobs[j].n, jobs[j].Z, jobs[j].scratch));
+    dc_run_group(st, pl);
+  }
   return hipGetLastError();
+}
+
+hipError_t tridiag_eig(hipStream_t st, double* D, const double* E, int n, double* Z, void* scratch) {
+  const TdEigJob job{D, E, n, Z, scratch};
+  return tridiag_eig_batched(st, &job, 1);
 }
 
 }  // namespace kern
