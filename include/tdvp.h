@@ -394,6 +394,23 @@ tdvp_status tdvp_env_right(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int m
  * and conquer (TDVP_ERR_NUMERIC when not applicable).  Synchronous. */
 tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows, double* lam);
 
+/* Eigendecomposition of a Hermitian matrix that is block diagonal under U(1)
+ * index charges, as the charged states' gauge moves, density matrices and
+ * the state-averaged mixed density matrix of section I.A need it (every
+ * kept state with a definite charge): H[i][j] = 0 unless charges[i] ==
+ * charges[j] (the indices of one charge need not be contiguous); each
+ * block is decomposed on its own (all blocks of 2 .. 512 indices side by
+ * side, larger ones by rocSOLVER's tridiagonal divide and conquer up to
+ * 1024, zheevd above).  H: device complex128 n x n row-major; charges: host
+ * int32[n]; rows: device complex128 n x n out, row j the conjugated
+ * eigenvector (zero outside its block); lam: host double[n] out, descending
+ * over all blocks (ties: lower charge first); charges_out: host int32[n]
+ * out, the charge of eigenvector j.  Synchronous.  Errors: TDVP_ERR_ARG for
+ * n < 1 or NULL pointers, TDVP_ERR_NUMERIC when a block's decomposition
+ * fails its checks on every route. */
+tdvp_status tdvp_eigh_sectors(tdvp_ctx ctx, int n, const void* H, const int32_t* charges, void* rows,
+                              double* lam, int32_t* charges_out);
+
 /* Cholesky factorisation with the inverse of the factor, as used by the gauge
  * moves (the orthonormal centre moves of eq. (3) and of the sweep, section
  * I.C item 3: the Cholesky-QR steps and the test that a truncation has

@@ -705,6 +705,24 @@ tdvp_status tdvp_eigh(tdvp_ctx ctx, int method, int n, const void* H, void* rows
   });
 }
 
+tdvp_status tdvp_eigh_sectors(tdvp_ctx ctx, int n, const void* H, const int32_t* charges, void* rows,
+                              double* lam, int32_t* charges_out) {
+  if (!ctx) return TDVP_ERR_ARG;
+  return guarded(ctx, [&] {
+    ARG_CHECK(n >= 1 && H && charges && rows && lam && charges_out, "bad arguments");
+    bind(ctx);
+    kern::SplitWorkspaceScope gws(ctx->split_workspace(), tdvp_ctx_s::SPLIT_WS_BYTES);
+    DBuf work(ctx);
+    const std::vector<int> q(charges, charges + n);
+    std::vector<double> w;
+    std::vector<int> qo;
+    la::eigh_sectors(ctx, H, n, q, w, rows, work, qo);
+    std::copy(w.begin(), w.end(), lam);
+    std::copy(qo.begin(), qo.end(), charges_out);
+    ctx->sync();
+  });
+}
+
 tdvp_status tdvp_cholesky(tdvp_ctx ctx, int n, const void* G, void* L, void* Linv, int* info) {
   if (!ctx) return TDVP_ERR_ARG;
   return guarded(ctx, [&] {

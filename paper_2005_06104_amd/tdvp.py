@@ -122,6 +122,7 @@ def load():
         "tdvp_env_left": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
         "tdvp_env_right": (i, [vp, i, i, i, i, i, C.POINTER(d), vp, vp, vp, vp]),
         "tdvp_eigh": (i, [vp, i, i, vp, vp, C.POINTER(d)]),
+        "tdvp_eigh_sectors": (i, [vp, i, vp, C.POINTER(C.c_int32), vp, C.POINTER(d), C.POINTER(C.c_int32)]),
         "tdvp_cholesky": (i, [vp, i, vp, vp, vp, C.POINTER(C.c_int)]),
         "tdvp_squeezing_xi2": (i, [i, d, d, d, d, d, d, C.POINTER(d)]),
     }
@@ -549,6 +550,21 @@ def tdvp_eigh(ctx: Context, H, rows, method: int = 0) -> np.ndarray:
     lam = np.zeros(n)
     ctx.check(ctx.lib.tdvp_eigh(ctx.h, int(method), n, _tp(H), _tp(rows), _dptr(lam)), "tdvp_eigh")
     return lam
+
+
+def tdvp_eigh_sectors(ctx: Context, H, charges, rows):
+    """Eigendecomposition of the complex128 device matrix H, block diagonal
+    under the index charges: fills rows (row j = v_j^dagger, zero outside its
+    block) and returns (eigenvalues descending, charge of each eigenvector)."""
+    n = H.shape[0]
+    q = np.ascontiguousarray(charges, dtype=np.int32)
+    if q.shape != (n,):
+        raise ValueError("one charge per index")
+    lam = np.zeros(n)
+    qo = np.zeros(n, dtype=np.int32)
+    ctx.check(ctx.lib.tdvp_eigh_sectors(ctx.h, n, _tp(H), q.ctypes.data_as(C.POINTER(C.c_int32)), _tp(rows),
+                                        _dptr(lam), qo.ctypes.data_as(C.POINTER(C.c_int32))), "tdvp_eigh_sectors")
+    return lam, qo
 
 
 def tdvp_cholesky(ctx: Context, G, L, Linv) -> int:

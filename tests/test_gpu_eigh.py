@@ -136,3 +136,42 @@ def test_eigh_routes_agree_on_subspaces(env):
     for k in (10, 50):
         P = [r[:k].conj().T @ r[:k] for _, r in out]
         assert np.abs(P[0] - P[1]).max() < 1e-9
+
+
+def test_eigh_sectors_many_uneven_blocks(env):
+    # block diagonal under scattered index charges: 1 x 1 blocks (three with
+    # equal values, whose order follows the charges), more than 16 blocks for
+    # the side-by-side divide and conquer (several launches), and one block
+    # above 512 (rocSOLVER's tridiagonal route); every spectrum kind above
+    T, torch, ctx = env
+    sizes = [1, 1, 1, 2, 3, 5, 15, 16, 17, 31, 32, 33, 47, 64, 65, 100, 128, 129, 200, 257, 512, 600]
+    kinds = sorted(CASES)
+    rng = np.random.default_rng(77)
+    n = sum(sizes)
+    charge_of_block = 2 * np.arange(len(sizes)) - len(sizes)
+    q = np.repeat(charge_of_block, sizes)[rng.permutation(n)]
+    H = np.zeros((n, n), complex)
+    ref = []
+    for b, (c, m) in enumerate(zip(charge_of_block, sizes)):
+        idx = np.flatnonzero(q == c)
+        B = CASES[kinds[b % len(kinds)]](m, 500 + b) if m > 1 else np.array([[0.25 + 0j]])
+        H[np.ix_(idx, idx)] = B
+        ref.append(np.linalg.eigvalsh(B))
+    ref = np.sort(np.concatenate(ref))[::-1]
+    dH = torch.from_numpy(H).cuda()
+    rows = torch.zeros_like(dH)
+    lam, qo = T.tdvp_eigh_sectors(ctx, dH, q, rows)
+    V = rows.cpu().numpy()
+    scale = np.abs(ref).max()
+    tol = (1e-14 * max(sizes) + 1e-13) * scale
+    assert np.all(np.diff(lam) <= 0)
+    assert np.abs(lam - ref).max() <= tol
+    # each eigenvector lies in the block of its charge, exactly
+    for c, m in zip(charge_of_block, sizes):
+        assert int((qo == c).sum()) == m
+    assert np.all(V[q[None, :] != qo[:, None]] == 0)
+    # equal eigenvalues of different charges: lower charge first
+    tie = np.flatnonzero(lam == 0.25)
+    assert len(tie) >= 3 and np.all(np.diff(qo[tie]) > 0)
+    assert np.abs(V @ V.conj().T - np.eye(n)).max() <= 1e-14 * max(sizes) + 1e-13
+    assert np.abs((V.conj().T * lam) @ V - H).max() <= tol
