@@ -293,8 +293,8 @@ def test_context_close_before_handles():
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
 @pytest.mark.parametrize("opa,opb", [(0, 0), (2, 0), (0, 2), (1, 3)])
 def test_gemm_bf16_large_tiles(env, prec, opa, opb):
-    # products with >= 256 tiles of 128 x 128 take the large-tile kernel;
-    # ragged in every dimension
+    # a product of a few thousand 64 x 64 output tiles, ragged in every
+    # dimension and with K not a multiple of the 32-wide K step
     T, torch, ctx = env
     M, N, K = 2048 + 17, 2048 + 3, 200
     rng = np.random.default_rng(900 + 4 * opa + opb)
