@@ -343,6 +343,23 @@ tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int 
                             const double* W_host, const void* L, const void* Rt, const void* C,
                             void* Y, void* workspace);
 
+/* tdvp_heff_apply for tensors that carry U(1) S^z charges (the block-sparse
+ * products a charged sweep issues): charges_l[ml] on the bond of a and a',
+ * charges_r[mr] on the bond of b and b', channel charges qw_l[wl] and
+ * qw_r[wr] of the MPO bonds (host int32 arrays; physical charge +1 for s = 0,
+ * -1 for s = 1).  Nonzero entries are allowed only where L[a',al,a] has
+ * q(a) = q(a') - q_w(al), C[a,s,b] has q(b) = q(a) + q(s), Rt[be,b,b'] has
+ * q(b) = q(b') - q_w(be) and W[al,be,s',s] has q(s) - q_w(al) = q(s') -
+ * q_w(be); L, C and Rt must hold zeros elsewhere (the products read some of
+ * those entries where the blocks' K ranges are joined).  Y is written in
+ * full, zeros outside its blocks.  The products walk the nonzero blocks
+ * only and the sparse-MPO stage reads by charge.  Workspace allocated
+ * internally; synchronous.  Errors: TDVP_ERR_ARG as tdvp_heff_apply, for
+ * NULL charge arrays, or for a nonzero W entry that breaks the rule above. */
+tdvp_status tdvp_heff_apply_u1(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
+                               const int32_t* charges_l, const int32_t* charges_r, const int32_t* qw_l,
+                               const int32_t* qw_r, const void* L, const void* Rt, const void* C, void* Y);
+
 /* tdvp_heff_apply for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same kernels on the same operands, with every piece of

@@ -750,6 +750,37 @@ tdvp_status tdvp_heff_apply(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int 
   });
 }
 
+tdvp_status tdvp_heff_apply_u1(tdvp_ctx ctx, int prec, int ml, int wl, int wr, int mr, const double* W_host,
+                               const int32_t* charges_l, const int32_t* charges_r, const int32_t* qw_l,
+                               const int32_t* qw_r, const void* L, const void* Rt, const void* C, void* Y) {
+  if (!W_host || !charges_l || !charges_r || !qw_l || !qw_r) return TDVP_ERR_ARG;
+  return kernel_call(ctx, prec, ml, wl, wr, mr, W_host, nullptr,
+                     [&](const SiteTables& tb, void* w1, void* w2, SplitWS sk) {
+    const std::vector<int> ql(charges_l, charges_l + ml), qr(charges_r, charges_r + mr);
+    const std::vector<int> qwl(qw_l, qw_l + wl), qwr(qw_r, qw_r + wr);
+    for (int a = 0; a < wl; ++a)
+      for (int b = 0; b < wr; ++b)
+        for (int sp = 0; sp < 2; ++sp)
+          for (int sk2 = 0; sk2 < 2; ++sk2) {
+            const size_t e = ((((size_t)a * wr + b) * 2 + sp) * 2 + sk2) * 2;
+            if (W_host[e] == 0.0 && W_host[e + 1] == 0.0) continue;
+            ARG_CHECK(phys_charge(sk2) - qwl[a] == phys_charge(sp) - qwr[b], "W entry breaks the channel charges");
+          }
+    MapCache& mc = map_cache(ctx);
+    const MapEntry& e1 = cmap_env_gemm1_nz(mc, ql, ql, qwl, qr);
+    const MapEntry& e2 = cmap_heff_gemm2(mc, ql, qr, qwr, qr);
+    const kern::KMap g1 = mc.use(e1), g2 = mc.use(e2);
+    ProdMaps pm{&g1, &g2, e1.exact_flops + e2.exact_flops};
+    kern::WCharges wc = wc_of(cmap_wstage(mc, ql, qr, qwl, qwr), ml, mr, wl);
+    // the stage stores only the outputs allowed by charge into cleared memory
+    kern::zfill(ctx->stream, w2, zc(0.0, 0.0), 2LL * ml * wr * mr, prec == TDVP_FP64 ? 16 : 8);
+    wc.zeros_kept = 1;
+    pm.wc = &wc;
+    if (prec == TDVP_FP64) heff_apply<double>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2, nullptr, sk, pm);
+    else heff_apply<float>(ctx, tb, ml, wl, wr, mr, L, Rt, C, Y, w1, w2, nullptr, sk, pm);
+  });
+}
+
 tdvp_status tdvp_keff_apply(tdvp_ctx ctx, int prec, int ml, int w, int mr, const void* L, const void* Rt,
                             const void* X, void* Y, void* workspace) {
   return kernel_call(ctx, prec, ml, w, w, mr, nullptr, workspace, [&](const SiteTables&, void* w1, void*, SplitWS sk) {

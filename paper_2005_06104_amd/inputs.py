@@ -320,6 +320,34 @@ def random_hermitian_env(m: int, w: int, seed: int, bra_first: bool = True) -> n
     return 0.5 * (e + np.conj(np.transpose(e, (2, 1, 0))))
 
 
+def charged_bond(sectors) -> np.ndarray:
+    """Bond charges in ascending order from {charge: number of states}."""
+    return np.repeat(np.array(sorted(sectors), dtype=np.int32), [sectors[c] for c in sorted(sectors)])
+
+
+def random_charged_heff_operands(ql, qr, qwl, qwr, seed: int):
+    """Seeded operands of a one-site effective Hamiltonian on charged bonds
+    (bond charges ql of a, a'; qr of b, b'; MPO channel charges qwl, qwr;
+    physical charge +1 for s = 0, -1 for s = 1): L[a', al, a], R[b', be, b]
+    and C[a, s, b] with complex Gaussian entries where the charges allow them
+    (L: q(a) = q(a') - qw(al); R: q(b) = q(b') - qw(be); C: q(b) = q(a) + q(s))
+    and exact zeros elsewhere."""
+    ql, qr, qwl, qwr = (np.asarray(x) for x in (ql, qr, qwl, qwr))
+    ps = np.array([1, -1])
+    rng = np.random.default_rng(seed)
+
+    def gauss(shape):
+        return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+    L = gauss((len(ql), len(qwl), len(ql)))
+    L[ql[None, None, :] != ql[:, None, None] - qwl[None, :, None]] = 0.0
+    R = gauss((len(qr), len(qwr), len(qr)))
+    R[qr[None, None, :] != qr[:, None, None] - qwr[None, :, None]] = 0.0
+    C = gauss((len(ql), 2, len(qr)))
+    C[qr[None, None, :] != ql[:, None, None] + ps[None, :, None]] = 0.0
+    return L, R, C
+
+
 def random_mpo_site(wl: int, wr: int, seed: int, density: float = 0.3) -> np.ndarray:
     """Random sparse MPO tensor W[alpha, beta, s', s] (about `density` nonzeros)."""
     rng = np.random.default_rng(seed)

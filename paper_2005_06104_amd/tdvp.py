@@ -590,6 +590,25 @@ def tdvp_heff_apply(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, workspace=None, 
                                       _tp(workspace)), "tdvp_heff_apply")
 
 
+def tdvp_heff_apply_u1(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, ql, qr, qwl, qwr, prec: Optional[str] = None):
+    """tdvp_heff_apply on charged tensors: bond charges ql (of a, a'), qr (of
+    b, b'), MPO channel charges qwl, qwr; the products walk the nonzero
+    blocks only."""
+    ml, wl, _ = L.shape
+    wr, mr, _ = Rt.shape
+    Wc, wp = _w_host(W)
+    arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in (ql, qr, qwl, qwr)]
+    if [a.shape for a in arrs] != [(ml,), (mr,), (wl,), (wr,)]:
+        raise ValueError("charge arrays do not match the tensor shapes")
+    ip = [a.ctypes.data_as(C.POINTER(C.c_int32)) for a in arrs]
+    fn = ctx.lib.tdvp_heff_apply_u1
+    fn.restype = C.c_int
+    fn.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)] + \
+        [C.POINTER(C.c_int32)] * 4 + [C.c_void_p] * 4
+    ctx.check(fn(ctx.h, _prec_of(L, prec), ml, wl, wr, mr, wp, *ip, _tp(L), _tp(Rt), _tp(Cin), _tp(Y)),
+              "tdvp_heff_apply_u1")
+
+
 def tdvp_heff_apply_noalloc(ctx: Context, W: np.ndarray, L, Rt, Cin, Y, prec: Optional[str] = None):
     ml, wl, _ = L.shape
     wr, mr, _ = Rt.shape
