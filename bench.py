@@ -121,8 +121,10 @@ def traffic_from_profile(name: str, sources):
         return None
 
 
-def run_workload(T, ctx, w, prec, warmup, steps, label):
-    """Evolve the workload from its seeded initial state; time `steps` steps after `warmup`."""
+def run_workload(T, ctx, w, prec, warmup, steps, label, mark=False):
+    """Evolve the workload from its seeded initial state; time `steps` steps
+    after `warmup` (mark: marker kernels right before and after the timed
+    steps, for cutting a kernel trace)."""
     import torch
     N = w.lattice.n_sites
     H = T.tdvp_create_mpo(ctx, N, w.terms)
@@ -142,6 +144,9 @@ def run_workload(T, ctx, w, prec, warmup, steps, label):
         log(f"[{label}] warmup {i}: {1e3 * (time.perf_counter() - t):.1f} ms, max bond {max(m['bond_dims'])}, "
             f"E={m['energy']:.10f}, matvecs {s['n_matvec']}")
     torch.cuda.synchronize()
+    if mark:
+        torch.cuda._sleep(1000)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     acc = {"ms_heff_gemm": 0.0, "flops_heff_gemm": 0.0, "n_heff_gemm": 0, "ms_matvec": 0.0, "flops_matvec": 0.0,
            "n_matvec": 0, "ms_sweep": 0.0, "ms_krylov": 0.0, "ms_extend": 0.0}
@@ -157,6 +162,9 @@ def run_workload(T, ctx, w, prec, warmup, steps, label):
             f"extend {e['ms_extend']:.1f}, sweep {s['ms']:.1f}), max bond {max(m['bond_dims'])}, E={m['energy']:.10f}")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if mark:
+        torch.cuda._sleep(1000)
+        torch.cuda.synchronize()
     acc["elapsed"] = el
     acc["final"] = T.tdvp_measure(ctx, [psi], [H])[0]
     acc["H"], acc["op"], acc["psi"] = H, op, psi
@@ -699,9 +707,9 @@ def main():
     ap.add_argument("--no-fp64-ref", dest="fp64_ref", action="store_false",
                     help="cylinder: skip the FP64 reference run (no fidelity or speedup figures)")
     ap.add_argument("--mark-timed", action="store_true",
-                    help="cylinder: launch a short marker kernel (torch.cuda._sleep) right before and after "
-                         "the headline precision's timed steps, for cutting a kernel trace or counter file, "
-                         "and a plain 64 MiB device copy after them for calibrating the byte counters")
+                    help="launch a short marker kernel (torch.cuda._sleep) right before and after the "
+                         "headline precision's timed steps, for cutting a kernel trace or counter file (cylinder: "
+                         "and a plain 64 MiB device copy after them for calibrating the byte counters)")
     ap.add_argument("--no-compare-prec", dest="compare_prec", action="store_false",
                     help="skip the runs in the other precisions (mixed vs FP64)")
     ap.add_argument("--batch", action="store_true",
@@ -759,7 +767,7 @@ def main():
     N = w.lattice.n_sites
     ctx = T.Context(0)
     log(f"workload {w.name}: N={N}, chi_max={w.chi_max}, k={w.k}, dt={w.dt}, prec={prec}")
-    main_run = run_workload(T, ctx, w, prec, args.warmup, args.steps, prec)
+    main_run = run_workload(T, ctx, w, prec, args.warmup, args.steps, prec, mark=args.mark_timed)
     res = summarize(main_run, args.steps, prec)
     gemm_tf = res["heff_gemm_tflops"]
     peak = PEAK_TFLOPS[prec]

@@ -23,7 +23,7 @@ middle of each gap, and to the kernel that ran before it.
 With --counters the file is the counter output of a `rocprofv3 --pmc` run
 (one row per dispatch and counter): the dispatches between the first and
 the last marker dispatch whose name contains SUBSTRING are averaged per
-counter; --calib names a plain copy kernel of N bytes read and N written
+counter (--marker none: every dispatch of the file); --calib names a plain copy kernel of N bytes read and N written
 (anywhere in the file), whose FETCH_SIZE / WRITE_SIZE give the factors that
 turn those counters into bytes.
 """
@@ -192,10 +192,13 @@ def counters(path, kernel, marker="spin_kernel", calib=None, calib_bytes=None):
     for d, n, c, v in _counter_rows(path):
         per[d][c] += v
         names[d] = n
-    marks = sorted(d for d, n in names.items() if marker in n)
-    if len(marks) < 2:
-        raise SystemExit(f"fewer than two marker dispatches ({marker!r}) in {path}")
-    lo, hi = marks[0], marks[-1]
+    if marker:
+        marks = sorted(d for d, n in names.items() if marker in n)
+        if len(marks) < 2:
+            raise SystemExit(f"fewer than two marker dispatches ({marker!r}) in {path}")
+        lo, hi = marks[0], marks[-1]
+    else:   # no window: every dispatch of the file
+        lo, hi = min(names) - 1, max(names) + 1
     sel = [d for d, n in names.items() if lo < d < hi and kernel in n]
     if not sel:
         raise SystemExit(f"no dispatch of {kernel!r} between the markers in {path}")
@@ -232,7 +235,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.counters:
         import json
-        print(json.dumps(counters(a.trace, a.kernel, a.marker, a.calib, a.calib_bytes), indent=1))
+        marker = None if a.marker.lower() == "none" else a.marker
+        print(json.dumps(counters(a.trace, a.kernel, marker, a.calib, a.calib_bytes), indent=1))
         return
     print(summarize(a.trace, a.marker, a.split_grid, a.top, a.ranges))
 
