@@ -540,8 +540,9 @@ def cylinder_mode(args):
     reaches chi_max; from that state each precision runs W + K steps, the last
     K timed.  The headline mixed precision (default FP32 contractions; the
     Lanczos recurrences, factorisations and stored tensors stay FP64) and
-    BF16 inputs with FP32 accumulation are compared with FP64 on the same
-    steps: fidelity, energy and <S^z_i> differences of the final states."""
+    BF16 inputs with FP32 accumulation (split into two BF16 terms, and
+    plain) are compared with FP64 on the same steps: fidelity, energy and
+    <S^z_i> differences of the final states."""
     import torch
 
     from paper_2005_06104_amd import inputs as I
@@ -666,7 +667,7 @@ def cylinder_mode(args):
         rf = summarize(ref_run, args.steps, "fp64")
         out["speedup_vs_fp64"] = res["value"] / rf["value"]
         out["fp64"] = rf
-    others = args.compare.split(",") if args.compare else ["bf16"]
+    others = args.compare.split(",") if args.compare else ["bf16x3", "bf16"]
     for other in others if args.compare_prec else []:
         if other in (prec, "fp64") or other not in PEAK_TFLOPS:
             continue
