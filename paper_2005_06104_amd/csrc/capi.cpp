@@ -1,4 +1,5 @@
 // extern "C" entry points: argument checks, status codes, context plumbing.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -82,6 +83,7 @@ void tdvp_ctx_s::destroy_workers() {
   for (tdvp_ctx_s* w : workers) {
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     w->destroy_maps();
+    w->destroy_uploads();
     w->dfree(w->split_ws);
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     if (w->hstage) (void)hipHostFree(w->hstage);
@@ -104,6 +106,38 @@ void tdvp_ctx_s::destroy_workers() {
 }
 
 void tdvp_ctx_s::sync() { HIP_CHECK(hipStreamSynchronize(stream)); }
+
+void tdvp_ctx_s::upload_async(void* dev, const void* host, size_t bytes) {
+  if (bytes == 0) return;
+  const int k = up_pos;
+  up_pos = (up_pos + 1) % UP_SLOTS;
+  if (up_ev[k]) HIP_CHECK(hipEventSynchronize(up_ev[k]));
+  else HIP_CHECK(hipEventCreateWithFlags(&up_ev[k], hipEventDisableTiming));
+  if (up_cap[k] < bytes) {
+    if (up_buf[k]) HIP_CHECK(hipHostFree(up_buf[k]));
+    up_buf[k] = nullptr;
+    up_cap[k] = 0;
+    const size_t cap = std::max<size_t>(bytes + bytes / 2, 16384);
+    HIP_CHECK(hipHostMalloc(&up_buf[k], cap, hipHostMallocDefault));
+    up_cap[k] = cap;
+  }
+  std::memcpy(up_buf[k], host, bytes);
+  HIP_CHECK(hipMemcpyAsync(dev, up_buf[k], bytes, hipMemcpyHostToDevice, stream));
+  HIP_CHECK(hipEventRecord(up_ev[k], stream));
+}
+
+void tdvp_ctx_s::destroy_uploads() {
+  for (int k = 0; k < UP_SLOTS; ++k) {
+    if (up_ev[k]) {
+      (void)hipEventSynchronize(up_ev[k]);
+      (void)hipEventDestroy(up_ev[k]);
+      up_ev[k] = nullptr;
+    }
+    if (up_buf[k]) (void)hipHostFree(up_buf[k]);
+    up_buf[k] = nullptr;
+    up_cap[k] = 0;
+  }
+}
 
 void tdvp_ctx_s::ensure_hstage() {
   if (hstage) return;
@@ -316,6 +350,7 @@ void tdvp_ctx_destroy(tdvp_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   ctx->destroy_workers();
   ctx->destroy_maps();
+  ctx->destroy_uploads();
   ctx->dfree(ctx->split_ws);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->hstage) (void)hipHostFree(ctx->hstage);

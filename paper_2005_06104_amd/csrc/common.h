@@ -82,6 +82,18 @@ struct tdvp_ctx_s {
   void* stage_slot_dev(int k);
   const void* stage_mark(int k);
 
+  // Uploads of small host arrays without a stream sync: the bytes are copied
+  // into one of UP_SLOTS pinned buffers, which the stream then copies to the
+  // device; a slot is reused once the event of its previous copy completed.
+  // Released (after their copies) by destroy_uploads, before the stream goes.
+  static constexpr int UP_SLOTS = 16;
+  void* up_buf[UP_SLOTS] = {};
+  size_t up_cap[UP_SLOTS] = {};
+  hipEvent_t up_ev[UP_SLOTS] = {};
+  int up_pos = 0;
+  void upload_async(void* dev, const void* host, size_t bytes);
+  void destroy_uploads();
+
   void* dalloc(size_t bytes);
   void dfree(void* p);
   void sync();

@@ -587,9 +587,7 @@ Sectors group_by_charge(const std::vector<int>& q) {
 // host ints to the device (waits: `v` may be temporary)
 int* upload_ints(tdvp_ctx_s* ctx, DBuf& buf, const std::vector<int>& v) {
   buf.ensure(sizeof(int) * std::max<size_t>(1, v.size()));
-  if (!v.empty())
-    HIP_CHECK(hipMemcpyAsync(buf.p, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, ctx->stream));
-  HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  ctx->upload_async(buf.p, v.data(), sizeof(int) * v.size());   // staged: v may go at once
   return buf.as<int>();
 }
 
@@ -788,7 +786,8 @@ void eigh_sectors(tdvp_ctx_s* ctx, const void* H, int n, const std::vector<int>&
     lam[j] = lam_sec[perm[j]];
     qout[j] = sc.charge[sec_of[perm[j]]];
   }
-  HIP_CHECK(hipStreamSynchronize(s));   // the local buffers die here
+  // the local device buffers are released in stream order (the context's
+  // allocator reuses them only for later work on this stream), so no wait
 }
 
 void svd_sectors(tdvp_ctx_s* ctx, const void* C, int rows, int cols, const std::vector<int>& qrow,
