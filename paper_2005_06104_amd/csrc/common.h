@@ -263,6 +263,25 @@ size_t tridiag_eig_scratch_bytes(int n);
 hipError_t tridiag_eig(hipStream_t s, double* D, const double* E, int n, double* Z, void* scratch);
 // Several such problems (each n <= 512 with its own scratch) side by side:
 // one launch per stage for all of them (results as from tridiag_eig).
+// The charge blocks of one block-diagonal Hermitian n x n matrix, handled
+// side by side (one launch per step for all blocks): block b holds indices
+// idx[off .. off + m) of the matrix; X its m x m work matrix, Z the m x m
+// real eigenvectors (column-major, ascending) of its tridiagonal problem, R
+// its back-transformed rows.
+struct EigBlock {
+  double2* X;
+  const double* Z;
+  double2* R;
+  int off, m;
+};
+// X = (H_b + H_b^H) / 2 for every block
+void eig_blocks_gather(hipStream_t s, const EigBlock* blk, int nb, const void* H, long long n, const int* idx);
+// X = the rows of Z, descending (as zrows_from_real_desc)
+void eig_blocks_rows(hipStream_t s, const EigBlock* blk, int nb);
+// sums[b] = sum |R_b|^2 (complex128 slots, imaginary part zero)
+void eig_blocks_norms(hipStream_t s, const EigBlock* blk, int nb, void* sums);
+// rows[off + i][idx[off + j]] = R_b[i][j] (rows: n x n complex128)
+void eig_blocks_scatter(hipStream_t s, const EigBlock* blk, int nb, void* rows, long long n, const int* idx);
 struct TdEigJob {
   double* D;
   const double* E;

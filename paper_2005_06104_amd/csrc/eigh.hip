@@ -405,10 +405,104 @@ __global__ __launch_bounds__(TNT) void shift_by_trace_kernel(double2* G, const d
   }
 }
 
-__global__ void td_reset_kernel(unsigned* w, int nw, int* err) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nw) w[i] = 0u;
-  if (i == 0 && err) *err = 0;
+// the tagged exchange words of up to TD_RESET_MAX sectors (problem y of
+// the launch: nw[y] words at w[y]) and the shared error flag
+constexpr int TD_RESET_MAX = 64;
+struct TdReset {
+  int n;
+  int* err;
+  unsigned* w[TD_RESET_MAX];
+  int nw[TD_RESET_MAX];
+};
+__global__ void td_reset_kernel(const TdReset r) {
+  const int y = blockIdx.y;
+  if (y >= r.n) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < r.nw[y]; i += gridDim.x * blockDim.x) r.w[y][i] = 0u;
+  if (y == 0 && blockIdx.x == 0 && threadIdx.x == 0 && r.err) *r.err = 0;
+}
+
+// ------------------------------------------------ charge blocks side by side
+// Block y of the launch (kern::EigBlock) holds indices idx[off .. off + m) of
+// the n x n matrix; every kernel walks its m x m entries with a grid-stride
+// loop over blockIdx.x.
+constexpr int EB_MAX = 64;
+struct EigBlockBatch {
+  int n;
+  kern::EigBlock b[EB_MAX];
+};
+static_assert(sizeof(EigBlockBatch) <= 4096 && sizeof(TdReset) <= 4096, "kernel arguments too large");
+
+// X = (H_b + H_b^H) / 2 of the gathered block (the diagonal's imaginary part
+// dropped), as a gather followed by zhermitize would give it
+__global__ void eb_gather_kernel(const EigBlockBatch bt, const double2* __restrict__ H, long long n,
+                                 const int* __restrict__ idx) {
+  const int y = blockIdx.y;
+  if (y >= bt.n) return;
+  const kern::EigBlock e = bt.b[y];
+  const long long mm = (long long)e.m * e.m;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < mm; t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / e.m), j = (int)(t % e.m);
+    const long long ri = idx[e.off + i], rj = idx[e.off + j];
+    const double2 a = H[ri * n + rj];
+    if (i == j) {
+      e.X[t] = make_double2(a.x, 0.0);
+    } else {
+      const double2 b = H[rj * n + ri];
+      e.X[t] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    }
+  }
+}
+
+// X[j][k] = Z[k][m-1-j] (real eigenvectors, column-major ascending -> rows, descending)
+__global__ void eb_rows_kernel(const EigBlockBatch bt) {
+  const int y = blockIdx.y;
+  if (y >= bt.n) return;
+  const kern::EigBlock e = bt.b[y];
+  const long long mm = (long long)e.m * e.m;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < mm; t += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(t / e.m), k = (int)(t % e.m);
+    e.X[t] = double2{e.Z[(size_t)(e.m - 1 - j) * e.m + k], 0.0};
+  }
+}
+
+// sums[y] = sum |R_y|^2 (one workgroup per block; the check of the back
+// transformation: m for orthonormal rows)
+__global__ __launch_bounds__(TNT) void eb_norms_kernel(const EigBlockBatch bt, double2* __restrict__ sums) {
+  __shared__ double red[TNT / 64];
+  const int y = blockIdx.y;
+  if (y >= bt.n) return;
+  const kern::EigBlock e = bt.b[y];
+  const long long mm = (long long)e.m * e.m;
+  double acc = 0.0;
+  for (long long t = threadIdx.x; t < mm; t += TNT) acc += e.R[t].x * e.R[t].x + e.R[t].y * e.R[t].y;
+  acc = wave::sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < TNT / 64; ++w) tot += red[w];
+    sums[y] = make_double2(tot, 0.0);
+  }
+}
+
+// rows[off + i][idx[off + j]] = R[i][j]
+__global__ void eb_scatter_kernel(const EigBlockBatch bt, double2* __restrict__ rows, long long n,
+                                  const int* __restrict__ idx) {
+  const int y = blockIdx.y;
+  if (y >= bt.n) return;
+  const kern::EigBlock e = bt.b[y];
+  const long long mm = (long long)e.m * e.m;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < mm; t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / e.m), j = (int)(t % e.m);
+    rows[(long long)(e.off + i) * n + idx[e.off + j]] = e.R[t];
+  }
+}
+
+// grid x for an m x m walk (capped: the loops stride)
+unsigned eb_grid_x(const kern::EigBlock* blk, int nb) {
+  long long mx = 1;
+  for (int i = 0; i < nb; ++i) mx = std::max(mx, (long long)blk[i].m * blk[i].m);
+  return (unsigned)std::min<long long>(1024, (mx + 255) / 256);
 }
 
 }  // namespace
@@ -468,10 +562,17 @@ hipError_t tridiag_batched(hipStream_t s, const TdSector* sec, int nsec, int* er
   for (int i = 0; i < nsec; ++i)
     if (sec[i].n < 2 || sec[i].n > TD_NMAX_BIG || !sec[i].scratch) return hipErrorInvalidValue;
   // the tagged words of every sector, and the error flag once
-  for (int i = 0; i < nsec; ++i) {
-    const int nw = 2 * 4 * 4 * sec[i].n;   // 32-bit halves of the tagged words
-    hipLaunchKernelGGL(td_reset_kernel, dim3((nw + 255) / 256), dim3(256), 0, s,
-                       static_cast<unsigned*>(sec[i].scratch), nw, i == 0 ? err : nullptr);
+  for (int i0 = 0; i0 < nsec; i0 += TD_RESET_MAX) {
+    TdReset r{};
+    r.err = i0 == 0 ? err : nullptr;
+    int mx = 1;
+    for (int i = i0; i < std::min(nsec, i0 + TD_RESET_MAX); ++i) {
+      r.w[r.n] = static_cast<unsigned*>(sec[i].scratch);
+      r.nw[r.n] = 2 * 4 * 4 * sec[i].n;   // 32-bit halves of the tagged words
+      mx = std::max(mx, r.nw[r.n]);
+      ++r.n;
+    }
+    hipLaunchKernelGGL(td_reset_kernel, dim3((unsigned)std::min(64, (mx + 255) / 256), r.n), dim3(256), 0, s, r);
   }
   // two variants (Q rows in LDS up to n = 512, in the output above); in
   // each, sectors in decreasing size packed into launches
@@ -542,6 +643,44 @@ void shift_by_trace(hipStream_t s, void* G, int n, double frac, const void* S) {
   const long long nn = (long long)n * n;
   const unsigned blocks = src == G ? 1u : (unsigned)std::min<long long>(256, (nn + TNT - 1) / TNT);
   hipLaunchKernelGGL(shift_by_trace_kernel, dim3(blocks), dim3(TNT), 0, s, static_cast<double2*>(G), src, n, frac);
+}
+
+void eig_blocks_gather(hipStream_t s, const EigBlock* blk, int nb, const void* H, long long n, const int* idx) {
+  for (int g = 0; g < nb; g += EB_MAX) {
+    EigBlockBatch bt{};
+    bt.n = std::min(EB_MAX, nb - g);
+    std::copy(blk + g, blk + g + bt.n, bt.b);
+    hipLaunchKernelGGL(eb_gather_kernel, dim3(eb_grid_x(bt.b, bt.n), bt.n), dim3(256), 0, s, bt,
+                       static_cast<const double2*>(H), n, idx);
+  }
+}
+
+void eig_blocks_rows(hipStream_t s, const EigBlock* blk, int nb) {
+  for (int g = 0; g < nb; g += EB_MAX) {
+    EigBlockBatch bt{};
+    bt.n = std::min(EB_MAX, nb - g);
+    std::copy(blk + g, blk + g + bt.n, bt.b);
+    hipLaunchKernelGGL(eb_rows_kernel, dim3(eb_grid_x(bt.b, bt.n), bt.n), dim3(256), 0, s, bt);
+  }
+}
+
+void eig_blocks_norms(hipStream_t s, const EigBlock* blk, int nb, void* sums) {
+  for (int g = 0; g < nb; g += EB_MAX) {
+    EigBlockBatch bt{};
+    bt.n = std::min(EB_MAX, nb - g);
+    std::copy(blk + g, blk + g + bt.n, bt.b);
+    hipLaunchKernelGGL(eb_norms_kernel, dim3(1, bt.n), dim3(TNT), 0, s, bt, static_cast<double2*>(sums) + g);
+  }
+}
+
+void eig_blocks_scatter(hipStream_t s, const EigBlock* blk, int nb, void* rows, long long n, const int* idx) {
+  for (int g = 0; g < nb; g += EB_MAX) {
+    EigBlockBatch bt{};
+    bt.n = std::min(EB_MAX, nb - g);
+    std::copy(blk + g, blk + g + bt.n, bt.b);
+    hipLaunchKernelGGL(eb_scatter_kernel, dim3(eb_grid_x(bt.b, bt.n), bt.n), dim3(256), 0, s, bt,
+                       static_cast<double2*>(rows), n, idx);
+  }
 }
 
 void zrows_from_real_desc(hipStream_t s, void* out, const double* Z, int n) {

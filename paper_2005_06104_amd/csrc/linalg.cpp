@@ -605,12 +605,11 @@ bool eigh_blocks(tdvp_ctx_s* ctx, const void* H, int n, const int* didx, const s
   hipStream_t s = ctx->stream;
   const int B = (int)off.size();
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-  // layout: per block X | Q | R | Z | E | scratch, then dots partials, then the staged block
+  // layout: per block X | Q | R | Z | E | scratch, then the staged block
   std::vector<size_t> oX(B), oQ(B), oR(B), oZ(B), oE(B), oS(B);
-  size_t tot = 0, nd = 0, maxnn = 1;
+  size_t tot = 0, nd = 0;
   for (int b = 0; b < B; ++b) {
     const size_t m = nbv[b], mm = m * m;
-    maxnn = std::max(maxnn, mm);
     oX[b] = tot; tot += up(sizeof(rz) * mm);
     oQ[b] = tot; tot += up(sizeof(rz) * mm);
     oR[b] = tot; tot += up(sizeof(rz) * mm);
@@ -619,9 +618,6 @@ bool eigh_blocks(tdvp_ctx_s* ctx, const void* H, int n, const int* didx, const s
     oS[b] = tot; tot += up(std::max(kern::tridiag_scratch_bytes((int)m), kern::tridiag_eig_scratch_bytes((int)m)));
     nd += m;
   }
-  const int nbd = kern::zdots_blocks((long long)maxnn);
-  const size_t oP = tot;
-  tot += up(sizeof(rz) * (size_t)nbd);
   // staged: error word and per-block info (ints, 16-byte padded), sums |v|^2, eigenvalues
   const size_t ints = (size_t)(1 + B + 3) / 4 * 4;
   const size_t stage_bytes = sizeof(int) * ints + sizeof(rz) * B + sizeof(double) * nd;
@@ -635,17 +631,20 @@ bool eigh_blocks(tdvp_ctx_s* ctx, const void* H, int n, const int* didx, const s
   double* dD = reinterpret_cast<double*>(dsum + B);
   kern::zfill(s, stage, zc(0.0, 0.0), (long long)(sizeof(int) * ints / 16), 16);   // error and info words
   std::vector<kern::TdSector> td(B);
+  std::vector<kern::EigBlock> eb(B);
   size_t od = 0;
   std::vector<size_t> oDv(B);
   for (int b = 0; b < B; ++b) {
     const int m = nbv[b];
     rz* X = reinterpret_cast<rz*>(base + oX[b]);
-    kern::zgather(s, X, m, H, n, didx + off[b], m, didx + off[b], m);
-    kern::zhermitize_to(s, X, X, m);
+    eb[b] = kern::EigBlock{reinterpret_cast<double2*>(X), reinterpret_cast<const double*>(base + oZ[b]),
+                           reinterpret_cast<double2*>(base + oR[b]), off[b], m};
     oDv[b] = od;
     td[b] = kern::TdSector{X, base + oQ[b], dD + od, reinterpret_cast<double*>(base + oE[b]), base + oS[b], m};
     od += m;
   }
+  // every block gathered and made Hermitian in one launch
+  kern::eig_blocks_gather(s, eb.data(), B, H, n, didx);
   if (kern::tridiag_batched(s, td.data(), B, derr) != hipSuccess) {
     (void)hipGetLastError();
     return false;
@@ -666,17 +665,18 @@ bool eigh_blocks(tdvp_ctx_s* ctx, const void* H, int n, const int* didx, const s
     (void)hipGetLastError();
     return false;
   }
+  // back transformation: rows of the tridiagonal eigenvectors (one launch),
+  // R = rows Q^dagger per block, the checks' sums and the scatter into sec
+  // (one launch each)
+  kern::eig_blocks_rows(s, eb.data(), B);
   for (int b = 0; b < B; ++b) {
     const int m = nbv[b];
-    double* Z = reinterpret_cast<double*>(base + oZ[b]);
     rz* X = reinterpret_cast<rz*>(base + oX[b]);
     rz* R = reinterpret_cast<rz*>(base + oR[b]);
-    kern::zrows_from_real_desc(s, X, Z, m);
     kern::gemm<double>(s, TDVP_OP_N, TDVP_OP_C, m, m, m, 1.0, X, m, 0, base + oQ[b], m, 0, 0.0, R, m, 0, 1);
-    kern::zdots(s, R, (long long)m * m, 1, R, (long long)m * m, base + oP, kern::zdots_blocks((long long)m * m),
-                dsum + b);
-    kern::zscatter_cols(s, static_cast<char*>(sec) + sizeof(zc) * (size_t)off[b] * n, n, R, m, m, didx + off[b], m);
   }
+  kern::eig_blocks_norms(s, eb.data(), B, dsum);
+  kern::eig_blocks_scatter(s, eb.data(), B, sec, n, didx);
   const char* hs = static_cast<const char*>(ctx->fetch(stage, stage_bytes));
   int herr;
   std::memcpy(&herr, hs, sizeof(int));
