@@ -151,7 +151,7 @@ struct MapCache {
   };
   static constexpr size_t MAX_BYTES = size_t(1) << 30;
   static constexpr unsigned long long PROTECT = 256;
-  static constexpr int NSTAGE = 4;
+  static constexpr int NSTAGE = 32;
   tdvp_ctx_s* ctx;
   std::unordered_map<unsigned long long, std::vector<std::unique_ptr<Entry>>> tab;
   size_t bytes = 0;
