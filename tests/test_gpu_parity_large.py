@@ -284,3 +284,42 @@ def test_cylinder_workload_first_steps_match_oracle(env):
                     assert loss < 1e-8 * t and dsz < 1e-8, (p, loss, dsz)
                 else:
                     assert loss < 1e-5 * t and dsz < 1e-4, (p, loss, dsz)
+
+
+def test_ladder128_workload_first_step_matches_oracle(env):
+    # The 2 x 64 rung-coupled ladder workload (128 sites, snake path, Neel
+    # quench, dt = 0.1, k = 3, eps_K = 1e-4, eps_M = 1e-8, eps = 0, chi_max =
+    # 512, FP32 contractions) with U(1) charges on the device: its first step
+    # against the dense oracle (density-matrix Krylov vectors on both sides),
+    # FP64 and FP32, to the fidelity targets per unit time; then two more
+    # steps held to energy conservation (as for the cylinder: later states
+    # depend on the kept directions of near-degenerate spectra).
+    from oracle import gse, mpo, mps as M, observables as O
+    T, ctx = env
+    w = I.workload(2)
+    N = w.lattice.n_sites
+    terms = w.terms
+    Ws, Wop = mpo.build_mpo(N, terms), mpo.build_mpo(N, terms, 1.0, -1j * w.tau)
+    H = T.tdvp_create_mpo(ctx, N, terms)
+    op = T.tdvp_create_mpo(ctx, N, terms, 1.0, -1j * w.tau)
+    states = w.lattice.neel()
+    psi = I.product_mps(states)
+    e0 = O.energy(psi, Ws)
+    dev = {p: T.tdvp_mps_from_host(ctx, I.product_mps(states), I.product_charges(states)) for p in ("fp64", "fp32")}
+    psi, _ = gse.gse_step(psi, Ws, Wop, w.dt, w.k, w.eps_K, w.eps_M, w.eps, w.chi_max, 1e-12, 30, False)
+    t = abs(w.dt)
+    sz_ref = O.sz(psi)
+    for step in range(3):
+        for p, g in dev.items():
+            T.tdvp_expand_basis(ctx, [g], [op], w.k, w.eps_K, w.eps_M, w.chi_max, p)
+            T.tdvp_sweep(ctx, [g], [H], w.dt, w.eps, w.chi_max, 1e-12, 30, p, False)
+            m = T.tdvp_measure(ctx, [g], [H])[0]
+            drift = abs(m["energy"] - e0) / abs(e0)
+            assert drift < (1e-10 if p == "fp64" else 1e-6), (step, p, drift)
+            if step == 0:
+                loss = 1 - M.fidelity(T.tdvp_mps_to_host(g), psi)
+                dsz = np.abs(m["sz"] - sz_ref).max()
+                if p == "fp64":
+                    assert loss < 1e-8 * t and dsz < 1e-8, (p, loss, dsz)
+                else:
+                    assert loss < 1e-5 * t and dsz < 1e-4, (p, loss, dsz)
