@@ -461,12 +461,26 @@ std::vector<int> phys2() { return {2, 0, 0, -2}; }   // (s, v): q(s) + q(v)
 
 namespace {
 
-// the maps of a batch of products, one per batch entry (batch outer)
-void join_batches(const std::vector<KMapHost>& parts, KMapHost& out) {
+// the maps of a batch of products, one per batch entry (batch outer);
+// entries with equal charges share one map
+void join_batches(const std::vector<const KMapHost*>& parts, KMapHost& out) {
   out = KMapHost();
+  size_t ne = 0, niv = 0, nti = 0;
+  for (const KMapHost* p : parts) {
+    ne += p->etile.size();
+    niv += p->iv.size();
+    nti += p->tinfo.size();
+  }
+  out.off.reserve(ne + 1);
+  out.iv.reserve(niv);
+  out.etile.reserve(ne);
+  out.erng.reserve(4 * ne);
+  out.epart.reserve(ne);
+  out.enone.reserve(ne);
+  out.tinfo.reserve(nti);
   out.off.assign(1, 0);
   for (size_t x = 0; x < parts.size(); ++x) {
-    const KMapHost& p = parts[x];
+    const KMapHost& p = *parts[x];
     const int base = (int)(out.iv.size() / 2);
     for (size_t t = 1; t < p.off.size(); ++t) out.off.push_back(base + p.off[t]);
     out.iv.insert(out.iv.end(), p.iv.begin(), p.iv.end());
@@ -489,18 +503,20 @@ void join_batches(const std::vector<KMapHost>& parts, KMapHost& out) {
 // (the channels take few distinct charges: one map per distinct shift)
 void build_batched(const std::vector<int>& qrow, const std::vector<int>& shift, int sign, const std::vector<int>& kq,
                    const std::vector<int>& cq, KMapHost& out) {
-  std::vector<KMapHost> parts(shift.size());
+  std::vector<KMapHost> uniq(shift.size());   // sized up front: parts point into it
+  std::vector<const KMapHost*> parts(shift.size());
   std::map<int, size_t> first;
   std::vector<int> rq(qrow.size());
   for (size_t x = 0; x < shift.size(); ++x) {
     const auto it = first.find(shift[x]);
     if (it != first.end()) {
-      parts[x] = parts[it->second];
+      parts[x] = &uniq[it->second];
       continue;
     }
     first[shift[x]] = x;
     for (size_t r = 0; r < qrow.size(); ++r) rq[r] = qrow[r] + sign * shift[x];
-    build_kmap(rq, kq, cq, parts[x]);
+    build_kmap(rq, kq, cq, uniq[x]);
+    parts[x] = &uniq[x];
   }
   join_batches(parts, out);
 }
@@ -530,18 +546,20 @@ void kmap_env_left_gemm2(const std::vector<int>& qlo, const std::vector<int>& qr
 void kmap_env_right_gemm1(const std::vector<int>& qli, const std::vector<int>& qri, const std::vector<int>& qwr,
                           const std::vector<int>& qro, KMapHost& out) {
   const std::vector<int> rq = fuse2(qli, kPhys, 1, 1);
-  std::vector<KMapHost> parts(qwr.size());
+  std::vector<KMapHost> uniq(qwr.size());   // sized up front: parts point into it
+  std::vector<const KMapHost*> parts(qwr.size());
   std::map<int, size_t> first;
   std::vector<int> cq(qro.size());
   for (size_t x = 0; x < qwr.size(); ++x) {
     const auto it = first.find(qwr[x]);
     if (it != first.end()) {
-      parts[x] = parts[it->second];
+      parts[x] = &uniq[it->second];
       continue;
     }
     first[qwr[x]] = x;
     for (size_t c = 0; c < qro.size(); ++c) cq[c] = qro[c] - qwr[x];
-    build_kmap(rq, qri, cq, parts[x]);
+    build_kmap(rq, qri, cq, uniq[x]);
+    parts[x] = &uniq[x];
   }
   join_batches(parts, out);
   split_kmap(out);
@@ -654,9 +672,15 @@ kern::WCharges wc_of(const MapEntry& e, int nrow, int ncol, int win) {
   const int* b = e.map.iv;
   return kern::WCharges{b, b + nrow, b + nrow + ncol, b + nrow + ncol + 2 * win, 0};
 }
+// The second product reads Y1[a',(al,b)] only where q(a') = q(al) + q(b),
+// inside the first product's sub-blocks that share a charge: the others
+// (four in five at a bond of 1024 on the cylinder) are left unwritten.
 std::pair<const MapEntry*, const MapEntry*> cmap_keff(MapCache& c, const VI& ql, const VI& qr, const VI& qw) {
   return c.get2(map_key(MK_KEFF1, {&ql, &qr, &qw}), map_key(MK_KEFF2, {&ql, &qr, &qw}),
-                [&](KMapHost& g1, KMapHost& g2) { kmap_keff(ql, qr, qw, g1, g2); });
+                [&](KMapHost& g1, KMapHost& g2) {
+                  kmap_keff(ql, qr, qw, g1, g2);
+                  g1.drop_empty = true;
+                });
 }
 std::pair<const MapEntry*, const MapEntry*> cmap_two_site(MapCache& c, const VI& qlo, const VI& qli, const VI& qwl,
                                                           const VI& qri, const VI& qwr, const VI& qro) {
