@@ -84,18 +84,48 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
   const auto rs = tile_segments(rq, M, cmin), cs = tile_segments(cq, N, cmin);
   const int tm = (int)rs.size(), tn = (int)cs.size();
   out = KMapHost();
-  out.off.assign(1, 0);
   out.tiles = tm * tn;
   out.tinfo.assign((size_t)6 * tm * tn, 0);
+  size_t nsub = 0;
+  {
+    size_t sr = 0, sc = 0;
+    for (const auto& r : rs) sr += r.size();
+    for (const auto& c : cs) sc += c.size();
+    nsub = sr * sc;
+  }
+  out.ivb.reserve(nsub);
+  out.ive.reserve(nsub);
+  out.etile.reserve(nsub);
+  out.erng.reserve(4 * nsub);
+  out.epart.reserve(nsub);
+  out.enone.reserve(nsub);
   // the merged intervals depend only on the set of charges a sub-block
-  // meets: merge once per distinct set
+  // meets: merged once per distinct set (a single charge: by its index)
   struct Merged {
     std::vector<int> iv;
     long long klen = 0;
+    bool done = false;
+    int pos = -1;   // first interval of the list in out.iv, once an entry uses it
   };
+  auto merge = [&](const std::vector<int>& common, Merged& m) {
+    std::vector<Run> sel;
+    for (int x : common) sel.insert(sel.end(), runs[x].begin(), runs[x].end());
+    std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
+    for (size_t j = 0; j < sel.size();) {
+      Run cur = sel[j++];
+      while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
+      m.iv.push_back(cur.b);
+      m.iv.push_back(cur.e);
+      m.klen += cur.e - cur.b;
+    }
+    m.done = true;
+  };
+  std::vector<Merged> single(R);
+  Merged none;
+  none.done = true;
+  none.pos = 0;
   std::map<std::vector<int>, Merged> cache;
   std::vector<int> common;
-  std::vector<Run> sel;
   for (int a = 0; a < tm; ++a)
     for (int b = 0; b < tn; ++b) {
       const int t = a * tn + b;
@@ -103,30 +133,43 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
       out.tinfo[6 * (size_t)t + 1] = cs[b].size() == 2 ? cs[b][1].b - b * TILE : TILE;
       for (const Seg& r : rs[a])
         for (const Seg& c : cs[b]) {
-          common.clear();
-          std::set_intersection(r.q.begin(), r.q.end(), c.q.begin(), c.q.end(), std::back_inserter(common));
-          auto it = cache.find(common);
-          if (it == cache.end()) {
-            Merged m;
-            sel.clear();
-            for (int x : common) sel.insert(sel.end(), runs[x].begin(), runs[x].end());
-            std::sort(sel.begin(), sel.end(), [](const Run& x, const Run& y) { return x.b < y.b; });
-            for (size_t j = 0; j < sel.size();) {
-              Run cur = sel[j++];
-              while (j < sel.size() && sel[j].b - cur.e < GAP) cur.e = std::max(cur.e, sel[j++].e);
-              m.iv.push_back(cur.b);
-              m.iv.push_back(cur.e);
-              m.klen += cur.e - cur.b;
+          Merged* mp;
+          bool empty;
+          if (r.q.size() == 1 && c.q.size() == 1) {
+            empty = r.q[0] != c.q[0];
+            if (empty) {
+              mp = &none;
+            } else {
+              Merged& m = single[r.q[0]];
+              if (!m.done) merge(r.q, m);
+              mp = &m;
             }
-            it = cache.emplace(common, std::move(m)).first;
+          } else {
+            common.clear();
+            std::set_intersection(r.q.begin(), r.q.end(), c.q.begin(), c.q.end(), std::back_inserter(common));
+            empty = common.empty();
+            auto it = cache.find(common);
+            if (it == cache.end()) {
+              Merged m;
+              merge(common, m);
+              it = cache.emplace(common, std::move(m)).first;
+            }
+            mp = &it->second;
           }
-          out.iv.insert(out.iv.end(), it->second.iv.begin(), it->second.iv.end());
-          out.off.push_back((int)(out.iv.size() / 2));
+          if (mp->pos < 0) {
+            mp->pos = (int)(out.iv.size() / 2);
+            out.iv.insert(out.iv.end(), mp->iv.begin(), mp->iv.end());
+          }
+          out.ivb.push_back(mp->pos);
+          out.ive.push_back(mp->pos + (int)(mp->iv.size() / 2));
           out.etile.push_back(t);
-          out.erng.insert(out.erng.end(), {r.b - a * TILE, r.e - a * TILE, c.b - b * TILE, c.e - b * TILE});
+          out.erng.push_back(r.b - a * TILE);
+          out.erng.push_back(r.e - a * TILE);
+          out.erng.push_back(c.b - b * TILE);
+          out.erng.push_back(c.e - b * TILE);
           out.epart.push_back(0);
-          out.enone.push_back(common.empty() ? 1 : 0);
-          out.tile_macs += (double)(r.e - r.b) * (c.e - c.b) * it->second.klen;
+          out.enone.push_back(empty ? 1 : 0);
+          out.tile_macs += (double)(r.e - r.b) * (c.e - c.b) * mp->klen;
         }
     }
   // nonzero multiply-adds: per charge, rows x columns x K indices of it
@@ -153,13 +196,13 @@ void split_kmap(KMapHost& h) {
   Range r_("maps.split");
   constexpr int SPLIT_MIN_TILES = 768, SPLIT_TARGET = 1024, SPLIT_MAX = 16, SPLIT_MIN_K = 256;
   h.splits = 1;
-  const int E = (int)h.off.size() - 1;
+  const int E = (int)h.ivb.size();
   if (E <= 0) return;
   std::vector<long long> klen(E, 0);
   long long sum = 0, kmax = 0;
   int active = 0;
   for (int e = 0; e < E; ++e) {
-    for (int v = h.off[e]; v < h.off[e + 1]; ++v) klen[e] += h.iv[2 * v + 1] - h.iv[2 * v];
+    for (int v = h.ivb[e]; v < h.ive[e]; ++v) klen[e] += h.iv[2 * v + 1] - h.iv[2 * v];
     sum += klen[e];
     kmax = std::max(kmax, klen[e]);
     active += klen[e] > 0;
@@ -173,7 +216,7 @@ void split_kmap(KMapHost& h) {
     chunk = up((kmax + S - 1) / S);
   }
   if (S <= 1) return;
-  std::vector<int> off(1, 0), iv, etile, erng, epart;
+  std::vector<int> ivb, ive, iv, etile, erng, epart;
   iv.reserve(h.iv.size() + (size_t)2 * E);
   for (int e = 0; e < E; ++e) {
     const int t = h.etile[e];
@@ -184,7 +227,8 @@ void split_kmap(KMapHost& h) {
       const long long lo = sp * chunk, hi = std::min(klen[e], lo + chunk);
       if (lo >= hi) break;
       long long pos = 0;   // K entries of the sub-block before interval v
-      for (int v = h.off[e]; v < h.off[e + 1] && pos < hi; ++v) {
+      ivb.push_back((int)(iv.size() / 2));
+      for (int v = h.ivb[e]; v < h.ive[e] && pos < hi; ++v) {
         const int x = h.iv[2 * v], y = h.iv[2 * v + 1];
         const long long a = std::max(lo, pos), z = std::min(hi, pos + (y - x));
         if (a < z) {
@@ -193,7 +237,7 @@ void split_kmap(KMapHost& h) {
         }
         pos += y - x;
       }
-      off.push_back((int)(iv.size() / 2));
+      ive.push_back((int)(iv.size() / 2));
       etile.push_back(t);
       erng.insert(erng.end(), rg, rg + 4);
       epart.push_back(sp);
@@ -201,7 +245,8 @@ void split_kmap(KMapHost& h) {
     }
     h.tinfo[6 * (size_t)t + 2 + sub] = parts;
   }
-  h.off.swap(off);
+  h.ivb.swap(ivb);
+  h.ive.swap(ive);
   h.iv.swap(iv);
   h.etile.swap(etile);
   h.erng.swap(erng);
@@ -304,23 +349,47 @@ std::pair<const MapCache::Entry*, const MapCache::Entry*> MapCache::get2(
   return {e1, e2};
 }
 
+std::vector<int> kmap_item_order(const KMapHost& h) {
+  const int E = (int)h.ivb.size();
+  std::vector<long long> kl(E, -1);   // -1: not a work item
+  long long kmax = 0;
+  for (int e = 0; e < E; ++e) {
+    long long k = 0;
+    for (int v = h.ivb[e]; v < h.ive[e]; ++v) k += h.iv[2 * v + 1] - h.iv[2 * v];
+    // the reduction covers empty sub-blocks; drop_empty maps leave those
+    // that share no charge unwritten
+    if (h.splits > 1 && k == 0) continue;
+    if (h.splits == 1 && h.drop_empty && (size_t)e < h.enone.size() && h.enone[e]) continue;
+    kl[e] = k;
+    kmax = std::max(kmax, k);
+  }
+  std::vector<int> order;
+  if (kmax > (1 << 24)) {   // K beyond any product here: comparison sort
+    for (int e = 0; e < E; ++e)
+      if (kl[e] >= 0) order.push_back(e);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return kl[x] > kl[y]; });
+    return order;
+  }
+  // counting sort by decreasing K length, equal lengths in entry order
+  std::vector<int> start((size_t)kmax + 2, 0);
+  for (int e = 0; e < E; ++e)
+    if (kl[e] >= 0) ++start[(size_t)kl[e]];
+  int run = 0;
+  for (long long k = kmax; k >= 0; --k) {
+    const int c = start[(size_t)k];
+    start[(size_t)k] = run;
+    run += c;
+  }
+  order.resize(run);
+  for (int e = 0; e < E; ++e)
+    if (kl[e] >= 0) order[start[(size_t)kl[e]]++] = e;
+  return order;
+}
+
 MapCache::Entry& MapCache::insert(std::vector<int>&& key, unsigned long long hk, const KMapHost& h) {
   Range r_("maps.upload");
   // work items {tile, part, first interval, end}, {r0, r1, c0, c1}, longest K first
-  const int E = (int)h.off.size() - 1;
-  std::vector<std::pair<long long, int>> order;
-  order.reserve(E);
-  for (int e = 0; e < E; ++e) {
-    long long kl = 0;
-    for (int v = h.off[e]; v < h.off[e + 1]; ++v) kl += h.iv[2 * v + 1] - h.iv[2 * v];
-    // the reduction covers empty sub-blocks; drop_empty maps leave those
-    // that share no charge unwritten
-    if (h.splits > 1 && kl == 0) continue;
-    if (h.splits == 1 && h.drop_empty && (size_t)e < h.enone.size() && h.enone[e]) continue;
-    order.push_back({-kl, e});
-  }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<long long, int>& x, const std::pair<long long, int>& y) { return x.first < y.first; });
+  const std::vector<int> order = kmap_item_order(h);
   const size_t ni = 8 * order.size(), nv = h.iv.size(), ns = h.splits > 1 ? h.tinfo.size() : 0, nt = ni + nv + ns;
   // one upload from pinned memory, ordered on the stream; the host waits
   // only for the copy that last used this staging buffer (long done in the
@@ -338,12 +407,11 @@ MapCache::Entry& MapCache::insert(std::vector<int>&& key, unsigned long long hk,
     stage_cap[si] = cap;
   }
   int* st = stage[si];
-  for (const auto& o : order) {
-    const int e = o.second;
+  for (const int e : order) {
     st[0] = h.etile[e];
     st[1] = h.epart[e];
-    st[2] = h.off[e];
-    st[3] = h.off[e + 1];
+    st[2] = h.ivb[e];
+    st[3] = h.ive[e];
     std::copy(h.erng.begin() + 4 * (size_t)e, h.erng.begin() + 4 * (size_t)e + 4, st + 4);
     st += 8;
   }
@@ -471,18 +539,19 @@ void join_batches(const std::vector<const KMapHost*>& parts, KMapHost& out) {
     niv += p->iv.size();
     nti += p->tinfo.size();
   }
-  out.off.reserve(ne + 1);
+  out.ivb.reserve(ne);
+  out.ive.reserve(ne);
   out.iv.reserve(niv);
   out.etile.reserve(ne);
   out.erng.reserve(4 * ne);
   out.epart.reserve(ne);
   out.enone.reserve(ne);
   out.tinfo.reserve(nti);
-  out.off.assign(1, 0);
   for (size_t x = 0; x < parts.size(); ++x) {
     const KMapHost& p = *parts[x];
     const int base = (int)(out.iv.size() / 2);
-    for (size_t t = 1; t < p.off.size(); ++t) out.off.push_back(base + p.off[t]);
+    for (int b : p.ivb) out.ivb.push_back(base + b);
+    for (int e : p.ive) out.ive.push_back(base + e);
     out.iv.insert(out.iv.end(), p.iv.begin(), p.iv.end());
     for (int t : p.etile) out.etile.push_back((int)x * p.tiles + t);
     out.erng.insert(out.erng.end(), p.erng.begin(), p.erng.end());
@@ -657,7 +726,6 @@ const MapEntry& cmap_wstage(MapCache& c, const VI& qrow, const VI& qcol, const V
   return c.get(map_key(MK_WSTAGE, {&qrow, &qcol, &qwin, &qwout, &sg}), [&](KMapHost& h) {
     // no work items: the table rides in the interval array
     h = KMapHost();
-    h.off.assign(1, 0);
     h.iv = qrow;
     h.iv.insert(h.iv.end(), qcol.begin(), qcol.end());
     for (int w : qwin)

@@ -109,11 +109,12 @@ struct MatvecTimer {
 // Entries are sub-blocks of the 64 x 64 output tiles: tile etile[e] (batch
 // entry outer, then row-major tiles), rows erng[4e] .. erng[4e+1] and
 // columns erng[4e+2] .. erng[4e+3] inside the tile, split part epart[e], K
-// intervals iv[off[e] .. off[e+1]).  tinfo (6 per tile): the row and column
+// intervals iv[ivb[e] .. ive[e]) (the entries of an unsplit map that meet the
+// same charges share one list).  tinfo (6 per tile): the row and column
 // where the tile's second segment starts (64 if none), then the nonempty
 // parts of each of its up to four sub-blocks (split maps).
 struct KMapHost {
-  std::vector<int> off, iv, etile, erng, epart, tinfo;
+  std::vector<int> ivb, ive, iv, etile, erng, epart, tinfo;
   // per entry of an unsplit map: 1 when its rows and columns share no
   // charge (every output of the sub-block is zero by charge)
   std::vector<unsigned char> enone;
@@ -128,6 +129,9 @@ void build_kmap(const std::vector<int>& rq, const std::vector<int>& kq, const st
 // Split the K intervals of a map whose nonempty tiles are too few to fill
 // the GPU into parts of about equal length (see kern::KMap).
 void split_kmap(KMapHost& h);
+// The entries of h that become work items, longest K first (equal lengths in
+// entry order): the upload order, which spreads the long items over the XCDs.
+std::vector<int> kmap_item_order(const KMapHost& h);
 // The block-sparse maps of a context on the device, kept between calls and
 // keyed by the builder and the charge lists it was given.  Products whose
 // operands keep their charges from one call to the next (a sweep's exact
