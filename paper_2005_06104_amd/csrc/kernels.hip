@@ -132,7 +132,7 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
   constexpr int SI = BM / WM / 16, SJ = BN / WN / 16;   // MFMA tiles per wave
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const TileJob job = tile_job(M, N, K, S, Kc, kit, kiv);
   const int m0 = job.m0, n0 = job.n0, split = job.split;
@@ -221,6 +221,62 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
     const int c = wn * (BN / WN) + j * 16;
     act_j[j] = c < job.c1 && c + 16 > job.c0;
   }
+  // The wave's piece rows ro[i] and columns co[j] (tile offsets) and which
+  // of its pieces it computes.  By quadrant, a sub-block covering part of the
+  // tile can leave some waves with four pieces and others with none, and the
+  // item lasts as long as its busiest wave.  With four waves of 2 x 2 pieces,
+  // a block-sparse item whose covered pieces (ni x nj of 16 x 16) number at
+  // most four gets one per wave, one at most two pieces wide a row strip per
+  // wave, one at most two pieces tall a column strip per wave; larger ones
+  // keep the quadrants.
+  int ro[SI], co[SJ];
+  bool pact[SI][SJ];
+#pragma unroll
+  for (int i = 0; i < SI; ++i) ro[i] = wm * (BM / WM) + i * 16;
+#pragma unroll
+  for (int j = 0; j < SJ; ++j) co[j] = wn * (BN / WN) + j * 16;
+#pragma unroll
+  for (int i = 0; i < SI; ++i)
+#pragma unroll
+    for (int j = 0; j < SJ; ++j) pact[i][j] = act_i[i] && act_j[j];
+  if constexpr (SI == 2 && SJ == 2 && WM * WN == 4) {
+    const int pi0 = job.r0 >> 4, pj0 = job.c0 >> 4;
+    const int ni = ((job.r1 + 15) >> 4) - pi0, nj = ((job.c1 + 15) >> 4) - pj0;
+    const int shape = kit == nullptr ? 0 : ni * nj <= 4 ? 1 : nj <= 2 ? 2 : ni <= 2 ? 3 : 0;
+    if (shape != 0) {
+#pragma unroll
+      for (int i = 0; i < SI; ++i)
+#pragma unroll
+        for (int j = 0; j < SJ; ++j) pact[i][j] = false;
+      ro[1] = ro[0] = 0;
+      co[1] = co[0] = 0;
+      if (shape == 1) {   // one piece per wave
+        if (wave < ni * nj) {
+          ro[0] = (pi0 + wave / nj) * 16;
+          co[0] = (pj0 + wave % nj) * 16;
+          pact[0][0] = true;
+        }
+      } else if (shape == 2) {   // row strips: row pi0 + wave, nj <= 2 pieces
+        if (wave < ni) {
+          ro[0] = (pi0 + wave) * 16;
+#pragma unroll
+          for (int j = 0; j < SJ; ++j) {
+            co[j] = (pj0 + (j < nj ? j : 0)) * 16;
+            pact[0][j] = j < nj;
+          }
+        }
+      } else {   // column strips: column pj0 + wave, ni <= 2 pieces
+        if (wave < nj) {
+          co[0] = (pj0 + wave) * 16;
+#pragma unroll
+          for (int i = 0; i < SI; ++i) {
+            ro[i] = (pi0 + (i < ni ? i : 0)) * 16;
+            pact[i][0] = i < ni;
+          }
+        }
+      }
+    }
+  }
   // double-buffered LDS: compute on `cur` while the next tile's global loads
   // are in flight, then store them into the other buffer; one barrier per
   // tile.  The K steps walk the tile's intervals in order.
@@ -256,21 +312,21 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       T a_r[SI], a_i[SI], a_s[SI], b_r[SJ], b_i[SJ], b_s[SJ];
 #pragma unroll
       for (int i = 0; i < SI; ++i) {
-        a_r[i] = As_r[cur][kr][wm * (BM / WM) + i * 16 + lr];
-        a_i[i] = As_i[cur][kr][wm * (BM / WM) + i * 16 + lr];
+        a_r[i] = As_r[cur][kr][ro[i] + lr];
+        a_i[i] = As_i[cur][kr][ro[i] + lr];
         a_s[i] = a_r[i] + a_i[i];
       }
 #pragma unroll
       for (int j = 0; j < SJ; ++j) {
-        b_r[j] = Bs_r[cur][kr][wn * (BN / WN) + j * 16 + lr];
-        b_i[j] = Bs_i[cur][kr][wn * (BN / WN) + j * 16 + lr];
+        b_r[j] = Bs_r[cur][kr][co[j] + lr];
+        b_i[j] = Bs_i[cur][kr][co[j] + lr];
         b_s[j] = b_r[j] + b_i[j];
       }
 #pragma unroll
       for (int i = 0; i < SI; ++i)
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
-          if (!(act_i[i] && act_j[j])) continue;
+          if (!pact[i][j]) continue;
           p1[i][j] = mfma(a_r[i], b_r[j], p1[i][j]);
           p2[i][j] = mfma(a_i[i], b_i[j], p2[i][j]);
           p3[i][j] = mfma(a_s[i], b_s[j], p3[i][j]);
@@ -294,8 +350,9 @@ __global__ __launch_bounds__(gemm_threads<T>()) void gemm_kernel(int M, int N, i
       for (int r = 0; r < 4; ++r) {
         // output row inside the 16x16 tile: the f32 MFMA puts rows 4*(lane/16)+r
         // in a lane, the f64 MFMA rows (lane/16)+4*r (columns are lane%16 for both)
+        if (!pact[i][j]) continue;
         const int tr = sizeof(T) == 8 ? (lk + 4 * r) : (lk * 4 + r);
-        const int lm = wm * (BM / WM) + i * 16 + tr, ln = wn * (BN / WN) + j * 16 + lr;
+        const int lm = ro[i] + tr, ln = co[j] + lr;
         const int gm = m0 + lm;
         const int gn = n0 + ln;
         if (gm < M && gn < N && lm >= job.r0 && lm < job.r1 && ln >= job.c0 && ln < job.c1) {
